@@ -1,0 +1,248 @@
+/*
+ * mpmi.h -- C ABI of the MI355X library for model-predictive minimal
+ * intervention shared control (MPMI-SC).
+ *
+ * The library evaluates, once per control tick, a large batch of candidate
+ * user inputs against a learned Koopman model and a safety set, and returns
+ * the safe candidate closest to the user's own input (Algorithm 2, Sec. IV-C
+ * of the paper).  Every entry point below names the passage of the paper that
+ * defines the operation.
+ *
+ * Conventions shared by every entry point
+ *  - Pointers are DEVICE pointers (memory of the GPU the context was created
+ *    on) unless the parameter is marked "host".  The caller owns and allocates
+ *    every buffer it passes; the library owns only what mpmi_create()
+ *    allocates (per-loop selection slots and the fit workspace).
+ *  - Arrays are dense and row-major in the order their shape is written, the
+ *    LAST index fastest: cand[S][m][Nc] stores candidate c of input j in
+ *    segment g at cand[(g*m + j)*Nc + c].
+ *  - `stream` is a hipStream_t (NULL = the null stream).  Apart from
+ *    koopman_fit, calls only enqueue work and return at once; results are
+ *    ready when the stream reaches them.
+ *  - Arguments are validated on the host before anything is enqueued.  A bad
+ *    argument returns MPMI_EINVAL (or MPMI_EUNSUPPORTED for a valid but
+ *    unimplemented combination) and enqueues nothing; mpmi_last_error()
+ *    then holds a message.  A failed launch returns MPMI_EDEVICE.
+ *  - "No candidate is safe" is not an error: it is reported per tick in
+ *    mpmi_selection.status (device memory), because the host has returned
+ *    before the kernels run.
+ *  - One context may be used by one host thread at a time.  Calls on one
+ *    context that share a `loop` slot must be ordered on one stream.
+ */
+#ifndef MPMI_H
+#define MPMI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MPMI_ABI_VERSION 1
+
+/* Size limits (checked on the host). */
+#define MPMI_MAX_STATE 8      /* n */
+#define MPMI_MAX_INPUT 4      /* m */
+#define MPMI_MAX_DIM 64       /* D, basis size */
+#define MPMI_MAX_BOX 4        /* box constraints per system */
+#define MPMI_MAX_HORIZON 255  /* H, prediction steps */
+#define MPMI_MAX_SEGMENTS 8   /* S, piecewise-constant input segments */
+#define MPMI_MAX_CAND 33554431 /* Nc = N + 1 <= 2^25 - 1 */
+#define MPMI_MAX_LOOPS 4096   /* selection slots per context */
+
+typedef int32_t mpmi_status;
+enum {
+  MPMI_OK = 0,
+  MPMI_NO_SAFE = 1, /* informational: only ever stored in mpmi_selection.status */
+  MPMI_EINVAL = -1,
+  MPMI_ENOMEM = -2,
+  MPMI_EDEVICE = -3,
+  MPMI_EUNSUPPORTED = -4,
+  MPMI_ESINGULAR = -5
+};
+
+/* Basis families psi(w), w = [x; u] (Sec. IV-A: the Koopman operator acts on
+ * functions of the state; the functions used here are fixed families).
+ *  LINEAR       psi = w                                    D = n + m
+ *  BALANCE_BOT  n = 4, m = 1: [1, w_0..w_4, w_k w_l for 0 <= k <= l <= 4,
+ *               k outer, l inner]                           D = 21
+ *  RACE_CAR     n = 6, m = 2, w = [x, y, psi, vx, vy, r, delta, a]:
+ *               [1, w_0..w_7, w_k w_l (0 <= k <= l <= 7, k outer),
+ *                sin psi, cos psi, sin delta, cos delta,
+ *                sin psi * (vx, vy, r, a), cos psi * (vx, vy, r, a),
+ *                sin delta * (vx, vy, r), cos delta * (vx, vy, r),
+ *                a sin delta]                               D = 64        */
+enum { MPMI_BASIS_LINEAR = 0, MPMI_BASIS_BALANCE_BOT = 1, MPMI_BASIS_RACE_CAR = 2 };
+
+/* Arithmetic of the prediction step.
+ *  FP32    states, features and K in FP32, FP32 accumulation.
+ *  BF16X3  the contraction runs on BF16 matrix cores as three products of
+ *          hi/lo BF16 splits of the features and of (K - E) in residual form
+ *          x' = x + psi^T (K - E), FP32 accumulation; every candidate whose
+ *          margin comes within the system's eps band of a constraint is then
+ *          re-rolled in FP32 and the FP32 verdict is kept.                  */
+enum { MPMI_PREC_FP32 = 0, MPMI_PREC_BF16X3 = 1 };
+
+/* How a tick obtains candidates 1..N (candidate 0 is always the user's input,
+ * held over all segments; Sec. III-D: a safe user input passes unchanged).
+ *  EXPLICIT  read from a caller array cand[S][m][N] (candidate i at column i-1)
+ *  GRID      cell-centred grid (Sec. IV-B, equally spaced samples): index
+ *            k = i - 1 = k_0 + G_0 (k_1 + G_1 (...)), value of input j is
+ *            (float)(lo_j + (k_j + 0.5) * ((hi_j - lo_j) / G_j)) evaluated in
+ *            FP64 in that order; S must be 1
+ *  UNIFORM   counter-based uniform draws (Alg. 2's sampling step): for input
+ *            j of segment g, h = seed; h = mix((h ^ w) + G) for w in (tick,
+ *            loop, i, g*m + j), mix the SplitMix64 output function and G its
+ *            golden gamma 0x9E3779B97F4A7C15; r = (h >> 40) * 2^-24; value =
+ *            (float)(lo_j + (hi_j - lo_j) * r) in FP64.                     */
+enum { MPMI_GEN_EXPLICIT = 0, MPMI_GEN_GRID = 1, MPMI_GEN_UNIFORM = 2 };
+
+/* A controlled system: basis, safety set and input box (host struct, copied).
+ * Safety (Sec. IV-B predictive safety; inflated barrier of Sec. V-C-1): a
+ * predicted state x is safe iff every margin is > 0 (a NaN margin is not):
+ *   box j   : (box_bound[j] - box_infl[j]) - |x[box_index[j]]|
+ *   track   : (track_half - track_infl) - |rho - r_c(phi)|, (rho, phi) the
+ *             polar coordinates of (x[0], x[1]) and
+ *             r_c(phi) = track_r0 + sum_k track_amp[k] sin(track_freq[k] phi + track_phase[k])
+ * eps_box / eps_track: in BF16X3 mode, a candidate whose margin at some step
+ * falls below eps is re-rolled in FP32.                                     */
+typedef struct mpmi_system {
+  int32_t basis;          /* MPMI_BASIS_* */
+  int32_t n_state;        /* n (LINEAR: 1..8; fixed 4 / 6 for the others) */
+  int32_t n_input;        /* m (LINEAR: 1..4; fixed 1 / 2 for the others) */
+  int32_t n_box;          /* number of box constraints used, 0..4 */
+  int32_t box_index[4];   /* state index of box constraint j */
+  float box_bound[4];
+  float box_infl[4];
+  float eps_box[4];
+  int32_t has_track;      /* 0 or 1; needs n >= 2 */
+  int32_t track_n;        /* number of sinusoids used, 0..4 */
+  int32_t track_freq[4];  /* integer frequencies, 0..8 */
+  float track_amp[4];
+  float track_phase[4];
+  float track_r0;
+  float track_half;
+  float track_infl;
+  float eps_track;
+  float u_lo[4];          /* input box; cost divides input j by (u_hi-u_lo)/2 */
+  float u_hi[4];
+} mpmi_system;
+
+/* Result of one tick (device memory, written by the library).
+ * Selection (Alg. 2 selection step, Sec. IV-D): among candidates whose H
+ * predicted states are all safe, the least cost
+ *   cost_i = sum_j ((u_ij - u_h,j) / ((u_hi_j - u_lo_j)/2))^2
+ * on the first segment, ties to the lowest index.  If none is safe: the
+ * latest first violation, then least cost, then lowest index, with
+ * status = MPMI_NO_SAFE.                                                     */
+typedef struct mpmi_selection {
+  int32_t idx;             /* chosen candidate; 0 = the user's own input */
+  int32_t status;          /* MPMI_OK or MPMI_NO_SAFE */
+  int32_t n_safe;          /* safe candidates other than candidate 0 */
+  int32_t n_recheck;       /* candidates re-rolled in FP32 (BF16X3) */
+  float u_r[4];            /* applied input: first segment of candidate idx */
+  float cost;              /* cost of idx (FP32) */
+  float deviation;         /* Euclidean norm of u_r - u_h (Sec. VI-D-1) */
+  int32_t first_violation; /* of idx: 1..H, or H+1 when its rollout is safe */
+  int32_t n_cand;          /* Nc = N + 1 candidates evaluated */
+} mpmi_selection;
+
+/* One control tick's candidate set and horizon (host struct, copied). */
+typedef struct mpmi_tick_desc {
+  uint64_t seed;          /* UNIFORM: generator seed */
+  uint64_t tick;          /* UNIFORM: tick counter */
+  int32_t loop;           /* selection slot 0..MPMI_MAX_LOOPS-1; also an RNG word */
+  int32_t gen;            /* MPMI_GEN_* */
+  int32_t n_cand;         /* N, candidates besides candidate 0 (>= 0) */
+  int32_t grid[4];        /* GRID: points per input, product == N */
+  int32_t n_seg;          /* S, 1..8; step s (1..H) uses segment floor((s-1)S/H) */
+  int32_t horizon;        /* H, 1..255 */
+  int32_t precision;      /* MPMI_PREC_* */
+  int32_t block;          /* threads per workgroup: 0 (library default) or 64..1024, multiple of 64 */
+} mpmi_tick_desc;
+
+typedef struct mpmi_ctx_s* mpmi_ctx;
+
+/* Version of this header the library was built from. */
+int32_t mpmi_abi_version(void);
+
+/* Creates a context on HIP device `device` (makes it current on the calling
+ * thread) and allocates its slots and workspace.  *out is NULL on failure.  */
+mpmi_status mpmi_create(mpmi_ctx* out, int32_t device);
+void mpmi_destroy(mpmi_ctx ctx);
+/* Message of the last failed call on ctx (never NULL; "" after success).    */
+const char* mpmi_last_error(mpmi_ctx ctx);
+
+/* Size in bytes of a packed model (device blob read by every rollout).      */
+size_t mpmi_model_bytes(void);
+
+/* Packs a system and its fitted K (device FP64 [D][n], row f = feature f,
+ * column j = next-state component j; Sec. IV-A) into `model` (device,
+ * mpmi_model_bytes() bytes, 256-byte aligned): FP32 K, the residual K - E
+ * split into BF16 hi/lo operand tiles, and the safety constants.            */
+mpmi_status mpmi_model_pack(mpmi_ctx ctx, const mpmi_system* sys /* host */,
+                            const double* K, void* model, void* stream);
+
+/* Learns K from transitions (Sec. IV-A: the Koopman model is learned from
+ * data; least squares as in extended DMD).  X [T][n], U [T][m], Y [T][n] are
+ * device FP64 with Y[t] the successor of (X[t], U[t]).  Solves
+ *   min || Psi_s K_s - Y ||^2 + ridge || K_s ||^2,  Psi_s = Psi diag(1/s),
+ * s_f the RMS of feature f over the T rows, by an FP64 Gram accumulation,
+ * a Cholesky factorisation and two triangular solves; writes K = diag(1/s) K_s
+ * to K_out (device FP64 [D][n]) and, if cond_out is not NULL, an estimate of
+ * the 2-norm condition number of Psi_s to *cond_out (host).  Synchronous:
+ * returns after the result is in K_out.  MPMI_ESINGULAR when the scaled Gram
+ * matrix is not numerically positive definite.  T >= D required.           */
+mpmi_status koopman_fit(mpmi_ctx ctx, const mpmi_system* sys /* host */,
+                        const double* X, const double* U, const double* Y, int64_t T,
+                        double ridge, double* K_out, double* cond_out /* host */,
+                        void* stream);
+
+/* Predicts every candidate over the full horizon, without early exit
+ * (Alg. 2 prediction loop; Fig. 1's cloud of trajectories): from x0 [n],
+ * x_s = psi(x_{s-1}, u_c(seg(s)))^T K for s = 1..H.  cand [S][m][Nc];
+ * traj [H][n][Nc] receives x_1..x_H (candidate fastest).  FP32 only.        */
+mpmi_status rollout_batch(mpmi_ctx ctx, const void* model, int32_t precision,
+                          const float* x0, const float* cand, int32_t Nc, int32_t S,
+                          int32_t H, float* traj, void* stream);
+
+/* Safety verdicts of stored trajectories (Sec. IV-B; Alg. 2 safety check):
+ * first_violation[c] = first step s in 1..H whose state traj[s-1][.][c] is
+ * unsafe, or H+1.  min_margin (optional, may be NULL) [Nc] = the least
+ * margin over all constraints and over steps 1..min(first_violation, H).   */
+mpmi_status safe_mask(mpmi_ctx ctx, const void* model, const float* traj, int32_t Nc,
+                      int32_t H, int16_t* first_violation, float* min_margin,
+                      void* stream);
+
+/* Minimal-intervention choice (Alg. 2 selection step; Sec. III-D; Sec. IV-D)
+ * over candidates cand [S][m][Nc] with verdicts first_violation [Nc]
+ * (safe = H+1); candidate 0 is taken to be the user's input u_user [m] for
+ * n_safe.  Writes *out (device).  `loop` picks the selection slot.           */
+mpmi_status select_min_intervention(mpmi_ctx ctx, const void* model, const float* cand,
+                                    int32_t Nc, int32_t S, const int16_t* first_violation,
+                                    int32_t H, const float* u_user, int32_t loop,
+                                    mpmi_selection* out, void* stream);
+
+/* One fused control tick (Alg. 2 entire): candidates generated per desc,
+ * prediction with early exit at the first unsafe state, selection, in one
+ * kernel launch.  x_t [n] and u_user [m] device FP32.  cand: EXPLICIT only,
+ * [S][m][N].  Optional outputs (NULL to skip): first_violation [N+1];
+ * traj [H][n][N+1] (states after a candidate's first violation are left
+ * unwritten).  *out receives the selection.                                 */
+mpmi_status mpmi_tick(mpmi_ctx ctx, const void* model, const mpmi_tick_desc* desc /* host */,
+                      const float* x_t, const float* u_user, const float* cand,
+                      mpmi_selection* out, int16_t* first_violation, float* traj,
+                      void* stream);
+
+/* Writes the candidates a tick with `desc` evaluates, cand_out [S][m][N+1]
+ * (column 0 = u_user), so generated candidates can be inspected.           */
+mpmi_status mpmi_generate_candidates(mpmi_ctx ctx, const void* model,
+                                     const mpmi_tick_desc* desc /* host */,
+                                     const float* u_user, const float* cand,
+                                     float* cand_out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MPMI_H */

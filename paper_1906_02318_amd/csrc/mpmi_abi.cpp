@@ -1,0 +1,326 @@
+// C-ABI layer of libmpmi: context management, host-side argument validation
+// and dispatch to the kernel launchers.  Nothing here computes any part of
+// the method; every step runs in the HIP kernels.
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <unordered_map>
+
+#include "../../include/mpmi.h"
+#include "mpmi_launch.hpp"
+
+struct mpmi_ctx_s {
+  int device = 0;
+  void* slots = nullptr;       // MPMI_MAX_LOOPS selection slots
+  void* fit_work = nullptr;    // fit partial sums, totals and info
+  std::unordered_map<const void*, mpmi_system> models;  // packed models, by device address
+  std::string err;
+};
+
+namespace {
+
+mpmi_status fail(mpmi_ctx ctx, mpmi_status code, const char* fmt, ...) {
+  if (ctx) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    ctx->err = buf;
+  }
+  return code;
+}
+
+mpmi_status ok(mpmi_ctx ctx) {
+  ctx->err.clear();
+  return MPMI_OK;
+}
+
+mpmi_status check_hip(mpmi_ctx ctx, hipError_t e, const char* what) {
+  if (e == hipSuccess) return ok(ctx);
+  return fail(ctx, MPMI_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+int basis_dim(const mpmi_system& s) {
+  switch (s.basis) {
+    case MPMI_BASIS_LINEAR: return s.n_state + s.n_input;
+    case MPMI_BASIS_BALANCE_BOT: return 21;
+    case MPMI_BASIS_RACE_CAR: return 64;
+    default: return -1;
+  }
+}
+
+// Index in psi of feature w_0 = x_0 (the state features are contiguous).
+int state_feat0(const mpmi_system& s) { return s.basis == MPMI_BASIS_LINEAR ? 0 : 1; }
+
+mpmi_status validate_system(mpmi_ctx ctx, const mpmi_system* s) {
+  if (!s) return fail(ctx, MPMI_EINVAL, "system descriptor is NULL");
+  switch (s->basis) {
+    case MPMI_BASIS_LINEAR:
+      if (s->n_state < 1 || s->n_state > MPMI_MAX_STATE || s->n_input < 1 || s->n_input > MPMI_MAX_INPUT)
+        return fail(ctx, MPMI_EINVAL, "LINEAR basis needs 1 <= n <= %d and 1 <= m <= %d (got n=%d m=%d)",
+                    MPMI_MAX_STATE, MPMI_MAX_INPUT, s->n_state, s->n_input);
+      break;
+    case MPMI_BASIS_BALANCE_BOT:
+      if (s->n_state != 4 || s->n_input != 1)
+        return fail(ctx, MPMI_EINVAL, "BALANCE_BOT basis needs n=4, m=1 (got n=%d m=%d)", s->n_state, s->n_input);
+      break;
+    case MPMI_BASIS_RACE_CAR:
+      if (s->n_state != 6 || s->n_input != 2)
+        return fail(ctx, MPMI_EINVAL, "RACE_CAR basis needs n=6, m=2 (got n=%d m=%d)", s->n_state, s->n_input);
+      break;
+    default:
+      return fail(ctx, MPMI_EINVAL, "unknown basis %d", s->basis);
+  }
+  if (s->n_box < 0 || s->n_box > MPMI_MAX_BOX) return fail(ctx, MPMI_EINVAL, "n_box=%d out of 0..%d", s->n_box, MPMI_MAX_BOX);
+  for (int b = 0; b < s->n_box; ++b) {
+    if (s->box_index[b] < 0 || s->box_index[b] >= s->n_state)
+      return fail(ctx, MPMI_EINVAL, "box_index[%d]=%d is not a state index", b, s->box_index[b]);
+    if (!(s->box_infl[b] >= 0.0f)) return fail(ctx, MPMI_EINVAL, "box_infl[%d] must be >= 0", b);
+  }
+  if (s->has_track != 0 && s->has_track != 1) return fail(ctx, MPMI_EINVAL, "has_track must be 0 or 1");
+  if (s->has_track) {
+    if (s->n_state < 2) return fail(ctx, MPMI_EINVAL, "track constraint needs n >= 2");
+    if (s->track_n < 0 || s->track_n > 4) return fail(ctx, MPMI_EINVAL, "track_n=%d out of 0..4", s->track_n);
+    for (int k = 0; k < s->track_n; ++k)
+      if (s->track_freq[k] < 0 || s->track_freq[k] > 8)
+        return fail(ctx, MPMI_EINVAL, "track_freq[%d]=%d out of 0..8", k, s->track_freq[k]);
+    if (!(s->track_infl >= 0.0f)) return fail(ctx, MPMI_EINVAL, "track_infl must be >= 0");
+  }
+  for (int j = 0; j < s->n_input; ++j)
+    if (!(s->u_hi[j] > s->u_lo[j]))
+      return fail(ctx, MPMI_EINVAL, "input box %d is empty (lo=%g hi=%g)", j, (double)s->u_lo[j], (double)s->u_hi[j]);
+  return MPMI_OK;
+}
+
+// Host copy of the descriptor of a model packed by this context, so calls
+// that take only the model validate and dispatch without touching the device.
+mpmi_status model_system(mpmi_ctx ctx, const void* model, mpmi_system* out, hipStream_t) {
+  if (!model) return fail(ctx, MPMI_EINVAL, "model is NULL");
+  auto it = ctx->models.find(model);
+  if (it == ctx->models.end())
+    return fail(ctx, MPMI_EINVAL, "model %p was not packed by mpmi_model_pack on this context", model);
+  *out = it->second;
+  return MPMI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t mpmi_abi_version(void) { return MPMI_ABI_VERSION; }
+
+size_t mpmi_model_bytes(void) { return mpmi::model_bytes(); }
+
+mpmi_status mpmi_create(mpmi_ctx* out, int32_t device) {
+  if (!out) return MPMI_EINVAL;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count == 0) return MPMI_EDEVICE;
+  if (device < 0 || device >= count) return MPMI_EINVAL;
+  mpmi_ctx ctx = new (std::nothrow) mpmi_ctx_s();
+  if (!ctx) return MPMI_ENOMEM;
+  ctx->device = device;
+  if (hipSetDevice(device) != hipSuccess) {
+    delete ctx;
+    return MPMI_EDEVICE;
+  }
+  const size_t slot_bytes = (size_t)MPMI_MAX_LOOPS * mpmi::slot_bytes();
+  if (hipMalloc(&ctx->slots, slot_bytes) != hipSuccess ||
+      hipMalloc(&ctx->fit_work, mpmi::fit_workspace_bytes()) != hipSuccess) {
+    mpmi_destroy(ctx);
+    return MPMI_ENOMEM;
+  }
+  // Reset state of a slot: both keys all-ones, counters zero.
+  if (hipMemset(ctx->slots, 0, slot_bytes) != hipSuccess) {
+    mpmi_destroy(ctx);
+    return MPMI_EDEVICE;
+  }
+  for (int i = 0; i < MPMI_MAX_LOOPS; ++i) {
+    if (hipMemset((char*)ctx->slots + i * mpmi::slot_bytes(), 0xff, 16) != hipSuccess) {
+      mpmi_destroy(ctx);
+      return MPMI_EDEVICE;
+    }
+  }
+  if (hipDeviceSynchronize() != hipSuccess) {
+    mpmi_destroy(ctx);
+    return MPMI_EDEVICE;
+  }
+  *out = ctx;
+  return MPMI_OK;
+}
+
+void mpmi_destroy(mpmi_ctx ctx) {
+  if (!ctx) return;
+  if (ctx->slots) (void)hipFree(ctx->slots);
+  if (ctx->fit_work) (void)hipFree(ctx->fit_work);
+  delete ctx;
+}
+
+const char* mpmi_last_error(mpmi_ctx ctx) { return ctx ? ctx->err.c_str() : "NULL context"; }
+
+mpmi_status mpmi_model_pack(mpmi_ctx ctx, const mpmi_system* sys, const double* K, void* model, void* stream) {
+  if (!ctx) return MPMI_EINVAL;
+  mpmi_status s = validate_system(ctx, sys);
+  if (s != MPMI_OK) return s;
+  if (!K) return fail(ctx, MPMI_EINVAL, "K is NULL");
+  if (!model) return fail(ctx, MPMI_EINVAL, "model is NULL");
+  if (!aligned(model, 256)) return fail(ctx, MPMI_EINVAL, "model must be 256-byte aligned");
+  if (!aligned(K, 8)) return fail(ctx, MPMI_EINVAL, "K must be 8-byte aligned");
+  s = check_hip(ctx, mpmi::launch_pack(*sys, basis_dim(*sys), state_feat0(*sys), K, model, (hipStream_t)stream),
+                "mpmi_model_pack launch");
+  if (s == MPMI_OK) ctx->models[model] = *sys;
+  return s;
+}
+
+mpmi_status koopman_fit(mpmi_ctx ctx, const mpmi_system* sys, const double* X, const double* U, const double* Y,
+                        int64_t T, double ridge, double* K_out, double* cond_out, void* stream) {
+  if (!ctx) return MPMI_EINVAL;
+  mpmi_status s = validate_system(ctx, sys);
+  if (s != MPMI_OK) return s;
+  const int D = basis_dim(*sys);
+  if (!X || !U || !Y || !K_out) return fail(ctx, MPMI_EINVAL, "X, U, Y and K_out must be non-NULL");
+  if (T < D) return fail(ctx, MPMI_EINVAL, "T=%lld rows cannot determine D=%d features", (long long)T, D);
+  if (T > (int64_t)1 << 40) return fail(ctx, MPMI_EINVAL, "T=%lld too large", (long long)T);
+  if (!(ridge >= 0.0)) return fail(ctx, MPMI_EINVAL, "ridge must be >= 0");
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = mpmi::launch_fit(*sys, D, X, U, Y, T, ridge, K_out, ctx->fit_work, st);
+  if (e != hipSuccess) return fail(ctx, MPMI_EDEVICE, "koopman_fit launch: %s", hipGetErrorString(e));
+  e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return fail(ctx, MPMI_EDEVICE, "koopman_fit: %s", hipGetErrorString(e));
+  struct { int32_t status, pad; double cond; } info;
+  const size_t info_off = mpmi::fit_workspace_bytes() - 256;
+  e = hipMemcpy(&info, (char*)ctx->fit_work + info_off, sizeof info, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return fail(ctx, MPMI_EDEVICE, "koopman_fit readback: %s", hipGetErrorString(e));
+  if (cond_out) *cond_out = info.cond;
+  if (info.status != MPMI_OK)
+    return fail(ctx, MPMI_ESINGULAR, "scaled Gram matrix is not numerically positive definite");
+  return ok(ctx);
+}
+
+mpmi_status rollout_batch(mpmi_ctx ctx, const void* model, int32_t precision, const float* x0, const float* cand,
+                          int32_t Nc, int32_t S, int32_t H, float* traj, void* stream) {
+  if (!ctx) return MPMI_EINVAL;
+  if (precision != MPMI_PREC_FP32)
+    return fail(ctx, MPMI_EUNSUPPORTED, "rollout_batch stores FP32 trajectories; precision must be MPMI_PREC_FP32");
+  if (Nc < 1 || Nc > MPMI_MAX_CAND) return fail(ctx, MPMI_EINVAL, "Nc=%d out of 1..%d", Nc, MPMI_MAX_CAND);
+  if (S < 1 || S > MPMI_MAX_SEGMENTS) return fail(ctx, MPMI_EINVAL, "S=%d out of 1..%d", S, MPMI_MAX_SEGMENTS);
+  if (H < 1 || H > MPMI_MAX_HORIZON) return fail(ctx, MPMI_EINVAL, "H=%d out of 1..%d", H, MPMI_MAX_HORIZON);
+  if (!x0 || !cand || !traj) return fail(ctx, MPMI_EINVAL, "x0, cand and traj must be non-NULL");
+  mpmi_system sys;
+  mpmi_status s = model_system(ctx, model, &sys, (hipStream_t)stream);
+  if (s != MPMI_OK) return s;
+  return check_hip(ctx, mpmi::launch_rollout(sys.basis, model, Nc, S, H, x0, cand, traj, (hipStream_t)stream),
+                   "rollout_batch launch");
+}
+
+mpmi_status safe_mask(mpmi_ctx ctx, const void* model, const float* traj, int32_t Nc, int32_t H,
+                      int16_t* first_violation, float* min_margin, void* stream) {
+  if (!ctx) return MPMI_EINVAL;
+  if (Nc < 1 || Nc > MPMI_MAX_CAND) return fail(ctx, MPMI_EINVAL, "Nc=%d out of 1..%d", Nc, MPMI_MAX_CAND);
+  if (H < 1 || H > MPMI_MAX_HORIZON) return fail(ctx, MPMI_EINVAL, "H=%d out of 1..%d", H, MPMI_MAX_HORIZON);
+  if (!traj || !first_violation) return fail(ctx, MPMI_EINVAL, "traj and first_violation must be non-NULL");
+  mpmi_system sys;
+  mpmi_status s = model_system(ctx, model, &sys, (hipStream_t)stream);
+  if (s != MPMI_OK) return s;
+  return check_hip(ctx, mpmi::launch_mask(sys.basis, model, Nc, H, traj, first_violation, min_margin,
+                                          (hipStream_t)stream),
+                   "safe_mask launch");
+}
+
+mpmi_status select_min_intervention(mpmi_ctx ctx, const void* model, const float* cand, int32_t Nc, int32_t S,
+                                    const int16_t* first_violation, int32_t H, const float* u_user, int32_t loop,
+                                    mpmi_selection* out, void* stream) {
+  if (!ctx) return MPMI_EINVAL;
+  if (Nc < 1 || Nc > MPMI_MAX_CAND) return fail(ctx, MPMI_EINVAL, "Nc=%d out of 1..%d", Nc, MPMI_MAX_CAND);
+  if (S < 1 || S > MPMI_MAX_SEGMENTS) return fail(ctx, MPMI_EINVAL, "S=%d out of 1..%d", S, MPMI_MAX_SEGMENTS);
+  if (H < 1 || H > MPMI_MAX_HORIZON) return fail(ctx, MPMI_EINVAL, "H=%d out of 1..%d", H, MPMI_MAX_HORIZON);
+  if (loop < 0 || loop >= MPMI_MAX_LOOPS) return fail(ctx, MPMI_EINVAL, "loop=%d out of 0..%d", loop, MPMI_MAX_LOOPS - 1);
+  if (!cand || !first_violation || !u_user || !out)
+    return fail(ctx, MPMI_EINVAL, "cand, first_violation, u_user and out must be non-NULL");
+  mpmi_system sys;
+  mpmi_status s = model_system(ctx, model, &sys, (hipStream_t)stream);
+  if (s != MPMI_OK) return s;
+  void* slot = (char*)ctx->slots + (size_t)loop * mpmi::slot_bytes();
+  return check_hip(ctx, mpmi::launch_select(model, Nc, S, H, cand, first_violation, u_user, loop, slot, out,
+                                            (hipStream_t)stream),
+                   "select_min_intervention launch");
+}
+
+static mpmi_status validate_desc(mpmi_ctx ctx, const mpmi_system& sys, const mpmi_tick_desc* d) {
+  if (!d) return fail(ctx, MPMI_EINVAL, "tick descriptor is NULL");
+  if (d->n_cand < 0 || d->n_cand > MPMI_MAX_CAND - 1)
+    return fail(ctx, MPMI_EINVAL, "n_cand=%d out of 0..%d", d->n_cand, MPMI_MAX_CAND - 1);
+  if (d->horizon < 1 || d->horizon > MPMI_MAX_HORIZON)
+    return fail(ctx, MPMI_EINVAL, "horizon=%d out of 1..%d", d->horizon, MPMI_MAX_HORIZON);
+  if (d->n_seg < 1 || d->n_seg > MPMI_MAX_SEGMENTS)
+    return fail(ctx, MPMI_EINVAL, "n_seg=%d out of 1..%d", d->n_seg, MPMI_MAX_SEGMENTS);
+  if (d->loop < 0 || d->loop >= MPMI_MAX_LOOPS)
+    return fail(ctx, MPMI_EINVAL, "loop=%d out of 0..%d", d->loop, MPMI_MAX_LOOPS - 1);
+  if (d->block != 0 && (d->block < 64 || d->block > 1024 || d->block % 64 != 0))
+    return fail(ctx, MPMI_EINVAL, "block=%d must be 0 or a multiple of 64 in 64..1024", d->block);
+  if (d->precision != MPMI_PREC_FP32 && d->precision != MPMI_PREC_BF16X3)
+    return fail(ctx, MPMI_EINVAL, "unknown precision %d", d->precision);
+  switch (d->gen) {
+    case MPMI_GEN_EXPLICIT:
+    case MPMI_GEN_UNIFORM:
+      break;
+    case MPMI_GEN_GRID: {
+      if (d->n_seg != 1) return fail(ctx, MPMI_EINVAL, "GRID candidates need n_seg == 1");
+      long long prod = 1;
+      for (int j = 0; j < sys.n_input; ++j) {
+        if (d->grid[j] < 1) return fail(ctx, MPMI_EINVAL, "grid[%d]=%d must be >= 1", j, d->grid[j]);
+        prod *= d->grid[j];
+      }
+      if (prod != d->n_cand)
+        return fail(ctx, MPMI_EINVAL, "grid product %lld != n_cand %d", prod, d->n_cand);
+      break;
+    }
+    default:
+      return fail(ctx, MPMI_EINVAL, "unknown candidate generator %d", d->gen);
+  }
+  return MPMI_OK;
+}
+
+mpmi_status mpmi_tick(mpmi_ctx ctx, const void* model, const mpmi_tick_desc* desc, const float* x_t,
+                      const float* u_user, const float* cand, mpmi_selection* out, int16_t* first_violation,
+                      float* traj, void* stream) {
+  if (!ctx) return MPMI_EINVAL;
+  mpmi_system sys;
+  mpmi_status s = model_system(ctx, model, &sys, (hipStream_t)stream);
+  if (s != MPMI_OK) return s;
+  s = validate_desc(ctx, sys, desc);
+  if (s != MPMI_OK) return s;
+  if (!x_t || !u_user || !out) return fail(ctx, MPMI_EINVAL, "x_t, u_user and out must be non-NULL");
+  if (desc->gen == MPMI_GEN_EXPLICIT && desc->n_cand > 0 && !cand)
+    return fail(ctx, MPMI_EINVAL, "EXPLICIT candidates need cand");
+  if (desc->precision != MPMI_PREC_FP32)
+    return fail(ctx, MPMI_EUNSUPPORTED, "precision %d is not available in this build", desc->precision);
+  void* slot = (char*)ctx->slots + (size_t)desc->loop * mpmi::slot_bytes();
+  return check_hip(ctx, mpmi::launch_tick(sys.basis, model, *desc, x_t, u_user, cand, slot, out, first_violation,
+                                          traj, (hipStream_t)stream),
+                   "mpmi_tick launch");
+}
+
+mpmi_status mpmi_generate_candidates(mpmi_ctx ctx, const void* model, const mpmi_tick_desc* desc,
+                                     const float* u_user, const float* cand, float* cand_out, void* stream) {
+  if (!ctx) return MPMI_EINVAL;
+  mpmi_system sys;
+  mpmi_status s = model_system(ctx, model, &sys, (hipStream_t)stream);
+  if (s != MPMI_OK) return s;
+  s = validate_desc(ctx, sys, desc);
+  if (s != MPMI_OK) return s;
+  if (!u_user || !cand_out) return fail(ctx, MPMI_EINVAL, "u_user and cand_out must be non-NULL");
+  if (desc->gen == MPMI_GEN_EXPLICIT && desc->n_cand > 0 && !cand)
+    return fail(ctx, MPMI_EINVAL, "EXPLICIT candidates need cand");
+  return check_hip(ctx, mpmi::launch_gen(model, *desc, u_user, cand, cand_out, (hipStream_t)stream),
+                   "mpmi_generate_candidates launch");
+}
+
+}  // extern "C"

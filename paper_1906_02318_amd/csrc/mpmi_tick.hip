@@ -1,0 +1,475 @@
+// Kernels of the control tick: fused tick (generate -> predict with early exit
+// -> safety -> selection, one launch), and the separable stages rollout_batch,
+// safe_mask, select_min_intervention, candidate generation and model packing.
+//
+// Work decomposition: one candidate per lane (candidates are independent,
+// Alg. 2's parallel loop), the state kept in VGPRs across the whole horizon,
+// K read through uniform (scalar) loads from the packed model, so the
+// contraction is VALU FMAs with an SGPR operand and no LDS traffic.  The
+// arg-min is a 64-bit key reduced across the wave with shuffles, across the
+// workgroup in LDS, and across workgroups with one atomicMin per workgroup;
+// the last workgroup to finish decodes the key (no second launch).
+#include <hip/hip_runtime.h>
+
+#include "mpmi_device.hpp"
+#include "mpmi_launch.hpp"
+
+namespace mpmi {
+
+// Candidate source modes: the three public generators plus FULL (an explicit
+// array that already holds candidate 0 in column 0).
+constexpr int kGenFull = 3;
+
+__device__ __forceinline__ float cand_value(const GenParams& gp, const ModelDev* __restrict__ md,
+                                            const float* __restrict__ cand,
+                                            const float* __restrict__ u_user, int c, int g, int j) {
+  if (gp.gen == kGenFull) return cand[(size_t)(g * md->m + j) * (size_t)(gp.n_cand + 1) + (size_t)c];
+  if (c == 0) return u_user[j];
+  return gen_value(gp, md, cand, c, g, j);
+}
+
+template <int MS>
+__device__ __forceinline__ float cost_of(const ModelDev* __restrict__ md, const float* u0,
+                                         const float* __restrict__ u_user) {
+  float cst = 0.0f;
+#pragma unroll
+  for (int j = 0; j < MS; ++j) {
+    if (j < md->m) {
+      const float d = (u0[j] - u_user[j]) * md->half_inv[j];
+      cst = fmaf(d, d, cst);
+    }
+  }
+  return cst;
+}
+
+// Workgroup reduction of the two keys and the safe count, then one atomic of
+// each per workgroup; returns true in every thread of the last workgroup.
+__device__ __forceinline__ bool reduce_and_publish(unsigned long long ks, unsigned long long kf,
+                                                   bool safe_counted, Slot* __restrict__ slot) {
+  __shared__ unsigned long long s_ks[16], s_kf[16];
+  __shared__ unsigned int s_cnt[16];
+  __shared__ int s_last;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  ks = wave_min_u64(ks);
+  kf = wave_min_u64(kf);
+  const unsigned int cnt = (unsigned int)__popcll(__ballot(safe_counted));
+  if (lane == 0) {
+    s_ks[wave] = ks;
+    s_kf[wave] = kf;
+    s_cnt[wave] = cnt;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int nw = (blockDim.x + 63) >> 6;
+    unsigned long long bks = kKeyNone, bkf = kKeyNone;
+    unsigned int bcnt = 0;
+    for (int w = 0; w < nw; ++w) {
+      bks = s_ks[w] < bks ? s_ks[w] : bks;
+      bkf = s_kf[w] < bkf ? s_kf[w] : bkf;
+      bcnt += s_cnt[w];
+    }
+    if (bks != kKeyNone) atomicMin(&slot->key_safe, bks);
+    if (bkf != kKeyNone) atomicMin(&slot->key_fb, bkf);
+    if (bcnt) atomicAdd(&slot->n_safe, bcnt);
+    __threadfence();
+    const unsigned int prev = atomicAdd(&slot->done, 1u);
+    s_last = (prev == gridDim.x - 1);
+  }
+  __syncthreads();
+  return s_last != 0;
+}
+
+// Decodes the slot into the selection and resets the slot (one thread).
+template <int MS>
+__device__ void finalize(const ModelDev* __restrict__ md, const GenParams& gp,
+                         const float* __restrict__ cand, const float* __restrict__ u_user, int H,
+                         Slot* __restrict__ slot, mpmi_selection* __restrict__ out) {
+  __threadfence();
+  const unsigned long long ks = atomicMin(&slot->key_safe, kKeyNone);
+  const unsigned long long kf = atomicMin(&slot->key_fb, kKeyNone);
+  const unsigned int n_safe = atomicAdd(&slot->n_safe, 0u);
+  const unsigned int n_re = atomicAdd(&slot->n_recheck, 0u);
+  int idx, status, fv;
+  float cost;
+  if (ks != kKeyNone) {
+    idx = (int)(ks & 0xffffffffull);
+    cost = __uint_as_float((unsigned int)(ks >> 32));
+    status = MPMI_OK;
+    fv = H + 1;
+  } else {
+    idx = (int)(kf & 0x1ffffffull);
+    cost = __uint_as_float((unsigned int)((kf >> 25) & 0x7fffffffull));
+    status = MPMI_NO_SAFE;
+    fv = 255 - (int)(kf >> 56);
+  }
+  mpmi_selection sel;
+  sel.idx = idx;
+  sel.status = status;
+  sel.n_safe = (int)n_safe;
+  sel.n_recheck = (int)n_re;
+  float dev2 = 0.0f;
+#pragma unroll
+  for (int j = 0; j < MPMI_MAX_INPUT; ++j) {
+    float v = 0.0f;
+    if (j < md->m) {
+      v = cand_value(gp, md, cand, u_user, idx, 0, j);
+      const float d = v - u_user[j];
+      dev2 = fmaf(d, d, dev2);
+    }
+    sel.u_r[j] = v;
+  }
+  sel.cost = cost;
+  sel.deviation = sqrtf(dev2);
+  sel.first_violation = fv;
+  sel.n_cand = gp.n_cand + 1;
+  *out = sel;
+  slot->key_safe = kKeyNone;
+  slot->key_fb = kKeyNone;
+  slot->n_safe = 0u;
+  slot->n_recheck = 0u;
+  slot->done = 0u;
+  __threadfence();
+}
+
+// ---------------------------------------------------------------------------
+// Fused tick, FP32
+// ---------------------------------------------------------------------------
+template <int BASIS>
+__global__ void __launch_bounds__(1024)
+tick_fp32_kernel(const ModelDev* __restrict__ md, GenParams gp, int H, const float* __restrict__ x_t,
+                 const float* __restrict__ u_user, const float* __restrict__ cand,
+                 Slot* __restrict__ slot, mpmi_selection* __restrict__ out,
+                 int16_t* __restrict__ fv_out, float* __restrict__ traj) {
+  constexpr int NS = Dims<BASIS>::N, MS = Dims<BASIS>::M;
+  const int Nc = gp.n_cand + 1;
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = c < Nc;
+  const int n = md->n, S = gp.n_seg;
+
+  float x[NS], u[MS], u0[MS];
+#pragma unroll
+  for (int j = 0; j < NS; ++j) x[j] = (j < n) ? x_t[j] : 0.0f;
+#pragma unroll
+  for (int j = 0; j < MS; ++j) {
+    u0[j] = (valid && j < md->m) ? cand_value(gp, md, cand, u_user, c, 0, j) : 0.0f;
+    u[j] = u0[j];
+  }
+  float sd = 0.0f, cd = 1.0f;
+  if (BASIS == MPMI_BASIS_RACE_CAR) sincosf(u[0], &sd, &cd);
+
+  int fv = H + 1;
+  if (valid) {
+    int gcur = 0;
+    for (int s = 1; s <= H; ++s) {
+      const int g = ((s - 1) * S) / H;
+      if (g != gcur) {
+        gcur = g;
+#pragma unroll
+        for (int j = 0; j < MS; ++j)
+          u[j] = (j < md->m) ? cand_value(gp, md, cand, u_user, c, g, j) : 0.0f;
+        if (BASIS == MPMI_BASIS_RACE_CAR) sincosf(u[0], &sd, &cd);
+      }
+      if constexpr (BASIS == MPMI_BASIS_RACE_CAR) {
+        race_car_step(md, x, u, sd, cd);
+      } else {
+        koopman_step<BASIS>(md, x, u);
+      }
+      if (traj) {
+#pragma unroll
+        for (int j = 0; j < NS; ++j)
+          if (j < n) traj[((size_t)(s - 1) * n + j) * (size_t)Nc + c] = x[j];
+      }
+      if (!(min_margin<NS>(md, x) > 0.0f)) {
+        fv = s;
+        break;
+      }
+    }
+    if (fv_out) fv_out[c] = (int16_t)fv;
+  }
+  const float cst = valid ? cost_of<MS>(md, u0, u_user) : 0.0f;
+  const bool safe = valid && fv == H + 1;
+  const unsigned long long ks = safe ? safe_key(cst, c) : kKeyNone;
+  const unsigned long long kf = (valid && !safe) ? fallback_key(fv, cst, c) : kKeyNone;
+  if (reduce_and_publish(ks, kf, safe && c > 0, slot) && threadIdx.x == 0)
+    finalize<MS>(md, gp, cand, u_user, H, slot, out);
+}
+
+// ---------------------------------------------------------------------------
+// Separable stages
+// ---------------------------------------------------------------------------
+template <int BASIS>
+__global__ void __launch_bounds__(1024)
+rollout_fp32_kernel(const ModelDev* __restrict__ md, int Nc, int S, int H, const float* __restrict__ x0,
+                    const float* __restrict__ cand, float* __restrict__ traj) {
+  constexpr int NS = Dims<BASIS>::N, MS = Dims<BASIS>::M;
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= Nc) return;
+  const int n = md->n, m = md->m;
+  float x[NS], u[MS];
+#pragma unroll
+  for (int j = 0; j < NS; ++j) x[j] = (j < n) ? x0[j] : 0.0f;
+  int gcur = -1;
+  float sd = 0.0f, cd = 1.0f;
+  for (int s = 1; s <= H; ++s) {
+    const int g = ((s - 1) * S) / H;
+    if (g != gcur) {
+      gcur = g;
+#pragma unroll
+      for (int j = 0; j < MS; ++j) u[j] = (j < m) ? cand[((size_t)g * m + j) * (size_t)Nc + c] : 0.0f;
+      if (BASIS == MPMI_BASIS_RACE_CAR) sincosf(u[0], &sd, &cd);
+    }
+    if constexpr (BASIS == MPMI_BASIS_RACE_CAR) {
+      race_car_step(md, x, u, sd, cd);
+    } else {
+      koopman_step<BASIS>(md, x, u);
+    }
+#pragma unroll
+    for (int j = 0; j < NS; ++j)
+      if (j < n) traj[((size_t)(s - 1) * n + j) * (size_t)Nc + c] = x[j];
+  }
+}
+
+template <int NS>
+__global__ void __launch_bounds__(1024)
+mask_kernel(const ModelDev* __restrict__ md, int Nc, int H, const float* __restrict__ traj,
+            int16_t* __restrict__ fv_out, float* __restrict__ mm_out) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= Nc) return;
+  const int n = md->n;
+  int fv = H + 1;
+  float least = INFINITY;
+  for (int s = 1; s <= H; ++s) {
+    float x[NS];
+#pragma unroll
+    for (int j = 0; j < NS; ++j) x[j] = (j < n) ? traj[((size_t)(s - 1) * n + j) * (size_t)Nc + c] : 0.0f;
+    const float mg = min_margin<NS>(md, x);
+    least = (mg != mg) ? mg : fminf(least, mg);
+    if (!(mg > 0.0f)) {
+      fv = s;
+      break;
+    }
+  }
+  fv_out[c] = (int16_t)fv;
+  if (mm_out) mm_out[c] = least;
+}
+
+template <int MS>
+__global__ void __launch_bounds__(1024)
+select_kernel(const ModelDev* __restrict__ md, GenParams gp, int H, const float* __restrict__ cand,
+              const int16_t* __restrict__ fv_in, const float* __restrict__ u_user,
+              Slot* __restrict__ slot, mpmi_selection* __restrict__ out) {
+  const int Nc = gp.n_cand + 1;
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = c < Nc;
+  float u0[MS];
+#pragma unroll
+  for (int j = 0; j < MS; ++j)
+    u0[j] = (valid && j < md->m) ? cand[(size_t)j * (size_t)Nc + c] : 0.0f;
+  const int fv = valid ? (int)fv_in[c] : 0;
+  const float cst = valid ? cost_of<MS>(md, u0, u_user) : 0.0f;
+  const bool safe = valid && fv == H + 1;
+  const unsigned long long ks = safe ? safe_key(cst, c) : kKeyNone;
+  const unsigned long long kf = (valid && !safe) ? fallback_key(fv < 1 ? 1 : (fv > H ? H : fv), cst, c) : kKeyNone;
+  if (reduce_and_publish(ks, kf, safe && c > 0, slot) && threadIdx.x == 0)
+    finalize<MS>(md, gp, cand, u_user, H, slot, out);
+}
+
+__global__ void gen_kernel(const ModelDev* __restrict__ md, GenParams gp, const float* __restrict__ u_user,
+                           const float* __restrict__ cand, float* __restrict__ cand_out) {
+  const int Nc = gp.n_cand + 1;
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= Nc) return;
+  const int m = md->m;
+  for (int g = 0; g < gp.n_seg; ++g)
+    for (int j = 0; j < m; ++j)
+      cand_out[((size_t)g * m + j) * (size_t)Nc + c] = cand_value(gp, md, cand, u_user, c, g, j);
+}
+
+// ---------------------------------------------------------------------------
+// Model packing
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t bf16_bits_rne(float f) {
+  const uint32_t b = __float_as_uint(f);
+  if ((b & 0x7fffffffu) > 0x7f800000u) return 0x7fc0u;  // NaN
+  return (b + 0x7fffu + ((b >> 16) & 1u)) >> 16;
+}
+
+__global__ void pack_kernel(mpmi_system sys, int dim, int state_feat0, const double* __restrict__ K,
+                            ModelDev* __restrict__ md) {
+  const int t = threadIdx.x;
+  const int n = sys.n_state;
+  // FP32 K, zero-padded to 8 columns and MPMI_MAX_DIM rows.
+  for (int e = t; e < MPMI_MAX_DIM * 8; e += blockDim.x) {
+    const int f = e >> 3, j = e & 7;
+    md->K[f][j] = (f < dim && j < n) ? (float)K[(size_t)f * n + j] : 0.0f;
+  }
+  // Residual R = K - E as BF16 hi/lo splits in B-operand order of a 16x16x32
+  // MFMA: lane l holds column (l & 15), rows kb*32 + (l >> 4)*8 + [0..8).
+  for (int e = t; e < 2 * 64 * 8; e += blockDim.x) {
+    const int kb = e >> 9, lane = (e >> 3) & 63, q = e & 7;
+    const int col = lane & 15, row = kb * 32 + (lane >> 4) * 8 + q;
+    double r = 0.0;
+    if (row < dim && col < n) {
+      r = K[(size_t)row * n + col];
+      if (row == state_feat0 + col) r -= 1.0;
+    }
+    const float rf = (float)r;
+    const uint32_t hi = bf16_bits_rne(rf);
+    const float lo = rf - __uint_as_float(hi << 16);
+    const uint32_t lob = bf16_bits_rne(lo);
+    const int word = (kb * 64 + lane) * 4 + (q >> 1);
+    const int sh = (q & 1) * 16;
+    atomicOr(&md->Rhi[word], hi << sh);
+    atomicOr(&md->Rlo[word], lob << sh);
+  }
+  if (t == 0) {
+    md->sys = sys;
+    md->magic = kModelMagic;
+    md->dim = dim;
+    md->n = n;
+    md->m = sys.n_input;
+    md->state_feat0 = state_feat0;
+    for (int b = 0; b < MPMI_MAX_BOX; ++b)
+      md->bb_lim[b] = (b < sys.n_box) ? (float)((double)sys.box_bound[b] - (double)sys.box_infl[b]) : 0.0f;
+    md->trk_lim = (float)((double)sys.track_half - (double)sys.track_infl);
+    double r0 = sys.track_r0;
+    double ts[kMaxHarm + 1], tc[kMaxHarm + 1];
+    for (int h = 0; h <= kMaxHarm; ++h) ts[h] = tc[h] = 0.0;
+    int hmax = 0;
+    if (sys.has_track) {
+      for (int k = 0; k < sys.track_n; ++k) {
+        const int f = sys.track_freq[k];
+        const double a = sys.track_amp[k], p = sys.track_phase[k];
+        // a sin(f phi + p) = a cos(p) sin(f phi) + a sin(p) cos(f phi)
+        if (f == 0) {
+          r0 += a * sin(p);
+        } else {
+          ts[f] += a * cos(p);
+          tc[f] += a * sin(p);
+          hmax = f > hmax ? f : hmax;
+        }
+      }
+    }
+    md->trk_r0 = (float)r0;
+    for (int h = 0; h <= kMaxHarm; ++h) {
+      md->trk_s[h] = (float)ts[h];
+      md->trk_c[h] = (float)tc[h];
+    }
+    md->hmax = hmax;
+    for (int j = 0; j < MPMI_MAX_INPUT; ++j)
+      md->half_inv[j] = (j < sys.n_input) ? (float)(2.0 / ((double)sys.u_hi[j] - (double)sys.u_lo[j])) : 0.0f;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers
+// ---------------------------------------------------------------------------
+static GenParams make_gen(const mpmi_tick_desc& d) {
+  GenParams gp;
+  gp.seed = d.seed;
+  gp.tick = d.tick;
+  gp.loop = d.loop;
+  gp.gen = d.gen;
+  gp.n_cand = d.n_cand;
+  gp.n_seg = d.n_seg;
+  for (int j = 0; j < MPMI_MAX_INPUT; ++j) gp.grid[j] = d.grid[j] > 0 ? d.grid[j] : 1;
+  return gp;
+}
+
+static inline unsigned blocks_for(long long n, int block) { return (unsigned)((n + block - 1) / block); }
+
+hipError_t launch_pack(const mpmi_system& sys, int dim, int state_feat0, const double* K, void* model,
+                       hipStream_t st) {
+  hipError_t e = hipMemsetAsync(model, 0, sizeof(ModelDev), st);
+  if (e != hipSuccess) return e;
+  pack_kernel<<<1, 256, 0, st>>>(sys, dim, state_feat0, K, (ModelDev*)model);
+  return hipGetLastError();
+}
+
+hipError_t launch_tick(int basis, const void* model, const mpmi_tick_desc& d, const float* x_t,
+                       const float* u_user, const float* cand, void* slot, mpmi_selection* out,
+                       int16_t* fv, float* traj, hipStream_t st) {
+  const GenParams gp = make_gen(d);
+  const int block = d.block > 0 ? d.block : 256;
+  const unsigned grid = blocks_for((long long)d.n_cand + 1, block);
+  const ModelDev* md = (const ModelDev*)model;
+  Slot* sl = (Slot*)slot;
+  switch (basis) {
+    case MPMI_BASIS_LINEAR:
+      tick_fp32_kernel<MPMI_BASIS_LINEAR><<<grid, block, 0, st>>>(md, gp, d.horizon, x_t, u_user, cand, sl, out, fv, traj);
+      break;
+    case MPMI_BASIS_BALANCE_BOT:
+      tick_fp32_kernel<MPMI_BASIS_BALANCE_BOT><<<grid, block, 0, st>>>(md, gp, d.horizon, x_t, u_user, cand, sl, out, fv, traj);
+      break;
+    default:
+      tick_fp32_kernel<MPMI_BASIS_RACE_CAR><<<grid, block, 0, st>>>(md, gp, d.horizon, x_t, u_user, cand, sl, out, fv, traj);
+      break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_rollout(int basis, const void* model, int Nc, int S, int H, const float* x0,
+                          const float* cand, float* traj, hipStream_t st) {
+  const int block = 256;
+  const unsigned grid = blocks_for(Nc, block);
+  const ModelDev* md = (const ModelDev*)model;
+  switch (basis) {
+    case MPMI_BASIS_LINEAR:
+      rollout_fp32_kernel<MPMI_BASIS_LINEAR><<<grid, block, 0, st>>>(md, Nc, S, H, x0, cand, traj);
+      break;
+    case MPMI_BASIS_BALANCE_BOT:
+      rollout_fp32_kernel<MPMI_BASIS_BALANCE_BOT><<<grid, block, 0, st>>>(md, Nc, S, H, x0, cand, traj);
+      break;
+    default:
+      rollout_fp32_kernel<MPMI_BASIS_RACE_CAR><<<grid, block, 0, st>>>(md, Nc, S, H, x0, cand, traj);
+      break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_mask(int basis, const void* model, int Nc, int H, const float* traj, int16_t* fv,
+                       float* mm, hipStream_t st) {
+  const int block = 256;
+  const unsigned grid = blocks_for(Nc, block);
+  const ModelDev* md = (const ModelDev*)model;
+  switch (basis) {
+    case MPMI_BASIS_LINEAR:
+      mask_kernel<MPMI_MAX_STATE><<<grid, block, 0, st>>>(md, Nc, H, traj, fv, mm);
+      break;
+    case MPMI_BASIS_BALANCE_BOT:
+      mask_kernel<4><<<grid, block, 0, st>>>(md, Nc, H, traj, fv, mm);
+      break;
+    default:
+      mask_kernel<6><<<grid, block, 0, st>>>(md, Nc, H, traj, fv, mm);
+      break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_select(const void* model, int Nc, int S, int H, const float* cand, const int16_t* fv,
+                         const float* u_user, int loop, void* slot, mpmi_selection* out, hipStream_t st) {
+  GenParams gp{};
+  gp.gen = kGenFull;
+  gp.n_cand = Nc - 1;
+  gp.n_seg = S;
+  gp.loop = loop;
+  for (int j = 0; j < MPMI_MAX_INPUT; ++j) gp.grid[j] = 1;
+  const int block = 256;
+  select_kernel<MPMI_MAX_INPUT><<<blocks_for(Nc, block), block, 0, st>>>(
+      (const ModelDev*)model, gp, H, cand, fv, u_user, (Slot*)slot, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_gen(const void* model, const mpmi_tick_desc& d, const float* u_user, const float* cand,
+                      float* cand_out, hipStream_t st) {
+  const GenParams gp = make_gen(d);
+  const int block = 256;
+  gen_kernel<<<blocks_for((long long)d.n_cand + 1, block), block, 0, st>>>((const ModelDev*)model, gp, u_user,
+                                                                            cand, cand_out);
+  return hipGetLastError();
+}
+
+size_t model_bytes() { return sizeof(ModelDev); }
+size_t slot_bytes() { return sizeof(Slot); }
+
+}  // namespace mpmi

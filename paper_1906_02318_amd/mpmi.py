@@ -1,0 +1,347 @@
+"""Thin Python binding of libmpmi (include/mpmi.h), same names as the C ABI.
+
+Argument marshalling only: every step of the method runs in the library's
+HIP kernels.  PyTorch provides device memory (tensors) and streams; the
+binding passes their raw pointers.  If libmpmi.so has not been built this
+module raises on first use -- there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmpmi.so")
+
+# Constants mirrored from include/mpmi.h
+ABI_VERSION = 1
+MAX_STATE, MAX_INPUT, MAX_DIM, MAX_BOX = 8, 4, 64, 4
+MAX_HORIZON, MAX_SEGMENTS, MAX_CAND, MAX_LOOPS = 255, 8, 33554431, 4096
+OK, NO_SAFE, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED, ESINGULAR = 0, 1, -1, -2, -3, -4, -5
+BASIS_LINEAR, BASIS_BALANCE_BOT, BASIS_RACE_CAR = 0, 1, 2
+PREC_FP32, PREC_BF16X3 = 0, 1
+GEN_EXPLICIT, GEN_GRID, GEN_UNIFORM = 0, 1, 2
+
+_i32x4 = ctypes.c_int32 * 4
+_f32x4 = ctypes.c_float * 4
+
+
+class System(ctypes.Structure):
+    _fields_ = [
+        ("basis", ctypes.c_int32), ("n_state", ctypes.c_int32), ("n_input", ctypes.c_int32),
+        ("n_box", ctypes.c_int32), ("box_index", _i32x4), ("box_bound", _f32x4), ("box_infl", _f32x4),
+        ("eps_box", _f32x4), ("has_track", ctypes.c_int32), ("track_n", ctypes.c_int32),
+        ("track_freq", _i32x4), ("track_amp", _f32x4), ("track_phase", _f32x4),
+        ("track_r0", ctypes.c_float), ("track_half", ctypes.c_float), ("track_infl", ctypes.c_float),
+        ("eps_track", ctypes.c_float), ("u_lo", _f32x4), ("u_hi", _f32x4),
+    ]
+
+
+class Selection(ctypes.Structure):
+    _fields_ = [
+        ("idx", ctypes.c_int32), ("status", ctypes.c_int32), ("n_safe", ctypes.c_int32),
+        ("n_recheck", ctypes.c_int32), ("u_r", _f32x4), ("cost", ctypes.c_float),
+        ("deviation", ctypes.c_float), ("first_violation", ctypes.c_int32), ("n_cand", ctypes.c_int32),
+    ]
+
+
+SELECTION_BYTES = ctypes.sizeof(Selection)  # 48
+
+
+class TickDesc(ctypes.Structure):
+    _fields_ = [
+        ("seed", ctypes.c_uint64), ("tick", ctypes.c_uint64), ("loop", ctypes.c_int32),
+        ("gen", ctypes.c_int32), ("n_cand", ctypes.c_int32), ("grid", _i32x4),
+        ("n_seg", ctypes.c_int32), ("horizon", ctypes.c_int32), ("precision", ctypes.c_int32),
+        ("block", ctypes.c_int32),
+    ]
+
+
+class MpmiError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"mpmi status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def library() -> ctypes.CDLL:
+    """Loads libmpmi.so (after torch, so both share one HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1906_02318_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    sig = {
+        "mpmi_abi_version": (i32, []),
+        "mpmi_create": (i32, [ctypes.POINTER(vp), i32]),
+        "mpmi_destroy": (None, [vp]),
+        "mpmi_last_error": (ctypes.c_char_p, [vp]),
+        "mpmi_model_bytes": (ctypes.c_size_t, []),
+        "mpmi_model_pack": (i32, [vp, ctypes.POINTER(System), vp, vp, vp]),
+        "koopman_fit": (i32, [vp, ctypes.POINTER(System), vp, vp, vp, i64, f64, vp, ctypes.POINTER(f64), vp]),
+        "rollout_batch": (i32, [vp, vp, i32, vp, vp, i32, i32, i32, vp, vp]),
+        "safe_mask": (i32, [vp, vp, vp, i32, i32, vp, vp, vp]),
+        "select_min_intervention": (i32, [vp, vp, vp, i32, i32, vp, i32, vp, i32, vp, vp]),
+        "mpmi_tick": (i32, [vp, vp, ctypes.POINTER(TickDesc), vp, vp, vp, vp, vp, vp, vp]),
+        "mpmi_generate_candidates": (i32, [vp, vp, ctypes.POINTER(TickDesc), vp, vp, vp, vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    if lib.mpmi_abi_version() != ABI_VERSION:
+        raise RuntimeError(f"libmpmi ABI {lib.mpmi_abi_version()} != binding ABI {ABI_VERSION}")
+    _lib = lib
+    return lib
+
+
+# ---------------------------------------------------------------------------
+# System descriptors (plain data)
+# ---------------------------------------------------------------------------
+def _sys(basis, n, m, box, u_lo, u_hi, track=None, eps_box=None, eps_track=0.0):
+    s = System()
+    s.basis, s.n_state, s.n_input = basis, n, m
+    s.n_box = len(box)
+    for b, (idx, bound, infl) in enumerate(box):
+        s.box_index[b], s.box_bound[b], s.box_infl[b] = idx, bound, infl
+        s.eps_box[b] = 0.0 if eps_box is None else eps_box[b]
+    for j in range(m):
+        s.u_lo[j], s.u_hi[j] = float(u_lo[j]), float(u_hi[j])
+    if track is not None:
+        s.has_track = 1
+        s.track_n = len(track["amp"])
+        for k in range(s.track_n):
+            s.track_freq[k] = int(track["freq"][k])
+            s.track_amp[k] = float(track["amp"][k])
+            s.track_phase[k] = float(track["phase"][k])
+        s.track_r0, s.track_half, s.track_infl = track["r0"], track["half"], track.get("infl", 0.0)
+        s.eps_track = eps_track
+    return s
+
+
+def linear_system(n, m, box, u_lo, u_hi):
+    """psi = [x; u]; box = [(state index, bound, inflation), ...]."""
+    return _sys(BASIS_LINEAR, n, m, box, u_lo, u_hi)
+
+
+def balance_bot_system(theta_bound=0.5, p_bound=2.0, infl=0.0, u_lo=-5.0, u_hi=5.0, eps=(5e-5, 2e-4)):
+    """Cart-pole: |theta| < theta_bound - infl, |p| < p_bound - infl, u in [u_lo, u_hi]."""
+    return _sys(BASIS_BALANCE_BOT, 4, 1, [(2, theta_bound, infl), (0, p_bound, infl)], [u_lo], [u_hi],
+                eps_box=list(eps))
+
+
+def race_car_system(track: dict, vy_bound=2.0, infl=0.0, u_lo=(-0.4, -3.0), u_hi=(0.4, 3.0),
+                    eps_track=0.02, eps_vy=0.02):
+    """Dynamic bicycle on a track (dict r0, half, amp, freq, phase, infl) with |v_y| < vy_bound - infl."""
+    return _sys(BASIS_RACE_CAR, 6, 2, [(4, vy_bound, infl)], u_lo, u_hi, track=track,
+                eps_box=[eps_vy], eps_track=eps_track)
+
+
+# ---------------------------------------------------------------------------
+# Context and calls
+# ---------------------------------------------------------------------------
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _need(t, name, dtype, numel=None, device=None):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if device is not None and t.device != device:
+        raise ValueError(f"{name} is on {t.device}, the context is on {device}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if numel is not None and t.numel() < numel:
+        raise ValueError(f"{name} holds {t.numel()} elements, needs {numel}")
+    return t
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Context:
+    """Owns an mpmi_ctx (selection slots + fit workspace) on one device."""
+
+    def __init__(self, device: int = 0):
+        self.lib = library()
+        self.device = torch.device("cuda", device)
+        torch.cuda.set_device(self.device)
+        h = ctypes.c_void_p()
+        st = self.lib.mpmi_create(ctypes.byref(h), device)
+        if st != OK:
+            raise MpmiError(st, "mpmi_create failed")
+        self.handle = h
+        self._models = []
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.mpmi_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def check(self, st: int):
+        if st != OK:
+            raise MpmiError(st, self.lib.mpmi_last_error(self.handle).decode())
+
+
+@dataclass
+class Model:
+    """A packed model: the device blob plus the host descriptor it came from."""
+
+    blob: torch.Tensor
+    ptr: int
+    system: System
+
+    @property
+    def n(self):
+        return self.system.n_state
+
+    @property
+    def m(self):
+        return self.system.n_input
+
+
+def model_bytes() -> int:
+    return int(library().mpmi_model_bytes())
+
+
+def mpmi_model_pack(ctx: Context, system: System, K: torch.Tensor, stream=None) -> Model:
+    _need(K, "K", torch.float64, device=ctx.device)
+    nbytes = model_bytes()
+    blob = torch.empty(nbytes + 256, dtype=torch.uint8, device=ctx.device)
+    base = blob.data_ptr()
+    ptr = (base + 255) // 256 * 256
+    ctx.check(ctx.lib.mpmi_model_pack(ctx.handle, ctypes.byref(system), _ptr(K), ctypes.c_void_p(ptr),
+                                      _stream(stream)))
+    return Model(blob=blob, ptr=ptr, system=system)
+
+
+def koopman_fit(ctx: Context, system: System, X, U, Y, ridge: float = 0.0, stream=None):
+    """Returns (K (D, n) float64 device tensor, condition estimate of the scaled lifted data)."""
+    T, n = X.shape
+    m = U.shape[1]
+    for t, name in ((X, "X"), (U, "U"), (Y, "Y")):
+        _need(t, name, torch.float64, device=ctx.device)
+    if U.shape[0] != T or Y.shape != X.shape:
+        raise ValueError("X, U, Y must have T rows; Y shaped like X")
+    if n != system.n_state or m != system.n_input:
+        raise ValueError("X/U widths do not match the system")
+    D = {BASIS_LINEAR: n + m, BASIS_BALANCE_BOT: 21, BASIS_RACE_CAR: 64}[system.basis]
+    K = torch.empty((D, n), dtype=torch.float64, device=ctx.device)
+    cond = ctypes.c_double(0.0)
+    ctx.check(ctx.lib.koopman_fit(ctx.handle, ctypes.byref(system), _ptr(X), _ptr(U), _ptr(Y), T, float(ridge),
+                                  _ptr(K), ctypes.byref(cond), _stream(stream)))
+    return K, cond.value
+
+
+def rollout_batch(ctx: Context, model: Model, x0, cand, H: int, traj=None, precision=PREC_FP32, stream=None):
+    """cand (S, m, Nc) float32 -> traj (H, n, Nc) float32 (full horizon)."""
+    S, m, Nc = cand.shape
+    _need(x0, "x0", torch.float32, model.n, device=ctx.device)
+    _need(cand, "cand", torch.float32, device=ctx.device)
+    if traj is None:
+        traj = torch.empty((H, model.n, Nc), dtype=torch.float32, device=ctx.device)
+    _need(traj, "traj", torch.float32, H * model.n * Nc, device=ctx.device)
+    ctx.check(ctx.lib.rollout_batch(ctx.handle, ctypes.c_void_p(model.ptr), precision, _ptr(x0), _ptr(cand),
+                                    Nc, S, H, _ptr(traj), _stream(stream)))
+    return traj
+
+
+def safe_mask(ctx: Context, model: Model, traj, with_margin: bool = True, stream=None):
+    """traj (H, n, Nc) -> (first_violation int16 (Nc,), min_margin float32 (Nc,) or None)."""
+    H, n, Nc = traj.shape
+    _need(traj, "traj", torch.float32, device=ctx.device)
+    fv = torch.empty(Nc, dtype=torch.int16, device=ctx.device)
+    mm = torch.empty(Nc, dtype=torch.float32, device=ctx.device) if with_margin else None
+    ctx.check(ctx.lib.safe_mask(ctx.handle, ctypes.c_void_p(model.ptr), _ptr(traj), Nc, H, _ptr(fv), _ptr(mm),
+                                _stream(stream)))
+    return fv, mm
+
+
+def select_min_intervention(ctx: Context, model: Model, cand, first_violation, H: int, u_user, loop: int = 0,
+                            out=None, stream=None):
+    """cand (S, m, Nc), first_violation int16 (Nc,) -> selection record (uint8 device tensor of 48 B)."""
+    S, m, Nc = cand.shape
+    _need(cand, "cand", torch.float32, device=ctx.device)
+    _need(first_violation, "first_violation", torch.int16, Nc, device=ctx.device)
+    _need(u_user, "u_user", torch.float32, model.m, device=ctx.device)
+    if out is None:
+        out = torch.empty(SELECTION_BYTES, dtype=torch.uint8, device=ctx.device)
+    _need(out, "out", torch.uint8, SELECTION_BYTES, device=ctx.device)
+    ctx.check(ctx.lib.select_min_intervention(ctx.handle, ctypes.c_void_p(model.ptr), _ptr(cand), Nc, S,
+                                              _ptr(first_violation), H, _ptr(u_user), loop, _ptr(out),
+                                              _stream(stream)))
+    return out
+
+
+def tick_desc(n_cand, horizon, gen=GEN_GRID, grid=None, n_seg=1, seed=0, tick=0, loop=0,
+              precision=PREC_FP32, block=0) -> TickDesc:
+    d = TickDesc()
+    d.seed, d.tick, d.loop, d.gen, d.n_cand = seed, tick, loop, gen, n_cand
+    for j, g in enumerate(grid or []):
+        d.grid[j] = g
+    d.n_seg, d.horizon, d.precision, d.block = n_seg, horizon, precision, block
+    return d
+
+
+def mpmi_tick(ctx: Context, model: Model, desc: TickDesc, x_t, u_user, cand=None, out=None,
+              first_violation=None, traj=None, stream=None):
+    """One fused tick; returns the selection record (uint8 device tensor, 48 B)."""
+    _need(x_t, "x_t", torch.float32, model.n, device=ctx.device)
+    _need(u_user, "u_user", torch.float32, model.m, device=ctx.device)
+    Nc = desc.n_cand + 1
+    if cand is not None:
+        _need(cand, "cand", torch.float32, desc.n_seg * model.m * desc.n_cand, device=ctx.device)
+    if first_violation is not None:
+        _need(first_violation, "first_violation", torch.int16, Nc, device=ctx.device)
+    if traj is not None:
+        _need(traj, "traj", torch.float32, desc.horizon * model.n * Nc, device=ctx.device)
+    if out is None:
+        out = torch.empty(SELECTION_BYTES, dtype=torch.uint8, device=ctx.device)
+    _need(out, "out", torch.uint8, SELECTION_BYTES, device=ctx.device)
+    ctx.check(ctx.lib.mpmi_tick(ctx.handle, ctypes.c_void_p(model.ptr), ctypes.byref(desc), _ptr(x_t),
+                                _ptr(u_user), _ptr(cand), _ptr(out), _ptr(first_violation), _ptr(traj),
+                                _stream(stream)))
+    return out
+
+
+def mpmi_generate_candidates(ctx: Context, model: Model, desc: TickDesc, u_user, cand=None, stream=None):
+    """The candidates a tick with `desc` evaluates, (S, m, N+1) float32 (column 0 = u_user)."""
+    _need(u_user, "u_user", torch.float32, model.m, device=ctx.device)
+    if cand is not None:
+        _need(cand, "cand", torch.float32, desc.n_seg * model.m * desc.n_cand, device=ctx.device)
+    out = torch.empty((desc.n_seg, model.m, desc.n_cand + 1), dtype=torch.float32, device=ctx.device)
+    ctx.check(ctx.lib.mpmi_generate_candidates(ctx.handle, ctypes.c_void_p(model.ptr), ctypes.byref(desc),
+                                               _ptr(u_user), _ptr(cand), _ptr(out), _stream(stream)))
+    return out
+
+
+def decode_selection(rec) -> dict:
+    """Host view of one or more selection records (uint8 tensor of 48*k bytes)."""
+    raw = bytes(rec.detach().cpu().numpy().tobytes())
+    out = []
+    for k in range(len(raw) // SELECTION_BYTES):
+        s = Selection.from_buffer_copy(raw[k * SELECTION_BYTES:(k + 1) * SELECTION_BYTES])
+        out.append(dict(idx=s.idx, status=s.status, n_safe=s.n_safe, n_recheck=s.n_recheck,
+                        u_r=list(s.u_r), cost=s.cost, deviation=s.deviation,
+                        first_violation=s.first_violation, n_cand=s.n_cand))
+    return out[0] if len(out) == 1 else out
