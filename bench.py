@@ -1,0 +1,243 @@
+"""Throughput benchmark of the MPMI-SC control tick on one MI355X.
+
+A step is one control tick of the whole hot path -- candidate generation,
+Koopman prediction with early exit, safety checks and the minimal-intervention
+selection -- run as one fused kernel launch over the tick's candidate batch.
+Inputs (model, tick states, user inputs) are resident in HBM before timing.
+
+Prints one JSON line (see the keys below); `value` is candidate trajectories
+per second, every candidate counted once whatever its early exit.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "candidate trajectories/sec + p99 tick latency, plain vs learned proposal"
+PEAK_FP32_VECTOR_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
+
+# Algorithmic FP32 work of one unit (one candidate advanced one step and
+# checked), flops with an FMA counted as 2.
+#   race car: 51 feature products + 64x6 contraction (768) + track/v_y check (62)
+#   balance bot: 15 feature products + 21x4 contraction (168) + two box checks (4)
+FLOPS_PER_UNIT = {"race_car": 881, "balance_bot": 187}
+
+WORKLOADS = {
+    # Race car scaled to the >= 1M candidates-per-tick target: 1024 x 1024 grid.
+    "race_car_1m": dict(system="race_car", grid=[1024, 1024], H=60, gen="grid", S=1),
+    # Race car at its stated size: 128 x 128 grid.
+    "race_car": dict(system="race_car", grid=[128, 128], H=60, gen="grid", S=1),
+    # Balance bot at real-time size: 10,240 five-segment random sequences.
+    "balance_bot_rt": dict(system="balance_bot", N=10240, H=50, gen="uniform", S=5),
+    # Balance bot small: 1,024-point grid.
+    "balance_bot": dict(system="balance_bot", grid=[1024], H=20, gen="grid", S=1),
+}
+
+
+def setup(wl: dict, n_ticks: int):
+    """GPU-side setup through the product path: fit K on the GPU, pack it, and
+    place n_ticks tick inputs in HBM."""
+    import torch
+
+    import synth
+    from paper_1906_02318_amd import mpmi
+
+    ctx = mpmi.Context(0)
+    if wl["system"] == "race_car":
+        track = synth.make_track(3)
+        X, U, Y = synth.race_car_transitions(50000, seed=0, track=track)
+        trd = dict(r0=track.r0, half=track.half_width, amp=list(track.amp), freq=list(track.freq),
+                   phase=list(track.phase), infl=0.0)
+        system = mpmi.race_car_system(trd)
+        xs = synth.race_car_states(n_ticks, track, seed=1)
+        uh = synth.uniform_user(n_ticks, synth.RC_U_LO, synth.RC_U_HI, seed=2)
+    else:
+        track = None
+        X, U, Y = synth.balance_bot_transitions(5000, seed=0)
+        system = mpmi.balance_bot_system()
+        xs = synth.balance_bot_states(n_ticks, seed=1)
+        uh = synth.uniform_user(n_ticks, [synth.BB_U_LO], [synth.BB_U_HI], seed=2)
+    d = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+    K, cond = mpmi.koopman_fit(ctx, system, d(X), d(U), d(Y))
+    model = mpmi.mpmi_model_pack(ctx, system, K)
+    x_dev = torch.tensor(xs, dtype=torch.float32, device="cuda").contiguous()
+    u_dev = torch.tensor(uh, dtype=torch.float32, device="cuda").contiguous()
+    if wl["gen"] == "grid":
+        N = int(np.prod(wl["grid"]))
+        mk = lambda t: mpmi.tick_desc(N, wl["H"], gen=mpmi.GEN_GRID, grid=wl["grid"])
+    else:
+        N = wl["N"]
+        mk = lambda t: mpmi.tick_desc(N, wl["H"], gen=mpmi.GEN_UNIFORM, n_seg=wl["S"], seed=4, tick=t)
+    torch.cuda.synchronize()
+    return dict(ctx=ctx, model=model, K=K, x=x_dev, u=u_dev, xs=xs, uh=uh, N=N, mk=mk, track=track,
+                fit=(X, U, Y), cond=cond)
+
+
+def cpu_baseline(wl: dict, st: dict, budget_s: float = 15.0):
+    """FP64 oracle timed on this host's cores on a bounded sample of the same
+    workload: every k-th candidate of each tick's candidate set."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import mpmi_oracle as o
+
+    cores = len(os.sched_getaffinity(0))
+    X, U, Y = st["fit"]
+    kind = wl["system"]
+    K, _ = o.fit(kind, X, U, Y)
+    if kind == "race_car":
+        tr = st["track"]
+        f32 = lambda v: float(np.float32(v))
+        sysd = o.System("race_car", 6, 2, box=[(4, 2.0, 0.0)],
+                        track=dict(r0=30.0, half=3.0, amp=[f32(a) for a in tr.amp], freq=list(tr.freq),
+                                   phase=[f32(p) for p in tr.phase], infl=0.0),
+                        u_lo=[-0.4, -3.0], u_hi=[0.4, 3.0])
+    else:
+        sysd = o.System("balance_bot", 4, 1, box=[(2, 0.5, 0.0), (0, 2.0, 0.0)], u_lo=[-5.0], u_hi=[5.0])
+    N, H, S = st["N"], wl["H"], wl["S"]
+    stride = max(1, N // 16384)
+    sample = None
+    n_eval, t_used, ticks = 0, 0.0, 0
+    with threadpool_limits(limits=cores):
+        for t in range(len(st["xs"])):
+            if wl["gen"] == "grid":
+                full = o.grid_candidates(sysd, wl["grid"]) if sample is None else None
+                if sample is None:
+                    sample = full[::stride]
+                cand = o.with_user(sample, st["uh"][t].astype(np.float32), 1)
+            else:
+                cand = o.with_user(o.uniform_candidates(sysd, N, S, 4, t, 0)[::stride],
+                                   st["uh"][t].astype(np.float32), S)
+            x = st["xs"][t].astype(np.float32).astype(np.float64)
+            u = st["uh"][t].astype(np.float32).astype(np.float64)
+            t0 = time.perf_counter()
+            o.tick(sysd, K, x, u, cand, H)
+            t_used += time.perf_counter() - t0
+            n_eval += cand.shape[0]
+            ticks += 1
+            if t_used > budget_s:
+                break
+    return dict(value=n_eval / t_used, unit="trajectories/s", cores=cores, kind="oracle",
+                sample=f"{ticks} ticks x {n_eval // ticks} candidates (every {stride}th of the {N}-candidate set "
+                       f"plus u_h), H={H}, FP64 NumPy, {t_used:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="race_car_1m", choices=sorted(WORKLOADS))
+    ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the tick's candidates would shard "
+              f"across GPUs with one 8-byte arg-min exchange per loop, which this build does not run.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1906_02318_amd import mpmi
+
+    wl = WORKLOADS[args.workload]
+    n_inputs = 64
+    st = setup(wl, n_inputs)
+    ctx, model, N, H = st["ctx"], st["model"], st["N"], wl["H"]
+    Nc = N + 1
+    stream = torch.cuda.current_stream()
+    outs = torch.empty((n_inputs, mpmi.SELECTION_BYTES), dtype=torch.uint8, device="cuda")
+    descs = [st["mk"](t) for t in range(n_inputs)]
+    for d in descs:
+        d.block = args.block
+
+    def step(i):
+        t = i % n_inputs
+        mpmi.mpmi_tick(ctx, model, descs[t], st["x"][t], st["u"][t], out=outs[t], stream=stream)
+
+    # Executed units (candidate-steps after early exit), from an untimed pass.
+    fv = torch.empty(Nc, dtype=torch.int16, device="cuda")
+    units = []
+    for t in range(n_inputs):
+        mpmi.mpmi_tick(ctx, model, descs[t], st["x"][t], st["u"][t], out=outs[t], first_violation=fv, stream=stream)
+        units.append(int(torch.clamp(fv.to(torch.int64), max=H).sum().item()))
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ev[i][0].record(stream)
+        step(i)
+        ev[i][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    dev_ms = np.array([a.elapsed_time(b) for a, b in ev])
+    sels = mpmi.decode_selection(outs)
+    n_safe_frac = float(np.mean([s["n_safe"] / N for s in sels]))
+    zero_int = float(np.mean([s["idx"] == 0 for s in sels]))
+
+    ms_per_step = wall * 1e3 / args.steps
+    value = Nc * args.steps / wall
+    units_per_tick = float(np.mean([units[i % n_inputs] for i in range(args.steps)]))
+    avg_kernel_s = float(dev_ms.mean()) * 1e-3
+    flops = FLOPS_PER_UNIT[wl["system"]] * units_per_tick
+    achieved = flops / avg_kernel_s / 1e12
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "trajectories/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "fp32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{args.workload}: {wl['system']} tick, N={N} candidates + u_h, H={H}, "
+                        f"{'grid ' + 'x'.join(map(str, wl['grid'])) if wl['gen'] == 'grid' else 'uniform S=' + str(wl['S'])}",
+            "N": N, "H": H, "system": wl["system"], "precision": "fp32", "plain_or_learned": "plain",
+        },
+        "p50_tick_ms": float(np.percentile(dev_ms, 50)),
+        "p99_tick_ms": float(np.percentile(dev_ms, 99)),
+        "ticks_within_10ms": float(np.mean(dev_ms < 10.0)),
+        "units_per_tick": units_per_tick,
+        "units_per_s": units_per_tick * args.steps / wall,
+        "safe_fraction": n_safe_frac,
+        "zero_intervention_fraction": zero_int,
+        "roofline": {
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": PEAK_FP32_VECTOR_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32_VECTOR_TFLOPS,
+            "traffic": None,
+            "kernel": f"tick_fp32_kernel<{wl['system']}>",
+            "avg_kernel_ms": avg_kernel_s * 1e3,
+            "flops_per_unit": FLOPS_PER_UNIT[wl["system"]],
+        },
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl, st, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

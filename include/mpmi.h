@@ -242,6 +242,83 @@ mpmi_status mpmi_generate_candidates(mpmi_ctx ctx, const void* model,
                                      const float* u_user, const float* cand,
                                      float* cand_out, void* stream);
 
+
+/* ---------------------------------------------------------------------------
+ * Many concurrent control loops in one launch per tick.
+ *
+ * Each loop runs Alg. 2 on its own model, state, user input, candidate count
+ * and horizon.  The (loop, tile) work items of all loops, ordered
+ * longest-processing-time first (horizon x per-step cost), are taken from an
+ * atomic counter by a persistent grid; each loop's selection is finalised by
+ * the workgroup that completes its last tile.  Nothing is allocated and no
+ * host synchronisation happens per tick, so a tick can be captured once in a
+ * HIP graph (mpmi_multi_graph) and replayed.
+ * ------------------------------------------------------------------------- */
+
+/* One loop (host struct, copied into device memory by mpmi_multi_create;
+ * every pointer must stay valid for the life of the mpmi_multi). */
+typedef struct mpmi_loop_desc {
+  const void* model;          /* packed model on this context */
+  const float* x_t;           /* device [n]: current state, read every tick */
+  const float* u_user;        /* device [m]: user input, read every tick */
+  const float* cand;          /* EXPLICIT only: device [S][m][N] */
+  mpmi_selection* out;        /* device: selection written every tick */
+  int16_t* first_violation;   /* optional device [N+1] */
+  uint64_t seed;              /* UNIFORM: generator seed */
+  uint64_t tick;              /* UNIFORM: tick counter of the first tick; the
+                                 device adds one after every completed tick */
+  int32_t gen;                /* MPMI_GEN_* */
+  int32_t n_cand;             /* N */
+  int32_t grid[4];            /* GRID: points per input, product == N */
+  int32_t n_seg;              /* S */
+  int32_t horizon;            /* H */
+} mpmi_loop_desc;
+
+/* Launch shape: `block` threads per workgroup = candidates per tile
+ * (64..1024, multiple of 64); `grid` persistent workgroups (0 = library
+ * default: enough to fill every compute unit). */
+typedef struct mpmi_multi_config {
+  int32_t block;
+  int32_t grid;
+} mpmi_multi_config;
+
+typedef struct mpmi_multi_s* mpmi_multi;
+
+/* Validates the loops, copies them to device memory, builds the ordered
+ * work list for `cfg` (NULL = block 256, default grid) and allocates the
+ * per-loop selection slots.  Synchronous. */
+mpmi_status mpmi_multi_create(mpmi_ctx ctx, const mpmi_loop_desc* loops /* host */, int32_t n_loops,
+                              const mpmi_multi_config* cfg /* host, may be NULL */, mpmi_multi* out);
+void mpmi_multi_destroy(mpmi_multi multi);
+
+/* Re-plans the work list for a new launch shape (synchronous, no allocation). */
+mpmi_status mpmi_multi_set_config(mpmi_ctx ctx, mpmi_multi multi, const mpmi_multi_config* cfg /* host */);
+
+/* Current launch shape and work-list size (host outputs, may be NULL). */
+mpmi_status mpmi_multi_get_config(mpmi_multi multi, mpmi_multi_config* cfg, int32_t* n_work_items);
+
+/* Current device tick counters of the loops, ticks[n_loops] (host).
+ * Synchronous (waits for the device). */
+mpmi_status mpmi_multi_get_ticks(mpmi_ctx ctx, mpmi_multi multi, uint64_t* ticks /* host */);
+
+/* One tick of every loop: one kernel launch on `stream`. */
+mpmi_status mpmi_multi_tick(mpmi_ctx ctx, mpmi_multi multi, void* stream);
+
+/* Autotuner: times `reps` ticks (HIP events on `stream`) for each launch
+ * shape in the library's search space (block 64..512, grid 1..8 workgroups
+ * per compute unit), keeps the fastest, and reports it in *best and its mean
+ * tick time in *best_ms (host, may be NULL).  The timed ticks are real ticks:
+ * they write selections and advance tick counters. */
+mpmi_status mpmi_multi_autotune(mpmi_ctx ctx, mpmi_multi multi, int32_t reps, mpmi_multi_config* best /* host */,
+                                float* best_ms /* host */, void* stream);
+
+/* Captures one mpmi_multi_tick into an instantiated HIP graph (*graph_exec,
+ * a hipGraphExec_t).  Replays read x_t / u_user at the loops' fixed
+ * pointers, so the caller updates those buffers between replays. */
+mpmi_status mpmi_multi_graph(mpmi_ctx ctx, mpmi_multi multi, void** graph_exec);
+mpmi_status mpmi_graph_launch(mpmi_ctx ctx, void* graph_exec, void* stream);
+void mpmi_graph_destroy(void* graph_exec);
+
 #ifdef __cplusplus
 }
 #endif

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdarg>
+#include <cstddef>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -321,6 +322,186 @@ mpmi_status mpmi_generate_candidates(mpmi_ctx ctx, const void* model, const mpmi
     return fail(ctx, MPMI_EINVAL, "EXPLICIT candidates need cand");
   return check_hip(ctx, mpmi::launch_gen(model, *desc, u_user, cand, cand_out, (hipStream_t)stream),
                    "mpmi_generate_candidates launch");
+}
+
+struct mpmi_multi_s {
+  mpmi::MultiPlan plan;
+};
+
+mpmi_status mpmi_multi_create(mpmi_ctx ctx, const mpmi_loop_desc* loops, int32_t n_loops,
+                              const mpmi_multi_config* cfg, mpmi_multi* out) {
+  if (!ctx) return MPMI_EINVAL;
+  if (!out) return fail(ctx, MPMI_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!loops) return fail(ctx, MPMI_EINVAL, "loops is NULL");
+  if (n_loops < 1 || n_loops > MPMI_MAX_LOOPS)
+    return fail(ctx, MPMI_EINVAL, "n_loops=%d out of 1..%d", n_loops, MPMI_MAX_LOOPS);
+  const int block = cfg ? cfg->block : 256;
+  const int grid = cfg ? cfg->grid : 0;
+  if (block < 64 || block > 1024 || block % 64 != 0)
+    return fail(ctx, MPMI_EINVAL, "block=%d must be a multiple of 64 in 64..1024", block);
+  if (grid < 0) return fail(ctx, MPMI_EINVAL, "grid=%d must be >= 0", grid);
+  mpmi_multi m = new (std::nothrow) mpmi_multi_s();
+  if (!m) return fail(ctx, MPMI_ENOMEM, "out of host memory");
+  m->plan.n_loops = n_loops;
+  for (int l = 0; l < n_loops; ++l) {
+    const mpmi_loop_desc& L = loops[l];
+    mpmi_system sys;
+    mpmi_status s = model_system(ctx, L.model, &sys, nullptr);
+    if (s != MPMI_OK) {
+      delete m;
+      return fail(ctx, s, "loop %d: %s", l, ctx->err.c_str());
+    }
+    mpmi_tick_desc d{};
+    d.seed = L.seed;
+    d.tick = L.tick;
+    d.loop = 0;
+    d.gen = L.gen;
+    d.n_cand = L.n_cand;
+    for (int j = 0; j < 4; ++j) d.grid[j] = L.grid[j];
+    d.n_seg = L.n_seg;
+    d.horizon = L.horizon;
+    d.precision = MPMI_PREC_FP32;
+    s = validate_desc(ctx, sys, &d);
+    if (s != MPMI_OK) {
+      delete m;
+      return fail(ctx, s, "loop %d: %s", l, ctx->err.c_str());
+    }
+    if (!L.x_t || !L.u_user || !L.out || (L.gen == MPMI_GEN_EXPLICIT && L.n_cand > 0 && !L.cand)) {
+      delete m;
+      return fail(ctx, MPMI_EINVAL, "loop %d: x_t, u_user, out (and cand for EXPLICIT) must be non-NULL", l);
+    }
+    m->plan.host.push_back(L);
+    m->plan.basis.push_back(sys.basis);
+  }
+  hipError_t e = mpmi::multi_alloc(m->plan);
+  if (e == hipSuccess) e = mpmi::multi_plan(m->plan, block, grid);
+  if (e != hipSuccess) {
+    mpmi::multi_free(m->plan);
+    delete m;
+    return fail(ctx, e == hipErrorOutOfMemory ? MPMI_ENOMEM : MPMI_EDEVICE, "mpmi_multi_create: %s",
+                hipGetErrorString(e));
+  }
+  *out = m;
+  return ok(ctx);
+}
+
+void mpmi_multi_destroy(mpmi_multi m) {
+  if (!m) return;
+  mpmi::multi_free(m->plan);
+  delete m;
+}
+
+mpmi_status mpmi_multi_set_config(mpmi_ctx ctx, mpmi_multi m, const mpmi_multi_config* cfg) {
+  if (!ctx) return MPMI_EINVAL;
+  if (!m || !cfg) return fail(ctx, MPMI_EINVAL, "multi and cfg must be non-NULL");
+  if (cfg->block < 64 || cfg->block > 1024 || cfg->block % 64 != 0)
+    return fail(ctx, MPMI_EINVAL, "block=%d must be a multiple of 64 in 64..1024", cfg->block);
+  if (cfg->grid < 0) return fail(ctx, MPMI_EINVAL, "grid=%d must be >= 0", cfg->grid);
+  return check_hip(ctx, mpmi::multi_plan(m->plan, cfg->block, cfg->grid), "mpmi_multi_set_config");
+}
+
+mpmi_status mpmi_multi_get_config(mpmi_multi m, mpmi_multi_config* cfg, int32_t* n_work_items) {
+  if (!m) return MPMI_EINVAL;
+  if (cfg) {
+    cfg->block = m->plan.block;
+    cfg->grid = m->plan.grid;
+  }
+  if (n_work_items) *n_work_items = m->plan.n_work;
+  return MPMI_OK;
+}
+
+mpmi_status mpmi_multi_get_ticks(mpmi_ctx ctx, mpmi_multi m, uint64_t* ticks) {
+  if (!ctx) return MPMI_EINVAL;
+  if (!m || !ticks) return fail(ctx, MPMI_EINVAL, "multi and ticks must be non-NULL");
+  hipError_t e = hipDeviceSynchronize();
+  if (e == hipSuccess)
+    e = hipMemcpy2D(ticks, sizeof(uint64_t), (const char*)m->plan.d_loops + offsetof(mpmi_loop_desc, tick),
+                    sizeof(mpmi_loop_desc), sizeof(uint64_t), (size_t)m->plan.n_loops, hipMemcpyDeviceToHost);
+  return check_hip(ctx, e, "mpmi_multi_get_ticks");
+}
+
+mpmi_status mpmi_multi_tick(mpmi_ctx ctx, mpmi_multi m, void* stream) {
+  if (!ctx) return MPMI_EINVAL;
+  if (!m) return fail(ctx, MPMI_EINVAL, "multi is NULL");
+  return check_hip(ctx, mpmi::multi_launch(m->plan, (hipStream_t)stream), "mpmi_multi_tick launch");
+}
+
+mpmi_status mpmi_multi_autotune(mpmi_ctx ctx, mpmi_multi m, int32_t reps, mpmi_multi_config* best,
+                                float* best_ms, void* stream) {
+  if (!ctx) return MPMI_EINVAL;
+  if (!m) return fail(ctx, MPMI_EINVAL, "multi is NULL");
+  if (reps < 1 || reps > 100000) return fail(ctx, MPMI_EINVAL, "reps=%d out of 1..100000", reps);
+  hipStream_t st = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return fail(ctx, MPMI_EDEVICE, "hipEventCreate failed");
+  const int ncu = mpmi::device_cu_count();
+  float bms = 1e30f;
+  mpmi_multi_config bcfg{m->plan.block, m->plan.grid};
+  hipError_t e = hipSuccess;
+  for (int block : {64, 128, 256, 512}) {
+    const int maxb = mpmi::multi_max_blocks_per_cu(block);
+    for (int wpc : {1, 2, 4, 8}) {
+      if (wpc > maxb) continue;
+      if ((e = mpmi::multi_plan(m->plan, block, ncu * wpc)) != hipSuccess) break;
+      for (int w = 0; w < 2 && e == hipSuccess; ++w) e = mpmi::multi_launch(m->plan, st);
+      if (e == hipSuccess) e = hipEventRecord(e0, st);
+      for (int r = 0; r < reps && e == hipSuccess; ++r) e = mpmi::multi_launch(m->plan, st);
+      if (e == hipSuccess) e = hipEventRecord(e1, st);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.0f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e != hipSuccess) break;
+      ms /= (float)reps;
+      if (ms < bms) {
+        bms = ms;
+        bcfg.block = block;
+        bcfg.grid = m->plan.grid;
+      }
+    }
+    if (e != hipSuccess) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return fail(ctx, MPMI_EDEVICE, "mpmi_multi_autotune: %s", hipGetErrorString(e));
+  e = mpmi::multi_plan(m->plan, bcfg.block, bcfg.grid);
+  if (e != hipSuccess) return fail(ctx, MPMI_EDEVICE, "mpmi_multi_autotune: %s", hipGetErrorString(e));
+  if (best) *best = bcfg;
+  if (best_ms) *best_ms = bms;
+  return ok(ctx);
+}
+
+mpmi_status mpmi_multi_graph(mpmi_ctx ctx, mpmi_multi m, void** graph_exec) {
+  if (!ctx) return MPMI_EINVAL;
+  if (!m || !graph_exec) return fail(ctx, MPMI_EINVAL, "multi and graph_exec must be non-NULL");
+  *graph_exec = nullptr;
+  hipStream_t s = nullptr;
+  hipGraph_t g = nullptr;
+  hipGraphExec_t ge = nullptr;
+  hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    hipError_t el = mpmi::multi_launch(m->plan, s);
+    e = hipStreamEndCapture(s, &g);
+    if (el != hipSuccess) e = el;
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+  if (g) (void)hipGraphDestroy(g);
+  if (s) (void)hipStreamDestroy(s);
+  if (e != hipSuccess) return fail(ctx, MPMI_EDEVICE, "mpmi_multi_graph: %s", hipGetErrorString(e));
+  *graph_exec = (void*)ge;
+  return ok(ctx);
+}
+
+mpmi_status mpmi_graph_launch(mpmi_ctx ctx, void* graph_exec, void* stream) {
+  if (!ctx) return MPMI_EINVAL;
+  if (!graph_exec) return fail(ctx, MPMI_EINVAL, "graph_exec is NULL");
+  return check_hip(ctx, hipGraphLaunch((hipGraphExec_t)graph_exec, (hipStream_t)stream), "mpmi_graph_launch");
+}
+
+void mpmi_graph_destroy(void* graph_exec) {
+  if (graph_exec) (void)hipGraphExecDestroy((hipGraphExec_t)graph_exec);
 }
 
 }  // extern "C"

@@ -114,7 +114,19 @@ __device__ __forceinline__ float gen_value(const GenParams& gp, const ModelDev* 
 }
 
 // ---------------------------------------------------------------------------
-// Koopman step x' = psi(x, u)^T K (Sec. IV-A), FP32, K read as uniform values.
+// Koopman step x' = psi(x, u)^T K (Sec. IV-A), FP32.
+//
+// K is staged once per workgroup in LDS and read inside every step with
+// 16-byte broadcast loads; an opaque zero offset added to the LDS base at
+// every step keeps the compiler from hoisting those loads out of the horizon
+// loop (hoisted, the race-car coefficients overflow the scalar register file).
+//
+// The input is constant within a segment, so every feature that involves the
+// input (input-only terms and state x input products) is folded once per
+// segment into per-lane coefficients: a constant c_u, a linear map L on the
+// state and, for the race car, the coefficients of sin/cos of the heading.
+// A step then evaluates only the features made of state alone.  This is an
+// exact regrouping of psi^T K in real arithmetic.
 // ---------------------------------------------------------------------------
 template <int BASIS>
 struct Dims;
@@ -125,102 +137,209 @@ struct Dims<MPMI_BASIS_BALANCE_BOT> { static constexpr int N = 4, M = 1; };
 template <>
 struct Dims<MPMI_BASIS_RACE_CAR> { static constexpr int N = 6, M = 2; };
 
+// Index of the quadratic feature w_k w_l (k <= l) in a basis [1, w_0..w_{nw-1}, w_k w_l ...].
+__host__ __device__ constexpr int quad_index(int k, int l, int nw) {
+  return 1 + nw + (k * nw - (k * (k - 1)) / 2) + (l - k);
+}
+
+// LDS layout of the staged K (float offsets):
+//   LINEAR       rows padded to 8 floats                           [0, 8 D)
+//   BALANCE_BOT  all 21 rows, 4 floats each                        [0, 84)
+//                the 10 state-state quadratic rows (k <= l < 4)    [84, 124)
+//   RACE_CAR     all 64 rows, 6 floats each                        [0, 384)
+//                the 21 state-state quadratic rows (k <= l < 6), then
+//                sp*vx, sp*vy, sp*r, cp*vx, cp*vy, cp*r, 6 floats each  [384, 546)
+constexpr int kBbStepOff = 84;
+constexpr int kRcStepOff = 384;
+constexpr int kRcStepRows = 27;
+constexpr int kLdsKFloat4 = 137;  // 546 floats rounded up to float4
+
 template <int BASIS>
-__device__ __forceinline__ void koopman_step(const ModelDev* __restrict__ md, float* x, const float* u);
+__device__ __forceinline__ void stage_K(const ModelDev* __restrict__ md, float4* sK) {
+  float* f = reinterpret_cast<float*>(sK);
+  const int t = threadIdx.x, nt = blockDim.x;
+  if constexpr (BASIS == MPMI_BASIS_LINEAR) {
+    for (int e = t; e < md->dim * 8; e += nt) f[e] = md->K[e >> 3][e & 7];
+  } else if constexpr (BASIS == MPMI_BASIS_BALANCE_BOT) {
+    for (int e = t; e < 21 * 4; e += nt) f[e] = md->K[e >> 2][e & 3];
+    for (int e = t; e < 10 * 4; e += nt) {
+      const int q = e >> 2, j = e & 3;
+      int k = 0, r = q;
+      while (r >= 4 - k) { r -= 4 - k; ++k; }
+      f[kBbStepOff + e] = md->K[quad_index(k, k + r, 5)][j];
+    }
+  } else {
+    for (int e = t; e < 64 * 6; e += nt) f[e] = md->K[e / 6][e % 6];
+    for (int e = t; e < kRcStepRows * 6; e += nt) {
+      const int q = e / 6, j = e % 6;
+      int row;
+      if (q < 21) {
+        int k = 0, r = q;
+        while (r >= 6 - k) { r -= 6 - k; ++k; }
+        row = quad_index(k, k + r, 8);
+      } else {
+        constexpr int trig_rows[6] = {49, 50, 51, 53, 54, 55};  // sp*{vx,vy,r}, cp*{vx,vy,r}
+        row = trig_rows[q - 21];
+      }
+      f[kRcStepOff + e] = md->K[row][j];
+    }
+  }
+  __syncthreads();
+}
 
-// psi = w = [x; u] with run-time n, m.
+__device__ __forceinline__ const float4* opaque_lds(const float4* sK) {
+  int off = 0;
+  asm volatile("" : "+s"(off));
+  return sK + off;
+}
+
+template <int BASIS>
+struct Stepper;
+
+// psi = w = [x; u] with run-time n, m (identity basis; used for checks).
 template <>
-__device__ __forceinline__ void koopman_step<MPMI_BASIS_LINEAR>(const ModelDev* __restrict__ md,
-                                                                float* x, const float* u) {
-  constexpr int NM = MPMI_MAX_STATE, MM = MPMI_MAX_INPUT;
-  const int n = md->n, m = md->m;
-  float y[NM];
+struct Stepper<MPMI_BASIS_LINEAR> {
+  float u[MPMI_MAX_INPUT];
+  __device__ __forceinline__ void set_input(const ModelDev* __restrict__, const float4*, const float* uin) {
 #pragma unroll
-  for (int j = 0; j < NM; ++j) y[j] = 0.0f;
-#pragma unroll
-  for (int f = 0; f < NM; ++f) {
-    if (f < n) {
-#pragma unroll
-      for (int j = 0; j < NM; ++j) y[j] = fmaf(x[f], md->K[f][j], y[j]);
-    }
+    for (int j = 0; j < MPMI_MAX_INPUT; ++j) u[j] = uin[j];
   }
+  __device__ __forceinline__ void step(const ModelDev* __restrict__ md, const float4* sK, float* x) {
+    constexpr int NM = MPMI_MAX_STATE, MM = MPMI_MAX_INPUT;
+    const int n = md->n, m = md->m;
+    const float4* k = opaque_lds(sK);
+    float y[NM];
 #pragma unroll
-  for (int f = 0; f < MM; ++f) {
-    if (f < m) {
+    for (int j = 0; j < NM; ++j) y[j] = 0.0f;
 #pragma unroll
-      for (int j = 0; j < NM; ++j) y[j] = fmaf(u[f], md->K[n + f][j], y[j]);
+    for (int f = 0; f < NM + MM; ++f) {
+      const bool on = (f < NM) ? (f < n) : (f - NM < m);
+      if (on) {
+        const int row = (f < NM) ? f : n + (f - NM);
+        const float w = (f < NM) ? x[f] : u[f - NM];
+        const float4 a = k[2 * row], b = k[2 * row + 1];
+        y[0] = fmaf(w, a.x, y[0]); y[1] = fmaf(w, a.y, y[1]); y[2] = fmaf(w, a.z, y[2]); y[3] = fmaf(w, a.w, y[3]);
+        y[4] = fmaf(w, b.x, y[4]); y[5] = fmaf(w, b.y, y[5]); y[6] = fmaf(w, b.z, y[6]); y[7] = fmaf(w, b.w, y[7]);
+      }
     }
-  }
 #pragma unroll
-  for (int j = 0; j < NM; ++j) x[j] = (j < n) ? y[j] : 0.0f;
-}
+    for (int j = 0; j < NM; ++j) x[j] = (j < n) ? y[j] : 0.0f;
+  }
+};
 
-// [1, w_0..w_4, w_k w_l (k <= l)], w = [p, pd, th, thd, u].
+// Balance bot: [1, w_0..w_4, w_k w_l (k <= l)], w = [p, pd, th, thd, u].
 template <>
-__device__ __forceinline__ void koopman_step<MPMI_BASIS_BALANCE_BOT>(const ModelDev* __restrict__ md,
-                                                                     float* x, const float* u) {
-  const float w[5] = {x[0], x[1], x[2], x[3], u[0]};
-  float y[4];
+struct Stepper<MPMI_BASIS_BALANCE_BOT> {
+  float cu[4];     // 1, u, u^2 terms
+  float L[4][4];   // x_k and x_k u terms
+  __device__ __forceinline__ void set_input(const ModelDev* __restrict__, const float4* sK, const float* uin) {
+    const float* K = reinterpret_cast<const float*>(sK);
+    const float u = uin[0];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) y[j] = md->K[0][j];
+    for (int j = 0; j < 4; ++j) {
+      cu[j] = fmaf(u * u, K[quad_index(4, 4, 5) * 4 + j], fmaf(u, K[5 * 4 + j], K[j]));
 #pragma unroll
-  for (int k = 0; k < 5; ++k) {
-#pragma unroll
-    for (int j = 0; j < 4; ++j) y[j] = fmaf(w[k], md->K[1 + k][j], y[j]);
-  }
-  int f = 6;
-#pragma unroll
-  for (int k = 0; k < 5; ++k) {
-#pragma unroll
-    for (int l = k; l < 5; ++l) {
-      const float p = w[k] * w[l];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) y[j] = fmaf(p, md->K[f][j], y[j]);
-      ++f;
+      for (int k = 0; k < 4; ++k) L[k][j] = fmaf(u, K[quad_index(k, 4, 5) * 4 + j], K[(1 + k) * 4 + j]);
     }
   }
+  __device__ __forceinline__ void step(const ModelDev* __restrict__, const float4* sK, float* x) {
+    float y[4];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) x[j] = y[j];
-}
+    for (int j = 0; j < 4; ++j) {
+      y[j] = cu[j];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) y[j] = fmaf(L[k][j], x[k], y[j]);
+    }
+    const float4* kk = opaque_lds(sK) + kBbStepOff / 4;
+    int q = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int l = k; l < 4; ++l) {
+        const float p = x[k] * x[l];
+        const float4 a = kk[q++];
+        y[0] = fmaf(p, a.x, y[0]); y[1] = fmaf(p, a.y, y[1]); y[2] = fmaf(p, a.z, y[2]); y[3] = fmaf(p, a.w, y[3]);
+      }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) x[j] = y[j];
+  }
+};
 
-// Race-car basis; sd, cd = sin/cos of the steering input (constant within a
-// segment, so the caller evaluates them once per segment).
-__device__ __forceinline__ void race_car_step(const ModelDev* __restrict__ md, float* x,
-                                              const float* u, float sd, float cd) {
-  const float w[8] = {x[0], x[1], x[2], x[3], x[4], x[5], u[0], u[1]};
-  float sp, cp;
-  sincosf(x[2], &sp, &cp);
-  float y[6];
+// Race car: w = [x, y, psi, vx, vy, r, delta, a].
+template <>
+struct Stepper<MPMI_BASIS_RACE_CAR> {
+  float cu[6];     // 1, delta, a, delta^2, delta a, a^2, sin/cos delta, a sin delta terms
+  float L[6][6];   // x_k, x_k delta, x_k a, and sin/cos delta * (vx, vy, r) terms
+  float Ts[6];     // sin psi and a sin psi terms
+  float Tc[6];     // cos psi and a cos psi terms
+  __device__ __forceinline__ void set_input(const ModelDev* __restrict__, const float4* sK, const float* uin) {
+    const float* K = reinterpret_cast<const float*>(sK);
+    const float d = uin[0], a = uin[1];
+    float sd, cd;
+    sincosf(d, &sd, &cd);
 #pragma unroll
-  for (int j = 0; j < 6; ++j) y[j] = md->K[0][j];
+    for (int j = 0; j < 6; ++j) {
+      float c = K[j];
+      c = fmaf(d, K[7 * 6 + j], c);
+      c = fmaf(a, K[8 * 6 + j], c);
+      c = fmaf(d * d, K[quad_index(6, 6, 8) * 6 + j], c);
+      c = fmaf(d * a, K[quad_index(6, 7, 8) * 6 + j], c);
+      c = fmaf(a * a, K[quad_index(7, 7, 8) * 6 + j], c);
+      c = fmaf(sd, K[47 * 6 + j], c);
+      c = fmaf(cd, K[48 * 6 + j], c);
+      c = fmaf(a * sd, K[63 * 6 + j], c);
+      cu[j] = c;
 #pragma unroll
-  for (int k = 0; k < 8; ++k) {
-#pragma unroll
-    for (int j = 0; j < 6; ++j) y[j] = fmaf(w[k], md->K[1 + k][j], y[j]);
-  }
-  int f = 9;
-#pragma unroll
-  for (int k = 0; k < 8; ++k) {
-#pragma unroll
-    for (int l = k; l < 8; ++l) {
-      const float p = w[k] * w[l];
-#pragma unroll
-      for (int j = 0; j < 6; ++j) y[j] = fmaf(p, md->K[f][j], y[j]);
-      ++f;
+      for (int k = 0; k < 6; ++k)
+        L[k][j] = fmaf(a, K[quad_index(k, 7, 8) * 6 + j], fmaf(d, K[quad_index(k, 6, 8) * 6 + j], K[(1 + k) * 6 + j]));
+      L[3][j] = fmaf(cd, K[60 * 6 + j], fmaf(sd, K[57 * 6 + j], L[3][j]));
+      L[4][j] = fmaf(cd, K[61 * 6 + j], fmaf(sd, K[58 * 6 + j], L[4][j]));
+      L[5][j] = fmaf(cd, K[62 * 6 + j], fmaf(sd, K[59 * 6 + j], L[5][j]));
+      Ts[j] = fmaf(a, K[52 * 6 + j], K[45 * 6 + j]);
+      Tc[j] = fmaf(a, K[56 * 6 + j], K[46 * 6 + j]);
     }
   }
-  const float vx = w[3], vy = w[4], r = w[5], a = w[7];
-  const float extra[19] = {sp,      cp,      sd,      cd,      sp * vx, sp * vy, sp * r,
-                           sp * a,  cp * vx, cp * vy, cp * r,  cp * a,  sd * vx, sd * vy,
-                           sd * r,  cd * vx, cd * vy, cd * r,  a * sd};
+  __device__ __forceinline__ void step(const ModelDev* __restrict__, const float4* sK, float* x) {
+    float sp, cp;
+    sincosf(x[2], &sp, &cp);
+    float p[kRcStepRows + 1];
+    int q = 0;
 #pragma unroll
-  for (int e = 0; e < 19; ++e) {
+    for (int k = 0; k < 6; ++k)
 #pragma unroll
-    for (int j = 0; j < 6; ++j) y[j] = fmaf(extra[e], md->K[45 + e][j], y[j]);
+      for (int l = k; l < 6; ++l) p[q++] = x[k] * x[l];
+    p[21] = sp * x[3]; p[22] = sp * x[4]; p[23] = sp * x[5];
+    p[24] = cp * x[3]; p[25] = cp * x[4]; p[26] = cp * x[5];
+    p[27] = 0.0f;
+    float y[6];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      float v = fmaf(Tc[j], cp, fmaf(Ts[j], sp, cu[j]));
+#pragma unroll
+      for (int k = 0; k < 6; ++k) v = fmaf(L[k][j], x[k], v);
+      y[j] = v;
+    }
+    const float4* kk = opaque_lds(sK) + kRcStepOff / 4;
+#pragma unroll
+    for (int r = 0; r < 13; ++r) {
+      const float4 a = kk[3 * r], b = kk[3 * r + 1], c = kk[3 * r + 2];
+      const float p0 = p[2 * r], p1 = p[2 * r + 1];
+      y[0] = fmaf(p0, a.x, y[0]); y[1] = fmaf(p0, a.y, y[1]); y[2] = fmaf(p0, a.z, y[2]);
+      y[3] = fmaf(p0, a.w, y[3]); y[4] = fmaf(p0, b.x, y[4]); y[5] = fmaf(p0, b.y, y[5]);
+      y[0] = fmaf(p1, b.z, y[0]); y[1] = fmaf(p1, b.w, y[1]); y[2] = fmaf(p1, c.x, y[2]);
+      y[3] = fmaf(p1, c.y, y[3]); y[4] = fmaf(p1, c.z, y[4]); y[5] = fmaf(p1, c.w, y[5]);
+    }
+    {
+      const float4 a = kk[39];
+      const float2 b = *reinterpret_cast<const float2*>(kk + 40);
+      const float p0 = p[26];
+      y[0] = fmaf(p0, a.x, y[0]); y[1] = fmaf(p0, a.y, y[1]); y[2] = fmaf(p0, a.z, y[2]);
+      y[3] = fmaf(p0, a.w, y[3]); y[4] = fmaf(p0, b.x, y[4]); y[5] = fmaf(p0, b.y, y[5]);
+    }
+#pragma unroll
+    for (int j = 0; j < 6; ++j) x[j] = y[j];
   }
-#pragma unroll
-  for (int j = 0; j < 6; ++j) x[j] = y[j];
-}
+};
 
 // ---------------------------------------------------------------------------
 // Safety margins (Sec. IV-B geometric checks, Sec. V-C-1 inflation)
@@ -246,13 +365,13 @@ __device__ __forceinline__ float min_margin(const ModelDev* __restrict__ md, con
     mm = fminf(mm, mg);
   }
   if (md->hmax >= 0 && md->sys.has_track) {
-    const float rho = sqrtf(x[0] * x[0] + x[1] * x[1]);
-    float c1 = 1.0f, s1 = 0.0f;
-    if (rho > 0.0f) {
-      const float inv = 1.0f / rho;
-      c1 = x[0] * inv;
-      s1 = x[1] * inv;
-    }
+    // rho, cos phi, sin phi from one reciprocal square root (rho = 0 or an
+    // infinite coordinate gives NaN, i.e. unsafe; the centreline radius is
+    // far larger than the half-width there anyway).
+    const float r2 = fmaf(x[0], x[0], x[1] * x[1]);
+    const float inv = __builtin_amdgcn_rsqf(r2);
+    const float rho = r2 * inv;
+    const float c1 = x[0] * inv, s1 = x[1] * inv;
     float rc = md->trk_r0;
     float ch = 1.0f, sh = 0.0f;
     const int hmax = md->hmax;

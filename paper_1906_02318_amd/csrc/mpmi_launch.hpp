@@ -6,6 +6,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "../../include/mpmi.h"
 
 namespace mpmi {
@@ -31,5 +33,30 @@ hipError_t launch_gen(const void* model, const mpmi_tick_desc& d, const float* u
 size_t fit_workspace_bytes();
 hipError_t launch_fit(const mpmi_system& sys, int dim, const double* X, const double* U, const double* Y,
                       int64_t T, double ridge, double* K_out, void* work, hipStream_t st);
+
+// Many-loop tick (mpmi_multi.hip).
+struct WorkItem;
+struct MultiState;
+struct Slot;
+struct MultiPlan {
+  int n_loops = 0;
+  mpmi_loop_desc* d_loops = nullptr;  // device copy of the loop table
+  int* d_ntiles = nullptr;            // tiles per loop for the current block size
+  WorkItem* d_work = nullptr;         // ordered (loop, tile) items
+  MultiState* d_state = nullptr;      // work counter + exit counter
+  Slot* d_slots = nullptr;            // one selection slot per loop
+  size_t work_capacity = 0;
+  int n_work = 0;
+  int block = 256;
+  int grid = 0;
+  std::vector<mpmi_loop_desc> host;
+  std::vector<int> basis;
+};
+hipError_t multi_alloc(MultiPlan& p);
+void multi_free(MultiPlan& p);
+hipError_t multi_plan(MultiPlan& p, int block, int grid);
+hipError_t multi_launch(const MultiPlan& p, hipStream_t st);
+int multi_max_blocks_per_cu(int block);
+int device_cu_count();
 
 }  // namespace mpmi

@@ -4,8 +4,8 @@
 //
 // Work decomposition: one candidate per lane (candidates are independent,
 // Alg. 2's parallel loop), the state kept in VGPRs across the whole horizon,
-// K read through uniform (scalar) loads from the packed model, so the
-// contraction is VALU FMAs with an SGPR operand and no LDS traffic.  The
+// K staged once per workgroup in LDS and read with broadcast loads, so the
+// contraction is VALU FMAs fed from LDS with no HBM traffic.  The
 // arg-min is a 64-bit key reduced across the wave with shuffles, across the
 // workgroup in LDS, and across workgroups with one atomicMin per workgroup;
 // the last workgroup to finish decodes the key (no second launch).
@@ -13,123 +13,9 @@
 
 #include "mpmi_device.hpp"
 #include "mpmi_launch.hpp"
+#include "mpmi_tick_common.hpp"
 
 namespace mpmi {
-
-// Candidate source modes: the three public generators plus FULL (an explicit
-// array that already holds candidate 0 in column 0).
-constexpr int kGenFull = 3;
-
-__device__ __forceinline__ float cand_value(const GenParams& gp, const ModelDev* __restrict__ md,
-                                            const float* __restrict__ cand,
-                                            const float* __restrict__ u_user, int c, int g, int j) {
-  if (gp.gen == kGenFull) return cand[(size_t)(g * md->m + j) * (size_t)(gp.n_cand + 1) + (size_t)c];
-  if (c == 0) return u_user[j];
-  return gen_value(gp, md, cand, c, g, j);
-}
-
-template <int MS>
-__device__ __forceinline__ float cost_of(const ModelDev* __restrict__ md, const float* u0,
-                                         const float* __restrict__ u_user) {
-  float cst = 0.0f;
-#pragma unroll
-  for (int j = 0; j < MS; ++j) {
-    if (j < md->m) {
-      const float d = (u0[j] - u_user[j]) * md->half_inv[j];
-      cst = fmaf(d, d, cst);
-    }
-  }
-  return cst;
-}
-
-// Workgroup reduction of the two keys and the safe count, then one atomic of
-// each per workgroup; returns true in every thread of the last workgroup.
-__device__ __forceinline__ bool reduce_and_publish(unsigned long long ks, unsigned long long kf,
-                                                   bool safe_counted, Slot* __restrict__ slot) {
-  __shared__ unsigned long long s_ks[16], s_kf[16];
-  __shared__ unsigned int s_cnt[16];
-  __shared__ int s_last;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  ks = wave_min_u64(ks);
-  kf = wave_min_u64(kf);
-  const unsigned int cnt = (unsigned int)__popcll(__ballot(safe_counted));
-  if (lane == 0) {
-    s_ks[wave] = ks;
-    s_kf[wave] = kf;
-    s_cnt[wave] = cnt;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const int nw = (blockDim.x + 63) >> 6;
-    unsigned long long bks = kKeyNone, bkf = kKeyNone;
-    unsigned int bcnt = 0;
-    for (int w = 0; w < nw; ++w) {
-      bks = s_ks[w] < bks ? s_ks[w] : bks;
-      bkf = s_kf[w] < bkf ? s_kf[w] : bkf;
-      bcnt += s_cnt[w];
-    }
-    if (bks != kKeyNone) atomicMin(&slot->key_safe, bks);
-    if (bkf != kKeyNone) atomicMin(&slot->key_fb, bkf);
-    if (bcnt) atomicAdd(&slot->n_safe, bcnt);
-    __threadfence();
-    const unsigned int prev = atomicAdd(&slot->done, 1u);
-    s_last = (prev == gridDim.x - 1);
-  }
-  __syncthreads();
-  return s_last != 0;
-}
-
-// Decodes the slot into the selection and resets the slot (one thread).
-template <int MS>
-__device__ void finalize(const ModelDev* __restrict__ md, const GenParams& gp,
-                         const float* __restrict__ cand, const float* __restrict__ u_user, int H,
-                         Slot* __restrict__ slot, mpmi_selection* __restrict__ out) {
-  __threadfence();
-  const unsigned long long ks = atomicMin(&slot->key_safe, kKeyNone);
-  const unsigned long long kf = atomicMin(&slot->key_fb, kKeyNone);
-  const unsigned int n_safe = atomicAdd(&slot->n_safe, 0u);
-  const unsigned int n_re = atomicAdd(&slot->n_recheck, 0u);
-  int idx, status, fv;
-  float cost;
-  if (ks != kKeyNone) {
-    idx = (int)(ks & 0xffffffffull);
-    cost = __uint_as_float((unsigned int)(ks >> 32));
-    status = MPMI_OK;
-    fv = H + 1;
-  } else {
-    idx = (int)(kf & 0x1ffffffull);
-    cost = __uint_as_float((unsigned int)((kf >> 25) & 0x7fffffffull));
-    status = MPMI_NO_SAFE;
-    fv = 255 - (int)(kf >> 56);
-  }
-  mpmi_selection sel;
-  sel.idx = idx;
-  sel.status = status;
-  sel.n_safe = (int)n_safe;
-  sel.n_recheck = (int)n_re;
-  float dev2 = 0.0f;
-#pragma unroll
-  for (int j = 0; j < MPMI_MAX_INPUT; ++j) {
-    float v = 0.0f;
-    if (j < md->m) {
-      v = cand_value(gp, md, cand, u_user, idx, 0, j);
-      const float d = v - u_user[j];
-      dev2 = fmaf(d, d, dev2);
-    }
-    sel.u_r[j] = v;
-  }
-  sel.cost = cost;
-  sel.deviation = sqrtf(dev2);
-  sel.first_violation = fv;
-  sel.n_cand = gp.n_cand + 1;
-  *out = sel;
-  slot->key_safe = kKeyNone;
-  slot->key_fb = kKeyNone;
-  slot->n_safe = 0u;
-  slot->n_recheck = 0u;
-  slot->done = 0u;
-  __threadfence();
-}
 
 // ---------------------------------------------------------------------------
 // Fused tick, FP32
@@ -140,57 +26,12 @@ tick_fp32_kernel(const ModelDev* __restrict__ md, GenParams gp, int H, const flo
                  const float* __restrict__ u_user, const float* __restrict__ cand,
                  Slot* __restrict__ slot, mpmi_selection* __restrict__ out,
                  int16_t* __restrict__ fv_out, float* __restrict__ traj) {
-  constexpr int NS = Dims<BASIS>::N, MS = Dims<BASIS>::M;
-  const int Nc = gp.n_cand + 1;
+  constexpr int MS = Dims<BASIS>::M;
+  __shared__ float4 sK[kLdsKFloat4];
+  stage_K<BASIS>(md, sK);
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  const bool valid = c < Nc;
-  const int n = md->n, S = gp.n_seg;
-
-  float x[NS], u[MS], u0[MS];
-#pragma unroll
-  for (int j = 0; j < NS; ++j) x[j] = (j < n) ? x_t[j] : 0.0f;
-#pragma unroll
-  for (int j = 0; j < MS; ++j) {
-    u0[j] = (valid && j < md->m) ? cand_value(gp, md, cand, u_user, c, 0, j) : 0.0f;
-    u[j] = u0[j];
-  }
-  float sd = 0.0f, cd = 1.0f;
-  if (BASIS == MPMI_BASIS_RACE_CAR) sincosf(u[0], &sd, &cd);
-
-  int fv = H + 1;
-  if (valid) {
-    int gcur = 0;
-    for (int s = 1; s <= H; ++s) {
-      const int g = ((s - 1) * S) / H;
-      if (g != gcur) {
-        gcur = g;
-#pragma unroll
-        for (int j = 0; j < MS; ++j)
-          u[j] = (j < md->m) ? cand_value(gp, md, cand, u_user, c, g, j) : 0.0f;
-        if (BASIS == MPMI_BASIS_RACE_CAR) sincosf(u[0], &sd, &cd);
-      }
-      if constexpr (BASIS == MPMI_BASIS_RACE_CAR) {
-        race_car_step(md, x, u, sd, cd);
-      } else {
-        koopman_step<BASIS>(md, x, u);
-      }
-      if (traj) {
-#pragma unroll
-        for (int j = 0; j < NS; ++j)
-          if (j < n) traj[((size_t)(s - 1) * n + j) * (size_t)Nc + c] = x[j];
-      }
-      if (!(min_margin<NS>(md, x) > 0.0f)) {
-        fv = s;
-        break;
-      }
-    }
-    if (fv_out) fv_out[c] = (int16_t)fv;
-  }
-  const float cst = valid ? cost_of<MS>(md, u0, u_user) : 0.0f;
-  const bool safe = valid && fv == H + 1;
-  const unsigned long long ks = safe ? safe_key(cst, c) : kKeyNone;
-  const unsigned long long kf = (valid && !safe) ? fallback_key(fv, cst, c) : kKeyNone;
-  if (reduce_and_publish(ks, kf, safe && c > 0, slot) && threadIdx.x == 0)
+  const CandResult r = evaluate_candidate<BASIS>(md, sK, gp, H, x_t, u_user, cand, c, fv_out, traj);
+  if (reduce_and_publish(r.ks, r.kf, r.safe_counted, slot, gridDim.x) && threadIdx.x == 0)
     finalize<MS>(md, gp, cand, u_user, H, slot, out);
 }
 
@@ -202,6 +43,8 @@ __global__ void __launch_bounds__(1024)
 rollout_fp32_kernel(const ModelDev* __restrict__ md, int Nc, int S, int H, const float* __restrict__ x0,
                     const float* __restrict__ cand, float* __restrict__ traj) {
   constexpr int NS = Dims<BASIS>::N, MS = Dims<BASIS>::M;
+  __shared__ float4 sK[kLdsKFloat4];
+  stage_K<BASIS>(md, sK);
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= Nc) return;
   const int n = md->n, m = md->m;
@@ -209,20 +52,16 @@ rollout_fp32_kernel(const ModelDev* __restrict__ md, int Nc, int S, int H, const
 #pragma unroll
   for (int j = 0; j < NS; ++j) x[j] = (j < n) ? x0[j] : 0.0f;
   int gcur = -1;
-  float sd = 0.0f, cd = 1.0f;
+  Stepper<BASIS> stp;
   for (int s = 1; s <= H; ++s) {
     const int g = ((s - 1) * S) / H;
     if (g != gcur) {
       gcur = g;
 #pragma unroll
       for (int j = 0; j < MS; ++j) u[j] = (j < m) ? cand[((size_t)g * m + j) * (size_t)Nc + c] : 0.0f;
-      if (BASIS == MPMI_BASIS_RACE_CAR) sincosf(u[0], &sd, &cd);
+      stp.set_input(md, sK, u);
     }
-    if constexpr (BASIS == MPMI_BASIS_RACE_CAR) {
-      race_car_step(md, x, u, sd, cd);
-    } else {
-      koopman_step<BASIS>(md, x, u);
-    }
+    stp.step(md, sK, x);
 #pragma unroll
     for (int j = 0; j < NS; ++j)
       if (j < n) traj[((size_t)(s - 1) * n + j) * (size_t)Nc + c] = x[j];
@@ -270,7 +109,7 @@ select_kernel(const ModelDev* __restrict__ md, GenParams gp, int H, const float*
   const bool safe = valid && fv == H + 1;
   const unsigned long long ks = safe ? safe_key(cst, c) : kKeyNone;
   const unsigned long long kf = (valid && !safe) ? fallback_key(fv < 1 ? 1 : (fv > H ? H : fv), cst, c) : kKeyNone;
-  if (reduce_and_publish(ks, kf, safe && c > 0, slot) && threadIdx.x == 0)
+  if (reduce_and_publish(ks, kf, safe && c > 0, slot, gridDim.x) && threadIdx.x == 0)
     finalize<MS>(md, gp, cand, u_user, H, slot, out);
 }
 

@@ -1,0 +1,189 @@
+// Device code shared by the single-loop and many-loop ticks: candidate
+// values, cost, one candidate's prediction with early exit, and the
+// workgroup/cross-workgroup arg-min with its last-workgroup finalisation.
+#pragma once
+
+#include "mpmi_device.hpp"
+
+namespace mpmi {
+
+// Candidate source modes: the three public generators plus FULL (an explicit
+// array that already holds candidate 0 in column 0).
+constexpr int kGenFull = 3;
+
+__device__ __forceinline__ float cand_value(const GenParams& gp, const ModelDev* __restrict__ md,
+                                            const float* __restrict__ cand,
+                                            const float* __restrict__ u_user, int c, int g, int j) {
+  if (gp.gen == kGenFull) return cand[(size_t)(g * md->m + j) * (size_t)(gp.n_cand + 1) + (size_t)c];
+  if (c == 0) return u_user[j];
+  return gen_value(gp, md, cand, c, g, j);
+}
+
+template <int MS>
+__device__ __forceinline__ float cost_of(const ModelDev* __restrict__ md, const float* u0,
+                                         const float* __restrict__ u_user) {
+  float cst = 0.0f;
+#pragma unroll
+  for (int j = 0; j < MS; ++j) {
+    if (j < md->m) {
+      const float d = (u0[j] - u_user[j]) * md->half_inv[j];
+      cst = fmaf(d, d, cst);
+    }
+  }
+  return cst;
+}
+
+// Workgroup reduction of the two keys and the safe count, then one atomic of
+// each per workgroup; returns true in every thread of the workgroup that
+// publishes last among the n_parts workgroups serving this slot.
+__device__ __forceinline__ bool reduce_and_publish(unsigned long long ks, unsigned long long kf,
+                                                   bool safe_counted, Slot* __restrict__ slot,
+                                                   unsigned int n_parts) {
+  __shared__ unsigned long long s_ks[16], s_kf[16];
+  __shared__ unsigned int s_cnt[16];
+  __shared__ int s_last;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  ks = wave_min_u64(ks);
+  kf = wave_min_u64(kf);
+  const unsigned int cnt = (unsigned int)__popcll(__ballot(safe_counted));
+  if (lane == 0) {
+    s_ks[wave] = ks;
+    s_kf[wave] = kf;
+    s_cnt[wave] = cnt;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int nw = (blockDim.x + 63) >> 6;
+    unsigned long long bks = kKeyNone, bkf = kKeyNone;
+    unsigned int bcnt = 0;
+    for (int w = 0; w < nw; ++w) {
+      bks = s_ks[w] < bks ? s_ks[w] : bks;
+      bkf = s_kf[w] < bkf ? s_kf[w] : bkf;
+      bcnt += s_cnt[w];
+    }
+    if (bks != kKeyNone) atomicMin(&slot->key_safe, bks);
+    if (bkf != kKeyNone) atomicMin(&slot->key_fb, bkf);
+    if (bcnt) atomicAdd(&slot->n_safe, bcnt);
+    __threadfence();
+    const unsigned int prev = atomicAdd(&slot->done, 1u);
+    s_last = (prev == n_parts - 1);
+  }
+  __syncthreads();
+  return s_last != 0;
+}
+
+// Decodes the slot into the selection and resets the slot (one thread).
+template <int MS>
+__device__ void finalize(const ModelDev* __restrict__ md, const GenParams& gp,
+                         const float* __restrict__ cand, const float* __restrict__ u_user, int H,
+                         Slot* __restrict__ slot, mpmi_selection* __restrict__ out) {
+  __threadfence();
+  const unsigned long long ks = atomicMin(&slot->key_safe, kKeyNone);
+  const unsigned long long kf = atomicMin(&slot->key_fb, kKeyNone);
+  const unsigned int n_safe = atomicAdd(&slot->n_safe, 0u);
+  const unsigned int n_re = atomicAdd(&slot->n_recheck, 0u);
+  int idx, status, fv;
+  float cost;
+  if (ks != kKeyNone) {
+    idx = (int)(ks & 0xffffffffull);
+    cost = __uint_as_float((unsigned int)(ks >> 32));
+    status = MPMI_OK;
+    fv = H + 1;
+  } else {
+    idx = (int)(kf & 0x1ffffffull);
+    cost = __uint_as_float((unsigned int)((kf >> 25) & 0x7fffffffull));
+    status = MPMI_NO_SAFE;
+    fv = 255 - (int)(kf >> 56);
+  }
+  mpmi_selection sel;
+  sel.idx = idx;
+  sel.status = status;
+  sel.n_safe = (int)n_safe;
+  sel.n_recheck = (int)n_re;
+  float dev2 = 0.0f;
+#pragma unroll
+  for (int j = 0; j < MPMI_MAX_INPUT; ++j) {
+    float v = 0.0f;
+    if (j < md->m) {
+      v = cand_value(gp, md, cand, u_user, idx, 0, j);
+      const float d = v - u_user[j];
+      dev2 = fmaf(d, d, dev2);
+    }
+    sel.u_r[j] = v;
+  }
+  sel.cost = cost;
+  sel.deviation = sqrtf(dev2);
+  sel.first_violation = fv;
+  sel.n_cand = gp.n_cand + 1;
+  *out = sel;
+  slot->key_safe = kKeyNone;
+  slot->key_fb = kKeyNone;
+  slot->n_safe = 0u;
+  slot->n_recheck = 0u;
+  slot->done = 0u;
+  __threadfence();
+}
+
+struct CandResult {
+  unsigned long long ks, kf;
+  bool safe_counted;
+};
+
+// Prediction of candidate c with early exit at the first unsafe state
+// (Alg. 2 inner loop), then its selection keys.  Lanes with c >= Nc return
+// empty keys.  fv_out / traj are optional.
+template <int BASIS>
+__device__ __forceinline__ CandResult evaluate_candidate(const ModelDev* __restrict__ md, const float4* sK,
+                                                         const GenParams& gp, int H,
+                                                         const float* __restrict__ x_t,
+                                                         const float* __restrict__ u_user,
+                                                         const float* __restrict__ cand, int c,
+                                                         int16_t* __restrict__ fv_out, float* __restrict__ traj) {
+  constexpr int NS = Dims<BASIS>::N, MS = Dims<BASIS>::M;
+  const int Nc = gp.n_cand + 1;
+  const bool valid = c < Nc;
+  const int n = md->n, S = gp.n_seg;
+  float x[NS], u[MS], u0[MS];
+#pragma unroll
+  for (int j = 0; j < NS; ++j) x[j] = (j < n) ? x_t[j] : 0.0f;
+#pragma unroll
+  for (int j = 0; j < MS; ++j) {
+    u0[j] = (valid && j < md->m) ? cand_value(gp, md, cand, u_user, c, 0, j) : 0.0f;
+    u[j] = u0[j];
+  }
+  Stepper<BASIS> stp;
+  stp.set_input(md, sK, u);
+  int fv = H + 1;
+  if (valid) {
+    int gcur = 0;
+    for (int s = 1; s <= H; ++s) {
+      const int g = ((s - 1) * S) / H;
+      if (g != gcur) {
+        gcur = g;
+#pragma unroll
+        for (int j = 0; j < MS; ++j) u[j] = (j < md->m) ? cand_value(gp, md, cand, u_user, c, g, j) : 0.0f;
+        stp.set_input(md, sK, u);
+      }
+      stp.step(md, sK, x);
+      if (traj) {
+#pragma unroll
+        for (int j = 0; j < NS; ++j)
+          if (j < n) traj[((size_t)(s - 1) * n + j) * (size_t)Nc + c] = x[j];
+      }
+      if (!(min_margin<NS>(md, x) > 0.0f)) {
+        fv = s;
+        break;
+      }
+    }
+    if (fv_out) fv_out[c] = (int16_t)fv;
+  }
+  const float cst = valid ? cost_of<MS>(md, u0, u_user) : 0.0f;
+  const bool safe = valid && fv == H + 1;
+  CandResult r;
+  r.ks = safe ? safe_key(cst, c) : kKeyNone;
+  r.kf = (valid && !safe) ? fallback_key(fv, cst, c) : kKeyNone;
+  r.safe_counted = safe && c > 0;
+  return r;
+}
+
+}  // namespace mpmi

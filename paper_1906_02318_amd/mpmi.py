@@ -60,6 +60,19 @@ class TickDesc(ctypes.Structure):
     ]
 
 
+class LoopDesc(ctypes.Structure):
+    _fields_ = [
+        ("model", ctypes.c_void_p), ("x_t", ctypes.c_void_p), ("u_user", ctypes.c_void_p),
+        ("cand", ctypes.c_void_p), ("out", ctypes.c_void_p), ("first_violation", ctypes.c_void_p),
+        ("seed", ctypes.c_uint64), ("tick", ctypes.c_uint64), ("gen", ctypes.c_int32),
+        ("n_cand", ctypes.c_int32), ("grid", _i32x4), ("n_seg", ctypes.c_int32), ("horizon", ctypes.c_int32),
+    ]
+
+
+class MultiConfig(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int32), ("grid", ctypes.c_int32)]
+
+
 class MpmiError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"mpmi status {status}: {msg}")
@@ -91,6 +104,16 @@ def library() -> ctypes.CDLL:
         "select_min_intervention": (i32, [vp, vp, vp, i32, i32, vp, i32, vp, i32, vp, vp]),
         "mpmi_tick": (i32, [vp, vp, ctypes.POINTER(TickDesc), vp, vp, vp, vp, vp, vp, vp]),
         "mpmi_generate_candidates": (i32, [vp, vp, ctypes.POINTER(TickDesc), vp, vp, vp, vp]),
+        "mpmi_multi_create": (i32, [vp, ctypes.POINTER(LoopDesc), i32, ctypes.POINTER(MultiConfig), ctypes.POINTER(vp)]),
+        "mpmi_multi_destroy": (None, [vp]),
+        "mpmi_multi_set_config": (i32, [vp, vp, ctypes.POINTER(MultiConfig)]),
+        "mpmi_multi_get_config": (i32, [vp, ctypes.POINTER(MultiConfig), ctypes.POINTER(i32)]),
+        "mpmi_multi_tick": (i32, [vp, vp, vp]),
+        "mpmi_multi_get_ticks": (i32, [vp, vp, vp]),
+        "mpmi_multi_autotune": (i32, [vp, vp, i32, ctypes.POINTER(MultiConfig), ctypes.POINTER(ctypes.c_float), vp]),
+        "mpmi_multi_graph": (i32, [vp, vp, ctypes.POINTER(vp)]),
+        "mpmi_graph_launch": (i32, [vp, vp, vp]),
+        "mpmi_graph_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -345,3 +368,96 @@ def decode_selection(rec) -> dict:
                         u_r=list(s.u_r), cost=s.cost, deviation=s.deviation,
                         first_violation=s.first_violation, n_cand=s.n_cand))
     return out[0] if len(out) == 1 else out
+
+
+# ---------------------------------------------------------------------------
+# Many loops in one launch per tick
+# ---------------------------------------------------------------------------
+class Multi:
+    """A set of control loops served by one persistent launch per tick.
+
+    `loops` is a list of dicts with keys model (Model), x_t, u_user (device
+    tensors at fixed addresses, read every tick), out (uint8 tensor of 48 B),
+    n_cand, horizon and optionally gen, grid, n_seg, seed, tick, cand,
+    first_violation.  The tensors are kept alive by this object.
+    """
+
+    def __init__(self, ctx: Context, loops, block: int = 256, grid: int = 0):
+        self.ctx = ctx
+        self._keep = []
+        arr = (LoopDesc * len(loops))()
+        for i, l in enumerate(loops):
+            d = arr[i]
+            model = l["model"]
+            _need(l["x_t"], "x_t", torch.float32, model.n, device=ctx.device)
+            _need(l["u_user"], "u_user", torch.float32, model.m, device=ctx.device)
+            _need(l["out"], "out", torch.uint8, SELECTION_BYTES, device=ctx.device)
+            d.model = model.ptr
+            d.x_t = l["x_t"].data_ptr()
+            d.u_user = l["u_user"].data_ptr()
+            d.out = l["out"].data_ptr()
+            d.cand = l["cand"].data_ptr() if l.get("cand") is not None else None
+            fv = l.get("first_violation")
+            if fv is not None:
+                _need(fv, "first_violation", torch.int16, l["n_cand"] + 1, device=ctx.device)
+            d.first_violation = fv.data_ptr() if fv is not None else None
+            d.seed, d.tick = l.get("seed", 0), l.get("tick", 0)
+            d.gen, d.n_cand = l.get("gen", GEN_UNIFORM), l["n_cand"]
+            for j, g in enumerate(l.get("grid") or []):
+                d.grid[j] = g
+            d.n_seg, d.horizon = l.get("n_seg", 1), l["horizon"]
+            self._keep.append(l)
+        cfg = MultiConfig(block, grid)
+        h = ctypes.c_void_p()
+        ctx.check(ctx.lib.mpmi_multi_create(ctx.handle, arr, len(loops), ctypes.byref(cfg), ctypes.byref(h)))
+        self.handle = h
+        self.graph = None
+
+    def config(self):
+        cfg, n = MultiConfig(), ctypes.c_int32()
+        self.ctx.lib.mpmi_multi_get_config(self.handle, ctypes.byref(cfg), ctypes.byref(n))
+        return dict(block=cfg.block, grid=cfg.grid, n_work=n.value)
+
+    def set_config(self, block: int, grid: int = 0):
+        self.ctx.check(self.ctx.lib.mpmi_multi_set_config(self.ctx.handle, self.handle,
+                                                         ctypes.byref(MultiConfig(block, grid))))
+
+    def tick(self, stream=None):
+        self.ctx.check(self.ctx.lib.mpmi_multi_tick(self.ctx.handle, self.handle, _stream(stream)))
+
+    def ticks(self):
+        """Device tick counters of the loops (synchronous)."""
+        arr = (ctypes.c_uint64 * len(self._keep))()
+        self.ctx.check(self.ctx.lib.mpmi_multi_get_ticks(self.ctx.handle, self.handle, arr))
+        return list(arr)
+
+    def autotune(self, reps: int = 20, stream=None):
+        best, ms = MultiConfig(), ctypes.c_float()
+        self.ctx.check(self.ctx.lib.mpmi_multi_autotune(self.ctx.handle, self.handle, reps, ctypes.byref(best),
+                                                        ctypes.byref(ms), _stream(stream)))
+        return dict(block=best.block, grid=best.grid, ms=ms.value)
+
+    def capture_graph(self):
+        if self.graph is not None:
+            self.ctx.lib.mpmi_graph_destroy(self.graph)
+        g = ctypes.c_void_p()
+        self.ctx.check(self.ctx.lib.mpmi_multi_graph(self.ctx.handle, self.handle, ctypes.byref(g)))
+        self.graph = g
+        return g
+
+    def launch_graph(self, stream=None):
+        self.ctx.check(self.ctx.lib.mpmi_graph_launch(self.ctx.handle, self.graph, _stream(stream)))
+
+    def close(self):
+        if getattr(self, "graph", None) is not None:
+            self.ctx.lib.mpmi_graph_destroy(self.graph)
+            self.graph = None
+        if getattr(self, "handle", None):
+            self.ctx.lib.mpmi_multi_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

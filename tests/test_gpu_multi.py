@@ -1,0 +1,126 @@
+"""GPU checks of the many-loop tick (one persistent launch for many control
+loops), its HIP-graph replay and its autotuner."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import mpmi_oracle as o
+from paper_1906_02318_amd import mpmi
+from tests import workloads as W
+from tests.parity import check_tick
+
+pytestmark = pytest.mark.gpu
+
+EPS = {"bb": [1e-4, 4e-4], "rc": [1e-3, 1e-3]}
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(a, dtype):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype).cuda()
+
+
+@pytest.fixture(scope="module")
+def setup():
+    assert torch.cuda.is_available()
+    ctx = mpmi.Context(0)
+    Kb, Kr = W.bb_model()[0], W.rc_model()[0]
+    mb = mpmi.mpmi_model_pack(ctx, mpmi.balance_bot_system(), dev(Kb, torch.float64))
+    mr = mpmi.mpmi_model_pack(ctx, mpmi.race_car_system(W.track_dict(W.rc_track())), dev(Kr, torch.float64))
+    rng = np.random.default_rng(5)
+    kinds = ["bb", "rc", "bb", "rc", "rc", "bb", "rc", "bb"]
+    Ns = [300, 5000, 20000, 777, 12000, 64, 2500, 1024]
+    Hs = [20, 60, 45, 33, 25, 60, 41, 50]
+    xb = synth.balance_bot_states(8, seed=17)
+    xr = synth.race_car_states(8, W.rc_track(), seed=17)
+    loops, meta = [], []
+    for i, (k, N, H) in enumerate(zip(kinds, Ns, Hs)):
+        if k == "bb":
+            x, u = W.f32(xb[i]), W.f32(rng.uniform(-5, 5, size=1))
+        else:
+            x, u = W.f32(xr[i]), W.f32(rng.uniform(synth.RC_U_LO, synth.RC_U_HI))
+        loops.append(dict(model=mb if k == "bb" else mr, x_t=dev(x, torch.float32), u_user=dev(u, torch.float32),
+                          out=torch.zeros(mpmi.SELECTION_BYTES, dtype=torch.uint8, device="cuda"),
+                          first_violation=torch.zeros(N + 1, dtype=torch.int16, device="cuda"),
+                          n_cand=N, horizon=H, gen=mpmi.GEN_UNIFORM, seed=100 + i, tick=1000 * i))
+        meta.append(dict(kind=k, x=x, u=u, N=N, H=H, seed=100 + i, tick0=1000 * i))
+    multi = mpmi.Multi(ctx, loops, block=256)
+    systems = {"bb": (W.bb_oracle_system(), Kb, mb), "rc": (W.rc_oracle_system(W.rc_track()), Kr, mr)}
+    return ctx, multi, loops, meta, systems
+
+
+def single_tick_records(ctx, loops, meta, systems, tick_offset):
+    """The same ticks run one loop at a time through mpmi_tick."""
+    recs = []
+    for i, (l, mt) in enumerate(zip(loops, meta)):
+        model = systems[mt["kind"]][2]
+        d = mpmi.tick_desc(mt["N"], mt["H"], gen=mpmi.GEN_UNIFORM, seed=mt["seed"], tick=mt["tick0"] + tick_offset,
+                           loop=i)
+        recs.append(mpmi.mpmi_tick(ctx, model, d, l["x_t"], l["u_user"]).cpu().numpy().tobytes())
+    return recs
+
+
+def multi_records(loops):
+    return [l["out"].cpu().numpy().tobytes() for l in loops]
+
+
+def test_multi_tick_matches_oracle_and_single_ticks(setup):
+    ctx, multi, loops, meta, systems = setup
+    log(f"[multi] config {multi.config()}")
+    multi.tick()
+    torch.cuda.synchronize()
+    got = multi_records(loops)
+    for i, (l, mt) in enumerate(zip(loops, meta)):
+        so, K, _ = systems[mt["kind"]]
+        cand = o.with_user(o.uniform_candidates(so, mt["N"], 1, mt["seed"], mt["tick0"], i), mt["u"], 1)
+        sel = mpmi.decode_selection(l["out"])
+        res = check_tick(so, K, mt["x"], mt["u"], cand, mt["H"], sel, l["first_violation"].cpu().numpy(),
+                         EPS[mt["kind"]], label=f"multi loop {i} ({mt['kind']} N={mt['N']} H={mt['H']})")
+        log(f"[multi] loop {i}: {res['kind']} idx={sel['idx']} status={sel['status']} n_safe={sel['n_safe']}")
+    assert got == single_tick_records(ctx, loops, meta, systems, 0)
+    # the device advanced every tick counter: the next tick uses tick0 + 1
+    multi.tick()
+    torch.cuda.synchronize()
+    assert multi_records(loops) == single_tick_records(ctx, loops, meta, systems, 1)
+
+
+def test_multi_graph_replay(setup):
+    ctx, multi, loops, meta, systems = setup
+    # two ticks ran in the previous test (offsets 0, 1): replays continue at 2
+    multi.capture_graph()
+    for r in range(3):
+        multi.launch_graph()
+        torch.cuda.synchronize()
+        got = multi_records(loops)
+        # eager work between replays
+        junk = torch.randn(1 << 20, device="cuda").sum()
+        torch.cuda.synchronize()
+        assert got == single_tick_records(ctx, loops, meta, systems, 2 + r), f"replay {r}"
+        del junk
+    log("[multi] 3 graph replays identical to eager single ticks")
+
+
+def test_multi_autotune_and_block_sizes_deterministic(setup):
+    ctx, multi, loops, meta, systems = setup
+    offset = 5  # ticks so far: 2 eager + 3 replays
+    for block in (64, 128, 512):
+        multi.set_config(block)
+        multi.tick()
+        torch.cuda.synchronize()
+        assert multi_records(loops) == single_tick_records(ctx, loops, meta, systems, offset), f"block {block}"
+        offset += 1
+    best = multi.autotune(reps=5)
+    log(f"[multi] autotuned {best}, plan {multi.config()}")
+    assert best["block"] in (64, 128, 256, 512) and best["grid"] >= 1 and best["ms"] > 0
+    ticks = multi.ticks()
+    offs = [t - mt["tick0"] for t, mt in zip(ticks, meta)]
+    assert len(set(offs)) == 1 and offs[0] > offset
+    multi.tick()
+    torch.cuda.synchronize()
+    assert multi_records(loops) == single_tick_records(ctx, loops, meta, systems, offs[0])
