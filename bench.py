@@ -132,6 +132,162 @@ def cpu_baseline(wl: dict, st: dict, budget_s: float = 15.0):
                        f"plus u_h), H={H}, FP64 NumPy, {t_used:.1f} s")
 
 
+def run_multi(n_ticks: int = 2000, warmup: int = 50, seed: int = 5):
+    """64 closed control loops (32 cart-pole, 32 race car; N_l log-uniform in
+    [1,024, 65,536], H_l in 20..60) served by one graph-replayed launch per tick.
+    Each tick: inputs host->device, replay, selections device->host, plants and
+    AR(1) users advanced on the host with the applied inputs."""
+    import torch
+
+    import synth
+    from paper_1906_02318_amd import mpmi
+
+    ctx = mpmi.Context(0)
+    track = synth.make_track(3)
+    d = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+    Xb, Ub, Yb = synth.balance_bot_transitions(5000, seed=0)
+    sb = mpmi.balance_bot_system()
+    mb = mpmi.mpmi_model_pack(ctx, sb, mpmi.koopman_fit(ctx, sb, d(Xb), d(Ub), d(Yb))[0])
+    Xr, Ur, Yr = synth.race_car_transitions(50000, seed=0, track=track)
+    trd = dict(r0=track.r0, half=track.half_width, amp=list(track.amp), freq=list(track.freq),
+               phase=list(track.phase), infl=0.0)
+    sr = mpmi.race_car_system(trd)
+    mr = mpmi.mpmi_model_pack(ctx, sr, mpmi.koopman_fit(ctx, sr, d(Xr), d(Ur), d(Yr))[0])
+    N, H = synth.loop_sizes(64, seed=seed)
+    kinds = ["bb"] * 32 + ["rc"] * 32
+    xs = np.zeros((64, 8), np.float32)
+    us = np.zeros((64, 4), np.float32)
+    xs[:32, :4] = synth.balance_bot_states(32, seed=1)
+    xs[32:, :6] = synth.race_car_states(32, track, seed=1)
+    users = [synth.AR1User([-5.0], [5.0], seed=100 + i) for i in range(32)] + \
+            [synth.AR1User(synth.RC_U_LO, synth.RC_U_HI, sigma=[0.08, 0.6], seed=200 + i) for i in range(32)]
+    x_dev = torch.zeros((64, 8), dtype=torch.float32, device="cuda")
+    u_dev = torch.zeros((64, 4), dtype=torch.float32, device="cuda")
+    out_dev = torch.zeros((64, mpmi.SELECTION_BYTES), dtype=torch.uint8, device="cuda")
+    x_pin = torch.zeros((64, 8), dtype=torch.float32).pin_memory()
+    u_pin = torch.zeros((64, 4), dtype=torch.float32).pin_memory()
+    o_pin = torch.zeros((64, mpmi.SELECTION_BYTES), dtype=torch.uint8).pin_memory()
+    loops = [dict(model=mb if k == "bb" else mr, x_t=x_dev[i], u_user=u_dev[i], out=out_dev[i], n_cand=int(N[i]),
+                  horizon=int(H[i]), gen=mpmi.GEN_UNIFORM, seed=1000 + i, tick=0) for i, k in enumerate(kinds)]
+    multi = mpmi.Multi(ctx, loops)
+    stream = torch.cuda.current_stream()
+    for i in range(64):
+        us[i, :users[i].lo.size] = users[i].next()
+    x_pin.copy_(torch.from_numpy(xs))
+    u_pin.copy_(torch.from_numpy(us))
+    x_dev.copy_(x_pin)
+    u_dev.copy_(u_pin)
+    tuned = multi.autotune(reps=10)
+    multi.capture_graph()
+    dev_ms, e2e_ms, resets, interventions, nosafe = [], [], 0, 0, 0
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for t in range(warmup + n_ticks):
+        t0 = time.perf_counter()
+        x_pin.copy_(torch.from_numpy(xs))
+        u_pin.copy_(torch.from_numpy(us))
+        x_dev.copy_(x_pin, non_blocking=True)
+        u_dev.copy_(u_pin, non_blocking=True)
+        ev0.record(stream)
+        multi.launch_graph(stream)
+        ev1.record(stream)
+        o_pin.copy_(out_dev, non_blocking=True)
+        stream.synchronize()
+        t1 = time.perf_counter()
+        rec = o_pin.numpy()
+        raw = rec.view(np.int32).reshape(64, -1)
+        flt = rec.view(np.float32).reshape(64, -1)
+        if t >= warmup:
+            dev_ms.append(ev0.elapsed_time(ev1))
+            e2e_ms.append((t1 - t0) * 1e3)
+            interventions += int(np.sum(raw[:, 0] != 0))
+            nosafe += int(np.sum(raw[:, 1] != 0))
+        # plants advance with the applied inputs; users move on
+        ub = flt[:32, 4:5].astype(np.float64)
+        xb = synth.cartpole_step(xs[:32, :4].astype(np.float64), ub[:, 0])
+        bad = (np.abs(xb[:, 2]) > 0.5) | (np.abs(xb[:, 0]) > 2.0)
+        resets += int(bad.sum())
+        if bad.any():
+            xb[bad] = synth.balance_bot_states(int(bad.sum()), seed=7 + t)
+        xs[:32, :4] = xb
+        xr = synth.bicycle_step(xs[32:, :6].astype(np.float64), flt[32:, 4:6].astype(np.float64))
+        rho = np.hypot(xr[:, 0], xr[:, 1])
+        off = rho - track.centre_radius(np.arctan2(xr[:, 1], xr[:, 0]))
+        badr = (np.abs(off) > 3.0) | (np.abs(xr[:, 4]) > 2.0)
+        resets += int(badr.sum())
+        if badr.any():
+            xr[badr] = synth.race_car_states(int(badr.sum()), track, seed=9 + t)
+        xs[32:, :6] = xr
+        for i in range(64):
+            us[i, :users[i].lo.size] = users[i].next()
+    multi.close()
+    dev = np.array(dev_ms)
+    e2e = np.array(e2e_ms)
+    cands = float(np.sum(N + 1))
+    return {
+        "workload": "64 loops (32 cart-pole + 32 race car), N_l log-uniform [1024, 65536] "
+                    f"(sum {int(cands)}), H_l in [20, 60], closed loop, one graph replay per tick",
+        "ticks": n_ticks, "autotuned": tuned,
+        "trajectories_per_s_device": cands / (dev.mean() * 1e-3),
+        "trajectories_per_s_end_to_end": cands / (e2e.mean() * 1e-3),
+        "p50_tick_ms": float(np.percentile(dev, 50)), "p99_tick_ms": float(np.percentile(dev, 99)),
+        "p50_end_to_end_ms": float(np.percentile(e2e, 50)), "p99_end_to_end_ms": float(np.percentile(e2e, 99)),
+        "interventions_per_tick": interventions / n_ticks, "no_safe_per_tick": nosafe / n_ticks,
+        "plant_resets": resets,
+    }
+
+
+def run_plain_vs_learned(n_ticks: int = 500, warmup: int = 20):
+    """Race car at its stated size: exhaustive 128 x 128 grid tick vs the learned
+    2,048-proposal tick (exhaustive fallback), on the same tick inputs."""
+    import torch
+
+    import synth
+    from paper_1906_02318_amd import mpmi
+    from paper_1906_02318_amd.proposal import ASSET, LearnedTicker, ProposalNet
+
+    st = setup(WORKLOADS["race_car"], 64)
+    ctx, model = st["ctx"], st["model"]
+    stream = torch.cuda.current_stream()
+    plain = mpmi.tick_desc(128 * 128, 60, gen=mpmi.GEN_GRID, grid=[128, 128], loop=0)
+    out = {}
+    runs = [("plain", None)]
+    if os.path.exists(ASSET):
+        runs.append(("learned", LearnedTicker(ctx, model, ProposalNet.load(ctx, ASSET))))
+    for name, ticker in runs:
+        outs = torch.empty((64, mpmi.SELECTION_BYTES), dtype=torch.uint8, device="cuda")
+
+        def step(t):
+            i = t % 64
+            if ticker is None:
+                mpmi.mpmi_tick(ctx, model, plain, st["x"][i], st["u"][i], out=outs[i], stream=stream)
+            else:
+                ticker.tick(st["x"][i], st["u"][i], tick=t, out=outs[i], stream=stream)
+
+        for t in range(warmup):
+            step(t)
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n_ticks)]
+        n_eval = 0
+        t0 = time.perf_counter()
+        for t in range(n_ticks):
+            ev[t][0].record(stream)
+            step(t)
+            ev[t][1].record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ms = np.array([a.elapsed_time(b) for a, b in ev])
+        sels = mpmi.decode_selection(outs)
+        ncand = float(np.mean([s["n_cand"] for s in sels]))
+        out[name] = {"trajectories_per_s": ncand * n_ticks / wall, "candidates_per_tick": ncand,
+                     "p50_tick_ms": float(np.percentile(ms, 50)), "p99_tick_ms": float(np.percentile(ms, 99)),
+                     "ms_per_tick": wall * 1e3 / n_ticks}
+        if ticker is not None:
+            out[name]["fallback_rate"] = float(np.mean([s["n_cand"] != ticker.P + 1 for s in sels]))
+    if "learned" not in out:
+        out["learned"] = None
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -141,6 +297,8 @@ def main():
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-extras", action="store_true", help="skip the many-loop and plain-vs-learned legs")
+    ap.add_argument("--multi-ticks", type=int, default=2000)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the tick's candidates would shard "
@@ -234,6 +392,9 @@ def main():
             "flops_per_unit": FLOPS_PER_UNIT[wl["system"]],
         },
     }
+    if not args.no_extras and args.workload == "race_car_1m":
+        out["race_car_16k"] = run_plain_vs_learned()
+        out["many_loops"] = run_multi(n_ticks=args.multi_ticks)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, st, args.cpu_budget)
     print(json.dumps(out), flush=True)

@@ -319,6 +319,77 @@ mpmi_status mpmi_multi_graph(mpmi_ctx ctx, mpmi_multi multi, void** graph_exec);
 mpmi_status mpmi_graph_launch(mpmi_ctx ctx, void* graph_exec, void* stream);
 void mpmi_graph_destroy(void* graph_exec);
 
+/* ---------------------------------------------------------------------------
+ * Learned proposal (race car).  A small network maps (state, user input) to
+ * a mixture over inputs near the safe minimal-intervention choice, so a tick
+ * can evaluate a few thousand proposals instead of an exhaustive grid; the
+ * exhaustive sampler of Sec. IV-B remains the fallback whenever no proposal
+ * (and not the user's own input) is safe.
+ *
+ * Network: 8 inputs [x (6); u_user (2)], standardised by in_mean / in_std,
+ * three hidden layers of 256 with GELU 0.5 z (1 + tanh(sqrt(2/pi)(z + 0.044715 z^3))),
+ * 80 outputs = 16 x {logit, mu_0, mu_1, log sigma_0, log sigma_1} of a
+ * diagonal-Gaussian mixture over the input mapped to [-1, 1]^2; log sigma is
+ * clamped to [-7, 2].  Parameters: one flat vector of MPMI_MLP_PARAMS values,
+ * per layer W [in][out] row-major then b [out], layers in order.  Products
+ * use the BF16 copy of the weights with FP32 accumulation; biases and the
+ * Adam state are FP32.  Workspace: caller-allocated device memory of
+ * mlp_workspace_bytes(B) bytes (256-byte aligned).
+ * ------------------------------------------------------------------------- */
+#define MPMI_MLP_IN 8
+#define MPMI_MLP_HIDDEN 256
+#define MPMI_MLP_COMP 16
+#define MPMI_MLP_OUT 80
+#define MPMI_MLP_PARAMS 154448
+#define MPMI_MLP_MAX_BATCH 65536
+
+size_t mlp_workspace_bytes(int32_t batch);
+
+/* Y [B][80] = network(X [B][8]).  w_bf16 / w_f32: the parameters in BF16
+ * (products) and FP32 (biases). */
+mpmi_status mlp_forward(mpmi_ctx ctx, const uint16_t* w_bf16, const float* w_f32, const float* in_mean,
+                        const float* in_std, const float* X, int32_t B, float* Y, void* work,
+                        size_t work_bytes, void* stream);
+
+/* Mean mixture negative log-likelihood of targets T [B][2] (inputs mapped
+ * to [-1, 1]) and its gradient grad [MPMI_MLP_PARAMS] (FP32) with respect
+ * to the parameters; *loss (device FP32) receives the mean NLL. */
+mpmi_status mlp_grad(mpmi_ctx ctx, const uint16_t* w_bf16, const float* w_f32, const float* in_mean,
+                     const float* in_std, const float* X, const float* T, int32_t B, float* grad, float* loss,
+                     void* work, size_t work_bytes, void* stream);
+
+/* One Adam step (Kingma & Ba 2015; beta 0.9 / 0.999, eps 1e-8, bias
+ * correction with step >= 1) on the FP32 master weights; refreshes w_bf16. */
+mpmi_status mlp_adam(mpmi_ctx ctx, float* w_f32, uint16_t* w_bf16, float* adam_m, float* adam_v,
+                     const float* grad, int32_t step, float lr, void* stream);
+
+/* P proposals from one mixture head (80 floats, device): component by the
+ * inverse CDF of the FP32 mixture weights at r0, two Box-Muller normals from
+ * r1 in (0, 1] and r2 in [0, 1), mu + sigma z clipped to [-1, 1], mapped to
+ * the model's input box; r_s = top 24 bits of the counter hash of (seed,
+ * tick, loop, p, s) as in MPMI_GEN_UNIFORM (r1 adds one unit first).
+ * cand [1][m][P] (EXPLICIT layout). */
+mpmi_status mdn_sample(mpmi_ctx ctx, const void* model, const float* head, int32_t P, uint64_t seed,
+                       uint64_t tick, int32_t loop, float* cand, void* stream);
+
+/* A learned-proposal tick: network on [x_t; u_user], P = prop->n_cand
+ * proposals drawn with (prop->seed, prop->tick, prop->loop), a fused tick
+ * over {u_user} + proposals (EXPLICIT) into *out, then the exhaustive
+ * fallback tick described by *fallback (GRID or UNIFORM), which runs only if
+ * *out holds MPMI_NO_SAFE and then overwrites it (out->n_cand tells which
+ * candidate set decided).  cand_work [1][2][P] device; head_out [80] device
+ * or NULL.  Race-car models only. */
+mpmi_status mpmi_proposal_tick(mpmi_ctx ctx, const void* model, const uint16_t* w_bf16, const float* w_f32,
+                               const float* in_mean, const float* in_std, const float* x_t,
+                               const float* u_user, const mpmi_tick_desc* prop /* host */,
+                               const mpmi_tick_desc* fallback /* host */, float* cand_work, float* head_out,
+                               mpmi_selection* out, void* work, size_t work_bytes, void* stream);
+
+/* C = op(A) op(B) on the BF16 matrix-core path (test hook): A, B BF16,
+ * op transposes when ta / tb is 1, C [M][N] FP32. */
+mpmi_status mpmi_gemm_bf16(mpmi_ctx ctx, const uint16_t* A, const uint16_t* B, int32_t M, int32_t N, int32_t K,
+                           int32_t ta, int32_t tb, float* C, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

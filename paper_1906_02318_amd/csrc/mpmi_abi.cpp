@@ -504,4 +504,111 @@ void mpmi_graph_destroy(void* graph_exec) {
   if (graph_exec) (void)hipGraphExecDestroy((hipGraphExec_t)graph_exec);
 }
 
+size_t mlp_workspace_bytes(int32_t batch) {
+  if (batch < 1 || batch > MPMI_MLP_MAX_BATCH) return 0;
+  return mpmi::mlp_workspace_bytes(batch);
+}
+
+static mpmi_status check_mlp_common(mpmi_ctx ctx, const void* w16, const void* w32, const void* mean,
+                                    const void* stdv, int32_t B, void* work, size_t work_bytes) {
+  if (!w16 || !w32 || !mean || !stdv) return fail(ctx, MPMI_EINVAL, "weights, in_mean and in_std must be non-NULL");
+  if (B < 1 || B > MPMI_MLP_MAX_BATCH) return fail(ctx, MPMI_EINVAL, "batch %d out of 1..%d", B, MPMI_MLP_MAX_BATCH);
+  if (!work || !aligned(work, 256)) return fail(ctx, MPMI_EINVAL, "workspace must be non-NULL and 256-byte aligned");
+  if (work_bytes < mpmi::mlp_workspace_bytes(B))
+    return fail(ctx, MPMI_EINVAL, "workspace of %zu bytes < mlp_workspace_bytes(%d) = %zu", work_bytes, B,
+                mpmi::mlp_workspace_bytes(B));
+  return MPMI_OK;
+}
+
+mpmi_status mlp_forward(mpmi_ctx ctx, const uint16_t* w_bf16, const float* w_f32, const float* in_mean,
+                        const float* in_std, const float* X, int32_t B, float* Y, void* work, size_t work_bytes,
+                        void* stream) {
+  if (!ctx) return MPMI_EINVAL;
+  mpmi_status s = check_mlp_common(ctx, w_bf16, w_f32, in_mean, in_std, B, work, work_bytes);
+  if (s != MPMI_OK) return s;
+  if (!X || !Y) return fail(ctx, MPMI_EINVAL, "X and Y must be non-NULL");
+  return check_hip(ctx, mpmi::launch_mlp_forward(w_bf16, w_f32, in_mean, in_std, X, B, Y, work, (hipStream_t)stream),
+                   "mlp_forward launch");
+}
+
+mpmi_status mlp_grad(mpmi_ctx ctx, const uint16_t* w_bf16, const float* w_f32, const float* in_mean,
+                     const float* in_std, const float* X, const float* T, int32_t B, float* grad, float* loss,
+                     void* work, size_t work_bytes, void* stream) {
+  if (!ctx) return MPMI_EINVAL;
+  mpmi_status s = check_mlp_common(ctx, w_bf16, w_f32, in_mean, in_std, B, work, work_bytes);
+  if (s != MPMI_OK) return s;
+  if (!X || !T || !grad) return fail(ctx, MPMI_EINVAL, "X, T and grad must be non-NULL");
+  return check_hip(ctx, mpmi::launch_mlp_grad(w_bf16, w_f32, in_mean, in_std, X, T, B, grad, loss, work,
+                                              (hipStream_t)stream),
+                   "mlp_grad launch");
+}
+
+mpmi_status mlp_adam(mpmi_ctx ctx, float* w_f32, uint16_t* w_bf16, float* adam_m, float* adam_v, const float* grad,
+                     int32_t step, float lr, void* stream) {
+  if (!ctx) return MPMI_EINVAL;
+  if (!w_f32 || !w_bf16 || !adam_m || !adam_v || !grad) return fail(ctx, MPMI_EINVAL, "NULL argument");
+  if (step < 1) return fail(ctx, MPMI_EINVAL, "step=%d must be >= 1", step);
+  if (!(lr > 0.0f)) return fail(ctx, MPMI_EINVAL, "lr must be > 0");
+  return check_hip(ctx, mpmi::launch_mlp_adam(w_f32, w_bf16, adam_m, adam_v, grad, step, lr, (hipStream_t)stream),
+                   "mlp_adam launch");
+}
+
+mpmi_status mdn_sample(mpmi_ctx ctx, const void* model, const float* head, int32_t P, uint64_t seed, uint64_t tick,
+                       int32_t loop, float* cand, void* stream) {
+  if (!ctx) return MPMI_EINVAL;
+  mpmi_system sys;
+  mpmi_status s = model_system(ctx, model, &sys, nullptr);
+  if (s != MPMI_OK) return s;
+  if (sys.n_input != 2) return fail(ctx, MPMI_EUNSUPPORTED, "the proposal head is over 2 inputs");
+  if (!head || !cand) return fail(ctx, MPMI_EINVAL, "head and cand must be non-NULL");
+  if (P < 1 || P > MPMI_MAX_CAND - 1) return fail(ctx, MPMI_EINVAL, "P=%d out of range", P);
+  return check_hip(ctx, mpmi::launch_mdn_sample(model, head, P, seed, tick, loop, cand, (hipStream_t)stream),
+                   "mdn_sample launch");
+}
+
+mpmi_status mpmi_proposal_tick(mpmi_ctx ctx, const void* model, const uint16_t* w_bf16, const float* w_f32,
+                               const float* in_mean, const float* in_std, const float* x_t, const float* u_user,
+                               const mpmi_tick_desc* prop, const mpmi_tick_desc* fallback, float* cand_work,
+                               float* head_out, mpmi_selection* out, void* work, size_t work_bytes, void* stream) {
+  if (!ctx) return MPMI_EINVAL;
+  mpmi_system sys;
+  mpmi_status s = model_system(ctx, model, &sys, nullptr);
+  if (s != MPMI_OK) return s;
+  if (sys.basis != MPMI_BASIS_RACE_CAR) return fail(ctx, MPMI_EUNSUPPORTED, "the proposal network serves race-car models");
+  s = check_mlp_common(ctx, w_bf16, w_f32, in_mean, in_std, 1, work, work_bytes);
+  if (s != MPMI_OK) return s;
+  if (!prop || !fallback) return fail(ctx, MPMI_EINVAL, "prop and fallback descriptors must be non-NULL");
+  mpmi_tick_desc pd = *prop;
+  pd.gen = MPMI_GEN_EXPLICIT;
+  if ((s = validate_desc(ctx, sys, &pd)) != MPMI_OK) return s;
+  if ((s = validate_desc(ctx, sys, fallback)) != MPMI_OK) return s;
+  if (pd.n_cand < 1 || pd.n_seg != 1) return fail(ctx, MPMI_EINVAL, "proposals need n_cand >= 1 and n_seg == 1");
+  if (fallback->gen == MPMI_GEN_EXPLICIT) return fail(ctx, MPMI_EINVAL, "the fallback must be GRID or UNIFORM");
+  if (pd.precision != MPMI_PREC_FP32 || fallback->precision != MPMI_PREC_FP32)
+    return fail(ctx, MPMI_EUNSUPPORTED, "only FP32 ticks are available");
+  if (!x_t || !u_user || !cand_work || !out) return fail(ctx, MPMI_EINVAL, "x_t, u_user, cand_work, out must be non-NULL");
+  hipStream_t st = (hipStream_t)stream;
+  float* row = nullptr;
+  float* head = nullptr;
+  hipError_t e = mpmi::launch_mlp_row(x_t, u_user, work, &row, &head, st);
+  if (head_out) head = head_out;
+  if (e == hipSuccess) e = mpmi::launch_mlp_forward(w_bf16, w_f32, in_mean, in_std, row, 1, head, work, st);
+  if (e == hipSuccess) e = mpmi::launch_mdn_sample(model, head, pd.n_cand, pd.seed, pd.tick, pd.loop, cand_work, st);
+  void* slot = (char*)ctx->slots + (size_t)pd.loop * mpmi::slot_bytes();
+  if (e == hipSuccess) e = mpmi::launch_tick(sys.basis, model, pd, x_t, u_user, cand_work, slot, out, nullptr, nullptr, st);
+  void* slot2 = (char*)ctx->slots + (size_t)fallback->loop * mpmi::slot_bytes();
+  if (e == hipSuccess)
+    e = mpmi::launch_tick(sys.basis, model, *fallback, x_t, u_user, nullptr, slot2, out, nullptr, nullptr, st, out);
+  return check_hip(ctx, e, "mpmi_proposal_tick launch");
+}
+
+mpmi_status mpmi_gemm_bf16(mpmi_ctx ctx, const uint16_t* A, const uint16_t* B, int32_t M, int32_t N, int32_t K,
+                           int32_t ta, int32_t tb, float* C, void* stream) {
+  if (!ctx) return MPMI_EINVAL;
+  if (!A || !B || !C) return fail(ctx, MPMI_EINVAL, "NULL argument");
+  if (M < 1 || N < 1 || K < 1 || (ta != 0 && ta != 1) || (tb != 0 && tb != 1))
+    return fail(ctx, MPMI_EINVAL, "bad GEMM shape or transpose flag");
+  return check_hip(ctx, mpmi::launch_gemm_test(A, B, M, N, K, ta, tb, C, (hipStream_t)stream), "mpmi_gemm_bf16");
+}
+
 }  // extern "C"

@@ -20,6 +20,20 @@ constexpr uint64_t kGoldenGamma = 0x9E3779B97F4A7C15ull;
 // splits side by side.
 constexpr int kRTileWords = 2 /*k-blocks*/ * 64 /*lanes*/ * 4 /*u32 = 8 bf16*/;
 
+// Proposal network shape (fixed).
+constexpr int kMlpIn = 8, kMlpHid = 256, kMlpComp = 16, kMlpOut = 5 * kMlpComp;
+constexpr int kMlpParams = kMlpIn * kMlpHid + kMlpHid + 2 * (kMlpHid * kMlpHid + kMlpHid) + kMlpHid * kMlpOut + kMlpOut;
+constexpr float kLogSigMin = -7.0f, kLogSigMax = 2.0f;
+constexpr float kLog2Pi = 1.8378770664093453f;
+
+// FP32 -> BF16 bits, round to nearest even (NaN stays NaN).
+__host__ __device__ inline uint32_t bf16_bits_rne_u(float f) {
+  uint32_t b;
+  __builtin_memcpy(&b, &f, 4);
+  if ((b & 0x7fffffffu) > 0x7f800000u) return 0x7fc0u;
+  return (b + 0x7fffu + ((b >> 16) & 1u)) >> 16;
+}
+
 // Packed model: everything a rollout reads, in one device blob.
 struct alignas(256) ModelDev {
   mpmi_system sys;

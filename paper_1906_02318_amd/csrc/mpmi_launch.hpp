@@ -19,7 +19,7 @@ hipError_t launch_pack(const mpmi_system& sys, int dim, int state_feat0, const d
                        hipStream_t st);
 hipError_t launch_tick(int basis, const void* model, const mpmi_tick_desc& d, const float* x_t,
                        const float* u_user, const float* cand, void* slot, mpmi_selection* out,
-                       int16_t* fv, float* traj, hipStream_t st);
+                       int16_t* fv, float* traj, hipStream_t st, const mpmi_selection* gate = nullptr);
 hipError_t launch_rollout(int basis, const void* model, int Nc, int S, int H, const float* x0,
                           const float* cand, float* traj, hipStream_t st);
 hipError_t launch_mask(int basis, const void* model, int Nc, int H, const float* traj, int16_t* fv,
@@ -33,6 +33,22 @@ hipError_t launch_gen(const void* model, const mpmi_tick_desc& d, const float* u
 size_t fit_workspace_bytes();
 hipError_t launch_fit(const mpmi_system& sys, int dim, const double* X, const double* U, const double* Y,
                       int64_t T, double ridge, double* K_out, void* work, hipStream_t st);
+
+// Proposal network (mpmi_mlp.hip).
+size_t mlp_workspace_bytes(int B);
+hipError_t launch_mlp_forward(const uint16_t* w16, const float* w32, const float* mean, const float* stdv,
+                              const float* X, int B, float* Y, void* work, hipStream_t st);
+hipError_t launch_mlp_grad(const uint16_t* w16, const float* w32, const float* mean, const float* stdv,
+                           const float* X, const float* T, int B, float* grad, float* loss, void* work,
+                           hipStream_t st);
+hipError_t launch_mlp_adam(float* w32, uint16_t* w16, float* m, float* v, const float* grad, int step, float lr,
+                           hipStream_t st);
+hipError_t launch_mdn_sample(const void* model, const float* Yrow, int P, uint64_t seed, uint64_t tick, int loop,
+                             float* cand, hipStream_t st);
+hipError_t launch_mlp_row(const float* x_t, const float* u_user, void* work, float** row, float** head,
+                          hipStream_t st);
+hipError_t launch_gemm_test(const uint16_t* A, const uint16_t* B, int M, int N, int K, int ta, int tb, float* C,
+                            hipStream_t st);
 
 // Many-loop tick (mpmi_multi.hip).
 struct WorkItem;

@@ -1,0 +1,437 @@
+// Learned proposal network: forward, mixture loss, backward, Adam and the
+// mixture sampler, all hand-written for gfx950.
+//
+// Shape (fixed): 8 standardised inputs -> 256 -> 256 -> 256 -> 80, GELU (tanh
+// form) on the hidden layers; the 80 outputs are 16 x {logit, mu_0, mu_1,
+// log sigma_0, log sigma_1} of a diagonal-Gaussian mixture over the input
+// normalised to [-1, 1]^2.  Weights are BF16 (FP32 master copy for Adam);
+// every product accumulates in FP32.
+//
+// The dense products run on BF16 matrix cores (v_mfma_f32_16x16x32_bf16):
+// a 256-thread workgroup computes a 64 x 64 tile of C = op(A) op(B), each wave
+// a 32 x 32 quarter as 2 x 2 MFMA blocks, with 64 x 32 slices of A and B
+// staged through LDS per k-step (transposed operands are transposed while
+// staging, so one kernel serves the forward product and both backward ones).
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+
+#include "mpmi_device.hpp"
+#include "mpmi_launch.hpp"
+
+namespace mpmi {
+
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+constexpr int kGelu = 1, kLinear = 2, kGeluBack = 3, kPlain = 4;
+constexpr float kGeluC = 0.7978845608028654f;  // sqrt(2/pi)
+constexpr float kGeluA = 0.044715f;
+
+__device__ __forceinline__ uint16_t f2bf(float f) { return (uint16_t)bf16_bits_rne_u(f); }
+__device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+__device__ __forceinline__ float gelu_f(float z) {
+  return 0.5f * z * (1.0f + tanhf(kGeluC * fmaf(kGeluA * z * z, z, z)));
+}
+__device__ __forceinline__ float gelu_grad_f(float z) {
+  const float t = tanhf(kGeluC * fmaf(kGeluA * z * z, z, z));
+  return 0.5f * (1.0f + t) + 0.5f * z * (1.0f - t * t) * kGeluC * fmaf(3.0f * kGeluA, z * z, 1.0f);
+}
+
+struct GemmArgs {
+  const uint16_t* A;  // bf16
+  const uint16_t* B;  // bf16
+  int M, N, K;
+  int lda, ldb;
+  int ta, tb;          // A(m,k) = ta ? A[k*lda+m] : A[m*lda+k]; B(k,n) = tb ? B[n*ldb+k] : B[k*ldb+n]
+  const float* bias;   // [N] or NULL
+  const float* zin;    // kGeluBack: pre-activation [M][N] FP32
+  float* out_f32;      // [M][N] or NULL
+  uint16_t* out_bf16;  // [M][N] or NULL
+};
+
+template <int EPI>
+__global__ void __launch_bounds__(256) gemm_bf16_kernel(GemmArgs g) {
+  constexpr int KP = 40;  // padded k extent of an LDS row (80 B, keeps 16-B alignment)
+  __shared__ __attribute__((aligned(16))) uint16_t As[64][KP];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[64][KP];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+  f32x4_t acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+  const int lr = t >> 2, lk = (t & 3) * 8;  // staging: row/col lr, k chunk lk..lk+7
+  for (int k0 = 0; k0 < g.K; k0 += 32) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int k = k0 + lk + q;
+      const int m = m0 + lr, n = n0 + lr;
+      uint16_t a = 0, b = 0;
+      if (m < g.M && k < g.K) a = g.ta ? g.A[(size_t)k * g.lda + m] : g.A[(size_t)m * g.lda + k];
+      if (n < g.N && k < g.K) b = g.tb ? g.B[(size_t)n * g.ldb + k] : g.B[(size_t)k * g.ldb + n];
+      As[lr][lk + q] = a;
+      Bs[lr][lk + q] = b;
+    }
+    __syncthreads();
+    const int kq = (lane >> 4) * 8;
+    bf16x8_t af[2], bfr[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      af[i] = *reinterpret_cast<const bf16x8_t*>(&As[wm * 32 + i * 16 + (lane & 15)][kq]);
+      bfr[i] = *reinterpret_cast<const bf16x8_t*>(&Bs[wn * 32 + i * 16 + (lane & 15)][kq]);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+    __syncthreads();
+  }
+  // D fragment: lane holds column (lane & 15), rows (lane >> 4) * 4 + r.
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wm * 32 + i * 16 + (lane >> 4) * 4 + r;
+        const int n = n0 + wn * 32 + j * 16 + (lane & 15);
+        if (m >= g.M || n >= g.N) continue;
+        float v = acc[i][j][r];
+        const size_t o = (size_t)m * g.N + n;
+        if (EPI == kGelu) {
+          v += g.bias[n];
+          if (g.out_f32) g.out_f32[o] = v;
+          g.out_bf16[o] = f2bf(gelu_f(v));
+        } else if (EPI == kLinear) {
+          v += g.bias[n];
+          if (g.out_f32) g.out_f32[o] = v;
+          if (g.out_bf16) g.out_bf16[o] = f2bf(v);
+        } else if (EPI == kGeluBack) {
+          v *= gelu_grad_f(g.zin[o]);
+          if (g.out_f32) g.out_f32[o] = v;
+          g.out_bf16[o] = f2bf(v);
+        } else {
+          if (g.out_f32) g.out_f32[o] = v;
+          if (g.out_bf16) g.out_bf16[o] = f2bf(v);
+        }
+      }
+}
+
+template <int EPI>
+static hipError_t gemm(const GemmArgs& g, hipStream_t st) {
+  dim3 grid((g.N + 63) / 64, (g.M + 63) / 64);
+  gemm_bf16_kernel<EPI><<<grid, 256, 0, st>>>(g);
+  return hipGetLastError();
+}
+
+// Standardised inputs, BF16: X [B][8] -> H0 [B][8].
+__global__ void mlp_input_kernel(const float* __restrict__ X, const float* __restrict__ mean,
+                                 const float* __restrict__ stdv, int B, uint16_t* __restrict__ H0) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= B * kMlpIn) return;
+  const int j = e % kMlpIn;
+  H0[e] = f2bf((X[e] - mean[j]) / stdv[j]);
+}
+
+// Mixture negative log-likelihood of targets T [B][2] under heads Y [B][80]:
+// per-sample NLL (FP32) and dNLL/dY / B as FP32 and BF16.  One thread per sample.
+__global__ void mdn_loss_kernel(const float* __restrict__ Y, const float* __restrict__ T, int B,
+                                float* __restrict__ nll, float* __restrict__ dY32, uint16_t* __restrict__ dY16,
+                                float* __restrict__ loss_sum) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  float contrib = 0.0f;
+  if (b < B) {
+    const float* y = Y + (size_t)b * kMlpOut;
+    const float t0 = T[2 * b], t1 = T[2 * b + 1];
+    float a[kMlpComp], lp[kMlpComp];
+    float lmax = -INFINITY;
+    for (int k = 0; k < kMlpComp; ++k) lmax = fmaxf(lmax, y[5 * k]);
+    float se = 0.0f;
+    for (int k = 0; k < kMlpComp; ++k) se += expf(y[5 * k] - lmax);
+    const float lse_logit = lmax + logf(se);
+    float amax = -INFINITY;
+    for (int k = 0; k < kMlpComp; ++k) {
+      const float l0 = fminf(fmaxf(y[5 * k + 3], kLogSigMin), kLogSigMax);
+      const float l1 = fminf(fmaxf(y[5 * k + 4], kLogSigMin), kLogSigMax);
+      const float d0 = (t0 - y[5 * k + 1]) * expf(-l0);
+      const float d1 = (t1 - y[5 * k + 2]) * expf(-l1);
+      lp[k] = y[5 * k] - lse_logit;
+      a[k] = lp[k] - (0.5f * (d0 * d0 + d1 * d1) + l0 + l1 + kLog2Pi);
+      amax = fmaxf(amax, a[k]);
+    }
+    float sa = 0.0f;
+    for (int k = 0; k < kMlpComp; ++k) sa += expf(a[k] - amax);
+    const float lse = amax + logf(sa);
+    nll[b] = -lse;
+    contrib = -lse;
+    const float inv_b = 1.0f / (float)B;
+    for (int k = 0; k < kMlpComp; ++k) {
+      const float gam = expf(a[k] - lse);
+      const float pi = expf(lp[k]);
+      const float r0 = y[5 * k + 3], r1 = y[5 * k + 4];
+      const float l0 = fminf(fmaxf(r0, kLogSigMin), kLogSigMax);
+      const float l1 = fminf(fmaxf(r1, kLogSigMin), kLogSigMax);
+      const float is0 = expf(-l0), is1 = expf(-l1);
+      const float d0 = (t0 - y[5 * k + 1]) * is0;
+      const float d1 = (t1 - y[5 * k + 2]) * is1;
+      float gk[5];
+      gk[0] = pi - gam;
+      gk[1] = -gam * d0 * is0;
+      gk[2] = -gam * d1 * is1;
+      gk[3] = (r0 > kLogSigMin && r0 < kLogSigMax) ? gam * (1.0f - d0 * d0) : 0.0f;
+      gk[4] = (r1 > kLogSigMin && r1 < kLogSigMax) ? gam * (1.0f - d1 * d1) : 0.0f;
+      for (int q = 0; q < 5; ++q) {
+        const float v = gk[q] * inv_b;
+        dY32[(size_t)b * kMlpOut + 5 * k + q] = v;
+        dY16[(size_t)b * kMlpOut + 5 * k + q] = f2bf(v);
+      }
+    }
+  }
+  // Workgroup sum of the NLL, one atomic per workgroup (reported loss only).
+  __shared__ float red[256];
+  red[threadIdx.x] = contrib;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && loss_sum) atomicAdd(loss_sum, red[0] / (float)B);
+}
+
+// Column sums of dZ [M][N] (FP32), deterministic: one thread per column.
+__global__ void colsum_kernel(const float* __restrict__ dZ, int M, int N, float* __restrict__ db) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  float s = 0.0f;
+  for (int m = 0; m < M; ++m) s += dZ[(size_t)m * N + n];
+  db[n] = s;
+}
+
+// Adam (Kingma & Ba 2015) with bias correction on the FP32 master weights,
+// refreshing the BF16 copy used by the products.
+__global__ void adam_kernel(float* __restrict__ w, uint16_t* __restrict__ w16, float* __restrict__ mom,
+                            float* __restrict__ vel, const float* __restrict__ grad, int n, float lr, float b1,
+                            float b2, float eps, float c1, float c2) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float g = grad[i];
+  const float m = b1 * mom[i] + (1.0f - b1) * g;
+  const float v = b2 * vel[i] + (1.0f - b2) * g * g;
+  mom[i] = m;
+  vel[i] = v;
+  const float wi = w[i] - lr * (m / c1) / (sqrtf(v / c2) + eps);
+  w[i] = wi;
+  w16[i] = f2bf(wi);
+}
+
+// Proposal p of one mixture head: component by inverse CDF of the FP32
+// softmax weights, Box-Muller normals, clip to [-1, 1], map to the input box.
+// Writes cand [1][m][P] (EXPLICIT layout, m = 2).
+__global__ void mdn_sample_kernel(const ModelDev* __restrict__ md, const float* __restrict__ Yrow, int P,
+                                  uint64_t seed, uint64_t tick, int loop, float* __restrict__ cand) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  float w[kMlpComp];
+  float lmax = -INFINITY;
+  for (int k = 0; k < kMlpComp; ++k) lmax = fmaxf(lmax, Yrow[5 * k]);
+  float acc = 0.0f;
+  for (int k = 0; k < kMlpComp; ++k) {
+    acc += expf(Yrow[5 * k] - lmax);
+    w[k] = acc;
+  }
+  const uint64_t h0 = hash_counter(seed, tick, (uint64_t)(uint32_t)loop, (uint64_t)p, 0);
+  const uint64_t h1 = hash_counter(seed, tick, (uint64_t)(uint32_t)loop, (uint64_t)p, 1);
+  const uint64_t h2 = hash_counter(seed, tick, (uint64_t)(uint32_t)loop, (uint64_t)p, 2);
+  const float r0 = (float)((double)(h0 >> 40) * 0x1p-24);
+  int kc = 0;
+  for (int k = 0; k < kMlpComp; ++k) kc += (w[k] / acc <= r0) ? 1 : 0;
+  kc = kc < kMlpComp ? kc : kMlpComp - 1;
+  const float r1 = (float)(((double)(h1 >> 40) + 1.0) * 0x1p-24);
+  const float r2 = (float)((double)(h2 >> 40) * 0x1p-24);
+  const float rad = sqrtf(-2.0f * logf(r1));
+  float sn, cs;
+  sincosf(6.283185307179586f * r2, &sn, &cs);
+  const float z[2] = {rad * cs, rad * sn};
+  for (int j = 0; j < 2; ++j) {
+    const float ls = fminf(fmaxf(Yrow[5 * kc + 3 + j], kLogSigMin), kLogSigMax);
+    float un = fmaf(expf(ls), z[j], Yrow[5 * kc + 1 + j]);
+    un = fminf(fmaxf(un, -1.0f), 1.0f);
+    const float lo = md->sys.u_lo[j], hi = md->sys.u_hi[j];
+    cand[(size_t)j * P + p] = fmaf(0.5f * (hi - lo), un, 0.5f * (lo + hi));
+  }
+}
+
+// [x_t; u_user] -> one input row.
+__global__ void mlp_row_kernel(const float* __restrict__ x_t, const float* __restrict__ u_user,
+                               float* __restrict__ X) {
+  const int j = threadIdx.x;
+  if (j < 6) X[j] = x_t[j];
+  else if (j < 8) X[j] = u_user[j - 6];
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers
+// ---------------------------------------------------------------------------
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct MlpWork {
+  uint16_t *h0, *h1, *h2, *h3, *dY16, *dz16;
+  float *z1, *z2, *z3, *Y, *dY32, *dz32, *nll, *loss, *row;
+};
+
+static MlpWork carve(void* base, int B) {
+  char* p = (char*)base;
+  MlpWork w;
+  auto take = [&](size_t bytes) { char* r = p; p += align256(bytes); return (void*)r; };
+  w.h0 = (uint16_t*)take((size_t)B * kMlpIn * 2);
+  w.h1 = (uint16_t*)take((size_t)B * kMlpHid * 2);
+  w.h2 = (uint16_t*)take((size_t)B * kMlpHid * 2);
+  w.h3 = (uint16_t*)take((size_t)B * kMlpHid * 2);
+  w.dY16 = (uint16_t*)take((size_t)B * kMlpOut * 2);
+  w.dz16 = (uint16_t*)take((size_t)B * kMlpHid * 2 * 2);  // two ping-pong halves
+  w.z1 = (float*)take((size_t)B * kMlpHid * 4);
+  w.z2 = (float*)take((size_t)B * kMlpHid * 4);
+  w.z3 = (float*)take((size_t)B * kMlpHid * 4);
+  w.Y = (float*)take((size_t)B * kMlpOut * 4);
+  w.dY32 = (float*)take((size_t)B * kMlpOut * 4);
+  w.dz32 = (float*)take((size_t)B * kMlpHid * 4 * 2);
+  w.nll = (float*)take((size_t)B * 4);
+  w.loss = (float*)take(4);
+  w.row = (float*)take(kMlpIn * 4);
+  return w;
+}
+
+size_t mlp_workspace_bytes(int B) {
+  char* base = nullptr;
+  MlpWork w = carve((void*)base, B);
+  return (size_t)((char*)w.row - base) + align256(kMlpIn * 4);
+}
+
+// Offsets of (W_l, b_l) in the flat parameter vector.
+static void layer_offsets(size_t* ow, size_t* ob) {
+  const int dims[5] = {kMlpIn, kMlpHid, kMlpHid, kMlpHid, kMlpOut};
+  size_t o = 0;
+  for (int l = 0; l < 4; ++l) {
+    ow[l] = o;
+    o += (size_t)dims[l] * dims[l + 1];
+    ob[l] = o;
+    o += dims[l + 1];
+  }
+}
+
+static hipError_t forward_into(const uint16_t* w16, const float* bias32, const float* mean, const float* stdv,
+                               const float* X, int B, const MlpWork& w, float* Y, hipStream_t st) {
+  size_t ow[4], ob[4];
+  layer_offsets(ow, ob);
+  mlp_input_kernel<<<(B * kMlpIn + 255) / 256, 256, 0, st>>>(X, mean, stdv, B, w.h0);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const uint16_t* hin[4] = {w.h0, w.h1, w.h2, w.h3};
+  uint16_t* hout[3] = {w.h1, w.h2, w.h3};
+  float* zout[3] = {w.z1, w.z2, w.z3};
+  const int din[4] = {kMlpIn, kMlpHid, kMlpHid, kMlpHid};
+  for (int l = 0; l < 3; ++l) {
+    GemmArgs g{};
+    g.A = hin[l]; g.B = w16 + ow[l]; g.M = B; g.N = kMlpHid; g.K = din[l];
+    g.lda = din[l]; g.ldb = kMlpHid; g.bias = bias32 + ob[l]; g.out_f32 = zout[l]; g.out_bf16 = hout[l];
+    if ((e = gemm<kGelu>(g, st)) != hipSuccess) return e;
+  }
+  GemmArgs g{};
+  g.A = w.h3; g.B = w16 + ow[3]; g.M = B; g.N = kMlpOut; g.K = kMlpHid;
+  g.lda = kMlpHid; g.ldb = kMlpOut; g.bias = bias32 + ob[3]; g.out_f32 = Y;
+  return gemm<kLinear>(g, st);
+}
+
+// Biases are kept in FP32 (they add to FP32 accumulators): the FP32 master
+// vector is passed alongside the BF16 weights.
+hipError_t launch_mlp_forward(const uint16_t* w16, const float* w32, const float* mean, const float* stdv,
+                              const float* X, int B, float* Y, void* work, hipStream_t st) {
+  const MlpWork w = carve(work, B);
+  return forward_into(w16, w32, mean, stdv, X, B, w, Y, st);
+}
+
+hipError_t launch_mlp_grad(const uint16_t* w16, const float* w32, const float* mean, const float* stdv,
+                           const float* X, const float* T, int B, float* grad, float* loss, void* work,
+                           hipStream_t st) {
+  const MlpWork w = carve(work, B);
+  hipError_t e = hipMemsetAsync(w.loss, 0, sizeof(float), st);
+  if (e != hipSuccess) return e;
+  if ((e = forward_into(w16, w32, mean, stdv, X, B, w, w.Y, st)) != hipSuccess) return e;
+  mdn_loss_kernel<<<(B + 255) / 256, 256, 0, st>>>(w.Y, T, B, w.nll, w.dY32, w.dY16, w.loss);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  size_t ow[4], ob[4];
+  layer_offsets(ow, ob);
+  const int dims[5] = {kMlpIn, kMlpHid, kMlpHid, kMlpHid, kMlpOut};
+  const uint16_t* hin[4] = {w.h0, w.h1, w.h2, w.h3};
+  const float* zin[4] = {nullptr, w.z1, w.z2, w.z3};
+  // dz of the current layer (output width dims[l+1]): FP32 for bias sums, BF16 as operand.
+  const float* dz32 = w.dY32;
+  const uint16_t* dz16 = w.dY16;
+  for (int l = 3; l >= 0; --l) {
+    const int kin = dims[l], nout = dims[l + 1];
+    // dW_l = h_{l-1}^T dz  ([kin][nout])
+    GemmArgs gw{};
+    gw.A = hin[l]; gw.ta = 1; gw.lda = kin;
+    gw.B = dz16; gw.ldb = nout;
+    gw.M = kin; gw.N = nout; gw.K = B; gw.out_f32 = grad + ow[l];
+    if ((e = gemm<kPlain>(gw, st)) != hipSuccess) return e;
+    colsum_kernel<<<(nout + 255) / 256, 256, 0, st>>>(dz32, B, nout, grad + ob[l]);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (l == 0) break;
+    // dz_{l-1} = (dz W_l^T) * gelu'(z_{l-1})  ([B][kin])
+    const int half = (l % 2) * B * kMlpHid;
+    GemmArgs gd{};
+    gd.A = dz16; gd.lda = nout;
+    gd.B = w16 + ow[l]; gd.tb = 1; gd.ldb = nout;
+    gd.M = B; gd.N = kin; gd.K = nout;
+    gd.zin = zin[l]; gd.out_f32 = w.dz32 + half; gd.out_bf16 = w.dz16 + half;
+    if ((e = gemm<kGeluBack>(gd, st)) != hipSuccess) return e;
+    dz32 = w.dz32 + half;
+    dz16 = w.dz16 + half;
+  }
+  if (loss) {
+    e = hipMemcpyAsync(loss, w.loss, sizeof(float), hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_mlp_adam(float* w32, uint16_t* w16, float* m, float* v, const float* grad, int step, float lr,
+                           hipStream_t st) {
+  const float b1 = 0.9f, b2 = 0.999f;
+  const float c1 = (float)(1.0 - pow(0.9, step)), c2 = (float)(1.0 - pow(0.999, step));
+  adam_kernel<<<(kMlpParams + 255) / 256, 256, 0, st>>>(w32, w16, m, v, grad, kMlpParams, lr, b1, b2, 1e-8f, c1, c2);
+  return hipGetLastError();
+}
+
+hipError_t launch_mdn_sample(const void* model, const float* Yrow, int P, uint64_t seed, uint64_t tick, int loop,
+                             float* cand, hipStream_t st) {
+  mdn_sample_kernel<<<(P + 255) / 256, 256, 0, st>>>((const ModelDev*)model, Yrow, P, seed, tick, loop, cand);
+  return hipGetLastError();
+}
+
+// Assembles the single input row in the workspace; *row is that row and
+// *head the workspace's output area for a one-row forward.
+hipError_t launch_mlp_row(const float* x_t, const float* u_user, void* work, float** row, float** head,
+                          hipStream_t st) {
+  const MlpWork w = carve(work, 1);
+  mlp_row_kernel<<<1, 64, 0, st>>>(x_t, u_user, w.row);
+  *row = w.row;
+  *head = w.Y;
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm_test(const uint16_t* A, const uint16_t* B, int M, int N, int K, int ta, int tb, float* C,
+                            hipStream_t st) {
+  GemmArgs g{};
+  g.A = A; g.B = B; g.M = M; g.N = N; g.K = K; g.ta = ta; g.tb = tb;
+  g.lda = ta ? M : K;
+  g.ldb = tb ? K : N;
+  g.out_f32 = C;
+  return gemm<kPlain>(g, st);
+}
+
+}  // namespace mpmi

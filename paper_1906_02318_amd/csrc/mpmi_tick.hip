@@ -25,8 +25,12 @@ __global__ void __launch_bounds__(1024)
 tick_fp32_kernel(const ModelDev* __restrict__ md, GenParams gp, int H, const float* __restrict__ x_t,
                  const float* __restrict__ u_user, const float* __restrict__ cand,
                  Slot* __restrict__ slot, mpmi_selection* __restrict__ out,
-                 int16_t* __restrict__ fv_out, float* __restrict__ traj) {
+                 int16_t* __restrict__ fv_out, float* __restrict__ traj,
+                 const mpmi_selection* __restrict__ gate) {
   constexpr int MS = Dims<BASIS>::M;
+  // Gated form (fallback after a proposal tick): nothing to do if the gate
+  // selection already found a safe candidate.  Uniform across the grid.
+  if (gate && gate->status == MPMI_OK) return;
   __shared__ float4 sK[kLdsKFloat4];
   stage_K<BASIS>(md, sK);
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
@@ -127,12 +131,6 @@ __global__ void gen_kernel(const ModelDev* __restrict__ md, GenParams gp, const 
 // ---------------------------------------------------------------------------
 // Model packing
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t bf16_bits_rne(float f) {
-  const uint32_t b = __float_as_uint(f);
-  if ((b & 0x7fffffffu) > 0x7f800000u) return 0x7fc0u;  // NaN
-  return (b + 0x7fffu + ((b >> 16) & 1u)) >> 16;
-}
-
 __global__ void pack_kernel(mpmi_system sys, int dim, int state_feat0, const double* __restrict__ K,
                             ModelDev* __restrict__ md) {
   const int t = threadIdx.x;
@@ -153,9 +151,9 @@ __global__ void pack_kernel(mpmi_system sys, int dim, int state_feat0, const dou
       if (row == state_feat0 + col) r -= 1.0;
     }
     const float rf = (float)r;
-    const uint32_t hi = bf16_bits_rne(rf);
+    const uint32_t hi = bf16_bits_rne_u(rf);
     const float lo = rf - __uint_as_float(hi << 16);
-    const uint32_t lob = bf16_bits_rne(lo);
+    const uint32_t lob = bf16_bits_rne_u(lo);
     const int word = (kb * 64 + lane) * 4 + (q >> 1);
     const int sh = (q & 1) * 16;
     atomicOr(&md->Rhi[word], hi << sh);
@@ -227,7 +225,7 @@ hipError_t launch_pack(const mpmi_system& sys, int dim, int state_feat0, const d
 
 hipError_t launch_tick(int basis, const void* model, const mpmi_tick_desc& d, const float* x_t,
                        const float* u_user, const float* cand, void* slot, mpmi_selection* out,
-                       int16_t* fv, float* traj, hipStream_t st) {
+                       int16_t* fv, float* traj, hipStream_t st, const mpmi_selection* gate) {
   const GenParams gp = make_gen(d);
   const int block = d.block > 0 ? d.block : 256;
   const unsigned grid = blocks_for((long long)d.n_cand + 1, block);
@@ -235,13 +233,13 @@ hipError_t launch_tick(int basis, const void* model, const mpmi_tick_desc& d, co
   Slot* sl = (Slot*)slot;
   switch (basis) {
     case MPMI_BASIS_LINEAR:
-      tick_fp32_kernel<MPMI_BASIS_LINEAR><<<grid, block, 0, st>>>(md, gp, d.horizon, x_t, u_user, cand, sl, out, fv, traj);
+      tick_fp32_kernel<MPMI_BASIS_LINEAR><<<grid, block, 0, st>>>(md, gp, d.horizon, x_t, u_user, cand, sl, out, fv, traj, gate);
       break;
     case MPMI_BASIS_BALANCE_BOT:
-      tick_fp32_kernel<MPMI_BASIS_BALANCE_BOT><<<grid, block, 0, st>>>(md, gp, d.horizon, x_t, u_user, cand, sl, out, fv, traj);
+      tick_fp32_kernel<MPMI_BASIS_BALANCE_BOT><<<grid, block, 0, st>>>(md, gp, d.horizon, x_t, u_user, cand, sl, out, fv, traj, gate);
       break;
     default:
-      tick_fp32_kernel<MPMI_BASIS_RACE_CAR><<<grid, block, 0, st>>>(md, gp, d.horizon, x_t, u_user, cand, sl, out, fv, traj);
+      tick_fp32_kernel<MPMI_BASIS_RACE_CAR><<<grid, block, 0, st>>>(md, gp, d.horizon, x_t, u_user, cand, sl, out, fv, traj, gate);
       break;
   }
   return hipGetLastError();

@@ -114,6 +114,14 @@ def library() -> ctypes.CDLL:
         "mpmi_multi_graph": (i32, [vp, vp, ctypes.POINTER(vp)]),
         "mpmi_graph_launch": (i32, [vp, vp, vp]),
         "mpmi_graph_destroy": (None, [vp]),
+        "mlp_workspace_bytes": (ctypes.c_size_t, [i32]),
+        "mlp_forward": (i32, [vp, vp, vp, vp, vp, vp, i32, vp, vp, ctypes.c_size_t, vp]),
+        "mlp_grad": (i32, [vp, vp, vp, vp, vp, vp, vp, i32, vp, vp, vp, ctypes.c_size_t, vp]),
+        "mlp_adam": (i32, [vp, vp, vp, vp, vp, vp, i32, ctypes.c_float, vp]),
+        "mdn_sample": (i32, [vp, vp, vp, i32, ctypes.c_uint64, ctypes.c_uint64, i32, vp, vp]),
+        "mpmi_proposal_tick": (i32, [vp, vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(TickDesc),
+                                     ctypes.POINTER(TickDesc), vp, vp, vp, vp, ctypes.c_size_t, vp]),
+        "mpmi_gemm_bf16": (i32, [vp, vp, vp, i32, i32, i32, i32, i32, vp, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -461,3 +469,77 @@ class Multi:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------------------
+# Proposal network
+# ---------------------------------------------------------------------------
+MLP_IN, MLP_HIDDEN, MLP_COMP, MLP_OUT, MLP_PARAMS = 8, 256, 16, 80, 154448
+
+
+def mlp_workspace(ctx: Context, batch: int) -> torch.Tensor:
+    n = int(ctx.lib.mlp_workspace_bytes(batch))
+    if n == 0:
+        raise ValueError(f"batch {batch} out of range")
+    buf = torch.empty(n + 256, dtype=torch.uint8, device=ctx.device)
+    off = (-buf.data_ptr()) % 256
+    return buf[off:off + n]
+
+
+def mlp_forward(ctx: Context, w16, w32, mean, std, X, work=None, stream=None):
+    B = X.shape[0]
+    _need(w16, "w16", torch.bfloat16, MLP_PARAMS, device=ctx.device)
+    _need(w32, "w32", torch.float32, MLP_PARAMS, device=ctx.device)
+    _need(X, "X", torch.float32, B * MLP_IN, device=ctx.device)
+    work = mlp_workspace(ctx, B) if work is None else work
+    Y = torch.empty((B, MLP_OUT), dtype=torch.float32, device=ctx.device)
+    ctx.check(ctx.lib.mlp_forward(ctx.handle, _ptr(w16), _ptr(w32), _ptr(mean), _ptr(std), _ptr(X), B, _ptr(Y),
+                                  _ptr(work), work.numel(), _stream(stream)))
+    return Y
+
+
+def mlp_grad(ctx: Context, w16, w32, mean, std, X, T, work=None, grad=None, loss=None, stream=None):
+    B = X.shape[0]
+    _need(X, "X", torch.float32, B * MLP_IN, device=ctx.device)
+    _need(T, "T", torch.float32, B * 2, device=ctx.device)
+    work = mlp_workspace(ctx, B) if work is None else work
+    grad = torch.empty(MLP_PARAMS, dtype=torch.float32, device=ctx.device) if grad is None else grad
+    loss = torch.empty(1, dtype=torch.float32, device=ctx.device) if loss is None else loss
+    ctx.check(ctx.lib.mlp_grad(ctx.handle, _ptr(w16), _ptr(w32), _ptr(mean), _ptr(std), _ptr(X), _ptr(T), B,
+                               _ptr(grad), _ptr(loss), _ptr(work), work.numel(), _stream(stream)))
+    return grad, loss
+
+
+def mlp_adam(ctx: Context, w32, w16, m, v, grad, step: int, lr: float = 1e-3, stream=None):
+    ctx.check(ctx.lib.mlp_adam(ctx.handle, _ptr(w32), _ptr(w16), _ptr(m), _ptr(v), _ptr(grad), step, lr,
+                               _stream(stream)))
+
+
+def mdn_sample(ctx: Context, model: Model, head, P: int, seed: int = 0, tick: int = 0, loop: int = 0,
+               cand=None, stream=None):
+    """P proposals (1, 2, P) float32 from one head (80,)."""
+    _need(head, "head", torch.float32, MLP_OUT, device=ctx.device)
+    cand = torch.empty((1, 2, P), dtype=torch.float32, device=ctx.device) if cand is None else cand
+    ctx.check(ctx.lib.mdn_sample(ctx.handle, ctypes.c_void_p(model.ptr), _ptr(head), P, seed, tick, loop,
+                                 _ptr(cand), _stream(stream)))
+    return cand
+
+
+def mpmi_proposal_tick(ctx: Context, model: Model, net: dict, x_t, u_user, prop: TickDesc, fallback: TickDesc,
+                       cand_work, work, out=None, head_out=None, stream=None):
+    """Learned-proposal tick; net holds w16, w32, mean, std device tensors."""
+    out = torch.empty(SELECTION_BYTES, dtype=torch.uint8, device=ctx.device) if out is None else out
+    _need(cand_work, "cand_work", torch.float32, 2 * prop.n_cand, device=ctx.device)
+    ctx.check(ctx.lib.mpmi_proposal_tick(
+        ctx.handle, ctypes.c_void_p(model.ptr), _ptr(net["w16"]), _ptr(net["w32"]), _ptr(net["mean"]),
+        _ptr(net["std"]), _ptr(x_t), _ptr(u_user), ctypes.byref(prop), ctypes.byref(fallback), _ptr(cand_work),
+        _ptr(head_out), _ptr(out), _ptr(work), work.numel(), _stream(stream)))
+    return out
+
+
+def mpmi_gemm_bf16(ctx: Context, A, B, M: int, N: int, K: int, ta: int = 0, tb: int = 0, stream=None):
+    _need(A, "A", torch.bfloat16, M * K, device=ctx.device)
+    _need(B, "B", torch.bfloat16, K * N, device=ctx.device)
+    C = torch.empty((M, N), dtype=torch.float32, device=ctx.device)
+    ctx.check(ctx.lib.mpmi_gemm_bf16(ctx.handle, _ptr(A), _ptr(B), M, N, K, ta, tb, _ptr(C), _stream(stream)))
+    return C

@@ -253,3 +253,20 @@ def loop_sizes(n_loops: int = 64, seed: int = 5, n_lo: int = 1024, n_hi: int = 6
     N = np.rint(np.exp(rng.uniform(math.log(n_lo), math.log(n_hi), size=n_loops))).astype(np.int64)
     H = rng.integers(h_lo, h_hi + 1, size=n_loops)
     return N, H
+
+
+# ----------------------------------------------------------------------------
+# Proposal-network initialisation and label states
+# ----------------------------------------------------------------------------
+MLP_LAYERS = [(8, 256), (256, 256), (256, 256), (256, 80)]
+
+
+def mlp_init(seed: int = 6) -> np.ndarray:
+    """Flat initial parameters: per layer W [in][out] ~ U(-1/sqrt(in), 1/sqrt(in)), b = 0."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for k, n in MLP_LAYERS:
+        lim = 1.0 / math.sqrt(k)
+        parts.append(rng.uniform(-lim, lim, size=k * n))
+        parts.append(np.zeros(n))
+    return np.concatenate(parts)
