@@ -236,6 +236,61 @@ def run_multi(n_ticks: int = 2000, warmup: int = 50, seed: int = 5):
     }
 
 
+def run_closed_loop_balance_bot(n_ticks: int = 1000, warmup: int = 20):
+    """Cart-pole at real-time size: N = 10,240 five-segment sequences, H = 50,
+    a 1,000-tick closed loop (plant advanced on the host with the applied input,
+    user input an AR(1) walk, rho 0.95, sigma 1 N) against a 10 ms budget."""
+    import torch
+
+    import synth
+    from paper_1906_02318_amd import mpmi
+
+    st = setup(WORKLOADS["balance_bot_rt"], 1)
+    ctx, model = st["ctx"], st["model"]
+    stream = torch.cuda.current_stream()
+    x = synth.balance_bot_states(1, seed=3)[0]
+    user = synth.AR1User([-5.0], [5.0], rho=0.95, sigma=1.0, seed=2)
+    x_pin = torch.zeros(4, dtype=torch.float32).pin_memory()
+    u_pin = torch.zeros(1, dtype=torch.float32).pin_memory()
+    o_pin = torch.zeros(mpmi.SELECTION_BYTES, dtype=torch.uint8).pin_memory()
+    x_dev = torch.zeros(4, dtype=torch.float32, device="cuda")
+    u_dev = torch.zeros(1, dtype=torch.float32, device="cuda")
+    out = torch.zeros(mpmi.SELECTION_BYTES, dtype=torch.uint8, device="cuda")
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    dev_ms, e2e_ms, falls, interventions = [], [], 0, 0
+    for t in range(warmup + n_ticks):
+        u = user.next()
+        t0 = time.perf_counter()
+        x_pin.copy_(torch.from_numpy(x.astype(np.float32)))
+        u_pin.copy_(torch.from_numpy(u.astype(np.float32)))
+        x_dev.copy_(x_pin, non_blocking=True)
+        u_dev.copy_(u_pin, non_blocking=True)
+        desc = mpmi.tick_desc(10240, 50, gen=mpmi.GEN_UNIFORM, n_seg=5, seed=4, tick=t)
+        ev0.record(stream)
+        mpmi.mpmi_tick(ctx, model, desc, x_dev, u_dev, out=out, stream=stream)
+        ev1.record(stream)
+        o_pin.copy_(out, non_blocking=True)
+        stream.synchronize()
+        t1 = time.perf_counter()
+        rec = o_pin.numpy()
+        u_r = float(rec.view(np.float32)[4])
+        if t >= warmup:
+            dev_ms.append(ev0.elapsed_time(ev1))
+            e2e_ms.append((t1 - t0) * 1e3)
+            interventions += int(rec.view(np.int32)[0] != 0)
+        x = synth.cartpole_step(x, np.array([u_r]))[0]
+        if abs(x[2]) > 0.5 or abs(x[0]) > 2.0:
+            falls += 1
+            x = synth.balance_bot_states(1, seed=100 + t)[0]
+    dev, e2e = np.array(dev_ms), np.array(e2e_ms)
+    return {"workload": "cart-pole closed loop, N=10240 sequences (S=5) + u_h, H=50, AR(1) user",
+            "ticks": n_ticks, "trajectories_per_s_device": 10241 / (dev.mean() * 1e-3),
+            "p50_tick_ms": float(np.percentile(dev, 50)), "p99_tick_ms": float(np.percentile(dev, 99)),
+            "p50_end_to_end_ms": float(np.percentile(e2e, 50)), "p99_end_to_end_ms": float(np.percentile(e2e, 99)),
+            "within_10ms_budget": float(np.mean(e2e < 10.0)), "interventions": interventions,
+            "safety_violations": falls}
+
+
 def run_plain_vs_learned(n_ticks: int = 500, warmup: int = 20):
     """Race car at its stated size: exhaustive 128 x 128 grid tick vs the learned
     2,048-proposal tick (exhaustive fallback), on the same tick inputs."""
@@ -299,6 +354,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-extras", action="store_true", help="skip the many-loop and plain-vs-learned legs")
     ap.add_argument("--multi-ticks", type=int, default=2000)
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="after timing, run one device-to-device copy of this many bytes (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the tick's candidates would shard "
@@ -392,9 +449,16 @@ def main():
             "flops_per_unit": FLOPS_PER_UNIT[wl["system"]],
         },
     }
+    if args.copy_bytes > 0:
+        src = torch.empty(args.copy_bytes, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["calibration_copy_bytes"] = args.copy_bytes
     if not args.no_extras and args.workload == "race_car_1m":
         out["race_car_16k"] = run_plain_vs_learned()
         out["many_loops"] = run_multi(n_ticks=args.multi_ticks)
+        out["balance_bot_closed_loop"] = run_closed_loop_balance_bot()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, st, args.cpu_budget)
     print(json.dumps(out), flush=True)

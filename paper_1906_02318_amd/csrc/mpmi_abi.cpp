@@ -18,6 +18,7 @@ struct mpmi_ctx_s {
   int device = 0;
   void* slots = nullptr;       // MPMI_MAX_LOOPS selection slots
   void* fit_work = nullptr;    // fit partial sums, totals and info
+  void* recheck = nullptr;     // BF16X3 recheck list (count + indices)
   std::unordered_map<const void*, mpmi_system> models;  // packed models, by device address
   std::string err;
 };
@@ -134,12 +135,13 @@ mpmi_status mpmi_create(mpmi_ctx* out, int32_t device) {
   }
   const size_t slot_bytes = (size_t)MPMI_MAX_LOOPS * mpmi::slot_bytes();
   if (hipMalloc(&ctx->slots, slot_bytes) != hipSuccess ||
-      hipMalloc(&ctx->fit_work, mpmi::fit_workspace_bytes()) != hipSuccess) {
+      hipMalloc(&ctx->fit_work, mpmi::fit_workspace_bytes()) != hipSuccess ||
+      hipMalloc(&ctx->recheck, mpmi::recheck_bytes(mpmi::kRecheckCapacity)) != hipSuccess) {
     mpmi_destroy(ctx);
     return MPMI_ENOMEM;
   }
   // Reset state of a slot: both keys all-ones, counters zero.
-  if (hipMemset(ctx->slots, 0, slot_bytes) != hipSuccess) {
+  if (hipMemset(ctx->slots, 0, slot_bytes) != hipSuccess || hipMemset(ctx->recheck, 0, 256) != hipSuccess) {
     mpmi_destroy(ctx);
     return MPMI_EDEVICE;
   }
@@ -161,6 +163,7 @@ void mpmi_destroy(mpmi_ctx ctx) {
   if (!ctx) return;
   if (ctx->slots) (void)hipFree(ctx->slots);
   if (ctx->fit_work) (void)hipFree(ctx->fit_work);
+  if (ctx->recheck) (void)hipFree(ctx->recheck);
   delete ctx;
 }
 
@@ -301,9 +304,18 @@ mpmi_status mpmi_tick(mpmi_ctx ctx, const void* model, const mpmi_tick_desc* des
   if (!x_t || !u_user || !out) return fail(ctx, MPMI_EINVAL, "x_t, u_user and out must be non-NULL");
   if (desc->gen == MPMI_GEN_EXPLICIT && desc->n_cand > 0 && !cand)
     return fail(ctx, MPMI_EINVAL, "EXPLICIT candidates need cand");
-  if (desc->precision != MPMI_PREC_FP32)
-    return fail(ctx, MPMI_EUNSUPPORTED, "precision %d is not available in this build", desc->precision);
   void* slot = (char*)ctx->slots + (size_t)desc->loop * mpmi::slot_bytes();
+  if (desc->precision == MPMI_PREC_BF16X3) {
+    if (sys.basis != MPMI_BASIS_RACE_CAR)
+      return fail(ctx, MPMI_EUNSUPPORTED, "BF16X3 is implemented for race-car models");
+    if (traj) return fail(ctx, MPMI_EUNSUPPORTED, "BF16X3 ticks do not store trajectories");
+    if (desc->block != 0 && desc->block != 256)
+      return fail(ctx, MPMI_EUNSUPPORTED, "BF16X3 ticks use 256-thread workgroups");
+    return check_hip(ctx, mpmi::launch_tick_bf16(model, *desc, x_t, u_user, cand, slot, out, first_violation,
+                                                 ctx->recheck, mpmi::kRecheckCapacity,
+                                                 mpmi::device_cu_count() * 4, (hipStream_t)stream),
+                     "mpmi_tick (BF16X3) launch");
+  }
   return check_hip(ctx, mpmi::launch_tick(sys.basis, model, *desc, x_t, u_user, cand, slot, out, first_violation,
                                           traj, (hipStream_t)stream),
                    "mpmi_tick launch");

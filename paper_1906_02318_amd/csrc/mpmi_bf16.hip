@@ -1,0 +1,291 @@
+// Race-car tick with the shared-coefficient part of the contraction on BF16
+// matrix cores (precision MPMI_PREC_BF16X3), plus the FP32 recheck of every
+// candidate that comes within eps of a constraint.
+//
+// Per step, each lane (one candidate) forms the 27 features made of state
+// alone (21 quadratics and sin/cos psi x (vx, vy, r)) whose K rows are shared
+// by every candidate; the input-dependent terms stay folded into per-lane FP32
+// coefficients as in the FP32 path.  The 27 features are split into BF16
+// hi + lo parts and written to LDS; each wave then runs, for its four groups
+// of 16 candidates, hi*Khi + hi*Klo + lo*Khi on v_mfma_f32_16x16x32_bf16 with
+// FP32 accumulation (about 16 mantissa bits per product), and reads its own
+// six outputs back.  The horizon loop is wave-uniform (a matrix instruction
+// needs every lane), and a lane that left the safe set keeps its state frozen.
+//
+// A candidate whose margin to some constraint is below that constraint's eps
+// at some step up to its first violation is appended to a recheck list
+// instead of publishing; a second launch re-rolls the listed candidates in
+// FP32, publishes them, and its last workgroup finalises the selection.
+#include <hip/hip_runtime.h>
+
+#include "mpmi_device.hpp"
+#include "mpmi_launch.hpp"
+#include "mpmi_tick_common.hpp"
+
+namespace mpmi {
+
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+constexpr int kWaves = 4;            // waves per workgroup (256 threads)
+constexpr int kArow = 40;            // bf16 per LDS feature row (32 + 8 pad = 80 B)
+
+struct RecheckList {
+  unsigned int count;
+  unsigned int pad[63];
+  int idx[1];  // capacity entries follow
+};
+
+// true if some constraint margin of x is within eps of zero (either side).
+__device__ __forceinline__ bool near_boundary(const ModelDev* __restrict__ md, const float* x) {
+  bool near = false;
+  const int nb = md->sys.n_box;
+  for (int b = 0; b < nb; ++b) {
+    const float mg = md->bb_lim[b] - fabsf(pick<6>(x, md->sys.box_index[b]));
+    near |= fabsf(mg) < md->sys.eps_box[b];
+  }
+  if (md->sys.has_track) {
+    const float r2 = fmaf(x[0], x[0], x[1] * x[1]);
+    const float inv = __builtin_amdgcn_rsqf(r2);
+    const float rho = r2 * inv;
+    const float c1 = x[0] * inv, s1 = x[1] * inv;
+    float rc = md->trk_r0, ch = 1.0f, sh = 0.0f;
+    for (int h = 1; h <= md->hmax; ++h) {
+      const float cn = ch * c1 - sh * s1;
+      const float sn = sh * c1 + ch * s1;
+      ch = cn;
+      sh = sn;
+      rc = fmaf(md->trk_s[h], sh, rc);
+      rc = fmaf(md->trk_c[h], ch, rc);
+    }
+    near |= fabsf(md->trk_lim - fabsf(rho - rc)) < md->sys.eps_track;
+  }
+  return near;
+}
+
+__device__ __forceinline__ uint16_t bf16_hi(float v) { return (uint16_t)bf16_bits_rne_u(v); }
+
+__global__ void __launch_bounds__(256)
+tick_bf16_race_car_kernel(const ModelDev* __restrict__ md, GenParams gp, int H, const float* __restrict__ x_t,
+                          const float* __restrict__ u_user, const float* __restrict__ cand,
+                          Slot* __restrict__ slot, int16_t* __restrict__ fv_out, RecheckList* __restrict__ rl,
+                          int capacity) {
+  __shared__ float4 sK[kLdsKFloat4];
+  __shared__ __attribute__((aligned(16))) uint16_t sA[kWaves][2][64][kArow];  // [wave][hi/lo][cand][k]
+  __shared__ __attribute__((aligned(16))) float sD[kWaves][64][8];            // [wave][cand][output]
+  stage_K<MPMI_BASIS_RACE_CAR>(md, sK);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int Nc = gp.n_cand + 1;
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = c < Nc;
+
+  // B operand: the 27 shared K rows (k) x 6 outputs (n), zero-padded to 32 x 16.
+  bf16x8_t bhi, blo;
+  {
+    const float* Ks = reinterpret_cast<const float*>(sK) + kRcStepOff;
+    const int n = lane & 15, k0 = (lane >> 4) * 8;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int k = k0 + i;
+      const float v = (n < 6 && k < kRcStepRows) ? Ks[k * 6 + n] : 0.0f;
+      const uint16_t h = bf16_hi(v);
+      const float vh = __uint_as_float((uint32_t)h << 16);
+      const uint16_t l = bf16_hi(v - vh);
+      bhi[i] = __builtin_bit_cast(__bf16, h);
+      blo[i] = __builtin_bit_cast(__bf16, l);
+    }
+  }
+
+  float x[6], u[2], u0[2];
+#pragma unroll
+  for (int j = 0; j < 6; ++j) x[j] = x_t[j];
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    u0[j] = valid ? cand_value(gp, md, cand, u_user, c, 0, j) : 0.0f;
+    u[j] = u0[j];
+  }
+  Stepper<MPMI_BASIS_RACE_CAR> stp;  // folded per-lane coefficients (FP32)
+  stp.set_input(md, sK, u);
+  bool alive = valid, near = false;
+  int fv = H + 1;
+  const int S = gp.n_seg;
+  int gcur = 0;
+  for (int s = 1; s <= H; ++s) {
+    if (!__any(alive)) break;  // wave-uniform
+    const int g = ((s - 1) * S) / H;
+    if (g != gcur) {
+      gcur = g;
+#pragma unroll
+      for (int j = 0; j < 2; ++j) u[j] = valid ? cand_value(gp, md, cand, u_user, c, g, j) : 0.0f;
+      stp.set_input(md, sK, u);
+    }
+    float sp, cp;
+    sincosf(x[2], &sp, &cp);
+    // Per-step shared-coefficient features, split into BF16 hi/lo, to LDS.
+    float q[32];
+    {
+      int f = 0;
+#pragma unroll
+      for (int k = 0; k < 6; ++k)
+#pragma unroll
+        for (int l = k; l < 6; ++l) q[f++] = x[k] * x[l];
+      q[21] = sp * x[3]; q[22] = sp * x[4]; q[23] = sp * x[5];
+      q[24] = cp * x[3]; q[25] = cp * x[4]; q[26] = cp * x[5];
+#pragma unroll
+      for (int k = 27; k < 32; ++k) q[k] = 0.0f;
+    }
+#pragma unroll
+    for (int k8 = 0; k8 < 4; ++k8) {
+      bf16x8_t h8, l8;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const float v = q[k8 * 8 + i];
+        const uint16_t h = bf16_hi(v);
+        const float vh = __uint_as_float((uint32_t)h << 16);
+        h8[i] = __builtin_bit_cast(__bf16, h);
+        l8[i] = __builtin_bit_cast(__bf16, bf16_hi(v - vh));
+      }
+      *reinterpret_cast<bf16x8_t*>(&sA[wave][0][lane][k8 * 8]) = h8;
+      *reinterpret_cast<bf16x8_t*>(&sA[wave][1][lane][k8 * 8]) = l8;
+    }
+    __builtin_amdgcn_wave_barrier();
+    // Four groups of 16 candidates: D = Ahi Bhi + Ahi Blo + Alo Bhi.
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) {
+      const int row = rb * 16 + (lane & 15), k0 = (lane >> 4) * 8;
+      const bf16x8_t ah = *reinterpret_cast<const bf16x8_t*>(&sA[wave][0][row][k0]);
+      const bf16x8_t al = *reinterpret_cast<const bf16x8_t*>(&sA[wave][1][row][k0]);
+      f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bhi, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, blo, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bhi, acc, 0, 0, 0);
+      const int col = lane & 15;
+      if (col < 6) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) sD[wave][rb * 16 + (lane >> 4) * 4 + r][col] = acc[r];
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+    float y[6];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      float v = fmaf(stp.Tc[j], cp, fmaf(stp.Ts[j], sp, stp.cu[j]));
+#pragma unroll
+      for (int k = 0; k < 6; ++k) v = fmaf(stp.L[k][j], x[k], v);
+      y[j] = v + sD[wave][lane][j];
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (alive) {
+#pragma unroll
+      for (int j = 0; j < 6; ++j) x[j] = y[j];
+      near |= near_boundary(md, x);
+      if (!(min_margin<6>(md, x) > 0.0f)) {
+        fv = s;
+        alive = false;
+      }
+    }
+  }
+  // Near-boundary candidates go to the FP32 recheck; the rest publish now.
+  bool listed = false;
+  if (valid && near) {
+    const unsigned int at = atomicAdd(&rl->count, 1u);
+    if ((int)at < capacity) {
+      rl->idx[at] = c;
+      listed = true;
+    }
+  }
+  if (valid && !listed && fv_out) fv_out[c] = (int16_t)fv;
+  const bool pub = valid && !listed;
+  const float cst = pub ? cost_of<2>(md, u0, u_user) : 0.0f;
+  const bool safe = pub && fv == H + 1;
+  const unsigned long long ks = safe ? safe_key(cst, c) : kKeyNone;
+  const unsigned long long kf = (pub && !safe) ? fallback_key(fv, cst, c) : kKeyNone;
+  // Publish without completing the slot (the recheck launch finalises).
+  __shared__ unsigned long long s_ks[kWaves], s_kf[kWaves];
+  __shared__ unsigned int s_cnt[kWaves], s_re[kWaves];
+  const unsigned long long wks = wave_min_u64(ks), wkf = wave_min_u64(kf);
+  const unsigned int wcnt = (unsigned int)__popcll(__ballot(safe && c > 0));
+  const unsigned int wre = (unsigned int)__popcll(__ballot(listed));
+  if (lane == 0) {
+    s_ks[wave] = wks;
+    s_kf[wave] = wkf;
+    s_cnt[wave] = wcnt;
+    s_re[wave] = wre;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long bks = kKeyNone, bkf = kKeyNone;
+    unsigned int bcnt = 0, bre = 0;
+    for (int w = 0; w < kWaves; ++w) {
+      bks = s_ks[w] < bks ? s_ks[w] : bks;
+      bkf = s_kf[w] < bkf ? s_kf[w] : bkf;
+      bcnt += s_cnt[w];
+      bre += s_re[w];
+    }
+    if (bks != kKeyNone) atomicMin(&slot->key_safe, bks);
+    if (bkf != kKeyNone) atomicMin(&slot->key_fb, bkf);
+    if (bcnt) atomicAdd(&slot->n_safe, bcnt);
+    if (bre) atomicAdd(&slot->n_recheck, bre);
+  }
+}
+
+// FP32 re-roll of the listed candidates, then the selection.  Every workgroup
+// publishes (possibly empty keys) so the last one can finalise.
+__global__ void __launch_bounds__(256)
+recheck_race_car_kernel(const ModelDev* __restrict__ md, GenParams gp, int H, const float* __restrict__ x_t,
+                        const float* __restrict__ u_user, const float* __restrict__ cand,
+                        Slot* __restrict__ slot, mpmi_selection* __restrict__ out,
+                        int16_t* __restrict__ fv_out, RecheckList* __restrict__ rl, int capacity) {
+  __shared__ float4 sK[kLdsKFloat4];
+  stage_K<MPMI_BASIS_RACE_CAR>(md, sK);
+  const unsigned int cnt_raw = rl->count;
+  const int count = (int)(cnt_raw < (unsigned int)capacity ? cnt_raw : (unsigned int)capacity);
+  unsigned long long ks = kKeyNone, kf = kKeyNone;
+  unsigned int n_safe_local = 0;
+  const int stride = gridDim.x * blockDim.x;
+  for (int e0 = blockIdx.x * blockDim.x; e0 < count; e0 += stride) {
+    const int e = e0 + threadIdx.x;
+    const int c = e < count ? rl->idx[e] : gp.n_cand + 1;  // past the end: an invalid lane
+    const CandResult r = evaluate_candidate<MPMI_BASIS_RACE_CAR>(md, sK, gp, H, x_t, u_user, cand, c, fv_out,
+                                                                 nullptr);
+    ks = r.ks < ks ? r.ks : ks;
+    kf = r.kf < kf ? r.kf : kf;
+    n_safe_local += r.safe_counted ? 1u : 0u;
+  }
+  // A lane may have served several listed candidates: add its safe count to
+  // the slot directly (reduce_and_publish counts one flag per lane).
+  unsigned int wsum = n_safe_local;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) wsum += __shfl_xor(wsum, off, 64);
+  if ((threadIdx.x & 63) == 0 && wsum) atomicAdd(&slot->n_safe, wsum);
+  if (reduce_and_publish(ks, kf, false, slot, gridDim.x) && threadIdx.x == 0) {
+    finalize<2>(md, gp, cand, u_user, H, slot, out);
+    rl->count = 0u;
+    __threadfence();
+  }
+}
+
+size_t recheck_bytes(int capacity) { return sizeof(RecheckList) + sizeof(int) * (size_t)capacity; }
+
+hipError_t launch_tick_bf16(const void* model, const mpmi_tick_desc& d, const float* x_t, const float* u_user,
+                            const float* cand, void* slot, mpmi_selection* out, int16_t* fv, void* recheck,
+                            int capacity, int recheck_grid, hipStream_t st) {
+  GenParams gp;
+  gp.seed = d.seed;
+  gp.tick = d.tick;
+  gp.loop = d.loop;
+  gp.gen = d.gen;
+  gp.n_cand = d.n_cand;
+  gp.n_seg = d.n_seg;
+  for (int j = 0; j < MPMI_MAX_INPUT; ++j) gp.grid[j] = d.grid[j] > 0 ? d.grid[j] : 1;
+  const unsigned grid = (unsigned)(((long long)d.n_cand + 1 + 255) / 256);
+  tick_bf16_race_car_kernel<<<grid, 256, 0, st>>>((const ModelDev*)model, gp, d.horizon, x_t, u_user, cand,
+                                                    (Slot*)slot, fv, (RecheckList*)recheck, capacity);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  recheck_race_car_kernel<<<recheck_grid, 256, 0, st>>>((const ModelDev*)model, gp, d.horizon, x_t, u_user, cand,
+                                                          (Slot*)slot, out, fv, (RecheckList*)recheck, capacity);
+  return hipGetLastError();
+}
+
+}  // namespace mpmi

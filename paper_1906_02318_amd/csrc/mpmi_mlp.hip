@@ -214,12 +214,12 @@ __global__ void colsum_kernel(const float* __restrict__ dZ, int M, int N, float*
 // refreshing the BF16 copy used by the products.
 __global__ void adam_kernel(float* __restrict__ w, uint16_t* __restrict__ w16, float* __restrict__ mom,
                             float* __restrict__ vel, const float* __restrict__ grad, int n, float lr, float b1,
-                            float b2, float eps, float c1, float c2) {
+                            float b2, float omb1, float omb2, float eps, float c1, float c2) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const float g = grad[i];
-  const float m = b1 * mom[i] + (1.0f - b1) * g;
-  const float v = b2 * vel[i] + (1.0f - b2) * g * g;
+  const float m = b1 * mom[i] + omb1 * g;
+  const float v = b2 * vel[i] + omb2 * g * g;
   mom[i] = m;
   vel[i] = v;
   const float wi = w[i] - lr * (m / c1) / (sqrtf(v / c2) + eps);
@@ -401,9 +401,12 @@ hipError_t launch_mlp_grad(const uint16_t* w16, const float* w32, const float* m
 
 hipError_t launch_mlp_adam(float* w32, uint16_t* w16, float* m, float* v, const float* grad, int step, float lr,
                            hipStream_t st) {
-  const float b1 = 0.9f, b2 = 0.999f;
-  const float c1 = (float)(1.0 - pow(0.9, step)), c2 = (float)(1.0 - pow(0.999, step));
-  adam_kernel<<<(kMlpParams + 255) / 256, 256, 0, st>>>(w32, w16, m, v, grad, kMlpParams, lr, b1, b2, 1e-8f, c1, c2);
+  // Constants and their complements rounded once from FP64 (1 - 0.999f in
+  // FP32 would carry a 1e-5 relative error into the second moment).
+  const double b1 = 0.9, b2 = 0.999;
+  const float c1 = (float)(1.0 - pow(b1, step)), c2 = (float)(1.0 - pow(b2, step));
+  adam_kernel<<<(kMlpParams + 255) / 256, 256, 0, st>>>(w32, w16, m, v, grad, kMlpParams, lr, (float)b1, (float)b2,
+                                                        (float)(1.0 - b1), (float)(1.0 - b2), 1e-8f, c1, c2);
   return hipGetLastError();
 }
 

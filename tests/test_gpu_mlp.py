@@ -130,7 +130,8 @@ def test_mdn_sample_parity(ctx):
     P = 4096
     cand = mpmi.mdn_sample(ctx, model, torch.tensor(head, device="cuda"), P, seed=5, tick=6, loop=7).cpu().numpy()
     ref, _ = M.sample(head.astype(np.float64), P, 5, 6, 7, so.u_lo, so.u_hi)
-    np.testing.assert_allclose(cand[0].T, ref, rtol=0, atol=2e-5 * np.array([0.8, 6.0]))
+    for j, span in enumerate((0.8, 6.0)):
+        np.testing.assert_allclose(cand[0, j], ref[:, j], rtol=0, atol=2e-5 * span)
 
 
 def test_proposal_tick_and_fallback(ctx):
@@ -170,15 +171,36 @@ def test_proposal_tick_and_fallback(ctx):
             assert plain == sel
         log(f"[proposal] tick {t}: n_cand={sel['n_cand']} idx={sel['idx']} status={sel['status']} "
             f"n_safe={sel['n_safe']}")
-    # A head with all mass on an unsafe corner forces the fallback.
+    # A constant network whose head puts every proposal on one input corner:
+    # find a tick where that corner and the user's own input are both unsafe,
+    # so the gated exhaustive fallback must decide, exactly as a plain tick.
     bad = np.zeros((16, 5), np.float32)
-    bad[:, 0] = 0.0
-    bad[:, 1] = 1.0
-    bad[:, 2] = 1.0
+    bad[:, 1] = 2.0   # normalised means beyond the box: clipping puts every draw on the corner
+    bad[:, 2] = 2.0
     bad[:, 3:5] = -7.0
-    out = torch.empty(mpmi.SELECTION_BYTES, dtype=torch.uint8, device="cuda")
-    # drive the sampler directly with the degenerate head, then the gated fallback through a tick
+    const = np.zeros(M.param_count())
+    const[-80:] = bad.ravel()
+    cnet = net_tensors(const, np.zeros(8), np.ones(8))
     c = mpmi.mdn_sample(ctx, model, torch.tensor(bad.ravel(), device="cuda"), P, seed=1)
-    assert torch.allclose(c[0, 0], torch.full((P,), 0.4, device="cuda")) and torch.allclose(
-        c[0, 1], torch.full((P,), 3.0, device="cuda"))
-    del out
+    assert torch.all(c[0, 0] == 0.4) and torch.all(c[0, 1] == 3.0)
+    corner = torch.tensor([[[0.4], [3.0]]], dtype=torch.float32, device="cuda")
+    xs2 = synth.race_car_states(200, W.rc_track(), seed=77)
+    uh2 = synth.uniform_user(200, synth.RC_U_LO, synth.RC_U_HI, seed=78)
+    fb = mpmi.tick_desc(128 * 128, 60, gen=mpmi.GEN_GRID, grid=[128, 128], loop=2)
+    tried = 0
+    for t in range(200):
+        xt = torch.tensor(W.f32(xs2[t]), dtype=torch.float32, device="cuda")
+        ut = torch.tensor(W.f32(uh2[t]), dtype=torch.float32, device="cuda")
+        one = mpmi.decode_selection(mpmi.mpmi_tick(ctx, model, mpmi.tick_desc(1, 60, gen=mpmi.GEN_EXPLICIT, loop=3),
+                                                   xt, ut, cand=corner.reshape(-1)))
+        if one["status"] == mpmi.OK:
+            continue  # the user's input or the corner is safe: no fallback here
+        tried += 1
+        prop = mpmi.tick_desc(P, 60, gen=mpmi.GEN_EXPLICIT, seed=8, tick=t, loop=1)
+        sel = mpmi.decode_selection(mpmi.mpmi_proposal_tick(ctx, model, cnet, xt, ut, prop, fb, cand_work, work))
+        plain = mpmi.decode_selection(mpmi.mpmi_tick(ctx, model, fb, xt, ut))
+        assert sel["n_cand"] == 128 * 128 + 1 and sel == plain
+        if tried >= 3:
+            break
+    log(f"[proposal] fallback exercised on {tried} ticks")
+    assert tried >= 1

@@ -380,3 +380,57 @@ def test_invalid_arguments_rejected(ctx, bb):
     s.n_state = 5
     with pytest.raises(mpmi.MpmiError):
         mpmi.mpmi_model_pack(ctx, s, dev(np.zeros((21, 4)), torch.float64))
+
+
+def test_closed_loop_balance_bot_decisions_replayed(ctx, bb):
+    """Closed loop at real-time size (N = 10,240 five-segment sequences, H = 50):
+    the plant advances with the applied input, the user input is an AR(1) walk;
+    every GPU decision is replayed by the oracle on the visited (x_t, u_h)."""
+    so, model, K = bb
+    T = 40
+    x = synth.balance_bot_states(1, seed=3)[0]
+    user = synth.AR1User([-5.0], [5.0], rho=0.95, sigma=1.0, seed=2)
+    kinds = {}
+    for t in range(T):
+        u = W.f32(user.next())
+        xt = W.f32(x)
+        desc = mpmi.tick_desc(10240, 50, gen=mpmi.GEN_UNIFORM, n_seg=5, seed=4, tick=t)
+        fv = torch.empty(10241, dtype=torch.int16, device="cuda")
+        sel = mpmi.decode_selection(mpmi.mpmi_tick(ctx, model, desc, dev(xt, torch.float32), dev(u, torch.float32),
+                                                   first_violation=fv))
+        cand = o.with_user(o.uniform_candidates(so, 10240, 5, 4, t, 0), u, 5)
+        res = check_tick(so, K, xt, u, cand, 50, sel, fv.cpu().numpy(), EPS_BB, label=f"closed loop tick {t}")
+        kinds[res["kind"]] = kinds.get(res["kind"], 0) + 1
+        x = synth.cartpole_step(x, np.array([sel["u_r"][0]], np.float64))[0]
+        if abs(x[2]) > 0.5 or abs(x[0]) > 2.0:
+            x = synth.balance_bot_states(1, seed=100 + t)[0]
+    log(f"[closed loop] {kinds}")
+    assert kinds.get("identical", 0) + kinds.get("equal_cost", 0) >= T - 1
+
+
+def test_tick_race_car_bf16x3_with_fp32_recheck(ctx, rc):
+    """Race car, N = 16,384 grid, H = 60, shared-coefficient contraction on BF16
+    matrix cores (hi/lo split) and FP32 recheck of candidates within 0.02 of a
+    constraint: final verdicts and selections against the FP64 oracle."""
+    so, model, K = rc
+    T = 6
+    xs = synth.race_car_states(T, W.rc_track(), seed=1)
+    uhs = synth.uniform_user(T, synth.RC_U_LO, synth.RC_U_HI, seed=2)
+    grid = o.grid_candidates(so, [128, 128])
+    kinds, rechecks = {}, []
+    for t in range(T):
+        x, u = W.f32(xs[t]), W.f32(uhs[t])
+        desc = mpmi.tick_desc(128 * 128, 60, gen=mpmi.GEN_GRID, grid=[128, 128], precision=mpmi.PREC_BF16X3)
+        fv = torch.empty(128 * 128 + 1, dtype=torch.int16, device="cuda")
+        recs = []
+        for _ in range(2):
+            recs.append(mpmi.mpmi_tick(ctx, model, desc, dev(x, torch.float32), dev(u, torch.float32),
+                                       first_violation=fv).cpu().numpy().tobytes())
+        assert recs[0] == recs[1], "BF16X3 tick is not deterministic"
+        sel = mpmi.decode_selection(torch.tensor(np.frombuffer(recs[0], np.uint8)))
+        res = check_tick(so, K, x, u, o.with_user(grid, u, 1), 60, sel, fv.cpu().numpy(), EPS_RC,
+                         label=f"bf16x3 tick {t}")
+        kinds[res["kind"]] = kinds.get(res["kind"], 0) + 1
+        rechecks.append(sel["n_recheck"])
+    log(f"[tick] rc bf16x3: {kinds}, rechecked per tick {rechecks}")
+    assert kinds.get("identical", 0) + kinds.get("equal_cost", 0) + kinds.get("eps_band", 0) == T
