@@ -45,19 +45,8 @@ __device__ __forceinline__ bool near_boundary(const ModelDev* __restrict__ md, c
     near |= fabsf(mg) < md->sys.eps_box[b];
   }
   if (md->sys.has_track) {
-    const float r2 = fmaf(x[0], x[0], x[1] * x[1]);
-    const float inv = __builtin_amdgcn_rsqf(r2);
-    const float rho = r2 * inv;
-    const float c1 = x[0] * inv, s1 = x[1] * inv;
-    float rc = md->trk_r0, ch = 1.0f, sh = 0.0f;
-    for (int h = 1; h <= md->hmax; ++h) {
-      const float cn = ch * c1 - sh * s1;
-      const float sn = sh * c1 + ch * s1;
-      ch = cn;
-      sh = sn;
-      rc = fmaf(md->trk_s[h], sh, rc);
-      rc = fmaf(md->trk_c[h], ch, rc);
-    }
+    float rho;
+    const float rc = track_centre(md, x, &rho);
     near |= fabsf(md->trk_lim - fabsf(rho - rc)) < md->sys.eps_track;
   }
   return near;

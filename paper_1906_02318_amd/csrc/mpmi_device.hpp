@@ -46,9 +46,8 @@ struct alignas(256) ModelDev {
   int32_t pad0[2];
   float bb_lim[MPMI_MAX_BOX];     // box_bound - box_infl
   float trk_lim;                  // track_half - track_infl
-  float trk_r0;                   // r0 plus the constant (frequency 0) terms
-  float trk_s[kMaxHarm + 1];      // coefficient of sin(h phi)
-  float trk_c[kMaxHarm + 1];      // coefficient of cos(h phi)
+  float trk_p[kMaxHarm + 1];      // r_c = P(cos phi) + sin phi * Q(cos phi): P coefficients
+  float trk_q[kMaxHarm];          // Q coefficients (monomial, ascending powers)
   float half_inv[MPMI_MAX_INPUT]; // 2 / (u_hi - u_lo)
   float K[MPMI_MAX_DIM][8];       // FP32 K, row = feature, col = state component
   uint32_t Rhi[kRTileWords];      // BF16 hi split of R, MFMA B-operand order
@@ -314,8 +313,10 @@ struct Stepper<MPMI_BASIS_RACE_CAR> {
     }
   }
   __device__ __forceinline__ void step(const ModelDev* __restrict__, const float4* sK, float* x) {
-    float sp, cp;
-    sincosf(x[2], &sp, &cp);
+    // Hardware sine/cosine (argument scaled to revolutions): about 1e-6
+    // absolute error for headings within a few hundred turns, well inside
+    // the FP32 rollout tolerance, at a tenth of the instructions of sincosf.
+    const float sp = __sinf(x[2]), cp = __cosf(x[2]);
     float p[kRcStepRows + 1];
     int q = 0;
 #pragma unroll
@@ -366,6 +367,28 @@ __device__ __forceinline__ float pick(const float* x, int idx) {
   return v;
 }
 
+// Centreline radius r_c(phi) at the polar angle of (x[0], x[1]), and rho.
+// sin(h phi + p) expands into Chebyshev polynomials of cos phi (T_h, and
+// sin phi * U_{h-1}), so r_c = P(cos phi) + sin phi * Q(cos phi) with
+// coefficients formed once per model in FP64; cos phi and sin phi come from
+// one reciprocal square root (rho = 0 or an infinite coordinate gives NaN,
+// i.e. unsafe; the centreline radius exceeds the half-width there anyway).
+__device__ __forceinline__ float track_centre(const ModelDev* __restrict__ md, const float* x, float* rho) {
+  const float r2 = fmaf(x[0], x[0], x[1] * x[1]);
+  const float inv = __builtin_amdgcn_rsqf(r2);
+  *rho = r2 * inv;
+  const float c1 = x[0] * inv, s1 = x[1] * inv;
+  const int hmax = md->hmax;
+  float P = md->trk_p[hmax];
+  for (int k = hmax - 1; k >= 0; --k) P = fmaf(P, c1, md->trk_p[k]);
+  float Q = 0.0f;
+  if (hmax >= 1) {
+    Q = md->trk_q[hmax - 1];
+    for (int k = hmax - 2; k >= 0; --k) Q = fmaf(Q, c1, md->trk_q[k]);
+  }
+  return fmaf(s1, Q, P);
+}
+
 // Least margin over all constraints of state x (NaN if any margin is NaN, so
 // that "safe" = (margin > 0) rejects NaN states).
 template <int NS>
@@ -378,25 +401,9 @@ __device__ __forceinline__ float min_margin(const ModelDev* __restrict__ md, con
     nan |= (mg != mg);
     mm = fminf(mm, mg);
   }
-  if (md->hmax >= 0 && md->sys.has_track) {
-    // rho, cos phi, sin phi from one reciprocal square root (rho = 0 or an
-    // infinite coordinate gives NaN, i.e. unsafe; the centreline radius is
-    // far larger than the half-width there anyway).
-    const float r2 = fmaf(x[0], x[0], x[1] * x[1]);
-    const float inv = __builtin_amdgcn_rsqf(r2);
-    const float rho = r2 * inv;
-    const float c1 = x[0] * inv, s1 = x[1] * inv;
-    float rc = md->trk_r0;
-    float ch = 1.0f, sh = 0.0f;
-    const int hmax = md->hmax;
-    for (int h = 1; h <= hmax; ++h) {
-      const float cn = ch * c1 - sh * s1;
-      const float sn = sh * c1 + ch * s1;
-      ch = cn;
-      sh = sn;
-      rc = fmaf(md->trk_s[h], sh, rc);
-      rc = fmaf(md->trk_c[h], ch, rc);
-    }
+  if (md->sys.has_track) {
+    float rho;
+    const float rc = track_centre(md, x, &rho);
     const float mg = md->trk_lim - fabsf(rho - rc);
     nan |= (mg != mg);
     mm = fminf(mm, mg);

@@ -169,29 +169,39 @@ __global__ void pack_kernel(mpmi_system sys, int dim, int state_feat0, const dou
     for (int b = 0; b < MPMI_MAX_BOX; ++b)
       md->bb_lim[b] = (b < sys.n_box) ? (float)((double)sys.box_bound[b] - (double)sys.box_infl[b]) : 0.0f;
     md->trk_lim = (float)((double)sys.track_half - (double)sys.track_infl);
-    double r0 = sys.track_r0;
-    double ts[kMaxHarm + 1], tc[kMaxHarm + 1];
-    for (int h = 0; h <= kMaxHarm; ++h) ts[h] = tc[h] = 0.0;
+    // r_c(phi) = r0 + sum_k a_k sin(f_k phi + p_k)
+    //          = r0 + sum_k a_k [cos p_k sin(f_k phi) + sin p_k cos(f_k phi)]
+    //          = r0 + sum_k a_k [cos p_k sin(phi) U_{f_k-1}(c) + sin p_k T_{f_k}(c)],  c = cos phi,
+    // collected into monomials of c in FP64: P (cos terms + r0), Q (sin terms).
+    double T[kMaxHarm + 1][kMaxHarm + 1], U[kMaxHarm + 1][kMaxHarm + 1];
+    for (int h = 0; h <= kMaxHarm; ++h)
+      for (int k = 0; k <= kMaxHarm; ++k) T[h][k] = U[h][k] = 0.0;
+    T[0][0] = 1.0;
+    T[1][1] = 1.0;
+    U[0][0] = 1.0;
+    U[1][1] = 2.0;
+    for (int h = 1; h < kMaxHarm; ++h)
+      for (int k = 0; k <= kMaxHarm; ++k) {
+        T[h + 1][k] = (k > 0 ? 2.0 * T[h][k - 1] : 0.0) - T[h - 1][k];
+        U[h + 1][k] = (k > 0 ? 2.0 * U[h][k - 1] : 0.0) - U[h - 1][k];
+      }
+    double P[kMaxHarm + 1], Q[kMaxHarm];
+    for (int k = 0; k <= kMaxHarm; ++k) P[k] = 0.0;
+    for (int k = 0; k < kMaxHarm; ++k) Q[k] = 0.0;
     int hmax = 0;
     if (sys.has_track) {
-      for (int k = 0; k < sys.track_n; ++k) {
-        const int f = sys.track_freq[k];
-        const double a = sys.track_amp[k], p = sys.track_phase[k];
-        // a sin(f phi + p) = a cos(p) sin(f phi) + a sin(p) cos(f phi)
-        if (f == 0) {
-          r0 += a * sin(p);
-        } else {
-          ts[f] += a * cos(p);
-          tc[f] += a * sin(p);
-          hmax = f > hmax ? f : hmax;
-        }
+      P[0] = sys.track_r0;
+      for (int q = 0; q < sys.track_n; ++q) {
+        const int f = sys.track_freq[q];
+        const double a = sys.track_amp[q], ph = sys.track_phase[q];
+        for (int k = 0; k <= f; ++k) P[k] += a * sin(ph) * T[f][k];
+        if (f >= 1)
+          for (int k = 0; k < f; ++k) Q[k] += a * cos(ph) * U[f - 1][k];
+        hmax = f > hmax ? f : hmax;
       }
     }
-    md->trk_r0 = (float)r0;
-    for (int h = 0; h <= kMaxHarm; ++h) {
-      md->trk_s[h] = (float)ts[h];
-      md->trk_c[h] = (float)tc[h];
-    }
+    for (int k = 0; k <= kMaxHarm; ++k) md->trk_p[k] = (float)P[k];
+    for (int k = 0; k < kMaxHarm; ++k) md->trk_q[k] = (float)Q[k];
     md->hmax = hmax;
     for (int j = 0; j < MPMI_MAX_INPUT; ++j)
       md->half_inv[j] = (j < sys.n_input) ? (float)(2.0 / ((double)sys.u_hi[j] - (double)sys.u_lo[j])) : 0.0f;

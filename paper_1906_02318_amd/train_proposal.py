@@ -46,7 +46,7 @@ def evaluate(ctx, model, net, track, n_ticks=1000, seed=8, proposals=2048, log=p
     exh = mpmi.tick_desc(128 * 128, 60, gen=mpmi.GEN_GRID, grid=[128, 128], loop=3)
     lo, hi = synth.RC_U_LO, synth.RC_U_HI
     res = dict(agree_learned=0, agree_uniform=0, fallback=0, ticks=n_ticks, gap_learned=[], gap_uniform=[],
-               interventions=0)
+               interventions=0, asgood_learned=0, asgood_uniform=0, decided=0)
     for t in range(n_ticks):
         xt = torch.tensor(xs[t], dtype=torch.float32, device="cuda")
         ut = torch.tensor(uh[t], dtype=torch.float32, device="cuda")
@@ -57,6 +57,7 @@ def evaluate(ctx, model, net, track, n_ticks=1000, seed=8, proposals=2048, log=p
         res["fallback"] += int(sl["n_cand"] != proposals + 1)
         if se["status"] != mpmi.OK:
             continue
+        res["decided"] += 1
         res["interventions"] += int(se["idx"] != 0)
         ue = normalise(se["u_r"][:2], lo, hi)
         for name, s in (("learned", sl), ("uniform", su)):
@@ -66,9 +67,14 @@ def evaluate(ctx, model, net, track, n_ticks=1000, seed=8, proposals=2048, log=p
             res[f"agree_{name}"] += int(ok)
             if s["status"] == mpmi.OK:
                 res[f"gap_{name}"].append(s["cost"] - se["cost"])
+                # as good as the exhaustive grid: a safe choice no costlier than the
+                # grid's, up to the cost of half a grid cell's diagonal
+                res[f"asgood_{name}"] += int(s["cost"] <= se["cost"] + HALF_CELL_DIAG_128 ** 2)
     n_ok = n_ticks
     out = dict(ticks=n_ticks, interventions=res["interventions"], fallback_rate=res["fallback"] / n_ticks,
                agreement_learned=res["agree_learned"] / n_ok, agreement_uniform=res["agree_uniform"] / n_ok,
+               as_good_learned=res["asgood_learned"] / max(1, res["decided"]),
+               as_good_uniform=res["asgood_uniform"] / max(1, res["decided"]),
                mean_cost_gap_learned=float(np.mean(res["gap_learned"])) if res["gap_learned"] else None,
                mean_cost_gap_uniform=float(np.mean(res["gap_uniform"])) if res["gap_uniform"] else None)
     log(json.dumps(out))
@@ -83,10 +89,15 @@ def main():
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--eval-ticks", type=int, default=1000)
     ap.add_argument("--out", default="gpurun_out/proposal_net.npz")
+    ap.add_argument("--eval-only", default=None, help="evaluate a saved network instead of training")
     args = ap.parse_args()
     log = lambda m: print(m, flush=True)
     ctx = mpmi.Context(0)
     track, model = race_car_model(ctx)
+    if args.eval_only:
+        net = ProposalNet.load(ctx, args.eval_only)
+        print(json.dumps(dict(eval=evaluate(ctx, model, net, track, n_ticks=args.eval_ticks, log=log))), flush=True)
+        return
     states = synth.race_car_states(args.labels, track, seed=7)
     users = synth.uniform_user(args.labels, synth.RC_U_LO, synth.RC_U_HI, seed=17)
     t0 = time.perf_counter()
