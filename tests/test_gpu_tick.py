@@ -434,3 +434,47 @@ def test_tick_race_car_bf16x3_with_fp32_recheck(ctx, rc):
         rechecks.append(sel["n_recheck"])
     log(f"[tick] rc bf16x3: {kinds}, rechecked per tick {rechecks}")
     assert kinds.get("identical", 0) + kinds.get("equal_cost", 0) + kinds.get("eps_band", 0) == T
+
+
+def test_full_size_race_car_sampled_parity_and_properties(ctx, rc):
+    """Bench configuration (race car, 1024 x 1024 grid + u_h, H = 60, default
+    launch shape): first violations of ~3,000 sampled candidates (plus the
+    chosen one) against the oracle; the choice is oracle-safe and no sampled
+    oracle-safe candidate is cheaper; properties at full size: the mask is
+    monotone under inflation and a safe user input passes unchanged."""
+    so, model, K = rc
+    N = 1024 * 1024
+    H = 60
+    rng = np.random.default_rng(21)
+    xs = synth.race_car_states(3, W.rc_track(), seed=1)
+    uhs = synth.uniform_user(3, synth.RC_U_LO, synth.RC_U_HI, seed=2)
+    grid = o.grid_candidates(so, [1024, 1024])
+    desc = mpmi.tick_desc(N, H, gen=mpmi.GEN_GRID, grid=[1024, 1024])
+    model_infl = mpmi.mpmi_model_pack(ctx, mpmi.race_car_system(W.track_dict(W.rc_track(), infl=0.3), infl=0.3),
+                                      dev(K, torch.float64))
+    for t in range(3):
+        x, u = W.f32(xs[t]), W.f32(uhs[t])
+        fv = torch.empty(N + 1, dtype=torch.int16, device="cuda")
+        sel = mpmi.decode_selection(mpmi.mpmi_tick(ctx, model, desc, dev(x, torch.float32), dev(u, torch.float32),
+                                                   first_violation=fv))
+        fvg = fv.cpu().numpy().astype(np.int64)
+        idx = np.unique(np.concatenate([[0, sel["idx"]], rng.integers(1, N + 1, size=3000)]))
+        cand = o.with_user(grid, u, 1)[idx]
+        traj, fvo = o.rollout(so, K, x, cand, H, early_exit=False)
+        from tests.parity import ambiguous
+        amb = ambiguous(so, traj, fvo, fvg[idx], EPS_RC)
+        assert np.all((fvo == fvg[idx]) | amb), f"tick {t}: sampled first violations differ"
+        cost = o.cost(so, cand, u)
+        j = int(np.nonzero(idx == sel["idx"])[0][0])
+        if sel["status"] == mpmi.OK:
+            assert fvo[j] == H + 1 or amb[j]
+            cheaper = (fvo == H + 1) & ~amb & (cost < cost[j] * (1 - 1e-6) - 1e-12)
+            assert not cheaper.any(), f"tick {t}: a sampled safe candidate is cheaper than the choice"
+        if fvo[0] == H + 1 and not amb[0]:
+            assert sel["idx"] == 0 and sel["deviation"] == 0.0
+        # monotone under inflation (same candidates, tighter set)
+        fv2 = torch.empty(N + 1, dtype=torch.int16, device="cuda")
+        mpmi.mpmi_tick(ctx, model_infl, desc, dev(x, torch.float32), dev(u, torch.float32), first_violation=fv2)
+        assert np.all(fv2.cpu().numpy() <= fvg), f"tick {t}: mask not monotone under inflation"
+        log(f"[full size] tick {t}: idx={sel['idx']} status={sel['status']} n_safe={sel['n_safe']} "
+            f"sampled={idx.size} ambiguous={int(amb.sum())}")
