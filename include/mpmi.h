@@ -27,7 +27,13 @@
  *    mpmi_selection.status (device memory), because the host has returned
  *    before the kernels run.
  *  - One context may be used by one host thread at a time.  Calls on one
- *    context that share a `loop` slot must be ordered on one stream.
+ *    context that share a `loop` slot must be ordered on one stream, and so
+ *    must all BF16X3 ticks of a context (they share its recheck list).
+ *  - Set-up calls (mpmi_create, mpmi_model_pack, koopman_fit,
+ *    mpmi_multi_create / _set_config / _autotune / _graph) may allocate or
+ *    synchronise and are not meant for stream capture; tick calls allocate
+ *    nothing and do not synchronise.
+ *  - A model pointer is valid only on the context that packed it.
  */
 #ifndef MPMI_H
 #define MPMI_H
