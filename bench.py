@@ -449,6 +449,34 @@ def main():
             "flops_per_unit": FLOPS_PER_UNIT[wl["system"]],
         },
     }
+    if not args.no_extras and args.workload == "race_car_1m":
+        # Same ticks with the shared-coefficient contraction on BF16 matrix cores
+        # (hi/lo split) and the FP32 recheck of near-boundary candidates.
+        bdescs = [st["mk"](t) for t in range(n_inputs)]
+        for d in bdescs:
+            d.precision = mpmi.PREC_BF16X3
+        for i in range(5):
+            mpmi.mpmi_tick(ctx, model, bdescs[i % n_inputs], st["x"][i % n_inputs], st["u"][i % n_inputs],
+                           out=outs[i % n_inputs], stream=stream)
+        torch.cuda.synchronize()
+        nb = min(args.steps, 100)
+        evb = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(nb)]
+        t0b = time.perf_counter()
+        for i in range(nb):
+            t = i % n_inputs
+            evb[i][0].record(stream)
+            mpmi.mpmi_tick(ctx, model, bdescs[t], st["x"][t], st["u"][t], out=outs[t], stream=stream)
+            evb[i][1].record(stream)
+        torch.cuda.synchronize()
+        wb = time.perf_counter() - t0b
+        msb = np.array([a.elapsed_time(b) for a, b in evb])
+        sb = mpmi.decode_selection(outs)
+        out["race_car_1m_bf16x3"] = {
+            "trajectories_per_s": Nc * nb / wb, "p50_tick_ms": float(np.percentile(msb, 50)),
+            "p99_tick_ms": float(np.percentile(msb, 99)),
+            "rechecked_per_tick": float(np.mean([s_["n_recheck"] for s_ in sb])),
+            "note": "27 shared-coefficient features on v_mfma_f32_16x16x32_bf16 (hi/lo split), FP32 recheck "
+                    "of candidates within 0.02 of a constraint; two launches per tick"}
     if args.copy_bytes > 0:
         src = torch.empty(args.copy_bytes, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)
