@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define MPMI_ABI_VERSION 1
+#define MPMI_ABI_VERSION 2
 
 /* Size limits (checked on the host). */
 #define MPMI_MAX_STATE 8      /* n */
@@ -112,7 +112,14 @@ enum { MPMI_GEN_EXPLICIT = 0, MPMI_GEN_GRID = 1, MPMI_GEN_UNIFORM = 2 };
  *             polar coordinates of (x[0], x[1]) and
  *             r_c(phi) = track_r0 + sum_k track_amp[k] sin(track_freq[k] phi + track_phase[k])
  * eps_box / eps_track: in BF16X3 mode, a candidate whose margin at some step
- * falls below eps is re-rolled in FP32.                                     */
+ * falls below eps is re-rolled in FP32.
+ * noise_sigma: process noise of the fused tick (Alg. 2 adds a Gaussian z_i to
+ * every predicted state): after step s, component j of candidate i's state
+ * gains noise_sigma[j] * z_j.  z comes in pairs (components 2q, 2q+1) from
+ * one 64-bit draw h = hash(seed, tick, loop, i, 65536 + 4 (s-1) + q) of the
+ * MPMI_GEN_UNIFORM generator: u1 = ((h >> 40) + 1) 2^-24, u2 = ((h >> 16) &
+ * 0xFFFFFF) 2^-24, z_2q = sqrt(-2 ln u1) cos(2 pi u2), z_2q+1 = sqrt(-2 ln u1)
+ * sin(2 pi u2).  All zero = a deterministic model.                          */
 typedef struct mpmi_system {
   int32_t basis;          /* MPMI_BASIS_* */
   int32_t n_state;        /* n (LINEAR: 1..8; fixed 4 / 6 for the others) */
@@ -133,6 +140,7 @@ typedef struct mpmi_system {
   float eps_track;
   float u_lo[4];          /* input box; cost divides input j by (u_hi-u_lo)/2 */
   float u_hi[4];
+  float noise_sigma[8];   /* per state component, >= 0 */
 } mpmi_system;
 
 /* Result of one tick (device memory, written by the library).

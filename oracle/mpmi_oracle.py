@@ -55,6 +55,8 @@ class System:
                 radial gap |rho - r_c(phi)| < half - infl, with rho, phi the
                 polar coordinates of (x[0], x[1])
     u_lo, u_hi  input box (FP32 numbers)
+    noise       per-component standard deviations of the process noise added
+                to every predicted state (Alg. 2's z_i), or None
     """
 
     kind: str
@@ -64,6 +66,7 @@ class System:
     track: Optional[dict] = None
     u_lo: np.ndarray = None
     u_hi: np.ndarray = None
+    noise: Optional[np.ndarray] = None
 
     def __post_init__(self):
         self.u_lo = np.asarray(np.float32(self.u_lo), np.float64).reshape(-1)
@@ -284,6 +287,30 @@ def with_user(cand: np.ndarray, u_h, S: int) -> np.ndarray:
     return np.concatenate([u0, cand], axis=0)
 
 
+NOISE_SLOT = 65536
+
+
+def process_noise(seed, tick, loop, idx, s: int, n: int) -> np.ndarray:
+    """Standard normals (len(idx), n) for step s of candidates idx.
+
+    Components 2q, 2q+1 come from one draw h = hash(seed, tick, loop, i,
+    65536 + 4 (s - 1) + q): u1 = ((h >> 40) + 1) 2^-24, u2 = ((h >> 16) &
+    0xFFFFFF) 2^-24, and the Box-Muller pair sqrt(-2 ln u1) (cos, sin)(2 pi u2).
+    """
+    idx = np.asarray(idx, np.uint64)
+    out = np.zeros((idx.size, n))
+    for q in range((n + 1) // 2):
+        h = hash_counter(np.uint64(seed), np.uint64(tick), np.uint64(loop), idx,
+                         np.uint64(NOISE_SLOT + 4 * (s - 1) + q))
+        u1 = ((h >> np.uint64(40)).astype(np.float64) + 1.0) * 2.0 ** -24
+        u2 = ((h >> np.uint64(16)) & np.uint64(0xFFFFFF)).astype(np.float64) * 2.0 ** -24
+        r = np.sqrt(-2.0 * np.log(u1))
+        out[:, 2 * q] = r * np.cos(2.0 * np.pi * u2)
+        if 2 * q + 1 < n:
+            out[:, 2 * q + 1] = r * np.sin(2.0 * np.pi * u2)
+    return out
+
+
 def segment_of_step(s: int, S: int, H: int) -> int:
     """Segment used at prediction step s (1..H): floor((s - 1) * S / H)."""
     return ((s - 1) * S) // H
@@ -292,13 +319,16 @@ def segment_of_step(s: int, S: int, H: int) -> int:
 # ----------------------------------------------------------------------------
 # Prediction with early exit (Alg. 2 inner loop)
 # ----------------------------------------------------------------------------
-def rollout(sys: System, K: np.ndarray, x0, cand: np.ndarray, H: int, early_exit: bool = True):
+def rollout(sys: System, K: np.ndarray, x0, cand: np.ndarray, H: int, early_exit: bool = True,
+            noise_key=None, index=None):
     """Roll every candidate forward H steps from x0.
 
     cand: (Nc, S, m).  Returns (traj, fv): traj (H, Nc, n) with NaN where a
     rollout had already stopped, and fv (Nc,) the first step (1..H) whose
     predicted state is unsafe, or H + 1 if every state was safe.  With
-    early_exit=False every step is predicted (fv is unchanged).
+    early_exit=False every step is predicted (fv is unchanged).  If the system
+    has process noise, noise_key = (seed, tick, loop) and index (candidate
+    numbers of the rows, default 0..Nc-1) select the draws.
     """
     cand = np.asarray(cand, np.float64)
     Nc, S, _ = cand.shape
@@ -314,6 +344,10 @@ def rollout(sys: System, K: np.ndarray, x0, cand: np.ndarray, H: int, early_exit
             break
         with np.errstate(over="ignore", invalid="ignore"):
             x[idx] = predict(sys.kind, K, x[idx], cand[idx, g, :])
+            if sys.noise is not None and np.any(np.asarray(sys.noise) > 0):
+                rows = np.arange(Nc) if index is None else np.asarray(index)
+                z = process_noise(*noise_key, rows[idx], s, sys.n)
+                x[idx] = x[idx] + np.asarray(sys.noise, np.float64)[None, :sys.n] * z
         traj[s - 1, idx] = x[idx]
         bad = idx[~is_safe(sys, x[idx])]
         newly = bad[fv[bad] == H + 1]
@@ -358,9 +392,9 @@ def select(sys: System, cand: np.ndarray, fv: np.ndarray, H: int, u_h) -> dict:
                 deviation=float(np.linalg.norm(u_r - np.asarray(u_h, np.float64).reshape(-1))))
 
 
-def tick(sys: System, K, x_t, u_h, cand: np.ndarray, H: int) -> dict:
+def tick(sys: System, K, x_t, u_h, cand: np.ndarray, H: int, noise_key=None) -> dict:
     """One MPMI-SC control tick over an explicit candidate set (N+1, S, m)."""
-    traj, fv = rollout(sys, K, x_t, cand, H, early_exit=True)
+    traj, fv = rollout(sys, K, x_t, cand, H, early_exit=True, noise_key=noise_key)
     out = select(sys, cand, fv, H, u_h)
     out["fv"] = fv
     return out

@@ -95,6 +95,9 @@ mpmi_status validate_system(mpmi_ctx ctx, const mpmi_system* s) {
         return fail(ctx, MPMI_EINVAL, "track_freq[%d]=%d out of 0..8", k, s->track_freq[k]);
     if (!(s->track_infl >= 0.0f)) return fail(ctx, MPMI_EINVAL, "track_infl must be >= 0");
   }
+  for (int j = 0; j < 8; ++j)
+    if (!(s->noise_sigma[j] >= 0.0f) || s->noise_sigma[j] > 1e30f)
+      return fail(ctx, MPMI_EINVAL, "noise_sigma[%d] must be finite and >= 0", j);
   for (int j = 0; j < s->n_input; ++j)
     if (!(s->u_hi[j] > s->u_lo[j]))
       return fail(ctx, MPMI_EINVAL, "input box %d is empty (lo=%g hi=%g)", j, (double)s->u_lo[j], (double)s->u_hi[j]);
@@ -309,6 +312,8 @@ mpmi_status mpmi_tick(mpmi_ctx ctx, const void* model, const mpmi_tick_desc* des
     if (sys.basis != MPMI_BASIS_RACE_CAR)
       return fail(ctx, MPMI_EUNSUPPORTED, "BF16X3 is implemented for race-car models");
     if (traj) return fail(ctx, MPMI_EUNSUPPORTED, "BF16X3 ticks do not store trajectories");
+    for (int j = 0; j < 8; ++j)
+      if (sys.noise_sigma[j] > 0.0f) return fail(ctx, MPMI_EUNSUPPORTED, "BF16X3 ticks are noise-free");
     if (desc->block != 0 && desc->block != 256)
       return fail(ctx, MPMI_EUNSUPPORTED, "BF16X3 ticks use 256-thread workgroups");
     return check_hip(ctx, mpmi::launch_tick_bf16(model, *desc, x_t, u_user, cand, slot, out, first_violation,

@@ -43,7 +43,8 @@ struct alignas(256) ModelDev {
   int32_t m;            // input size
   int32_t state_feat0;  // index of feature w_0 = x_0 in psi (E's first row)
   int32_t hmax;         // highest track harmonic used (0 = no track)
-  int32_t pad0[2];
+  int32_t has_noise;    // any noise_sigma > 0
+  int32_t pad0;
   float bb_lim[MPMI_MAX_BOX];     // box_bound - box_infl
   float trk_lim;                  // track_half - track_infl
   float trk_p[kMaxHarm + 1];      // r_c = P(cos phi) + sin phi * Q(cos phi): P coefficients
@@ -76,14 +77,43 @@ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
   return z ^ (z >> 31);
 }
 
-__device__ __forceinline__ uint64_t hash_counter(uint64_t seed, uint64_t tick, uint64_t loop,
-                                                 uint64_t idx, uint64_t slot) {
+// Chain over (seed, tick, loop, idx); hash_counter finishes it with the slot.
+__device__ __forceinline__ uint64_t hash_prefix(uint64_t seed, uint64_t tick, uint64_t loop, uint64_t idx) {
   uint64_t h = seed;
   h = mix64((h ^ tick) + kGoldenGamma);
   h = mix64((h ^ loop) + kGoldenGamma);
   h = mix64((h ^ idx) + kGoldenGamma);
-  h = mix64((h ^ slot) + kGoldenGamma);
   return h;
+}
+
+__device__ __forceinline__ uint64_t hash_finish(uint64_t prefix, uint64_t slot) {
+  return mix64((prefix ^ slot) + kGoldenGamma);
+}
+
+__device__ __forceinline__ uint64_t hash_counter(uint64_t seed, uint64_t tick, uint64_t loop,
+                                                 uint64_t idx, uint64_t slot) {
+  return hash_finish(hash_prefix(seed, tick, loop, idx), slot);
+}
+
+constexpr uint64_t kNoiseSlot = 65536;
+
+// Process noise after step s (Alg. 2's z_i): pairs of components from one
+// 64-bit draw, Box-Muller in FP32.
+template <int NS>
+__device__ __forceinline__ void add_process_noise(const float* sigma, uint64_t prefix, int s, int n, float* x) {
+#pragma unroll
+  for (int q = 0; q < (NS + 1) / 2; ++q) {
+    if (2 * q < n) {
+      const uint64_t h = hash_finish(prefix, kNoiseSlot + 4ull * (uint64_t)(s - 1) + (uint64_t)q);
+      const float u1 = (float)((h >> 40) + 1ull) * 0x1p-24f;
+      const float u2 = (float)((h >> 16) & 0xFFFFFFull) * 0x1p-24f;
+      const float r = sqrtf(-2.0f * logf(u1));
+      float sn, cs;
+      sincosf(6.283185307179586f * u2, &sn, &cs);
+      x[2 * q] = fmaf(sigma[2 * q], r * cs, x[2 * q]);
+      if (2 * q + 1 < n) x[2 * q + 1] = fmaf(sigma[2 * q + 1], r * sn, x[2 * q + 1]);
+    }
+  }
 }
 
 // Value of a UNIFORM candidate input: lo + (hi - lo) * r in FP64, r = top 24

@@ -203,6 +203,9 @@ __global__ void pack_kernel(mpmi_system sys, int dim, int state_feat0, const dou
     for (int k = 0; k <= kMaxHarm; ++k) md->trk_p[k] = (float)P[k];
     for (int k = 0; k < kMaxHarm; ++k) md->trk_q[k] = (float)Q[k];
     md->hmax = hmax;
+    int noisy = 0;
+    for (int j = 0; j < 8; ++j) noisy |= (j < n && sys.noise_sigma[j] > 0.0f) ? 1 : 0;
+    md->has_noise = noisy;
     for (int j = 0; j < MPMI_MAX_INPUT; ++j)
       md->half_inv[j] = (j < sys.n_input) ? (float)(2.0 / ((double)sys.u_hi[j] - (double)sys.u_lo[j])) : 0.0f;
   }

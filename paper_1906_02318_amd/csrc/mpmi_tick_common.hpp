@@ -155,6 +155,8 @@ __device__ __forceinline__ CandResult evaluate_candidate(const ModelDev* __restr
   stp.set_input(md, sK, u);
   int fv = H + 1;
   if (valid) {
+    const bool noisy = md->has_noise != 0;
+    const uint64_t nprefix = noisy ? hash_prefix(gp.seed, gp.tick, (uint64_t)(uint32_t)gp.loop, (uint64_t)c) : 0ull;
     int gcur = 0;
     for (int s = 1; s <= H; ++s) {
       const int g = ((s - 1) * S) / H;
@@ -165,6 +167,7 @@ __device__ __forceinline__ CandResult evaluate_candidate(const ModelDev* __restr
         stp.set_input(md, sK, u);
       }
       stp.step(md, sK, x);
+      if (noisy) add_process_noise<NS>(md->sys.noise_sigma, nprefix, s, n, x);
       if (traj) {
 #pragma unroll
         for (int j = 0; j < NS; ++j)

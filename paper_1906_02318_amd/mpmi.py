@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmpmi.so")
 
 # Constants mirrored from include/mpmi.h
-ABI_VERSION = 1
+ABI_VERSION = 2
 MAX_STATE, MAX_INPUT, MAX_DIM, MAX_BOX = 8, 4, 64, 4
 MAX_HORIZON, MAX_SEGMENTS, MAX_CAND, MAX_LOOPS = 255, 8, 33554431, 4096
 OK, NO_SAFE, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED, ESINGULAR = 0, 1, -1, -2, -3, -4, -5
@@ -37,6 +37,7 @@ class System(ctypes.Structure):
         ("track_freq", _i32x4), ("track_amp", _f32x4), ("track_phase", _f32x4),
         ("track_r0", ctypes.c_float), ("track_half", ctypes.c_float), ("track_infl", ctypes.c_float),
         ("eps_track", ctypes.c_float), ("u_lo", _f32x4), ("u_hi", _f32x4),
+        ("noise_sigma", ctypes.c_float * 8),
     ]
 
 
@@ -136,8 +137,10 @@ def library() -> ctypes.CDLL:
 # ---------------------------------------------------------------------------
 # System descriptors (plain data)
 # ---------------------------------------------------------------------------
-def _sys(basis, n, m, box, u_lo, u_hi, track=None, eps_box=None, eps_track=0.0):
+def _sys(basis, n, m, box, u_lo, u_hi, track=None, eps_box=None, eps_track=0.0, noise=None):
     s = System()
+    for j, v in enumerate(noise or []):
+        s.noise_sigma[j] = float(v)
     s.basis, s.n_state, s.n_input = basis, n, m
     s.n_box = len(box)
     for b, (idx, bound, infl) in enumerate(box):
@@ -162,17 +165,18 @@ def linear_system(n, m, box, u_lo, u_hi):
     return _sys(BASIS_LINEAR, n, m, box, u_lo, u_hi)
 
 
-def balance_bot_system(theta_bound=0.5, p_bound=2.0, infl=0.0, u_lo=-5.0, u_hi=5.0, eps=(5e-5, 2e-4)):
+def balance_bot_system(theta_bound=0.5, p_bound=2.0, infl=0.0, u_lo=-5.0, u_hi=5.0, eps=(5e-5, 2e-4),
+                       noise=None):
     """Cart-pole: |theta| < theta_bound - infl, |p| < p_bound - infl, u in [u_lo, u_hi]."""
     return _sys(BASIS_BALANCE_BOT, 4, 1, [(2, theta_bound, infl), (0, p_bound, infl)], [u_lo], [u_hi],
-                eps_box=list(eps))
+                eps_box=list(eps), noise=noise)
 
 
 def race_car_system(track: dict, vy_bound=2.0, infl=0.0, u_lo=(-0.4, -3.0), u_hi=(0.4, 3.0),
-                    eps_track=0.02, eps_vy=0.02):
+                    eps_track=0.02, eps_vy=0.02, noise=None):
     """Dynamic bicycle on a track (dict r0, half, amp, freq, phase, infl) with |v_y| < vy_bound - infl."""
     return _sys(BASIS_RACE_CAR, 6, 2, [(4, vy_bound, infl)], u_lo, u_hi, track=track,
-                eps_box=[eps_vy], eps_track=eps_track)
+                eps_box=[eps_vy], eps_track=eps_track, noise=noise)
 
 
 # ---------------------------------------------------------------------------

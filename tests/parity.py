@@ -43,9 +43,9 @@ def ambiguous(sys: o.System, traj64: np.ndarray, fv_a: np.ndarray, fv_b: np.ndar
 
 
 def check_tick(sys: o.System, K, x_t, u_h, cand64: np.ndarray, H: int, sel: dict, fv_gpu: np.ndarray, eps,
-               label: str = "") -> dict:
+               label: str = "", noise_key=None) -> dict:
     """Checks one GPU tick against the oracle; returns counters for reporting."""
-    traj, fv_o = o.rollout(sys, K, x_t, cand64, H, early_exit=False)
+    traj, fv_o = o.rollout(sys, K, x_t, cand64, H, early_exit=False, noise_key=noise_key)
     fv_gpu = np.asarray(fv_gpu, np.int64)
     amb = ambiguous(sys, traj, fv_o, fv_gpu, eps)
     mism = (fv_o != fv_gpu) & ~amb

@@ -478,3 +478,39 @@ def test_full_size_race_car_sampled_parity_and_properties(ctx, rc):
         assert np.all(fv2.cpu().numpy() <= fvg), f"tick {t}: mask not monotone under inflation"
         log(f"[full size] tick {t}: idx={sel['idx']} status={sel['status']} n_safe={sel['n_safe']} "
             f"sampled={idx.size} ambiguous={int(amb.sum())}")
+
+
+@pytest.mark.parametrize("system", ["bb", "rc"])
+def test_tick_with_process_noise(ctx, system):
+    """Alg. 2's process noise z_i: every predicted state gains sigma * z, z from
+    the counter generator (same definition on both sides)."""
+    if system == "bb":
+        K = W.bb_model()[0]
+        sig = [0.002, 0.01, 0.002, 0.02]
+        so = W.bb_oracle_system()
+        model = mpmi.mpmi_model_pack(ctx, mpmi.balance_bot_system(noise=sig), dev(K, torch.float64))
+        xs = synth.balance_bot_states(4, seed=61)
+        uhs = synth.uniform_user(4, [-5.0], [5.0], seed=62)
+        N, H, S, eps = 4000, 50, 5, EPS_BB
+    else:
+        K = W.rc_model()[0]
+        sig = [0.01, 0.01, 0.002, 0.05, 0.02, 0.005]
+        so = W.rc_oracle_system(W.rc_track())
+        model = mpmi.mpmi_model_pack(ctx, mpmi.race_car_system(W.track_dict(W.rc_track()), noise=sig),
+                                     dev(K, torch.float64))
+        xs = synth.race_car_states(4, W.rc_track(), seed=61)
+        uhs = synth.uniform_user(4, synth.RC_U_LO, synth.RC_U_HI, seed=62)
+        N, H, S, eps = 4000, 60, 1, EPS_RC
+    so.noise = W.f32(sig)
+    kinds = {}
+    for t in range(4):
+        x, u = W.f32(xs[t]), W.f32(uhs[t])
+        desc = mpmi.tick_desc(N, H, gen=mpmi.GEN_UNIFORM, n_seg=S, seed=21, tick=t, loop=3)
+        fv = torch.empty(N + 1, dtype=torch.int16, device="cuda")
+        sel = mpmi.decode_selection(mpmi.mpmi_tick(ctx, model, desc, dev(x, torch.float32), dev(u, torch.float32),
+                                                   first_violation=fv))
+        cand = o.with_user(o.uniform_candidates(so, N, S, 21, t, 3), u, S)
+        res = check_tick(so, K, x, u, cand, H, sel, fv.cpu().numpy(), eps, label=f"noisy {system} tick {t}",
+                         noise_key=(21, t, 3))
+        kinds[res["kind"]] = kinds.get(res["kind"], 0) + 1
+    log(f"[noise] {system}: {kinds}")

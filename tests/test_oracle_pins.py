@@ -342,3 +342,39 @@ def test_no_safe_fallback_rule():
     fv = np.array([3, 11, 11, 11])
     r = o.select(sys, cand, fv, 10, [0.0])
     assert r["status"] == o.STATUS_OK and r["idx"] == 1 and r["n_safe"] == 3
+
+
+# ------------------------------------------------------- process noise (Alg. 2 z_i) --
+def test_process_noise_is_standard_normal():
+    z = o.process_noise(3, 4, 5, np.arange(1, 20001), 7, 6)
+    assert z.shape == (20000, 6)
+    for j in range(6):
+        assert scipy.stats.kstest(z[:, j], "norm").pvalue > 1e-3
+    c = np.corrcoef(z.T)
+    assert np.max(np.abs(c - np.eye(6))) < 0.03
+    # different steps and candidates give different draws
+    assert not np.allclose(o.process_noise(3, 4, 5, [1], 1, 6), o.process_noise(3, 4, 5, [1], 2, 6))
+
+
+def test_noisy_linear_rollout_closed_form():
+    """x_s = A x_{s-1} + B u + sigma z_s, so x_s = A^s x0 + sum_j A^j B u + sum_k A^{s-k} sigma z_k."""
+    A, B, _, _, _ = _linear_case()
+    K = np.vstack([A.T, B.T])
+    sig = np.array([0.1, 0.02, 0.05, 0.3])
+    sys = o.System("linear", 4, 1, box=[], u_lo=[-1.0], u_hi=[1.0], noise=sig)
+    x0 = np.array([0.3, -0.2, 0.5, 0.1])
+    cand = o.with_user(o.grid_candidates(sys, [9]), [0.25], 1)
+    H = 8
+    traj, _ = o.rollout(sys, K, x0, cand, H, early_exit=False, noise_key=(11, 12, 13))
+    zs = [o.process_noise(11, 12, 13, np.arange(cand.shape[0]), s, 4) for s in range(1, H + 1)]
+    for s in range(1, H + 1):
+        exp = (np.linalg.matrix_power(A, s) @ x0)[None, :] + \
+            np.outer(cand[:, 0, 0], sum(np.linalg.matrix_power(A, j) @ B[:, 0] for j in range(s)))
+        for k in range(1, s + 1):
+            exp = exp + (zs[k - 1] * sig[None, :]) @ np.linalg.matrix_power(A, s - k).T
+        np.testing.assert_allclose(traj[s - 1], exp, rtol=1e-11, atol=1e-12)
+    # zero noise reproduces the deterministic rollout
+    sys0 = o.System("linear", 4, 1, box=[], u_lo=[-1.0], u_hi=[1.0], noise=np.zeros(4))
+    t0, _ = o.rollout(sys0, K, x0, cand, H, early_exit=False, noise_key=(11, 12, 13))
+    t1, _ = o.rollout(o.System("linear", 4, 1, box=[], u_lo=[-1.0], u_hi=[1.0]), K, x0, cand, H, early_exit=False)
+    np.testing.assert_array_equal(t0, t1)
