@@ -54,7 +54,23 @@ __device__ __forceinline__ bool near_boundary(const ModelDev* __restrict__ md, c
 
 __device__ __forceinline__ uint16_t bf16_hi(float v) { return (uint16_t)bf16_bits_rne_u(v); }
 
-__global__ void __launch_bounds__(256)
+// Shared-coefficient feature f of the race-car step (f is a compile-time
+// constant after unrolling, so this folds to one product).
+__device__ __forceinline__ float rc_shared_feature(int f, const float* x, float sp, float cp) {
+  if (f < 21) {
+    int k = 0, r = f;
+    while (r >= 6 - k) {
+      r -= 6 - k;
+      ++k;
+    }
+    return x[k] * x[k + r];
+  }
+  if (f < 24) return sp * x[3 + (f - 21)];
+  if (f < 27) return cp * x[3 + (f - 24)];
+  return 0.0f;
+}
+
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 4)))
 tick_bf16_race_car_kernel(const ModelDev* __restrict__ md, GenParams gp, int H, const float* __restrict__ x_t,
                           const float* __restrict__ u_user, const float* __restrict__ cand,
                           Slot* __restrict__ slot, int16_t* __restrict__ fv_out, RecheckList* __restrict__ rl,
@@ -110,25 +126,15 @@ tick_bf16_race_car_kernel(const ModelDev* __restrict__ md, GenParams gp, int H, 
     }
     float sp, cp;
     sincosf(x[2], &sp, &cp);
-    // Per-step shared-coefficient features, split into BF16 hi/lo, to LDS.
-    float q[32];
-    {
-      int f = 0;
-#pragma unroll
-      for (int k = 0; k < 6; ++k)
-#pragma unroll
-        for (int l = k; l < 6; ++l) q[f++] = x[k] * x[l];
-      q[21] = sp * x[3]; q[22] = sp * x[4]; q[23] = sp * x[5];
-      q[24] = cp * x[3]; q[25] = cp * x[4]; q[26] = cp * x[5];
-#pragma unroll
-      for (int k = 27; k < 32; ++k) q[k] = 0.0f;
-    }
+    // Per-step shared-coefficient features, split into BF16 hi/lo, to LDS,
+    // eight at a time (feature f < 21: x_k x_l in (k <= l) order; 21..23:
+    // sin psi (vx, vy, r); 24..26: cos psi (vx, vy, r); 27..31: zero).
 #pragma unroll
     for (int k8 = 0; k8 < 4; ++k8) {
       bf16x8_t h8, l8;
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
-        const float v = q[k8 * 8 + i];
+        const float v = rc_shared_feature(k8 * 8 + i, x, sp, cp);
         const uint16_t h = bf16_hi(v);
         const float vh = __uint_as_float((uint32_t)h << 16);
         h8[i] = __builtin_bit_cast(__bf16, h);
