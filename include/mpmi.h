@@ -174,6 +174,8 @@ typedef struct mpmi_tick_desc {
   int32_t horizon;        /* H, 1..255 */
   int32_t precision;      /* MPMI_PREC_* */
   int32_t block;          /* threads per workgroup: 0 (library default) or 64..1024, multiple of 64 */
+  int32_t lanes_per_cand; /* FP32 ticks: 0 or 1 (one lane per candidate), or 2 / 4 lanes per candidate,
+                             each lane computing a share of the state (lower latency at small N) */
 } mpmi_tick_desc;
 
 typedef struct mpmi_ctx_s* mpmi_ctx;
@@ -248,6 +250,15 @@ mpmi_status mpmi_tick(mpmi_ctx ctx, const void* model, const mpmi_tick_desc* des
                       const float* x_t, const float* u_user, const float* cand,
                       mpmi_selection* out, int16_t* first_violation, float* traj,
                       void* stream);
+
+/* Tick autotuner: times `reps` ticks of *desc for every launch shape in the
+ * library's search space (block 64..512, lanes_per_cand 1, 2, 4; FP32 only)
+ * and writes the fastest into desc->block and desc->lanes_per_cand (host);
+ * *best_ms (host, may be NULL) receives its mean tick time.  The timed ticks
+ * are real ticks writing *out. */
+mpmi_status mpmi_tick_autotune(mpmi_ctx ctx, const void* model, mpmi_tick_desc* desc /* host, in/out */,
+                               const float* x_t, const float* u_user, const float* cand, mpmi_selection* out,
+                               int32_t reps, float* best_ms /* host */, void* stream);
 
 /* Writes the candidates a tick with `desc` evaluates, cand_out [S][m][N+1]
  * (column 0 = u_user), so generated candidates can be inspected.           */

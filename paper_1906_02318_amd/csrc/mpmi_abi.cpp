@@ -274,6 +274,10 @@ static mpmi_status validate_desc(mpmi_ctx ctx, const mpmi_system& sys, const mpm
     return fail(ctx, MPMI_EINVAL, "block=%d must be 0 or a multiple of 64 in 64..1024", d->block);
   if (d->precision != MPMI_PREC_FP32 && d->precision != MPMI_PREC_BF16X3)
     return fail(ctx, MPMI_EINVAL, "unknown precision %d", d->precision);
+  if (d->lanes_per_cand != 0 && d->lanes_per_cand != 1 && d->lanes_per_cand != 2 && d->lanes_per_cand != 4)
+    return fail(ctx, MPMI_EINVAL, "lanes_per_cand=%d must be 0, 1, 2 or 4", d->lanes_per_cand);
+  if (d->lanes_per_cand > 1 && (d->precision != MPMI_PREC_FP32 || sys.basis == MPMI_BASIS_LINEAR))
+    return fail(ctx, MPMI_EUNSUPPORTED, "several lanes per candidate: FP32 ticks of the fixed bases only");
   switch (d->gen) {
     case MPMI_GEN_EXPLICIT:
     case MPMI_GEN_UNIFORM:
@@ -308,6 +312,15 @@ mpmi_status mpmi_tick(mpmi_ctx ctx, const void* model, const mpmi_tick_desc* des
   if (desc->gen == MPMI_GEN_EXPLICIT && desc->n_cand > 0 && !cand)
     return fail(ctx, MPMI_EINVAL, "EXPLICIT candidates need cand");
   void* slot = (char*)ctx->slots + (size_t)desc->loop * mpmi::slot_bytes();
+  if (desc->lanes_per_cand > 1) {
+    if (traj) return fail(ctx, MPMI_EUNSUPPORTED, "several lanes per candidate: no trajectory store");
+    for (int j = 0; j < 8; ++j)
+      if (sys.noise_sigma[j] > 0.0f)
+        return fail(ctx, MPMI_EUNSUPPORTED, "several lanes per candidate: noise-free models only");
+    return check_hip(ctx, mpmi::launch_tick_split(sys.basis, desc->lanes_per_cand, model, *desc, x_t, u_user, cand,
+                                                  slot, out, first_violation, (hipStream_t)stream),
+                     "mpmi_tick (split) launch");
+  }
   if (desc->precision == MPMI_PREC_BF16X3) {
     if (sys.basis != MPMI_BASIS_RACE_CAR)
       return fail(ctx, MPMI_EUNSUPPORTED, "BF16X3 is implemented for race-car models");
@@ -324,6 +337,55 @@ mpmi_status mpmi_tick(mpmi_ctx ctx, const void* model, const mpmi_tick_desc* des
   return check_hip(ctx, mpmi::launch_tick(sys.basis, model, *desc, x_t, u_user, cand, slot, out, first_violation,
                                           traj, (hipStream_t)stream),
                    "mpmi_tick launch");
+}
+
+mpmi_status mpmi_tick_autotune(mpmi_ctx ctx, const void* model, mpmi_tick_desc* desc, const float* x_t,
+                               const float* u_user, const float* cand, mpmi_selection* out, int32_t reps,
+                               float* best_ms, void* stream) {
+  if (!ctx) return MPMI_EINVAL;
+  if (!desc) return fail(ctx, MPMI_EINVAL, "desc is NULL");
+  if (reps < 1 || reps > 100000) return fail(ctx, MPMI_EINVAL, "reps=%d out of 1..100000", reps);
+  if (desc->precision != MPMI_PREC_FP32) return fail(ctx, MPMI_EUNSUPPORTED, "the tick autotuner times FP32 ticks");
+  mpmi_system sys;
+  mpmi_status s = model_system(ctx, model, &sys, nullptr);
+  if (s != MPMI_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return fail(ctx, MPMI_EDEVICE, "hipEventCreate failed");
+  mpmi_tick_desc d = *desc;
+  float bms = 1e30f;
+  int bblock = 256, blanes = 1;
+  for (int lanes : {1, 2, 4}) {
+    if (lanes > 1 && sys.basis == MPMI_BASIS_LINEAR) continue;
+    for (int block : {64, 128, 256, 512}) {
+      d.block = block;
+      d.lanes_per_cand = lanes;
+      for (int w = 0; w < 2 && s == MPMI_OK; ++w) s = mpmi_tick(ctx, model, &d, x_t, u_user, cand, out, nullptr, nullptr, stream);
+      if (s == MPMI_OK && hipEventRecord(e0, st) != hipSuccess) s = MPMI_EDEVICE;
+      for (int r = 0; r < reps && s == MPMI_OK; ++r)
+        s = mpmi_tick(ctx, model, &d, x_t, u_user, cand, out, nullptr, nullptr, stream);
+      float ms = 0.0f;
+      if (s == MPMI_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                           hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+        s = MPMI_EDEVICE;
+      if (s != MPMI_OK) break;
+      ms /= (float)reps;
+      if (ms < bms) {
+        bms = ms;
+        bblock = block;
+        blanes = lanes;
+      }
+    }
+    if (s != MPMI_OK) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (s != MPMI_OK) return s;
+  desc->block = bblock;
+  desc->lanes_per_cand = blanes;
+  if (best_ms) *best_ms = bms;
+  return ok(ctx);
 }
 
 mpmi_status mpmi_generate_candidates(mpmi_ctx ctx, const void* model, const mpmi_tick_desc* desc,

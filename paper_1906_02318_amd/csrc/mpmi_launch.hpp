@@ -34,6 +34,11 @@ size_t fit_workspace_bytes();
 hipError_t launch_fit(const mpmi_system& sys, int dim, const double* X, const double* U, const double* Y,
                       int64_t T, double ridge, double* K_out, void* work, hipStream_t st);
 
+// Latency form of the tick (mpmi_split.hip).
+hipError_t launch_tick_split(int basis, int split, const void* model, const mpmi_tick_desc& d, const float* x_t,
+                             const float* u_user, const float* cand, void* slot, mpmi_selection* out, int16_t* fv,
+                             hipStream_t st);
+
 // BF16X3 race-car tick + FP32 recheck (mpmi_bf16.hip).
 constexpr int kRecheckCapacity = 1 << 22;
 size_t recheck_bytes(int capacity);

@@ -1,0 +1,239 @@
+// Latency form of the fused tick: each candidate spread over SPLIT lanes.
+//
+// With few candidates per tick a wave's 60-step serial chain, not the chip's
+// throughput, sets the tick time.  Here lane h of a group of SPLIT computes
+// output columns [h J, h J + J) of every step (J = ceil(n / SPLIT)) from the
+// full feature set, and the group rebuilds the full next state with
+// cross-lane permutes, so each lane's chain per step is about half (SPLIT =
+// 2) of the one-lane form, at the price of redundant feature and safety work.
+// The autotuner picks SPLIT (1, 2 or 4) and the workgroup size per workload.
+#include <hip/hip_runtime.h>
+
+#include "mpmi_device.hpp"
+#include "mpmi_launch.hpp"
+#include "mpmi_tick_common.hpp"
+
+namespace mpmi {
+
+// LDS rows of 8 floats; column j of a row sits at (j / J) * A + (j % J), A = 4
+// when J = 3 (so a lane's three columns are one aligned float4), else J.
+template <int J>
+struct SplitLayout {
+  static constexpr int A = (J == 3) ? 4 : J;
+  static __device__ __forceinline__ int pos(int j) { return (j / J) * A + (j % J); }
+};
+
+constexpr int kSplitRows = 64 + 27;  // full rows + per-step rows (race car is the larger)
+
+template <int BASIS, int J>
+__device__ __forceinline__ void stage_K_split(const ModelDev* __restrict__ md, float* sK8) {
+  constexpr int NS = Dims<BASIS>::N;
+  const int D = md->dim;
+  const int R = (BASIS == MPMI_BASIS_RACE_CAR) ? kRcStepRows : 10;
+  for (int e = threadIdx.x; e < (D + R) * 8; e += blockDim.x) sK8[e] = 0.0f;
+  __syncthreads();
+  for (int e = threadIdx.x; e < (D + R) * NS; e += blockDim.x) {
+    const int r = e / NS, j = e % NS;
+    int row;
+    if (r < D) {
+      row = r;
+    } else {
+      const int q = r - D;
+      if (BASIS == MPMI_BASIS_RACE_CAR) {
+        if (q < 21) {
+          int k = 0, t = q;
+          while (t >= 6 - k) { t -= 6 - k; ++k; }
+          row = quad_index(k, k + t, 8);
+        } else {
+          constexpr int trig_rows[6] = {49, 50, 51, 53, 54, 55};
+          row = trig_rows[q - 21];
+        }
+      } else {
+        int k = 0, t = q;
+        while (t >= 4 - k) { t -= 4 - k; ++k; }
+        row = quad_index(k, k + t, 5);
+      }
+    }
+    sK8[r * 8 + SplitLayout<J>::pos(j)] = md->K[row][j];
+  }
+  __syncthreads();
+}
+
+// Loads J consecutive floats at an aligned LDS position.
+template <int J>
+__device__ __forceinline__ void ldsJ(const float* p, float* out) {
+  if constexpr (J == 3 || J == 4) {
+    const float4 v = *reinterpret_cast<const float4*>(p);
+    out[0] = v.x; out[1] = v.y; out[2] = v.z;
+    if constexpr (J == 4) out[3] = v.w;
+  } else if constexpr (J == 2) {
+    const float2 v = *reinterpret_cast<const float2*>(p);
+    out[0] = v.x; out[1] = v.y;
+  } else {
+    out[0] = p[0];
+  }
+}
+
+template <int BASIS, int SPLIT>
+__global__ void __launch_bounds__(1024)
+tick_split_kernel(const ModelDev* __restrict__ md, GenParams gp, int H, const float* __restrict__ x_t,
+                  const float* __restrict__ u_user, const float* __restrict__ cand, Slot* __restrict__ slot,
+                  mpmi_selection* __restrict__ out, int16_t* __restrict__ fv_out) {
+  constexpr int NS = Dims<BASIS>::N, MS = Dims<BASIS>::M;
+  constexpr int J = (NS + SPLIT - 1) / SPLIT;
+  constexpr int D = (BASIS == MPMI_BASIS_RACE_CAR) ? 64 : 21;
+  constexpr int R = (BASIS == MPMI_BASIS_RACE_CAR) ? kRcStepRows : 10;
+  __shared__ __attribute__((aligned(16))) float sK8[kSplitRows * 8];
+  stage_K_split<BASIS, J>(md, sK8);
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = gid / SPLIT, h = gid % SPLIT;
+  const int base = (threadIdx.x & 63) - h;  // first lane of this group within the wave
+  const int Nc = gp.n_cand + 1;
+  const bool valid = c < Nc;
+  const int colpos = h * SplitLayout<J>::A;
+
+  float x[NS], u[MS], u0[MS];
+#pragma unroll
+  for (int j = 0; j < NS; ++j) x[j] = x_t[j];
+#pragma unroll
+  for (int j = 0; j < MS; ++j) {
+    u0[j] = valid ? cand_value(gp, md, cand, u_user, c, 0, j) : 0.0f;
+    u[j] = u0[j];
+  }
+  // Folded per-lane coefficients for this lane's columns.
+  float cu[J], L[NS][J], Ts[J], Tc[J];
+  auto fold = [&](const float* uu) {
+    float sd = 0.0f, cd = 1.0f;
+    if (BASIS == MPMI_BASIS_RACE_CAR) sincosf(uu[0], &sd, &cd);
+#pragma unroll
+    for (int jj = 0; jj < J; ++jj) {
+      const int p = colpos + jj;
+      auto Kr = [&](int f) { return sK8[f * 8 + p]; };
+      if (BASIS == MPMI_BASIS_RACE_CAR) {
+        const float d = uu[0], a = uu[1];
+        float v = Kr(0);
+        v = fmaf(d, Kr(7), v);
+        v = fmaf(a, Kr(8), v);
+        v = fmaf(d * d, Kr(quad_index(6, 6, 8)), v);
+        v = fmaf(d * a, Kr(quad_index(6, 7, 8)), v);
+        v = fmaf(a * a, Kr(quad_index(7, 7, 8)), v);
+        v = fmaf(sd, Kr(47), v);
+        v = fmaf(cd, Kr(48), v);
+        v = fmaf(a * sd, Kr(63), v);
+        cu[jj] = v;
+#pragma unroll
+        for (int k = 0; k < 6; ++k)
+          L[k][jj] = fmaf(a, Kr(quad_index(k, 7, 8)), fmaf(d, Kr(quad_index(k, 6, 8)), Kr(1 + k)));
+        L[3][jj] = fmaf(cd, Kr(60), fmaf(sd, Kr(57), L[3][jj]));
+        L[4][jj] = fmaf(cd, Kr(61), fmaf(sd, Kr(58), L[4][jj]));
+        L[5][jj] = fmaf(cd, Kr(62), fmaf(sd, Kr(59), L[5][jj]));
+        Ts[jj] = fmaf(a, Kr(52), Kr(45));
+        Tc[jj] = fmaf(a, Kr(56), Kr(46));
+      } else {
+        const float uv = uu[0];
+        cu[jj] = fmaf(uv * uv, Kr(quad_index(4, 4, 5)), fmaf(uv, Kr(5), Kr(0)));
+#pragma unroll
+        for (int k = 0; k < NS; ++k) L[k][jj] = fmaf(uv, Kr(quad_index(k, 4, 5)), Kr(1 + k));
+        Ts[jj] = Tc[jj] = 0.0f;
+      }
+    }
+  };
+  fold(u);
+  int fv = H + 1;
+  if (valid) {
+    const int S = gp.n_seg;
+    int gcur = 0;
+    for (int s = 1; s <= H; ++s) {
+      const int g = ((s - 1) * S) / H;
+      if (g != gcur) {
+        gcur = g;
+#pragma unroll
+        for (int j = 0; j < MS; ++j) u[j] = cand_value(gp, md, cand, u_user, c, g, j);
+        fold(u);
+      }
+      float sp = 0.0f, cp = 0.0f;
+      if (BASIS == MPMI_BASIS_RACE_CAR) {
+        sp = __sinf(x[2]);
+        cp = __cosf(x[2]);
+      }
+      float y[J];
+#pragma unroll
+      for (int jj = 0; jj < J; ++jj) {
+        float v = cu[jj];
+        if (BASIS == MPMI_BASIS_RACE_CAR) v = fmaf(Tc[jj], cp, fmaf(Ts[jj], sp, v));
+#pragma unroll
+        for (int k = 0; k < NS; ++k) v = fmaf(L[k][jj], x[k], v);
+        y[jj] = v;
+      }
+      int q = 0;
+#pragma unroll
+      for (int k = 0; k < NS; ++k)
+#pragma unroll
+        for (int l = k; l < NS; ++l) {
+          float kv[J];
+          ldsJ<J>(&sK8[(D + q) * 8 + colpos], kv);
+          const float p = x[k] * x[l];
+#pragma unroll
+          for (int jj = 0; jj < J; ++jj) y[jj] = fmaf(p, kv[jj], y[jj]);
+          ++q;
+        }
+      if (BASIS == MPMI_BASIS_RACE_CAR) {
+        const float tp[6] = {sp * x[3], sp * x[4], sp * x[5], cp * x[3], cp * x[4], cp * x[5]};
+#pragma unroll
+        for (int t = 0; t < 6; ++t) {
+          float kv[J];
+          ldsJ<J>(&sK8[(D + 21 + t) * 8 + colpos], kv);
+#pragma unroll
+          for (int jj = 0; jj < J; ++jj) y[jj] = fmaf(tp[t], kv[jj], y[jj]);
+        }
+      }
+      (void)R;
+      // Rebuild the full state from the group's lanes.
+#pragma unroll
+      for (int j = 0; j < NS; ++j) x[j] = __shfl(y[j % J], base + j / J, 64);
+      if (!(min_margin<NS>(md, x) > 0.0f)) {
+        fv = s;
+        break;
+      }
+    }
+    if (fv_out && h == 0) fv_out[c] = (int16_t)fv;
+  }
+  const bool lead = valid && h == 0;
+  const float cst = lead ? cost_of<MS>(md, u0, u_user) : 0.0f;
+  const bool safe = lead && fv == H + 1;
+  const unsigned long long ks = safe ? safe_key(cst, c) : kKeyNone;
+  const unsigned long long kf = (lead && !safe) ? fallback_key(fv, cst, c) : kKeyNone;
+  if (reduce_and_publish(ks, kf, safe && c > 0, slot, gridDim.x) && threadIdx.x == 0)
+    finalize<MS>(md, gp, cand, u_user, H, slot, out);
+}
+
+hipError_t launch_tick_split(int basis, int split, const void* model, const mpmi_tick_desc& d, const float* x_t,
+                             const float* u_user, const float* cand, void* slot, mpmi_selection* out, int16_t* fv,
+                             hipStream_t st) {
+  GenParams gp;
+  gp.seed = d.seed;
+  gp.tick = d.tick;
+  gp.loop = d.loop;
+  gp.gen = d.gen;
+  gp.n_cand = d.n_cand;
+  gp.n_seg = d.n_seg;
+  for (int j = 0; j < MPMI_MAX_INPUT; ++j) gp.grid[j] = d.grid[j] > 0 ? d.grid[j] : 1;
+  const int block = d.block > 0 ? d.block : 256;
+  const unsigned grid = (unsigned)((((long long)d.n_cand + 1) * split + block - 1) / block);
+  const ModelDev* md = (const ModelDev*)model;
+  Slot* sl = (Slot*)slot;
+  if (basis == MPMI_BASIS_RACE_CAR) {
+    if (split == 2)
+      tick_split_kernel<MPMI_BASIS_RACE_CAR, 2><<<grid, block, 0, st>>>(md, gp, d.horizon, x_t, u_user, cand, sl, out, fv);
+    else
+      tick_split_kernel<MPMI_BASIS_RACE_CAR, 4><<<grid, block, 0, st>>>(md, gp, d.horizon, x_t, u_user, cand, sl, out, fv);
+  } else {
+    if (split == 2)
+      tick_split_kernel<MPMI_BASIS_BALANCE_BOT, 2><<<grid, block, 0, st>>>(md, gp, d.horizon, x_t, u_user, cand, sl, out, fv);
+    else
+      tick_split_kernel<MPMI_BASIS_BALANCE_BOT, 4><<<grid, block, 0, st>>>(md, gp, d.horizon, x_t, u_user, cand, sl, out, fv);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace mpmi

@@ -57,7 +57,7 @@ class TickDesc(ctypes.Structure):
         ("seed", ctypes.c_uint64), ("tick", ctypes.c_uint64), ("loop", ctypes.c_int32),
         ("gen", ctypes.c_int32), ("n_cand", ctypes.c_int32), ("grid", _i32x4),
         ("n_seg", ctypes.c_int32), ("horizon", ctypes.c_int32), ("precision", ctypes.c_int32),
-        ("block", ctypes.c_int32),
+        ("block", ctypes.c_int32), ("lanes_per_cand", ctypes.c_int32),
     ]
 
 
@@ -123,6 +123,8 @@ def library() -> ctypes.CDLL:
         "mpmi_proposal_tick": (i32, [vp, vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(TickDesc),
                                      ctypes.POINTER(TickDesc), vp, vp, vp, vp, ctypes.c_size_t, vp]),
         "mpmi_gemm_bf16": (i32, [vp, vp, vp, i32, i32, i32, i32, i32, vp, vp]),
+        "mpmi_tick_autotune": (i32, [vp, vp, ctypes.POINTER(TickDesc), vp, vp, vp, vp, i32,
+                                     ctypes.POINTER(ctypes.c_float), vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -329,8 +331,9 @@ def select_min_intervention(ctx: Context, model: Model, cand, first_violation, H
 
 
 def tick_desc(n_cand, horizon, gen=GEN_GRID, grid=None, n_seg=1, seed=0, tick=0, loop=0,
-              precision=PREC_FP32, block=0) -> TickDesc:
+              precision=PREC_FP32, block=0, lanes_per_cand=0) -> TickDesc:
     d = TickDesc()
+    d.lanes_per_cand = lanes_per_cand
     d.seed, d.tick, d.loop, d.gen, d.n_cand = seed, tick, loop, gen, n_cand
     for j, g in enumerate(grid or []):
         d.grid[j] = g
@@ -357,6 +360,17 @@ def mpmi_tick(ctx: Context, model: Model, desc: TickDesc, x_t, u_user, cand=None
                                 _ptr(u_user), _ptr(cand), _ptr(out), _ptr(first_violation), _ptr(traj),
                                 _stream(stream)))
     return out
+
+
+def mpmi_tick_autotune(ctx: Context, model: Model, desc: TickDesc, x_t, u_user, cand=None, reps: int = 20,
+                       stream=None):
+    """Times the launch shapes of a tick and sets desc.block / desc.lanes_per_cand to the fastest."""
+    out = torch.empty(SELECTION_BYTES, dtype=torch.uint8, device=ctx.device)
+    ms = ctypes.c_float()
+    ctx.check(ctx.lib.mpmi_tick_autotune(ctx.handle, ctypes.c_void_p(model.ptr), ctypes.byref(desc), _ptr(x_t),
+                                         _ptr(u_user), _ptr(cand), _ptr(out), reps, ctypes.byref(ms),
+                                         _stream(stream)))
+    return dict(block=desc.block, lanes_per_cand=desc.lanes_per_cand, ms=ms.value)
 
 
 def mpmi_generate_candidates(ctx: Context, model: Model, desc: TickDesc, u_user, cand=None, stream=None):

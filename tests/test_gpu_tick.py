@@ -514,3 +514,37 @@ def test_tick_with_process_noise(ctx, system):
                          noise_key=(21, t, 3))
         kinds[res["kind"]] = kinds.get(res["kind"], 0) + 1
     log(f"[noise] {system}: {kinds}")
+
+
+@pytest.mark.parametrize("system", ["bb", "rc"])
+def test_tick_lanes_per_candidate_identical_and_autotuned(ctx, bb, rc, system):
+    """The latency form (2 or 4 lanes per candidate) performs the same FP32
+    operations in the same order: selections and first violations are
+    identical to the one-lane form, and the tick autotuner keeps them so."""
+    so, model, K = bb if system == "bb" else rc
+    if system == "bb":
+        x, u = W.f32(synth.balance_bot_states(1, seed=44)[0]), W.f32([3.0])
+        base = dict(n_cand=10240, horizon=50, gen=mpmi.GEN_UNIFORM, n_seg=5, seed=4, tick=2)
+    else:
+        x, u = W.f32(synth.race_car_states(1, W.rc_track(), seed=44)[0]), W.f32([0.3, -2.0])
+        base = dict(n_cand=16384, horizon=60, gen=mpmi.GEN_GRID, grid=[128, 128])
+    N = base["n_cand"]
+    recs, fvs = [], []
+    for lanes in (1, 2, 4):
+        for block in (64, 256):
+            d = mpmi.tick_desc(base["n_cand"], base["horizon"], gen=base["gen"], grid=base.get("grid"),
+                               n_seg=base.get("n_seg", 1), seed=base.get("seed", 0), tick=base.get("tick", 0),
+                               block=block, lanes_per_cand=lanes)
+            fv = torch.empty(N + 1, dtype=torch.int16, device="cuda")
+            recs.append(mpmi.mpmi_tick(ctx, model, d, dev(x, torch.float32), dev(u, torch.float32),
+                                       first_violation=fv).cpu().numpy().tobytes())
+            fvs.append(fv.cpu().numpy())
+    assert all(r == recs[0] for r in recs)
+    assert all(np.array_equal(f, fvs[0]) for f in fvs)
+    d = mpmi.tick_desc(base["n_cand"], base["horizon"], gen=base["gen"], grid=base.get("grid"),
+                       n_seg=base.get("n_seg", 1), seed=base.get("seed", 0), tick=base.get("tick", 0))
+    best = mpmi.mpmi_tick_autotune(ctx, model, d, dev(x, torch.float32), dev(u, torch.float32), reps=10)
+    log(f"[autotune] {system}: {best}")
+    assert best["lanes_per_cand"] in (1, 2, 4) and best["block"] in (64, 128, 256, 512)
+    rec = mpmi.mpmi_tick(ctx, model, d, dev(x, torch.float32), dev(u, torch.float32)).cpu().numpy().tobytes()
+    assert rec == recs[0]
