@@ -175,7 +175,8 @@ typedef struct mpmi_tick_desc {
   int32_t precision;      /* MPMI_PREC_* */
   int32_t block;          /* threads per workgroup: 0 (library default) or 64..1024, multiple of 64 */
   int32_t lanes_per_cand; /* FP32 ticks: 0 or 1 (one lane per candidate), or 2 / 4 lanes per candidate,
-                             each lane computing a share of the state (lower latency at small N) */
+                             each lane computing a share of the state (lower latency at small N;
+                             block <= 256) */
 } mpmi_tick_desc;
 
 typedef struct mpmi_ctx_s* mpmi_ctx;

@@ -314,6 +314,7 @@ mpmi_status mpmi_tick(mpmi_ctx ctx, const void* model, const mpmi_tick_desc* des
   void* slot = (char*)ctx->slots + (size_t)desc->loop * mpmi::slot_bytes();
   if (desc->lanes_per_cand > 1) {
     if (traj) return fail(ctx, MPMI_EUNSUPPORTED, "several lanes per candidate: no trajectory store");
+    if (desc->block > 256) return fail(ctx, MPMI_EUNSUPPORTED, "several lanes per candidate: block <= 256");
     for (int j = 0; j < 8; ++j)
       if (sys.noise_sigma[j] > 0.0f)
         return fail(ctx, MPMI_EUNSUPPORTED, "several lanes per candidate: noise-free models only");
@@ -359,6 +360,7 @@ mpmi_status mpmi_tick_autotune(mpmi_ctx ctx, const void* model, mpmi_tick_desc* 
   for (int lanes : {1, 2, 4}) {
     if (lanes > 1 && sys.basis == MPMI_BASIS_LINEAR) continue;
     for (int block : {64, 128, 256, 512}) {
+      if (lanes > 1 && block > 256) continue;
       d.block = block;
       d.lanes_per_cand = lanes;
       for (int w = 0; w < 2 && s == MPMI_OK; ++w) s = mpmi_tick(ctx, model, &d, x_t, u_user, cand, out, nullptr, nullptr, stream);

@@ -74,8 +74,50 @@ __device__ __forceinline__ void ldsJ(const float* p, float* out) {
   }
 }
 
+// Folded per-lane coefficients for this lane's J columns (LDS position p0).
+template <int BASIS, int J>
+struct SplitFold {
+  static constexpr int NS = Dims<BASIS>::N;
+  float cu[J], L[NS][J], Ts[J], Tc[J];
+  __device__ __forceinline__ void fold(const float* sK8, int p0, const float* uu) {
+    float sd = 0.0f, cd = 1.0f;
+    if (BASIS == MPMI_BASIS_RACE_CAR) sincosf(uu[0], &sd, &cd);
+#pragma unroll
+    for (int jj = 0; jj < J; ++jj) {
+      const float* Kc = sK8 + p0 + jj;  // column jj of this lane: Kc[f * 8]
+      if (BASIS == MPMI_BASIS_RACE_CAR) {
+        const float d = uu[0], a = uu[1];
+        float v = Kc[0];
+        v = fmaf(d, Kc[7 * 8], v);
+        v = fmaf(a, Kc[8 * 8], v);
+        v = fmaf(d * d, Kc[quad_index(6, 6, 8) * 8], v);
+        v = fmaf(d * a, Kc[quad_index(6, 7, 8) * 8], v);
+        v = fmaf(a * a, Kc[quad_index(7, 7, 8) * 8], v);
+        v = fmaf(sd, Kc[47 * 8], v);
+        v = fmaf(cd, Kc[48 * 8], v);
+        v = fmaf(a * sd, Kc[63 * 8], v);
+        cu[jj] = v;
+#pragma unroll
+        for (int k = 0; k < 6; ++k)
+          L[k][jj] = fmaf(a, Kc[quad_index(k, 7, 8) * 8], fmaf(d, Kc[quad_index(k, 6, 8) * 8], Kc[(1 + k) * 8]));
+        L[3][jj] = fmaf(cd, Kc[60 * 8], fmaf(sd, Kc[57 * 8], L[3][jj]));
+        L[4][jj] = fmaf(cd, Kc[61 * 8], fmaf(sd, Kc[58 * 8], L[4][jj]));
+        L[5][jj] = fmaf(cd, Kc[62 * 8], fmaf(sd, Kc[59 * 8], L[5][jj]));
+        Ts[jj] = fmaf(a, Kc[52 * 8], Kc[45 * 8]);
+        Tc[jj] = fmaf(a, Kc[56 * 8], Kc[46 * 8]);
+      } else {
+        const float uv = uu[0];
+        cu[jj] = fmaf(uv * uv, Kc[quad_index(4, 4, 5) * 8], fmaf(uv, Kc[5 * 8], Kc[0]));
+#pragma unroll
+        for (int k = 0; k < NS; ++k) L[k][jj] = fmaf(uv, Kc[quad_index(k, 4, 5) * 8], Kc[(1 + k) * 8]);
+        Ts[jj] = Tc[jj] = 0.0f;
+      }
+    }
+  }
+};
+
 template <int BASIS, int SPLIT>
-__global__ void __launch_bounds__(1024)
+__global__ void __launch_bounds__(256)
 tick_split_kernel(const ModelDev* __restrict__ md, GenParams gp, int H, const float* __restrict__ x_t,
                   const float* __restrict__ u_user, const float* __restrict__ cand, Slot* __restrict__ slot,
                   mpmi_selection* __restrict__ out, int16_t* __restrict__ fv_out) {
@@ -100,45 +142,8 @@ tick_split_kernel(const ModelDev* __restrict__ md, GenParams gp, int H, const fl
     u0[j] = valid ? cand_value(gp, md, cand, u_user, c, 0, j) : 0.0f;
     u[j] = u0[j];
   }
-  // Folded per-lane coefficients for this lane's columns.
-  float cu[J], L[NS][J], Ts[J], Tc[J];
-  auto fold = [&](const float* uu) {
-    float sd = 0.0f, cd = 1.0f;
-    if (BASIS == MPMI_BASIS_RACE_CAR) sincosf(uu[0], &sd, &cd);
-#pragma unroll
-    for (int jj = 0; jj < J; ++jj) {
-      const int p = colpos + jj;
-      auto Kr = [&](int f) { return sK8[f * 8 + p]; };
-      if (BASIS == MPMI_BASIS_RACE_CAR) {
-        const float d = uu[0], a = uu[1];
-        float v = Kr(0);
-        v = fmaf(d, Kr(7), v);
-        v = fmaf(a, Kr(8), v);
-        v = fmaf(d * d, Kr(quad_index(6, 6, 8)), v);
-        v = fmaf(d * a, Kr(quad_index(6, 7, 8)), v);
-        v = fmaf(a * a, Kr(quad_index(7, 7, 8)), v);
-        v = fmaf(sd, Kr(47), v);
-        v = fmaf(cd, Kr(48), v);
-        v = fmaf(a * sd, Kr(63), v);
-        cu[jj] = v;
-#pragma unroll
-        for (int k = 0; k < 6; ++k)
-          L[k][jj] = fmaf(a, Kr(quad_index(k, 7, 8)), fmaf(d, Kr(quad_index(k, 6, 8)), Kr(1 + k)));
-        L[3][jj] = fmaf(cd, Kr(60), fmaf(sd, Kr(57), L[3][jj]));
-        L[4][jj] = fmaf(cd, Kr(61), fmaf(sd, Kr(58), L[4][jj]));
-        L[5][jj] = fmaf(cd, Kr(62), fmaf(sd, Kr(59), L[5][jj]));
-        Ts[jj] = fmaf(a, Kr(52), Kr(45));
-        Tc[jj] = fmaf(a, Kr(56), Kr(46));
-      } else {
-        const float uv = uu[0];
-        cu[jj] = fmaf(uv * uv, Kr(quad_index(4, 4, 5)), fmaf(uv, Kr(5), Kr(0)));
-#pragma unroll
-        for (int k = 0; k < NS; ++k) L[k][jj] = fmaf(uv, Kr(quad_index(k, 4, 5)), Kr(1 + k));
-        Ts[jj] = Tc[jj] = 0.0f;
-      }
-    }
-  };
-  fold(u);
+  SplitFold<BASIS, J> F;
+  F.fold(sK8, colpos, u);
   int fv = H + 1;
   if (valid) {
     const int S = gp.n_seg;
@@ -149,7 +154,7 @@ tick_split_kernel(const ModelDev* __restrict__ md, GenParams gp, int H, const fl
         gcur = g;
 #pragma unroll
         for (int j = 0; j < MS; ++j) u[j] = cand_value(gp, md, cand, u_user, c, g, j);
-        fold(u);
+        F.fold(sK8, colpos, u);
       }
       float sp = 0.0f, cp = 0.0f;
       if (BASIS == MPMI_BASIS_RACE_CAR) {
@@ -159,19 +164,23 @@ tick_split_kernel(const ModelDev* __restrict__ md, GenParams gp, int H, const fl
       float y[J];
 #pragma unroll
       for (int jj = 0; jj < J; ++jj) {
-        float v = cu[jj];
-        if (BASIS == MPMI_BASIS_RACE_CAR) v = fmaf(Tc[jj], cp, fmaf(Ts[jj], sp, v));
+        float v = F.cu[jj];
+        if (BASIS == MPMI_BASIS_RACE_CAR) v = fmaf(F.Tc[jj], cp, fmaf(F.Ts[jj], sp, v));
 #pragma unroll
-        for (int k = 0; k < NS; ++k) v = fmaf(L[k][jj], x[k], v);
+        for (int k = 0; k < NS; ++k) v = fmaf(F.L[k][jj], x[k], v);
         y[jj] = v;
       }
+      // Opaque zero offset: keeps the per-step K loads inside the loop.
+      int zoff = 0;
+      asm volatile("" : "+v"(zoff));
+      const float* kk = sK8 + zoff;
       int q = 0;
 #pragma unroll
       for (int k = 0; k < NS; ++k)
 #pragma unroll
         for (int l = k; l < NS; ++l) {
           float kv[J];
-          ldsJ<J>(&sK8[(D + q) * 8 + colpos], kv);
+          ldsJ<J>(&kk[(D + q) * 8 + colpos], kv);
           const float p = x[k] * x[l];
 #pragma unroll
           for (int jj = 0; jj < J; ++jj) y[jj] = fmaf(p, kv[jj], y[jj]);
@@ -182,7 +191,7 @@ tick_split_kernel(const ModelDev* __restrict__ md, GenParams gp, int H, const fl
 #pragma unroll
         for (int t = 0; t < 6; ++t) {
           float kv[J];
-          ldsJ<J>(&sK8[(D + 21 + t) * 8 + colpos], kv);
+          ldsJ<J>(&kk[(D + 21 + t) * 8 + colpos], kv);
 #pragma unroll
           for (int jj = 0; jj < J; ++jj) y[jj] = fmaf(tp[t], kv[jj], y[jj]);
         }
