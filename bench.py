@@ -344,6 +344,12 @@ def run_plain_vs_learned(n_ticks: int = 500, warmup: int = 20):
             out[name]["fallback_rate"] = float(np.mean([s["n_cand"] != ticker.P + 1 for s in sels]))
     if "learned" not in out:
         out["learned"] = None
+    else:
+        # Decision quality of the learned ticks against exhaustive 128 x 128 ticks
+        # (and of 2,048 uniform samples, the method without the network).
+        from paper_1906_02318_amd.train_proposal import evaluate
+        out["learned"]["quality"] = evaluate(ctx, model, ProposalNet.load(ctx, ASSET), st["track"], n_ticks=300,
+                                             log=lambda m: None)
     return out
 
 
@@ -357,7 +363,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-extras", action="store_true", help="skip the many-loop and plain-vs-learned legs")
-    ap.add_argument("--multi-ticks", type=int, default=2000)
+    ap.add_argument("--multi-ticks", type=int, default=10000)
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="after timing, run one device-to-device copy of this many bytes (counter calibration)")
     args = ap.parse_args()
