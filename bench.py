@@ -37,6 +37,43 @@ FLOPS_PER_UNIT = {"race_car": 881, "balance_bot": 187}
 #   balance bot: 10 feature products + 56 FMAs + ~6 safety flops.
 EXECUTED_FLOPS_PER_UNIT = {"race_car": 478, "balance_bot": 128}
 
+# HBM traffic of the tick kernel, from rocprofv3 FETCH_SIZE / WRITE_SIZE runs
+# scaled by a copy-kernel calibration; the record names a digest of the
+# kernel's sources and is used only while the sources still match it.
+TRAFFIC_PROFILES = {"race_car_1m": os.path.join(ROOT, "profiles", "tick_fp32_race_car_N1048576_H60.md")}
+TICK_SOURCES = ["paper_1906_02318_amd/csrc/mpmi_tick.hip", "paper_1906_02318_amd/csrc/mpmi_device.hpp",
+                "paper_1906_02318_amd/csrc/mpmi_tick_common.hpp", "include/mpmi.h"]
+
+
+def tick_source_digest() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in TICK_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def traffic_record(workload: str):
+    """(bytes per launch, detail) from the workload's profile summary, or (None, reason)."""
+    path = TRAFFIC_PROFILES.get(workload)
+    if not path or not os.path.exists(path):
+        return None, "no counter profile for this workload"
+    rec = None
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("traffic-record:"):
+                rec = json.loads(line.split(":", 1)[1])
+    if rec is None:
+        return None, "profile has no traffic record"
+    if rec.get("sources_sha256") != tick_source_digest():
+        return None, "kernel sources changed since the counters were taken"
+    detail = {k: rec[k] for k in ("fetch_bytes", "write_bytes", "fetch_scale", "write_scale") if k in rec}
+    detail["profile"] = os.path.relpath(path, ROOT)
+    return rec["fetch_bytes"] + rec["write_bytes"], detail
+
+
 WORKLOADS = {
     # Race car scaled to the >= 1M candidates-per-tick target: 1024 x 1024 grid.
     "race_car_1m": dict(system="race_car", grid=[1024, 1024], H=60, gen="grid", S=1),
@@ -369,7 +406,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the tick's candidates would shard "
-              f"across GPUs with one 8-byte arg-min exchange per loop, which this build does not run.",
+              f"across GPUs with one 8-byte arg-min exchange per loop; multi-GPU runs are not implemented.",
               file=sys.stderr)
         sys.exit(2)
 
@@ -422,6 +459,7 @@ def main():
     avg_kernel_s = float(dev_ms.mean()) * 1e-3
     flops = FLOPS_PER_UNIT[wl["system"]] * units_per_tick
     achieved = flops / avg_kernel_s / 1e12
+    traffic = traffic_record(args.workload)
     out = {
         "metric": METRIC,
         "value": value,
@@ -453,7 +491,8 @@ def main():
             "peak": PEAK_FP32_VECTOR_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_VECTOR_TFLOPS,
-            "traffic": None,
+            "traffic": traffic[0],
+            "traffic_detail": traffic[1],
             "kernel": f"tick_fp32_kernel<{wl['system']}>",
             "avg_kernel_ms": avg_kernel_s * 1e3,
             "flops_per_unit": FLOPS_PER_UNIT[wl["system"]],

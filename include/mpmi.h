@@ -282,7 +282,11 @@ mpmi_status mpmi_generate_candidates(mpmi_ctx ctx, const void* model,
  * ------------------------------------------------------------------------- */
 
 /* One loop (host struct, copied into device memory by mpmi_multi_create;
- * every pointer must stay valid for the life of the mpmi_multi). */
+ * every pointer must stay valid for the life of the mpmi_multi).  The
+ * mpmi_multi keeps its own copy of each distinct packed model, taken at
+ * mpmi_multi_create and again at every re-plan (mpmi_multi_set_config,
+ * mpmi_multi_autotune): a model re-packed in place is seen by the loops from
+ * the next re-plan on. */
 typedef struct mpmi_loop_desc {
   const void* model;          /* packed model on this context */
   const float* x_t;           /* device [n]: current state, read every tick */

@@ -10,6 +10,7 @@
 #include <new>
 #include <string>
 #include <unordered_map>
+#include <vector>
 
 #include "../../include/mpmi.h"
 #include "mpmi_launch.hpp"
@@ -143,16 +144,14 @@ mpmi_status mpmi_create(mpmi_ctx* out, int32_t device) {
     mpmi_destroy(ctx);
     return MPMI_ENOMEM;
   }
-  // Reset state of a slot: both keys all-ones, counters zero.
-  if (hipMemset(ctx->slots, 0, slot_bytes) != hipSuccess || hipMemset(ctx->recheck, 0, 256) != hipSuccess) {
+  // Reset state of a slot: both keys all-ones, counters zero (one copy of a
+  // host image of all slots).
+  std::vector<unsigned char> image(slot_bytes, 0);
+  for (int i = 0; i < MPMI_MAX_LOOPS; ++i) std::memset(image.data() + (size_t)i * mpmi::slot_bytes(), 0xff, 16);
+  if (hipMemcpy(ctx->slots, image.data(), slot_bytes, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemset(ctx->recheck, 0, 256) != hipSuccess) {
     mpmi_destroy(ctx);
     return MPMI_EDEVICE;
-  }
-  for (int i = 0; i < MPMI_MAX_LOOPS; ++i) {
-    if (hipMemset((char*)ctx->slots + i * mpmi::slot_bytes(), 0xff, 16) != hipSuccess) {
-      mpmi_destroy(ctx);
-      return MPMI_EDEVICE;
-    }
   }
   if (hipDeviceSynchronize() != hipSuccess) {
     mpmi_destroy(ctx);
@@ -315,9 +314,8 @@ mpmi_status mpmi_tick(mpmi_ctx ctx, const void* model, const mpmi_tick_desc* des
   if (desc->lanes_per_cand > 1) {
     if (traj) return fail(ctx, MPMI_EUNSUPPORTED, "several lanes per candidate: no trajectory store");
     if (desc->block > 256) return fail(ctx, MPMI_EUNSUPPORTED, "several lanes per candidate: block <= 256");
-    for (int j = 0; j < 8; ++j)
-      if (sys.noise_sigma[j] > 0.0f)
-        return fail(ctx, MPMI_EUNSUPPORTED, "several lanes per candidate: noise-free models only");
+    if (mpmi::system_noisy(sys))
+      return fail(ctx, MPMI_EUNSUPPORTED, "several lanes per candidate: noise-free models only");
     return check_hip(ctx, mpmi::launch_tick_split(sys.basis, desc->lanes_per_cand, model, *desc, x_t, u_user, cand,
                                                   slot, out, first_violation, (hipStream_t)stream),
                      "mpmi_tick (split) launch");
@@ -326,8 +324,7 @@ mpmi_status mpmi_tick(mpmi_ctx ctx, const void* model, const mpmi_tick_desc* des
     if (sys.basis != MPMI_BASIS_RACE_CAR)
       return fail(ctx, MPMI_EUNSUPPORTED, "BF16X3 is implemented for race-car models");
     if (traj) return fail(ctx, MPMI_EUNSUPPORTED, "BF16X3 ticks do not store trajectories");
-    for (int j = 0; j < 8; ++j)
-      if (sys.noise_sigma[j] > 0.0f) return fail(ctx, MPMI_EUNSUPPORTED, "BF16X3 ticks are noise-free");
+    if (mpmi::system_noisy(sys)) return fail(ctx, MPMI_EUNSUPPORTED, "BF16X3 ticks are noise-free");
     if (desc->block != 0 && desc->block != 256)
       return fail(ctx, MPMI_EUNSUPPORTED, "BF16X3 ticks use 256-thread workgroups");
     return check_hip(ctx, mpmi::launch_tick_bf16(model, *desc, x_t, u_user, cand, slot, out, first_violation,
@@ -335,7 +332,7 @@ mpmi_status mpmi_tick(mpmi_ctx ctx, const void* model, const mpmi_tick_desc* des
                                                  mpmi::device_cu_count() * 4, (hipStream_t)stream),
                      "mpmi_tick (BF16X3) launch");
   }
-  return check_hip(ctx, mpmi::launch_tick(sys.basis, model, *desc, x_t, u_user, cand, slot, out, first_violation,
+  return check_hip(ctx, mpmi::launch_tick(sys, model, *desc, x_t, u_user, cand, slot, out, first_violation,
                                           traj, (hipStream_t)stream),
                    "mpmi_tick launch");
 }
@@ -358,7 +355,7 @@ mpmi_status mpmi_tick_autotune(mpmi_ctx ctx, const void* model, mpmi_tick_desc* 
   float bms = 1e30f;
   int bblock = 256, blanes = 1;
   for (int lanes : {1, 2, 4}) {
-    if (lanes > 1 && sys.basis == MPMI_BASIS_LINEAR) continue;
+    if (lanes > 1 && (sys.basis == MPMI_BASIS_LINEAR || mpmi::system_noisy(sys))) continue;
     for (int block : {64, 128, 256, 512}) {
       if (lanes > 1 && block > 256) continue;
       d.block = block;
@@ -454,6 +451,7 @@ mpmi_status mpmi_multi_create(mpmi_ctx ctx, const mpmi_loop_desc* loops, int32_t
     }
     m->plan.host.push_back(L);
     m->plan.basis.push_back(sys.basis);
+    m->plan.noisy = m->plan.noisy || mpmi::system_noisy(sys);
   }
   hipError_t e = mpmi::multi_alloc(m->plan);
   if (e == hipSuccess) e = mpmi::multi_plan(m->plan, block, grid);
@@ -497,8 +495,7 @@ mpmi_status mpmi_multi_get_ticks(mpmi_ctx ctx, mpmi_multi m, uint64_t* ticks) {
   if (!m || !ticks) return fail(ctx, MPMI_EINVAL, "multi and ticks must be non-NULL");
   hipError_t e = hipDeviceSynchronize();
   if (e == hipSuccess)
-    e = hipMemcpy2D(ticks, sizeof(uint64_t), (const char*)m->plan.d_loops + offsetof(mpmi_loop_desc, tick),
-                    sizeof(mpmi_loop_desc), sizeof(uint64_t), (size_t)m->plan.n_loops, hipMemcpyDeviceToHost);
+    e = hipMemcpy(ticks, m->plan.d_ticks, sizeof(uint64_t) * (size_t)m->plan.n_loops, hipMemcpyDeviceToHost);
   return check_hip(ctx, e, "mpmi_multi_get_ticks");
 }
 
@@ -522,7 +519,7 @@ mpmi_status mpmi_multi_autotune(mpmi_ctx ctx, mpmi_multi m, int32_t reps, mpmi_m
   mpmi_multi_config bcfg{m->plan.block, m->plan.grid};
   hipError_t e = hipSuccess;
   for (int block : {64, 128, 256, 512}) {
-    const int maxb = mpmi::multi_max_blocks_per_cu(block);
+    const int maxb = mpmi::multi_max_blocks_per_cu(block, m->plan.noisy);
     for (int wpc : {1, 2, 4, 8}) {
       if (wpc > maxb) continue;
       if ((e = mpmi::multi_plan(m->plan, block, ncu * wpc)) != hipSuccess) break;
@@ -676,10 +673,10 @@ mpmi_status mpmi_proposal_tick(mpmi_ctx ctx, const void* model, const uint16_t* 
   if (e == hipSuccess) e = mpmi::launch_mlp_forward(w_bf16, w_f32, in_mean, in_std, row, 1, head, work, st);
   if (e == hipSuccess) e = mpmi::launch_mdn_sample(model, head, pd.n_cand, pd.seed, pd.tick, pd.loop, cand_work, st);
   void* slot = (char*)ctx->slots + (size_t)pd.loop * mpmi::slot_bytes();
-  if (e == hipSuccess) e = mpmi::launch_tick(sys.basis, model, pd, x_t, u_user, cand_work, slot, out, nullptr, nullptr, st);
+  if (e == hipSuccess) e = mpmi::launch_tick(sys, model, pd, x_t, u_user, cand_work, slot, out, nullptr, nullptr, st);
   void* slot2 = (char*)ctx->slots + (size_t)fallback->loop * mpmi::slot_bytes();
   if (e == hipSuccess)
-    e = mpmi::launch_tick(sys.basis, model, *fallback, x_t, u_user, nullptr, slot2, out, nullptr, nullptr, st, out);
+    e = mpmi::launch_tick(sys, model, *fallback, x_t, u_user, nullptr, slot2, out, nullptr, nullptr, st, out);
   return check_hip(ctx, e, "mpmi_proposal_tick launch");
 }
 

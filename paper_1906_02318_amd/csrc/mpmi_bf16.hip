@@ -38,16 +38,20 @@ struct RecheckList {
 
 // true if some constraint margin of x is within eps of zero (either side).
 __device__ __forceinline__ bool near_boundary(const ModelDev* __restrict__ md, const float* x) {
+  const ConstSafety* sc = safety_of(md);
   bool near = false;
-  const int nb = md->sys.n_box;
-  for (int b = 0; b < nb; ++b) {
-    const float mg = md->bb_lim[b] - fabsf(pick<6>(x, md->sys.box_index[b]));
-    near |= fabsf(mg) < md->sys.eps_box[b];
+  const int nb = sc->n_box;
+#pragma unroll
+  for (int b = 0; b < MPMI_MAX_BOX; ++b) {
+    if (b < nb) {
+      const float mg = sc->bb_lim[b] - fabsf(pick<6>(x, sc->box_index[b]));
+      near |= fabsf(mg) < md->sys.eps_box[b];
+    }
   }
-  if (md->sys.has_track) {
+  if (sc->has_track) {
     float rho;
-    const float rc = track_centre(md, x, &rho);
-    near |= fabsf(md->trk_lim - fabsf(rho - rc)) < md->sys.eps_track;
+    const float rc = track_centre(sc, x, &rho);
+    near |= fabsf(sc->trk_lim - fabsf(rho - rc)) < md->sys.eps_track;
   }
   return near;
 }
@@ -241,7 +245,7 @@ recheck_race_car_kernel(const ModelDev* __restrict__ md, GenParams gp, int H, co
   for (int e0 = blockIdx.x * blockDim.x; e0 < count; e0 += stride) {
     const int e = e0 + threadIdx.x;
     const int c = e < count ? rl->idx[e] : gp.n_cand + 1;  // past the end: an invalid lane
-    const CandResult r = evaluate_candidate<MPMI_BASIS_RACE_CAR>(md, sK, gp, H, x_t, u_user, cand, c, fv_out,
+    const CandResult r = evaluate_candidate<MPMI_BASIS_RACE_CAR, false>(md, sK, gp, H, x_t, u_user, cand, c, fv_out,
                                                                  nullptr);
     ks = r.ks < ks ? r.ks : ks;
     kf = r.kf < kf ? r.kf : kf;

@@ -11,7 +11,8 @@
 namespace mpmi {
 
 constexpr uint32_t kModelMagic = 0x4d504d49u;  // "MPMI"
-constexpr int kMaxHarm = 8;                     // highest track frequency
+constexpr int kMaxHarm = 8;
+constexpr int kStepWords = 168;  // per-step K table (race car: 27 rows x 6)                     // highest track frequency
 constexpr uint64_t kGoldenGamma = 0x9E3779B97F4A7C15ull;
 
 // BF16X3 operand tiles of the residual operator R = K - E (E copies the state
@@ -34,6 +35,20 @@ __host__ __device__ inline uint32_t bf16_bits_rne_u(float f) {
   return (b + 0x7fffu + ((b >> 16) & 1u)) >> 16;
 }
 
+// Constraint constants read at every prediction step (Sec. IV-B checks with
+// the Sec. V-C-1 inflation), contiguous so that a step fetches them with two
+// scalar loads.  Track coefficients above the model's highest harmonic are 0.
+struct SafetyConsts {
+  float bb_lim[MPMI_MAX_BOX];        // box_bound - box_infl
+  int32_t box_index[MPMI_MAX_BOX];   // state component of each box constraint
+  int32_t n_box;
+  int32_t has_track;
+  int32_t hmax;                      // highest track harmonic (degree of P)
+  float trk_lim;                     // track_half - track_infl
+  float trk_p[kMaxHarm + 1];         // r_c = P(cos phi) + sin phi * Q(cos phi): P coefficients
+  float trk_q[kMaxHarm];             // Q coefficients (monomial, ascending powers)
+};
+
 // Packed model: everything a rollout reads, in one device blob.
 struct alignas(256) ModelDev {
   mpmi_system sys;
@@ -42,15 +57,13 @@ struct alignas(256) ModelDev {
   int32_t n;            // state size
   int32_t m;            // input size
   int32_t state_feat0;  // index of feature w_0 = x_0 in psi (E's first row)
-  int32_t hmax;         // highest track harmonic used (0 = no track)
   int32_t has_noise;    // any noise_sigma > 0
   int32_t pad0;
-  float bb_lim[MPMI_MAX_BOX];     // box_bound - box_infl
-  float trk_lim;                  // track_half - track_infl
-  float trk_p[kMaxHarm + 1];      // r_c = P(cos phi) + sin phi * Q(cos phi): P coefficients
-  float trk_q[kMaxHarm];          // Q coefficients (monomial, ascending powers)
+  int32_t pad1;
+  alignas(64) SafetyConsts safe;
   float half_inv[MPMI_MAX_INPUT]; // 2 / (u_hi - u_lo)
   float K[MPMI_MAX_DIM][8];       // FP32 K, row = feature, col = state component
+  float Kstep[kStepWords];        // race car: the rows of K the step reads, in its order
   uint32_t Rhi[kRTileWords];      // BF16 hi split of R, MFMA B-operand order
   uint32_t Rlo[kRTileWords];      // BF16 lo split of R
 };
@@ -197,6 +210,18 @@ constexpr int kRcStepOff = 384;
 constexpr int kRcStepRows = 27;
 constexpr int kLdsKFloat4 = 137;  // 546 floats rounded up to float4
 
+// Row of K feeding row q of the race-car step table: the 21 state-state
+// quadratic features (k <= l < 6), then sp*vx, sp*vy, sp*r, cp*vx, cp*vy, cp*r.
+__host__ __device__ inline int rc_step_row(int q) {
+  if (q < 21) {
+    int k = 0, r = q;
+    while (r >= 6 - k) { r -= 6 - k; ++k; }
+    return quad_index(k, k + r, 8);
+  }
+  const int trig_rows[6] = {49, 50, 51, 53, 54, 55};
+  return trig_rows[q - 21];
+}
+
 template <int BASIS>
 __device__ __forceinline__ void stage_K(const ModelDev* __restrict__ md, float4* sK) {
   float* f = reinterpret_cast<float*>(sK);
@@ -213,22 +238,15 @@ __device__ __forceinline__ void stage_K(const ModelDev* __restrict__ md, float4*
     }
   } else {
     for (int e = t; e < 64 * 6; e += nt) f[e] = md->K[e / 6][e % 6];
-    for (int e = t; e < kRcStepRows * 6; e += nt) {
-      const int q = e / 6, j = e % 6;
-      int row;
-      if (q < 21) {
-        int k = 0, r = q;
-        while (r >= 6 - k) { r -= 6 - k; ++k; }
-        row = quad_index(k, k + r, 8);
-      } else {
-        constexpr int trig_rows[6] = {49, 50, 51, 53, 54, 55};  // sp*{vx,vy,r}, cp*{vx,vy,r}
-        row = trig_rows[q - 21];
-      }
-      f[kRcStepOff + e] = md->K[row][j];
-    }
+    for (int e = t; e < kRcStepRows * 6; e += nt) f[kRcStepOff + e] = md->Kstep[e];
   }
   __syncthreads();
 }
+
+// Read-only model data seen through the constant address space, so uniform
+// loads from it become scalar loads whose results feed VALU operands directly.
+typedef const __attribute__((address_space(4))) float ConstF;
+typedef const __attribute__((address_space(4))) SafetyConsts ConstSafety;
 
 __device__ __forceinline__ const float4* opaque_lds(const float4* sK) {
   int off = 0;
@@ -374,13 +392,11 @@ struct Stepper<MPMI_BASIS_RACE_CAR> {
       y[0] = fmaf(p1, b.z, y[0]); y[1] = fmaf(p1, b.w, y[1]); y[2] = fmaf(p1, c.x, y[2]);
       y[3] = fmaf(p1, c.y, y[3]); y[4] = fmaf(p1, c.z, y[4]); y[5] = fmaf(p1, c.w, y[5]);
     }
-    {
-      const float4 a = kk[39];
-      const float2 b = *reinterpret_cast<const float2*>(kk + 40);
-      const float p0 = p[26];
-      y[0] = fmaf(p0, a.x, y[0]); y[1] = fmaf(p0, a.y, y[1]); y[2] = fmaf(p0, a.z, y[2]);
-      y[3] = fmaf(p0, a.w, y[3]); y[4] = fmaf(p0, b.x, y[4]); y[5] = fmaf(p0, b.y, y[5]);
-    }
+    const float4 a = kk[39];
+    const float2 b = *reinterpret_cast<const float2*>(kk + 40);
+    const float p0 = p[26];
+    y[0] = fmaf(p0, a.x, y[0]); y[1] = fmaf(p0, a.y, y[1]); y[2] = fmaf(p0, a.z, y[2]);
+    y[3] = fmaf(p0, a.w, y[3]); y[4] = fmaf(p0, b.x, y[4]); y[5] = fmaf(p0, b.y, y[5]);
 #pragma unroll
     for (int j = 0; j < 6; ++j) x[j] = y[j];
   }
@@ -403,38 +419,51 @@ __device__ __forceinline__ float pick(const float* x, int idx) {
 // coefficients formed once per model in FP64; cos phi and sin phi come from
 // one reciprocal square root (rho = 0 or an infinite coordinate gives NaN,
 // i.e. unsafe; the centreline radius exceeds the half-width there anyway).
-__device__ __forceinline__ float track_centre(const ModelDev* __restrict__ md, const float* x, float* rho) {
+// Horner runs over the full coefficient arrays: the zero coefficients above
+// the model's highest harmonic leave every partial sum exactly as it is, and
+// the fixed trip count lets all coefficients arrive in one scalar-load batch.
+__device__ __forceinline__ float track_centre(const ConstSafety* sc, const float* x, float* rho) {
   const float r2 = fmaf(x[0], x[0], x[1] * x[1]);
   const float inv = __builtin_amdgcn_rsqf(r2);
   *rho = r2 * inv;
   const float c1 = x[0] * inv, s1 = x[1] * inv;
-  const int hmax = md->hmax;
-  float P = md->trk_p[hmax];
-  for (int k = hmax - 1; k >= 0; --k) P = fmaf(P, c1, md->trk_p[k]);
-  float Q = 0.0f;
-  if (hmax >= 1) {
-    Q = md->trk_q[hmax - 1];
-    for (int k = hmax - 2; k >= 0; --k) Q = fmaf(Q, c1, md->trk_q[k]);
-  }
+  float P = sc->trk_p[kMaxHarm];
+#pragma unroll
+  for (int k = kMaxHarm - 1; k >= 0; --k) P = fmaf(P, c1, sc->trk_p[k]);
+  float Q = sc->trk_q[kMaxHarm - 1];
+#pragma unroll
+  for (int k = kMaxHarm - 2; k >= 0; --k) Q = fmaf(Q, c1, sc->trk_q[k]);
   return fmaf(s1, Q, P);
+}
+
+// The model's constraint constants as scalar-load operands, re-fetched at
+// each call (not held in registers across the horizon).
+__device__ __forceinline__ const ConstSafety* safety_of(const ModelDev* __restrict__ md) {
+  int off = 0;
+  asm volatile("" : "+s"(off));
+  return (const ConstSafety*)(uintptr_t)&md->safe + off;
 }
 
 // Least margin over all constraints of state x (NaN if any margin is NaN, so
 // that "safe" = (margin > 0) rejects NaN states).
 template <int NS>
 __device__ __forceinline__ float min_margin(const ModelDev* __restrict__ md, const float* x) {
+  const ConstSafety* sc = safety_of(md);
   float mm = INFINITY;
   bool nan = false;
-  const int nb = md->sys.n_box;
-  for (int b = 0; b < nb; ++b) {
-    const float mg = md->bb_lim[b] - fabsf(pick<NS>(x, md->sys.box_index[b]));
-    nan |= (mg != mg);
-    mm = fminf(mm, mg);
+  const int nb = sc->n_box;
+#pragma unroll
+  for (int b = 0; b < MPMI_MAX_BOX; ++b) {
+    if (b < nb) {
+      const float mg = sc->bb_lim[b] - fabsf(pick<NS>(x, sc->box_index[b]));
+      nan |= (mg != mg);
+      mm = fminf(mm, mg);
+    }
   }
-  if (md->sys.has_track) {
+  if (sc->has_track) {
     float rho;
-    const float rc = track_centre(md, x, &rho);
-    const float mg = md->trk_lim - fabsf(rho - rc);
+    const float rc = track_centre(sc, x, &rho);
+    const float mg = sc->trk_lim - fabsf(rho - rc);
     nan |= (mg != mg);
     mm = fminf(mm, mg);
   }

@@ -17,7 +17,15 @@ size_t slot_bytes();
 
 hipError_t launch_pack(const mpmi_system& sys, int dim, int state_feat0, const double* K, void* model,
                        hipStream_t st);
-hipError_t launch_tick(int basis, const void* model, const mpmi_tick_desc& d, const float* x_t,
+// Process noise is drawn when a state component has a positive sigma (the
+// packed model's has_noise flag follows the same rule).
+inline bool system_noisy(const mpmi_system& s) {
+  for (int j = 0; j < s.n_state && j < 8; ++j)
+    if (s.noise_sigma[j] > 0.0f) return true;
+  return false;
+}
+
+hipError_t launch_tick(const mpmi_system& sys, const void* model, const mpmi_tick_desc& d, const float* x_t,
                        const float* u_user, const float* cand, void* slot, mpmi_selection* out,
                        int16_t* fv, float* traj, hipStream_t st, const mpmi_selection* gate = nullptr);
 hipError_t launch_rollout(int basis, const void* model, int Nc, int S, int H, const float* x0,
@@ -66,6 +74,7 @@ hipError_t launch_gemm_test(const uint16_t* A, const uint16_t* B, int M, int N, 
 struct WorkItem;
 struct MultiState;
 struct Slot;
+struct ModelDev;
 struct MultiPlan {
   int n_loops = 0;
   mpmi_loop_desc* d_loops = nullptr;  // device copy of the loop table
@@ -73,18 +82,23 @@ struct MultiPlan {
   WorkItem* d_work = nullptr;         // ordered (loop, tile) items
   MultiState* d_state = nullptr;      // work counter + exit counter
   Slot* d_slots = nullptr;            // one selection slot per loop
+  uint64_t* d_ticks = nullptr;        // per-loop tick counters (advanced on the device)
+  ModelDev* d_models = nullptr;       // copy of each distinct packed model
+  std::vector<const void*> model_src; // the packed models the copies were taken from
+  std::vector<int> model_of_loop;     // loop -> index into d_models
   size_t work_capacity = 0;
   int n_work = 0;
   int block = 256;
   int grid = 0;
   std::vector<mpmi_loop_desc> host;
   std::vector<int> basis;
+  bool noisy = false;  // some loop's model draws process noise
 };
 hipError_t multi_alloc(MultiPlan& p);
 void multi_free(MultiPlan& p);
 hipError_t multi_plan(MultiPlan& p, int block, int grid);
 hipError_t multi_launch(const MultiPlan& p, hipStream_t st);
-int multi_max_blocks_per_cu(int block);
+int multi_max_blocks_per_cu(int block, bool noisy);
 int device_cu_count();
 
 }  // namespace mpmi

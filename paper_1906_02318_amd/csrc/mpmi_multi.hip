@@ -8,6 +8,13 @@
 // loop's last tile writes that loop's selection and advances its tick
 // counter; the last workgroup to leave resets the work counter, so the next
 // launch (or graph replay) starts clean without a memset.
+//
+// Everything the kernel reads per item is behind read-only kernel arguments:
+// the loop table (the advancing tick counters live in an array of their own)
+// and the plan's copy of each distinct packed model.  With the work-item
+// index made wave-uniform, every per-loop and per-model field is a scalar
+// load the compiler may re-issue instead of holding it, which leaves the
+// register budget to the prediction itself.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -22,6 +29,8 @@ namespace mpmi {
 struct WorkItem {
   uint32_t loop;
   uint32_t tile;
+  uint32_t model;  // index into the plan's model snapshot
+  uint32_t pad;
 };
 
 struct MultiState {
@@ -30,22 +39,23 @@ struct MultiState {
   unsigned int pad[62];
 };
 
+template <bool NOISE>
 __global__ void __launch_bounds__(1024)
-multi_kernel(mpmi_loop_desc* __restrict__ loops, const int* __restrict__ n_tiles,
-             const WorkItem* __restrict__ work, int n_work, MultiState* __restrict__ st,
-             Slot* __restrict__ slots) {
+multi_kernel(const mpmi_loop_desc* __restrict__ loops, const ModelDev* __restrict__ models,
+             const int* __restrict__ n_tiles, const WorkItem* __restrict__ work, int n_work,
+             MultiState* __restrict__ st, Slot* __restrict__ slots, uint64_t* __restrict__ ticks) {
   __shared__ float4 sK[kLdsKFloat4];
   __shared__ int s_item;
   const ModelDev* cached = nullptr;
   for (;;) {
     if (threadIdx.x == 0) s_item = (int)atomicAdd(&st->next, 1u);
     __syncthreads();
-    const int it = s_item;
+    const int it = __builtin_amdgcn_readfirstlane(s_item);
     __syncthreads();
     if (it >= n_work) break;
     const WorkItem w = work[it];
-    mpmi_loop_desc* L = &loops[w.loop];
-    const ModelDev* md = (const ModelDev*)L->model;
+    const mpmi_loop_desc* L = &loops[w.loop];
+    const ModelDev* md = models + w.model;
     const int basis = md->sys.basis;
     if (md != cached) {
       if (basis == MPMI_BASIS_RACE_CAR) stage_K<MPMI_BASIS_RACE_CAR>(md, sK);
@@ -55,7 +65,12 @@ multi_kernel(mpmi_loop_desc* __restrict__ loops, const int* __restrict__ n_tiles
     }
     GenParams gp;
     gp.seed = L->seed;
-    gp.tick = L->tick;
+    // Written below by the workgroup that completes this loop's tick; every
+    // tile of the loop reads it before that (the completing workgroup is the
+    // last of the loop's tiles to publish).
+    const uint64_t tk = ticks[w.loop];
+    gp.tick = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(tk >> 32)) << 32) |
+              (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)tk);
     gp.loop = (int32_t)w.loop;
     gp.gen = L->gen;
     gp.n_cand = L->n_cand;
@@ -66,19 +81,19 @@ multi_kernel(mpmi_loop_desc* __restrict__ loops, const int* __restrict__ n_tiles
     const int c = (int)w.tile * (int)blockDim.x + (int)threadIdx.x;
     CandResult r;
     if (basis == MPMI_BASIS_RACE_CAR)
-      r = evaluate_candidate<MPMI_BASIS_RACE_CAR>(md, sK, gp, H, L->x_t, L->u_user, L->cand, c,
-                                                  L->first_violation, nullptr);
+      r = evaluate_candidate<MPMI_BASIS_RACE_CAR, NOISE>(md, sK, gp, H, L->x_t, L->u_user, L->cand, c,
+                                                         L->first_violation, nullptr);
     else if (basis == MPMI_BASIS_BALANCE_BOT)
-      r = evaluate_candidate<MPMI_BASIS_BALANCE_BOT>(md, sK, gp, H, L->x_t, L->u_user, L->cand, c,
-                                                     L->first_violation, nullptr);
+      r = evaluate_candidate<MPMI_BASIS_BALANCE_BOT, NOISE>(md, sK, gp, H, L->x_t, L->u_user, L->cand, c,
+                                                            L->first_violation, nullptr);
     else
-      r = evaluate_candidate<MPMI_BASIS_LINEAR>(md, sK, gp, H, L->x_t, L->u_user, L->cand, c,
-                                                L->first_violation, nullptr);
+      r = evaluate_candidate<MPMI_BASIS_LINEAR, NOISE>(md, sK, gp, H, L->x_t, L->u_user, L->cand, c,
+                                                       L->first_violation, nullptr);
     Slot* slot = &slots[w.loop];
     if (reduce_and_publish(r.ks, r.kf, r.safe_counted, slot, (unsigned int)n_tiles[w.loop]) &&
         threadIdx.x == 0) {
       finalize<MPMI_MAX_INPUT>(md, gp, L->cand, L->u_user, H, slot, L->out);
-      L->tick = gp.tick + 1;
+      ticks[w.loop] = gp.tick + 1;
       __threadfence();
     }
   }
@@ -110,6 +125,21 @@ hipError_t multi_alloc(MultiPlan& p) {
   if ((e = hipMalloc(&p.d_work, sizeof(WorkItem) * (cap > 0 ? cap : 1))) != hipSuccess) return e;
   if ((e = hipMalloc(&p.d_state, sizeof(MultiState))) != hipSuccess) return e;
   if ((e = hipMalloc(&p.d_slots, sizeof(Slot) * p.n_loops)) != hipSuccess) return e;
+  if ((e = hipMalloc(&p.d_ticks, sizeof(uint64_t) * p.n_loops)) != hipSuccess) return e;
+  p.model_of_loop.assign(p.n_loops, 0);
+  p.model_src.clear();
+  for (int l = 0; l < p.n_loops; ++l) {
+    const void* m = p.host[l].model;
+    int k = 0;
+    while (k < (int)p.model_src.size() && p.model_src[k] != m) ++k;
+    if (k == (int)p.model_src.size()) p.model_src.push_back(m);
+    p.model_of_loop[l] = k;
+  }
+  if ((e = hipMalloc(&p.d_models, sizeof(ModelDev) * p.model_src.size())) != hipSuccess) return e;
+  std::vector<uint64_t> tk(p.n_loops);
+  for (int l = 0; l < p.n_loops; ++l) tk[l] = p.host[l].tick;
+  if ((e = hipMemcpy(p.d_ticks, tk.data(), sizeof(uint64_t) * p.n_loops, hipMemcpyHostToDevice)) != hipSuccess)
+    return e;
   if ((e = hipMemcpy(p.d_loops, p.host.data(), sizeof(mpmi_loop_desc) * p.n_loops, hipMemcpyHostToDevice)) !=
       hipSuccess)
     return e;
@@ -129,16 +159,22 @@ void multi_free(MultiPlan& p) {
   if (p.d_work) (void)hipFree(p.d_work);
   if (p.d_state) (void)hipFree(p.d_state);
   if (p.d_slots) (void)hipFree(p.d_slots);
+  if (p.d_ticks) (void)hipFree(p.d_ticks);
+  if (p.d_models) (void)hipFree(p.d_models);
   p.d_loops = nullptr;
   p.d_ntiles = nullptr;
   p.d_work = nullptr;
   p.d_state = nullptr;
   p.d_slots = nullptr;
+  p.d_ticks = nullptr;
+  p.d_models = nullptr;
 }
 
-int multi_max_blocks_per_cu(int block) {
+int multi_max_blocks_per_cu(int block, bool noisy) {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, multi_kernel, block, 0) != hipSuccess) return 1;
+  const hipError_t e = noisy ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, multi_kernel<true>, block, 0)
+                             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, multi_kernel<false>, block, 0);
+  if (e != hipSuccess) return 1;
   return nb > 0 ? nb : 1;
 }
 
@@ -168,21 +204,31 @@ hipError_t multi_plan(MultiPlan& p, int block, int grid) {
   std::vector<WorkItem> items;
   items.reserve(total);
   for (int l : order)
-    for (int t = 0; t < nt[l]; ++t) items.push_back(WorkItem{(uint32_t)l, (uint32_t)t});
+    for (int t = 0; t < nt[l]; ++t) items.push_back(WorkItem{(uint32_t)l, (uint32_t)t, (uint32_t)p.model_of_loop[l], 0u});
+  // Snapshot of the packed models (re-taken at every re-plan).
+  for (size_t k = 0; k < p.model_src.size(); ++k) {
+    e0 = hipMemcpy(p.d_models + k, p.model_src[k], sizeof(ModelDev), hipMemcpyDeviceToDevice);
+    if (e0 != hipSuccess) return e0;
+  }
   hipError_t e = hipMemcpy(p.d_work, items.data(), sizeof(WorkItem) * items.size(), hipMemcpyHostToDevice);
   if (e != hipSuccess) return e;
   e = hipMemcpy(p.d_ntiles, nt.data(), sizeof(int) * p.n_loops, hipMemcpyHostToDevice);
   if (e != hipSuccess) return e;
   p.n_work = (int)items.size();
   p.block = block;
-  const int full = device_cu_count() * multi_max_blocks_per_cu(block);
+  const int full = device_cu_count() * multi_max_blocks_per_cu(block, p.noisy);
   p.grid = grid > 0 ? grid : full;
   if (p.grid > p.n_work) p.grid = p.n_work > 0 ? p.n_work : 1;
   return hipDeviceSynchronize();
 }
 
 hipError_t multi_launch(const MultiPlan& p, hipStream_t st) {
-  multi_kernel<<<p.grid, p.block, 0, st>>>(p.d_loops, p.d_ntiles, p.d_work, p.n_work, p.d_state, p.d_slots);
+  if (p.noisy)
+    multi_kernel<true><<<p.grid, p.block, 0, st>>>(p.d_loops, p.d_models, p.d_ntiles, p.d_work, p.n_work,
+                                                   p.d_state, p.d_slots, p.d_ticks);
+  else
+    multi_kernel<false><<<p.grid, p.block, 0, st>>>(p.d_loops, p.d_models, p.d_ntiles, p.d_work, p.n_work,
+                                                    p.d_state, p.d_slots, p.d_ticks);
   return hipGetLastError();
 }
 

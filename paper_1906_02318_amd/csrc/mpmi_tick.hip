@@ -20,7 +20,7 @@ namespace mpmi {
 // ---------------------------------------------------------------------------
 // Fused tick, FP32
 // ---------------------------------------------------------------------------
-template <int BASIS>
+template <int BASIS, bool NOISE>
 __global__ void __launch_bounds__(1024)
 tick_fp32_kernel(const ModelDev* __restrict__ md, GenParams gp, int H, const float* __restrict__ x_t,
                  const float* __restrict__ u_user, const float* __restrict__ cand,
@@ -34,7 +34,7 @@ tick_fp32_kernel(const ModelDev* __restrict__ md, GenParams gp, int H, const flo
   __shared__ float4 sK[kLdsKFloat4];
   stage_K<BASIS>(md, sK);
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  const CandResult r = evaluate_candidate<BASIS>(md, sK, gp, H, x_t, u_user, cand, c, fv_out, traj);
+  const CandResult r = evaluate_candidate<BASIS, NOISE>(md, sK, gp, H, x_t, u_user, cand, c, fv_out, traj);
   if (reduce_and_publish(r.ks, r.kf, r.safe_counted, slot, gridDim.x) && threadIdx.x == 0)
     finalize<MS>(md, gp, cand, u_user, H, slot, out);
 }
@@ -140,6 +140,13 @@ __global__ void pack_kernel(mpmi_system sys, int dim, int state_feat0, const dou
     const int f = e >> 3, j = e & 7;
     md->K[f][j] = (f < dim && j < n) ? (float)K[(size_t)f * n + j] : 0.0f;
   }
+  // Race-car step table (the rows the per-step contraction reads, in order).
+  for (int e = t; e < kStepWords; e += blockDim.x) {
+    const int q = e / 6, j = e % 6;
+    md->Kstep[e] = (sys.basis == MPMI_BASIS_RACE_CAR && q < kRcStepRows && j < n)
+                       ? (float)K[(size_t)rc_step_row(q) * n + j]
+                       : 0.0f;
+  }
   // Residual R = K - E as BF16 hi/lo splits in B-operand order of a 16x16x32
   // MFMA: lane l holds column (l & 15), rows kb*32 + (l >> 4)*8 + [0..8).
   for (int e = t; e < 2 * 64 * 8; e += blockDim.x) {
@@ -167,8 +174,11 @@ __global__ void pack_kernel(mpmi_system sys, int dim, int state_feat0, const dou
     md->m = sys.n_input;
     md->state_feat0 = state_feat0;
     for (int b = 0; b < MPMI_MAX_BOX; ++b)
-      md->bb_lim[b] = (b < sys.n_box) ? (float)((double)sys.box_bound[b] - (double)sys.box_infl[b]) : 0.0f;
-    md->trk_lim = (float)((double)sys.track_half - (double)sys.track_infl);
+      md->safe.bb_lim[b] = (b < sys.n_box) ? (float)((double)sys.box_bound[b] - (double)sys.box_infl[b]) : 0.0f;
+    for (int b = 0; b < MPMI_MAX_BOX; ++b) md->safe.box_index[b] = (b < sys.n_box) ? sys.box_index[b] : 0;
+    md->safe.n_box = sys.n_box;
+    md->safe.has_track = sys.has_track;
+    md->safe.trk_lim = (float)((double)sys.track_half - (double)sys.track_infl);
     // r_c(phi) = r0 + sum_k a_k sin(f_k phi + p_k)
     //          = r0 + sum_k a_k [cos p_k sin(f_k phi) + sin p_k cos(f_k phi)]
     //          = r0 + sum_k a_k [cos p_k sin(phi) U_{f_k-1}(c) + sin p_k T_{f_k}(c)],  c = cos phi,
@@ -200,9 +210,9 @@ __global__ void pack_kernel(mpmi_system sys, int dim, int state_feat0, const dou
         hmax = f > hmax ? f : hmax;
       }
     }
-    for (int k = 0; k <= kMaxHarm; ++k) md->trk_p[k] = (float)P[k];
-    for (int k = 0; k < kMaxHarm; ++k) md->trk_q[k] = (float)Q[k];
-    md->hmax = hmax;
+    for (int k = 0; k <= kMaxHarm; ++k) md->safe.trk_p[k] = (float)P[k];
+    for (int k = 0; k < kMaxHarm; ++k) md->safe.trk_q[k] = (float)Q[k];
+    md->safe.hmax = hmax;
     int noisy = 0;
     for (int j = 0; j < 8; ++j) noisy |= (j < n && sys.noise_sigma[j] > 0.0f) ? 1 : 0;
     md->has_noise = noisy;
@@ -236,7 +246,17 @@ hipError_t launch_pack(const mpmi_system& sys, int dim, int state_feat0, const d
   return hipGetLastError();
 }
 
-hipError_t launch_tick(int basis, const void* model, const mpmi_tick_desc& d, const float* x_t,
+template <int BASIS>
+static void tick_dispatch(bool noisy, unsigned grid, int block, hipStream_t st, const ModelDev* md,
+                          const GenParams& gp, int H, const float* x_t, const float* u_user, const float* cand,
+                          Slot* sl, mpmi_selection* out, int16_t* fv, float* traj, const mpmi_selection* gate) {
+  if (noisy)
+    tick_fp32_kernel<BASIS, true><<<grid, block, 0, st>>>(md, gp, H, x_t, u_user, cand, sl, out, fv, traj, gate);
+  else
+    tick_fp32_kernel<BASIS, false><<<grid, block, 0, st>>>(md, gp, H, x_t, u_user, cand, sl, out, fv, traj, gate);
+}
+
+hipError_t launch_tick(const mpmi_system& sys, const void* model, const mpmi_tick_desc& d, const float* x_t,
                        const float* u_user, const float* cand, void* slot, mpmi_selection* out,
                        int16_t* fv, float* traj, hipStream_t st, const mpmi_selection* gate) {
   const GenParams gp = make_gen(d);
@@ -244,15 +264,19 @@ hipError_t launch_tick(int basis, const void* model, const mpmi_tick_desc& d, co
   const unsigned grid = blocks_for((long long)d.n_cand + 1, block);
   const ModelDev* md = (const ModelDev*)model;
   Slot* sl = (Slot*)slot;
-  switch (basis) {
+  const bool noisy = system_noisy(sys);
+  switch (sys.basis) {
     case MPMI_BASIS_LINEAR:
-      tick_fp32_kernel<MPMI_BASIS_LINEAR><<<grid, block, 0, st>>>(md, gp, d.horizon, x_t, u_user, cand, sl, out, fv, traj, gate);
+      tick_dispatch<MPMI_BASIS_LINEAR>(noisy, grid, block, st, md, gp, d.horizon, x_t, u_user, cand, sl, out, fv,
+                                       traj, gate);
       break;
     case MPMI_BASIS_BALANCE_BOT:
-      tick_fp32_kernel<MPMI_BASIS_BALANCE_BOT><<<grid, block, 0, st>>>(md, gp, d.horizon, x_t, u_user, cand, sl, out, fv, traj, gate);
+      tick_dispatch<MPMI_BASIS_BALANCE_BOT>(noisy, grid, block, st, md, gp, d.horizon, x_t, u_user, cand, sl, out,
+                                            fv, traj, gate);
       break;
     default:
-      tick_fp32_kernel<MPMI_BASIS_RACE_CAR><<<grid, block, 0, st>>>(md, gp, d.horizon, x_t, u_user, cand, sl, out, fv, traj, gate);
+      tick_dispatch<MPMI_BASIS_RACE_CAR>(noisy, grid, block, st, md, gp, d.horizon, x_t, u_user, cand, sl, out, fv,
+                                         traj, gate);
       break;
   }
   return hipGetLastError();

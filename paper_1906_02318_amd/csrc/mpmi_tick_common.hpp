@@ -131,8 +131,10 @@ struct CandResult {
 
 // Prediction of candidate c with early exit at the first unsafe state
 // (Alg. 2 inner loop), then its selection keys.  Lanes with c >= Nc return
-// empty keys.  fv_out / traj are optional.
-template <int BASIS>
+// empty keys.  fv_out / traj are optional.  NOISE compiles the process-noise
+// draw in (models with a positive sigma); noise-free instances carry none of
+// its registers (a noisy instance still skips the draw for a noise-free model).
+template <int BASIS, bool NOISE>
 __device__ __forceinline__ CandResult evaluate_candidate(const ModelDev* __restrict__ md, const float4* sK,
                                                          const GenParams& gp, int H,
                                                          const float* __restrict__ x_t,
@@ -143,19 +145,19 @@ __device__ __forceinline__ CandResult evaluate_candidate(const ModelDev* __restr
   const int Nc = gp.n_cand + 1;
   const bool valid = c < Nc;
   const int n = md->n, S = gp.n_seg;
-  float x[NS], u[MS], u0[MS];
+  float x[NS], u[MS];
 #pragma unroll
   for (int j = 0; j < NS; ++j) x[j] = (j < n) ? x_t[j] : 0.0f;
 #pragma unroll
-  for (int j = 0; j < MS; ++j) {
-    u0[j] = (valid && j < md->m) ? cand_value(gp, md, cand, u_user, c, 0, j) : 0.0f;
-    u[j] = u0[j];
-  }
+  for (int j = 0; j < MS; ++j) u[j] = (valid && j < md->m) ? cand_value(gp, md, cand, u_user, c, 0, j) : 0.0f;
+  // The cost needs only the first segment's input: taken now, so a single
+  // float instead of the input vector stays live across the horizon.
+  const float cst = valid ? cost_of<MS>(md, u, u_user) : 0.0f;
   Stepper<BASIS> stp;
   stp.set_input(md, sK, u);
   int fv = H + 1;
   if (valid) {
-    const bool noisy = md->has_noise != 0;
+    const bool noisy = NOISE && md->has_noise != 0;
     const uint64_t nprefix = noisy ? hash_prefix(gp.seed, gp.tick, (uint64_t)(uint32_t)gp.loop, (uint64_t)c) : 0ull;
     int gcur = 0;
     for (int s = 1; s <= H; ++s) {
@@ -180,7 +182,6 @@ __device__ __forceinline__ CandResult evaluate_candidate(const ModelDev* __restr
     }
     if (fv_out) fv_out[c] = (int16_t)fv;
   }
-  const float cst = valid ? cost_of<MS>(md, u0, u_user) : 0.0f;
   const bool safe = valid && fv == H + 1;
   CandResult r;
   r.ks = safe ? safe_key(cst, c) : kKeyNone;

@@ -261,12 +261,14 @@ def model_bytes() -> int:
     return int(library().mpmi_model_bytes())
 
 
-def mpmi_model_pack(ctx: Context, system: System, K: torch.Tensor, stream=None) -> Model:
+def mpmi_model_pack(ctx: Context, system: System, K: torch.Tensor, stream=None, into: "Model" = None) -> Model:
+    """Packs (system, K) into a new model, or in place into `into` (same blob)."""
     _need(K, "K", torch.float64, device=ctx.device)
-    nbytes = model_bytes()
-    blob = torch.empty(nbytes + 256, dtype=torch.uint8, device=ctx.device)
-    base = blob.data_ptr()
-    ptr = (base + 255) // 256 * 256
+    if into is None:
+        blob = torch.empty(model_bytes() + 256, dtype=torch.uint8, device=ctx.device)
+        ptr = (blob.data_ptr() + 255) // 256 * 256
+    else:
+        blob, ptr = into.blob, into.ptr
     ctx.check(ctx.lib.mpmi_model_pack(ctx.handle, ctypes.byref(system), _ptr(K), ctypes.c_void_p(ptr),
                                       _stream(stream)))
     return Model(blob=blob, ptr=ptr, system=system)

@@ -124,3 +124,39 @@ def test_multi_autotune_and_block_sizes_deterministic(setup):
     multi.tick()
     torch.cuda.synchronize()
     assert multi_records(loops) == single_tick_records(ctx, loops, meta, systems, offs[0])
+
+
+def test_multi_model_snapshot_taken_at_replan(setup):
+    """The plan reads its own copy of each packed model: a model re-packed in
+    place is used from the next re-plan on, not before."""
+    ctx, multi, loops, meta, systems = setup
+    so, Kr, mr = systems["rc"]
+    ticks = multi.ticks()
+    off = ticks[0] - meta[0]["tick0"]
+    K2 = Kr.copy()
+    K2[0, :] *= 0.5  # another constant-feature row: different predictions
+    try:
+        mpmi.mpmi_model_pack(ctx, mpmi.race_car_system(W.track_dict(W.rc_track())), dev(K2, torch.float64), into=mr)
+        torch.cuda.synchronize()
+        multi.tick()
+        torch.cuda.synchronize()
+        before = multi_records(loops)
+        mpmi.mpmi_model_pack(ctx, mpmi.race_car_system(W.track_dict(W.rc_track())), dev(Kr, torch.float64), into=mr)
+        torch.cuda.synchronize()
+        assert before == single_tick_records(ctx, loops, meta, systems, off), "re-pack seen before re-plan"
+        mpmi.mpmi_model_pack(ctx, mpmi.race_car_system(W.track_dict(W.rc_track())), dev(K2, torch.float64), into=mr)
+        torch.cuda.synchronize()
+        multi.set_config(multi.config()["block"])
+        multi.tick()
+        torch.cuda.synchronize()
+        after = multi_records(loops)
+        assert after == single_tick_records(ctx, loops, meta, systems, off + 1), "re-plan did not take the new model"
+        rc_loops = [i for i, mt in enumerate(meta) if mt["kind"] == "rc"]
+        mpmi.mpmi_model_pack(ctx, mpmi.race_car_system(W.track_dict(W.rc_track())), dev(Kr, torch.float64), into=mr)
+        torch.cuda.synchronize()
+        old = single_tick_records(ctx, loops, meta, systems, off + 1)
+        assert any(after[i] != old[i] for i in rc_loops), "K2 changed no race-car selection"
+    finally:
+        mpmi.mpmi_model_pack(ctx, mpmi.race_car_system(W.track_dict(W.rc_track())), dev(Kr, torch.float64), into=mr)
+        torch.cuda.synchronize()
+        multi.set_config(multi.config()["block"])
