@@ -274,9 +274,9 @@ mpmi_status mpmi_generate_candidates(mpmi_ctx ctx, const void* model,
  *
  * Each loop runs Alg. 2 on its own model, state, user input, candidate count
  * and horizon.  The (loop, tile) work items of all loops, ordered
- * longest-processing-time first (horizon x per-step cost), are taken from an
- * atomic counter by a persistent grid; each loop's selection is finalised by
- * the workgroup that completes its last tile.  Nothing is allocated and no
+ * longest-processing-time first (horizon x per-step cost), run as one
+ * workgroup each, which the hardware dispatches in list order; each loop's
+ * selection is finalised by the workgroup that completes its last tile.  Nothing is allocated and no
  * host synchronisation happens per tick, so a tick can be captured once in a
  * HIP graph (mpmi_multi_graph) and replayed.
  * ------------------------------------------------------------------------- */
@@ -305,8 +305,9 @@ typedef struct mpmi_loop_desc {
 } mpmi_loop_desc;
 
 /* Launch shape: `block` threads per workgroup = candidates per tile
- * (64..1024, multiple of 64); `grid` persistent workgroups (0 = library
- * default: enough to fill every compute unit). */
+ * (64..1024, multiple of 64).  `grid` must be 0 on input; on output
+ * (mpmi_multi_get_config, mpmi_multi_autotune) it is the launch's workgroup
+ * count, one per work item. */
 typedef struct mpmi_multi_config {
   int32_t block;
   int32_t grid;
@@ -315,8 +316,8 @@ typedef struct mpmi_multi_config {
 typedef struct mpmi_multi_s* mpmi_multi;
 
 /* Validates the loops, copies them to device memory, builds the ordered
- * work list for `cfg` (NULL = block 256, default grid) and allocates the
- * per-loop selection slots.  Synchronous. */
+ * work list for `cfg` (NULL = block 256) and allocates the per-loop
+ * selection slots.  Synchronous. */
 mpmi_status mpmi_multi_create(mpmi_ctx ctx, const mpmi_loop_desc* loops /* host */, int32_t n_loops,
                               const mpmi_multi_config* cfg /* host, may be NULL */, mpmi_multi* out);
 void mpmi_multi_destroy(mpmi_multi multi);
@@ -334,17 +335,18 @@ mpmi_status mpmi_multi_get_ticks(mpmi_ctx ctx, mpmi_multi multi, uint64_t* ticks
 /* One tick of every loop: one kernel launch on `stream`. */
 mpmi_status mpmi_multi_tick(mpmi_ctx ctx, mpmi_multi multi, void* stream);
 
-/* Autotuner: times `reps` ticks (HIP events on `stream`) for each launch
- * shape in the library's search space (block 64..512, grid 1..8 workgroups
- * per compute unit), keeps the fastest, and reports it in *best and its mean
- * tick time in *best_ms (host, may be NULL).  The timed ticks are real ticks:
+/* Autotuner: times `reps` ticks (HIP events on `stream`) for each block size
+ * in 64, 128, 256, 512, 1024, keeps the fastest, and reports it in *best and
+ * its mean tick time in *best_ms (host, may be NULL).  The timed ticks are real ticks:
  * they write selections and advance tick counters. */
 mpmi_status mpmi_multi_autotune(mpmi_ctx ctx, mpmi_multi multi, int32_t reps, mpmi_multi_config* best /* host */,
                                 float* best_ms /* host */, void* stream);
 
 /* Captures one mpmi_multi_tick into an instantiated HIP graph (*graph_exec,
  * a hipGraphExec_t).  Replays read x_t / u_user at the loops' fixed
- * pointers, so the caller updates those buffers between replays. */
+ * pointers, so the caller updates those buffers between replays.  The graph
+ * holds the launch shape of the plan at capture: after mpmi_multi_set_config
+ * or mpmi_multi_autotune, destroy it and capture again. */
 mpmi_status mpmi_multi_graph(mpmi_ctx ctx, mpmi_multi multi, void** graph_exec);
 mpmi_status mpmi_graph_launch(mpmi_ctx ctx, void* graph_exec, void* stream);
 void mpmi_graph_destroy(void* graph_exec);

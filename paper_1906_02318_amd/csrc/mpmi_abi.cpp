@@ -418,7 +418,7 @@ mpmi_status mpmi_multi_create(mpmi_ctx ctx, const mpmi_loop_desc* loops, int32_t
   const int grid = cfg ? cfg->grid : 0;
   if (block < 64 || block > 1024 || block % 64 != 0)
     return fail(ctx, MPMI_EINVAL, "block=%d must be a multiple of 64 in 64..1024", block);
-  if (grid < 0) return fail(ctx, MPMI_EINVAL, "grid=%d must be >= 0", grid);
+  if (grid != 0) return fail(ctx, MPMI_EINVAL, "grid=%d must be 0 (one workgroup per work item)", grid);
   mpmi_multi m = new (std::nothrow) mpmi_multi_s();
   if (!m) return fail(ctx, MPMI_ENOMEM, "out of host memory");
   m->plan.n_loops = n_loops;
@@ -454,7 +454,7 @@ mpmi_status mpmi_multi_create(mpmi_ctx ctx, const mpmi_loop_desc* loops, int32_t
     m->plan.noisy = m->plan.noisy || mpmi::system_noisy(sys);
   }
   hipError_t e = mpmi::multi_alloc(m->plan);
-  if (e == hipSuccess) e = mpmi::multi_plan(m->plan, block, grid);
+  if (e == hipSuccess) e = mpmi::multi_plan(m->plan, block);
   if (e != hipSuccess) {
     mpmi::multi_free(m->plan);
     delete m;
@@ -476,15 +476,15 @@ mpmi_status mpmi_multi_set_config(mpmi_ctx ctx, mpmi_multi m, const mpmi_multi_c
   if (!m || !cfg) return fail(ctx, MPMI_EINVAL, "multi and cfg must be non-NULL");
   if (cfg->block < 64 || cfg->block > 1024 || cfg->block % 64 != 0)
     return fail(ctx, MPMI_EINVAL, "block=%d must be a multiple of 64 in 64..1024", cfg->block);
-  if (cfg->grid < 0) return fail(ctx, MPMI_EINVAL, "grid=%d must be >= 0", cfg->grid);
-  return check_hip(ctx, mpmi::multi_plan(m->plan, cfg->block, cfg->grid), "mpmi_multi_set_config");
+  if (cfg->grid != 0) return fail(ctx, MPMI_EINVAL, "grid=%d must be 0 (one workgroup per work item)", cfg->grid);
+  return check_hip(ctx, mpmi::multi_plan(m->plan, cfg->block), "mpmi_multi_set_config");
 }
 
 mpmi_status mpmi_multi_get_config(mpmi_multi m, mpmi_multi_config* cfg, int32_t* n_work_items) {
   if (!m) return MPMI_EINVAL;
   if (cfg) {
     cfg->block = m->plan.block;
-    cfg->grid = m->plan.grid;
+    cfg->grid = m->plan.n_work;
   }
   if (n_work_items) *n_work_items = m->plan.n_work;
   return MPMI_OK;
@@ -514,38 +514,34 @@ mpmi_status mpmi_multi_autotune(mpmi_ctx ctx, mpmi_multi m, int32_t reps, mpmi_m
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
     return fail(ctx, MPMI_EDEVICE, "hipEventCreate failed");
-  const int ncu = mpmi::device_cu_count();
   float bms = 1e30f;
-  mpmi_multi_config bcfg{m->plan.block, m->plan.grid};
+  int bblock = m->plan.block;
   hipError_t e = hipSuccess;
-  for (int block : {64, 128, 256, 512}) {
-    const int maxb = mpmi::multi_max_blocks_per_cu(block, m->plan.noisy);
-    for (int wpc : {1, 2, 4, 8}) {
-      if (wpc > maxb) continue;
-      if ((e = mpmi::multi_plan(m->plan, block, ncu * wpc)) != hipSuccess) break;
-      for (int w = 0; w < 2 && e == hipSuccess; ++w) e = mpmi::multi_launch(m->plan, st);
-      if (e == hipSuccess) e = hipEventRecord(e0, st);
-      for (int r = 0; r < reps && e == hipSuccess; ++r) e = mpmi::multi_launch(m->plan, st);
-      if (e == hipSuccess) e = hipEventRecord(e1, st);
-      if (e == hipSuccess) e = hipEventSynchronize(e1);
-      float ms = 0.0f;
-      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-      if (e != hipSuccess) break;
-      ms /= (float)reps;
-      if (ms < bms) {
-        bms = ms;
-        bcfg.block = block;
-        bcfg.grid = m->plan.grid;
-      }
-    }
+  for (int block : {64, 128, 256, 512, 1024}) {
+    if ((e = mpmi::multi_plan(m->plan, block)) != hipSuccess) break;
+    for (int w = 0; w < 2 && e == hipSuccess; ++w) e = mpmi::multi_launch(m->plan, st);
+    if (e == hipSuccess) e = hipEventRecord(e0, st);
+    for (int r = 0; r < reps && e == hipSuccess; ++r) e = mpmi::multi_launch(m->plan, st);
+    if (e == hipSuccess) e = hipEventRecord(e1, st);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
     if (e != hipSuccess) break;
+    ms /= (float)reps;
+    if (ms < bms) {
+      bms = ms;
+      bblock = block;
+    }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (e != hipSuccess) return fail(ctx, MPMI_EDEVICE, "mpmi_multi_autotune: %s", hipGetErrorString(e));
-  e = mpmi::multi_plan(m->plan, bcfg.block, bcfg.grid);
+  e = mpmi::multi_plan(m->plan, bblock);
   if (e != hipSuccess) return fail(ctx, MPMI_EDEVICE, "mpmi_multi_autotune: %s", hipGetErrorString(e));
-  if (best) *best = bcfg;
+  if (best) {
+    best->block = m->plan.block;
+    best->grid = m->plan.n_work;
+  }
   if (best_ms) *best_ms = bms;
   return ok(ctx);
 }

@@ -39,6 +39,8 @@ __host__ __device__ inline uint32_t bf16_bits_rne_u(float f) {
 // the Sec. V-C-1 inflation), contiguous so that a step fetches them with two
 // scalar loads.  Track coefficients above the model's highest harmonic are 0.
 struct SafetyConsts {
+  float comp_lim[MPMI_MAX_STATE];    // per state component: least box_bound - box_infl over its boxes
+  int32_t comp_mask;                 // bit k set if component k has a box
   float bb_lim[MPMI_MAX_BOX];        // box_bound - box_infl
   int32_t box_index[MPMI_MAX_BOX];   // state component of each box constraint
   int32_t n_box;
@@ -254,6 +256,16 @@ __device__ __forceinline__ const float4* opaque_lds(const float4* sK) {
   return sK + off;
 }
 
+// Marks every component of the new state as computed at this point (no
+// instruction is emitted).  Without it the compiler may sink the step's
+// per-component contractions into the branches of the safety check that use
+// them, holding all the step coefficients live across those branches.
+template <int NS>
+__device__ __forceinline__ void settle_state(float* x) {
+#pragma unroll
+  for (int j = 0; j < NS; ++j) asm volatile("" : "+v"(x[j]));
+}
+
 template <int BASIS>
 struct Stepper;
 
@@ -419,20 +431,24 @@ __device__ __forceinline__ float pick(const float* x, int idx) {
 // coefficients formed once per model in FP64; cos phi and sin phi come from
 // one reciprocal square root (rho = 0 or an infinite coordinate gives NaN,
 // i.e. unsafe; the centreline radius exceeds the half-width there anyway).
-// Horner runs over the full coefficient arrays: the zero coefficients above
-// the model's highest harmonic leave every partial sum exactly as it is, and
-// the fixed trip count lets all coefficients arrive in one scalar-load batch.
+// Horner runs over a fixed DEG (>= the model's highest harmonic, chosen on
+// the host): the zero coefficients above the model's degree leave every
+// partial sum exactly as it is, and the fixed trip count lets all the
+// coefficients arrive in one scalar-load batch.
+constexpr int kSmallTrackDeg = 5;  // the paper's track: harmonics 2..5
+template <int DEG = kMaxHarm>
 __device__ __forceinline__ float track_centre(const ConstSafety* sc, const float* x, float* rho) {
+  static_assert(DEG >= 1 && DEG <= kMaxHarm, "track degree");
   const float r2 = fmaf(x[0], x[0], x[1] * x[1]);
   const float inv = __builtin_amdgcn_rsqf(r2);
   *rho = r2 * inv;
   const float c1 = x[0] * inv, s1 = x[1] * inv;
-  float P = sc->trk_p[kMaxHarm];
+  float P = sc->trk_p[DEG];
 #pragma unroll
-  for (int k = kMaxHarm - 1; k >= 0; --k) P = fmaf(P, c1, sc->trk_p[k]);
-  float Q = sc->trk_q[kMaxHarm - 1];
+  for (int k = DEG - 1; k >= 0; --k) P = fmaf(P, c1, sc->trk_p[k]);
+  float Q = sc->trk_q[DEG - 1];
 #pragma unroll
-  for (int k = kMaxHarm - 2; k >= 0; --k) Q = fmaf(Q, c1, sc->trk_q[k]);
+  for (int k = DEG - 2; k >= 0; --k) Q = fmaf(Q, c1, sc->trk_q[k]);
   return fmaf(s1, Q, P);
 }
 
@@ -446,23 +462,26 @@ __device__ __forceinline__ const ConstSafety* safety_of(const ModelDev* __restri
 
 // Least margin over all constraints of state x (NaN if any margin is NaN, so
 // that "safe" = (margin > 0) rejects NaN states).
-template <int NS>
+// Boxes are taken per state component (wave-uniform branches on the mask,
+// compile-time register indices): several boxes on one component reduce to
+// the least limit, which gives the same least margin.
+template <int NS, int DEG = kMaxHarm>
 __device__ __forceinline__ float min_margin(const ModelDev* __restrict__ md, const float* x) {
   const ConstSafety* sc = safety_of(md);
   float mm = INFINITY;
   bool nan = false;
-  const int nb = sc->n_box;
+  const int mask = sc->comp_mask;
 #pragma unroll
-  for (int b = 0; b < MPMI_MAX_BOX; ++b) {
-    if (b < nb) {
-      const float mg = sc->bb_lim[b] - fabsf(pick<NS>(x, sc->box_index[b]));
+  for (int k = 0; k < NS; ++k) {
+    if (mask & (1 << k)) {
+      const float mg = sc->comp_lim[k] - fabsf(x[k]);
       nan |= (mg != mg);
       mm = fminf(mm, mg);
     }
   }
   if (sc->has_track) {
     float rho;
-    const float rc = track_centre(sc, x, &rho);
+    const float rc = track_centre<DEG>(sc, x, &rho);
     const float mg = sc->trk_lim - fabsf(rho - rc);
     nan |= (mg != mg);
     mm = fminf(mm, mg);

@@ -25,6 +25,15 @@ inline bool system_noisy(const mpmi_system& s) {
   return false;
 }
 
+// Highest harmonic of the track (degree of its centreline polynomial in
+// cos phi); 0 without a track.
+inline int track_degree(const mpmi_system& s) {
+  int h = 0;
+  if (s.has_track)
+    for (int q = 0; q < s.track_n && q < 4; ++q) h = s.track_freq[q] > h ? s.track_freq[q] : h;
+  return h;
+}
+
 hipError_t launch_tick(const mpmi_system& sys, const void* model, const mpmi_tick_desc& d, const float* x_t,
                        const float* u_user, const float* cand, void* slot, mpmi_selection* out,
                        int16_t* fv, float* traj, hipStream_t st, const mpmi_selection* gate = nullptr);
@@ -72,7 +81,6 @@ hipError_t launch_gemm_test(const uint16_t* A, const uint16_t* B, int M, int N, 
 
 // Many-loop tick (mpmi_multi.hip).
 struct WorkItem;
-struct MultiState;
 struct Slot;
 struct ModelDev;
 struct MultiPlan {
@@ -80,7 +88,6 @@ struct MultiPlan {
   mpmi_loop_desc* d_loops = nullptr;  // device copy of the loop table
   int* d_ntiles = nullptr;            // tiles per loop for the current block size
   WorkItem* d_work = nullptr;         // ordered (loop, tile) items
-  MultiState* d_state = nullptr;      // work counter + exit counter
   Slot* d_slots = nullptr;            // one selection slot per loop
   uint64_t* d_ticks = nullptr;        // per-loop tick counters (advanced on the device)
   ModelDev* d_models = nullptr;       // copy of each distinct packed model
@@ -89,16 +96,14 @@ struct MultiPlan {
   size_t work_capacity = 0;
   int n_work = 0;
   int block = 256;
-  int grid = 0;
   std::vector<mpmi_loop_desc> host;
   std::vector<int> basis;
   bool noisy = false;  // some loop's model draws process noise
 };
 hipError_t multi_alloc(MultiPlan& p);
 void multi_free(MultiPlan& p);
-hipError_t multi_plan(MultiPlan& p, int block, int grid);
+hipError_t multi_plan(MultiPlan& p, int block);
 hipError_t multi_launch(const MultiPlan& p, hipStream_t st);
-int multi_max_blocks_per_cu(int block, bool noisy);
 int device_cu_count();
 
 }  // namespace mpmi

@@ -1,20 +1,19 @@
-// Many control loops in one persistent launch per tick.
+// Many control loops in one launch per tick.
 //
 // The (loop, tile) work items of every loop are ordered longest-processing-
-// time first on the host and taken from an atomic counter by a grid sized to
-// fill the chip.  A workgroup keeps the K of the loop it served last in LDS
-// and restages only when the next item belongs to another model.  Each tile
-// publishes its arg-min keys into its loop's slot; the workgroup completing a
-// loop's last tile writes that loop's selection and advances its tick
-// counter; the last workgroup to leave resets the work counter, so the next
-// launch (or graph replay) starts clean without a memset.
+// time first on the host, and the launch runs one workgroup per item: the
+// hardware dispatcher hands workgroups to compute units in index order as
+// they free up, which serves the list longest-first without a work counter.
+// Each tile publishes its arg-min keys into its loop's slot; the workgroup
+// completing a loop's last tile writes that loop's selection and advances
+// the loop's tick counter.
 //
 // Everything the kernel reads per item is behind read-only kernel arguments:
 // the loop table (the advancing tick counters live in an array of their own)
-// and the plan's copy of each distinct packed model.  With the work-item
-// index made wave-uniform, every per-loop and per-model field is a scalar
-// load the compiler may re-issue instead of holding it, which leaves the
-// register budget to the prediction itself.
+// and the plan's copy of each distinct packed model.  Every per-loop and
+// per-model field is then a scalar load the compiler may re-issue instead of
+// holding it, and with no loop around the item the register budget goes to
+// the prediction itself, as in the single-loop tick.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -33,77 +32,50 @@ struct WorkItem {
   uint32_t pad;
 };
 
-struct MultiState {
-  unsigned int next;    // next work item
-  unsigned int exited;  // workgroups that found the list empty
-  unsigned int pad[62];
-};
-
 template <bool NOISE>
 __global__ void __launch_bounds__(1024)
 multi_kernel(const mpmi_loop_desc* __restrict__ loops, const ModelDev* __restrict__ models,
-             const int* __restrict__ n_tiles, const WorkItem* __restrict__ work, int n_work,
-             MultiState* __restrict__ st, Slot* __restrict__ slots, uint64_t* __restrict__ ticks) {
+             const int* __restrict__ n_tiles, const WorkItem* __restrict__ work, Slot* __restrict__ slots,
+             uint64_t* __restrict__ ticks) {
   __shared__ float4 sK[kLdsKFloat4];
-  __shared__ int s_item;
-  const ModelDev* cached = nullptr;
-  for (;;) {
-    if (threadIdx.x == 0) s_item = (int)atomicAdd(&st->next, 1u);
-    __syncthreads();
-    const int it = __builtin_amdgcn_readfirstlane(s_item);
-    __syncthreads();
-    if (it >= n_work) break;
-    const WorkItem w = work[it];
-    const mpmi_loop_desc* L = &loops[w.loop];
-    const ModelDev* md = models + w.model;
-    const int basis = md->sys.basis;
-    if (md != cached) {
-      if (basis == MPMI_BASIS_RACE_CAR) stage_K<MPMI_BASIS_RACE_CAR>(md, sK);
-      else if (basis == MPMI_BASIS_BALANCE_BOT) stage_K<MPMI_BASIS_BALANCE_BOT>(md, sK);
-      else stage_K<MPMI_BASIS_LINEAR>(md, sK);
-      cached = md;
-    }
-    GenParams gp;
-    gp.seed = L->seed;
-    // Written below by the workgroup that completes this loop's tick; every
-    // tile of the loop reads it before that (the completing workgroup is the
-    // last of the loop's tiles to publish).
-    const uint64_t tk = ticks[w.loop];
-    gp.tick = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(tk >> 32)) << 32) |
-              (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)tk);
-    gp.loop = (int32_t)w.loop;
-    gp.gen = L->gen;
-    gp.n_cand = L->n_cand;
-    gp.n_seg = L->n_seg;
+  const WorkItem w = work[blockIdx.x];
+  const mpmi_loop_desc* L = &loops[w.loop];
+  const ModelDev* md = models + w.model;
+  const int basis = md->sys.basis;
+  if (basis == MPMI_BASIS_RACE_CAR) stage_K<MPMI_BASIS_RACE_CAR>(md, sK);
+  else if (basis == MPMI_BASIS_BALANCE_BOT) stage_K<MPMI_BASIS_BALANCE_BOT>(md, sK);
+  else stage_K<MPMI_BASIS_LINEAR>(md, sK);
+  GenParams gp;
+  gp.seed = L->seed;
+  // Written below by the workgroup that completes this loop's tick; every
+  // tile of the loop reads it before that (the completing workgroup is the
+  // last of the loop's tiles to publish).
+  const uint64_t tk = ticks[w.loop];
+  gp.tick = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(tk >> 32)) << 32) |
+            (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)tk);
+  gp.loop = (int32_t)w.loop;
+  gp.gen = L->gen;
+  gp.n_cand = L->n_cand;
+  gp.n_seg = L->n_seg;
 #pragma unroll
-    for (int j = 0; j < MPMI_MAX_INPUT; ++j) gp.grid[j] = L->grid[j] > 0 ? L->grid[j] : 1;
-    const int H = L->horizon;
-    const int c = (int)w.tile * (int)blockDim.x + (int)threadIdx.x;
-    CandResult r;
-    if (basis == MPMI_BASIS_RACE_CAR)
-      r = evaluate_candidate<MPMI_BASIS_RACE_CAR, NOISE>(md, sK, gp, H, L->x_t, L->u_user, L->cand, c,
-                                                         L->first_violation, nullptr);
-    else if (basis == MPMI_BASIS_BALANCE_BOT)
-      r = evaluate_candidate<MPMI_BASIS_BALANCE_BOT, NOISE>(md, sK, gp, H, L->x_t, L->u_user, L->cand, c,
-                                                            L->first_violation, nullptr);
-    else
-      r = evaluate_candidate<MPMI_BASIS_LINEAR, NOISE>(md, sK, gp, H, L->x_t, L->u_user, L->cand, c,
+  for (int j = 0; j < MPMI_MAX_INPUT; ++j) gp.grid[j] = L->grid[j] > 0 ? L->grid[j] : 1;
+  const int H = L->horizon;
+  const int c = (int)w.tile * (int)blockDim.x + (int)threadIdx.x;
+  CandResult r;
+  if (basis == MPMI_BASIS_RACE_CAR)
+    r = evaluate_candidate<MPMI_BASIS_RACE_CAR, NOISE>(md, sK, gp, H, L->x_t, L->u_user, L->cand, c,
                                                        L->first_violation, nullptr);
-    Slot* slot = &slots[w.loop];
-    if (reduce_and_publish(r.ks, r.kf, r.safe_counted, slot, (unsigned int)n_tiles[w.loop]) &&
-        threadIdx.x == 0) {
-      finalize<MPMI_MAX_INPUT>(md, gp, L->cand, L->u_user, H, slot, L->out);
-      ticks[w.loop] = gp.tick + 1;
-      __threadfence();
-    }
-  }
-  if (threadIdx.x == 0) {
+  else if (basis == MPMI_BASIS_BALANCE_BOT)
+    r = evaluate_candidate<MPMI_BASIS_BALANCE_BOT, NOISE>(md, sK, gp, H, L->x_t, L->u_user, L->cand, c,
+                                                          L->first_violation, nullptr);
+  else
+    r = evaluate_candidate<MPMI_BASIS_LINEAR, NOISE>(md, sK, gp, H, L->x_t, L->u_user, L->cand, c,
+                                                     L->first_violation, nullptr);
+  Slot* slot = &slots[w.loop];
+  if (reduce_and_publish(r.ks, r.kf, r.safe_counted, slot, (unsigned int)n_tiles[w.loop]) && threadIdx.x == 0) {
+    finalize<MPMI_MAX_INPUT>(md, gp, L->cand, L->u_user, H, slot, L->out);
+    ticks[w.loop] = gp.tick + 1;
     __threadfence();
-    if (atomicAdd(&st->exited, 1u) == gridDim.x - 1) {
-      st->next = 0u;
-      st->exited = 0u;
-      __threadfence();
-    }
   }
 }
 
@@ -123,7 +95,6 @@ hipError_t multi_alloc(MultiPlan& p) {
   if ((e = hipMalloc(&p.d_loops, sizeof(mpmi_loop_desc) * p.n_loops)) != hipSuccess) return e;
   if ((e = hipMalloc(&p.d_ntiles, sizeof(int) * p.n_loops)) != hipSuccess) return e;
   if ((e = hipMalloc(&p.d_work, sizeof(WorkItem) * (cap > 0 ? cap : 1))) != hipSuccess) return e;
-  if ((e = hipMalloc(&p.d_state, sizeof(MultiState))) != hipSuccess) return e;
   if ((e = hipMalloc(&p.d_slots, sizeof(Slot) * p.n_loops)) != hipSuccess) return e;
   if ((e = hipMalloc(&p.d_ticks, sizeof(uint64_t) * p.n_loops)) != hipSuccess) return e;
   p.model_of_loop.assign(p.n_loops, 0);
@@ -143,7 +114,6 @@ hipError_t multi_alloc(MultiPlan& p) {
   if ((e = hipMemcpy(p.d_loops, p.host.data(), sizeof(mpmi_loop_desc) * p.n_loops, hipMemcpyHostToDevice)) !=
       hipSuccess)
     return e;
-  if ((e = hipMemset(p.d_state, 0, sizeof(MultiState))) != hipSuccess) return e;
   std::vector<Slot> s(p.n_loops);
   for (auto& x : s) {
     x.key_safe = kKeyNone;
@@ -157,25 +127,15 @@ void multi_free(MultiPlan& p) {
   if (p.d_loops) (void)hipFree(p.d_loops);
   if (p.d_ntiles) (void)hipFree(p.d_ntiles);
   if (p.d_work) (void)hipFree(p.d_work);
-  if (p.d_state) (void)hipFree(p.d_state);
   if (p.d_slots) (void)hipFree(p.d_slots);
   if (p.d_ticks) (void)hipFree(p.d_ticks);
   if (p.d_models) (void)hipFree(p.d_models);
   p.d_loops = nullptr;
   p.d_ntiles = nullptr;
   p.d_work = nullptr;
-  p.d_state = nullptr;
   p.d_slots = nullptr;
   p.d_ticks = nullptr;
   p.d_models = nullptr;
-}
-
-int multi_max_blocks_per_cu(int block, bool noisy) {
-  int nb = 0;
-  const hipError_t e = noisy ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, multi_kernel<true>, block, 0)
-                             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, multi_kernel<false>, block, 0);
-  if (e != hipSuccess) return 1;
-  return nb > 0 ? nb : 1;
 }
 
 int device_cu_count() {
@@ -185,8 +145,9 @@ int device_cu_count() {
   return ncu > 0 ? ncu : 1;
 }
 
-// Builds the longest-first work list for `block` and uploads it (synchronous).
-hipError_t multi_plan(MultiPlan& p, int block, int grid) {
+// Builds the longest-first work list for `block`, uploads it and re-takes the
+// model snapshot (synchronous).
+hipError_t multi_plan(MultiPlan& p, int block) {
   // The work list may be in use by launches still queued on any stream.
   hipError_t e0 = hipDeviceSynchronize();
   if (e0 != hipSuccess) return e0;
@@ -216,19 +177,16 @@ hipError_t multi_plan(MultiPlan& p, int block, int grid) {
   if (e != hipSuccess) return e;
   p.n_work = (int)items.size();
   p.block = block;
-  const int full = device_cu_count() * multi_max_blocks_per_cu(block, p.noisy);
-  p.grid = grid > 0 ? grid : full;
-  if (p.grid > p.n_work) p.grid = p.n_work > 0 ? p.n_work : 1;
   return hipDeviceSynchronize();
 }
 
 hipError_t multi_launch(const MultiPlan& p, hipStream_t st) {
   if (p.noisy)
-    multi_kernel<true><<<p.grid, p.block, 0, st>>>(p.d_loops, p.d_models, p.d_ntiles, p.d_work, p.n_work,
-                                                   p.d_state, p.d_slots, p.d_ticks);
+    multi_kernel<true><<<p.n_work, p.block, 0, st>>>(p.d_loops, p.d_models, p.d_ntiles, p.d_work, p.d_slots,
+                                                     p.d_ticks);
   else
-    multi_kernel<false><<<p.grid, p.block, 0, st>>>(p.d_loops, p.d_models, p.d_ntiles, p.d_work, p.n_work,
-                                                    p.d_state, p.d_slots, p.d_ticks);
+    multi_kernel<false><<<p.n_work, p.block, 0, st>>>(p.d_loops, p.d_models, p.d_ntiles, p.d_work, p.d_slots,
+                                                      p.d_ticks);
   return hipGetLastError();
 }
 

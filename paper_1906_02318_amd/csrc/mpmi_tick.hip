@@ -20,7 +20,7 @@ namespace mpmi {
 // ---------------------------------------------------------------------------
 // Fused tick, FP32
 // ---------------------------------------------------------------------------
-template <int BASIS, bool NOISE>
+template <int BASIS, bool NOISE, int DEG>
 __global__ void __launch_bounds__(1024)
 tick_fp32_kernel(const ModelDev* __restrict__ md, GenParams gp, int H, const float* __restrict__ x_t,
                  const float* __restrict__ u_user, const float* __restrict__ cand,
@@ -34,7 +34,7 @@ tick_fp32_kernel(const ModelDev* __restrict__ md, GenParams gp, int H, const flo
   __shared__ float4 sK[kLdsKFloat4];
   stage_K<BASIS>(md, sK);
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  const CandResult r = evaluate_candidate<BASIS, NOISE>(md, sK, gp, H, x_t, u_user, cand, c, fv_out, traj);
+  const CandResult r = evaluate_candidate<BASIS, NOISE, DEG>(md, sK, gp, H, x_t, u_user, cand, c, fv_out, traj);
   if (reduce_and_publish(r.ks, r.kf, r.safe_counted, slot, gridDim.x) && threadIdx.x == 0)
     finalize<MS>(md, gp, cand, u_user, H, slot, out);
 }
@@ -176,6 +176,14 @@ __global__ void pack_kernel(mpmi_system sys, int dim, int state_feat0, const dou
     for (int b = 0; b < MPMI_MAX_BOX; ++b)
       md->safe.bb_lim[b] = (b < sys.n_box) ? (float)((double)sys.box_bound[b] - (double)sys.box_infl[b]) : 0.0f;
     for (int b = 0; b < MPMI_MAX_BOX; ++b) md->safe.box_index[b] = (b < sys.n_box) ? sys.box_index[b] : 0;
+    int cmask = 0;
+    for (int k = 0; k < MPMI_MAX_STATE; ++k) md->safe.comp_lim[k] = INFINITY;
+    for (int b = 0; b < sys.n_box; ++b) {
+      const int k = sys.box_index[b];
+      cmask |= 1 << k;
+      md->safe.comp_lim[k] = fminf(md->safe.comp_lim[k], md->safe.bb_lim[b]);
+    }
+    md->safe.comp_mask = cmask;
     md->safe.n_box = sys.n_box;
     md->safe.has_track = sys.has_track;
     md->safe.trk_lim = (float)((double)sys.track_half - (double)sys.track_infl);
@@ -246,14 +254,14 @@ hipError_t launch_pack(const mpmi_system& sys, int dim, int state_feat0, const d
   return hipGetLastError();
 }
 
-template <int BASIS>
+template <int BASIS, int DEG>
 static void tick_dispatch(bool noisy, unsigned grid, int block, hipStream_t st, const ModelDev* md,
                           const GenParams& gp, int H, const float* x_t, const float* u_user, const float* cand,
                           Slot* sl, mpmi_selection* out, int16_t* fv, float* traj, const mpmi_selection* gate) {
   if (noisy)
-    tick_fp32_kernel<BASIS, true><<<grid, block, 0, st>>>(md, gp, H, x_t, u_user, cand, sl, out, fv, traj, gate);
+    tick_fp32_kernel<BASIS, true, DEG><<<grid, block, 0, st>>>(md, gp, H, x_t, u_user, cand, sl, out, fv, traj, gate);
   else
-    tick_fp32_kernel<BASIS, false><<<grid, block, 0, st>>>(md, gp, H, x_t, u_user, cand, sl, out, fv, traj, gate);
+    tick_fp32_kernel<BASIS, false, DEG><<<grid, block, 0, st>>>(md, gp, H, x_t, u_user, cand, sl, out, fv, traj, gate);
 }
 
 hipError_t launch_tick(const mpmi_system& sys, const void* model, const mpmi_tick_desc& d, const float* x_t,
@@ -267,16 +275,20 @@ hipError_t launch_tick(const mpmi_system& sys, const void* model, const mpmi_tic
   const bool noisy = system_noisy(sys);
   switch (sys.basis) {
     case MPMI_BASIS_LINEAR:
-      tick_dispatch<MPMI_BASIS_LINEAR>(noisy, grid, block, st, md, gp, d.horizon, x_t, u_user, cand, sl, out, fv,
-                                       traj, gate);
+      tick_dispatch<MPMI_BASIS_LINEAR, kMaxHarm>(noisy, grid, block, st, md, gp, d.horizon, x_t, u_user, cand, sl,
+                                                 out, fv, traj, gate);
       break;
     case MPMI_BASIS_BALANCE_BOT:
-      tick_dispatch<MPMI_BASIS_BALANCE_BOT>(noisy, grid, block, st, md, gp, d.horizon, x_t, u_user, cand, sl, out,
-                                            fv, traj, gate);
+      tick_dispatch<MPMI_BASIS_BALANCE_BOT, kMaxHarm>(noisy, grid, block, st, md, gp, d.horizon, x_t, u_user, cand,
+                                                      sl, out, fv, traj, gate);
       break;
     default:
-      tick_dispatch<MPMI_BASIS_RACE_CAR>(noisy, grid, block, st, md, gp, d.horizon, x_t, u_user, cand, sl, out, fv,
-                                         traj, gate);
+      if (track_degree(sys) <= kSmallTrackDeg)
+        tick_dispatch<MPMI_BASIS_RACE_CAR, kSmallTrackDeg>(noisy, grid, block, st, md, gp, d.horizon, x_t, u_user,
+                                                           cand, sl, out, fv, traj, gate);
+      else
+        tick_dispatch<MPMI_BASIS_RACE_CAR, kMaxHarm>(noisy, grid, block, st, md, gp, d.horizon, x_t, u_user, cand,
+                                                     sl, out, fv, traj, gate);
       break;
   }
   return hipGetLastError();

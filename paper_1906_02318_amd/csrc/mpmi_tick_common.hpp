@@ -134,7 +134,8 @@ struct CandResult {
 // empty keys.  fv_out / traj are optional.  NOISE compiles the process-noise
 // draw in (models with a positive sigma); noise-free instances carry none of
 // its registers (a noisy instance still skips the draw for a noise-free model).
-template <int BASIS, bool NOISE>
+// DEG is the track polynomial's degree (>= the model's highest harmonic).
+template <int BASIS, bool NOISE, int DEG = kMaxHarm>
 __device__ __forceinline__ CandResult evaluate_candidate(const ModelDev* __restrict__ md, const float4* sK,
                                                          const GenParams& gp, int H,
                                                          const float* __restrict__ x_t,
@@ -169,13 +170,14 @@ __device__ __forceinline__ CandResult evaluate_candidate(const ModelDev* __restr
         stp.set_input(md, sK, u);
       }
       stp.step(md, sK, x);
+      settle_state<NS>(x);
       if (noisy) add_process_noise<NS>(md->sys.noise_sigma, nprefix, s, n, x);
       if (traj) {
 #pragma unroll
         for (int j = 0; j < NS; ++j)
           if (j < n) traj[((size_t)(s - 1) * n + j) * (size_t)Nc + c] = x[j];
       }
-      if (!(min_margin<NS>(md, x) > 0.0f)) {
+      if (!(min_margin<NS, DEG>(md, x) > 0.0f)) {
         fv = s;
         break;
       }

@@ -410,7 +410,7 @@ class Multi:
     first_violation.  The tensors are kept alive by this object.
     """
 
-    def __init__(self, ctx: Context, loops, block: int = 256, grid: int = 0):
+    def __init__(self, ctx: Context, loops, block: int = 256):
         self.ctx = ctx
         self._keep = []
         arr = (LoopDesc * len(loops))()
@@ -435,7 +435,7 @@ class Multi:
                 d.grid[j] = g
             d.n_seg, d.horizon = l.get("n_seg", 1), l["horizon"]
             self._keep.append(l)
-        cfg = MultiConfig(block, grid)
+        cfg = MultiConfig(block, 0)
         h = ctypes.c_void_p()
         ctx.check(ctx.lib.mpmi_multi_create(ctx.handle, arr, len(loops), ctypes.byref(cfg), ctypes.byref(h)))
         self.handle = h
@@ -446,9 +446,16 @@ class Multi:
         self.ctx.lib.mpmi_multi_get_config(self.handle, ctypes.byref(cfg), ctypes.byref(n))
         return dict(block=cfg.block, grid=cfg.grid, n_work=n.value)
 
-    def set_config(self, block: int, grid: int = 0):
+    def _drop_graph(self):
+        # A captured graph holds the launch shape of the plan it was taken from.
+        if self.graph is not None:
+            self.ctx.lib.mpmi_graph_destroy(self.graph)
+            self.graph = None
+
+    def set_config(self, block: int):
+        self._drop_graph()
         self.ctx.check(self.ctx.lib.mpmi_multi_set_config(self.ctx.handle, self.handle,
-                                                         ctypes.byref(MultiConfig(block, grid))))
+                                                         ctypes.byref(MultiConfig(block, 0))))
 
     def tick(self, stream=None):
         self.ctx.check(self.ctx.lib.mpmi_multi_tick(self.ctx.handle, self.handle, _stream(stream)))
@@ -460,6 +467,7 @@ class Multi:
         return list(arr)
 
     def autotune(self, reps: int = 20, stream=None):
+        self._drop_graph()
         best, ms = MultiConfig(), ctypes.c_float()
         self.ctx.check(self.ctx.lib.mpmi_multi_autotune(self.ctx.handle, self.handle, reps, ctypes.byref(best),
                                                         ctypes.byref(ms), _stream(stream)))

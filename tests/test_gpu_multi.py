@@ -109,7 +109,7 @@ def test_multi_graph_replay(setup):
 def test_multi_autotune_and_block_sizes_deterministic(setup):
     ctx, multi, loops, meta, systems = setup
     offset = 5  # ticks so far: 2 eager + 3 replays
-    for block in (64, 128, 512):
+    for block in (64, 128, 512, 1024):
         multi.set_config(block)
         multi.tick()
         torch.cuda.synchronize()
@@ -117,7 +117,8 @@ def test_multi_autotune_and_block_sizes_deterministic(setup):
         offset += 1
     best = multi.autotune(reps=5)
     log(f"[multi] autotuned {best}, plan {multi.config()}")
-    assert best["block"] in (64, 128, 256, 512) and best["grid"] >= 1 and best["ms"] > 0
+    assert best["block"] in (64, 128, 256, 512, 1024) and best["ms"] > 0
+    assert best["grid"] == multi.config()["n_work"] >= len(loops)
     ticks = multi.ticks()
     offs = [t - mt["tick0"] for t, mt in zip(ticks, meta)]
     assert len(set(offs)) == 1 and offs[0] > offset
