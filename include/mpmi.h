@@ -269,6 +269,13 @@ mpmi_status mpmi_generate_candidates(mpmi_ctx ctx, const void* model,
                                      float* cand_out, void* stream);
 
 
+/* Diagnostic: the device's non-packed FP32 FMA issue rate (TFLOP/s, host
+ * *tflops), measured by a register-only kernel with 16 independent FMA
+ * chains per lane and 8 workgroups of 256 lanes per compute unit; the best
+ * of three timed launches.  It is the ceiling of the tick's VALU-bound step.
+ * Synchronous (default stream, about 15 ms); allocates nothing. */
+mpmi_status mpmi_fp32_fma_rate(mpmi_ctx ctx, double* tflops /* host */);
+
 /* ---------------------------------------------------------------------------
  * Many concurrent control loops in one launch per tick.
  *

@@ -387,6 +387,12 @@ mpmi_status mpmi_tick_autotune(mpmi_ctx ctx, const void* model, mpmi_tick_desc* 
   return ok(ctx);
 }
 
+mpmi_status mpmi_fp32_fma_rate(mpmi_ctx ctx, double* tflops) {
+  if (!ctx) return MPMI_EINVAL;
+  if (!tflops) return fail(ctx, MPMI_EINVAL, "tflops is NULL");
+  return check_hip(ctx, mpmi::measure_fma_rate((float*)ctx->fit_work, tflops), "mpmi_fp32_fma_rate");
+}
+
 mpmi_status mpmi_generate_candidates(mpmi_ctx ctx, const void* model, const mpmi_tick_desc* desc,
                                      const float* u_user, const float* cand, float* cand_out, void* stream) {
   if (!ctx) return MPMI_EINVAL;

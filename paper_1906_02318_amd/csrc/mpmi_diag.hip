@@ -1,0 +1,58 @@
+// Device ceiling diagnostics.
+//
+// The fused tick's step is VALU-bound: its work is FP32 FMAs and products
+// issued one wave64 instruction per four cycles per SIMD (packed FP32 is
+// disabled in every kernel of the library).  fma_rate_kernel measures the
+// rate such instructions reach on the part: registers only, 16 independent
+// FMA chains per lane, 8 workgroups of 256 lanes per compute unit.
+#include <hip/hip_runtime.h>
+
+#include "mpmi_launch.hpp"
+
+namespace mpmi {
+
+constexpr int kFmaChains = 16;
+
+__global__ void __launch_bounds__(256) fma_rate_kernel(float* __restrict__ sink, int iters, float a, float b) {
+  float v[kFmaChains];
+#pragma unroll
+  for (int k = 0; k < kFmaChains; ++k) v[k] = (float)threadIdx.x * 1e-3f + (float)k;
+  for (int i = 0; i < iters; ++i) {
+#pragma unroll
+    for (int k = 0; k < kFmaChains; ++k) v[k] = fmaf(v[k], a, b);
+  }
+  float s = 0.0f;
+#pragma unroll
+  for (int k = 0; k < kFmaChains; ++k) s += v[k];
+  // Data-dependent store (never taken for the arguments used) keeps the
+  // chains live without writing memory.
+  if (s == -1.0f) sink[0] = s;
+}
+
+hipError_t measure_fma_rate(float* sink, double* tflops) {
+  const int ncu = device_cu_count();
+  const int block = 256, grid = ncu * 8, iters = 20000;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  float best = 1e30f;
+  for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
+    fma_rate_kernel<<<grid, block, 0, 0>>>(sink, iters, 0.999f, 0.001f);  // warm
+    if ((e = hipEventRecord(e0, 0)) != hipSuccess) break;
+    fma_rate_kernel<<<grid, block, 0, 0>>>(sink, iters, 0.999f, 0.001f);
+    if ((e = hipGetLastError()) != hipSuccess) break;
+    if ((e = hipEventRecord(e1, 0)) != hipSuccess) break;
+    if ((e = hipEventSynchronize(e1)) != hipSuccess) break;
+    float ms = 0.0f;
+    if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
+    best = ms < best ? ms : best;
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return e;
+  const double flops = 2.0 * kFmaChains * (double)iters * (double)grid * (double)block;
+  *tflops = flops / ((double)best * 1e-3) / 1e12;
+  return hipSuccess;
+}
+
+}  // namespace mpmi

@@ -79,6 +79,11 @@ hipError_t launch_mlp_row(const float* x_t, const float* u_user, void* work, flo
 hipError_t launch_gemm_test(const uint16_t* A, const uint16_t* B, int M, int N, int K, int ta, int tb, float* C,
                             hipStream_t st);
 
+// Device ceiling diagnostics (mpmi_diag.hip): non-packed FP32 FMA rate,
+// TFLOP/s; `sink` is any device buffer of >= 4 bytes (never written in
+// practice).
+hipError_t measure_fma_rate(float* sink, double* tflops);
+
 // Many-loop tick (mpmi_multi.hip).
 struct WorkItem;
 struct Slot;

@@ -105,6 +105,7 @@ def library() -> ctypes.CDLL:
         "select_min_intervention": (i32, [vp, vp, vp, i32, i32, vp, i32, vp, i32, vp, vp]),
         "mpmi_tick": (i32, [vp, vp, ctypes.POINTER(TickDesc), vp, vp, vp, vp, vp, vp, vp]),
         "mpmi_generate_candidates": (i32, [vp, vp, ctypes.POINTER(TickDesc), vp, vp, vp, vp]),
+        "mpmi_fp32_fma_rate": (i32, [vp, ctypes.POINTER(f64)]),
         "mpmi_multi_create": (i32, [vp, ctypes.POINTER(LoopDesc), i32, ctypes.POINTER(MultiConfig), ctypes.POINTER(vp)]),
         "mpmi_multi_destroy": (None, [vp]),
         "mpmi_multi_set_config": (i32, [vp, vp, ctypes.POINTER(MultiConfig)]),
@@ -384,6 +385,13 @@ def mpmi_generate_candidates(ctx: Context, model: Model, desc: TickDesc, u_user,
     ctx.check(ctx.lib.mpmi_generate_candidates(ctx.handle, ctypes.c_void_p(model.ptr), ctypes.byref(desc),
                                                _ptr(u_user), _ptr(cand), _ptr(out), _stream(stream)))
     return out
+
+
+def mpmi_fp32_fma_rate(ctx: Context) -> float:
+    """Measured non-packed FP32 FMA issue rate of the device, TFLOP/s (synchronous)."""
+    r = ctypes.c_double(0.0)
+    ctx.check(ctx.lib.mpmi_fp32_fma_rate(ctx.handle, ctypes.byref(r)))
+    return r.value
 
 
 def decode_selection(rec) -> dict:

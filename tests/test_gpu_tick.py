@@ -233,6 +233,30 @@ def test_tick_race_car(ctx, rc):
     assert kinds.get("identical", 0) + kinds.get("equal_cost", 0) + kinds.get("eps_band", 0) == T
 
 
+def test_tick_race_car_high_harmonic_track_and_stacked_boxes(ctx, rc):
+    """Race car on a track with harmonics up to the eighth (the degree-8 track
+    polynomial) and three boxes, two of them on v_y (the least limit binds)
+    and one on the yaw rate."""
+    so0, _, K = rc
+    tr = synth.Track(amp=np.array([1.0, 0.5, 0.3, 0.2]), freq=np.array([3, 5, 7, 8]),
+                     phase=np.random.default_rng(11).uniform(0.0, 2 * np.pi, size=4))
+    td = W.track_dict(tr)
+    boxes = [(4, float(W.f32(2.0)), 0.0), (4, float(W.f32(1.2)), 0.0), (5, float(W.f32(0.5)), 0.0)]
+    so = o.System("race_car", 6, 2, box=boxes, track=td, u_lo=synth.RC_U_LO, u_hi=synth.RC_U_HI)
+    sys_g = mpmi._sys(mpmi.BASIS_RACE_CAR, 6, 2, boxes, synth.RC_U_LO, synth.RC_U_HI, track=td,
+                      eps_box=[0.02] * 3, eps_track=0.02)
+    model = mpmi.mpmi_model_pack(ctx, sys_g, dev(K, torch.float64))
+    T = 6
+    xs = synth.race_car_states(T, tr, seed=4, offset=1.5, vy=(-0.3, 0.3), r=(-0.2, 0.2))
+    uhs = synth.uniform_user(T, synth.RC_U_LO, synth.RC_U_HI, seed=5)
+    grid = o.grid_candidates(so, [96, 96])
+    kinds = run_ticks(ctx, model, so, K, xs, uhs,
+                      lambda t: mpmi.tick_desc(96 * 96, 40, gen=mpmi.GEN_GRID, grid=[96, 96]), 40,
+                      [1e-3, 1e-3, 1e-3, 1e-3], "rc degree-8 track, stacked boxes N=9216 H=40",
+                      lambda t, u: o.with_user(grid, u, 1))
+    assert kinds.get("identical", 0) + kinds.get("equal_cost", 0) + kinds.get("eps_band", 0) == T
+
+
 @pytest.mark.parametrize("N,H,gen", [(0, 20, mpmi.GEN_UNIFORM), (777, 1, mpmi.GEN_UNIFORM), (1000, 33, mpmi.GEN_UNIFORM),
                                      (63, 5, mpmi.GEN_GRID), (65, 255, mpmi.GEN_GRID)])
 def test_tick_edge_sizes(ctx, bb, N, H, gen):
@@ -548,3 +572,12 @@ def test_tick_lanes_per_candidate_identical_and_autotuned(ctx, bb, rc, system):
     assert best["lanes_per_cand"] in (1, 2, 4) and best["block"] in (64, 128, 256, 512)
     rec = mpmi.mpmi_tick(ctx, model, d, dev(x, torch.float32), dev(u, torch.float32)).cpu().numpy().tobytes()
     assert rec == recs[0]
+
+
+def test_fp32_fma_rate_diagnostic(ctx):
+    """The non-packed FP32 FMA ceiling the roofline is judged against: within
+    the part's theoretical 78.6 TFLOP/s (256 CUs x 4 SIMDs x 16 lanes x 2 x
+    2.4 GHz) and well above half of it."""
+    r = mpmi.mpmi_fp32_fma_rate(ctx)
+    log(f"[diag] FP32 FMA rate {r:.1f} TFLOP/s")
+    assert 40.0 < r < 80.0
