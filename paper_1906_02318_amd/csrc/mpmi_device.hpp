@@ -315,24 +315,28 @@ struct Stepper<MPMI_BASIS_BALANCE_BOT> {
       for (int k = 0; k < 4; ++k) L[k][j] = fmaf(u, K[quad_index(k, 4, 5) * 4 + j], K[(1 + k) * 4 + j]);
     }
   }
+  // Nested form of the linear + quadratic part:
+  //   y_j = c_j + sum_k x_k (L_kj + sum_{l >= k} Q_klj x_l),
+  // the same polynomial as the plain feature sum with no feature products;
+  // each coefficient row (one LDS broadcast read) feeds all four outputs.
   __device__ __forceinline__ void step(const ModelDev* __restrict__, const float4* sK, float* x) {
+    const float4* kk = opaque_lds(sK) + kBbStepOff / 4;
     float y[4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      y[j] = cu[j];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) y[j] = fmaf(L[k][j], x[k], y[j]);
-    }
-    const float4* kk = opaque_lds(sK) + kBbStepOff / 4;
+    for (int j = 0; j < 4; ++j) y[j] = cu[j];
     int q = 0;
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
+    for (int k = 0; k < 4; ++k) {
+      float t[4] = {L[k][0], L[k][1], L[k][2], L[k][3]};
 #pragma unroll
-      for (int l = k; l < 4; ++l) {
-        const float p = x[k] * x[l];
-        const float4 a = kk[q++];
-        y[0] = fmaf(p, a.x, y[0]); y[1] = fmaf(p, a.y, y[1]); y[2] = fmaf(p, a.z, y[2]); y[3] = fmaf(p, a.w, y[3]);
+      for (int l = k; l < 4; ++l, ++q) {
+        const float4 a = kk[q];
+        t[0] = fmaf(a.x, x[l], t[0]); t[1] = fmaf(a.y, x[l], t[1]);
+        t[2] = fmaf(a.z, x[l], t[2]); t[3] = fmaf(a.w, x[l], t[3]);
       }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) y[j] = fmaf(x[k], t[j], y[j]);
+    }
 #pragma unroll
     for (int j = 0; j < 4; ++j) x[j] = y[j];
   }

@@ -161,45 +161,66 @@ tick_split_kernel(const ModelDev* __restrict__ md, GenParams gp, int H, const fl
         sp = __sinf(x[2]);
         cp = __cosf(x[2]);
       }
-      float y[J];
-#pragma unroll
-      for (int jj = 0; jj < J; ++jj) {
-        float v = F.cu[jj];
-        if (BASIS == MPMI_BASIS_RACE_CAR) v = fmaf(F.Tc[jj], cp, fmaf(F.Ts[jj], sp, v));
-#pragma unroll
-        for (int k = 0; k < NS; ++k) v = fmaf(F.L[k][jj], x[k], v);
-        y[jj] = v;
-      }
-      // Opaque zero offset: keeps the per-step K loads inside the loop.
+      // Each form in the one-lane kernel's operation order, so the two give
+      // bit-identical states: race car as the feature sum, balance bot nested.
+      // The opaque zero offset keeps the per-step K loads inside the loop.
       int zoff = 0;
       asm volatile("" : "+v"(zoff));
       const float* kk = sK8 + zoff;
-      int q = 0;
+      float y[J];
+      if constexpr (BASIS == MPMI_BASIS_RACE_CAR) {
 #pragma unroll
-      for (int k = 0; k < NS; ++k)
+        for (int jj = 0; jj < J; ++jj) {
+          float v = fmaf(F.Tc[jj], cp, fmaf(F.Ts[jj], sp, F.cu[jj]));
 #pragma unroll
-        for (int l = k; l < NS; ++l) {
-          float kv[J];
-          ldsJ<J>(&kk[(D + q) * 8 + colpos], kv);
-          const float p = x[k] * x[l];
-#pragma unroll
-          for (int jj = 0; jj < J; ++jj) y[jj] = fmaf(p, kv[jj], y[jj]);
-          ++q;
+          for (int k = 0; k < NS; ++k) v = fmaf(F.L[k][jj], x[k], v);
+          y[jj] = v;
         }
-      if (BASIS == MPMI_BASIS_RACE_CAR) {
+        int q = 0;
+#pragma unroll
+        for (int k = 0; k < NS; ++k)
+#pragma unroll
+          for (int l = k; l < NS; ++l, ++q) {
+            float kv[J];
+            ldsJ<J>(&kk[(D + q) * 8 + colpos], kv);
+            const float p = x[k] * x[l];
+#pragma unroll
+            for (int jj = 0; jj < J; ++jj) y[jj] = fmaf(p, kv[jj], y[jj]);
+          }
         const float tp[6] = {sp * x[3], sp * x[4], sp * x[5], cp * x[3], cp * x[4], cp * x[5]};
 #pragma unroll
-        for (int t = 0; t < 6; ++t) {
+        for (int r = 0; r < 6; ++r) {
           float kv[J];
-          ldsJ<J>(&kk[(D + 21 + t) * 8 + colpos], kv);
+          ldsJ<J>(&kk[(D + 21 + r) * 8 + colpos], kv);
 #pragma unroll
-          for (int jj = 0; jj < J; ++jj) y[jj] = fmaf(tp[t], kv[jj], y[jj]);
+          for (int jj = 0; jj < J; ++jj) y[jj] = fmaf(tp[r], kv[jj], y[jj]);
+        }
+      } else {
+        // y = c + sum_k x_k (L_k + sum_{l >= k} Q_kl x_l) per output column.
+#pragma unroll
+        for (int jj = 0; jj < J; ++jj) y[jj] = F.cu[jj];
+        int q = 0;
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+          float t[J];
+#pragma unroll
+          for (int jj = 0; jj < J; ++jj) t[jj] = F.L[k][jj];
+#pragma unroll
+          for (int l = k; l < NS; ++l, ++q) {
+            float kv[J];
+            ldsJ<J>(&kk[(D + q) * 8 + colpos], kv);
+#pragma unroll
+            for (int jj = 0; jj < J; ++jj) t[jj] = fmaf(kv[jj], x[l], t[jj]);
+          }
+#pragma unroll
+          for (int jj = 0; jj < J; ++jj) y[jj] = fmaf(x[k], t[jj], y[jj]);
         }
       }
       (void)R;
       // Rebuild the full state from the group's lanes.
 #pragma unroll
       for (int j = 0; j < NS; ++j) x[j] = __shfl(y[j % J], base + j / J, 64);
+      settle_state<NS>(x);
       if (!(min_margin<NS>(md, x) > 0.0f)) {
         fv = s;
         break;
