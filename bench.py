@@ -347,11 +347,20 @@ def run_plain_vs_learned(n_ticks: int = 500, warmup: int = 20):
     st = setup(WORKLOADS["race_car"], 64)
     ctx, model = st["ctx"], st["model"]
     stream = torch.cuda.current_stream()
+    # Launch shapes (block, lanes per candidate) of both forms from the tick
+    # autotuner, on the first tick's inputs.
     plain = mpmi.tick_desc(128 * 128, 60, gen=mpmi.GEN_GRID, grid=[128, 128], loop=0)
+    shapes = {"plain": mpmi.mpmi_tick_autotune(ctx, model, plain, st["x"][0], st["u"][0], reps=20)}
     out = {}
     runs = [("plain", None)]
     if os.path.exists(ASSET):
-        runs.append(("learned", LearnedTicker(ctx, model, ProposalNet.load(ctx, ASSET))))
+        ticker = LearnedTicker(ctx, model, ProposalNet.load(ctx, ASSET))
+        ticker.tick(st["x"][0], st["u"][0], tick=0)  # fills ticker.cand with the first tick's proposals
+        pdesc = mpmi.tick_desc(ticker.P, ticker.H, gen=mpmi.GEN_EXPLICIT, loop=ticker.loop)
+        shapes["learned"] = mpmi.mpmi_tick_autotune(ctx, model, pdesc, st["x"][0], st["u"][0],
+                                                    cand=ticker.cand.reshape(-1), reps=20)
+        ticker.lanes, ticker.block = pdesc.lanes_per_cand, pdesc.block
+        runs.append(("learned", ticker))
     for name, ticker in runs:
         outs = torch.empty((64, mpmi.SELECTION_BYTES), dtype=torch.uint8, device="cuda")
 
@@ -379,7 +388,7 @@ def run_plain_vs_learned(n_ticks: int = 500, warmup: int = 20):
         ncand = float(np.mean([s["n_cand"] for s in sels]))
         out[name] = {"trajectories_per_s": ncand * n_ticks / wall, "candidates_per_tick": ncand,
                      "p50_tick_ms": float(np.percentile(ms, 50)), "p99_tick_ms": float(np.percentile(ms, 99)),
-                     "ms_per_tick": wall * 1e3 / n_ticks}
+                     "ms_per_tick": wall * 1e3 / n_ticks, "launch_shape": shapes[name]}
         if ticker is not None:
             out[name]["fallback_rate"] = float(np.mean([s["n_cand"] != ticker.P + 1 for s in sels]))
     if "learned" not in out:

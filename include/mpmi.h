@@ -411,11 +411,13 @@ mpmi_status mlp_adam(mpmi_ctx ctx, float* w_f32, uint16_t* w_bf16, float* adam_m
 mpmi_status mdn_sample(mpmi_ctx ctx, const void* model, const float* head, int32_t P, uint64_t seed,
                        uint64_t tick, int32_t loop, float* cand, void* stream);
 
-/* A learned-proposal tick: network on [x_t; u_user], P = prop->n_cand
- * proposals drawn with (prop->seed, prop->tick, prop->loop), a fused tick
- * over {u_user} + proposals (EXPLICIT) into *out, then the exhaustive
- * fallback tick described by *fallback (GRID or UNIFORM), which runs only if
- * *out holds MPMI_NO_SAFE and then overwrites it (out->n_cand tells which
+/* A learned-proposal tick: network on [x_t; u_user] (one single-workgroup
+ * launch, the same arithmetic rules as mlp_forward, accumulation in input
+ * order), P = prop->n_cand proposals drawn with (prop->seed, prop->tick,
+ * prop->loop), a fused tick over {u_user} + proposals (EXPLICIT; block and
+ * lanes_per_cand as in mpmi_tick) into *out, then the exhaustive fallback
+ * tick described by *fallback (GRID or UNIFORM), which runs only if *out
+ * holds MPMI_NO_SAFE and then overwrites it (out->n_cand tells which
  * candidate set decided).  cand_work [1][2][P] device; head_out [80] device
  * or NULL.  Race-car models only. */
 mpmi_status mpmi_proposal_tick(mpmi_ctx ctx, const void* model, const uint16_t* w_bf16, const float* w_f32,

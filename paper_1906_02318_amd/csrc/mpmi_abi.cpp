@@ -667,15 +667,20 @@ mpmi_status mpmi_proposal_tick(mpmi_ctx ctx, const void* model, const uint16_t* 
   if (pd.precision != MPMI_PREC_FP32 || fallback->precision != MPMI_PREC_FP32)
     return fail(ctx, MPMI_EUNSUPPORTED, "only FP32 ticks are available");
   if (!x_t || !u_user || !cand_work || !out) return fail(ctx, MPMI_EINVAL, "x_t, u_user, cand_work, out must be non-NULL");
+  if (pd.lanes_per_cand > 1 && mpmi::system_noisy(sys))
+    return fail(ctx, MPMI_EUNSUPPORTED, "several lanes per candidate: noise-free models only");
   hipStream_t st = (hipStream_t)stream;
-  float* row = nullptr;
   float* head = nullptr;
-  hipError_t e = mpmi::launch_mlp_row(x_t, u_user, work, &row, &head, st);
-  if (head_out) head = head_out;
-  if (e == hipSuccess) e = mpmi::launch_mlp_forward(w_bf16, w_f32, in_mean, in_std, row, 1, head, work, st);
+  hipError_t e = mpmi::launch_mlp_row_forward(x_t, u_user, w_bf16, w_f32, in_mean, in_std, work, head_out, &head, st);
   if (e == hipSuccess) e = mpmi::launch_mdn_sample(model, head, pd.n_cand, pd.seed, pd.tick, pd.loop, cand_work, st);
   void* slot = (char*)ctx->slots + (size_t)pd.loop * mpmi::slot_bytes();
-  if (e == hipSuccess) e = mpmi::launch_tick(sys, model, pd, x_t, u_user, cand_work, slot, out, nullptr, nullptr, st);
+  if (e == hipSuccess) {
+    if (pd.lanes_per_cand > 1)
+      e = mpmi::launch_tick_split(sys.basis, pd.lanes_per_cand, model, pd, x_t, u_user, cand_work, slot, out, nullptr,
+                                  st);
+    else
+      e = mpmi::launch_tick(sys, model, pd, x_t, u_user, cand_work, slot, out, nullptr, nullptr, st);
+  }
   void* slot2 = (char*)ctx->slots + (size_t)fallback->loop * mpmi::slot_bytes();
   if (e == hipSuccess)
     e = mpmi::launch_tick(sys, model, *fallback, x_t, u_user, nullptr, slot2, out, nullptr, nullptr, st, out);

@@ -264,6 +264,65 @@ __global__ void mdn_sample_kernel(const ModelDev* __restrict__ md, const float* 
   }
 }
 
+// Offsets of (W_l, b_l) in the flat parameter vector (per layer W[in][out]
+// then b[out]), as plain constants: device code must not call a recursive
+// function (it would need a call stack of unbounded depth).
+constexpr size_t kMlpW0 = 0;
+constexpr size_t kMlpB0 = kMlpW0 + (size_t)kMlpIn * kMlpHid;
+constexpr size_t kMlpW1 = kMlpB0 + kMlpHid;
+constexpr size_t kMlpB1 = kMlpW1 + (size_t)kMlpHid * kMlpHid;
+constexpr size_t kMlpW2 = kMlpB1 + kMlpHid;
+constexpr size_t kMlpB2 = kMlpW2 + (size_t)kMlpHid * kMlpHid;
+constexpr size_t kMlpW3 = kMlpB2 + kMlpHid;
+constexpr size_t kMlpB3 = kMlpW3 + (size_t)kMlpHid * kMlpOut;
+static_assert(kMlpB3 + kMlpOut == MPMI_MLP_PARAMS, "parameter layout");
+
+// Forward pass of the one row [x_t; u_user] in one workgroup: lane j owns
+// unit j of each layer and the activations stay in LDS.  The arithmetic
+// rules are the batched path's (standardised input and activations rounded
+// to BF16, BF16 weights, FP32 accumulation, FP32 bias added last); the
+// accumulation runs in input order.  A serving tick needs one row, for which
+// a 64x64-tile GEMM per layer is four launches of mostly idle tiles.
+template <int L>
+__device__ __forceinline__ void mlp_row_layer(const float* hin, float* hout, const uint16_t* __restrict__ w16,
+                                              const float* __restrict__ w32, float* __restrict__ Y) {
+  constexpr int din = L == 0 ? kMlpIn : kMlpHid;
+  constexpr int dout = L == 3 ? kMlpOut : kMlpHid;
+  constexpr size_t woff = L == 0 ? kMlpW0 : L == 1 ? kMlpW1 : L == 2 ? kMlpW2 : kMlpW3;
+  constexpr size_t boff = L == 0 ? kMlpB0 : L == 1 ? kMlpB1 : L == 2 ? kMlpB2 : kMlpB3;
+  const int j = threadIdx.x;
+  if (j < dout) {
+    const uint16_t* W = w16 + woff + j;
+    float acc = 0.0f;
+#pragma unroll 16
+    for (int i = 0; i < din; ++i) acc = fmaf(hin[i], bf2f(W[(size_t)i * dout]), acc);
+    const float v = acc + w32[boff + j];
+    if constexpr (L < 3) hout[j] = bf2f(f2bf(gelu_f(v)));
+    else Y[j] = v;
+  }
+  __syncthreads();
+}
+
+__global__ void __launch_bounds__(256) mlp_row_forward_kernel(const float* __restrict__ x_t,
+                                                              const float* __restrict__ u_user,
+                                                              const uint16_t* __restrict__ w16,
+                                                              const float* __restrict__ w32,
+                                                              const float* __restrict__ mean,
+                                                              const float* __restrict__ stdv,
+                                                              float* __restrict__ Y) {
+  __shared__ float bufA[kMlpHid], bufB[kMlpHid];
+  const int j = threadIdx.x;
+  if (j < kMlpIn) {
+    const float xv = j < 6 ? x_t[j] : u_user[j - 6];
+    bufA[j] = bf2f(f2bf((xv - mean[j]) / stdv[j]));
+  }
+  __syncthreads();
+  mlp_row_layer<0>(bufA, bufB, w16, w32, Y);
+  mlp_row_layer<1>(bufB, bufA, w16, w32, Y);
+  mlp_row_layer<2>(bufA, bufB, w16, w32, Y);
+  mlp_row_layer<3>(bufB, bufA, w16, w32, Y);
+}
+
 // [x_t; u_user] -> one input row.
 __global__ void mlp_row_kernel(const float* __restrict__ x_t, const float* __restrict__ u_user,
                                float* __restrict__ X) {
@@ -418,6 +477,15 @@ hipError_t launch_mdn_sample(const void* model, const float* Yrow, int P, uint64
 
 // Assembles the single input row in the workspace; *row is that row and
 // *head the workspace's output area for a one-row forward.
+hipError_t launch_mlp_row_forward(const float* x_t, const float* u_user, const uint16_t* w16, const float* w32,
+                                  const float* mean, const float* stdv, void* work, float* head_out, float** head,
+                                  hipStream_t st) {
+  const MlpWork w = carve(work, 1);
+  *head = head_out ? head_out : w.Y;
+  mlp_row_forward_kernel<<<1, 256, 0, st>>>(x_t, u_user, w16, w32, mean, stdv, *head);
+  return hipGetLastError();
+}
+
 hipError_t launch_mlp_row(const float* x_t, const float* u_user, void* work, float** row, float** head,
                           hipStream_t st) {
   const MlpWork w = carve(work, 1);

@@ -85,6 +85,38 @@ def test_mlp_forward_parity(ctx, batch):
     assert rel < 3e-2
 
 
+def test_single_row_forward_parity(ctx, batch):
+    """The serving tick's one-workgroup forward (head_out of mpmi_proposal_tick)
+    against the oracle, to the batched forward's bound, and against the batched
+    kernels on the same rows: the same rounding rules, differing only in the
+    FP32 accumulation order (and the BF16 activations that order can flip)."""
+    X, T, flat, mean, std = batch
+    net = net_tensors(flat, mean, std)
+    model = mpmi.mpmi_model_pack(ctx, mpmi.race_car_system(W.track_dict(W.rc_track())),
+                                 torch.tensor(W.rc_model()[0], device="cuda"))
+    work = mpmi.mlp_workspace(ctx, 1)
+    P = 64
+    cand_work = torch.empty((1, 2, P), device="cuda")
+    head = torch.empty(80, device="cuda")
+    rows = X[:16]
+    Yb = mpmi.mlp_forward(ctx, net["w16"], net["w32"], net["mean"], net["std"],
+                          torch.tensor(rows, dtype=torch.float32, device="cuda")).cpu().numpy()
+    Yo, _ = M.forward(effective_params(flat), rows, mean, std)
+    fb = mpmi.tick_desc(256, 20, gen=mpmi.GEN_GRID, grid=[16, 16], loop=2)
+    worst_o, worst_b = 0.0, 0.0
+    for i, r in enumerate(rows):
+        xt = torch.tensor(r[:6], dtype=torch.float32, device="cuda")
+        ut = torch.tensor(r[6:], dtype=torch.float32, device="cuda")
+        prop = mpmi.tick_desc(P, 20, gen=mpmi.GEN_EXPLICIT, seed=3, tick=i, loop=1)
+        mpmi.mpmi_proposal_tick(ctx, model, net, xt, ut, prop, fb, cand_work, work, head_out=head)
+        y = head.cpu().numpy().astype(np.float64)
+        scale = np.sqrt(np.mean(Yo[i] ** 2))
+        worst_o = max(worst_o, np.abs(y - Yo[i]).max() / scale)
+        worst_b = max(worst_b, np.abs(y - Yb[i]).max() / scale)
+    log(f"[mlp] single-row forward: max err / rms vs oracle {worst_o:.3e}, vs batched kernels {worst_b:.3e}")
+    assert worst_o < 3e-2 and worst_b < 3e-2
+
+
 def test_mlp_gradient_parity(ctx, batch):
     X, T, flat, mean, std = batch
     net = net_tensors(flat, mean, std)
