@@ -27,12 +27,29 @@ FLAGS = [
 ]
 
 
+def _dynamic_stack_kernels(remarks: str) -> list:
+    """Kernels the compiler reports with a dynamic stack (a device call whose
+    depth it cannot bound, e.g. recursion): their private segment can overflow."""
+    bad, name = [], None
+    for line in remarks.splitlines():
+        if "remark: Function Name:" in line:
+            name = line.split("Function Name:", 1)[1].split("[-Rpass")[0].strip()
+        elif "remark:     Dynamic Stack: True" in line and name:
+            bad.append(name)
+    return bad
+
+
 def _compile(src: str) -> str:
     out = os.path.join(OBJ, os.path.splitext(src)[0] + ".o")
     cmd = [HIPCC, *FLAGS, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", out]
+    if src.endswith(".hip"):
+        cmd.append("-Rpass-analysis=kernel-resource-usage")
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    bad = _dynamic_stack_kernels(r.stderr)
+    if bad:
+        raise RuntimeError(f"{src}: device code with a dynamic stack (unbounded device calls): {bad}")
     return out
 
 
