@@ -5,8 +5,9 @@
 //              of Z^T Z restricted to the first D rows, Z = [Psi | Y];
 //   2. reduce: partial sums added in a fixed order (deterministic);
 //   3. solve:  one workgroup: RMS column scaling, ridge, Cholesky of the
-//              scaled Gram matrix in LDS, two triangular solves, unscaling,
-//              and a power-iteration estimate of the condition number.
+//              scaled Gram matrix in LDS, then, one wave per task, the two
+//              triangular solves per right-hand side, unscaling, and power /
+//              inverse iteration for the condition number.
 #include <hip/hip_runtime.h>
 
 #include "mpmi_launch.hpp"
@@ -111,6 +112,48 @@ __global__ void reduce_kernel(int nparts, int E, const double* __restrict__ part
   tot[e] = s;
 }
 
+// Value of x in lane k (k wave-uniform), to every lane of the wave.
+__device__ __forceinline__ double lane_bcast(double x, int k) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, k);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), k);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Sum over the 64 lanes (butterfly, the same order in every lane).
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+  return x;
+}
+
+// L z = b with the Cholesky factor in the lower triangle of Lf (diagonal
+// included): lane i holds b_i and returns z_i (lanes >= D hold 0).  Column
+// by column: z_k = r_k / L_kk once lane k's residual r_k is complete, then
+// every later row subtracts L_ik z_k.
+template <int LD>
+__device__ __forceinline__ double wave_lower_solve(const double (&Lf)[MPMI_MAX_DIM][LD], int D, int lane, double b) {
+  double r = b, z = 0.0;
+  for (int k = 0; k < D; ++k) {
+    const double zk = lane_bcast(r, k) / Lf[k][k];
+    if (lane == k) z = zk;
+    if (lane > k && lane < D) r = fma(-Lf[lane][k], zk, r);
+  }
+  return z;
+}
+
+// L^T y = z, the same way from the last row up.
+template <int LD>
+__device__ __forceinline__ double wave_upper_solve(const double (&Lf)[MPMI_MAX_DIM][LD], int D, int lane, double z) {
+  double r = z, y = 0.0;
+  for (int k = D - 1; k >= 0; --k) {
+    const double yk = lane_bcast(r, k) / Lf[k][k];
+    if (lane == k) y = yk;
+    if (lane < k) r = fma(-Lf[k][lane], yk, r);
+  }
+  return y;
+}
+
 // One workgroup.  tot holds [D][C]: G = columns 0..D-1, A = columns D..D+n-1.
 __global__ void __launch_bounds__(kFitThreads)
 solve_kernel(int n, int D, long long T, double ridge, const double* __restrict__ tot, double* __restrict__ K,
@@ -118,8 +161,6 @@ solve_kernel(int n, int D, long long T, double ridge, const double* __restrict__
   __shared__ double L[MPMI_MAX_DIM][MPMI_MAX_DIM + 1];
   __shared__ double B[MPMI_MAX_DIM][MPMI_MAX_STATE];
   __shared__ double sc[MPMI_MAX_DIM];
-  __shared__ double v[MPMI_MAX_DIM], w[MPMI_MAX_DIM];
-  __shared__ double red[kFitThreads];
   __shared__ int bad;
   const int t = threadIdx.x;
   const int C = D + n;
@@ -162,92 +203,52 @@ solve_kernel(int n, int D, long long T, double ridge, const double* __restrict__
     }
     __syncthreads();
   }
-  // Forward (L z = b) and back (L^T k = z) substitution, one thread per column.
-  if (t < n) {
-    for (int i = 0; i < D; ++i) {
-      double s = B[i][t];
-      for (int k = 0; k < i; ++k) s -= L[i][k] * B[k][t];
-      B[i][t] = s / L[i][i];
-    }
-    for (int i = D - 1; i >= 0; --i) {
-      double s = B[i][t];
-      for (int k = i + 1; k < D; ++k) s -= L[k][i] * B[k][t];
-      B[i][t] = s / L[i][i];
-    }
+  // Triangular solves and the condition estimate run one wave per task: lane
+  // i owns row i (D <= 64), the wave's lockstep orders the steps, and the
+  // values a step needs from another lane arrive by lane broadcast, so no
+  // workgroup barrier is involved.  The factor is read-only from here on.
+  const int lane = t & 63, wave = t >> 6;
+  const bool own = lane < D;
+  // K: wave q solves the right-hand sides q, q + 4 (n <= 8 columns).
+  for (int c = wave; c < n; c += kFitThreads / 64) {
+    const double z = wave_lower_solve(L, D, lane, own ? B[lane][c] : 0.0);
+    const double k = wave_upper_solve(L, D, lane, z);
+    if (own) K[(size_t)lane * n + c] = k / sc[lane];
   }
-  __syncthreads();
-  for (int e = t; e < D * n; e += blockDim.x) {
-    const int i = e / n, j = e % n;
-    K[(size_t)i * n + j] = B[i][j] / sc[i];
-  }
-  // Condition estimate of the scaled Gram matrix G_s: power iteration for the
-  // largest eigenvalue (G_s from its upper triangle + diagonal L L^T), inverse
-  // iteration through the Cholesky factor for the smallest.
-  for (int i = t; i < D; i += blockDim.x) v[i] = 1.0 + 0.01 * i;
-  __syncthreads();
-  double lmax = 0.0, lmin_inv = 0.0;
-  for (int it = 0; it < 60; ++it) {
-    // w = G_s v (diagonal of G_s is sum_k L[i][k]^2 for k <= i)
-    for (int i = t; i < D; i += blockDim.x) {
-      double s = 0.0;
+  // Condition estimate of the scaled Gram matrix G_s (wave 0): power
+  // iteration for the largest eigenvalue (G_s from its upper triangle and
+  // the diagonal of L L^T), inverse iteration through the Cholesky factor
+  // for the smallest.
+  if (wave == 0) {
+    double diag = 0.0;
+    if (own)
+      for (int k = 0; k <= lane; ++k) diag += L[lane][k] * L[lane][k];
+    double v = own ? 1.0 + 0.01 * lane : 0.0;
+    double lmax = 0.0;
+    for (int it = 0; it < 60; ++it) {
+      double w = 0.0;
       for (int j = 0; j < D; ++j) {
-        double g;
-        if (i == j) {
-          g = 0.0;
-          for (int k = 0; k <= i; ++k) g += L[i][k] * L[i][k];
-        } else {
-          g = i < j ? L[i][j] : L[j][i];
-        }
-        s += g * v[j];
+        const double vj = lane_bcast(v, j);
+        const double g = lane == j ? diag : (lane < j ? L[lane][j] : L[j][lane]);
+        w = own ? fma(g, vj, w) : 0.0;
       }
-      w[i] = s;
+      const double nn = sqrt(wave_sum(w * w));
+      lmax = wave_sum(w * v);
+      v = w / nn;
     }
-    __syncthreads();
-    if (t == 0) {
-      double nn = 0.0, dot = 0.0;
-      for (int i = 0; i < D; ++i) {
-        nn += w[i] * w[i];
-        dot += w[i] * v[i];
-      }
-      nn = sqrt(nn);
-      lmax = dot;
-      for (int i = 0; i < D; ++i) v[i] = w[i] / nn;
-      red[0] = lmax;
+    v = own ? 1.0 - 0.01 * lane : 0.0;
+    double lmin_inv = 0.0;
+    for (int it = 0; it < 60; ++it) {
+      const double w = wave_upper_solve(L, D, lane, wave_lower_solve(L, D, lane, v));
+      const double nn = sqrt(wave_sum(w * w));
+      lmin_inv = wave_sum(w * v);
+      v = w / nn;
     }
-    __syncthreads();
-  }
-  lmax = red[0];
-  for (int i = t; i < D; i += blockDim.x) v[i] = 1.0 - 0.01 * i;
-  __syncthreads();
-  for (int it = 0; it < 60; ++it) {
-    if (t == 0) {
-      // w = G_s^{-1} v via L L^T
-      for (int i = 0; i < D; ++i) {
-        double s = v[i];
-        for (int k = 0; k < i; ++k) s -= L[i][k] * w[k];
-        w[i] = s / L[i][i];
-      }
-      for (int i = D - 1; i >= 0; --i) {
-        double s = w[i];
-        for (int k = i + 1; k < D; ++k) s -= L[k][i] * w[k];
-        w[i] = s / L[i][i];
-      }
-      double nn = 0.0, dot = 0.0;
-      for (int i = 0; i < D; ++i) {
-        nn += w[i] * w[i];
-        dot += w[i] * v[i];
-      }
-      nn = sqrt(nn);
-      lmin_inv = dot;
-      for (int i = 0; i < D; ++i) v[i] = w[i] / nn;
-      red[1] = lmin_inv;
+    if (lane == 0) {
+      info->status = bad ? MPMI_ESINGULAR : MPMI_OK;
+      const double cg = lmax * lmin_inv;
+      info->cond = cg > 0.0 ? sqrt(cg) : INFINITY;
     }
-    __syncthreads();
-  }
-  if (t == 0) {
-    info->status = bad ? MPMI_ESINGULAR : MPMI_OK;
-    const double cg = red[0] * red[1];
-    info->cond = cg > 0.0 ? sqrt(cg) : INFINITY;
   }
 }
 
