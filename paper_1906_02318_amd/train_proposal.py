@@ -1,7 +1,7 @@
 """Trains the race-car proposal network on labels produced by the exhaustive
 tick, then evaluates it against the exhaustive sampler.
 
-python -m paper_1906_02318_amd.train_proposal --labels 2000000 --epochs 8 --out PATH
+python -m paper_1906_02318_amd.train_proposal --labels 2000000 --epochs 40 --out PATH
 
 Prints one JSON summary line (labels, losses, agreement and cost gaps).
 """
@@ -84,7 +84,7 @@ def evaluate(ctx, model, net, track, n_ticks=1000, seed=8, proposals=2048, log=p
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--labels", type=int, default=2_000_000)
-    ap.add_argument("--epochs", type=int, default=8)
+    ap.add_argument("--epochs", type=int, default=40)
     ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--eval-ticks", type=int, default=1000)
