@@ -144,10 +144,9 @@ mpmi_status mpmi_create(mpmi_ctx* out, int32_t device) {
     mpmi_destroy(ctx);
     return MPMI_ENOMEM;
   }
-  // Reset state of a slot: both keys all-ones, counters zero (one copy of a
-  // host image of all slots).
+  // All slots in their reset state (one copy of a host image).
   std::vector<unsigned char> image(slot_bytes, 0);
-  for (int i = 0; i < MPMI_MAX_LOOPS; ++i) std::memset(image.data() + (size_t)i * mpmi::slot_bytes(), 0xff, 16);
+  mpmi::slot_reset_image(image.data(), MPMI_MAX_LOOPS);
   if (hipMemcpy(ctx->slots, image.data(), slot_bytes, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemset(ctx->recheck, 0, 256) != hipSuccess) {
     mpmi_destroy(ctx);
@@ -316,7 +315,7 @@ mpmi_status mpmi_tick(mpmi_ctx ctx, const void* model, const mpmi_tick_desc* des
     if (desc->block > 256) return fail(ctx, MPMI_EUNSUPPORTED, "several lanes per candidate: block <= 256");
     if (mpmi::system_noisy(sys))
       return fail(ctx, MPMI_EUNSUPPORTED, "several lanes per candidate: noise-free models only");
-    return check_hip(ctx, mpmi::launch_tick_split(sys.basis, desc->lanes_per_cand, model, *desc, x_t, u_user, cand,
+    return check_hip(ctx, mpmi::launch_tick_split(sys, desc->lanes_per_cand, model, *desc, x_t, u_user, cand,
                                                   slot, out, first_violation, (hipStream_t)stream),
                      "mpmi_tick (split) launch");
   }
@@ -676,7 +675,7 @@ mpmi_status mpmi_proposal_tick(mpmi_ctx ctx, const void* model, const uint16_t* 
   void* slot = (char*)ctx->slots + (size_t)pd.loop * mpmi::slot_bytes();
   if (e == hipSuccess) {
     if (pd.lanes_per_cand > 1)
-      e = mpmi::launch_tick_split(sys.basis, pd.lanes_per_cand, model, pd, x_t, u_user, cand_work, slot, out, nullptr,
+      e = mpmi::launch_tick_split(sys, pd.lanes_per_cand, model, pd, x_t, u_user, cand_work, slot, out, nullptr,
                                   st);
     else
       e = mpmi::launch_tick(sys, model, pd, x_t, u_user, cand_work, slot, out, nullptr, nullptr, st);

@@ -221,10 +221,11 @@ tick_bf16_race_car_kernel(const ModelDev* __restrict__ md, GenParams gp, int H, 
       bcnt += s_cnt[w];
       bre += s_re[w];
     }
-    if (bks != kKeyNone) atomicMin(&slot->key_safe, bks);
-    if (bkf != kKeyNone) atomicMin(&slot->key_fb, bkf);
-    if (bcnt) atomicAdd(&slot->n_safe, bcnt);
-    if (bre) atomicAdd(&slot->n_recheck, bre);
+    SubSlot* ss = &slot->sub[blockIdx.x % kSubSlots];
+    if (bks != kKeyNone) atomicMin(&ss->key_safe, bks);
+    if (bkf != kKeyNone) atomicMin(&ss->key_fb, bkf);
+    if (bcnt) atomicAdd(&ss->count, (unsigned long long)bcnt);
+    if (bre) atomicAdd(&ss->n_recheck, bre);
   }
 }
 
@@ -256,8 +257,8 @@ recheck_race_car_kernel(const ModelDev* __restrict__ md, GenParams gp, int H, co
   unsigned int wsum = n_safe_local;
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) wsum += __shfl_xor(wsum, off, 64);
-  if ((threadIdx.x & 63) == 0 && wsum) atomicAdd(&slot->n_safe, wsum);
-  if (reduce_and_publish(ks, kf, false, slot, gridDim.x) && threadIdx.x == 0) {
+  if ((threadIdx.x & 63) == 0 && wsum) atomicAdd(&slot->sub[blockIdx.x % kSubSlots].count, (unsigned long long)wsum);
+  if (reduce_and_publish(ks, kf, false, slot, gridDim.x, blockIdx.x) && threadIdx.x == 0) {
     finalize<2>(md, gp, cand, u_user, H, slot, out);
     rl->count = 0u;
     __threadfence();

@@ -70,17 +70,28 @@ struct alignas(256) ModelDev {
   uint32_t Rlo[kRTileWords];      // BF16 lo split of R
 };
 
-// Per-loop selection slot (context-owned device memory).  Keys are reduced
-// with 64-bit atomicMin; the last workgroup of a launch decodes them, writes
-// the mpmi_selection and restores the slot to its reset state.
-struct Slot {
+// Per-loop selection slot (context-owned device memory).  The memory-side
+// atomic unit performs atomics on one address one after another, so the
+// workgroups ("parts") of a launch publish into kSubSlots sub-slots, part p
+// into sub-slot p % kSubSlots: keys by 64-bit atomicMin, and the safe count
+// together with a per-sub-slot ticket by one 64-bit atomicAdd.  The last part
+// of a sub-slot takes a ticket on the slot; the last of those decodes the keys
+// of all sub-slots, writes the mpmi_selection and restores the reset state
+// (keys all-ones, counters zero).
+constexpr int kSubSlots = 8;
+struct alignas(64) SubSlot {
   unsigned long long key_safe;  // (cost bits << 32) | idx  over safe candidates
   unsigned long long key_fb;    // ((255 - fv) << 56) | (cost bits << 25) | idx
-  unsigned int n_safe;
-  unsigned int done;
+  unsigned long long count;     // low 32 bits: safe count; high 32: parts published
   unsigned int n_recheck;
-  unsigned int pad;
+  unsigned int pad[9];
 };
+struct alignas(64) Slot {
+  SubSlot sub[kSubSlots];
+  unsigned int done;  // sub-slots whose parts have all published
+  unsigned int pad[15];
+};
+static_assert(sizeof(SubSlot) == 64 && sizeof(Slot) == 64 * (kSubSlots + 1), "slot layout");
 constexpr unsigned long long kKeyNone = ~0ull;
 
 // ---------------------------------------------------------------------------

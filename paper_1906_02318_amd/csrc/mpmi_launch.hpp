@@ -14,6 +14,8 @@ namespace mpmi {
 
 size_t model_bytes();
 size_t slot_bytes();
+// Host image of n slots in their reset state (keys all-ones, counters zero).
+void slot_reset_image(unsigned char* dst, int n);
 
 hipError_t launch_pack(const mpmi_system& sys, int dim, int state_feat0, const double* K, void* model,
                        hipStream_t st);
@@ -52,9 +54,9 @@ hipError_t launch_fit(const mpmi_system& sys, int dim, const double* X, const do
                       int64_t T, double ridge, double* K_out, void* work, hipStream_t st);
 
 // Latency form of the tick (mpmi_split.hip).
-hipError_t launch_tick_split(int basis, int split, const void* model, const mpmi_tick_desc& d, const float* x_t,
-                             const float* u_user, const float* cand, void* slot, mpmi_selection* out, int16_t* fv,
-                             hipStream_t st);
+hipError_t launch_tick_split(const mpmi_system& sys, int split, const void* model, const mpmi_tick_desc& d,
+                             const float* x_t, const float* u_user, const float* cand, void* slot,
+                             mpmi_selection* out, int16_t* fv, hipStream_t st);
 
 // BF16X3 race-car tick + FP32 recheck (mpmi_bf16.hip).
 constexpr int kRecheckCapacity = 1 << 22;

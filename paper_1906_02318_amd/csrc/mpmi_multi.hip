@@ -72,7 +72,8 @@ multi_kernel(const mpmi_loop_desc* __restrict__ loops, const ModelDev* __restric
     r = evaluate_candidate<MPMI_BASIS_LINEAR, NOISE>(md, sK, gp, H, L->x_t, L->u_user, L->cand, c,
                                                      L->first_violation, nullptr);
   Slot* slot = &slots[w.loop];
-  if (reduce_and_publish(r.ks, r.kf, r.safe_counted, slot, (unsigned int)n_tiles[w.loop]) && threadIdx.x == 0) {
+  if (reduce_and_publish(r.ks, r.kf, r.safe_counted, slot, (unsigned int)n_tiles[w.loop], w.tile) &&
+      threadIdx.x == 0) {
     finalize<MPMI_MAX_INPUT>(md, gp, L->cand, L->u_user, H, slot, L->out);
     ticks[w.loop] = gp.tick + 1;
     __threadfence();
@@ -114,13 +115,9 @@ hipError_t multi_alloc(MultiPlan& p) {
   if ((e = hipMemcpy(p.d_loops, p.host.data(), sizeof(mpmi_loop_desc) * p.n_loops, hipMemcpyHostToDevice)) !=
       hipSuccess)
     return e;
-  std::vector<Slot> s(p.n_loops);
-  for (auto& x : s) {
-    x.key_safe = kKeyNone;
-    x.key_fb = kKeyNone;
-    x.n_safe = x.done = x.n_recheck = x.pad = 0;
-  }
-  return hipMemcpy(p.d_slots, s.data(), sizeof(Slot) * p.n_loops, hipMemcpyHostToDevice);
+  std::vector<unsigned char> s(sizeof(Slot) * p.n_loops);
+  slot_reset_image(s.data(), p.n_loops);
+  return hipMemcpy(p.d_slots, s.data(), s.size(), hipMemcpyHostToDevice);
 }
 
 void multi_free(MultiPlan& p) {

@@ -116,7 +116,100 @@ struct SplitFold {
   }
 };
 
-template <int BASIS, int SPLIT>
+// This lane's columns of the per-step rows (quadratic state features, and for
+// the race car the six heading cross terms), held in registers for the whole
+// horizon: at one or two waves per SIMD nothing hides LDS latency, and a wave
+// of this kernel has the register file to itself.
+template <int BASIS, int J>
+struct SplitRows {
+  static constexpr int NQ = (BASIS == MPMI_BASIS_RACE_CAR) ? 21 : 10;
+  static constexpr int NT = (BASIS == MPMI_BASIS_RACE_CAR) ? 6 : 0;
+  float q[NQ][J], t[NT > 0 ? NT : 1][J];
+  __device__ __forceinline__ void load(const float* sK8, int D, int colpos) {
+#pragma unroll
+    for (int r = 0; r < NQ; ++r) ldsJ<J>(&sK8[(D + r) * 8 + colpos], q[r]);
+#pragma unroll
+    for (int r = 0; r < NT; ++r) ldsJ<J>(&sK8[(D + NQ + r) * 8 + colpos], t[r]);
+  }
+};
+
+// The constraint constants in registers, loaded once per launch, and the
+// safety verdict of a state.  safe(x) equals min_margin(x) > 0: every margin
+// lim - |v| is positive and none is NaN exactly when |v| < lim holds for each
+// (with denormals kept, the difference of two distinct finite floats is never
+// rounded to zero, and a NaN fails either comparison).  The track's
+// centreline radius takes track_centre's operations in its order.  TRACK is
+// the model's has_track flag, fixed per kernel instance; the float constants
+// are pinned to vector registers (the scalar file is too small to hold them
+// beside the loop's own state).
+template <int NS, int DEG, bool TRACK>
+struct SafetyRegs {
+  float lim[NS], p[DEG + 1], q[DEG], trk_lim;
+  bool chk[NS];
+  __device__ __forceinline__ void load(const ModelDev* __restrict__ md) {
+    const ConstSafety* sc = (const ConstSafety*)(uintptr_t)&md->safe;
+    const int mask = sc->comp_mask;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      chk[k] = (mask >> k) & 1;
+      lim[k] = sc->comp_lim[k];
+      asm volatile("" : "+v"(lim[k]));
+    }
+    if constexpr (TRACK) {
+      trk_lim = sc->trk_lim;
+      asm volatile("" : "+v"(trk_lim));
+#pragma unroll
+      for (int k = 0; k <= DEG; ++k) {
+        p[k] = sc->trk_p[k];
+        asm volatile("" : "+v"(p[k]));
+      }
+#pragma unroll
+      for (int k = 0; k < DEG; ++k) {
+        q[k] = sc->trk_q[k];
+        asm volatile("" : "+v"(q[k]));
+      }
+    }
+  }
+  // Bitwise, not short-circuit, combination: each test is one compare into a
+  // lane mask, with no branch.
+  __device__ __forceinline__ bool safe(const float* x) const {
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) ok &= (fabsf(x[k]) < lim[k]) | !chk[k];
+    if constexpr (TRACK) {
+      const float r2 = fmaf(x[0], x[0], x[1] * x[1]);
+      const float inv = __builtin_amdgcn_rsqf(r2);
+      const float rho = r2 * inv;
+      const float c1 = x[0] * inv, s1 = x[1] * inv;
+      float P = p[DEG];
+#pragma unroll
+      for (int k = DEG - 1; k >= 0; --k) P = fmaf(P, c1, p[k]);
+      float Q = q[DEG - 1];
+#pragma unroll
+      for (int k = DEG - 2; k >= 0; --k) Q = fmaf(Q, c1, q[k]);
+      ok &= fabsf(rho - fmaf(s1, Q, P)) < trk_lim;
+    }
+    return ok;
+  }
+};
+
+// Value of v in lane `src` of this lane's group (groups of SPLIT = 2 or 4
+// lanes sit inside one quad): a DPP quad permute, no LDS round trip.
+template <int SPLIT, int SRC>
+__device__ __forceinline__ float group_lane(float v) {
+  constexpr int ctrl = (SPLIT == 4) ? SRC * 0x55 : (SRC == 0 ? 0xA0 : 0xF5);  // quad_perm selectors
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), ctrl, 0xF, 0xF, true));
+}
+
+template <int NS, int J, int SPLIT, int JJ = 0>
+__device__ __forceinline__ void rebuild_state(const float* y, float* x) {
+  if constexpr (JJ < NS) {
+    x[JJ] = group_lane<SPLIT, JJ / J>(y[JJ % J]);
+    rebuild_state<NS, J, SPLIT, JJ + 1>(y, x);
+  }
+}
+
+template <int BASIS, int SPLIT, int DEG, bool TRACK>
 __global__ void __launch_bounds__(256)
 tick_split_kernel(const ModelDev* __restrict__ md, GenParams gp, int H, const float* __restrict__ x_t,
                   const float* __restrict__ u_user, const float* __restrict__ cand, Slot* __restrict__ slot,
@@ -124,12 +217,13 @@ tick_split_kernel(const ModelDev* __restrict__ md, GenParams gp, int H, const fl
   constexpr int NS = Dims<BASIS>::N, MS = Dims<BASIS>::M;
   constexpr int J = (NS + SPLIT - 1) / SPLIT;
   constexpr int D = (BASIS == MPMI_BASIS_RACE_CAR) ? 64 : 21;
-  constexpr int R = (BASIS == MPMI_BASIS_RACE_CAR) ? kRcStepRows : 10;
+  static_assert(SPLIT == 2 || SPLIT == 4, "groups of 2 or 4 lanes (one quad)");
   __shared__ __attribute__((aligned(16))) float sK8[kSplitRows * 8];
   stage_K_split<BASIS, J>(md, sK8);
+  // Groups never straddle a quad: the launch uses a block that is a multiple
+  // of 64, so lane l of a wave holds gid with gid % 64 == l.
   const int gid = blockIdx.x * blockDim.x + threadIdx.x;
   const int c = gid / SPLIT, h = gid % SPLIT;
-  const int base = (threadIdx.x & 63) - h;  // first lane of this group within the wave
   const int Nc = gp.n_cand + 1;
   const bool valid = c < Nc;
   const int colpos = h * SplitLayout<J>::A;
@@ -144,31 +238,33 @@ tick_split_kernel(const ModelDev* __restrict__ md, GenParams gp, int H, const fl
   }
   SplitFold<BASIS, J> F;
   F.fold(sK8, colpos, u);
+  SplitRows<BASIS, J> Kr;
+  Kr.load(sK8, D, colpos);
+  SafetyRegs<NS, DEG, TRACK> sr;
+  sr.load(md);
+  // Every register above is loaded before the horizon starts, so the loop
+  // carries no wait for them.
+  __syncthreads();
   int fv = H + 1;
   if (valid) {
     const int S = gp.n_seg;
+    // Segment g covers steps s with floor((s - 1) S / H) == g; the next
+    // boundary is the least s - 1 >= ceil((g + 1) H / S).
     int gcur = 0;
+    int nxt = (H + S - 1) / S;
     for (int s = 1; s <= H; ++s) {
-      const int g = ((s - 1) * S) / H;
-      if (g != gcur) {
-        gcur = g;
+      if (s - 1 >= nxt) {
+        gcur = ((s - 1) * S) / H;
+        nxt = ((gcur + 1) * H + S - 1) / S;
 #pragma unroll
-        for (int j = 0; j < MS; ++j) u[j] = cand_value(gp, md, cand, u_user, c, g, j);
+        for (int j = 0; j < MS; ++j) u[j] = cand_value(gp, md, cand, u_user, c, gcur, j);
         F.fold(sK8, colpos, u);
-      }
-      float sp = 0.0f, cp = 0.0f;
-      if (BASIS == MPMI_BASIS_RACE_CAR) {
-        sp = __sinf(x[2]);
-        cp = __cosf(x[2]);
       }
       // Each form in the one-lane kernel's operation order, so the two give
       // bit-identical states: race car as the feature sum, balance bot nested.
-      // The opaque zero offset keeps the per-step K loads inside the loop.
-      int zoff = 0;
-      asm volatile("" : "+v"(zoff));
-      const float* kk = sK8 + zoff;
       float y[J];
       if constexpr (BASIS == MPMI_BASIS_RACE_CAR) {
+        const float sp = __sinf(x[2]), cp = __cosf(x[2]);
 #pragma unroll
         for (int jj = 0; jj < J; ++jj) {
           float v = fmaf(F.Tc[jj], cp, fmaf(F.Ts[jj], sp, F.cu[jj]));
@@ -181,20 +277,15 @@ tick_split_kernel(const ModelDev* __restrict__ md, GenParams gp, int H, const fl
         for (int k = 0; k < NS; ++k)
 #pragma unroll
           for (int l = k; l < NS; ++l, ++q) {
-            float kv[J];
-            ldsJ<J>(&kk[(D + q) * 8 + colpos], kv);
             const float p = x[k] * x[l];
 #pragma unroll
-            for (int jj = 0; jj < J; ++jj) y[jj] = fmaf(p, kv[jj], y[jj]);
+            for (int jj = 0; jj < J; ++jj) y[jj] = fmaf(p, Kr.q[q][jj], y[jj]);
           }
         const float tp[6] = {sp * x[3], sp * x[4], sp * x[5], cp * x[3], cp * x[4], cp * x[5]};
 #pragma unroll
-        for (int r = 0; r < 6; ++r) {
-          float kv[J];
-          ldsJ<J>(&kk[(D + 21 + r) * 8 + colpos], kv);
+        for (int r = 0; r < 6; ++r)
 #pragma unroll
-          for (int jj = 0; jj < J; ++jj) y[jj] = fmaf(tp[r], kv[jj], y[jj]);
-        }
+          for (int jj = 0; jj < J; ++jj) y[jj] = fmaf(tp[r], Kr.t[r][jj], y[jj]);
       } else {
         // y = c + sum_k x_k (L_k + sum_{l >= k} Q_kl x_l) per output column.
 #pragma unroll
@@ -206,22 +297,18 @@ tick_split_kernel(const ModelDev* __restrict__ md, GenParams gp, int H, const fl
 #pragma unroll
           for (int jj = 0; jj < J; ++jj) t[jj] = F.L[k][jj];
 #pragma unroll
-          for (int l = k; l < NS; ++l, ++q) {
-            float kv[J];
-            ldsJ<J>(&kk[(D + q) * 8 + colpos], kv);
+          for (int l = k; l < NS; ++l, ++q)
 #pragma unroll
-            for (int jj = 0; jj < J; ++jj) t[jj] = fmaf(kv[jj], x[l], t[jj]);
-          }
+            for (int jj = 0; jj < J; ++jj) t[jj] = fmaf(Kr.q[q][jj], x[l], t[jj]);
 #pragma unroll
           for (int jj = 0; jj < J; ++jj) y[jj] = fmaf(x[k], t[jj], y[jj]);
         }
       }
-      (void)R;
-      // Rebuild the full state from the group's lanes.
-#pragma unroll
-      for (int j = 0; j < NS; ++j) x[j] = __shfl(y[j % J], base + j / J, 64);
+      // The group's lanes hold identical states (same values, same
+      // operations), so they leave the loop at the same step.
+      rebuild_state<NS, J, SPLIT>(y, x);
       settle_state<NS>(x);
-      if (!(min_margin<NS>(md, x) > 0.0f)) {
+      if (!sr.safe(x)) {
         fv = s;
         break;
       }
@@ -233,13 +320,23 @@ tick_split_kernel(const ModelDev* __restrict__ md, GenParams gp, int H, const fl
   const bool safe = lead && fv == H + 1;
   const unsigned long long ks = safe ? safe_key(cst, c) : kKeyNone;
   const unsigned long long kf = (lead && !safe) ? fallback_key(fv, cst, c) : kKeyNone;
-  if (reduce_and_publish(ks, kf, safe && c > 0, slot, gridDim.x) && threadIdx.x == 0)
+  if (reduce_and_publish(ks, kf, safe && c > 0, slot, gridDim.x, blockIdx.x) && threadIdx.x == 0)
     finalize<MS>(md, gp, cand, u_user, H, slot, out);
 }
 
-hipError_t launch_tick_split(int basis, int split, const void* model, const mpmi_tick_desc& d, const float* x_t,
-                             const float* u_user, const float* cand, void* slot, mpmi_selection* out, int16_t* fv,
-                             hipStream_t st) {
+template <int BASIS, int DEG, bool TRACK>
+static void split_dispatch(int split, unsigned grid, int block, hipStream_t st, const ModelDev* md, const GenParams& gp,
+                           int H, const float* x_t, const float* u_user, const float* cand, Slot* sl,
+                           mpmi_selection* out, int16_t* fv) {
+  if (split == 2)
+    tick_split_kernel<BASIS, 2, DEG, TRACK><<<grid, block, 0, st>>>(md, gp, H, x_t, u_user, cand, sl, out, fv);
+  else
+    tick_split_kernel<BASIS, 4, DEG, TRACK><<<grid, block, 0, st>>>(md, gp, H, x_t, u_user, cand, sl, out, fv);
+}
+
+hipError_t launch_tick_split(const mpmi_system& sys, int split, const void* model, const mpmi_tick_desc& d,
+                             const float* x_t, const float* u_user, const float* cand, void* slot,
+                             mpmi_selection* out, int16_t* fv, hipStream_t st) {
   GenParams gp;
   gp.seed = d.seed;
   gp.tick = d.tick;
@@ -252,16 +349,24 @@ hipError_t launch_tick_split(int basis, int split, const void* model, const mpmi
   const unsigned grid = (unsigned)((((long long)d.n_cand + 1) * split + block - 1) / block);
   const ModelDev* md = (const ModelDev*)model;
   Slot* sl = (Slot*)slot;
-  if (basis == MPMI_BASIS_RACE_CAR) {
-    if (split == 2)
-      tick_split_kernel<MPMI_BASIS_RACE_CAR, 2><<<grid, block, 0, st>>>(md, gp, d.horizon, x_t, u_user, cand, sl, out, fv);
+  const int H = d.horizon;
+  const bool small = track_degree(sys) <= kSmallTrackDeg;
+  if (sys.basis == MPMI_BASIS_RACE_CAR) {
+    if (!sys.has_track)
+      split_dispatch<MPMI_BASIS_RACE_CAR, 1, false>(split, grid, block, st, md, gp, H, x_t, u_user, cand, sl, out, fv);
+    else if (small)
+      split_dispatch<MPMI_BASIS_RACE_CAR, kSmallTrackDeg, true>(split, grid, block, st, md, gp, H, x_t, u_user, cand,
+                                                                sl, out, fv);
     else
-      tick_split_kernel<MPMI_BASIS_RACE_CAR, 4><<<grid, block, 0, st>>>(md, gp, d.horizon, x_t, u_user, cand, sl, out, fv);
+      split_dispatch<MPMI_BASIS_RACE_CAR, kMaxHarm, true>(split, grid, block, st, md, gp, H, x_t, u_user, cand, sl,
+                                                          out, fv);
   } else {
-    if (split == 2)
-      tick_split_kernel<MPMI_BASIS_BALANCE_BOT, 2><<<grid, block, 0, st>>>(md, gp, d.horizon, x_t, u_user, cand, sl, out, fv);
+    if (!sys.has_track)
+      split_dispatch<MPMI_BASIS_BALANCE_BOT, 1, false>(split, grid, block, st, md, gp, H, x_t, u_user, cand, sl, out,
+                                                       fv);
     else
-      tick_split_kernel<MPMI_BASIS_BALANCE_BOT, 4><<<grid, block, 0, st>>>(md, gp, d.horizon, x_t, u_user, cand, sl, out, fv);
+      split_dispatch<MPMI_BASIS_BALANCE_BOT, kMaxHarm, true>(split, grid, block, st, md, gp, H, x_t, u_user, cand, sl,
+                                                             out, fv);
   }
   return hipGetLastError();
 }

@@ -11,6 +11,8 @@
 // the last workgroup to finish decodes the key (no second launch).
 #include <hip/hip_runtime.h>
 
+#include <cstring>
+
 #include "mpmi_device.hpp"
 #include "mpmi_launch.hpp"
 #include "mpmi_tick_common.hpp"
@@ -35,7 +37,7 @@ tick_fp32_kernel(const ModelDev* __restrict__ md, GenParams gp, int H, const flo
   stage_K<BASIS>(md, sK);
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   const CandResult r = evaluate_candidate<BASIS, NOISE, DEG>(md, sK, gp, H, x_t, u_user, cand, c, fv_out, traj);
-  if (reduce_and_publish(r.ks, r.kf, r.safe_counted, slot, gridDim.x) && threadIdx.x == 0)
+  if (reduce_and_publish(r.ks, r.kf, r.safe_counted, slot, gridDim.x, blockIdx.x) && threadIdx.x == 0)
     finalize<MS>(md, gp, cand, u_user, H, slot, out);
 }
 
@@ -113,7 +115,7 @@ select_kernel(const ModelDev* __restrict__ md, GenParams gp, int H, const float*
   const bool safe = valid && fv == H + 1;
   const unsigned long long ks = safe ? safe_key(cst, c) : kKeyNone;
   const unsigned long long kf = (valid && !safe) ? fallback_key(fv < 1 ? 1 : (fv > H ? H : fv), cst, c) : kKeyNone;
-  if (reduce_and_publish(ks, kf, safe && c > 0, slot, gridDim.x) && threadIdx.x == 0)
+  if (reduce_and_publish(ks, kf, safe && c > 0, slot, gridDim.x, blockIdx.x) && threadIdx.x == 0)
     finalize<MS>(md, gp, cand, u_user, H, slot, out);
 }
 
@@ -357,5 +359,12 @@ hipError_t launch_gen(const void* model, const mpmi_tick_desc& d, const float* u
 
 size_t model_bytes() { return sizeof(ModelDev); }
 size_t slot_bytes() { return sizeof(Slot); }
+
+void slot_reset_image(unsigned char* dst, int n) {
+  Slot r;
+  std::memset(&r, 0, sizeof(r));
+  for (int i = 0; i < kSubSlots; ++i) r.sub[i].key_safe = r.sub[i].key_fb = kKeyNone;
+  for (int l = 0; l < n; ++l) std::memcpy(dst + (size_t)l * sizeof(Slot), &r, sizeof(Slot));
+}
 
 }  // namespace mpmi

@@ -33,12 +33,13 @@ __device__ __forceinline__ float cost_of(const ModelDev* __restrict__ md, const 
   return cst;
 }
 
-// Workgroup reduction of the two keys and the safe count, then one atomic of
-// each per workgroup; returns true in every thread of the workgroup that
-// publishes last among the n_parts workgroups serving this slot.
+// Workgroup reduction of the two keys and the safe count, then the part's
+// atomics on its sub-slot (part < n_parts; n_parts parts serve this slot in
+// this launch); returns true in every thread of the workgroup that completes
+// the slot.
 __device__ __forceinline__ bool reduce_and_publish(unsigned long long ks, unsigned long long kf,
                                                    bool safe_counted, Slot* __restrict__ slot,
-                                                   unsigned int n_parts) {
+                                                   unsigned int n_parts, unsigned int part) {
   __shared__ unsigned long long s_ks[16], s_kf[16];
   __shared__ unsigned int s_cnt[16];
   __shared__ int s_last;
@@ -61,27 +62,49 @@ __device__ __forceinline__ bool reduce_and_publish(unsigned long long ks, unsign
       bkf = s_kf[w] < bkf ? s_kf[w] : bkf;
       bcnt += s_cnt[w];
     }
-    if (bks != kKeyNone) atomicMin(&slot->key_safe, bks);
-    if (bkf != kKeyNone) atomicMin(&slot->key_fb, bkf);
-    if (bcnt) atomicAdd(&slot->n_safe, bcnt);
+    const unsigned int sidx = part % kSubSlots;
+    SubSlot* ss = &slot->sub[sidx];
+    if (bks != kKeyNone) atomicMin(&ss->key_safe, bks);
+    if (bkf != kKeyNone) atomicMin(&ss->key_fb, bkf);
     __threadfence();
-    const unsigned int prev = atomicAdd(&slot->done, 1u);
-    s_last = (prev == n_parts - 1);
+    // parts p < n_parts with p % kSubSlots == sidx
+    const unsigned int in_sub = (n_parts - sidx + kSubSlots - 1) / kSubSlots;
+    const unsigned long long prev = atomicAdd(&ss->count, (1ull << 32) | (unsigned long long)bcnt);
+    bool last = false;
+    if ((unsigned int)(prev >> 32) == in_sub - 1) {
+      __threadfence();
+      const unsigned int used = n_parts < (unsigned int)kSubSlots ? n_parts : (unsigned int)kSubSlots;
+      last = atomicAdd(&slot->done, 1u) == used - 1;
+    }
+    s_last = last;
   }
   __syncthreads();
   return s_last != 0;
 }
 
 // Decodes the slot into the selection and resets the slot (one thread).
+// Every read is an atomic exchange with the reset value: it sees the value
+// the other parts' atomics left and restores the reset state in one step.
 template <int MS>
 __device__ void finalize(const ModelDev* __restrict__ md, const GenParams& gp,
                          const float* __restrict__ cand, const float* __restrict__ u_user, int H,
                          Slot* __restrict__ slot, mpmi_selection* __restrict__ out) {
   __threadfence();
-  const unsigned long long ks = atomicMin(&slot->key_safe, kKeyNone);
-  const unsigned long long kf = atomicMin(&slot->key_fb, kKeyNone);
-  const unsigned int n_safe = atomicAdd(&slot->n_safe, 0u);
-  const unsigned int n_re = atomicAdd(&slot->n_recheck, 0u);
+  unsigned long long ks = kKeyNone, kf = kKeyNone;
+  unsigned int n_safe = 0, n_re = 0;
+#pragma unroll
+  for (int i = 0; i < kSubSlots; ++i) {
+    SubSlot* ss = &slot->sub[i];
+    const unsigned long long a = atomicExch(&ss->key_safe, kKeyNone);
+    const unsigned long long b = atomicExch(&ss->key_fb, kKeyNone);
+    const unsigned long long n = atomicExch(&ss->count, 0ull);
+    const unsigned int r = atomicExch(&ss->n_recheck, 0u);
+    ks = a < ks ? a : ks;
+    kf = b < kf ? b : kf;
+    n_safe += (unsigned int)(n & 0xffffffffull);
+    n_re += r;
+  }
+  (void)atomicExch(&slot->done, 0u);
   int idx, status, fv;
   float cost;
   if (ks != kKeyNone) {
@@ -116,11 +139,6 @@ __device__ void finalize(const ModelDev* __restrict__ md, const GenParams& gp,
   sel.first_violation = fv;
   sel.n_cand = gp.n_cand + 1;
   *out = sel;
-  slot->key_safe = kKeyNone;
-  slot->key_fb = kKeyNone;
-  slot->n_safe = 0u;
-  slot->n_recheck = 0u;
-  slot->done = 0u;
   __threadfence();
 }
 

@@ -540,19 +540,56 @@ def test_tick_with_process_noise(ctx, system):
     log(f"[noise] {system}: {kinds}")
 
 
-@pytest.mark.parametrize("system", ["bb", "rc"])
-def test_tick_lanes_per_candidate_identical_and_autotuned(ctx, bb, rc, system):
-    """The latency form (2 or 4 lanes per candidate) performs the same FP32
-    operations in the same order: selections and first violations are
-    identical to the one-lane form, and the tick autotuner keeps them so."""
-    so, model, K = bb if system == "bb" else rc
-    if system == "bb":
+def _lanes_case(ctx, bb, rc, case):
+    """(model, x, u, tick-descriptor fields) of one latency-form case."""
+    if case.startswith("bb"):
+        _, model, K = bb
         x, u = W.f32(synth.balance_bot_states(1, seed=44)[0]), W.f32([3.0])
         base = dict(n_cand=10240, horizon=50, gen=mpmi.GEN_UNIFORM, n_seg=5, seed=4, tick=2)
-    else:
-        x, u = W.f32(synth.race_car_states(1, W.rc_track(), seed=44)[0]), W.f32([0.3, -2.0])
-        base = dict(n_cand=16384, horizon=60, gen=mpmi.GEN_GRID, grid=[128, 128])
+        if case == "bb_short_horizon":  # more segments than steps: boundaries skip segments
+            base.update(n_cand=1000, horizon=3, n_seg=5, seed=9)
+        elif case == "bb_h7_s4":
+            base.update(n_cand=3000, horizon=7, n_seg=4, seed=10)
+        elif case == "bb_track":  # a track on (x0, x1): the degree-8 track variant of the balance bot
+            tr = synth.Track(amp=np.array([0.05, 0.03]), freq=np.array([2, 6]), phase=np.array([0.3, 1.1]),
+                             r0=0.3, half_width=0.4)
+            sg = mpmi._sys(mpmi.BASIS_BALANCE_BOT, 4, 1, [(2, float(W.f32(0.5)), 0.0), (0, float(W.f32(2.0)), 0.0)],
+                           [-5.0], [5.0], track=W.track_dict(tr), eps_box=[5e-5, 2e-4], eps_track=1e-3)
+            model = mpmi.mpmi_model_pack(ctx, sg, dev(K, torch.float64))
+            x = W.f32([0.25, 0.1, 0.05, -0.1])
+        return model, x, u, base
+    _, model, K = rc
+    x, u = W.f32(synth.race_car_states(1, W.rc_track(), seed=44)[0]), W.f32([0.3, -2.0])
+    base = dict(n_cand=16384, horizon=60, gen=mpmi.GEN_GRID, grid=[128, 128])
+    if case == "rc_segments":
+        base = dict(n_cand=8192, horizon=45, gen=mpmi.GEN_UNIFORM, n_seg=3, seed=12, tick=5)
+    elif case == "rc_degree8_stacked_boxes":
+        tr = synth.Track(amp=np.array([1.0, 0.5, 0.3, 0.2]), freq=np.array([3, 5, 7, 8]),
+                         phase=np.random.default_rng(11).uniform(0.0, 2 * np.pi, size=4))
+        boxes = [(4, float(W.f32(2.0)), 0.0), (4, float(W.f32(1.2)), 0.0), (5, float(W.f32(0.5)), 0.0)]
+        sg = mpmi._sys(mpmi.BASIS_RACE_CAR, 6, 2, boxes, synth.RC_U_LO, synth.RC_U_HI, track=W.track_dict(tr),
+                       eps_box=[0.02] * 3, eps_track=0.02)
+        model = mpmi.mpmi_model_pack(ctx, sg, dev(K, torch.float64))
+        x = W.f32(synth.race_car_states(1, tr, seed=4, offset=1.5, vy=(-0.3, 0.3), r=(-0.2, 0.2))[0])
+        base = dict(n_cand=96 * 96, horizon=40, gen=mpmi.GEN_GRID, grid=[96, 96])
+    elif case == "rc_no_track":  # boxes only: the track-free variant
+        boxes = [(4, float(W.f32(1.0)), 0.0), (3, float(W.f32(12.0)), 0.0), (5, float(W.f32(1.5)), 0.0)]
+        sg = mpmi._sys(mpmi.BASIS_RACE_CAR, 6, 2, boxes, synth.RC_U_LO, synth.RC_U_HI, eps_box=[0.02] * 3)
+        model = mpmi.mpmi_model_pack(ctx, sg, dev(K, torch.float64))
+    return model, x, u, base
+
+
+@pytest.mark.parametrize("case", ["bb", "bb_short_horizon", "bb_h7_s4", "bb_track", "rc", "rc_segments",
+                                  "rc_degree8_stacked_boxes", "rc_no_track"])
+def test_tick_lanes_per_candidate_identical_and_autotuned(ctx, bb, rc, case):
+    """The latency form (2 or 4 lanes per candidate) performs the same FP32
+    operations in the same order: selections and first violations are
+    identical to the one-lane form, and the tick autotuner keeps them so.
+    The cases cover each kernel instance (track polynomial of degree 5 or 8,
+    no track) and segment boundaries, also with more segments than steps."""
+    model, x, u, base = _lanes_case(ctx, bb, rc, case)
     N = base["n_cand"]
+    log(f"[lanes] {case}: N={N} H={base['horizon']} n_seg={base.get('n_seg', 1)}")
     recs, fvs = [], []
     for lanes in (1, 2, 4):
         for block in (64, 256):
@@ -565,10 +602,13 @@ def test_tick_lanes_per_candidate_identical_and_autotuned(ctx, bb, rc, system):
             fvs.append(fv.cpu().numpy())
     assert all(r == recs[0] for r in recs)
     assert all(np.array_equal(f, fvs[0]) for f in fvs)
+    log(f"[lanes] {case}: safe {(fvs[0] == base['horizon'] + 1).sum()} of {N + 1}")
+    if case not in ("bb", "rc"):
+        return
     d = mpmi.tick_desc(base["n_cand"], base["horizon"], gen=base["gen"], grid=base.get("grid"),
                        n_seg=base.get("n_seg", 1), seed=base.get("seed", 0), tick=base.get("tick", 0))
     best = mpmi.mpmi_tick_autotune(ctx, model, d, dev(x, torch.float32), dev(u, torch.float32), reps=10)
-    log(f"[autotune] {system}: {best}")
+    log(f"[autotune] {case}: {best}")
     assert best["lanes_per_cand"] in (1, 2, 4) and best["block"] in (64, 128, 256, 512)
     rec = mpmi.mpmi_tick(ctx, model, d, dev(x, torch.float32), dev(u, torch.float32)).cpu().numpy().tobytes()
     assert rec == recs[0]
