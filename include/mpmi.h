@@ -174,9 +174,10 @@ typedef struct mpmi_tick_desc {
   int32_t horizon;        /* H, 1..255 */
   int32_t precision;      /* MPMI_PREC_* */
   int32_t block;          /* threads per workgroup: 0 (library default) or 64..1024, multiple of 64 */
-  int32_t lanes_per_cand; /* FP32 ticks: 0 or 1 (one lane per candidate), or 2 / 4 lanes per candidate,
-                             each lane computing a share of the state (lower latency at small N;
-                             block <= 256) */
+  int32_t lanes_per_cand; /* FP32 ticks: 0 or 1 (one lane per candidate), or 2 / 4 / 8 lanes per
+                             candidate, each lane computing a share of the state (lower latency at
+                             small N; block <= 256); the same operations in the same order as one
+                             lane, so the same selection */
 } mpmi_tick_desc;
 
 typedef struct mpmi_ctx_s* mpmi_ctx;
@@ -253,7 +254,7 @@ mpmi_status mpmi_tick(mpmi_ctx ctx, const void* model, const mpmi_tick_desc* des
                       void* stream);
 
 /* Tick autotuner: times `reps` ticks of *desc for every launch shape in the
- * library's search space (block 64..512, lanes_per_cand 1, 2, 4; FP32 only)
+ * library's search space (block 64..512, lanes_per_cand 1, 2, 4, 8; FP32 only)
  * and writes the fastest into desc->block and desc->lanes_per_cand (host);
  * *best_ms (host, may be NULL) receives its mean tick time.  The timed ticks
  * are real ticks writing *out. */
@@ -411,15 +412,17 @@ mpmi_status mlp_adam(mpmi_ctx ctx, float* w_f32, uint16_t* w_bf16, float* adam_m
 mpmi_status mdn_sample(mpmi_ctx ctx, const void* model, const float* head, int32_t P, uint64_t seed,
                        uint64_t tick, int32_t loop, float* cand, void* stream);
 
-/* A learned-proposal tick: network on [x_t; u_user] (one single-workgroup
- * launch, the same arithmetic rules as mlp_forward, accumulation in input
- * order), P = prop->n_cand proposals drawn with (prop->seed, prop->tick,
- * prop->loop), a fused tick over {u_user} + proposals (EXPLICIT; block and
+/* A learned-proposal tick: network on [x_t; u_user] and P = prop->n_cand
+ * proposals drawn from its head as mdn_sample draws them, with (prop->seed,
+ * prop->tick, prop->loop), in one single-workgroup launch (the rounding rules
+ * of mlp_forward; each unit sums FP32 partials over blocks of 8 inputs, the
+ * blocks in input order), then a fused tick over {u_user} + proposals (EXPLICIT; block and
  * lanes_per_cand as in mpmi_tick) into *out, then the exhaustive fallback
  * tick described by *fallback (GRID or UNIFORM), which runs only if *out
  * holds MPMI_NO_SAFE and then overwrites it (out->n_cand tells which
  * candidate set decided).  cand_work [1][2][P] device; head_out [80] device
- * or NULL.  Race-car models only. */
+ * or NULL; w_bf16 16-byte aligned (MPMI_EINVAL otherwise).  Race-car models
+ * only. */
 mpmi_status mpmi_proposal_tick(mpmi_ctx ctx, const void* model, const uint16_t* w_bf16, const float* w_f32,
                                const float* in_mean, const float* in_std, const float* x_t,
                                const float* u_user, const mpmi_tick_desc* prop /* host */,

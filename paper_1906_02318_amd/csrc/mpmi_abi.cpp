@@ -272,8 +272,9 @@ static mpmi_status validate_desc(mpmi_ctx ctx, const mpmi_system& sys, const mpm
     return fail(ctx, MPMI_EINVAL, "block=%d must be 0 or a multiple of 64 in 64..1024", d->block);
   if (d->precision != MPMI_PREC_FP32 && d->precision != MPMI_PREC_BF16X3)
     return fail(ctx, MPMI_EINVAL, "unknown precision %d", d->precision);
-  if (d->lanes_per_cand != 0 && d->lanes_per_cand != 1 && d->lanes_per_cand != 2 && d->lanes_per_cand != 4)
-    return fail(ctx, MPMI_EINVAL, "lanes_per_cand=%d must be 0, 1, 2 or 4", d->lanes_per_cand);
+  if (d->lanes_per_cand != 0 && d->lanes_per_cand != 1 && d->lanes_per_cand != 2 && d->lanes_per_cand != 4 &&
+      d->lanes_per_cand != 8)
+    return fail(ctx, MPMI_EINVAL, "lanes_per_cand=%d must be 0, 1, 2, 4 or 8", d->lanes_per_cand);
   if (d->lanes_per_cand > 1 && (d->precision != MPMI_PREC_FP32 || sys.basis == MPMI_BASIS_LINEAR))
     return fail(ctx, MPMI_EUNSUPPORTED, "several lanes per candidate: FP32 ticks of the fixed bases only");
   switch (d->gen) {
@@ -353,7 +354,7 @@ mpmi_status mpmi_tick_autotune(mpmi_ctx ctx, const void* model, mpmi_tick_desc* 
   mpmi_tick_desc d = *desc;
   float bms = 1e30f;
   int bblock = 256, blanes = 1;
-  for (int lanes : {1, 2, 4}) {
+  for (int lanes : {1, 2, 4, 8}) {
     if (lanes > 1 && (sys.basis == MPMI_BASIS_LINEAR || mpmi::system_noisy(sys))) continue;
     for (int block : {64, 128, 256, 512}) {
       if (lanes > 1 && block > 256) continue;
@@ -666,12 +667,13 @@ mpmi_status mpmi_proposal_tick(mpmi_ctx ctx, const void* model, const uint16_t* 
   if (pd.precision != MPMI_PREC_FP32 || fallback->precision != MPMI_PREC_FP32)
     return fail(ctx, MPMI_EUNSUPPORTED, "only FP32 ticks are available");
   if (!x_t || !u_user || !cand_work || !out) return fail(ctx, MPMI_EINVAL, "x_t, u_user, cand_work, out must be non-NULL");
+  if (!aligned(w_bf16, 16)) return fail(ctx, MPMI_EINVAL, "w_bf16 must be 16-byte aligned");
   if (pd.lanes_per_cand > 1 && mpmi::system_noisy(sys))
     return fail(ctx, MPMI_EUNSUPPORTED, "several lanes per candidate: noise-free models only");
   hipStream_t st = (hipStream_t)stream;
   float* head = nullptr;
-  hipError_t e = mpmi::launch_mlp_row_forward(x_t, u_user, w_bf16, w_f32, in_mean, in_std, work, head_out, &head, st);
-  if (e == hipSuccess) e = mpmi::launch_mdn_sample(model, head, pd.n_cand, pd.seed, pd.tick, pd.loop, cand_work, st);
+  hipError_t e = mpmi::launch_mlp_row_forward(x_t, u_user, w_bf16, w_f32, in_mean, in_std, work, head_out, &head,
+                                              model, pd.n_cand, pd.seed, pd.tick, pd.loop, cand_work, st);
   void* slot = (char*)ctx->slots + (size_t)pd.loop * mpmi::slot_bytes();
   if (e == hipSuccess) {
     if (pd.lanes_per_cand > 1)

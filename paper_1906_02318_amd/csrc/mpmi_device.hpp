@@ -74,10 +74,10 @@ struct alignas(256) ModelDev {
 // atomic unit performs atomics on one address one after another, so the
 // workgroups ("parts") of a launch publish into kSubSlots sub-slots, part p
 // into sub-slot p % kSubSlots: keys by 64-bit atomicMin, and the safe count
-// together with a per-sub-slot ticket by one 64-bit atomicAdd.  The last part
-// of a sub-slot takes a ticket on the slot; the last of those decodes the keys
-// of all sub-slots, writes the mpmi_selection and restores the reset state
-// (keys all-ones, counters zero).
+// (with, for launches of many parts, a per-sub-slot ticket in its high half)
+// by one 64-bit atomicAdd.  Tickets on the slot find the part that completes
+// it; that part decodes the keys of all sub-slots, writes the mpmi_selection
+// and restores the reset state (keys all-ones, counters zero).
 constexpr int kSubSlots = 8;
 struct alignas(64) SubSlot {
   unsigned long long key_safe;  // (cost bits << 32) | idx  over safe candidates

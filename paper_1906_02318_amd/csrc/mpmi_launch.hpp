@@ -76,12 +76,12 @@ hipError_t launch_mlp_adam(float* w32, uint16_t* w16, float* m, float* v, const 
                            hipStream_t st);
 hipError_t launch_mdn_sample(const void* model, const float* Yrow, int P, uint64_t seed, uint64_t tick, int loop,
                              float* cand, hipStream_t st);
-hipError_t launch_mlp_row(const float* x_t, const float* u_user, void* work, float** row, float** head,
-                          hipStream_t st);
-// Forward pass of the one row [x_t; u_user] (one launch); the head goes to
-// head_out, or to the workspace's head buffer when head_out is NULL.
+// Forward pass of the one row [x_t; u_user] and P > 0 draws from its head
+// into cand (EXPLICIT layout), in one launch; the head goes to head_out, or to
+// the workspace's head buffer when head_out is NULL.  w16 16-byte aligned.
 hipError_t launch_mlp_row_forward(const float* x_t, const float* u_user, const uint16_t* w16, const float* w32,
                                   const float* mean, const float* stdv, void* work, float* head_out, float** head,
+                                  const void* model, int P, uint64_t seed, uint64_t tick, int loop, float* cand,
                                   hipStream_t st);
 hipError_t launch_gemm_test(const uint16_t* A, const uint16_t* B, int M, int N, int K, int ta, int tb, float* C,
                             hipStream_t st);

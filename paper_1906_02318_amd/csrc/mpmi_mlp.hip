@@ -227,27 +227,52 @@ __global__ void adam_kernel(float* __restrict__ w, uint16_t* __restrict__ w16, f
   w16[i] = f2bf(wi);
 }
 
-// Proposal p of one mixture head: component by inverse CDF of the FP32
-// softmax weights, Box-Muller normals, clip to [-1, 1], map to the input box.
-// Writes cand [1][m][P] (EXPLICIT layout, m = 2).
-__global__ void mdn_sample_kernel(const ModelDev* __restrict__ md, const float* __restrict__ Yrow, int P,
-                                  uint64_t seed, uint64_t tick, int loop, float* __restrict__ cand) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= P) return;
-  float w[kMlpComp];
-  float lmax = -INFINITY;
-  for (int k = 0; k < kMlpComp; ++k) lmax = fmaxf(lmax, Yrow[5 * k]);
-  float acc = 0.0f;
-  for (int k = 0; k < kMlpComp; ++k) {
-    acc += expf(Yrow[5 * k] - lmax);
-    w[k] = acc;
+// The mixture of one head in the form the draws use, built once per
+// workgroup in LDS: cdf[k] = (sum_{i<=k} e_i) / (sum_i e_i) with e_i =
+// exp(logit_i - max logit), summed in component order, and sig = exp of the
+// clamped log sigmas.
+struct MdnTable {
+  float e[kMlpComp], w[kMlpComp], cdf[kMlpComp], sig[kMlpComp][2], acc;
+};
+
+// Called by every thread of the workgroup (three barriers); head is readable
+// by all of them.
+__device__ __forceinline__ void mdn_table_build(const float* head, MdnTable* t) {
+  const int j = threadIdx.x;
+  if (j < kMlpComp) {
+    float lmax = -INFINITY;
+    for (int k = 0; k < kMlpComp; ++k) lmax = fmaxf(lmax, head[5 * k]);
+    t->e[j] = expf(head[5 * j] - lmax);
+  } else if (j < 3 * kMlpComp) {
+    const int k = (j - kMlpComp) >> 1, q = (j - kMlpComp) & 1;
+    t->sig[k][q] = expf(fminf(fmaxf(head[5 * k + 3 + q], kLogSigMin), kLogSigMax));
   }
-  const uint64_t h0 = hash_counter(seed, tick, (uint64_t)(uint32_t)loop, (uint64_t)p, 0);
-  const uint64_t h1 = hash_counter(seed, tick, (uint64_t)(uint32_t)loop, (uint64_t)p, 1);
-  const uint64_t h2 = hash_counter(seed, tick, (uint64_t)(uint32_t)loop, (uint64_t)p, 2);
+  __syncthreads();
+  if (j == 0) {
+    float acc = 0.0f;
+    for (int k = 0; k < kMlpComp; ++k) {
+      acc += t->e[k];
+      t->w[k] = acc;
+    }
+    t->acc = acc;
+  }
+  __syncthreads();
+  if (j < kMlpComp) t->cdf[j] = t->w[j] / t->acc;
+  __syncthreads();
+}
+
+// Proposal p: component by inverse CDF at r0, Box-Muller normals from r1,
+// r2, mu + sigma z clipped to [-1, 1], mapped to the input box.  Writes cand
+// [1][m][P] (EXPLICIT layout, m = 2).
+__device__ __forceinline__ void mdn_draw(const ModelDev* __restrict__ md, const float* head, const MdnTable* t,
+                                         int P, int p, uint64_t seed, uint64_t tick, int loop,
+                                         float* __restrict__ cand) {
+  const uint64_t pre = hash_prefix(seed, tick, (uint64_t)(uint32_t)loop, (uint64_t)p);
+  const uint64_t h0 = hash_finish(pre, 0), h1 = hash_finish(pre, 1), h2 = hash_finish(pre, 2);
   const float r0 = (float)((double)(h0 >> 40) * 0x1p-24);
   int kc = 0;
-  for (int k = 0; k < kMlpComp; ++k) kc += (w[k] / acc <= r0) ? 1 : 0;
+#pragma unroll
+  for (int k = 0; k < kMlpComp; ++k) kc += (t->cdf[k] <= r0) ? 1 : 0;
   kc = kc < kMlpComp ? kc : kMlpComp - 1;
   const float r1 = (float)(((double)(h1 >> 40) + 1.0) * 0x1p-24);
   const float r2 = (float)((double)(h2 >> 40) * 0x1p-24);
@@ -255,13 +280,22 @@ __global__ void mdn_sample_kernel(const ModelDev* __restrict__ md, const float* 
   float sn, cs;
   sincosf(6.283185307179586f * r2, &sn, &cs);
   const float z[2] = {rad * cs, rad * sn};
+#pragma unroll
   for (int j = 0; j < 2; ++j) {
-    const float ls = fminf(fmaxf(Yrow[5 * kc + 3 + j], kLogSigMin), kLogSigMax);
-    float un = fmaf(expf(ls), z[j], Yrow[5 * kc + 1 + j]);
+    float un = fmaf(t->sig[kc][j], z[j], head[5 * kc + 1 + j]);
     un = fminf(fmaxf(un, -1.0f), 1.0f);
     const float lo = md->sys.u_lo[j], hi = md->sys.u_hi[j];
     cand[(size_t)j * P + p] = fmaf(0.5f * (hi - lo), un, 0.5f * (lo + hi));
   }
+}
+
+__global__ void __launch_bounds__(256)
+mdn_sample_kernel(const ModelDev* __restrict__ md, const float* __restrict__ Yrow, int P, uint64_t seed,
+                  uint64_t tick, int loop, float* __restrict__ cand) {
+  __shared__ MdnTable tab;
+  mdn_table_build(Yrow, &tab);
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < P) mdn_draw(md, Yrow, &tab, P, p, seed, tick, loop, cand);
 }
 
 // Offsets of (W_l, b_l) in the flat parameter vector (per layer W[in][out]
@@ -277,58 +311,132 @@ constexpr size_t kMlpW3 = kMlpB2 + kMlpHid;
 constexpr size_t kMlpB3 = kMlpW3 + (size_t)kMlpHid * kMlpOut;
 static_assert(kMlpB3 + kMlpOut == MPMI_MLP_PARAMS, "parameter layout");
 
-// Forward pass of the one row [x_t; u_user] in one workgroup: lane j owns
-// unit j of each layer and the activations stay in LDS.  The arithmetic
-// rules are the batched path's (standardised input and activations rounded
-// to BF16, BF16 weights, FP32 accumulation, FP32 bias added last); the
-// accumulation runs in input order.  A serving tick needs one row, for which
-// a 64x64-tile GEMM per layer is four launches of mostly idle tiles.
-template <int L>
-__device__ __forceinline__ void mlp_row_layer(const float* hin, float* hout, const uint16_t* __restrict__ w16,
-                                              const float* __restrict__ w32, float* __restrict__ Y) {
-  constexpr int din = L == 0 ? kMlpIn : kMlpHid;
-  constexpr int dout = L == 3 ? kMlpOut : kMlpHid;
-  constexpr size_t woff = L == 0 ? kMlpW0 : L == 1 ? kMlpW1 : L == 2 ? kMlpW2 : kMlpW3;
-  constexpr size_t boff = L == 0 ? kMlpB0 : L == 1 ? kMlpB1 : L == 2 ? kMlpB2 : kMlpB3;
-  const int j = threadIdx.x;
-  if (j < dout) {
-    const uint16_t* W = w16 + woff + j;
-    float acc = 0.0f;
-#pragma unroll 16
-    for (int i = 0; i < din; ++i) acc = fmaf(hin[i], bf2f(W[(size_t)i * dout]), acc);
-    const float v = acc + w32[boff + j];
-    if constexpr (L < 3) hout[j] = bf2f(f2bf(gelu_f(v)));
-    else Y[j] = v;
+// Forward pass of the one row [x_t; u_user] in a workgroup of 1,024
+// threads, then draws from its head: each of the launch's workgroups runs the
+// same forward (bit-identical; workgroup 0 stores the head) and draws its
+// share of the P proposals, kRowDraws per workgroup and pass.  The arithmetic rules are the
+// batched path's (standardised input and activations rounded to BF16, BF16
+// weights, FP32 accumulation, FP32 bias added last).  In a layer of DIN
+// inputs and DOUT units, thread t takes units [8g, 8g + 8) (g = t % (DOUT/8))
+// over inputs [8s, 8s + 8) (s = t / (DOUT/8)): eight 16-byte weight loads and
+// 64 FMAs; its eight partial sums go to LDS, where one thread per unit adds
+// the DIN/8 partials in order.  Each layer's weight loads are issued before
+// the previous layer's reduction, so their latency overlaps it.  A serving
+// tick needs one row, for which a GEMM tile per layer is mostly idle.
+constexpr int kRowThreads = 1024;
+constexpr int kRowDraws = 256;
+constexpr int kRowMaxGroups = 64;
+
+// Workgroup barrier over LDS only: waits for this wave's LDS accesses, not
+// for its global loads (__syncthreads' fence also drains the vector-memory
+// counter, which would retire the next layer's weight prefetch at once).
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+template <int DIN, int DOUT>
+struct RowSlice {
+  static constexpr int G = DOUT / 8, S = DIN / 8;
+  static_assert(DOUT % 8 == 0 && DIN % 8 == 0 && G * S <= kRowThreads, "row layer shape");
+  uint4 w[8];
+  __device__ __forceinline__ bool active() const { return (int)threadIdx.x < G * S; }
+  __device__ __forceinline__ void load(const uint16_t* __restrict__ W) {
+    if (!active()) return;
+    const int g = threadIdx.x % G, sl = threadIdx.x / G;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) w[r] = *reinterpret_cast<const uint4*>(W + (size_t)(8 * sl + r) * DOUT + 8 * g);
   }
-  __syncthreads();
+  // red[s][DOUT]: this thread's eight partial sums.
+  __device__ __forceinline__ void partial(const float* hin, float* red) const {
+    if (!active()) return;
+    const int g = threadIdx.x % G, sl = threadIdx.x / G;
+    float acc[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc[u] = 0.0f;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const float h = hin[8 * sl + r];
+      const uint32_t q[4] = {w[r].x, w[r].y, w[r].z, w[r].w};
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        acc[2 * u] = fmaf(h, __uint_as_float(q[u] << 16), acc[2 * u]);
+        acc[2 * u + 1] = fmaf(h, __uint_as_float(q[u] & 0xffff0000u), acc[2 * u + 1]);
+      }
+    }
+    float4* dst = reinterpret_cast<float4*>(red + (size_t)sl * DOUT + 8 * g);
+    dst[0] = make_float4(acc[0], acc[1], acc[2], acc[3]);
+    dst[1] = make_float4(acc[4], acc[5], acc[6], acc[7]);
+  }
+};
+
+// Unit j's pre-activation: the DIN/8 partials in order, then the bias.
+template <int DIN, int DOUT>
+__device__ __forceinline__ float row_unit(const float* red, float bias, int j) {
+  float v = 0.0f;
+#pragma unroll 8
+  for (int sl = 0; sl < DIN / 8; ++sl) v += red[sl * DOUT + j];
+  return v + bias;
 }
 
-__global__ void __launch_bounds__(256) mlp_row_forward_kernel(const float* __restrict__ x_t,
-                                                              const float* __restrict__ u_user,
-                                                              const uint16_t* __restrict__ w16,
-                                                              const float* __restrict__ w32,
-                                                              const float* __restrict__ mean,
-                                                              const float* __restrict__ stdv,
-                                                              float* __restrict__ Y) {
-  __shared__ float bufA[kMlpHid], bufB[kMlpHid];
+__global__ void __launch_bounds__(kRowThreads)
+mlp_row_forward_kernel(const float* __restrict__ x_t, const float* __restrict__ u_user,
+                       const uint16_t* __restrict__ w16, const float* __restrict__ w32,
+                       const float* __restrict__ mean, const float* __restrict__ stdv,
+                       float* __restrict__ Y, const ModelDev* __restrict__ md, int P, uint64_t seed,
+                       uint64_t tick, int loop, float* __restrict__ cand) {
+  __shared__ __attribute__((aligned(16))) float red[(kMlpHid / 8) * kMlpHid];
+  __shared__ __attribute__((aligned(16))) float bufA[kMlpHid], bufB[kMlpHid], head[kMlpOut];
   const int j = threadIdx.x;
+  // Global loads in the order they are consumed (the vector-memory counter
+  // retires loads in issue order): input row and biases, then the weights of
+  // layers 0 and 1; layer l + 2's weights are issued before layer l + 1's
+  // products.
+  float xin = 0.0f, b0 = 0.0f, b1 = 0.0f, b2 = 0.0f, b3 = 0.0f;
+  float xm = 0.0f, xs = 1.0f;
   if (j < kMlpIn) {
-    const float xv = j < 6 ? x_t[j] : u_user[j - 6];
-    bufA[j] = bf2f(f2bf((xv - mean[j]) / stdv[j]));
+    xin = j < 6 ? x_t[j] : u_user[j - 6];
+    xm = mean[j];
+    xs = stdv[j];
   }
-  __syncthreads();
-  mlp_row_layer<0>(bufA, bufB, w16, w32, Y);
-  mlp_row_layer<1>(bufB, bufA, w16, w32, Y);
-  mlp_row_layer<2>(bufA, bufB, w16, w32, Y);
-  mlp_row_layer<3>(bufB, bufA, w16, w32, Y);
-}
-
-// [x_t; u_user] -> one input row.
-__global__ void mlp_row_kernel(const float* __restrict__ x_t, const float* __restrict__ u_user,
-                               float* __restrict__ X) {
-  const int j = threadIdx.x;
-  if (j < 6) X[j] = x_t[j];
-  else if (j < 8) X[j] = u_user[j - 6];
+  if (j < kMlpHid) {
+    b0 = w32[kMlpB0 + j];
+    b1 = w32[kMlpB1 + j];
+    b2 = w32[kMlpB2 + j];
+  }
+  if (j < kMlpOut) b3 = w32[kMlpB3 + j];
+  RowSlice<kMlpIn, kMlpHid> s0;
+  RowSlice<kMlpHid, kMlpHid> s1;
+  s0.load(w16 + kMlpW0);
+  s1.load(w16 + kMlpW1);
+  if (j < kMlpIn) bufA[j] = bf2f(f2bf((xin - xm) / xs));
+  lds_barrier();
+  s0.partial(bufA, red);
+  lds_barrier();
+  if (j < kMlpHid) bufB[j] = bf2f(f2bf(gelu_f(row_unit<kMlpIn, kMlpHid>(red, b0, j))));
+  lds_barrier();
+  RowSlice<kMlpHid, kMlpHid> s2;
+  s2.load(w16 + kMlpW2);
+  s1.partial(bufB, red);
+  lds_barrier();
+  if (j < kMlpHid) bufA[j] = bf2f(f2bf(gelu_f(row_unit<kMlpHid, kMlpHid>(red, b1, j))));
+  lds_barrier();
+  RowSlice<kMlpHid, kMlpOut> s3;
+  s3.load(w16 + kMlpW3);
+  s2.partial(bufA, red);
+  lds_barrier();
+  if (j < kMlpHid) bufB[j] = bf2f(f2bf(gelu_f(row_unit<kMlpHid, kMlpHid>(red, b2, j))));
+  lds_barrier();
+  s3.partial(bufB, red);
+  lds_barrier();
+  if (j < kMlpOut) {
+    const float v = row_unit<kMlpHid, kMlpOut>(red, b3, j);
+    head[j] = v;
+    if (blockIdx.x == 0) Y[j] = v;
+  }
+  if (P <= 0) return;
+  __shared__ MdnTable tab;
+  lds_barrier();
+  mdn_table_build(head, &tab);
+  for (int p = blockIdx.x * kRowDraws + j; j < kRowDraws && p < P; p += gridDim.x * kRowDraws)
+    mdn_draw(md, head, &tab, P, p, seed, tick, loop, cand);
 }
 
 // ---------------------------------------------------------------------------
@@ -475,23 +583,16 @@ hipError_t launch_mdn_sample(const void* model, const float* Yrow, int P, uint64
   return hipGetLastError();
 }
 
-// Assembles the single input row in the workspace; *row is that row and
-// *head the workspace's output area for a one-row forward.
 hipError_t launch_mlp_row_forward(const float* x_t, const float* u_user, const uint16_t* w16, const float* w32,
                                   const float* mean, const float* stdv, void* work, float* head_out, float** head,
+                                  const void* model, int P, uint64_t seed, uint64_t tick, int loop, float* cand,
                                   hipStream_t st) {
   const MlpWork w = carve(work, 1);
   *head = head_out ? head_out : w.Y;
-  mlp_row_forward_kernel<<<1, 256, 0, st>>>(x_t, u_user, w16, w32, mean, stdv, *head);
-  return hipGetLastError();
-}
-
-hipError_t launch_mlp_row(const float* x_t, const float* u_user, void* work, float** row, float** head,
-                          hipStream_t st) {
-  const MlpWork w = carve(work, 1);
-  mlp_row_kernel<<<1, 64, 0, st>>>(x_t, u_user, w.row);
-  *row = w.row;
-  *head = w.Y;
+  int groups = P > 0 ? (P + kRowDraws - 1) / kRowDraws : 1;
+  groups = groups < kRowMaxGroups ? groups : kRowMaxGroups;
+  mlp_row_forward_kernel<<<groups, kRowThreads, 0, st>>>(x_t, u_user, w16, w32, mean, stdv, *head,
+                                                         (const ModelDev*)model, P, seed, tick, loop, cand);
   return hipGetLastError();
 }
 

@@ -1,12 +1,14 @@
 // Latency form of the fused tick: each candidate spread over SPLIT lanes.
 //
 // With few candidates per tick a wave's 60-step serial chain, not the chip's
-// throughput, sets the tick time.  Here lane h of a group of SPLIT computes
-// output columns [h J, h J + J) of every step (J = ceil(n / SPLIT)) from the
-// full feature set, and the group rebuilds the full next state with
-// cross-lane permutes, so each lane's chain per step is about half (SPLIT =
-// 2) of the one-lane form, at the price of redundant feature and safety work.
-// The autotuner picks SPLIT (1, 2 or 4) and the workgroup size per workload.
+// throughput, sets the tick time: a wave issues one instruction per four
+// cycles, so the step's instruction count is its latency.  Here lane h of a
+// group of SPLIT computes output columns [h J, h J + J) of every step
+// (J = ceil(n / SPLIT)) from the full feature set, and the group rebuilds the
+// full next state with cross-lane permutes, so each lane's contraction is
+// J / n of the one-lane form, at the price of redundant feature and safety
+// work.  The autotuner picks SPLIT (1, 2, 4 or 8) and the workgroup size per
+// workload.
 #include <hip/hip_runtime.h>
 
 #include "mpmi_device.hpp"
@@ -193,12 +195,24 @@ struct SafetyRegs {
   }
 };
 
-// Value of v in lane `src` of this lane's group (groups of SPLIT = 2 or 4
-// lanes sit inside one quad): a DPP quad permute, no LDS round trip.
+// Value of v in lane `SRC` of this lane's group, with DPP permutes (no LDS
+// round trip).  Groups of 2 or 4 lanes sit inside one quad: one quad_perm.
+// A group of 8 is two quads of one row half: a quad_perm broadcasts lane
+// SRC % 4 of every quad, then the quad that does not hold SRC takes the value
+// of the quad beside it (row_shr:4 into banks 1 and 3, or row_shl:4 into
+// banks 0 and 2; the other banks keep the broadcast).
 template <int SPLIT, int SRC>
 __device__ __forceinline__ float group_lane(float v) {
-  constexpr int ctrl = (SPLIT == 4) ? SRC * 0x55 : (SRC == 0 ? 0xA0 : 0xF5);  // quad_perm selectors
-  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), ctrl, 0xF, 0xF, true));
+  const int iv = __builtin_bit_cast(int, v);
+  if constexpr (SPLIT == 8) {
+    const int b = __builtin_amdgcn_mov_dpp(iv, (SRC & 3) * 0x55, 0xF, 0xF, true);
+    constexpr int shift = SRC < 4 ? 0x114 : 0x104;      // row_shr:4 / row_shl:4
+    constexpr int banks = SRC < 4 ? 0xA : 0x5;          // the quads that take the neighbour's value
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(b, b, shift, 0xF, banks, false));
+  } else {
+    constexpr int ctrl = (SPLIT == 4) ? SRC * 0x55 : (SRC == 0 ? 0xA0 : 0xF5);  // quad_perm selectors
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(iv, ctrl, 0xF, 0xF, true));
+  }
 }
 
 template <int NS, int J, int SPLIT, int JJ = 0>
@@ -217,17 +231,18 @@ tick_split_kernel(const ModelDev* __restrict__ md, GenParams gp, int H, const fl
   constexpr int NS = Dims<BASIS>::N, MS = Dims<BASIS>::M;
   constexpr int J = (NS + SPLIT - 1) / SPLIT;
   constexpr int D = (BASIS == MPMI_BASIS_RACE_CAR) ? 64 : 21;
-  static_assert(SPLIT == 2 || SPLIT == 4, "groups of 2 or 4 lanes (one quad)");
+  static_assert(SPLIT == 2 || SPLIT == 4 || SPLIT == 8, "groups of 2, 4 or 8 lanes (one row half)");
   __shared__ __attribute__((aligned(16))) float sK8[kSplitRows * 8];
-  stage_K_split<BASIS, J>(md, sK8);
-  // Groups never straddle a quad: the launch uses a block that is a multiple
-  // of 64, so lane l of a wave holds gid with gid % 64 == l.
+  // A group never straddles a quad (2, 4) or a row half (8): the launch
+  // uses a block that is a multiple of 64, so lane l of a wave holds gid with
+  // gid % 64 == l.
   const int gid = blockIdx.x * blockDim.x + threadIdx.x;
   const int c = gid / SPLIT, h = gid % SPLIT;
   const int Nc = gp.n_cand + 1;
   const bool valid = c < Nc;
   const int colpos = h * SplitLayout<J>::A;
 
+  // State and candidate loads first: their latency overlaps the staging of K.
   float x[NS], u[MS], u0[MS];
 #pragma unroll
   for (int j = 0; j < NS; ++j) x[j] = x_t[j];
@@ -236,6 +251,7 @@ tick_split_kernel(const ModelDev* __restrict__ md, GenParams gp, int H, const fl
     u0[j] = valid ? cand_value(gp, md, cand, u_user, c, 0, j) : 0.0f;
     u[j] = u0[j];
   }
+  stage_K_split<BASIS, J>(md, sK8);
   SplitFold<BASIS, J> F;
   F.fold(sK8, colpos, u);
   SplitRows<BASIS, J> Kr;
@@ -330,8 +346,10 @@ static void split_dispatch(int split, unsigned grid, int block, hipStream_t st, 
                            mpmi_selection* out, int16_t* fv) {
   if (split == 2)
     tick_split_kernel<BASIS, 2, DEG, TRACK><<<grid, block, 0, st>>>(md, gp, H, x_t, u_user, cand, sl, out, fv);
-  else
+  else if (split == 4)
     tick_split_kernel<BASIS, 4, DEG, TRACK><<<grid, block, 0, st>>>(md, gp, H, x_t, u_user, cand, sl, out, fv);
+  else
+    tick_split_kernel<BASIS, 8, DEG, TRACK><<<grid, block, 0, st>>>(md, gp, H, x_t, u_user, cand, sl, out, fv);
 }
 
 hipError_t launch_tick_split(const mpmi_system& sys, int split, const void* model, const mpmi_tick_desc& d,

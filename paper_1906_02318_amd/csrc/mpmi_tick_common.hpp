@@ -36,7 +36,10 @@ __device__ __forceinline__ float cost_of(const ModelDev* __restrict__ md, const 
 // Workgroup reduction of the two keys and the safe count, then the part's
 // atomics on its sub-slot (part < n_parts; n_parts parts serve this slot in
 // this launch); returns true in every thread of the workgroup that completes
-// the slot.
+// the slot.  Up to kOneLevelParts parts take their ticket on the slot itself
+// (contention stays small); more parts take one on their sub-slot first, and
+// the last of each sub-slot one on the slot.
+constexpr unsigned int kOneLevelParts = 128;
 __device__ __forceinline__ bool reduce_and_publish(unsigned long long ks, unsigned long long kf,
                                                    bool safe_counted, Slot* __restrict__ slot,
                                                    unsigned int n_parts, unsigned int part) {
@@ -66,15 +69,22 @@ __device__ __forceinline__ bool reduce_and_publish(unsigned long long ks, unsign
     SubSlot* ss = &slot->sub[sidx];
     if (bks != kKeyNone) atomicMin(&ss->key_safe, bks);
     if (bkf != kKeyNone) atomicMin(&ss->key_fb, bkf);
-    __threadfence();
-    // parts p < n_parts with p % kSubSlots == sidx
-    const unsigned int in_sub = (n_parts - sidx + kSubSlots - 1) / kSubSlots;
-    const unsigned long long prev = atomicAdd(&ss->count, (1ull << 32) | (unsigned long long)bcnt);
     bool last = false;
-    if ((unsigned int)(prev >> 32) == in_sub - 1) {
+    if (n_parts <= kOneLevelParts) {
+      // Few parts: the count needs no ticket, and one ticket on the slot
+      // saves a round trip to memory on the completing part's path.
+      if (bcnt) atomicAdd(&ss->count, (unsigned long long)bcnt);
       __threadfence();
-      const unsigned int used = n_parts < (unsigned int)kSubSlots ? n_parts : (unsigned int)kSubSlots;
-      last = atomicAdd(&slot->done, 1u) == used - 1;
+      last = atomicAdd(&slot->done, 1u) == n_parts - 1;
+    } else {
+      __threadfence();
+      // parts p < n_parts with p % kSubSlots == sidx
+      const unsigned int in_sub = (n_parts - sidx + kSubSlots - 1) / kSubSlots;
+      const unsigned long long prev = atomicAdd(&ss->count, (1ull << 32) | (unsigned long long)bcnt);
+      if ((unsigned int)(prev >> 32) == in_sub - 1) {
+        __threadfence();
+        last = atomicAdd(&slot->done, 1u) == (unsigned int)kSubSlots - 1;
+      }
     }
     s_last = last;
   }

@@ -582,7 +582,7 @@ def _lanes_case(ctx, bb, rc, case):
 @pytest.mark.parametrize("case", ["bb", "bb_short_horizon", "bb_h7_s4", "bb_track", "rc", "rc_segments",
                                   "rc_degree8_stacked_boxes", "rc_no_track"])
 def test_tick_lanes_per_candidate_identical_and_autotuned(ctx, bb, rc, case):
-    """The latency form (2 or 4 lanes per candidate) performs the same FP32
+    """The latency form (2, 4 or 8 lanes per candidate) performs the same FP32
     operations in the same order: selections and first violations are
     identical to the one-lane form, and the tick autotuner keeps them so.
     The cases cover each kernel instance (track polynomial of degree 5 or 8,
@@ -591,7 +591,7 @@ def test_tick_lanes_per_candidate_identical_and_autotuned(ctx, bb, rc, case):
     N = base["n_cand"]
     log(f"[lanes] {case}: N={N} H={base['horizon']} n_seg={base.get('n_seg', 1)}")
     recs, fvs = [], []
-    for lanes in (1, 2, 4):
+    for lanes in (1, 2, 4, 8):
         for block in (64, 256):
             d = mpmi.tick_desc(base["n_cand"], base["horizon"], gen=base["gen"], grid=base.get("grid"),
                                n_seg=base.get("n_seg", 1), seed=base.get("seed", 0), tick=base.get("tick", 0),
@@ -609,7 +609,7 @@ def test_tick_lanes_per_candidate_identical_and_autotuned(ctx, bb, rc, case):
                        n_seg=base.get("n_seg", 1), seed=base.get("seed", 0), tick=base.get("tick", 0))
     best = mpmi.mpmi_tick_autotune(ctx, model, d, dev(x, torch.float32), dev(u, torch.float32), reps=10)
     log(f"[autotune] {case}: {best}")
-    assert best["lanes_per_cand"] in (1, 2, 4) and best["block"] in (64, 128, 256, 512)
+    assert best["lanes_per_cand"] in (1, 2, 4, 8) and best["block"] in (64, 128, 256, 512)
     rec = mpmi.mpmi_tick(ctx, model, d, dev(x, torch.float32), dev(u, torch.float32)).cpu().numpy().tobytes()
     assert rec == recs[0]
 
