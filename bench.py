@@ -307,6 +307,11 @@ def run_closed_loop_balance_bot(n_ticks: int = 1000, warmup: int = 20):
     out = torch.zeros(mpmi.SELECTION_BYTES, dtype=torch.uint8, device="cuda")
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     dev_ms, e2e_ms, falls, interventions = [], [], 0, 0
+    # launch shape (block, lanes per candidate) from the tick autotuner, on the
+    # first tick's inputs
+    x_dev.copy_(torch.from_numpy(x.astype(np.float32)))
+    shape = mpmi.mpmi_tick_autotune(ctx, model, mpmi.tick_desc(10240, 50, gen=mpmi.GEN_UNIFORM, n_seg=5, seed=4),
+                                    x_dev, u_dev, reps=20)
     for t in range(warmup + n_ticks):
         u = user.next()
         t0 = time.perf_counter()
@@ -314,7 +319,8 @@ def run_closed_loop_balance_bot(n_ticks: int = 1000, warmup: int = 20):
         u_pin.copy_(torch.from_numpy(u.astype(np.float32)))
         x_dev.copy_(x_pin, non_blocking=True)
         u_dev.copy_(u_pin, non_blocking=True)
-        desc = mpmi.tick_desc(10240, 50, gen=mpmi.GEN_UNIFORM, n_seg=5, seed=4, tick=t)
+        desc = mpmi.tick_desc(10240, 50, gen=mpmi.GEN_UNIFORM, n_seg=5, seed=4, tick=t, block=shape["block"],
+                              lanes_per_cand=shape["lanes_per_cand"])
         ev0.record(stream)
         mpmi.mpmi_tick(ctx, model, desc, x_dev, u_dev, out=out, stream=stream)
         ev1.record(stream)
@@ -337,7 +343,7 @@ def run_closed_loop_balance_bot(n_ticks: int = 1000, warmup: int = 20):
             "p50_tick_ms": float(np.percentile(dev, 50)), "p99_tick_ms": float(np.percentile(dev, 99)),
             "p50_end_to_end_ms": float(np.percentile(e2e, 50)), "p99_end_to_end_ms": float(np.percentile(e2e, 99)),
             "within_10ms_budget": float(np.mean(e2e < 10.0)), "interventions": interventions,
-            "safety_violations": falls}
+            "safety_violations": falls, "launch_shape": shape}
 
 
 def run_plain_vs_learned(n_ticks: int = 500, warmup: int = 20):

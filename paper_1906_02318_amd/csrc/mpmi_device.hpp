@@ -515,13 +515,31 @@ __device__ __forceinline__ unsigned long long fallback_key(int fv, float cost, i
   return ((unsigned long long)(255 - fv) << 56) | (cb << 25) | (unsigned long long)(uint32_t)idx;
 }
 
+// One step of a DPP min-reduction: v against the value CTRL selects (rows
+// and banks outside the masks, and sources outside the row, read all-ones,
+// the identity of min).
+template <int CTRL, int ROW_MASK, int BANK_MASK>
+__device__ __forceinline__ unsigned long long dpp_min_u64(unsigned long long v) {
+  const int lo = __builtin_amdgcn_update_dpp(-1, (int)(uint32_t)v, CTRL, ROW_MASK, BANK_MASK, false);
+  const int hi = __builtin_amdgcn_update_dpp(-1, (int)(uint32_t)(v >> 32), CTRL, ROW_MASK, BANK_MASK, false);
+  const unsigned long long o = ((unsigned long long)(uint32_t)hi << 32) | (uint32_t)lo;
+  return o < v ? o : v;
+}
+
+// Minimum of v over the wave (every lane active), in every lane: within each
+// row of 16, shifts by 1, 2, 4, 8 leave lane 15 with the row's minimum; the
+// row broadcasts of lanes 15 and 31 carry it to lane 63, read back as a
+// scalar.  No LDS round trip (a shuffle butterfly is six ds_bpermute waits).
 __device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    const unsigned long long o = __shfl_xor(v, off, 64);
-    v = o < v ? o : v;
-  }
-  return v;
+  v = dpp_min_u64<0x111, 0xF, 0xF>(v);  // row_shr:1
+  v = dpp_min_u64<0x112, 0xF, 0xF>(v);  // row_shr:2
+  v = dpp_min_u64<0x114, 0xF, 0xF>(v);  // row_shr:4
+  v = dpp_min_u64<0x118, 0xF, 0xF>(v);  // row_shr:8
+  v = dpp_min_u64<0x142, 0xA, 0xF>(v);  // row_bcast:15 into rows 1 and 3
+  v = dpp_min_u64<0x143, 0xC, 0xF>(v);  // row_bcast:31 into rows 2 and 3
+  const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)v, 63);
+  const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), 63);
+  return ((unsigned long long)hi << 32) | lo;
 }
 
 }  // namespace mpmi

@@ -258,6 +258,10 @@ tick_split_kernel(const ModelDev* __restrict__ md, GenParams gp, int H, const fl
   Kr.load(sK8, D, colpos);
   SafetyRegs<NS, DEG, TRACK> sr;
   sr.load(md);
+  // The cost needs only the first segment's input: taken now, so its loads
+  // are not on the path after the horizon.
+  const bool lead = valid && h == 0;
+  const float cst = lead ? cost_of<MS>(md, u0, u_user) : 0.0f;
   // Every register above is loaded before the horizon starts, so the loop
   // carries no wait for them.
   __syncthreads();
@@ -331,8 +335,6 @@ tick_split_kernel(const ModelDev* __restrict__ md, GenParams gp, int H, const fl
     }
     if (fv_out && h == 0) fv_out[c] = (int16_t)fv;
   }
-  const bool lead = valid && h == 0;
-  const float cst = lead ? cost_of<MS>(md, u0, u_user) : 0.0f;
   const bool safe = lead && fv == H + 1;
   const unsigned long long ks = safe ? safe_key(cst, c) : kKeyNone;
   const unsigned long long kf = (lead && !safe) ? fallback_key(fv, cst, c) : kKeyNone;

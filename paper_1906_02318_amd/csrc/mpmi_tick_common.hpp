@@ -92,14 +92,16 @@ __device__ __forceinline__ bool reduce_and_publish(unsigned long long ks, unsign
   return s_last != 0;
 }
 
-// Decodes the slot into the selection and resets the slot (one thread).
-// Every read is an atomic exchange with the reset value: it sees the value
-// the other parts' atomics left and restores the reset state in one step.
+// Decodes the slot into the selection and resets the slot (one thread, in
+// the part whose ticket completed the slot).  Every slot read is an atomic
+// exchange with the reset value, performed where the other parts' atomics
+// were: it sees the values they left (their tickets followed their keys) and
+// restores the reset state in one step, so no fence is needed here; the other
+// inputs were written before the launch, and the selection is read after it.
 template <int MS>
 __device__ void finalize(const ModelDev* __restrict__ md, const GenParams& gp,
                          const float* __restrict__ cand, const float* __restrict__ u_user, int H,
                          Slot* __restrict__ slot, mpmi_selection* __restrict__ out) {
-  __threadfence();
   unsigned long long ks = kKeyNone, kf = kKeyNone;
   unsigned int n_safe = 0, n_re = 0;
 #pragma unroll
@@ -149,7 +151,6 @@ __device__ void finalize(const ModelDev* __restrict__ md, const GenParams& gp,
   sel.first_violation = fv;
   sel.n_cand = gp.n_cand + 1;
   *out = sel;
-  __threadfence();
 }
 
 struct CandResult {
