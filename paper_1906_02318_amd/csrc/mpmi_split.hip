@@ -27,36 +27,42 @@ struct SplitLayout {
 
 constexpr int kSplitRows = 64 + 27;  // full rows + per-step rows (race car is the larger)
 
+// Row r of the table: K row r (r < D), or the per-step row r - D (the
+// quadratic state features, then for the race car the heading terms).
+template <int BASIS>
+__device__ __forceinline__ int split_row(int r) {
+  constexpr int D = (BASIS == MPMI_BASIS_RACE_CAR) ? 64 : 21;
+  if (r < D) return r;
+  const int q = r - D;
+  if (BASIS == MPMI_BASIS_RACE_CAR) {
+    if (q < 21) {
+      int k = 0, t = q;
+      while (t >= 6 - k) { t -= 6 - k; ++k; }
+      return quad_index(k, k + t, 8);
+    }
+    constexpr int trig_rows[6] = {49, 50, 51, 53, 54, 55};
+    return trig_rows[q - 21];
+  }
+  int k = 0, t = q;
+  while (t >= 4 - k) { t -= 4 - k; ++k; }
+  return quad_index(k, k + t, 5);
+}
+
+// One pass over the table: every entry is written once, with its K value or
+// zero (positions no column maps to), so one barrier suffices; D and R are
+// the basis' constants, so the loads start without a round trip.
 template <int BASIS, int J>
 __device__ __forceinline__ void stage_K_split(const ModelDev* __restrict__ md, float* sK8) {
   constexpr int NS = Dims<BASIS>::N;
-  const int D = md->dim;
-  const int R = (BASIS == MPMI_BASIS_RACE_CAR) ? kRcStepRows : 10;
-  for (int e = threadIdx.x; e < (D + R) * 8; e += blockDim.x) sK8[e] = 0.0f;
-  __syncthreads();
-  for (int e = threadIdx.x; e < (D + R) * NS; e += blockDim.x) {
-    const int r = e / NS, j = e % NS;
-    int row;
-    if (r < D) {
-      row = r;
-    } else {
-      const int q = r - D;
-      if (BASIS == MPMI_BASIS_RACE_CAR) {
-        if (q < 21) {
-          int k = 0, t = q;
-          while (t >= 6 - k) { t -= 6 - k; ++k; }
-          row = quad_index(k, k + t, 8);
-        } else {
-          constexpr int trig_rows[6] = {49, 50, 51, 53, 54, 55};
-          row = trig_rows[q - 21];
-        }
-      } else {
-        int k = 0, t = q;
-        while (t >= 4 - k) { t -= 4 - k; ++k; }
-        row = quad_index(k, k + t, 5);
-      }
-    }
-    sK8[r * 8 + SplitLayout<J>::pos(j)] = md->K[row][j];
+  constexpr int D = (BASIS == MPMI_BASIS_RACE_CAR) ? 64 : 21;
+  constexpr int R = (BASIS == MPMI_BASIS_RACE_CAR) ? kRcStepRows : 10;
+  constexpr int A = SplitLayout<J>::A;
+  for (int e = threadIdx.x; e < (D + R) * 8; e += blockDim.x) {
+    const int r = e >> 3, p = e & 7;
+    const int j = (p / A) * J + (p % A);  // the column at position p, if p % A < J
+    float v = 0.0f;
+    if (p % A < J && j < NS) v = md->K[split_row<BASIS>(r)][j];
+    sK8[e] = v;
   }
   __syncthreads();
 }
