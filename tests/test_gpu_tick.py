@@ -273,6 +273,31 @@ def test_tick_edge_sizes(ctx, bb, N, H, gen):
     check_tick(so, K, x, u, cand, H, sel, fv.cpu().numpy(), EPS_BB, label=f"edge N={N} H={H}")
 
 
+@pytest.mark.parametrize("N", [7, 600, 8191, 8192])
+def test_tick_selection_across_ticket_levels(ctx, bb, N):
+    """The selection does not depend on how the workgroups publish: from one
+    workgroup to more than the 128 that take their ticket on the slot itself
+    (N = 8,191 at 64 lanes: 128 workgroups; 8,192: 129, each sub-slot's last
+    workgroup taking the slot ticket), records and first violations are
+    identical across launch shapes and agree with the oracle."""
+    so, model, K = bb
+    x, u = W.f32(synth.balance_bot_states(1, seed=6)[0]), W.f32([2.5])
+    cand = o.with_user(o.uniform_candidates(so, N, 1, 9, 4, 0), u, 1)
+    recs, fvs = [], []
+    for block, lanes in ((64, 1), (256, 1), (64, 2), (128, 8)):
+        desc = mpmi.tick_desc(N, 30, gen=mpmi.GEN_UNIFORM, seed=9, tick=4, block=block, lanes_per_cand=lanes)
+        parts = ((N + 1) * lanes + block - 1) // block
+        log(f"[tickets] N={N} block={block} lanes={lanes} workgroups={parts}")
+        fv = torch.empty(N + 1, dtype=torch.int16, device="cuda")
+        recs.append(mpmi.mpmi_tick(ctx, model, desc, dev(x, torch.float32), dev(u, torch.float32),
+                                   first_violation=fv).cpu().numpy().tobytes())
+        fvs.append(fv.cpu().numpy())
+    assert all(r == recs[0] for r in recs)
+    assert all(np.array_equal(f, fvs[0]) for f in fvs)
+    sel = mpmi.decode_selection(torch.tensor(np.frombuffer(recs[0], np.uint8)))
+    check_tick(so, K, x, u, cand, 30, sel, fvs[0], EPS_BB, label=f"tickets N={N}")
+
+
 def test_tick_no_safe_candidate(ctx, bb):
     """Inflation larger than the bounds: nothing is safe; the fallback rule decides."""
     so0, _, K = bb
