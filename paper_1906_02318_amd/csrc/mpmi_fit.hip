@@ -17,7 +17,7 @@ namespace mpmi {
 constexpr int kFitRows = 64;       // rows per LDS tile
 constexpr int kFitBlocks = 256;    // maximum partial-sum workgroups
 constexpr int kFitCols = MPMI_MAX_DIM + MPMI_MAX_STATE;  // D + n <= 72
-constexpr int kFitThreads = 256;
+constexpr int kFitThreads = 256;  // four waves: the solve kernel gives each a task
 constexpr int kFitPerThread = (MPMI_MAX_DIM * kFitCols + kFitThreads - 1) / kFitThreads;  // 18
 
 struct FitInfo {
@@ -104,12 +104,21 @@ gram_kernel(int basis, int n, int m, int D, const double* __restrict__ X, const 
   }
 }
 
-__global__ void reduce_kernel(int nparts, int E, const double* __restrict__ part, double* __restrict__ tot) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= E) return;
+// tot[e] = sum over the parts of part[p][e], in a fixed order: the four
+// threads of element e sum parts p = q, q + 4, ... (q = 0..3), then add the
+// four quarters in order.  A workgroup covers kReduceElems elements.
+constexpr int kReduceElems = 64;
+__global__ void __launch_bounds__(4 * kReduceElems)
+reduce_kernel(int nparts, int E, const double* __restrict__ part, double* __restrict__ tot) {
+  __shared__ double q4[4][kReduceElems];
+  const int el = threadIdx.x % kReduceElems, q = threadIdx.x / kReduceElems;
+  const int e = blockIdx.x * kReduceElems + el;
   double s = 0.0;
-  for (int p = 0; p < nparts; ++p) s += part[(size_t)p * E + e];
-  tot[e] = s;
+  if (e < E)
+    for (int p = q; p < nparts; p += 4) s += part[(size_t)p * E + e];
+  q4[q][el] = s;
+  __syncthreads();
+  if (q == 0 && e < E) tot[e] = ((q4[0][el] + q4[1][el]) + q4[2][el]) + q4[3][el];
 }
 
 // Value of x in lane k (k wave-uniform), to every lane of the wave.
@@ -120,22 +129,41 @@ __device__ __forceinline__ double lane_bcast(double x, int k) {
   return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
-// Sum over the 64 lanes (butterfly, the same order in every lane).
+// One step of a DPP sum: x plus the value CTRL selects (0 where the source
+// is outside the row or the row and bank masks).
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_add(double x) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, ROW_MASK, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, ROW_MASK, 0xF, false);
+  return x + __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// Sum over the 64 lanes (every lane active), the same value in every lane:
+// shifts by 1, 2, 4, 8 within each row of 16, the row broadcasts of lanes 15
+// and 31, then lane 63's total read back.  A fixed order; no LDS round trip.
 __device__ __forceinline__ double wave_sum(double x) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
-  return x;
+  x = dpp_add<0x111, 0xF>(x);  // row_shr:1
+  x = dpp_add<0x112, 0xF>(x);  // row_shr:2
+  x = dpp_add<0x114, 0xF>(x);  // row_shr:4
+  x = dpp_add<0x118, 0xF>(x);  // row_shr:8
+  x = dpp_add<0x142, 0xA>(x);  // row_bcast:15 into rows 1 and 3
+  x = dpp_add<0x143, 0xC>(x);  // row_bcast:31 into rows 2 and 3
+  return lane_bcast(x, 63);
 }
 
 // L z = b with the Cholesky factor in the lower triangle of Lf (diagonal
-// included): lane i holds b_i and returns z_i (lanes >= D hold 0).  Column
-// by column: z_k = r_k / L_kk once lane k's residual r_k is complete, then
-// every later row subtracts L_ik z_k.
+// included): lane i holds b_i and 1 / L_ii (rinv) and returns z_i (lanes >= D
+// hold 0).  Column by column: z_k = r_k / L_kk once lane k's residual r_k is
+// complete (lane k forms the quotient, the wave reads it back), then every
+// later row subtracts L_ik z_k.  No division in the serial chain.
 template <int LD>
-__device__ __forceinline__ double wave_lower_solve(const double (&Lf)[MPMI_MAX_DIM][LD], int D, int lane, double b) {
+__device__ __forceinline__ double wave_lower_solve(const double (&Lf)[MPMI_MAX_DIM][LD], int D, int lane, double rinv,
+                                                   double b) {
   double r = b, z = 0.0;
+#pragma unroll 4
   for (int k = 0; k < D; ++k) {
-    const double zk = lane_bcast(r, k) / Lf[k][k];
+    const double zk = lane_bcast(r * rinv, k);
     if (lane == k) z = zk;
     if (lane > k && lane < D) r = fma(-Lf[lane][k], zk, r);
   }
@@ -144,10 +172,12 @@ __device__ __forceinline__ double wave_lower_solve(const double (&Lf)[MPMI_MAX_D
 
 // L^T y = z, the same way from the last row up.
 template <int LD>
-__device__ __forceinline__ double wave_upper_solve(const double (&Lf)[MPMI_MAX_DIM][LD], int D, int lane, double z) {
+__device__ __forceinline__ double wave_upper_solve(const double (&Lf)[MPMI_MAX_DIM][LD], int D, int lane, double rinv,
+                                                   double z) {
   double r = z, y = 0.0;
+#pragma unroll 4
   for (int k = D - 1; k >= 0; --k) {
-    const double yk = lane_bcast(r, k) / Lf[k][k];
+    const double yk = lane_bcast(r * rinv, k);
     if (lane == k) y = yk;
     if (lane < k) r = fma(-Lf[k][lane], yk, r);
   }
@@ -203,52 +233,85 @@ solve_kernel(int n, int D, long long T, double ridge, const double* __restrict__
     }
     __syncthreads();
   }
-  // Triangular solves and the condition estimate run one wave per task: lane
-  // i owns row i (D <= 64), the wave's lockstep orders the steps, and the
-  // values a step needs from another lane arrive by lane broadcast, so no
-  // workgroup barrier is involved.  The factor is read-only from here on.
+  // Triangular solves and the condition estimate run one wave per task, the
+  // tasks concurrently: lane i owns row i (D <= 64), the wave's lockstep
+  // orders the steps, and the values a step needs from another lane arrive
+  // by lane broadcast, so no workgroup barrier is involved.  The factor is
+  // read-only from here on.
   const int lane = t & 63, wave = t >> 6;
   const bool own = lane < D;
-  // K: wave q solves the right-hand sides q, q + 4 (n <= 8 columns).
-  for (int c = wave; c < n; c += kFitThreads / 64) {
-    const double z = wave_lower_solve(L, D, lane, own ? B[lane][c] : 0.0);
-    const double k = wave_upper_solve(L, D, lane, z);
-    if (own) K[(size_t)lane * n + c] = k / sc[lane];
-  }
-  // Condition estimate of the scaled Gram matrix G_s (wave 0): power
-  // iteration for the largest eigenvalue (G_s from its upper triangle and
-  // the diagonal of L L^T), inverse iteration through the Cholesky factor
-  // for the smallest.
-  if (wave == 0) {
+  const double rinv = own ? 1.0 / L[lane][lane] : 0.0;
+  __shared__ double s_lmax, s_lmin_inv;
+  if (wave >= 2) {
+    // K: waves 2 and 3 solve the right-hand sides c = wave - 2, wave, ...
+    for (int c = wave - 2; c < n; c += 2) {
+      const double z = wave_lower_solve(L, D, lane, rinv, own ? B[lane][c] : 0.0);
+      const double k = wave_upper_solve(L, D, lane, rinv, z);
+      if (own) K[(size_t)lane * n + c] = k / sc[lane];
+    }
+  } else if (wave == 1) {
+    // Largest eigenvalue of the scaled Gram matrix G_s by power iteration
+    // (G_s from its upper triangle and the diagonal of L L^T).  Lane i holds
+    // row i of G_s in registers; the loops run over the 64-row maximum with
+    // compile-time indices (rows and columns past D are zero).
     double diag = 0.0;
     if (own)
       for (int k = 0; k <= lane; ++k) diag += L[lane][k] * L[lane][k];
+    double grow[MPMI_MAX_DIM];
+#pragma unroll
+    for (int j = 0; j < MPMI_MAX_DIM; ++j)
+      grow[j] = (own && j < D) ? (lane == j ? diag : (lane < j ? L[lane][j] : L[j][lane])) : 0.0;
     double v = own ? 1.0 + 0.01 * lane : 0.0;
     double lmax = 0.0;
     for (int it = 0; it < 60; ++it) {
       double w = 0.0;
-      for (int j = 0; j < D; ++j) {
-        const double vj = lane_bcast(v, j);
-        const double g = lane == j ? diag : (lane < j ? L[lane][j] : L[j][lane]);
-        w = own ? fma(g, vj, w) : 0.0;
-      }
+#pragma unroll
+      for (int j = 0; j < MPMI_MAX_DIM; ++j) w = fma(grow[j], lane_bcast(v, j), w);
       const double nn = sqrt(wave_sum(w * w));
       lmax = wave_sum(w * v);
       v = w / nn;
     }
-    v = own ? 1.0 - 0.01 * lane : 0.0;
+    if (lane == 0) s_lmax = lmax;
+  } else {
+    // Smallest eigenvalue by inverse iteration through the Cholesky factor.
+    // Lane i holds m[k] = L_ik for k < i (its row) and L_ki for k > i (its
+    // column) in registers.  The forward solve uses lane i's residual only up
+    // to step i and the backward solve only down to step i, so each may
+    // subtract the other half's entries after that point: a solve step is a
+    // multiply, a broadcast and an FMA.
+    double m[MPMI_MAX_DIM];
+#pragma unroll
+    for (int k = 0; k < MPMI_MAX_DIM; ++k)
+      m[k] = (own && k < D && k != lane) ? (k < lane ? L[lane][k] : L[k][lane]) : 0.0;
+    double v = own ? 1.0 - 0.01 * lane : 0.0;
     double lmin_inv = 0.0;
     for (int it = 0; it < 60; ++it) {
-      const double w = wave_upper_solve(L, D, lane, wave_lower_solve(L, D, lane, v));
-      const double nn = sqrt(wave_sum(w * w));
-      lmin_inv = wave_sum(w * v);
-      v = w / nn;
+      double r = v, z = 0.0;
+#pragma unroll
+      for (int k = 0; k < MPMI_MAX_DIM; ++k) {  // L z = v
+        const double zk = lane_bcast(r * rinv, k);
+        z = lane == k ? zk : z;
+        r = fma(-m[k], zk, r);
+      }
+      double y = 0.0;
+      r = z;
+#pragma unroll
+      for (int k = MPMI_MAX_DIM - 1; k >= 0; --k) {  // L^T y = z
+        const double yk = lane_bcast(r * rinv, k);
+        y = lane == k ? yk : y;
+        r = fma(-m[k], yk, r);
+      }
+      const double nn = sqrt(wave_sum(y * y));
+      lmin_inv = wave_sum(y * v);
+      v = y / nn;
     }
-    if (lane == 0) {
-      info->status = bad ? MPMI_ESINGULAR : MPMI_OK;
-      const double cg = lmax * lmin_inv;
-      info->cond = cg > 0.0 ? sqrt(cg) : INFINITY;
-    }
+    if (lane == 0) s_lmin_inv = lmin_inv;
+  }
+  __syncthreads();
+  if (t == 0) {
+    info->status = bad ? MPMI_ESINGULAR : MPMI_OK;
+    const double cg = s_lmax * s_lmin_inv;
+    info->cond = cg > 0.0 ? sqrt(cg) : INFINITY;
   }
 }
 
@@ -269,7 +332,7 @@ hipError_t launch_fit(const mpmi_system& sys, int dim, const double* X, const do
   gram_kernel<<<nparts, kFitThreads, 0, st>>>(sys.basis, n, m, dim, X, U, Y, (long long)T, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  reduce_kernel<<<(E + 255) / 256, 256, 0, st>>>(nparts, E, part, tot);
+  reduce_kernel<<<(E + kReduceElems - 1) / kReduceElems, 4 * kReduceElems, 0, st>>>(nparts, E, part, tot);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   solve_kernel<<<1, kFitThreads, 0, st>>>(n, dim, (long long)T, ridge, tot, K_out, info);
