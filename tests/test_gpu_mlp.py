@@ -189,6 +189,13 @@ def test_proposal_tick_and_fallback(ctx):
                                                             head_out=head))
         # the oracle's view of the same proposals (the head is an input here)
         props, _ = M.sample(head.cpu().numpy().astype(np.float64), P, 8, t, 1, so.u_lo, so.u_hi)
+        # the draws made inside the fused launch are the standalone sampler's,
+        # bit for bit, and the oracle's to FP32 transcendental rounding
+        alone = mpmi.mdn_sample(ctx, model, head, P, seed=8, tick=t, loop=1)
+        assert torch.equal(alone, cand_work)
+        cw = cand_work.cpu().numpy()
+        for j, span in enumerate((0.8, 6.0)):
+            np.testing.assert_allclose(cw[0, j], props[:, j], rtol=0, atol=2e-5 * span)
         cand = o.with_user(props, u, 1)
         traj, fv = o.rollout(so, K, x, cand, 60)
         ref = o.select(so, cand, fv, 60, u)
