@@ -346,6 +346,50 @@ def run_closed_loop_balance_bot(n_ticks: int = 1000, warmup: int = 20):
             "safety_violations": falls, "launch_shape": shape}
 
 
+def run_trajectory_store(st: dict, reps: int = 10):
+    """Trajectory mode (the predicted-state cloud stored, traj[H][n][N+1],
+    candidate index fastest) against the decision-only tick, race car, H = 60,
+    at the stated size (128 x 128 grid) and at 1,024 x 1,024.  Bytes written
+    = executed units x n x 4 (a lane stores the states it computes, up to its
+    first violation)."""
+    import torch
+
+    from paper_1906_02318_amd import mpmi
+
+    ctx, model = st["ctx"], st["model"]
+    stream = torch.cuda.current_stream()
+    H, n = 60, 6
+    res = {}
+    for name, side in (("race_car_16k", 128), ("race_car_1m", 1024)):
+        N = side * side
+        desc = mpmi.tick_desc(N, H, gen=mpmi.GEN_GRID, grid=[side, side])
+        x, u = st["x"][0], st["u"][0]
+        fv = torch.empty(N + 1, dtype=torch.int16, device="cuda")
+        mpmi.mpmi_tick(ctx, model, desc, x, u, first_violation=fv)
+        units = int(torch.clamp(fv.to(torch.int64), max=H).sum().item())
+        traj = torch.empty((H, n, N + 1), dtype=torch.float32, device="cuda")
+        out = torch.empty(mpmi.SELECTION_BYTES, dtype=torch.uint8, device="cuda")
+        times = {}
+        for mode, tr in (("decision", None), ("trajectory", traj)):
+            for _ in range(3):
+                mpmi.mpmi_tick(ctx, model, desc, x, u, out=out, traj=tr, stream=stream)
+            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+            for a, b in ev:
+                a.record(stream)
+                mpmi.mpmi_tick(ctx, model, desc, x, u, out=out, traj=tr, stream=stream)
+                b.record(stream)
+            torch.cuda.synchronize()
+            times[mode] = float(np.median([a.elapsed_time(b) for a, b in ev]))
+        wbytes = units * n * 4
+        res[name] = {"candidates": N + 1, "executed_units": units, "traj_bytes_allocated": traj.numel() * 4,
+                     "ms_decision": times["decision"], "ms_trajectory": times["trajectory"],
+                     "bytes_written": wbytes, "write_GB_s": wbytes / (times["trajectory"] * 1e-3) / 1e9,
+                     "hbm_frac": wbytes / (times["trajectory"] * 1e-3) / 8e12}
+        del traj
+        torch.cuda.empty_cache()
+    return res
+
+
 def run_plain_vs_learned(n_ticks: int = 500, warmup: int = 20):
     """Race car at its stated size: exhaustive 128 x 128 grid tick vs the learned
     2,048-proposal tick (exhaustive fallback), on the same tick inputs."""
@@ -565,6 +609,7 @@ def main():
         torch.cuda.synchronize()
         out["calibration_copy_bytes"] = args.copy_bytes
     if not args.no_extras and args.workload == "race_car_1m":
+        out["trajectory_store"] = run_trajectory_store(st)
         out["race_car_16k"] = run_plain_vs_learned()
         out["many_loops"] = run_multi(n_ticks=args.multi_ticks)
         out["balance_bot_closed_loop"] = run_closed_loop_balance_bot()

@@ -70,7 +70,7 @@ rollout_fp32_kernel(const ModelDev* __restrict__ md, int Nc, int S, int H, const
     stp.step(md, sK, x);
 #pragma unroll
     for (int j = 0; j < NS; ++j)
-      if (j < n) traj[((size_t)(s - 1) * n + j) * (size_t)Nc + c] = x[j];
+      if (j < n) __builtin_nontemporal_store(x[j], &traj[((size_t)(s - 1) * n + j) * (size_t)Nc + c]);
   }
 }
 

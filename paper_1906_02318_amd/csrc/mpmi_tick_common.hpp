@@ -202,9 +202,10 @@ __device__ __forceinline__ CandResult evaluate_candidate(const ModelDev* __restr
       settle_state<NS>(x);
       if (noisy) add_process_noise<NS>(md->sys.noise_sigma, nprefix, s, n, x);
       if (traj) {
+        // Streaming stores: the cloud is written once, for a later reader.
 #pragma unroll
         for (int j = 0; j < NS; ++j)
-          if (j < n) traj[((size_t)(s - 1) * n + j) * (size_t)Nc + c] = x[j];
+          if (j < n) __builtin_nontemporal_store(x[j], &traj[((size_t)(s - 1) * n + j) * (size_t)Nc + c]);
       }
       if (!(min_margin<NS, DEG>(md, x) > 0.0f)) {
         fv = s;
