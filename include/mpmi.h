@@ -414,7 +414,7 @@ mpmi_status mdn_sample(mpmi_ctx ctx, const void* model, const float* head, int32
 
 /* A learned-proposal tick: network on [x_t; u_user] and P = prop->n_cand
  * proposals drawn from its head as mdn_sample draws them, with (prop->seed,
- * prop->tick, prop->loop), in one single-workgroup launch (the rounding rules
+ * prop->tick, prop->loop), in one launch (the rounding rules
  * of mlp_forward; each unit sums FP32 partials over blocks of 8 inputs, the
  * blocks in input order), then a fused tick over {u_user} + proposals (EXPLICIT; block and
  * lanes_per_cand as in mpmi_tick) into *out, then the exhaustive fallback

@@ -86,7 +86,7 @@ def test_mlp_forward_parity(ctx, batch):
 
 
 def test_single_row_forward_parity(ctx, batch):
-    """The serving tick's one-workgroup forward (head_out of mpmi_proposal_tick)
+    """The serving tick's single-row forward (head_out of mpmi_proposal_tick)
     against the oracle, to the batched forward's bound, and against the batched
     kernels on the same rows: the same rounding rules, differing only in the
     FP32 accumulation order (and the BF16 activations that order can flip)."""
