@@ -599,7 +599,8 @@ def main():
         out["race_car_1m_bf16x3"] = {
             "trajectories_per_s": Nc * nb / wb, "p50_tick_ms": float(np.percentile(msb, 50)),
             "p99_tick_ms": float(np.percentile(msb, 99)),
-            "rechecked_per_tick": float(np.mean([s_["n_recheck"] for s_ in sb])),
+            # the records the BF16 ticks wrote (inputs 0 .. min(nb, n_inputs) - 1)
+            "rechecked_per_tick": float(np.mean([s_["n_recheck"] for s_ in sb[:min(nb, n_inputs)]])),
             "note": "27 shared-coefficient features on v_mfma_f32_16x16x32_bf16 (hi/lo split), FP32 recheck "
                     "of candidates within 0.02 of a constraint; two launches per tick"}
     if args.copy_bytes > 0:

@@ -327,7 +327,7 @@ mpmi_status mpmi_tick(mpmi_ctx ctx, const void* model, const mpmi_tick_desc* des
     if (mpmi::system_noisy(sys)) return fail(ctx, MPMI_EUNSUPPORTED, "BF16X3 ticks are noise-free");
     if (desc->block != 0 && desc->block != 256)
       return fail(ctx, MPMI_EUNSUPPORTED, "BF16X3 ticks use 256-thread workgroups");
-    return check_hip(ctx, mpmi::launch_tick_bf16(model, *desc, x_t, u_user, cand, slot, out, first_violation,
+    return check_hip(ctx, mpmi::launch_tick_bf16(sys, model, *desc, x_t, u_user, cand, slot, out, first_violation,
                                                  ctx->recheck, mpmi::kRecheckCapacity,
                                                  mpmi::device_cu_count() * 4, (hipStream_t)stream),
                      "mpmi_tick (BF16X3) launch");

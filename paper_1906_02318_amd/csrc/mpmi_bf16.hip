@@ -36,24 +36,57 @@ struct RecheckList {
   int idx[1];  // capacity entries follow
 };
 
-// true if some constraint margin of x is within eps of zero (either side).
-__device__ __forceinline__ bool near_boundary(const ModelDev* __restrict__ md, const float* x) {
+// Safety verdict of x (min_margin's rule: every checked margin positive, a
+// NaN margin unsafe) and whether some constraint margin is within its eps of
+// zero (either side), with the track's centreline evaluated once.
+template <int DEG>
+__device__ __forceinline__ bool check_rc(const ModelDev* __restrict__ md, const float* x, bool* near) {
   const ConstSafety* sc = safety_of(md);
-  bool near = false;
+  float mm = INFINITY;
+  bool nan = false, nr = false;
+  const int mask = sc->comp_mask;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    if (mask & (1 << k)) {
+      const float mg = sc->comp_lim[k] - fabsf(x[k]);
+      nan |= (mg != mg);
+      mm = fminf(mm, mg);
+    }
+  }
   const int nb = sc->n_box;
 #pragma unroll
   for (int b = 0; b < MPMI_MAX_BOX; ++b) {
     if (b < nb) {
       const float mg = sc->bb_lim[b] - fabsf(pick<6>(x, sc->box_index[b]));
-      near |= fabsf(mg) < md->sys.eps_box[b];
+      nr |= fabsf(mg) < md->sys.eps_box[b];
     }
   }
   if (sc->has_track) {
     float rho;
-    const float rc = track_centre(sc, x, &rho);
-    near |= fabsf(sc->trk_lim - fabsf(rho - rc)) < md->sys.eps_track;
+    const float rc = track_centre<DEG>(sc, x, &rho);
+    const float mg = sc->trk_lim - fabsf(rho - rc);
+    nan |= (mg != mg);
+    mm = fminf(mm, mg);
+    nr |= fabsf(mg) < md->sys.eps_track;
   }
-  return near;
+  *near = nr;
+  return !nan && mm > 0.0f;
+}
+
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+
+// hi = RNE_bf16(v) and lo = RNE_bf16(v - hi) for two features at once
+// (v_cvt_pk_bf16_f32), packed two per 32-bit word.
+__device__ __forceinline__ void split_pair(float a, float b, uint32_t* hi, uint32_t* lo) {
+  bf16x2_t h;
+  h[0] = (__bf16)a;
+  h[1] = (__bf16)b;
+  const uint32_t hb = __builtin_bit_cast(uint32_t, h);
+  bf16x2_t l;
+  l[0] = (__bf16)(a - __uint_as_float(hb << 16));
+  l[1] = (__bf16)(b - __uint_as_float(hb & 0xffff0000u));
+  *hi = hb;
+  *lo = __builtin_bit_cast(uint32_t, l);
 }
 
 __device__ __forceinline__ uint16_t bf16_hi(float v) { return (uint16_t)bf16_bits_rne_u(v); }
@@ -74,6 +107,7 @@ __device__ __forceinline__ float rc_shared_feature(int f, const float* x, float 
   return 0.0f;
 }
 
+template <int DEG>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 4)))
 tick_bf16_race_car_kernel(const ModelDev* __restrict__ md, GenParams gp, int H, const float* __restrict__ x_t,
                           const float* __restrict__ u_user, const float* __restrict__ cand,
@@ -81,7 +115,7 @@ tick_bf16_race_car_kernel(const ModelDev* __restrict__ md, GenParams gp, int H, 
                           int capacity) {
   __shared__ float4 sK[kLdsKFloat4];
   __shared__ __attribute__((aligned(16))) uint16_t sA[kWaves][2][64][kArow];  // [wave][hi/lo][cand][k]
-  __shared__ __attribute__((aligned(16))) float sD[kWaves][64][8];            // [wave][cand][output]
+  __shared__ __attribute__((aligned(16))) float sD[kWaves][8][64];            // [wave][output][cand]
   stage_K<MPMI_BASIS_RACE_CAR>(md, sK);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int Nc = gp.n_cand + 1;
@@ -119,36 +153,34 @@ tick_bf16_race_car_kernel(const ModelDev* __restrict__ md, GenParams gp, int H, 
   int fv = H + 1;
   const int S = gp.n_seg;
   int gcur = 0;
+  int nxt = (H + S - 1) / S;  // first s - 1 of the next segment
   for (int s = 1; s <= H; ++s) {
     if (!__any(alive)) break;  // wave-uniform
-    const int g = ((s - 1) * S) / H;
-    if (g != gcur) {
-      gcur = g;
+    if (s - 1 >= nxt) {
+      gcur = ((s - 1) * S) / H;
+      nxt = ((gcur + 1) * H + S - 1) / S;
 #pragma unroll
-      for (int j = 0; j < 2; ++j) u[j] = valid ? cand_value(gp, md, cand, u_user, c, g, j) : 0.0f;
+      for (int j = 0; j < 2; ++j) u[j] = valid ? cand_value(gp, md, cand, u_user, c, gcur, j) : 0.0f;
       stp.set_input(md, sK, u);
     }
-    float sp, cp;
-    sincosf(x[2], &sp, &cp);
+    // The FP32 path's hardware sine and cosine (the recheck re-rolls with it).
+    const float sp = __sinf(x[2]), cp = __cosf(x[2]);
     // Per-step shared-coefficient features, split into BF16 hi/lo, to LDS,
     // eight at a time (feature f < 21: x_k x_l in (k <= l) order; 21..23:
     // sin psi (vx, vy, r); 24..26: cos psi (vx, vy, r); 27..31: zero).
 #pragma unroll
     for (int k8 = 0; k8 < 4; ++k8) {
-      bf16x8_t h8, l8;
+      uint32_t h[4], l[4];
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const float v = rc_shared_feature(k8 * 8 + i, x, sp, cp);
-        const uint16_t h = bf16_hi(v);
-        const float vh = __uint_as_float((uint32_t)h << 16);
-        h8[i] = __builtin_bit_cast(__bf16, h);
-        l8[i] = __builtin_bit_cast(__bf16, bf16_hi(v - vh));
-      }
-      *reinterpret_cast<bf16x8_t*>(&sA[wave][0][lane][k8 * 8]) = h8;
-      *reinterpret_cast<bf16x8_t*>(&sA[wave][1][lane][k8 * 8]) = l8;
+      for (int i = 0; i < 4; ++i)
+        split_pair(rc_shared_feature(k8 * 8 + 2 * i, x, sp, cp), rc_shared_feature(k8 * 8 + 2 * i + 1, x, sp, cp),
+                   &h[i], &l[i]);
+      *reinterpret_cast<uint4*>(&sA[wave][0][lane][k8 * 8]) = make_uint4(h[0], h[1], h[2], h[3]);
+      *reinterpret_cast<uint4*>(&sA[wave][1][lane][k8 * 8]) = make_uint4(l[0], l[1], l[2], l[3]);
     }
     __builtin_amdgcn_wave_barrier();
-    // Four groups of 16 candidates: D = Ahi Bhi + Ahi Blo + Alo Bhi.
+    // Four groups of 16 candidates: D = Ahi Bhi + Ahi Blo + Alo Bhi.  Lane
+    // (col, quarter) holds outputs col of four consecutive candidates.
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb) {
       const int row = rb * 16 + (lane & 15), k0 = (lane >> 4) * 8;
@@ -159,10 +191,8 @@ tick_bf16_race_car_kernel(const ModelDev* __restrict__ md, GenParams gp, int H, 
       acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, blo, acc, 0, 0, 0);
       acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bhi, acc, 0, 0, 0);
       const int col = lane & 15;
-      if (col < 6) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) sD[wave][rb * 16 + (lane >> 4) * 4 + r][col] = acc[r];
-      }
+      if (col < 6)
+        *reinterpret_cast<float4*>(&sD[wave][col][rb * 16 + (lane >> 4) * 4]) = make_float4(acc[0], acc[1], acc[2], acc[3]);
     }
     __builtin_amdgcn_wave_barrier();
     float y[6];
@@ -171,14 +201,16 @@ tick_bf16_race_car_kernel(const ModelDev* __restrict__ md, GenParams gp, int H, 
       float v = fmaf(stp.Tc[j], cp, fmaf(stp.Ts[j], sp, stp.cu[j]));
 #pragma unroll
       for (int k = 0; k < 6; ++k) v = fmaf(stp.L[k][j], x[k], v);
-      y[j] = v + sD[wave][lane][j];
+      y[j] = v + sD[wave][j][lane];
     }
     __builtin_amdgcn_wave_barrier();
     if (alive) {
 #pragma unroll
       for (int j = 0; j < 6; ++j) x[j] = y[j];
-      near |= near_boundary(md, x);
-      if (!(min_margin<6>(md, x) > 0.0f)) {
+      bool nr;
+      const bool ok = check_rc<DEG>(md, x, &nr);
+      near |= nr;
+      if (!ok) {
         fv = s;
         alive = false;
       }
@@ -231,6 +263,7 @@ tick_bf16_race_car_kernel(const ModelDev* __restrict__ md, GenParams gp, int H, 
 
 // FP32 re-roll of the listed candidates, then the selection.  Every workgroup
 // publishes (possibly empty keys) so the last one can finalise.
+template <int DEG>
 __global__ void __launch_bounds__(256)
 recheck_race_car_kernel(const ModelDev* __restrict__ md, GenParams gp, int H, const float* __restrict__ x_t,
                         const float* __restrict__ u_user, const float* __restrict__ cand,
@@ -246,8 +279,8 @@ recheck_race_car_kernel(const ModelDev* __restrict__ md, GenParams gp, int H, co
   for (int e0 = blockIdx.x * blockDim.x; e0 < count; e0 += stride) {
     const int e = e0 + threadIdx.x;
     const int c = e < count ? rl->idx[e] : gp.n_cand + 1;  // past the end: an invalid lane
-    const CandResult r = evaluate_candidate<MPMI_BASIS_RACE_CAR, false>(md, sK, gp, H, x_t, u_user, cand, c, fv_out,
-                                                                 nullptr);
+    const CandResult r = evaluate_candidate<MPMI_BASIS_RACE_CAR, false, DEG>(md, sK, gp, H, x_t, u_user, cand, c,
+                                                                      fv_out, nullptr);
     ks = r.ks < ks ? r.ks : ks;
     kf = r.kf < kf ? r.kf : kf;
     n_safe_local += r.safe_counted ? 1u : 0u;
@@ -267,9 +300,21 @@ recheck_race_car_kernel(const ModelDev* __restrict__ md, GenParams gp, int H, co
 
 size_t recheck_bytes(int capacity) { return sizeof(RecheckList) + sizeof(int) * (size_t)capacity; }
 
-hipError_t launch_tick_bf16(const void* model, const mpmi_tick_desc& d, const float* x_t, const float* u_user,
-                            const float* cand, void* slot, mpmi_selection* out, int16_t* fv, void* recheck,
-                            int capacity, int recheck_grid, hipStream_t st) {
+template <int DEG>
+static hipError_t bf16_dispatch(const ModelDev* md, const GenParams& gp, int H, const float* x_t, const float* u_user,
+                                const float* cand, Slot* sl, mpmi_selection* out, int16_t* fv, RecheckList* rl,
+                                int capacity, int recheck_grid, hipStream_t st) {
+  const unsigned grid = (unsigned)(((long long)gp.n_cand + 1 + 255) / 256);
+  tick_bf16_race_car_kernel<DEG><<<grid, 256, 0, st>>>(md, gp, H, x_t, u_user, cand, sl, fv, rl, capacity);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  recheck_race_car_kernel<DEG><<<recheck_grid, 256, 0, st>>>(md, gp, H, x_t, u_user, cand, sl, out, fv, rl, capacity);
+  return hipGetLastError();
+}
+
+hipError_t launch_tick_bf16(const mpmi_system& sys, const void* model, const mpmi_tick_desc& d, const float* x_t,
+                            const float* u_user, const float* cand, void* slot, mpmi_selection* out, int16_t* fv,
+                            void* recheck, int capacity, int recheck_grid, hipStream_t st) {
   GenParams gp;
   gp.seed = d.seed;
   gp.tick = d.tick;
@@ -278,14 +323,12 @@ hipError_t launch_tick_bf16(const void* model, const mpmi_tick_desc& d, const fl
   gp.n_cand = d.n_cand;
   gp.n_seg = d.n_seg;
   for (int j = 0; j < MPMI_MAX_INPUT; ++j) gp.grid[j] = d.grid[j] > 0 ? d.grid[j] : 1;
-  const unsigned grid = (unsigned)(((long long)d.n_cand + 1 + 255) / 256);
-  tick_bf16_race_car_kernel<<<grid, 256, 0, st>>>((const ModelDev*)model, gp, d.horizon, x_t, u_user, cand,
-                                                    (Slot*)slot, fv, (RecheckList*)recheck, capacity);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  recheck_race_car_kernel<<<recheck_grid, 256, 0, st>>>((const ModelDev*)model, gp, d.horizon, x_t, u_user, cand,
-                                                          (Slot*)slot, out, fv, (RecheckList*)recheck, capacity);
-  return hipGetLastError();
+  const ModelDev* md = (const ModelDev*)model;
+  if (track_degree(sys) <= kSmallTrackDeg)
+    return bf16_dispatch<kSmallTrackDeg>(md, gp, d.horizon, x_t, u_user, cand, (Slot*)slot, out, fv,
+                                         (RecheckList*)recheck, capacity, recheck_grid, st);
+  return bf16_dispatch<kMaxHarm>(md, gp, d.horizon, x_t, u_user, cand, (Slot*)slot, out, fv, (RecheckList*)recheck,
+                                 capacity, recheck_grid, st);
 }
 
 }  // namespace mpmi
