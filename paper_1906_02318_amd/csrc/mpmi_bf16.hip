@@ -57,7 +57,13 @@ __device__ __forceinline__ bool check_rc(const ModelDev* __restrict__ md, const 
 #pragma unroll
   for (int b = 0; b < MPMI_MAX_BOX; ++b) {
     if (b < nb) {
-      const float mg = sc->bb_lim[b] - fabsf(pick<6>(x, sc->box_index[b]));
+      // x[box_index] by bit masks: a select chain on a run-time index is
+      // turned into an indexed stack load, which would keep x in memory.
+      const int bi = sc->box_index[b];
+      uint32_t xb = 0u;
+#pragma unroll
+      for (int k = 0; k < 6; ++k) xb |= __float_as_uint(x[k]) & (bi == k ? 0xffffffffu : 0u);
+      const float mg = sc->bb_lim[b] - fabsf(__uint_as_float(xb));
       nr |= fabsf(mg) < md->sys.eps_box[b];
     }
   }
@@ -91,20 +97,23 @@ __device__ __forceinline__ void split_pair(float a, float b, uint32_t* hi, uint3
 
 __device__ __forceinline__ uint16_t bf16_hi(float v) { return (uint16_t)bf16_bits_rne_u(v); }
 
-// Shared-coefficient feature f of the race-car step (f is a compile-time
-// constant after unrolling, so this folds to one product).
-__device__ __forceinline__ float rc_shared_feature(int f, const float* x, float sp, float cp) {
-  if (f < 21) {
-    int k = 0, r = f;
-    while (r >= 6 - k) {
-      r -= 6 - k;
-      ++k;
-    }
-    return x[k] * x[k + r];
+// The 32 shared-coefficient features of the race-car step, zero-padded:
+// f < 21: x_k x_l in (k <= l) order; 21..23: sin psi (vx, vy, r); 24..26:
+// cos psi (vx, vy, r).  Nested unrolled loops keep every index a compile-time
+// constant (the state stays in registers).
+__device__ __forceinline__ void rc_shared_features(const float* x, float sp, float cp, float* f) {
+  int q = 0;
+#pragma unroll
+  for (int k = 0; k < 6; ++k)
+#pragma unroll
+    for (int l = k; l < 6; ++l) f[q++] = x[k] * x[l];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    f[21 + r] = sp * x[3 + r];
+    f[24 + r] = cp * x[3 + r];
   }
-  if (f < 24) return sp * x[3 + (f - 21)];
-  if (f < 27) return cp * x[3 + (f - 24)];
-  return 0.0f;
+#pragma unroll
+  for (int r = 27; r < 32; ++r) f[r] = 0.0f;
 }
 
 template <int DEG>
@@ -166,15 +175,14 @@ tick_bf16_race_car_kernel(const ModelDev* __restrict__ md, GenParams gp, int H, 
     // The FP32 path's hardware sine and cosine (the recheck re-rolls with it).
     const float sp = __sinf(x[2]), cp = __cosf(x[2]);
     // Per-step shared-coefficient features, split into BF16 hi/lo, to LDS,
-    // eight at a time (feature f < 21: x_k x_l in (k <= l) order; 21..23:
-    // sin psi (vx, vy, r); 24..26: cos psi (vx, vy, r); 27..31: zero).
+    // eight at a time.
+    float feat[32];
+    rc_shared_features(x, sp, cp, feat);
 #pragma unroll
     for (int k8 = 0; k8 < 4; ++k8) {
       uint32_t h[4], l[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
-        split_pair(rc_shared_feature(k8 * 8 + 2 * i, x, sp, cp), rc_shared_feature(k8 * 8 + 2 * i + 1, x, sp, cp),
-                   &h[i], &l[i]);
+      for (int i = 0; i < 4; ++i) split_pair(feat[k8 * 8 + 2 * i], feat[k8 * 8 + 2 * i + 1], &h[i], &l[i]);
       *reinterpret_cast<uint4*>(&sA[wave][0][lane][k8 * 8]) = make_uint4(h[0], h[1], h[2], h[3]);
       *reinterpret_cast<uint4*>(&sA[wave][1][lane][k8 * 8]) = make_uint4(l[0], l[1], l[2], l[3]);
     }
