@@ -381,10 +381,15 @@ def run_trajectory_store(st: dict, reps: int = 10):
             torch.cuda.synchronize()
             times[mode] = float(np.median([a.elapsed_time(b) for a, b in ev]))
         wbytes = units * n * 4
+        rate = wbytes / (times["trajectory"] * 1e-3) / 1e9
+        # the layout's own write ceiling (the store pattern alone) and a
+        # contiguous stream, measured live on the same buffer
+        ceil = mpmi.mpmi_write_rates(ctx, traj.view(-1), N + 1, H * n)
         res[name] = {"candidates": N + 1, "executed_units": units, "traj_bytes_allocated": traj.numel() * 4,
                      "ms_decision": times["decision"], "ms_trajectory": times["trajectory"],
-                     "bytes_written": wbytes, "write_GB_s": wbytes / (times["trajectory"] * 1e-3) / 1e9,
-                     "hbm_frac": wbytes / (times["trajectory"] * 1e-3) / 8e12}
+                     "bytes_written": wbytes, "write_GB_s": rate, "hbm_frac": rate / 8000.0,
+                     "pattern_ceiling_GB_s": ceil["pattern_GB_s"], "stream_ceiling_GB_s": ceil["stream_GB_s"],
+                     "pattern_frac": rate / ceil["pattern_GB_s"]}
         del traj
         torch.cuda.empty_cache()
     return res

@@ -277,6 +277,17 @@ mpmi_status mpmi_generate_candidates(mpmi_ctx ctx, const void* model,
  * Synchronous (default stream, about 15 ms); allocates nothing. */
 mpmi_status mpmi_fp32_fma_rate(mpmi_ctx ctx, double* tflops /* host */);
 
+/* Diagnostic: HBM write ceilings of the trajectory store (GB/s, host), on a
+ * caller buffer buf of rows * Nc floats (device, 16-byte aligned; contents
+ * overwritten): *pattern_gbs for the store pattern of traj[rows][Nc] alone
+ * (lane c writes element c of every row, streaming stores, no compute),
+ * *stream_gbs for contiguous 16-byte stores of the same size; best of three
+ * timed launches each.  Synchronous (default stream); allocates nothing.
+ * MPMI_EINVAL for NULL pointers, misalignment, Nc or rows < 1, or more than
+ * 2^33 elements. */
+mpmi_status mpmi_write_rates(mpmi_ctx ctx, float* buf, int32_t Nc, int32_t rows, double* pattern_gbs /* host */,
+                             double* stream_gbs /* host */);
+
 /* ---------------------------------------------------------------------------
  * Many concurrent control loops in one launch per tick.
  *

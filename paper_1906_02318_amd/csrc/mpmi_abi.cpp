@@ -393,6 +393,16 @@ mpmi_status mpmi_fp32_fma_rate(mpmi_ctx ctx, double* tflops) {
   return check_hip(ctx, mpmi::measure_fma_rate((float*)ctx->fit_work, tflops), "mpmi_fp32_fma_rate");
 }
 
+mpmi_status mpmi_write_rates(mpmi_ctx ctx, float* buf, int32_t Nc, int32_t rows, double* pattern_gbs,
+                             double* stream_gbs) {
+  if (!ctx) return MPMI_EINVAL;
+  if (!buf || !pattern_gbs || !stream_gbs) return fail(ctx, MPMI_EINVAL, "buf, pattern_gbs and stream_gbs must be non-NULL");
+  if (!aligned(buf, 16)) return fail(ctx, MPMI_EINVAL, "buf must be 16-byte aligned");
+  if (Nc < 1 || rows < 1 || (long long)Nc * rows > (1ll << 33))
+    return fail(ctx, MPMI_EINVAL, "Nc=%d rows=%d out of range", Nc, rows);
+  return check_hip(ctx, mpmi::measure_write_rates(buf, Nc, rows, pattern_gbs, stream_gbs), "mpmi_write_rates");
+}
+
 mpmi_status mpmi_generate_candidates(mpmi_ctx ctx, const void* model, const mpmi_tick_desc* desc,
                                      const float* u_user, const float* cand, float* cand_out, void* stream) {
   if (!ctx) return MPMI_EINVAL;

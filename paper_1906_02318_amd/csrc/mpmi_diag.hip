@@ -55,4 +55,57 @@ hipError_t measure_fma_rate(float* sink, double* tflops) {
   return hipSuccess;
 }
 
+// HBM write ceilings for the trajectory store: the store pattern of
+// traj[H][n][Nc] alone (lane c writes element c of each of the H * n rows,
+// no compute), and a contiguous stream of 16-byte stores of the same size.
+__global__ void __launch_bounds__(256) traj_pattern_kernel(float* __restrict__ traj, int Nc, int rows) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= Nc) return;
+  float v = (float)c;
+  for (int r = 0; r < rows; ++r) {
+    v = fmaf(v, 1.0001f, 1.0f);
+    __builtin_nontemporal_store(v, &traj[(size_t)r * (size_t)Nc + c]);
+  }
+}
+
+__global__ void __launch_bounds__(256) write_stream_kernel(float4* __restrict__ out, size_t n4) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride)
+    out[i] = make_float4(1.0f, 2.0f, 3.0f, (float)i);
+}
+
+hipError_t measure_write_rates(void* buf, int Nc, int rows, double* pattern_gbs, double* stream_gbs) {
+  const size_t bytes = (size_t)rows * (size_t)Nc * sizeof(float);
+  const size_t n4 = bytes / 16;
+  const int block = 256;
+  const unsigned grid_p = (unsigned)((Nc + block - 1) / block);
+  const unsigned grid_s = (unsigned)(device_cu_count() * 16);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  float best_p = 1e30f, best_s = 1e30f;
+  for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
+    for (int kind = 0; kind < 2 && e == hipSuccess; ++kind) {
+      if (kind == 0) traj_pattern_kernel<<<grid_p, block, 0, 0>>>((float*)buf, Nc, rows);  // warm
+      else write_stream_kernel<<<grid_s, block, 0, 0>>>((float4*)buf, n4);
+      if ((e = hipEventRecord(e0, 0)) != hipSuccess) break;
+      if (kind == 0) traj_pattern_kernel<<<grid_p, block, 0, 0>>>((float*)buf, Nc, rows);
+      else write_stream_kernel<<<grid_s, block, 0, 0>>>((float4*)buf, n4);
+      if ((e = hipGetLastError()) != hipSuccess) break;
+      if ((e = hipEventRecord(e1, 0)) != hipSuccess) break;
+      if ((e = hipEventSynchronize(e1)) != hipSuccess) break;
+      float ms = 0.0f;
+      if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
+      if (kind == 0) best_p = ms < best_p ? ms : best_p;
+      else best_s = ms < best_s ? ms : best_s;
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return e;
+  *pattern_gbs = (double)bytes / ((double)best_p * 1e-3) / 1e9;
+  *stream_gbs = (double)(n4 * 16) / ((double)best_s * 1e-3) / 1e9;
+  return hipSuccess;
+}
+
 }  // namespace mpmi

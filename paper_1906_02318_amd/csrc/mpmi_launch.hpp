@@ -90,6 +90,9 @@ hipError_t launch_gemm_test(const uint16_t* A, const uint16_t* B, int M, int N, 
 // TFLOP/s; `sink` is any device buffer of >= 4 bytes (never written in
 // practice).
 hipError_t measure_fma_rate(float* sink, double* tflops);
+// Write ceilings on buf (rows * Nc floats, overwritten): the trajectory
+// store's pattern and a contiguous stream, GB/s.
+hipError_t measure_write_rates(void* buf, int Nc, int rows, double* pattern_gbs, double* stream_gbs);
 
 // Many-loop tick (mpmi_multi.hip).
 struct WorkItem;

@@ -106,6 +106,7 @@ def library() -> ctypes.CDLL:
         "mpmi_tick": (i32, [vp, vp, ctypes.POINTER(TickDesc), vp, vp, vp, vp, vp, vp, vp]),
         "mpmi_generate_candidates": (i32, [vp, vp, ctypes.POINTER(TickDesc), vp, vp, vp, vp]),
         "mpmi_fp32_fma_rate": (i32, [vp, ctypes.POINTER(f64)]),
+        "mpmi_write_rates": (i32, [vp, vp, i32, i32, ctypes.POINTER(f64), ctypes.POINTER(f64)]),
         "mpmi_multi_create": (i32, [vp, ctypes.POINTER(LoopDesc), i32, ctypes.POINTER(MultiConfig), ctypes.POINTER(vp)]),
         "mpmi_multi_destroy": (None, [vp]),
         "mpmi_multi_set_config": (i32, [vp, vp, ctypes.POINTER(MultiConfig)]),
@@ -385,6 +386,15 @@ def mpmi_generate_candidates(ctx: Context, model: Model, desc: TickDesc, u_user,
     ctx.check(ctx.lib.mpmi_generate_candidates(ctx.handle, ctypes.c_void_p(model.ptr), ctypes.byref(desc),
                                                _ptr(u_user), _ptr(cand), _ptr(out), _stream(stream)))
     return out
+
+
+def mpmi_write_rates(ctx: Context, buf, Nc: int, rows: int) -> dict:
+    """Write ceilings (GB/s) of the trajectory store's pattern and of a
+    contiguous stream, on buf (rows * Nc float32, overwritten; synchronous)."""
+    _need(buf, "buf", torch.float32, rows * Nc, device=ctx.device)
+    p, q = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    ctx.check(ctx.lib.mpmi_write_rates(ctx.handle, _ptr(buf), Nc, rows, ctypes.byref(p), ctypes.byref(q)))
+    return dict(pattern_GB_s=p.value, stream_GB_s=q.value)
 
 
 def mpmi_fp32_fma_rate(ctx: Context) -> float:

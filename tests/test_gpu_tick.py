@@ -639,6 +639,20 @@ def test_tick_lanes_per_candidate_identical_and_autotuned(ctx, bb, rc, case):
     assert rec == recs[0]
 
 
+def test_write_rate_diagnostic(ctx):
+    """The trajectory store's write ceilings: both rates finite, below the
+    part's 8 TB/s, and the scattered-row pattern no faster than the
+    contiguous stream (within timing noise)."""
+    Nc, rows = 262145, 60
+    buf = torch.empty(rows * Nc, dtype=torch.float32, device="cuda")
+    r = mpmi.mpmi_write_rates(ctx, buf, Nc, rows)
+    log(f"[diag] write ceilings: {r}")
+    assert 100.0 < r["pattern_GB_s"] < 8000.0 and 100.0 < r["stream_GB_s"] < 8000.0
+    assert r["pattern_GB_s"] <= 1.1 * r["stream_GB_s"]
+    with pytest.raises(mpmi.MpmiError):
+        mpmi.mpmi_write_rates(ctx, buf[1:], Nc - 1, rows)  # misaligned
+
+
 def test_fp32_fma_rate_diagnostic(ctx):
     """The non-packed FP32 FMA ceiling the roofline is judged against: within
     the part's theoretical 78.6 TFLOP/s (256 CUs x 4 SIMDs x 16 lanes x 2 x
