@@ -18,6 +18,7 @@ constexpr int kFitRows = 64;       // rows per LDS tile
 constexpr int kFitBlocks = 256;    // maximum partial-sum workgroups
 constexpr int kFitCols = MPMI_MAX_DIM + MPMI_MAX_STATE;  // D + n <= 72
 constexpr int kFitThreads = 256;  // four waves: the solve kernel gives each a task
+static_assert(kFitThreads == 4 * 64, "solve_kernel assigns tasks to exactly four waves");
 constexpr int kFitPerThread = (MPMI_MAX_DIM * kFitCols + kFitThreads - 1) / kFitThreads;  // 18
 
 struct FitInfo {
