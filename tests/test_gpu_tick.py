@@ -529,6 +529,55 @@ def test_full_size_race_car_sampled_parity_and_properties(ctx, rc):
             f"sampled={idx.size} ambiguous={int(amb.sum())}")
 
 
+def test_tick_maximum_candidate_count(ctx, bb):
+    """The largest tick the interface allows (Nc = MPMI_MAX_CAND: a 1-D grid of
+    2^25 - 2 inputs + u_h), cart-pole, H = 10: one lane and four lanes per
+    candidate give identical records and first violations (the four-lane
+    launch has 2^19 workgroups, so every sub-slot serves 2^16 of them); first
+    violations of ~3,000 sampled candidates agree with the oracle; n_safe is
+    the count of safe candidates besides u_h; the choice is oracle-safe and no
+    sampled safe candidate is cheaper."""
+    so, model, K = bb
+    N = mpmi.MAX_CAND - 1
+    H = 10
+    # a pole falling at 1.2 rad/s from 0.35 rad: about half the inputs keep it
+    # up for 10 steps, and the user's -4 N is not one of them
+    x, u = W.f32([0.0, 0.0, 0.35, 1.2]), W.f32([-4.0])
+    recs, fvs = [], []
+    for lanes in (1, 4):
+        desc = mpmi.tick_desc(N, H, gen=mpmi.GEN_GRID, grid=[N], lanes_per_cand=lanes)
+        fv = torch.empty(N + 1, dtype=torch.int16, device="cuda")
+        recs.append(mpmi.mpmi_tick(ctx, model, desc, dev(x, torch.float32), dev(u, torch.float32),
+                                   first_violation=fv).cpu().numpy().tobytes())
+        fvs.append(fv)
+    assert recs[0] == recs[1]
+    assert torch.equal(fvs[0], fvs[1])
+    fvg = fvs[0].cpu().numpy().astype(np.int64)
+    del fvs
+    sel = mpmi.decode_selection(torch.tensor(np.frombuffer(recs[0], np.uint8)))
+    assert sel["n_cand"] == N + 1
+    assert sel["n_safe"] == int(np.count_nonzero(fvg[1:] == H + 1))
+    assert 0 < sel["n_safe"] < N and fvg[0] <= H  # a mixed tick: the user's input is unsafe
+    assert sel["status"] == mpmi.OK and sel["idx"] != 0
+    rng = np.random.default_rng(5)
+    idx = np.unique(np.concatenate([[0, sel["idx"]], rng.integers(1, N + 1, size=3000)]))
+    grid = o.grid_candidates(so, [N])
+    cand = o.with_user(grid[idx[1:] - 1], u, 1)  # idx[0] == 0: u_h first, then the sampled grid points
+    del grid
+    traj, fvo = o.rollout(so, K, x, cand, H, early_exit=False)
+    from tests.parity import ambiguous
+    amb = ambiguous(so, traj, fvo, fvg[idx], EPS_BB)
+    assert np.all((fvo == fvg[idx]) | amb)
+    cost = o.cost(so, cand, u)
+    j = int(np.nonzero(idx == sel["idx"])[0][0])
+    if sel["status"] == mpmi.OK:
+        assert fvo[j] == H + 1 or amb[j]
+        cheaper = (fvo == H + 1) & ~amb & (cost < cost[j] * (1 - 1e-6) - 1e-12)
+        assert not cheaper.any()
+    log(f"[max size] Nc={N + 1}: idx={sel['idx']} status={sel['status']} n_safe={sel['n_safe']} "
+        f"ambiguous={int(amb.sum())}")
+
+
 @pytest.mark.parametrize("system", ["bb", "rc"])
 def test_tick_with_process_noise(ctx, system):
     """Alg. 2's process noise z_i: every predicted state gains sigma * z, z from
