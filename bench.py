@@ -390,6 +390,32 @@ def run_trajectory_store(st: dict, reps: int = 10):
                      "bytes_written": wbytes, "write_GB_s": rate, "hbm_frac": rate / 8000.0,
                      "pattern_ceiling_GB_s": ceil["pattern_GB_s"], "stream_ceiling_GB_s": ceil["stream_GB_s"],
                      "pattern_frac": rate / ceil["pattern_GB_s"]}
+        if side == 1024:
+            # The same tick through the separable calls: candidates, full
+            # rollout (no early exit: the mask decides afterwards), safe mask,
+            # selection -- against the fused launch.
+            cand = mpmi.mpmi_generate_candidates(ctx, model, desc, u)
+            sel_f = mpmi.decode_selection(mpmi.mpmi_tick(ctx, model, desc, x, u))
+            ph = {"rollout_batch": [], "safe_mask": [], "select_min_intervention": []}
+            for r in range(reps + 2):
+                ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+                ev[0].record(stream)
+                mpmi.rollout_batch(ctx, model, x, cand, H, traj=traj, stream=stream)
+                ev[1].record(stream)
+                fvs, _ = mpmi.safe_mask(ctx, model, traj, with_margin=False, stream=stream)
+                ev[2].record(stream)
+                rec = mpmi.select_min_intervention(ctx, model, cand, fvs, H, u, stream=stream)
+                ev[3].record(stream)
+                torch.cuda.synchronize()
+                if r >= 2:
+                    for k, name in enumerate(ph):
+                        ph[name].append(ev[k].elapsed_time(ev[k + 1]))
+            sel_s = mpmi.decode_selection(rec)
+            res["separable_calls_1m"] = {k: float(np.median(v)) for k, v in ph.items()}
+            res["separable_calls_1m"]["ms_total"] = float(sum(np.median(v) for v in ph.values()))
+            res["separable_calls_1m"]["ms_fused_tick"] = times["decision"]
+            res["separable_calls_1m"]["same_selection"] = bool(sel_s == sel_f)
+            del cand
         del traj
         torch.cuda.empty_cache()
     return res

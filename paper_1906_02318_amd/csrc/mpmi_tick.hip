@@ -68,6 +68,7 @@ rollout_fp32_kernel(const ModelDev* __restrict__ md, int Nc, int S, int H, const
       stp.set_input(md, sK, u);
     }
     stp.step(md, sK, x);
+    settle_state<NS>(x);
 #pragma unroll
     for (int j = 0; j < NS; ++j)
       if (j < n) __builtin_nontemporal_store(x[j], &traj[((size_t)(s - 1) * n + j) * (size_t)Nc + c]);
