@@ -11,6 +11,7 @@
 // the last workgroup to finish decodes the key (no second launch).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstring>
 
 #include "mpmi_device.hpp"
@@ -75,6 +76,15 @@ rollout_fp32_kernel(const ModelDev* __restrict__ md, int Nc, int S, int H, const
   }
 }
 
+// Safety of stored trajectories (Alg. 2's check over predicted states), one
+// candidate per lane.  The states of kMaskChunk steps are loaded before any
+// of them is checked, so a lane keeps that many steps' loads in flight
+// instead of one memory round trip per step; they are then checked in step
+// order, so the first violation and the least margin up to it are those of
+// a step-by-step scan.  At most kMaskChunk - 1 steps past the first violation
+// are read and ignored.
+constexpr int kMaskChunk = 4;
+
 template <int NS>
 __global__ void __launch_bounds__(1024)
 mask_kernel(const ModelDev* __restrict__ md, int Nc, int H, const float* __restrict__ traj,
@@ -84,39 +94,108 @@ mask_kernel(const ModelDev* __restrict__ md, int Nc, int H, const float* __restr
   const int n = md->n;
   int fv = H + 1;
   float least = INFINITY;
-  for (int s = 1; s <= H; ++s) {
-    float x[NS];
+  for (int s0 = 1; s0 <= H && fv > H; s0 += kMaskChunk) {
+    float x[kMaskChunk][NS];
+    // Every load is issued: a step past the horizon rereads the last one
+    // (never checked) and a component past n rereads component n - 1 (then
+    // zeroed), so no load sits behind a branch that waits for it.
 #pragma unroll
-    for (int j = 0; j < NS; ++j) x[j] = (j < n) ? traj[((size_t)(s - 1) * n + j) * (size_t)Nc + c] : 0.0f;
-    const float mg = min_margin<NS>(md, x);
-    least = (mg != mg) ? mg : fminf(least, mg);
-    if (!(mg > 0.0f)) {
-      fv = s;
-      break;
+    for (int k = 0; k < kMaskChunk; ++k) {
+      const int s = min(s0 + k, H);
+#pragma unroll
+      for (int j = 0; j < NS; ++j) {
+        const int jj = j < n ? j : n - 1;
+        const float v = traj[((size_t)(s - 1) * n + jj) * (size_t)Nc + c];
+        x[k][j] = j < n ? v : 0.0f;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kMaskChunk; ++k) {
+      if (s0 + k > H) break;
+      const float mg = min_margin<NS>(md, x[k]);
+      least = (mg != mg) ? mg : fminf(least, mg);
+      if (!(mg > 0.0f)) {
+        fv = s0 + k;
+        break;
+      }
     }
   }
   fv_out[c] = (int16_t)fv;
   if (mm_out) mm_out[c] = least;
 }
 
+// Selection over given first violations (Alg. 2's arg-min).  A pass of a
+// workgroup covers kSelectPer * kSelectBlock candidates, kSelectPer per lane
+// (lane t takes base + q * kSelectBlock + t, so each load stays coalesced),
+// all of a lane's loads issued before its keys are formed; passes repeat over
+// at most kSelectParts workgroups.  A workgroup per 256 candidates would make
+// the parts' slot atomics, not the ten bytes read per candidate, the cost at
+// a million candidates.  The keys carry the candidate index, so the minimum
+// does not depend on which part saw which candidate.
+constexpr int kSelectBlock = 1024, kSelectPer = 4;
+constexpr unsigned int kSelectParts = 256;
+
 template <int MS>
-__global__ void __launch_bounds__(1024)
+__global__ void __launch_bounds__(kSelectBlock)
 select_kernel(const ModelDev* __restrict__ md, GenParams gp, int H, const float* __restrict__ cand,
               const int16_t* __restrict__ fv_in, const float* __restrict__ u_user,
               Slot* __restrict__ slot, mpmi_selection* __restrict__ out) {
   const int Nc = gp.n_cand + 1;
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  const bool valid = c < Nc;
-  float u0[MS];
+  const int m = md->m;
+  const long long pass = (long long)gridDim.x * kSelectBlock * kSelectPer;
+  // The cost with unused components weighted zero: the same sum as the
+  // tick's (each skipped term adds 0 * 0 to a non-negative sum), with no
+  // branch for the compiler to sink a candidate load into.
+  float uu[MS], hw[MS];
 #pragma unroll
-  for (int j = 0; j < MS; ++j)
-    u0[j] = (valid && j < md->m) ? cand[(size_t)j * (size_t)Nc + c] : 0.0f;
-  const int fv = valid ? (int)fv_in[c] : 0;
-  const float cst = valid ? cost_of<MS>(md, u0, u_user) : 0.0f;
-  const bool safe = valid && fv == H + 1;
-  const unsigned long long ks = safe ? safe_key(cst, c) : kKeyNone;
-  const unsigned long long kf = (valid && !safe) ? fallback_key(fv < 1 ? 1 : (fv > H ? H : fv), cst, c) : kKeyNone;
-  if (reduce_and_publish(ks, kf, safe && c > 0, slot, gridDim.x, blockIdx.x) && threadIdx.x == 0)
+  for (int j = 0; j < MS; ++j) {
+    uu[j] = j < m ? u_user[j] : 0.0f;
+    hw[j] = j < m ? md->half_inv[j] : 0.0f;
+  }
+  unsigned long long ks = kKeyNone, kf = kKeyNone;
+  unsigned int n_safe = 0;  // uniform across the wave
+  for (long long base = (long long)blockIdx.x * kSelectBlock * kSelectPer; base < Nc; base += pass) {
+    float u0[kSelectPer][MS];
+    int fv[kSelectPer];
+    // Lanes past the end read the last candidate (in bounds) and drop it.
+#pragma unroll
+    for (int q = 0; q < kSelectPer; ++q) {
+      const int cc = (int)min(base + q * kSelectBlock + threadIdx.x, (long long)Nc - 1);
+#pragma unroll
+      for (int j = 0; j < MS; ++j) u0[q][j] = cand[(size_t)(j < m ? j : m - 1) * (size_t)Nc + cc];
+      fv[q] = fv_in[cc];
+    }
+    // One wait for all of them: the empty statement takes every loaded value,
+    // so no key arithmetic is scheduled between the loads.
+    static_assert(kSelectPer == 4 && MS == 4, "operand list below");
+    asm volatile("" : "+v"(u0[0][0]), "+v"(u0[0][1]), "+v"(u0[0][2]), "+v"(u0[0][3]), "+v"(u0[1][0]),
+                      "+v"(u0[1][1]), "+v"(u0[1][2]), "+v"(u0[1][3]), "+v"(u0[2][0]), "+v"(u0[2][1]),
+                      "+v"(u0[2][2]), "+v"(u0[2][3]), "+v"(u0[3][0]), "+v"(u0[3][1]), "+v"(u0[3][2]),
+                      "+v"(u0[3][3]), "+v"(fv[0]), "+v"(fv[1]), "+v"(fv[2]), "+v"(fv[3]));
+#pragma unroll
+    for (int q = 0; q < kSelectPer; ++q)
+#pragma unroll
+      for (int j = 1; j < MS; ++j) u0[q][j] = j < m ? u0[q][j] : 0.0f;  // m >= 1
+#pragma unroll
+    for (int q = 0; q < kSelectPer; ++q) {
+      const int c = (int)(base + q * kSelectBlock + threadIdx.x);
+      const bool valid = base + q * kSelectBlock + threadIdx.x < Nc;
+      float cst = 0.0f;
+#pragma unroll
+      for (int j = 0; j < MS; ++j) {
+        const float d = (u0[q][j] - uu[j]) * hw[j];
+        cst = fmaf(d, d, cst);
+      }
+      const bool safe = valid && fv[q] == H + 1;
+      const unsigned long long a = safe ? safe_key(cst, c) : kKeyNone;
+      const unsigned long long b =
+          (valid && !safe) ? fallback_key(fv[q] < 1 ? 1 : (fv[q] > H ? H : fv[q]), cst, c) : kKeyNone;
+      ks = a < ks ? a : ks;
+      kf = b < kf ? b : kf;
+      n_safe += (unsigned int)__popcll(__ballot(safe && c > 0));
+    }
+  }
+  if (publish_wave_counted(ks, kf, n_safe, slot, gridDim.x, blockIdx.x) && threadIdx.x == 0)
     finalize<MS>(md, gp, cand, u_user, H, slot, out);
 }
 
@@ -343,8 +422,8 @@ hipError_t launch_select(const void* model, int Nc, int S, int H, const float* c
   gp.n_seg = S;
   gp.loop = loop;
   for (int j = 0; j < MPMI_MAX_INPUT; ++j) gp.grid[j] = 1;
-  const int block = 256;
-  select_kernel<MPMI_MAX_INPUT><<<blocks_for(Nc, block), block, 0, st>>>(
+  const unsigned grid = std::min(blocks_for(Nc, kSelectBlock * kSelectPer), kSelectParts);
+  select_kernel<MPMI_MAX_INPUT><<<grid, kSelectBlock, 0, st>>>(
       (const ModelDev*)model, gp, H, cand, fv, u_user, (Slot*)slot, out);
   return hipGetLastError();
 }

@@ -33,23 +33,23 @@ __device__ __forceinline__ float cost_of(const ModelDev* __restrict__ md, const 
   return cst;
 }
 
-// Workgroup reduction of the two keys and the safe count, then the part's
-// atomics on its sub-slot (part < n_parts; n_parts parts serve this slot in
-// this launch); returns true in every thread of the workgroup that completes
-// the slot.  Up to kOneLevelParts parts take their ticket on the slot itself
-// (contention stays small); more parts take one on their sub-slot first, and
-// the last of each sub-slot one on the slot.
+// Workgroup reduction of the two keys and the waves' safe counts (cnt is the
+// wave's count, uniform across it), then the part's atomics on its sub-slot
+// (part < n_parts; n_parts parts serve this slot in this launch); returns
+// true in every thread of the workgroup that completes the slot.  Up to
+// kOneLevelParts parts take their ticket on the slot itself (contention stays
+// small); more parts take one on their sub-slot first, and the last of each
+// sub-slot one on the slot.
 constexpr unsigned int kOneLevelParts = 128;
-__device__ __forceinline__ bool reduce_and_publish(unsigned long long ks, unsigned long long kf,
-                                                   bool safe_counted, Slot* __restrict__ slot,
-                                                   unsigned int n_parts, unsigned int part) {
+__device__ __forceinline__ bool publish_wave_counted(unsigned long long ks, unsigned long long kf,
+                                                     unsigned int cnt, Slot* __restrict__ slot,
+                                                     unsigned int n_parts, unsigned int part) {
   __shared__ unsigned long long s_ks[16], s_kf[16];
   __shared__ unsigned int s_cnt[16];
   __shared__ int s_last;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   ks = wave_min_u64(ks);
   kf = wave_min_u64(kf);
-  const unsigned int cnt = (unsigned int)__popcll(__ballot(safe_counted));
   if (lane == 0) {
     s_ks[wave] = ks;
     s_kf[wave] = kf;
@@ -90,6 +90,14 @@ __device__ __forceinline__ bool reduce_and_publish(unsigned long long ks, unsign
   }
   __syncthreads();
   return s_last != 0;
+}
+
+// The same for one candidate per lane: the wave's count is its number of
+// lanes with safe_counted set.
+__device__ __forceinline__ bool reduce_and_publish(unsigned long long ks, unsigned long long kf,
+                                                   bool safe_counted, Slot* __restrict__ slot,
+                                                   unsigned int n_parts, unsigned int part) {
+  return publish_wave_counted(ks, kf, (unsigned int)__popcll(__ballot(safe_counted)), slot, n_parts, part);
 }
 
 // Decodes the slot into the selection and resets the slot (one thread, in

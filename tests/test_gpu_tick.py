@@ -151,12 +151,14 @@ def test_safe_mask_on_synthetic_trajectories(ctx, bb, rc, system):
 
 
 # ------------------------------------------------------------------ select --
-@pytest.mark.parametrize("case", ["mixed", "user_safe", "none_safe", "ragged_large"])
+@pytest.mark.parametrize("case", ["mixed", "user_safe", "none_safe", "ragged_large", "million"])
 def test_select_min_intervention_parity(ctx, bb, rc, case):
-    rng = np.random.default_rng({"mixed": 1, "user_safe": 2, "none_safe": 3, "ragged_large": 4}[case])
+    """The million case has more candidates than the launch has lanes: each
+    lane scans several, the last pass ragged."""
+    rng = np.random.default_rng({"mixed": 1, "user_safe": 2, "none_safe": 3, "ragged_large": 4, "million": 5}[case])
     so, model, _ = rc
     H, S = 60, 2
-    Nc = 200_001 if case == "ragged_large" else 4097
+    Nc = {"ragged_large": 200_001, "million": 1_048_577}.get(case, 4097)
     cand = W.f32(o.with_user(o.uniform_candidates(so, Nc - 1, S, 5, 0, 0), [0.1, 0.4], S))
     fv = rng.integers(1, H + 2, size=Nc)
     if case == "user_safe":
