@@ -2,12 +2,14 @@
 // least squares as in extended DMD).  Three launches:
 //   1. gram:   every workgroup lifts tiles of 64 rows into LDS (psi computed on
 //              the fly, never materialised in HBM) and accumulates its share
-//              of Z^T Z restricted to the first D rows, Z = [Psi | Y];
+//              of Z^T Z restricted to the first D rows, Z = [Psi | Y], in
+//              4 x 6 register blocks;
 //   2. reduce: partial sums added in a fixed order (deterministic);
 //   3. solve:  one workgroup: RMS column scaling, ridge, Cholesky of the
 //              scaled Gram matrix in LDS, then, one wave per task, the two
-//              triangular solves per right-hand side, unscaling, and power /
-//              inverse iteration for the condition number.
+//              triangular solves per right-hand side and unscaling, power
+//              iteration on the Gram matrix and on its inverse (formed from
+//              the factor's inverse) for the condition number.
 #include <hip/hip_runtime.h>
 
 #include "mpmi_launch.hpp"
@@ -19,7 +21,6 @@ constexpr int kFitBlocks = 256;    // maximum partial-sum workgroups
 constexpr int kFitCols = MPMI_MAX_DIM + MPMI_MAX_STATE;  // D + n <= 72
 constexpr int kFitThreads = 256;  // four waves: the solve kernel gives each a task
 static_assert(kFitThreads == 4 * 64, "solve_kernel assigns tasks to exactly four waves");
-constexpr int kFitPerThread = (MPMI_MAX_DIM * kFitCols + kFitThreads - 1) / kFitThreads;  // 18
 
 struct FitInfo {
   int32_t status;
@@ -27,99 +28,137 @@ struct FitInfo {
   double cond;
 };
 
-// psi(x, u) in FP64, same feature order as the FP32 path.
-__device__ void lift_f64(int basis, int n, int m, const double* x, const double* u, double* psi) {
+// psi(x, u) of one transition in FP64, the FP32 path's feature order,
+// written to z (an LDS row) from the row's state xr[n] and input ur[m].  The
+// fixed bases take their atoms into registers by constant index.
+__device__ __forceinline__ void lift_row(int basis, int n, int m, const double* __restrict__ xr,
+                                         const double* __restrict__ ur, double* z) {
   if (basis == MPMI_BASIS_LINEAR) {
-    for (int k = 0; k < n; ++k) psi[k] = x[k];
-    for (int k = 0; k < m; ++k) psi[n + k] = u[k];
+    for (int k = 0; k < n; ++k) z[k] = xr[k];
+    for (int k = 0; k < m; ++k) z[n + k] = ur[k];
     return;
   }
   if (basis == MPMI_BASIS_BALANCE_BOT) {
-    const double w[5] = {x[0], x[1], x[2], x[3], u[0]};
+    const double w[5] = {xr[0], xr[1], xr[2], xr[3], ur[0]};
     int f = 0;
-    psi[f++] = 1.0;
-    for (int k = 0; k < 5; ++k) psi[f++] = w[k];
+    z[f++] = 1.0;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) z[f++] = w[k];
+#pragma unroll
     for (int k = 0; k < 5; ++k)
-      for (int l = k; l < 5; ++l) psi[f++] = w[k] * w[l];
+#pragma unroll
+      for (int l = k; l < 5; ++l) z[f++] = w[k] * w[l];
     return;
   }
-  const double w[8] = {x[0], x[1], x[2], x[3], x[4], x[5], u[0], u[1]};
+  const double w[8] = {xr[0], xr[1], xr[2], xr[3], xr[4], xr[5], ur[0], ur[1]};
   int f = 0;
-  psi[f++] = 1.0;
-  for (int k = 0; k < 8; ++k) psi[f++] = w[k];
+  z[f++] = 1.0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) z[f++] = w[k];
+#pragma unroll
   for (int k = 0; k < 8; ++k)
-    for (int l = k; l < 8; ++l) psi[f++] = w[k] * w[l];
+#pragma unroll
+    for (int l = k; l < 8; ++l) z[f++] = w[k] * w[l];
   const double sp = sin(w[2]), cp = cos(w[2]), sd = sin(w[6]), cd = cos(w[6]);
   const double vx = w[3], vy = w[4], r = w[5], a = w[7];
-  psi[f++] = sp; psi[f++] = cp; psi[f++] = sd; psi[f++] = cd;
-  psi[f++] = sp * vx; psi[f++] = sp * vy; psi[f++] = sp * r; psi[f++] = sp * a;
-  psi[f++] = cp * vx; psi[f++] = cp * vy; psi[f++] = cp * r; psi[f++] = cp * a;
-  psi[f++] = sd * vx; psi[f++] = sd * vy; psi[f++] = sd * r;
-  psi[f++] = cd * vx; psi[f++] = cd * vy; psi[f++] = cd * r;
-  psi[f++] = a * sd;
+  z[f++] = sp; z[f++] = cp; z[f++] = sd; z[f++] = cd;
+  z[f++] = sp * vx; z[f++] = sp * vy; z[f++] = sp * r; z[f++] = sp * a;
+  z[f++] = cp * vx; z[f++] = cp * vy; z[f++] = cp * r; z[f++] = cp * a;
+  z[f++] = sd * vx; z[f++] = sd * vy; z[f++] = sd * r;
+  z[f++] = cd * vx; z[f++] = cd * vy; z[f++] = cd * r;
+  z[f++] = a * sd;
 }
+
+// Register blocks of the accumulation: thread t owns rows a0 .. a0 + 3 by
+// columns b0 .. b0 + 5 of Z^T Z, so a tile row costs it 10 LDS reads for 24
+// FMAs.  Each entry still sums the rows in their order.
+constexpr int kGa = 4, kGb = 6;
+constexpr int kGaBlocks = MPMI_MAX_DIM / kGa;            // 16
+constexpr int kGbBlocks = (kFitCols + kGb - 1) / kGb;    // 12
+constexpr int kZCols = kGbBlocks * kGb;                  // 72: every block's columns lie in the row
+constexpr int kZStride = kZCols + 2;                     // 16-byte aligned rows
+static_assert(kGaBlocks * kGbBlocks <= kFitThreads, "one register block per thread");
+static_assert(MPMI_MAX_DIM % kGa == 0, "feature blocks");
 
 __global__ void __launch_bounds__(kFitThreads)
 gram_kernel(int basis, int n, int m, int D, const double* __restrict__ X, const double* __restrict__ U,
             const double* __restrict__ Y, long long T, double* __restrict__ part) {
-  __shared__ double Z[kFitRows][kFitCols + 1];
+  __shared__ __attribute__((aligned(16))) double Z[kFitRows][kZStride];
   const int C = D + n;
   const int E = D * C;
-  double acc[kFitPerThread];
-  int ea[kFitPerThread], eb[kFitPerThread];
+  const int ab = (int)threadIdx.x / kGbBlocks, bb = (int)threadIdx.x % kGbBlocks;
+  const int a0 = ab * kGa, b0 = bb * kGb;
+  const bool active = ab < kGaBlocks && a0 < D && b0 < C;
+  double acc[kGa][kGb];
 #pragma unroll
-  for (int k = 0; k < kFitPerThread; ++k) {
-    acc[k] = 0.0;
-    const int e = threadIdx.x + k * kFitThreads;
-    ea[k] = e < E ? e / C : 0;
-    eb[k] = e < E ? e % C : 0;
-  }
+  for (int i = 0; i < kGa; ++i)
+#pragma unroll
+    for (int j = 0; j < kGb; ++j) acc[i][j] = 0.0;
   const long long ntiles = (T + kFitRows - 1) / kFitRows;
   for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const long long r0 = tile * kFitRows;
     if (threadIdx.x < kFitRows) {
       const long long r = r0 + threadIdx.x;
-      double psi[MPMI_MAX_DIM];
-      double x[MPMI_MAX_STATE], u[MPMI_MAX_INPUT];
+      double* z = Z[threadIdx.x];
       if (r < T) {
-        for (int k = 0; k < n; ++k) x[k] = X[r * n + k];
-        for (int k = 0; k < m; ++k) u[k] = U[r * m + k];
-        lift_f64(basis, n, m, x, u, psi);
-        for (int k = 0; k < D; ++k) Z[threadIdx.x][k] = psi[k];
-        for (int k = 0; k < n; ++k) Z[threadIdx.x][D + k] = Y[r * n + k];
+        lift_row(basis, n, m, X + r * n, U + r * m, z);
+        for (int k = 0; k < n; ++k) z[D + k] = Y[r * n + k];
       } else {
-        for (int k = 0; k < C; ++k) Z[threadIdx.x][k] = 0.0;
+        for (int k = 0; k < C; ++k) z[k] = 0.0;
+      }
+      for (int k = C; k < kZCols; ++k) z[k] = 0.0;
+    }
+    __syncthreads();
+    if (active) {
+#pragma unroll 4
+      for (int rr = 0; rr < kFitRows; ++rr) {
+        double av[kGa], bv[kGb];
+#pragma unroll
+        for (int i = 0; i < kGa; ++i) av[i] = Z[rr][a0 + i];
+#pragma unroll
+        for (int j = 0; j < kGb; ++j) bv[j] = Z[rr][b0 + j];
+#pragma unroll
+        for (int i = 0; i < kGa; ++i)
+#pragma unroll
+          for (int j = 0; j < kGb; ++j) acc[i][j] = fma(av[i], bv[j], acc[i][j]);
       }
     }
     __syncthreads();
-    for (int rr = 0; rr < kFitRows; ++rr) {
-#pragma unroll
-      for (int k = 0; k < kFitPerThread; ++k) acc[k] = fma(Z[rr][ea[k]], Z[rr][eb[k]], acc[k]);
-    }
-    __syncthreads();
   }
+  if (!active) return;
+  double* out = part + (size_t)blockIdx.x * E;
 #pragma unroll
-  for (int k = 0; k < kFitPerThread; ++k) {
-    const int e = threadIdx.x + k * kFitThreads;
-    if (e < E) part[(size_t)blockIdx.x * E + e] = acc[k];
-  }
+  for (int i = 0; i < kGa; ++i)
+#pragma unroll
+    for (int j = 0; j < kGb; ++j)
+      if (a0 + i < D && b0 + j < C) out[(a0 + i) * C + b0 + j] = acc[i][j];
 }
 
-// tot[e] = sum over the parts of part[p][e], in a fixed order: the four
-// threads of element e sum parts p = q, q + 4, ... (q = 0..3), then add the
-// four quarters in order.  A workgroup covers kReduceElems elements.
-constexpr int kReduceElems = 64;
-__global__ void __launch_bounds__(4 * kReduceElems)
+// tot[e] = sum over the parts of part[p][e], in a fixed order: the
+// kReduceWays threads of element e sum parts p = q, q + kReduceWays, ...
+// (q = 0 .. kReduceWays - 1), then one of them adds the partial sums in q
+// order.  A workgroup covers kReduceElems elements (lanes of one q read
+// consecutive elements); the grid spreads the ~4,500 elements of the race
+// car over ~280 workgroups.
+constexpr int kReduceElems = 16, kReduceWays = 16;
+__global__ void __launch_bounds__(kReduceElems * kReduceWays)
 reduce_kernel(int nparts, int E, const double* __restrict__ part, double* __restrict__ tot) {
-  __shared__ double q4[4][kReduceElems];
+  __shared__ double qs[kReduceWays][kReduceElems];
   const int el = threadIdx.x % kReduceElems, q = threadIdx.x / kReduceElems;
   const int e = blockIdx.x * kReduceElems + el;
   double s = 0.0;
-  if (e < E)
-    for (int p = q; p < nparts; p += 4) s += part[(size_t)p * E + e];
-  q4[q][el] = s;
+  if (e < E) {
+#pragma unroll 4
+    for (int p = q; p < nparts; p += kReduceWays) s += part[(size_t)p * E + e];
+  }
+  qs[q][el] = s;
   __syncthreads();
-  if (q == 0 && e < E) tot[e] = ((q4[0][el] + q4[1][el]) + q4[2][el]) + q4[3][el];
+  if (q == 0 && e < E) {
+    double t = qs[0][el];
+#pragma unroll
+    for (int k = 1; k < kReduceWays; ++k) t += qs[k][el];
+    tot[e] = t;
+  }
 }
 
 // Value of x in lane k (k wave-uniform), to every lane of the wave.
@@ -153,36 +192,72 @@ __device__ __forceinline__ double wave_sum(double x) {
   return lane_bcast(x, 63);
 }
 
-// L z = b with the Cholesky factor in the lower triangle of Lf (diagonal
-// included): lane i holds b_i and 1 / L_ii (rinv) and returns z_i (lanes >= D
-// hold 0).  Column by column: z_k = r_k / L_kk once lane k's residual r_k is
-// complete (lane k forms the quotient, the wave reads it back), then every
-// later row subtracts L_ik z_k.  No division in the serial chain.
-template <int LD>
-__device__ __forceinline__ double wave_lower_solve(const double (&Lf)[MPMI_MAX_DIM][LD], int D, int lane, double rinv,
-                                                   double b) {
-  double r = b, z = 0.0;
-#pragma unroll 4
-  for (int k = 0; k < D; ++k) {
-    const double zk = lane_bcast(r * rinv, k);
-    if (lane == k) z = zk;
-    if (lane > k && lane < D) r = fma(-Lf[lane][k], zk, r);
-  }
-  return z;
+// The factor as lane i keeps it in registers: m[k] = L_ik for k < i (its
+// row) and L_ki for k > i (its column), zero past D.  The forward solve uses
+// lane i's residual only up to step i and the backward solve only down to
+// step i, so each may subtract the other half's entries after that point; a
+// solve step is then a multiply, a broadcast and an FMA, with no memory
+// access in the serial chain.
+__device__ __forceinline__ void load_packed_factor(const double (&L)[MPMI_MAX_DIM][MPMI_MAX_DIM + 1], int D, int lane,
+                                                   double (&m)[MPMI_MAX_DIM]) {
+  const bool own = lane < D;
+#pragma unroll
+  for (int k = 0; k < MPMI_MAX_DIM; ++k)
+    m[k] = (own && k < D && k != lane) ? (k < lane ? L[lane][k] : L[k][lane]) : 0.0;
 }
 
-// L^T y = z, the same way from the last row up.
-template <int LD>
-__device__ __forceinline__ double wave_upper_solve(const double (&Lf)[MPMI_MAX_DIM][LD], int D, int lane, double rinv,
-                                                   double z) {
-  double r = z, y = 0.0;
-#pragma unroll 4
-  for (int k = D - 1; k >= 0; --k) {
+// L L^T y = b: lane i holds b_i and rinv = 1 / L_ii (0 past D) and returns
+// y_i.  Step k of the forward solve fixes z_k = r_k / L_kk once lane k's
+// residual is complete; the backward solve runs from the last row up.
+__device__ __forceinline__ double packed_cholesky_solve(const double (&m)[MPMI_MAX_DIM], int lane, double rinv,
+                                                        double b) {
+  double r = b, z = 0.0;
+#pragma unroll
+  for (int k = 0; k < MPMI_MAX_DIM; ++k) {  // L z = b
+    const double zk = lane_bcast(r * rinv, k);
+    z = lane == k ? zk : z;
+    r = fma(-m[k], zk, r);
+  }
+  double y = 0.0;
+  r = z;
+#pragma unroll
+  for (int k = MPMI_MAX_DIM - 1; k >= 0; --k) {  // L^T y = z
     const double yk = lane_bcast(r * rinv, k);
-    if (lane == k) y = yk;
-    if (lane < k) r = fma(-Lf[k][lane], yk, r);
+    y = lane == k ? yk : y;
+    r = fma(-m[k], yk, r);
   }
   return y;
+}
+
+// Orders this wave's LDS accesses before and after it (the lanes of a wave
+// exchange values through LDS with no workgroup barrier).
+__device__ __forceinline__ void wave_lds_sync() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+
+// Largest eigenvalue of the symmetric matrix whose row `lane` the lane holds
+// in a[] (rows and columns past D zero) by 60 steps of power iteration from
+// v0: the Rayleigh quotient (w . v) / (v . v), w = A v, of the last step.
+// The iterate reaches every lane through vb (this wave's 64 doubles of LDS)
+// as broadcast reads.  Between steps it is rescaled by the hardware's
+// reciprocal square root of w . w: the quotient does not depend on the
+// scale, so no exact square root or division sits in the steps' chain.
+__device__ __forceinline__ double power_rayleigh(const double (&a)[MPMI_MAX_DIM], bool own, int lane, double v0,
+                                                 double* vb) {
+  double v = own ? v0 : 0.0, w = 0.0;
+  for (int it = 0; it < 60; ++it) {
+    vb[lane] = v;
+    wave_lds_sync();
+    double w0 = 0.0, w1 = 0.0, w2 = 0.0, w3 = 0.0;
+#pragma unroll
+    for (int j = 0; j < MPMI_MAX_DIM; j += 4) {
+      w0 = fma(a[j], vb[j], w0);
+      w1 = fma(a[j + 1], vb[j + 1], w1);
+      w2 = fma(a[j + 2], vb[j + 2], w2);
+      w3 = fma(a[j + 3], vb[j + 3], w3);
+    }
+    w = (w0 + w1) + (w2 + w3);
+    if (it + 1 < 60) v = w * __builtin_amdgcn_rsq(wave_sum(w * w));
+  }
+  return wave_sum(w * v) / wave_sum(v * v);
 }
 
 // One workgroup.  tot holds [D][C]: G = columns 0..D-1, A = columns D..D+n-1.
@@ -190,10 +265,14 @@ __global__ void __launch_bounds__(kFitThreads)
 solve_kernel(int n, int D, long long T, double ridge, const double* __restrict__ tot, double* __restrict__ K,
              FitInfo* __restrict__ info) {
   __shared__ double L[MPMI_MAX_DIM][MPMI_MAX_DIM + 1];
+  __shared__ __attribute__((aligned(16))) double Lt[MPMI_MAX_DIM][MPMI_MAX_DIM + 2];  // (L^-1)^T (wave 0)
+  __shared__ __attribute__((aligned(16))) double Lz[MPMI_MAX_DIM][MPMI_MAX_DIM + 2];  // strictly lower L, then G_s^-1
   __shared__ double B[MPMI_MAX_DIM][MPMI_MAX_STATE];
-  __shared__ double sc[MPMI_MAX_DIM];
+  __shared__ double sc[MPMI_MAX_DIM], srinv[MPMI_MAX_DIM], piv[MPMI_MAX_DIM];
+  __shared__ __attribute__((aligned(16))) double vbuf[2][MPMI_MAX_DIM];
   __shared__ int bad;
   const int t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6;
   const int C = D + n;
   if (t == 0) bad = 0;
   for (int f = t; f < D; f += blockDim.x) {
@@ -202,59 +281,101 @@ solve_kernel(int n, int D, long long T, double ridge, const double* __restrict__
     sc[f] = s > 0.0 ? s : 1.0;
   }
   __syncthreads();
-  for (int e = t; e < D * D; e += blockDim.x) {
-    const int i = e / D, j = e % D;
-    double g = tot[(size_t)i * C + j] / (sc[i] * sc[j]);
-    if (i == j) g += ridge;
-    L[i][j] = g;
+  // Thread (wave w, lane j) holds entries (w + 4r, j), r = 0..15, of G_s in
+  // registers through the factorisation; G_s itself also goes to L, whose
+  // upper triangle the condition estimate reads.  Loads use clamped (valid)
+  // indices so that none waits behind a branch.
+  constexpr int kRowsPerWave = MPMI_MAX_DIM / 4;
+  double a[kRowsPerWave];
+  {
+    const int jc = min(lane, D - 1);
+#pragma unroll
+    for (int r = 0; r < kRowsPerWave; ++r) a[r] = tot[(size_t)min(wave + 4 * r, D - 1) * C + jc];
+#pragma unroll
+    for (int r = 0; r < kRowsPerWave; ++r) {
+      const int i = wave + 4 * r;
+      a[r] = (i < D && lane < D) ? a[r] / (sc[i] * sc[lane]) + (i == lane ? ridge : 0.0) : 0.0;
+      if (i < D && lane < D) L[i][lane] = a[r];
+    }
   }
   for (int e = t; e < D * n; e += blockDim.x) {
     const int i = e / n, j = e % n;
     B[i][j] = tot[(size_t)i * C + D + j] / sc[i];
   }
+  // Cholesky, right-looking, on the register copy; one barrier per column.
+  // Column k (entries not yet scaled) is published in LDS by its owners, the
+  // threads of lane k, as col[k & 1][w][r] = entry (w + 4r, k).  Step k: with
+  // d the pivot, every thread of lane j > k subtracts c_i c_j / d from its
+  // entries (i, j) (entries above the diagonal become garbage and are never
+  // read); the threads of lane k + 1 then publish column k + 1, complete at
+  // that point.  Reads and writes of the published columns alternate between
+  // the two buffers.  The pivots are kept, and each column is scaled into
+  // the factor (L_ik = c_i / sqrt(d_k), L_kk = sqrt(d_k)) after the loop, off
+  // the steps' serial chain.
+  __shared__ __attribute__((aligned(16))) double col[2][4][kRowsPerWave];
+  if (lane == 0)
+#pragma unroll
+    for (int r = 0; r < kRowsPerWave; ++r) col[0][wave][r] = a[r];
   __syncthreads();
-  // Keep the scaled Gram matrix's upper triangle (i < j) for the condition
-  // estimate; the factor goes to the lower triangle and the diagonal.
   const double pivot_floor = 1e-14 * (double)T;
   for (int k = 0; k < D; ++k) {
-    if (t == 0) {
-      double d = L[k][k];
-      if (!(d > pivot_floor)) {
-        bad = 1;
-        d = 1.0;
-      }
-      L[k][k] = sqrt(d);
+    const double(*cur)[kRowsPerWave] = col[k & 1];
+    double d = cur[k & 3][k >> 2];
+    if (!(d > pivot_floor)) {
+      if (t == 0) bad = 1;
+      d = 1.0;
     }
-    __syncthreads();
-    for (int i = k + 1 + t; i < D; i += blockDim.x) L[i][k] /= L[k][k];
-    __syncthreads();
-    for (int e = t; e < (D - k - 1) * (D - k - 1); e += blockDim.x) {
-      const int i = k + 1 + e / (D - k - 1), j = k + 1 + e % (D - k - 1);
-      if (j <= i) L[i][j] -= L[i][k] * L[j][k];
+    if (t == 0) piv[k] = d;
+    if (lane > k) {
+      // 1 / d: the hardware estimate and two Newton steps (d > 0, normal).
+      double rd = __builtin_amdgcn_rcp(d);
+      rd = fma(rd, fma(-d, rd, 1.0), rd);
+      rd = fma(rd, fma(-d, rd, 1.0), rd);
+      const double tj = cur[lane & 3][lane >> 2] * rd;
+#pragma unroll
+      for (int r = 0; r < kRowsPerWave; ++r) a[r] = fma(-cur[wave][r], tj, a[r]);
     }
+    if (lane == k + 1)
+#pragma unroll
+      for (int r = 0; r < kRowsPerWave; ++r) col[(k + 1) & 1][wave][r] = a[r];
     __syncthreads();
   }
+  if (lane < D) {
+    const double lkk = sqrt(piv[lane]), rs = 1.0 / lkk;
+#pragma unroll
+    for (int r = 0; r < kRowsPerWave; ++r) {
+      const int i = wave + 4 * r;
+      a[r] = i == lane ? lkk : a[r] * rs;
+    }
+  }
+  // The factor to L (lower triangle and diagonal; G_s stays above), and its
+  // strictly lower part, zero elsewhere, to Lz for the inverse.
+#pragma unroll
+  for (int r = 0; r < kRowsPerWave; ++r) {
+    const int i = wave + 4 * r;
+    if (i < D && lane <= i) L[i][lane] = a[r];
+    Lz[i][lane] = (i < D && lane < i) ? a[r] : 0.0;
+  }
+  __syncthreads();
   // Triangular solves and the condition estimate run one wave per task, the
   // tasks concurrently: lane i owns row i (D <= 64), the wave's lockstep
   // orders the steps, and the values a step needs from another lane arrive
-  // by lane broadcast, so no workgroup barrier is involved.  The factor is
-  // read-only from here on.
-  const int lane = t & 63, wave = t >> 6;
+  // by lane broadcast or through LDS written by the same wave, so no
+  // workgroup barrier is involved.  The factor is read-only from here on.
   const bool own = lane < D;
   const double rinv = own ? 1.0 / L[lane][lane] : 0.0;
   __shared__ double s_lmax, s_lmin_inv;
   if (wave >= 2) {
     // K: waves 2 and 3 solve the right-hand sides c = wave - 2, wave, ...
+    double m[MPMI_MAX_DIM];
+    load_packed_factor(L, D, lane, m);
     for (int c = wave - 2; c < n; c += 2) {
-      const double z = wave_lower_solve(L, D, lane, rinv, own ? B[lane][c] : 0.0);
-      const double k = wave_upper_solve(L, D, lane, rinv, z);
+      const double k = packed_cholesky_solve(m, lane, rinv, own ? B[lane][c] : 0.0);
       if (own) K[(size_t)lane * n + c] = k / sc[lane];
     }
   } else if (wave == 1) {
-    // Largest eigenvalue of the scaled Gram matrix G_s by power iteration
-    // (G_s from its upper triangle and the diagonal of L L^T).  Lane i holds
-    // row i of G_s in registers; the loops run over the 64-row maximum with
-    // compile-time indices (rows and columns past D are zero).
+    // Largest eigenvalue of the scaled Gram matrix G_s (from its upper
+    // triangle and the diagonal of L L^T); lane i holds row i.
     double diag = 0.0;
     if (own)
       for (int k = 0; k <= lane; ++k) diag += L[lane][k] * L[lane][k];
@@ -262,50 +383,55 @@ solve_kernel(int n, int D, long long T, double ridge, const double* __restrict__
 #pragma unroll
     for (int j = 0; j < MPMI_MAX_DIM; ++j)
       grow[j] = (own && j < D) ? (lane == j ? diag : (lane < j ? L[lane][j] : L[j][lane])) : 0.0;
-    double v = own ? 1.0 + 0.01 * lane : 0.0;
-    double lmax = 0.0;
-    for (int it = 0; it < 60; ++it) {
-      double w = 0.0;
-#pragma unroll
-      for (int j = 0; j < MPMI_MAX_DIM; ++j) w = fma(grow[j], lane_bcast(v, j), w);
-      const double nn = sqrt(wave_sum(w * w));
-      lmax = wave_sum(w * v);
-      v = w / nn;
-    }
+    const double lmax = power_rayleigh(grow, own, lane, 1.0 + 0.01 * lane, vbuf[1]);
     if (lane == 0) s_lmax = lmax;
   } else {
-    // Smallest eigenvalue by inverse iteration through the Cholesky factor.
-    // Lane i holds m[k] = L_ik for k < i (its row) and L_ki for k > i (its
-    // column) in registers.  The forward solve uses lane i's residual only up
-    // to step i and the backward solve only down to step i, so each may
-    // subtract the other half's entries after that point: a solve step is a
-    // multiply, a broadcast and an FMA.
-    double m[MPMI_MAX_DIM];
+    // Smallest eigenvalue of G_s as 1 / the largest of G_s^-1 = L^-T L^-1.
+    // Lane c forms column c of L^-1 by forward substitution into row c of
+    // Lt = (L^-1)^T (row k: a dot product of the strictly lower row k of L
+    // with the entries found so far, over blocks of 16 up to k), then lane i
+    // row i of G_s^-1: (G_s^-1)_ij = sum_{k >= j} (L^-1)_ki (L^-1)_kj, the
+    // entries of L^-1 above the diagonal being zero.  Power iteration on
+    // G_s^-1 from the start vector is the inverse iteration on G_s through
+    // the factor.  Loops, not unrolled code, so the task stays in the
+    // instruction cache beside the other waves'.
+    srinv[lane] = rinv;
 #pragma unroll
-    for (int k = 0; k < MPMI_MAX_DIM; ++k)
-      m[k] = (own && k < D && k != lane) ? (k < lane ? L[lane][k] : L[k][lane]) : 0.0;
-    double v = own ? 1.0 - 0.01 * lane : 0.0;
-    double lmin_inv = 0.0;
-    for (int it = 0; it < 60; ++it) {
-      double r = v, z = 0.0;
+    for (int k = 0; k < MPMI_MAX_DIM; ++k) Lt[lane][k] = 0.0;
+    wave_lds_sync();
+    for (int k = 0; k < D; ++k) {
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+      for (int j0 = 0; j0 < k; j0 += 16) {
 #pragma unroll
-      for (int k = 0; k < MPMI_MAX_DIM; ++k) {  // L z = v
-        const double zk = lane_bcast(r * rinv, k);
-        z = lane == k ? zk : z;
-        r = fma(-m[k], zk, r);
+        for (int j = j0; j < j0 + 16; j += 4) {
+          s0 = fma(Lz[k][j], Lt[lane][j], s0);
+          s1 = fma(Lz[k][j + 1], Lt[lane][j + 1], s1);
+          s2 = fma(Lz[k][j + 2], Lt[lane][j + 2], s2);
+          s3 = fma(Lz[k][j + 3], Lt[lane][j + 3], s3);
+        }
       }
-      double y = 0.0;
-      r = z;
-#pragma unroll
-      for (int k = MPMI_MAX_DIM - 1; k >= 0; --k) {  // L^T y = z
-        const double yk = lane_bcast(r * rinv, k);
-        y = lane == k ? yk : y;
-        r = fma(-m[k], yk, r);
-      }
-      const double nn = sqrt(wave_sum(y * y));
-      lmin_inv = wave_sum(y * v);
-      v = y / nn;
+      Lt[lane][k] = ((k == lane ? 1.0 : 0.0) - ((s0 + s1) + (s2 + s3))) * srinv[k];
     }
+    wave_lds_sync();
+    // G_s^-1 row by row into Lz (no longer needed), then row `lane` back.
+    for (int j = 0; j < D; ++j) {
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+      for (int k0 = j & ~15; k0 < MPMI_MAX_DIM; k0 += 16) {
+#pragma unroll
+        for (int k = k0; k < k0 + 16; k += 4) {
+          s0 = fma(Lt[lane][k], Lt[j][k], s0);
+          s1 = fma(Lt[lane][k + 1], Lt[j][k + 1], s1);
+          s2 = fma(Lt[lane][k + 2], Lt[j][k + 2], s2);
+          s3 = fma(Lt[lane][k + 3], Lt[j][k + 3], s3);
+        }
+      }
+      Lz[j][lane] = (s0 + s1) + (s2 + s3);
+    }
+    wave_lds_sync();
+    double gi[MPMI_MAX_DIM];
+#pragma unroll
+    for (int j = 0; j < MPMI_MAX_DIM; ++j) gi[j] = (own && j < D) ? Lz[j][lane] : 0.0;
+    const double lmin_inv = power_rayleigh(gi, own, lane, 1.0 - 0.01 * lane, vbuf[0]);
     if (lane == 0) s_lmin_inv = lmin_inv;
   }
   __syncthreads();
@@ -333,7 +459,7 @@ hipError_t launch_fit(const mpmi_system& sys, int dim, const double* X, const do
   gram_kernel<<<nparts, kFitThreads, 0, st>>>(sys.basis, n, m, dim, X, U, Y, (long long)T, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  reduce_kernel<<<(E + kReduceElems - 1) / kReduceElems, 4 * kReduceElems, 0, st>>>(nparts, E, part, tot);
+  reduce_kernel<<<(E + kReduceElems - 1) / kReduceElems, kReduceElems * kReduceWays, 0, st>>>(nparts, E, part, tot);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   solve_kernel<<<1, kFitThreads, 0, st>>>(n, dim, (long long)T, ridge, tot, K_out, info);
