@@ -114,16 +114,29 @@ def test_rollout_batch_parity(ctx, bb, rc, system):
 
 
 # --------------------------------------------------------------- safe_mask --
-@pytest.mark.parametrize("system", ["bb", "rc"])
-def test_safe_mask_on_synthetic_trajectories(ctx, bb, rc, system):
-    rng = np.random.default_rng(77)
+@pytest.mark.parametrize("system,H", [("bb", 30), ("rc", 40), ("rc", 3), ("linear", 1), ("linear", 9)])
+def test_safe_mask_on_synthetic_trajectories(ctx, bb, rc, system, H):
+    """The kernel loads four steps ahead of its checks: horizons that end
+    inside such a group (1, 3, 9, 30) reread in-range steps and drop them.
+    The linear system (n = 3 of 8 component slots) rereads component n - 1
+    for the missing components."""
+    rng = np.random.default_rng(77 + H)
+    Nc = 3001
     if system == "bb":
         so, model, _ = bb
-        n, H, Nc = 4, 30, 3001
+        n = 4
         traj = rng.normal(0.0, [1.0, 1.0, 0.25, 1.0], size=(H, Nc, n))
+    elif system == "linear":
+        n = 3
+        so = o.System("linear", n, 1, box=[(0, float(W.f32(1.0)), 0.0), (2, float(W.f32(0.5)), float(W.f32(0.125)))],
+                      u_lo=[-1.0], u_hi=[1.0])
+        sys_g = mpmi.linear_system(n, 1, [(0, 1.0, 0.0), (2, 0.5, 0.125)], [-1.0], [1.0])
+        K = torch.zeros((n + 1, n), dtype=torch.float64, device="cuda")
+        model = mpmi.mpmi_model_pack(ctx, sys_g, K)
+        traj = rng.normal(0.0, [0.45, 5.0, 0.18], size=(H, Nc, n))
     else:
         so, model, _ = rc
-        n, H, Nc = 6, 40, 3001
+        n = 6
         tr = W.rc_track()
         phi = rng.uniform(0, 2 * np.pi, size=(H, Nc))
         rho = tr.centre_radius(phi) + rng.uniform(-3.3, 3.3, size=(H, Nc))
