@@ -410,6 +410,26 @@ def test_koopman_fit_parity(ctx, system):
         np.testing.assert_allclose(K, np.vstack([A.T, B.T]), rtol=0, atol=1e-10)
 
 
+def test_koopman_fit_deterministic_and_single_tile(ctx):
+    """Repeated fits are bit-identical (fixed-order partial sums, no atomics);
+    a fit from fewer rows than one Gram tile (T = 40 < 64) matches the
+    oracle."""
+    K_o, info, (X, U, Y) = W.rc_model()
+    sys_g = mpmi.race_car_system(W.track_dict(W.rc_track()))
+    Xd, Ud, Yd = dev(X, torch.float64), dev(U, torch.float64), dev(Y, torch.float64)
+    runs = [mpmi.koopman_fit(ctx, sys_g, Xd, Ud, Yd) for _ in range(3)]
+    for K, cond in runs[1:]:
+        assert torch.equal(K, runs[0][0]) and cond == runs[0][1]
+    A, B = synth.linear_plant(4, 1, seed=21)
+    X, U, Y = synth.linear_transitions(A, B, T=40, seed=22)
+    K_o, info = o.fit("linear", X, U, Y)
+    K, cond = mpmi.koopman_fit(ctx, mpmi.linear_system(4, 1, [], [-1.0], [1.0]), dev(X, torch.float64),
+                               dev(U, torch.float64), dev(Y, torch.float64))
+    log(f"[fit] T=40: cond oracle {info['cond']:.4g} gpu {cond:.4g}")
+    np.testing.assert_allclose(K.cpu().numpy(), K_o, rtol=0, atol=max(1e-12, 50 * info["cond"] ** 2 * 2.2e-16))
+    assert abs(cond - info["cond"]) <= 1e-3 * info["cond"]
+
+
 def test_koopman_fit_singular(ctx):
     rng = np.random.default_rng(0)
     X = rng.normal(size=(200, 3))
