@@ -367,7 +367,9 @@ def run_trajectory_store(st: dict, reps: int = 10):
         fv = torch.empty(N + 1, dtype=torch.int16, device="cuda")
         mpmi.mpmi_tick(ctx, model, desc, x, u, first_violation=fv)
         units = int(torch.clamp(fv.to(torch.int64), max=H).sum().item())
-        traj = torch.empty((H, n, N + 1), dtype=torch.float32, device="cuda")
+        ld = mpmi.traj_ld(N + 1)
+        base = torch.empty(H * n * ld, dtype=torch.float32, device="cuda")
+        traj = base.view(H, n, ld)[:, :, : N + 1]  # rows padded to 256-byte boundaries
         out = torch.empty(mpmi.SELECTION_BYTES, dtype=torch.uint8, device="cuda")
         times = {}
         for mode, tr in (("decision", None), ("trajectory", traj)):
@@ -382,13 +384,17 @@ def run_trajectory_store(st: dict, reps: int = 10):
             times[mode] = float(np.median([a.elapsed_time(b) for a, b in ev]))
         wbytes = units * n * 4
         rate = wbytes / (times["trajectory"] * 1e-3) / 1e9
-        # the layout's own write ceiling (the store pattern alone) and a
+        # the layout's own write ceiling (the store pattern alone, padded rows
+        # as used, and unpadded rows N + 1 floats apart for comparison) and a
         # contiguous stream, measured live on the same buffer
-        ceil = mpmi.mpmi_write_rates(ctx, traj.view(-1), N + 1, H * n)
-        res[name] = {"candidates": N + 1, "executed_units": units, "traj_bytes_allocated": traj.numel() * 4,
+        ceil = mpmi.mpmi_write_rates(ctx, base, N + 1, H * n, ld=ld)
+        ceil_unpadded = mpmi.mpmi_write_rates(ctx, base, N + 1, H * n, ld=N + 1)
+        res[name] = {"candidates": N + 1, "executed_units": units, "traj_row_floats": ld,
+                     "traj_bytes_allocated": base.numel() * 4,
                      "ms_decision": times["decision"], "ms_trajectory": times["trajectory"],
                      "bytes_written": wbytes, "write_GB_s": rate, "hbm_frac": rate / 8000.0,
                      "pattern_ceiling_GB_s": ceil["pattern_GB_s"], "stream_ceiling_GB_s": ceil["stream_GB_s"],
+                     "pattern_ceiling_unpadded_GB_s": ceil_unpadded["pattern_GB_s"],
                      "pattern_frac": rate / ceil["pattern_GB_s"]}
         if side == 1024:
             # The same tick through the separable calls: candidates, full
@@ -416,7 +422,7 @@ def run_trajectory_store(st: dict, reps: int = 10):
             res["separable_calls_1m"]["ms_fused_tick"] = times["decision"]
             res["separable_calls_1m"]["same_selection"] = bool(sel_s == sel_f)
             del cand
-        del traj
+        del traj, base
         torch.cuda.empty_cache()
     return res
 

@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define MPMI_ABI_VERSION 2
+#define MPMI_ABI_VERSION 3
 
 /* Size limits (checked on the host). */
 #define MPMI_MAX_STATE 8      /* n */
@@ -220,17 +220,26 @@ mpmi_status koopman_fit(mpmi_ctx ctx, const mpmi_system* sys /* host */,
 /* Predicts every candidate over the full horizon, without early exit
  * (Alg. 2 prediction loop; Fig. 1's cloud of trajectories): from x0 [n],
  * x_s = psi(x_{s-1}, u_c(seg(s)))^T K for s = 1..H.  cand [S][m][Nc];
- * traj [H][n][Nc] receives x_1..x_H (candidate fastest).  FP32 only.        */
+ * traj [H][n][traj_ld] receives x_1..x_H (candidate fastest; row stride
+ * traj_ld >= Nc floats, columns past Nc untouched).  FP32 only.
+ *
+ * Trajectory rows and write rate (this call, mpmi_tick, safe_mask): rows
+ * that start on 256-byte boundaries (traj 256-byte aligned, traj_ld a
+ * multiple of 64) are stored as whole memory lines.  With traj_ld = Nc =
+ * N + 1 consecutive rows start 4 bytes apart, every wave's store straddles
+ * lines, and the store runs at about half the rate (measured on MI355X).
+ * MPMI_EINVAL for traj_ld < Nc.                                              */
 mpmi_status rollout_batch(mpmi_ctx ctx, const void* model, int32_t precision,
                           const float* x0, const float* cand, int32_t Nc, int32_t S,
-                          int32_t H, float* traj, void* stream);
+                          int32_t H, float* traj, int64_t traj_ld, void* stream);
 
 /* Safety verdicts of stored trajectories (Sec. IV-B; Alg. 2 safety check):
- * first_violation[c] = first step s in 1..H whose state traj[s-1][.][c] is
- * unsafe, or H+1.  min_margin (optional, may be NULL) [Nc] = the least
- * margin over all constraints and over steps 1..min(first_violation, H).   */
-mpmi_status safe_mask(mpmi_ctx ctx, const void* model, const float* traj, int32_t Nc,
-                      int32_t H, int16_t* first_violation, float* min_margin,
+ * traj [H][n][traj_ld] (traj_ld >= Nc); first_violation[c] = first step s in
+ * 1..H whose state traj[s-1][.][c] is unsafe, or H+1.  min_margin
+ * (optional, may be NULL) [Nc] = the least margin over all constraints and
+ * over steps 1..min(first_violation, H).                                     */
+mpmi_status safe_mask(mpmi_ctx ctx, const void* model, const float* traj, int64_t traj_ld,
+                      int32_t Nc, int32_t H, int16_t* first_violation, float* min_margin,
                       void* stream);
 
 /* Minimal-intervention choice (Alg. 2 selection step; Sec. III-D; Sec. IV-D)
@@ -246,12 +255,13 @@ mpmi_status select_min_intervention(mpmi_ctx ctx, const void* model, const float
  * prediction with early exit at the first unsafe state, selection, in one
  * kernel launch.  x_t [n] and u_user [m] device FP32.  cand: EXPLICIT only,
  * [S][m][N].  Optional outputs (NULL to skip): first_violation [N+1];
- * traj [H][n][N+1] (states after a candidate's first violation are left
- * unwritten).  *out receives the selection.                                 */
+ * traj [H][n][traj_ld], traj_ld >= N+1 (states after a candidate's first
+ * violation are left unwritten; traj_ld is ignored when traj is NULL).
+ * *out receives the selection.                                               */
 mpmi_status mpmi_tick(mpmi_ctx ctx, const void* model, const mpmi_tick_desc* desc /* host */,
                       const float* x_t, const float* u_user, const float* cand,
                       mpmi_selection* out, int16_t* first_violation, float* traj,
-                      void* stream);
+                      int64_t traj_ld, void* stream);
 
 /* Tick autotuner: times `reps` ticks of *desc for every launch shape in the
  * library's search space (block 64..512, lanes_per_cand 1, 2, 4, 8; FP32 only)
@@ -278,15 +288,15 @@ mpmi_status mpmi_generate_candidates(mpmi_ctx ctx, const void* model,
 mpmi_status mpmi_fp32_fma_rate(mpmi_ctx ctx, double* tflops /* host */);
 
 /* Diagnostic: HBM write ceilings of the trajectory store (GB/s, host), on a
- * caller buffer buf of rows * Nc floats (device, 16-byte aligned; contents
- * overwritten): *pattern_gbs for the store pattern of traj[rows][Nc] alone
- * (lane c writes element c of every row, streaming stores, no compute),
- * *stream_gbs for contiguous 16-byte stores of the same size; best of three
- * timed launches each.  Synchronous (default stream); allocates nothing.
- * MPMI_EINVAL for NULL pointers, misalignment, Nc or rows < 1, or more than
- * 2^33 elements. */
-mpmi_status mpmi_write_rates(mpmi_ctx ctx, float* buf, int32_t Nc, int32_t rows, double* pattern_gbs /* host */,
-                             double* stream_gbs /* host */);
+ * caller buffer buf of rows * ld floats (device, 16-byte aligned; contents
+ * overwritten): *pattern_gbs for the store pattern of traj[rows][ld] alone
+ * (lane c < Nc writes element c of every row, streaming stores, no
+ * compute), *stream_gbs for contiguous 16-byte stores of rows * Nc floats;
+ * best of three timed launches each.  Synchronous (default stream);
+ * allocates nothing.  MPMI_EINVAL for NULL pointers, misalignment, Nc or
+ * rows < 1, ld < Nc, or more than 2^33 elements. */
+mpmi_status mpmi_write_rates(mpmi_ctx ctx, float* buf, int32_t Nc, int64_t ld, int32_t rows,
+                             double* pattern_gbs /* host */, double* stream_gbs /* host */);
 
 /* ---------------------------------------------------------------------------
  * Many concurrent control loops in one launch per tick.

@@ -210,7 +210,7 @@ mpmi_status koopman_fit(mpmi_ctx ctx, const mpmi_system* sys, const double* X, c
 }
 
 mpmi_status rollout_batch(mpmi_ctx ctx, const void* model, int32_t precision, const float* x0, const float* cand,
-                          int32_t Nc, int32_t S, int32_t H, float* traj, void* stream) {
+                          int32_t Nc, int32_t S, int32_t H, float* traj, int64_t traj_ld, void* stream) {
   if (!ctx) return MPMI_EINVAL;
   if (precision != MPMI_PREC_FP32)
     return fail(ctx, MPMI_EUNSUPPORTED, "rollout_batch stores FP32 trajectories; precision must be MPMI_PREC_FP32");
@@ -218,23 +218,25 @@ mpmi_status rollout_batch(mpmi_ctx ctx, const void* model, int32_t precision, co
   if (S < 1 || S > MPMI_MAX_SEGMENTS) return fail(ctx, MPMI_EINVAL, "S=%d out of 1..%d", S, MPMI_MAX_SEGMENTS);
   if (H < 1 || H > MPMI_MAX_HORIZON) return fail(ctx, MPMI_EINVAL, "H=%d out of 1..%d", H, MPMI_MAX_HORIZON);
   if (!x0 || !cand || !traj) return fail(ctx, MPMI_EINVAL, "x0, cand and traj must be non-NULL");
+  if (traj_ld < Nc) return fail(ctx, MPMI_EINVAL, "traj_ld=%lld below Nc=%d", (long long)traj_ld, Nc);
   mpmi_system sys;
   mpmi_status s = model_system(ctx, model, &sys, (hipStream_t)stream);
   if (s != MPMI_OK) return s;
-  return check_hip(ctx, mpmi::launch_rollout(sys.basis, model, Nc, S, H, x0, cand, traj, (hipStream_t)stream),
+  return check_hip(ctx, mpmi::launch_rollout(sys.basis, model, Nc, S, H, x0, cand, traj, traj_ld, (hipStream_t)stream),
                    "rollout_batch launch");
 }
 
-mpmi_status safe_mask(mpmi_ctx ctx, const void* model, const float* traj, int32_t Nc, int32_t H,
+mpmi_status safe_mask(mpmi_ctx ctx, const void* model, const float* traj, int64_t traj_ld, int32_t Nc, int32_t H,
                       int16_t* first_violation, float* min_margin, void* stream) {
   if (!ctx) return MPMI_EINVAL;
   if (Nc < 1 || Nc > MPMI_MAX_CAND) return fail(ctx, MPMI_EINVAL, "Nc=%d out of 1..%d", Nc, MPMI_MAX_CAND);
   if (H < 1 || H > MPMI_MAX_HORIZON) return fail(ctx, MPMI_EINVAL, "H=%d out of 1..%d", H, MPMI_MAX_HORIZON);
   if (!traj || !first_violation) return fail(ctx, MPMI_EINVAL, "traj and first_violation must be non-NULL");
+  if (traj_ld < Nc) return fail(ctx, MPMI_EINVAL, "traj_ld=%lld below Nc=%d", (long long)traj_ld, Nc);
   mpmi_system sys;
   mpmi_status s = model_system(ctx, model, &sys, (hipStream_t)stream);
   if (s != MPMI_OK) return s;
-  return check_hip(ctx, mpmi::launch_mask(sys.basis, model, Nc, H, traj, first_violation, min_margin,
+  return check_hip(ctx, mpmi::launch_mask(sys.basis, model, Nc, H, traj, traj_ld, first_violation, min_margin,
                                           (hipStream_t)stream),
                    "safe_mask launch");
 }
@@ -300,7 +302,7 @@ static mpmi_status validate_desc(mpmi_ctx ctx, const mpmi_system& sys, const mpm
 
 mpmi_status mpmi_tick(mpmi_ctx ctx, const void* model, const mpmi_tick_desc* desc, const float* x_t,
                       const float* u_user, const float* cand, mpmi_selection* out, int16_t* first_violation,
-                      float* traj, void* stream) {
+                      float* traj, int64_t traj_ld, void* stream) {
   if (!ctx) return MPMI_EINVAL;
   mpmi_system sys;
   mpmi_status s = model_system(ctx, model, &sys, (hipStream_t)stream);
@@ -310,6 +312,8 @@ mpmi_status mpmi_tick(mpmi_ctx ctx, const void* model, const mpmi_tick_desc* des
   if (!x_t || !u_user || !out) return fail(ctx, MPMI_EINVAL, "x_t, u_user and out must be non-NULL");
   if (desc->gen == MPMI_GEN_EXPLICIT && desc->n_cand > 0 && !cand)
     return fail(ctx, MPMI_EINVAL, "EXPLICIT candidates need cand");
+  if (traj && traj_ld < (int64_t)desc->n_cand + 1)
+    return fail(ctx, MPMI_EINVAL, "traj_ld=%lld below N+1=%d", (long long)traj_ld, desc->n_cand + 1);
   void* slot = (char*)ctx->slots + (size_t)desc->loop * mpmi::slot_bytes();
   if (desc->lanes_per_cand > 1) {
     if (traj) return fail(ctx, MPMI_EUNSUPPORTED, "several lanes per candidate: no trajectory store");
@@ -333,7 +337,7 @@ mpmi_status mpmi_tick(mpmi_ctx ctx, const void* model, const mpmi_tick_desc* des
                      "mpmi_tick (BF16X3) launch");
   }
   return check_hip(ctx, mpmi::launch_tick(sys, model, *desc, x_t, u_user, cand, slot, out, first_violation,
-                                          traj, (hipStream_t)stream),
+                                          traj, traj ? traj_ld : 0, (hipStream_t)stream),
                    "mpmi_tick launch");
 }
 
@@ -360,10 +364,11 @@ mpmi_status mpmi_tick_autotune(mpmi_ctx ctx, const void* model, mpmi_tick_desc* 
       if (lanes > 1 && block > 256) continue;
       d.block = block;
       d.lanes_per_cand = lanes;
-      for (int w = 0; w < 2 && s == MPMI_OK; ++w) s = mpmi_tick(ctx, model, &d, x_t, u_user, cand, out, nullptr, nullptr, stream);
+      for (int w = 0; w < 2 && s == MPMI_OK; ++w)
+        s = mpmi_tick(ctx, model, &d, x_t, u_user, cand, out, nullptr, nullptr, 0, stream);
       if (s == MPMI_OK && hipEventRecord(e0, st) != hipSuccess) s = MPMI_EDEVICE;
       for (int r = 0; r < reps && s == MPMI_OK; ++r)
-        s = mpmi_tick(ctx, model, &d, x_t, u_user, cand, out, nullptr, nullptr, stream);
+        s = mpmi_tick(ctx, model, &d, x_t, u_user, cand, out, nullptr, nullptr, 0, stream);
       float ms = 0.0f;
       if (s == MPMI_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
                            hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
@@ -393,14 +398,15 @@ mpmi_status mpmi_fp32_fma_rate(mpmi_ctx ctx, double* tflops) {
   return check_hip(ctx, mpmi::measure_fma_rate((float*)ctx->fit_work, tflops), "mpmi_fp32_fma_rate");
 }
 
-mpmi_status mpmi_write_rates(mpmi_ctx ctx, float* buf, int32_t Nc, int32_t rows, double* pattern_gbs,
+mpmi_status mpmi_write_rates(mpmi_ctx ctx, float* buf, int32_t Nc, int64_t ld, int32_t rows, double* pattern_gbs,
                              double* stream_gbs) {
   if (!ctx) return MPMI_EINVAL;
   if (!buf || !pattern_gbs || !stream_gbs) return fail(ctx, MPMI_EINVAL, "buf, pattern_gbs and stream_gbs must be non-NULL");
   if (!aligned(buf, 16)) return fail(ctx, MPMI_EINVAL, "buf must be 16-byte aligned");
-  if (Nc < 1 || rows < 1 || (long long)Nc * rows > (1ll << 33))
-    return fail(ctx, MPMI_EINVAL, "Nc=%d rows=%d out of range", Nc, rows);
-  return check_hip(ctx, mpmi::measure_write_rates(buf, Nc, rows, pattern_gbs, stream_gbs), "mpmi_write_rates");
+  if (Nc < 1 || rows < 1 || ld < Nc || (long long)ld * rows > (1ll << 33))
+    return fail(ctx, MPMI_EINVAL, "Nc=%d ld=%lld rows=%d out of range", Nc, (long long)ld, rows);
+  return check_hip(ctx, mpmi::measure_write_rates(buf, Nc, (long long)ld, rows, pattern_gbs, stream_gbs),
+                   "mpmi_write_rates");
 }
 
 mpmi_status mpmi_generate_candidates(mpmi_ctx ctx, const void* model, const mpmi_tick_desc* desc,
@@ -690,11 +696,11 @@ mpmi_status mpmi_proposal_tick(mpmi_ctx ctx, const void* model, const uint16_t* 
       e = mpmi::launch_tick_split(sys, pd.lanes_per_cand, model, pd, x_t, u_user, cand_work, slot, out, nullptr,
                                   st);
     else
-      e = mpmi::launch_tick(sys, model, pd, x_t, u_user, cand_work, slot, out, nullptr, nullptr, st);
+      e = mpmi::launch_tick(sys, model, pd, x_t, u_user, cand_work, slot, out, nullptr, nullptr, 0, st);
   }
   void* slot2 = (char*)ctx->slots + (size_t)fallback->loop * mpmi::slot_bytes();
   if (e == hipSuccess)
-    e = mpmi::launch_tick(sys, model, *fallback, x_t, u_user, nullptr, slot2, out, nullptr, nullptr, st, out);
+    e = mpmi::launch_tick(sys, model, *fallback, x_t, u_user, nullptr, slot2, out, nullptr, nullptr, 0, st, out);
   return check_hip(ctx, e, "mpmi_proposal_tick launch");
 }
 

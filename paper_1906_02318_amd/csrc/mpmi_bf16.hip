@@ -288,7 +288,7 @@ recheck_race_car_kernel(const ModelDev* __restrict__ md, GenParams gp, int H, co
     const int e = e0 + threadIdx.x;
     const int c = e < count ? rl->idx[e] : gp.n_cand + 1;  // past the end: an invalid lane
     const CandResult r = evaluate_candidate<MPMI_BASIS_RACE_CAR, false, DEG>(md, sK, gp, H, x_t, u_user, cand, c,
-                                                                      fv_out, nullptr);
+                                                                      fv_out, nullptr, 0);
     ks = r.ks < ks ? r.ks : ks;
     kf = r.kf < kf ? r.kf : kf;
     n_safe_local += r.safe_counted ? 1u : 0u;

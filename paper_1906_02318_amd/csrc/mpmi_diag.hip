@@ -56,15 +56,17 @@ hipError_t measure_fma_rate(float* sink, double* tflops) {
 }
 
 // HBM write ceilings for the trajectory store: the store pattern of
-// traj[H][n][Nc] alone (lane c writes element c of each of the H * n rows,
-// no compute), and a contiguous stream of 16-byte stores of the same size.
-__global__ void __launch_bounds__(256) traj_pattern_kernel(float* __restrict__ traj, int Nc, int rows) {
+// traj[H][n][ld] alone (rows ld floats apart; lane c < Nc writes element c
+// of each of the H * n rows, no compute), and a contiguous stream of
+// 16-byte stores of the same number of bytes.
+__global__ void __launch_bounds__(256) traj_pattern_kernel(float* __restrict__ traj, int Nc, long long ld,
+                                                           int rows) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= Nc) return;
   float v = (float)c;
   for (int r = 0; r < rows; ++r) {
     v = fmaf(v, 1.0001f, 1.0f);
-    __builtin_nontemporal_store(v, &traj[(size_t)r * (size_t)Nc + c]);
+    __builtin_nontemporal_store(v, &traj[(size_t)r * (size_t)ld + c]);
   }
 }
 
@@ -74,7 +76,7 @@ __global__ void __launch_bounds__(256) write_stream_kernel(float4* __restrict__ 
     out[i] = make_float4(1.0f, 2.0f, 3.0f, (float)i);
 }
 
-hipError_t measure_write_rates(void* buf, int Nc, int rows, double* pattern_gbs, double* stream_gbs) {
+hipError_t measure_write_rates(void* buf, int Nc, long long ld, int rows, double* pattern_gbs, double* stream_gbs) {
   const size_t bytes = (size_t)rows * (size_t)Nc * sizeof(float);
   const size_t n4 = bytes / 16;
   const int block = 256;
@@ -86,10 +88,10 @@ hipError_t measure_write_rates(void* buf, int Nc, int rows, double* pattern_gbs,
   float best_p = 1e30f, best_s = 1e30f;
   for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
     for (int kind = 0; kind < 2 && e == hipSuccess; ++kind) {
-      if (kind == 0) traj_pattern_kernel<<<grid_p, block, 0, 0>>>((float*)buf, Nc, rows);  // warm
+      if (kind == 0) traj_pattern_kernel<<<grid_p, block, 0, 0>>>((float*)buf, Nc, ld, rows);  // warm
       else write_stream_kernel<<<grid_s, block, 0, 0>>>((float4*)buf, n4);
       if ((e = hipEventRecord(e0, 0)) != hipSuccess) break;
-      if (kind == 0) traj_pattern_kernel<<<grid_p, block, 0, 0>>>((float*)buf, Nc, rows);
+      if (kind == 0) traj_pattern_kernel<<<grid_p, block, 0, 0>>>((float*)buf, Nc, ld, rows);
       else write_stream_kernel<<<grid_s, block, 0, 0>>>((float4*)buf, n4);
       if ((e = hipGetLastError()) != hipSuccess) break;
       if ((e = hipEventRecord(e1, 0)) != hipSuccess) break;

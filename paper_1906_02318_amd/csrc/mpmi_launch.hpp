@@ -38,11 +38,12 @@ inline int track_degree(const mpmi_system& s) {
 
 hipError_t launch_tick(const mpmi_system& sys, const void* model, const mpmi_tick_desc& d, const float* x_t,
                        const float* u_user, const float* cand, void* slot, mpmi_selection* out,
-                       int16_t* fv, float* traj, hipStream_t st, const mpmi_selection* gate = nullptr);
+                       int16_t* fv, float* traj, long long traj_ld, hipStream_t st,
+                       const mpmi_selection* gate = nullptr);
 hipError_t launch_rollout(int basis, const void* model, int Nc, int S, int H, const float* x0,
-                          const float* cand, float* traj, hipStream_t st);
-hipError_t launch_mask(int basis, const void* model, int Nc, int H, const float* traj, int16_t* fv,
-                       float* mm, hipStream_t st);
+                          const float* cand, float* traj, long long traj_ld, hipStream_t st);
+hipError_t launch_mask(int basis, const void* model, int Nc, int H, const float* traj, long long traj_ld,
+                       int16_t* fv, float* mm, hipStream_t st);
 hipError_t launch_select(const void* model, int Nc, int S, int H, const float* cand, const int16_t* fv,
                          const float* u_user, int loop, void* slot, mpmi_selection* out, hipStream_t st);
 hipError_t launch_gen(const void* model, const mpmi_tick_desc& d, const float* u_user, const float* cand,
@@ -92,7 +93,7 @@ hipError_t launch_gemm_test(const uint16_t* A, const uint16_t* B, int M, int N, 
 hipError_t measure_fma_rate(float* sink, double* tflops);
 // Write ceilings on buf (rows * Nc floats, overwritten): the trajectory
 // store's pattern and a contiguous stream, GB/s.
-hipError_t measure_write_rates(void* buf, int Nc, int rows, double* pattern_gbs, double* stream_gbs);
+hipError_t measure_write_rates(void* buf, int Nc, long long ld, int rows, double* pattern_gbs, double* stream_gbs);
 
 // Many-loop tick (mpmi_multi.hip).
 struct WorkItem;

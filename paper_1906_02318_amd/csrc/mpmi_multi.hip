@@ -64,13 +64,13 @@ multi_kernel(const mpmi_loop_desc* __restrict__ loops, const ModelDev* __restric
   CandResult r;
   if (basis == MPMI_BASIS_RACE_CAR)
     r = evaluate_candidate<MPMI_BASIS_RACE_CAR, NOISE>(md, sK, gp, H, L->x_t, L->u_user, L->cand, c,
-                                                       L->first_violation, nullptr);
+                                                       L->first_violation, nullptr, 0);
   else if (basis == MPMI_BASIS_BALANCE_BOT)
     r = evaluate_candidate<MPMI_BASIS_BALANCE_BOT, NOISE>(md, sK, gp, H, L->x_t, L->u_user, L->cand, c,
-                                                          L->first_violation, nullptr);
+                                                          L->first_violation, nullptr, 0);
   else
     r = evaluate_candidate<MPMI_BASIS_LINEAR, NOISE>(md, sK, gp, H, L->x_t, L->u_user, L->cand, c,
-                                                     L->first_violation, nullptr);
+                                                     L->first_violation, nullptr, 0);
   Slot* slot = &slots[w.loop];
   if (reduce_and_publish(r.ks, r.kf, r.safe_counted, slot, (unsigned int)n_tiles[w.loop], w.tile) &&
       threadIdx.x == 0) {

@@ -28,7 +28,7 @@ __global__ void __launch_bounds__(1024)
 tick_fp32_kernel(const ModelDev* __restrict__ md, GenParams gp, int H, const float* __restrict__ x_t,
                  const float* __restrict__ u_user, const float* __restrict__ cand,
                  Slot* __restrict__ slot, mpmi_selection* __restrict__ out,
-                 int16_t* __restrict__ fv_out, float* __restrict__ traj,
+                 int16_t* __restrict__ fv_out, float* __restrict__ traj, long long traj_ld,
                  const mpmi_selection* __restrict__ gate) {
   constexpr int MS = Dims<BASIS>::M;
   // Gated form (fallback after a proposal tick): nothing to do if the gate
@@ -37,7 +37,8 @@ tick_fp32_kernel(const ModelDev* __restrict__ md, GenParams gp, int H, const flo
   __shared__ float4 sK[kLdsKFloat4];
   stage_K<BASIS>(md, sK);
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  const CandResult r = evaluate_candidate<BASIS, NOISE, DEG>(md, sK, gp, H, x_t, u_user, cand, c, fv_out, traj);
+  const CandResult r =
+      evaluate_candidate<BASIS, NOISE, DEG>(md, sK, gp, H, x_t, u_user, cand, c, fv_out, traj, (size_t)traj_ld);
   if (reduce_and_publish(r.ks, r.kf, r.safe_counted, slot, gridDim.x, blockIdx.x) && threadIdx.x == 0)
     finalize<MS>(md, gp, cand, u_user, H, slot, out);
 }
@@ -48,7 +49,7 @@ tick_fp32_kernel(const ModelDev* __restrict__ md, GenParams gp, int H, const flo
 template <int BASIS>
 __global__ void __launch_bounds__(1024)
 rollout_fp32_kernel(const ModelDev* __restrict__ md, int Nc, int S, int H, const float* __restrict__ x0,
-                    const float* __restrict__ cand, float* __restrict__ traj) {
+                    const float* __restrict__ cand, float* __restrict__ traj, long long traj_ld) {
   constexpr int NS = Dims<BASIS>::N, MS = Dims<BASIS>::M;
   __shared__ float4 sK[kLdsKFloat4];
   stage_K<BASIS>(md, sK);
@@ -72,7 +73,7 @@ rollout_fp32_kernel(const ModelDev* __restrict__ md, int Nc, int S, int H, const
     settle_state<NS>(x);
 #pragma unroll
     for (int j = 0; j < NS; ++j)
-      if (j < n) __builtin_nontemporal_store(x[j], &traj[((size_t)(s - 1) * n + j) * (size_t)Nc + c]);
+      if (j < n) __builtin_nontemporal_store(x[j], &traj[((size_t)(s - 1) * n + j) * (size_t)traj_ld + c]);
   }
 }
 
@@ -87,7 +88,7 @@ constexpr int kMaskChunk = 4;
 
 template <int NS>
 __global__ void __launch_bounds__(1024)
-mask_kernel(const ModelDev* __restrict__ md, int Nc, int H, const float* __restrict__ traj,
+mask_kernel(const ModelDev* __restrict__ md, int Nc, int H, const float* __restrict__ traj, long long traj_ld,
             int16_t* __restrict__ fv_out, float* __restrict__ mm_out) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= Nc) return;
@@ -105,7 +106,7 @@ mask_kernel(const ModelDev* __restrict__ md, int Nc, int H, const float* __restr
 #pragma unroll
       for (int j = 0; j < NS; ++j) {
         const int jj = j < n ? j : n - 1;
-        const float v = traj[((size_t)(s - 1) * n + jj) * (size_t)Nc + c];
+        const float v = traj[((size_t)(s - 1) * n + jj) * (size_t)traj_ld + c];
         x[k][j] = j < n ? v : 0.0f;
       }
     }
@@ -339,16 +340,19 @@ hipError_t launch_pack(const mpmi_system& sys, int dim, int state_feat0, const d
 template <int BASIS, int DEG>
 static void tick_dispatch(bool noisy, unsigned grid, int block, hipStream_t st, const ModelDev* md,
                           const GenParams& gp, int H, const float* x_t, const float* u_user, const float* cand,
-                          Slot* sl, mpmi_selection* out, int16_t* fv, float* traj, const mpmi_selection* gate) {
+                          Slot* sl, mpmi_selection* out, int16_t* fv, float* traj, long long ld,
+                          const mpmi_selection* gate) {
   if (noisy)
-    tick_fp32_kernel<BASIS, true, DEG><<<grid, block, 0, st>>>(md, gp, H, x_t, u_user, cand, sl, out, fv, traj, gate);
+    tick_fp32_kernel<BASIS, true, DEG>
+        <<<grid, block, 0, st>>>(md, gp, H, x_t, u_user, cand, sl, out, fv, traj, ld, gate);
   else
-    tick_fp32_kernel<BASIS, false, DEG><<<grid, block, 0, st>>>(md, gp, H, x_t, u_user, cand, sl, out, fv, traj, gate);
+    tick_fp32_kernel<BASIS, false, DEG>
+        <<<grid, block, 0, st>>>(md, gp, H, x_t, u_user, cand, sl, out, fv, traj, ld, gate);
 }
 
 hipError_t launch_tick(const mpmi_system& sys, const void* model, const mpmi_tick_desc& d, const float* x_t,
                        const float* u_user, const float* cand, void* slot, mpmi_selection* out,
-                       int16_t* fv, float* traj, hipStream_t st, const mpmi_selection* gate) {
+                       int16_t* fv, float* traj, long long traj_ld, hipStream_t st, const mpmi_selection* gate) {
   const GenParams gp = make_gen(d);
   const int block = d.block > 0 ? d.block : 256;
   const unsigned grid = blocks_for((long long)d.n_cand + 1, block);
@@ -358,57 +362,57 @@ hipError_t launch_tick(const mpmi_system& sys, const void* model, const mpmi_tic
   switch (sys.basis) {
     case MPMI_BASIS_LINEAR:
       tick_dispatch<MPMI_BASIS_LINEAR, kMaxHarm>(noisy, grid, block, st, md, gp, d.horizon, x_t, u_user, cand, sl,
-                                                 out, fv, traj, gate);
+                                                 out, fv, traj, traj_ld, gate);
       break;
     case MPMI_BASIS_BALANCE_BOT:
       tick_dispatch<MPMI_BASIS_BALANCE_BOT, kMaxHarm>(noisy, grid, block, st, md, gp, d.horizon, x_t, u_user, cand,
-                                                      sl, out, fv, traj, gate);
+                                                      sl, out, fv, traj, traj_ld, gate);
       break;
     default:
       if (track_degree(sys) <= kSmallTrackDeg)
         tick_dispatch<MPMI_BASIS_RACE_CAR, kSmallTrackDeg>(noisy, grid, block, st, md, gp, d.horizon, x_t, u_user,
-                                                           cand, sl, out, fv, traj, gate);
+                                                           cand, sl, out, fv, traj, traj_ld, gate);
       else
         tick_dispatch<MPMI_BASIS_RACE_CAR, kMaxHarm>(noisy, grid, block, st, md, gp, d.horizon, x_t, u_user, cand,
-                                                     sl, out, fv, traj, gate);
+                                                     sl, out, fv, traj, traj_ld, gate);
       break;
   }
   return hipGetLastError();
 }
 
 hipError_t launch_rollout(int basis, const void* model, int Nc, int S, int H, const float* x0,
-                          const float* cand, float* traj, hipStream_t st) {
+                          const float* cand, float* traj, long long traj_ld, hipStream_t st) {
   const int block = 256;
   const unsigned grid = blocks_for(Nc, block);
   const ModelDev* md = (const ModelDev*)model;
   switch (basis) {
     case MPMI_BASIS_LINEAR:
-      rollout_fp32_kernel<MPMI_BASIS_LINEAR><<<grid, block, 0, st>>>(md, Nc, S, H, x0, cand, traj);
+      rollout_fp32_kernel<MPMI_BASIS_LINEAR><<<grid, block, 0, st>>>(md, Nc, S, H, x0, cand, traj, traj_ld);
       break;
     case MPMI_BASIS_BALANCE_BOT:
-      rollout_fp32_kernel<MPMI_BASIS_BALANCE_BOT><<<grid, block, 0, st>>>(md, Nc, S, H, x0, cand, traj);
+      rollout_fp32_kernel<MPMI_BASIS_BALANCE_BOT><<<grid, block, 0, st>>>(md, Nc, S, H, x0, cand, traj, traj_ld);
       break;
     default:
-      rollout_fp32_kernel<MPMI_BASIS_RACE_CAR><<<grid, block, 0, st>>>(md, Nc, S, H, x0, cand, traj);
+      rollout_fp32_kernel<MPMI_BASIS_RACE_CAR><<<grid, block, 0, st>>>(md, Nc, S, H, x0, cand, traj, traj_ld);
       break;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_mask(int basis, const void* model, int Nc, int H, const float* traj, int16_t* fv,
-                       float* mm, hipStream_t st) {
+hipError_t launch_mask(int basis, const void* model, int Nc, int H, const float* traj, long long traj_ld,
+                       int16_t* fv, float* mm, hipStream_t st) {
   const int block = 256;
   const unsigned grid = blocks_for(Nc, block);
   const ModelDev* md = (const ModelDev*)model;
   switch (basis) {
     case MPMI_BASIS_LINEAR:
-      mask_kernel<MPMI_MAX_STATE><<<grid, block, 0, st>>>(md, Nc, H, traj, fv, mm);
+      mask_kernel<MPMI_MAX_STATE><<<grid, block, 0, st>>>(md, Nc, H, traj, traj_ld, fv, mm);
       break;
     case MPMI_BASIS_BALANCE_BOT:
-      mask_kernel<4><<<grid, block, 0, st>>>(md, Nc, H, traj, fv, mm);
+      mask_kernel<4><<<grid, block, 0, st>>>(md, Nc, H, traj, traj_ld, fv, mm);
       break;
     default:
-      mask_kernel<6><<<grid, block, 0, st>>>(md, Nc, H, traj, fv, mm);
+      mask_kernel<6><<<grid, block, 0, st>>>(md, Nc, H, traj, traj_ld, fv, mm);
       break;
   }
   return hipGetLastError();

@@ -168,7 +168,7 @@ struct CandResult {
 
 // Prediction of candidate c with early exit at the first unsafe state
 // (Alg. 2 inner loop), then its selection keys.  Lanes with c >= Nc return
-// empty keys.  fv_out / traj are optional.  NOISE compiles the process-noise
+// empty keys.  fv_out / traj are optional; traj rows are traj_ld floats apart.  NOISE compiles the process-noise
 // draw in (models with a positive sigma); noise-free instances carry none of
 // its registers (a noisy instance still skips the draw for a noise-free model).
 // DEG is the track polynomial's degree (>= the model's highest harmonic).
@@ -178,7 +178,8 @@ __device__ __forceinline__ CandResult evaluate_candidate(const ModelDev* __restr
                                                          const float* __restrict__ x_t,
                                                          const float* __restrict__ u_user,
                                                          const float* __restrict__ cand, int c,
-                                                         int16_t* __restrict__ fv_out, float* __restrict__ traj) {
+                                                         int16_t* __restrict__ fv_out, float* __restrict__ traj,
+                                                         size_t traj_ld) {
   constexpr int NS = Dims<BASIS>::N, MS = Dims<BASIS>::M;
   const int Nc = gp.n_cand + 1;
   const bool valid = c < Nc;
@@ -213,7 +214,7 @@ __device__ __forceinline__ CandResult evaluate_candidate(const ModelDev* __restr
         // Streaming stores: the cloud is written once, for a later reader.
 #pragma unroll
         for (int j = 0; j < NS; ++j)
-          if (j < n) __builtin_nontemporal_store(x[j], &traj[((size_t)(s - 1) * n + j) * (size_t)Nc + c]);
+          if (j < n) __builtin_nontemporal_store(x[j], &traj[((size_t)(s - 1) * n + j) * traj_ld + c]);
       }
       if (!(min_margin<NS, DEG>(md, x) > 0.0f)) {
         fv = s;

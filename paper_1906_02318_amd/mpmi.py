@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmpmi.so")
 
 # Constants mirrored from include/mpmi.h
-ABI_VERSION = 2
+ABI_VERSION = 3
 MAX_STATE, MAX_INPUT, MAX_DIM, MAX_BOX = 8, 4, 64, 4
 MAX_HORIZON, MAX_SEGMENTS, MAX_CAND, MAX_LOOPS = 255, 8, 33554431, 4096
 OK, NO_SAFE, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED, ESINGULAR = 0, 1, -1, -2, -3, -4, -5
@@ -100,13 +100,13 @@ def library() -> ctypes.CDLL:
         "mpmi_model_bytes": (ctypes.c_size_t, []),
         "mpmi_model_pack": (i32, [vp, ctypes.POINTER(System), vp, vp, vp]),
         "koopman_fit": (i32, [vp, ctypes.POINTER(System), vp, vp, vp, i64, f64, vp, ctypes.POINTER(f64), vp]),
-        "rollout_batch": (i32, [vp, vp, i32, vp, vp, i32, i32, i32, vp, vp]),
-        "safe_mask": (i32, [vp, vp, vp, i32, i32, vp, vp, vp]),
+        "rollout_batch": (i32, [vp, vp, i32, vp, vp, i32, i32, i32, vp, i64, vp]),
+        "safe_mask": (i32, [vp, vp, vp, i64, i32, i32, vp, vp, vp]),
         "select_min_intervention": (i32, [vp, vp, vp, i32, i32, vp, i32, vp, i32, vp, vp]),
-        "mpmi_tick": (i32, [vp, vp, ctypes.POINTER(TickDesc), vp, vp, vp, vp, vp, vp, vp]),
+        "mpmi_tick": (i32, [vp, vp, ctypes.POINTER(TickDesc), vp, vp, vp, vp, vp, vp, i64, vp]),
         "mpmi_generate_candidates": (i32, [vp, vp, ctypes.POINTER(TickDesc), vp, vp, vp, vp]),
         "mpmi_fp32_fma_rate": (i32, [vp, ctypes.POINTER(f64)]),
-        "mpmi_write_rates": (i32, [vp, vp, i32, i32, ctypes.POINTER(f64), ctypes.POINTER(f64)]),
+        "mpmi_write_rates": (i32, [vp, vp, i32, i64, i32, ctypes.POINTER(f64), ctypes.POINTER(f64)]),
         "mpmi_multi_create": (i32, [vp, ctypes.POINTER(LoopDesc), i32, ctypes.POINTER(MultiConfig), ctypes.POINTER(vp)]),
         "mpmi_multi_destroy": (None, [vp]),
         "mpmi_multi_set_config": (i32, [vp, vp, ctypes.POINTER(MultiConfig)]),
@@ -206,6 +206,42 @@ def _need(t, name, dtype, numel=None, device=None):
     return t
 
 
+# Trajectory buffers: rows of traj[H][n][.] start on 256-byte boundaries when
+# the row stride is a multiple of 64 floats; with a stride of N + 1 floats
+# every row starts 4 bytes off the last and the store runs at about half the
+# rate.  The calls take the stride from the tensor, so a (H, n, Nc) view of a
+# padded buffer is passed as is.
+TRAJ_ROW_FLOATS = 64
+
+
+def traj_ld(Nc: int) -> int:
+    """Row stride (floats) of a padded trajectory buffer for Nc candidates."""
+    return -(-Nc // TRAJ_ROW_FLOATS) * TRAJ_ROW_FLOATS
+
+
+def new_traj(ctx: "Context", H: int, n: int, Nc: int):
+    """A (H, n, Nc) float32 view of a (H, n, traj_ld(Nc)) device buffer."""
+    return torch.empty((H, n, traj_ld(Nc)), dtype=torch.float32, device=ctx.device)[:, :, :Nc]
+
+
+def _traj_stride(t, name, H, n, Nc, device):
+    """Row stride of a trajectory tensor of shape (H, n, Nc): unit column
+    stride, rows ld >= Nc floats apart, steps n * ld apart."""
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.dtype != torch.float32:
+        raise TypeError(f"{name} must be torch.float32, got {t.dtype}")
+    if not t.is_cuda or (device is not None and t.device != device):
+        raise ValueError(f"{name} must be a device tensor on {device}")
+    if tuple(t.shape) != (H, n, Nc):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, needs {(H, n, Nc)}")
+    ld = t.stride(1) if n > 1 else (t.stride(0) if H > 1 else Nc)
+    if (Nc > 1 and t.stride(2) != 1) or ld < Nc or (H > 1 and t.stride(0) != n * ld):
+        raise ValueError(f"{name} needs unit column stride and rows ld >= Nc floats apart, steps n * ld apart; "
+                         f"got strides {t.stride()}")
+    return ld
+
+
 def _stream(stream):
     if stream is None:
         stream = torch.cuda.current_stream()
@@ -295,25 +331,27 @@ def koopman_fit(ctx: Context, system: System, X, U, Y, ridge: float = 0.0, strea
 
 
 def rollout_batch(ctx: Context, model: Model, x0, cand, H: int, traj=None, precision=PREC_FP32, stream=None):
-    """cand (S, m, Nc) float32 -> traj (H, n, Nc) float32 (full horizon)."""
+    """cand (S, m, Nc) float32 -> traj (H, n, Nc) float32 (full horizon); by
+    default a view of a buffer with padded rows (new_traj)."""
     S, m, Nc = cand.shape
     _need(x0, "x0", torch.float32, model.n, device=ctx.device)
     _need(cand, "cand", torch.float32, device=ctx.device)
     if traj is None:
-        traj = torch.empty((H, model.n, Nc), dtype=torch.float32, device=ctx.device)
-    _need(traj, "traj", torch.float32, H * model.n * Nc, device=ctx.device)
+        traj = new_traj(ctx, H, model.n, Nc)
+    ld = _traj_stride(traj, "traj", H, model.n, Nc, ctx.device)
     ctx.check(ctx.lib.rollout_batch(ctx.handle, ctypes.c_void_p(model.ptr), precision, _ptr(x0), _ptr(cand),
-                                    Nc, S, H, _ptr(traj), _stream(stream)))
+                                    Nc, S, H, _ptr(traj), ld, _stream(stream)))
     return traj
 
 
 def safe_mask(ctx: Context, model: Model, traj, with_margin: bool = True, stream=None):
-    """traj (H, n, Nc) -> (first_violation int16 (Nc,), min_margin float32 (Nc,) or None)."""
+    """traj (H, n, Nc), rows possibly padded -> (first_violation int16 (Nc,),
+    min_margin float32 (Nc,) or None)."""
     H, n, Nc = traj.shape
-    _need(traj, "traj", torch.float32, device=ctx.device)
+    ld = _traj_stride(traj, "traj", H, n, Nc, ctx.device)
     fv = torch.empty(Nc, dtype=torch.int16, device=ctx.device)
     mm = torch.empty(Nc, dtype=torch.float32, device=ctx.device) if with_margin else None
-    ctx.check(ctx.lib.safe_mask(ctx.handle, ctypes.c_void_p(model.ptr), _ptr(traj), Nc, H, _ptr(fv), _ptr(mm),
+    ctx.check(ctx.lib.safe_mask(ctx.handle, ctypes.c_void_p(model.ptr), _ptr(traj), ld, Nc, H, _ptr(fv), _ptr(mm),
                                 _stream(stream)))
     return fv, mm
 
@@ -355,13 +393,12 @@ def mpmi_tick(ctx: Context, model: Model, desc: TickDesc, x_t, u_user, cand=None
         _need(cand, "cand", torch.float32, desc.n_seg * model.m * desc.n_cand, device=ctx.device)
     if first_violation is not None:
         _need(first_violation, "first_violation", torch.int16, Nc, device=ctx.device)
-    if traj is not None:
-        _need(traj, "traj", torch.float32, desc.horizon * model.n * Nc, device=ctx.device)
+    ld = 0 if traj is None else _traj_stride(traj, "traj", desc.horizon, model.n, Nc, ctx.device)
     if out is None:
         out = torch.empty(SELECTION_BYTES, dtype=torch.uint8, device=ctx.device)
     _need(out, "out", torch.uint8, SELECTION_BYTES, device=ctx.device)
     ctx.check(ctx.lib.mpmi_tick(ctx.handle, ctypes.c_void_p(model.ptr), ctypes.byref(desc), _ptr(x_t),
-                                _ptr(u_user), _ptr(cand), _ptr(out), _ptr(first_violation), _ptr(traj),
+                                _ptr(u_user), _ptr(cand), _ptr(out), _ptr(first_violation), _ptr(traj), ld,
                                 _stream(stream)))
     return out
 
@@ -388,12 +425,14 @@ def mpmi_generate_candidates(ctx: Context, model: Model, desc: TickDesc, u_user,
     return out
 
 
-def mpmi_write_rates(ctx: Context, buf, Nc: int, rows: int) -> dict:
-    """Write ceilings (GB/s) of the trajectory store's pattern and of a
-    contiguous stream, on buf (rows * Nc float32, overwritten; synchronous)."""
-    _need(buf, "buf", torch.float32, rows * Nc, device=ctx.device)
+def mpmi_write_rates(ctx: Context, buf, Nc: int, rows: int, ld: int = None) -> dict:
+    """Write ceilings (GB/s) of the trajectory store's pattern (rows ld >= Nc
+    floats apart; default Nc) and of a contiguous stream, on buf (rows * ld
+    float32, overwritten; synchronous)."""
+    ld = Nc if ld is None else ld
+    _need(buf, "buf", torch.float32, rows * ld, device=ctx.device)
     p, q = ctypes.c_double(0.0), ctypes.c_double(0.0)
-    ctx.check(ctx.lib.mpmi_write_rates(ctx.handle, _ptr(buf), Nc, rows, ctypes.byref(p), ctypes.byref(q)))
+    ctx.check(ctx.lib.mpmi_write_rates(ctx.handle, _ptr(buf), Nc, ld, rows, ctypes.byref(p), ctypes.byref(q)))
     return dict(pattern_GB_s=p.value, stream_GB_s=q.value)
 
 

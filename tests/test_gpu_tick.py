@@ -4,6 +4,7 @@ Every test drives the HIP path through the C ABI (Python binding) and checks
 the result against the oracle on the same seeded inputs, with the rules of
 tests/parity.py.
 """
+import ctypes
 import sys
 
 import numpy as np
@@ -724,17 +725,55 @@ def test_tick_lanes_per_candidate_identical_and_autotuned(ctx, bb, rc, case):
 
 
 def test_write_rate_diagnostic(ctx):
-    """The trajectory store's write ceilings: both rates finite, below the
-    part's 8 TB/s, and the scattered-row pattern no faster than the
-    contiguous stream (within timing noise)."""
+    """The trajectory store's write ceilings: rates finite and below the
+    part's 8 TB/s, for rows Nc floats apart and for rows padded to 256-byte
+    boundaries; misaligned buffers and strides below Nc are rejected."""
     Nc, rows = 262145, 60
-    buf = torch.empty(rows * Nc, dtype=torch.float32, device="cuda")
+    ld = mpmi.traj_ld(Nc)
+    buf = torch.empty(rows * ld, dtype=torch.float32, device="cuda")
     r = mpmi.mpmi_write_rates(ctx, buf, Nc, rows)
-    log(f"[diag] write ceilings: {r}")
-    assert 100.0 < r["pattern_GB_s"] < 8000.0 and 100.0 < r["stream_GB_s"] < 8000.0
-    assert r["pattern_GB_s"] <= 1.1 * r["stream_GB_s"]
+    rp = mpmi.mpmi_write_rates(ctx, buf, Nc, rows, ld=ld)
+    log(f"[diag] write ceilings: rows {Nc} floats apart {r}; rows {ld} floats apart {rp}")
+    for q in (r, rp):
+        assert 100.0 < q["pattern_GB_s"] < 8000.0 and 100.0 < q["stream_GB_s"] < 8000.0
     with pytest.raises(mpmi.MpmiError):
         mpmi.mpmi_write_rates(ctx, buf[1:], Nc - 1, rows)  # misaligned
+    with pytest.raises(mpmi.MpmiError):
+        mpmi.mpmi_write_rates(ctx, buf, Nc, rows, ld=Nc - 1)
+
+
+def test_trajectory_row_stride(ctx, rc):
+    """rollout_batch, safe_mask and the fused tick's store give the same
+    states, verdicts and margins with rows N + 1 floats apart and with rows
+    padded to 256-byte boundaries (columns past N + 1 untouched); a stride
+    below N + 1 is rejected at the boundary."""
+    so, model, _ = rc
+    N, H, n = 5000, 25, 6
+    desc = mpmi.tick_desc(N, H, gen=mpmi.GEN_UNIFORM, seed=9, tick=2)
+    x, u = dev(synth.race_car_states(1, W.rc_track(), seed=91)[0], torch.float32), dev([0.05, 0.4], torch.float32)
+    cand = mpmi.mpmi_generate_candidates(ctx, model, desc, u)
+    plain = torch.full((H, n, N + 1), float("nan"), device="cuda")
+    mpmi.rollout_batch(ctx, model, x, cand, H, traj=plain)
+    ld = mpmi.traj_ld(N + 1)
+    assert ld % 64 == 0 and ld > N + 1
+    base = torch.full((H, n, ld), -7.0, device="cuda")
+    padded = base[:, :, : N + 1]
+    mpmi.rollout_batch(ctx, model, x, cand, H, traj=padded)
+    assert torch.equal(plain, padded)
+    assert bool((base[:, :, N + 1:] == -7.0).all())
+    fa, ma = mpmi.safe_mask(ctx, model, plain)
+    fb, mb = mpmi.safe_mask(ctx, model, padded)
+    assert torch.equal(fa, fb) and torch.equal(ma, mb)
+    tb = torch.full((H, n, ld), float("nan"), device="cuda")
+    fv = torch.empty(N + 1, dtype=torch.int16, device="cuda")
+    mpmi.mpmi_tick(ctx, model, desc, x, u, first_violation=fv, traj=tb[:, :, : N + 1])
+    assert torch.equal(fv, fa)
+    steps = torch.arange(1, H + 1, device="cuda")[:, None, None]
+    written = steps <= torch.clamp(fv.to(torch.int64), max=H)[None, None, :]
+    assert torch.equal(torch.where(written, tb[:, :, : N + 1], 0.0), torch.where(written, plain, 0.0))
+    st = ctx.lib.rollout_batch(ctx.handle, ctypes.c_void_p(model.ptr), mpmi.PREC_FP32, x.data_ptr(),
+                               cand.data_ptr(), N + 1, 1, H, base.data_ptr(), N, None)
+    assert st == mpmi.EINVAL
 
 
 def test_fp32_fma_rate_diagnostic(ctx):
