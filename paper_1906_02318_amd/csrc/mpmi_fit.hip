@@ -3,7 +3,8 @@
 //   1. gram:   every workgroup lifts tiles of 64 rows into LDS (psi computed on
 //              the fly, never materialised in HBM) and accumulates its share
 //              of Z^T Z restricted to the first D rows, Z = [Psi | Y], in
-//              4 x 6 register blocks;
+//              4 x 6 register blocks, one wave lifting the next tile while
+//              three accumulate the current one;
 //   2. reduce: partial sums added in a fixed order (deterministic);
 //   3. solve:  one workgroup: RMS column scaling, ridge, Cholesky of the
 //              scaled Gram matrix in LDS, then, one wave per task, the two
@@ -69,54 +70,65 @@ __device__ __forceinline__ void lift_row(int basis, int n, int m, const double* 
   z[f++] = a * sd;
 }
 
-// Register blocks of the accumulation: thread t owns rows a0 .. a0 + 3 by
-// columns b0 .. b0 + 5 of Z^T Z, so a tile row costs it 10 LDS reads for 24
-// FMAs.  Each entry still sums the rows in their order.
+// Register blocks of the accumulation: thread t of waves 1..3 owns rows
+// a0 .. a0 + 3 by columns b0 .. b0 + 5 of Z^T Z, so a tile row costs it 10
+// LDS reads for 24 FMAs; the 16 x 12 blocks fill those three waves exactly.
+// Wave 0 lifts the next tile into the other LDS buffer meanwhile, so a tile
+// costs the longer of the lift and the accumulation, not their sum.  Each
+// entry still sums the rows in their order.
 constexpr int kGa = 4, kGb = 6;
 constexpr int kGaBlocks = MPMI_MAX_DIM / kGa;            // 16
 constexpr int kGbBlocks = (kFitCols + kGb - 1) / kGb;    // 12
 constexpr int kZCols = kGbBlocks * kGb;                  // 72: every block's columns lie in the row
 constexpr int kZStride = kZCols + 2;                     // 16-byte aligned rows
-static_assert(kGaBlocks * kGbBlocks <= kFitThreads, "one register block per thread");
+static_assert(kGaBlocks * kGbBlocks == kFitThreads - 64, "one register block per thread of waves 1..3");
 static_assert(MPMI_MAX_DIM % kGa == 0, "feature blocks");
+static_assert(kFitRows == 64, "wave 0 lifts one row per lane");
 
 __global__ void __launch_bounds__(kFitThreads)
 gram_kernel(int basis, int n, int m, int D, const double* __restrict__ X, const double* __restrict__ U,
             const double* __restrict__ Y, long long T, double* __restrict__ part) {
-  __shared__ __attribute__((aligned(16))) double Z[kFitRows][kZStride];
+  __shared__ __attribute__((aligned(16))) double Z[2][kFitRows][kZStride];
   const int C = D + n;
   const int E = D * C;
-  const int ab = (int)threadIdx.x / kGbBlocks, bb = (int)threadIdx.x % kGbBlocks;
+  const bool lifter = threadIdx.x < 64;
+  const int blk = (int)threadIdx.x - 64;
+  const int ab = blk / kGbBlocks, bb = blk % kGbBlocks;
   const int a0 = ab * kGa, b0 = bb * kGb;
-  const bool active = ab < kGaBlocks && a0 < D && b0 < C;
+  const bool active = !lifter && a0 < D && b0 < C;
   double acc[kGa][kGb];
 #pragma unroll
   for (int i = 0; i < kGa; ++i)
 #pragma unroll
     for (int j = 0; j < kGb; ++j) acc[i][j] = 0.0;
   const long long ntiles = (T + kFitRows - 1) / kFitRows;
-  for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    const long long r0 = tile * kFitRows;
-    if (threadIdx.x < kFitRows) {
-      const long long r = r0 + threadIdx.x;
-      double* z = Z[threadIdx.x];
-      if (r < T) {
-        lift_row(basis, n, m, X + r * n, U + r * m, z);
-        for (int k = 0; k < n; ++k) z[D + k] = Y[r * n + k];
-      } else {
-        for (int k = 0; k < C; ++k) z[k] = 0.0;
-      }
-      for (int k = C; k < kZCols; ++k) z[k] = 0.0;
+  // This workgroup's tiles: blockIdx.x + k * gridDim.x, k = 0 .. count - 1.
+  const long long count = blockIdx.x < ntiles ? (ntiles - 1 - blockIdx.x) / gridDim.x + 1 : 0;
+  auto lift_tile = [&](long long k, int buf) {
+    const long long r = (blockIdx.x + k * gridDim.x) * kFitRows + threadIdx.x;
+    double* z = Z[buf][threadIdx.x];
+    if (r < T) {
+      lift_row(basis, n, m, X + r * n, U + r * m, z);
+      for (int q = 0; q < n; ++q) z[D + q] = Y[r * n + q];
+    } else {
+      for (int q = 0; q < C; ++q) z[q] = 0.0;
     }
-    __syncthreads();
-    if (active) {
+    for (int q = C; q < kZCols; ++q) z[q] = 0.0;
+  };
+  if (lifter && count > 0) lift_tile(0, 0);
+  __syncthreads();
+  for (long long k = 0; k < count; ++k) {
+    if (lifter) {
+      if (k + 1 < count) lift_tile(k + 1, (int)((k + 1) & 1));
+    } else if (active) {
+      const int buf = (int)(k & 1);
 #pragma unroll 4
       for (int rr = 0; rr < kFitRows; ++rr) {
         double av[kGa], bv[kGb];
 #pragma unroll
-        for (int i = 0; i < kGa; ++i) av[i] = Z[rr][a0 + i];
+        for (int i = 0; i < kGa; ++i) av[i] = Z[buf][rr][a0 + i];
 #pragma unroll
-        for (int j = 0; j < kGb; ++j) bv[j] = Z[rr][b0 + j];
+        for (int j = 0; j < kGb; ++j) bv[j] = Z[buf][rr][b0 + j];
 #pragma unroll
         for (int i = 0; i < kGa; ++i)
 #pragma unroll
