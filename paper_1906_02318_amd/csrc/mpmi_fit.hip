@@ -9,8 +9,9 @@
 //   3. solve:  one workgroup: RMS column scaling, ridge, Cholesky of the
 //              scaled Gram matrix in LDS, then, one wave per task, the two
 //              triangular solves per right-hand side and unscaling, power
-//              iteration on the Gram matrix and on its inverse (formed from
-//              the factor's inverse) for the condition number.
+//              iteration on the Gram matrix and, after all four waves form
+//              its inverse from the factor's inverse, on that, for the
+//              condition number.
 #include <hip/hip_runtime.h>
 
 #include "mpmi_launch.hpp"
@@ -373,7 +374,8 @@ solve_kernel(int n, int D, long long T, double ridge, const double* __restrict__
   // tasks concurrently: lane i owns row i (D <= 64), the wave's lockstep
   // orders the steps, and the values a step needs from another lane arrive
   // by lane broadcast or through LDS written by the same wave, so no
-  // workgroup barrier is involved.  The factor is read-only from here on.
+  // workgroup barrier is involved until the inverse is complete.  The factor
+  // is read-only from here on.
   const bool own = lane < D;
   const double rinv = own ? 1.0 / L[lane][lane] : 0.0;
   __shared__ double s_lmax, s_lmin_inv;
@@ -398,15 +400,13 @@ solve_kernel(int n, int D, long long T, double ridge, const double* __restrict__
     const double lmax = power_rayleigh(grow, own, lane, 1.0 + 0.01 * lane, vbuf[1]);
     if (lane == 0) s_lmax = lmax;
   } else {
-    // Smallest eigenvalue of G_s as 1 / the largest of G_s^-1 = L^-T L^-1.
-    // Lane c forms column c of L^-1 by forward substitution into row c of
-    // Lt = (L^-1)^T (row k: a dot product of the strictly lower row k of L
-    // with the entries found so far, over blocks of 16 up to k), then lane i
-    // row i of G_s^-1: (G_s^-1)_ij = sum_{k >= j} (L^-1)_ki (L^-1)_kj, the
-    // entries of L^-1 above the diagonal being zero.  Power iteration on
-    // G_s^-1 from the start vector is the inverse iteration on G_s through
-    // the factor.  Loops, not unrolled code, so the task stays in the
-    // instruction cache beside the other waves'.
+    // Smallest eigenvalue of G_s as 1 / the largest of G_s^-1 = L^-T L^-1
+    // (power iteration on G_s^-1 from the start vector is the inverse
+    // iteration on G_s through the factor).  Here lane c forms column c of
+    // L^-1 by forward substitution into row c of Lt = (L^-1)^T: row k is a
+    // dot product of the strictly lower row k of L with the entries found
+    // so far, over blocks of 16 up to k.  Loops, not unrolled code, so the
+    // task stays in the instruction cache beside the other waves'.
     srinv[lane] = rinv;
 #pragma unroll
     for (int k = 0; k < MPMI_MAX_DIM; ++k) Lt[lane][k] = 0.0;
@@ -424,22 +424,26 @@ solve_kernel(int n, int D, long long T, double ridge, const double* __restrict__
       }
       Lt[lane][k] = ((k == lane ? 1.0 : 0.0) - ((s0 + s1) + (s2 + s3))) * srinv[k];
     }
-    wave_lds_sync();
-    // G_s^-1 row by row into Lz (no longer needed), then row `lane` back.
-    for (int j = 0; j < D; ++j) {
-      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-      for (int k0 = j & ~15; k0 < MPMI_MAX_DIM; k0 += 16) {
+  }
+  __syncthreads();
+  // G_s^-1 into Lz (no longer needed), its rows spread over the four waves:
+  // (G_s^-1)_ji = sum_{k >= j} (L^-1)_ki (L^-1)_kj, lane i of row j, the
+  // entries of L^-1 above the diagonal being zero.
+  for (int j = wave; j < D; j += 4) {
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    for (int k0 = j & ~15; k0 < MPMI_MAX_DIM; k0 += 16) {
 #pragma unroll
-        for (int k = k0; k < k0 + 16; k += 4) {
-          s0 = fma(Lt[lane][k], Lt[j][k], s0);
-          s1 = fma(Lt[lane][k + 1], Lt[j][k + 1], s1);
-          s2 = fma(Lt[lane][k + 2], Lt[j][k + 2], s2);
-          s3 = fma(Lt[lane][k + 3], Lt[j][k + 3], s3);
-        }
+      for (int k = k0; k < k0 + 16; k += 4) {
+        s0 = fma(Lt[lane][k], Lt[j][k], s0);
+        s1 = fma(Lt[lane][k + 1], Lt[j][k + 1], s1);
+        s2 = fma(Lt[lane][k + 2], Lt[j][k + 2], s2);
+        s3 = fma(Lt[lane][k + 3], Lt[j][k + 3], s3);
       }
-      Lz[j][lane] = (s0 + s1) + (s2 + s3);
     }
-    wave_lds_sync();
+    Lz[j][lane] = (s0 + s1) + (s2 + s3);
+  }
+  __syncthreads();
+  if (wave == 0) {
     double gi[MPMI_MAX_DIM];
 #pragma unroll
     for (int j = 0; j < MPMI_MAX_DIM; ++j) gi[j] = (own && j < D) ? Lz[j][lane] : 0.0;
