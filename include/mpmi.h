@@ -226,8 +226,9 @@ mpmi_status koopman_fit(mpmi_ctx ctx, const mpmi_system* sys /* host */,
  * Trajectory rows and write rate (this call, mpmi_tick, safe_mask): rows
  * that start on 256-byte boundaries (traj 256-byte aligned, traj_ld a
  * multiple of 64) are stored as whole memory lines.  With traj_ld = Nc =
- * N + 1 consecutive rows start 4 bytes apart, every wave's store straddles
- * lines, and the store runs at about half the rate (measured on MI355X).
+ * N + 1 each row starts 4 bytes further past a 256-byte boundary than the
+ * last, every wave's store straddles lines, and the store runs at about half
+ * the rate (measured on MI355X).
  * MPMI_EINVAL for traj_ld < Nc.                                              */
 mpmi_status rollout_batch(mpmi_ctx ctx, const void* model, int32_t precision,
                           const float* x0, const float* cand, int32_t Nc, int32_t S,

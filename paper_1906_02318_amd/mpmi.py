@@ -208,8 +208,8 @@ def _need(t, name, dtype, numel=None, device=None):
 
 # Trajectory buffers: rows of traj[H][n][.] start on 256-byte boundaries when
 # the row stride is a multiple of 64 floats; with a stride of N + 1 floats
-# every row starts 4 bytes off the last and the store runs at about half the
-# rate.  The calls take the stride from the tensor, so a (H, n, Nc) view of a
+# each row starts 4 bytes further past such a boundary than the last, and
+# the store runs at about half the rate.  The calls take the stride from the tensor, so a (H, n, Nc) view of a
 # padded buffer is passed as is.
 TRAJ_ROW_FLOATS = 64
 
