@@ -742,15 +742,24 @@ def test_write_rate_diagnostic(ctx):
         mpmi.mpmi_write_rates(ctx, buf, Nc, rows, ld=Nc - 1)
 
 
-def test_trajectory_row_stride(ctx, rc):
+@pytest.mark.parametrize("system", ["rc", "bb"])
+def test_trajectory_row_stride(ctx, bb, rc, system):
     """rollout_batch, safe_mask and the fused tick's store give the same
     states, verdicts and margins with rows N + 1 floats apart and with rows
     padded to 256-byte boundaries (columns past N + 1 untouched); a stride
-    below N + 1 is rejected at the boundary."""
-    so, model, _ = rc
-    N, H, n = 5000, 25, 6
-    desc = mpmi.tick_desc(N, H, gen=mpmi.GEN_UNIFORM, seed=9, tick=2)
-    x, u = dev(synth.race_car_states(1, W.rc_track(), seed=91)[0], torch.float32), dev([0.05, 0.4], torch.float32)
+    below N + 1 is rejected at the boundary.  Cart-pole with five input
+    segments, race car with one."""
+    if system == "rc":
+        so, model, _ = rc
+        N, H, n, S = 5000, 25, 6, 1
+        x = dev(synth.race_car_states(1, W.rc_track(), seed=91)[0], torch.float32)
+        u = dev([0.05, 0.4], torch.float32)
+    else:
+        so, model, _ = bb
+        N, H, n, S = 3001, 50, 4, 5
+        x = dev(synth.balance_bot_states(1, seed=92)[0], torch.float32)
+        u = dev([0.7], torch.float32)
+    desc = mpmi.tick_desc(N, H, gen=mpmi.GEN_UNIFORM, seed=9, tick=2, n_seg=S)
     cand = mpmi.mpmi_generate_candidates(ctx, model, desc, u)
     plain = torch.full((H, n, N + 1), float("nan"), device="cuda")
     mpmi.rollout_batch(ctx, model, x, cand, H, traj=plain)
@@ -759,20 +768,22 @@ def test_trajectory_row_stride(ctx, rc):
     base = torch.full((H, n, ld), -7.0, device="cuda")
     padded = base[:, :, : N + 1]
     mpmi.rollout_batch(ctx, model, x, cand, H, traj=padded)
-    assert torch.equal(plain, padded)
+    same = dict(rtol=0, atol=0, equal_nan=True)  # exact, a diverged state's NaN included
+    torch.testing.assert_close(padded, plain, **same)
     assert bool((base[:, :, N + 1:] == -7.0).all())
     fa, ma = mpmi.safe_mask(ctx, model, plain)
     fb, mb = mpmi.safe_mask(ctx, model, padded)
-    assert torch.equal(fa, fb) and torch.equal(ma, mb)
+    assert torch.equal(fa, fb)
+    torch.testing.assert_close(mb, ma, **same)
     tb = torch.full((H, n, ld), float("nan"), device="cuda")
     fv = torch.empty(N + 1, dtype=torch.int16, device="cuda")
     mpmi.mpmi_tick(ctx, model, desc, x, u, first_violation=fv, traj=tb[:, :, : N + 1])
     assert torch.equal(fv, fa)
     steps = torch.arange(1, H + 1, device="cuda")[:, None, None]
     written = steps <= torch.clamp(fv.to(torch.int64), max=H)[None, None, :]
-    assert torch.equal(torch.where(written, tb[:, :, : N + 1], 0.0), torch.where(written, plain, 0.0))
+    torch.testing.assert_close(torch.where(written, tb[:, :, : N + 1], 0.0), torch.where(written, plain, 0.0), **same)
     st = ctx.lib.rollout_batch(ctx.handle, ctypes.c_void_p(model.ptr), mpmi.PREC_FP32, x.data_ptr(),
-                               cand.data_ptr(), N + 1, 1, H, base.data_ptr(), N, None)
+                               cand.data_ptr(), N + 1, S, H, base.data_ptr(), N, None)
     assert st == mpmi.EINVAL
 
 
