@@ -742,14 +742,23 @@ def test_write_rate_diagnostic(ctx):
         mpmi.mpmi_write_rates(ctx, buf, Nc, rows, ld=Nc - 1)
 
 
-@pytest.mark.parametrize("system", ["rc", "bb"])
+@pytest.mark.parametrize("system", ["rc", "bb", "linear"])
 def test_trajectory_row_stride(ctx, bb, rc, system):
     """rollout_batch, safe_mask and the fused tick's store give the same
     states, verdicts and margins with rows N + 1 floats apart and with rows
     padded to 256-byte boundaries (columns past N + 1 untouched); a stride
     below N + 1 is rejected at the boundary.  Cart-pole with five input
-    segments, race car with one."""
-    if system == "rc":
+    segments, race car with one, and a linear system with three of eight
+    state slots."""
+    if system == "linear":
+        N, H, n, S = 4100, 30, 3, 2
+        sys_g = mpmi.linear_system(n, 1, [(0, 1.0, 0.0), (2, 0.5, 0.125)], [-1.0], [1.0])
+        A = np.array([[0.97, 0.05, 0.0], [-0.05, 0.97, 0.02], [0.0, -0.02, 0.99]])
+        B = np.array([[0.0, 0.04, 0.02]])
+        model = mpmi.mpmi_model_pack(ctx, sys_g, dev(np.vstack([A.T, B]), torch.float64))
+        x = dev([0.3, -0.2, 0.1], torch.float32)
+        u = dev([0.25], torch.float32)
+    elif system == "rc":
         so, model, _ = rc
         N, H, n, S = 5000, 25, 6, 1
         x = dev(synth.race_car_states(1, W.rc_track(), seed=91)[0], torch.float32)
