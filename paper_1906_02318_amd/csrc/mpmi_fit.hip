@@ -7,7 +7,7 @@
 //              three accumulate the current one;
 //   2. reduce: partial sums added in a fixed order (deterministic);
 //   3. solve:  one workgroup: RMS column scaling, ridge, Cholesky of the
-//              scaled Gram matrix in LDS, then, one wave per task, the two
+//              scaled Gram matrix in registers, then, one wave per task, the two
 //              triangular solves per right-hand side and unscaling, power
 //              iteration on the Gram matrix and, after all four waves form
 //              its inverse from the factor's inverse, on that, for the
@@ -315,44 +315,70 @@ solve_kernel(int n, int D, long long T, double ridge, const double* __restrict__
     const int i = e / n, j = e % n;
     B[i][j] = tot[(size_t)i * C + D + j] / sc[i];
   }
-  // Cholesky, right-looking, on the register copy; one barrier per column.
-  // Column k (entries not yet scaled) is published in LDS by its owners, the
-  // threads of lane k, as col[k & 1][w][r] = entry (w + 4r, k).  Step k: with
-  // d the pivot, every thread of lane j > k subtracts c_i c_j / d from its
-  // entries (i, j) (entries above the diagonal become garbage and are never
-  // read); the threads of lane k + 1 then publish column k + 1, complete at
-  // that point.  Reads and writes of the published columns alternate between
-  // the two buffers.  The pivots are kept, and each column is scaled into
-  // the factor (L_ik = c_i / sqrt(d_k), L_kk = sqrt(d_k)) after the loop, off
-  // the steps' serial chain.
-  __shared__ __attribute__((aligned(16))) double col[2][4][kRowsPerWave];
-  if (lane == 0)
+  // Cholesky, right-looking, on the register copy; one barrier per two
+  // columns.  With c_k column k before its own step (entries not yet
+  // scaled) and d_k its pivot, step k subtracts c_ik c_jk / d_k from every
+  // entry (i, j) with j > k (entries above the diagonal become garbage and
+  // are never read).  Columns k and k + 1 as they stand before step k are
+  // published in LDS by their owners, the threads of lanes k and k + 1, as
+  // col[.][0 or 1][w][r] = entry (w + 4r, column).  Each thread then applies
+  // steps k and k + 1 itself, forming the step-k update of column k + 1 that
+  // it needs exactly as lane k + 1 forms it (so the factor is the
+  // one-column-per-step factor, bit for bit); the threads of lanes k + 2 and
+  // k + 3 publish the next pair.  The pair buffers alternate.  The pivots
+  // are kept, and each column is scaled into the factor (L_ik = c_i /
+  // sqrt(d_k), L_kk = sqrt(d_k)) after the loop, off the steps' chain.
+  __shared__ __attribute__((aligned(16))) double col[2][2][4][kRowsPerWave];
+  if (lane < 2)
 #pragma unroll
-    for (int r = 0; r < kRowsPerWave; ++r) col[0][wave][r] = a[r];
+    for (int r = 0; r < kRowsPerWave; ++r) col[0][lane][wave][r] = a[r];
   __syncthreads();
   const double pivot_floor = 1e-14 * (double)T;
-  for (int k = 0; k < D; ++k) {
-    const double(*cur)[kRowsPerWave] = col[k & 1];
-    double d = cur[k & 3][k >> 2];
+  // A pivot below the floor marks the fit singular and is replaced by 1.
+  auto pivot = [&](double d) {
     if (!(d > pivot_floor)) {
       if (t == 0) bad = 1;
       d = 1.0;
     }
-    if (t == 0) piv[k] = d;
-    if (lane > k) {
-      // 1 / d: the hardware estimate and two Newton steps (d > 0, normal).
-      double rd = __builtin_amdgcn_rcp(d);
-      rd = fma(rd, fma(-d, rd, 1.0), rd);
-      rd = fma(rd, fma(-d, rd, 1.0), rd);
-      const double tj = cur[lane & 3][lane >> 2] * rd;
-#pragma unroll
-      for (int r = 0; r < kRowsPerWave; ++r) a[r] = fma(-cur[wave][r], tj, a[r]);
+    return d;
+  };
+  // 1 / d: the hardware estimate and two Newton steps (d > 0, normal).
+  auto recip = [](double d) {
+    double rd = __builtin_amdgcn_rcp(d);
+    rd = fma(rd, fma(-d, rd, 1.0), rd);
+    return fma(rd, fma(-d, rd, 1.0), rd);
+  };
+  int k = 0;
+  for (; k + 1 < D; k += 2) {
+    const double(*c0)[kRowsPerWave] = col[(k >> 1) & 1][0];
+    const double(*c1)[kRowsPerWave] = col[(k >> 1) & 1][1];
+    const int k1 = k + 1;
+    const double d0 = pivot(c0[k & 3][k >> 2]);
+    const double r0 = recip(d0);
+    const double t01 = c0[k1 & 3][k1 >> 2] * r0;  // step k's multiplier of column k + 1
+    const double d1 = pivot(fma(-c0[k1 & 3][k1 >> 2], t01, c1[k1 & 3][k1 >> 2]));
+    if (t == 0) {
+      piv[k] = d0;
+      piv[k1] = d1;
     }
-    if (lane == k + 1)
+    if (lane > k) {
+      const double tj0 = c0[lane & 3][lane >> 2] * r0;
 #pragma unroll
-      for (int r = 0; r < kRowsPerWave; ++r) col[(k + 1) & 1][wave][r] = a[r];
+      for (int r = 0; r < kRowsPerWave; ++r) a[r] = fma(-c0[wave][r], tj0, a[r]);
+    }
+    if (lane > k1) {
+      const double r1 = recip(d1);
+      const double tj1 = fma(-c0[lane & 3][lane >> 2], t01, c1[lane & 3][lane >> 2]) * r1;
+#pragma unroll
+      for (int r = 0; r < kRowsPerWave; ++r) a[r] = fma(-fma(-c0[wave][r], t01, c1[wave][r]), tj1, a[r]);
+    }
+    if (lane == k + 2 || lane == k + 3)
+#pragma unroll
+      for (int r = 0; r < kRowsPerWave; ++r) col[((k >> 1) + 1) & 1][lane - k - 2][wave][r] = a[r];
     __syncthreads();
   }
+  if (k < D && t == 0) piv[k] = pivot(col[(k >> 1) & 1][0][k & 3][k >> 2]);  // odd D: the last column
+  __syncthreads();
   if (lane < D) {
     const double lkk = sqrt(piv[lane]), rs = 1.0 / lkk;
 #pragma unroll
