@@ -389,13 +389,16 @@ def run_trajectory_store(st: dict, reps: int = 10):
         # contiguous stream, measured live on the same buffer
         ceil = mpmi.mpmi_write_rates(ctx, base, N + 1, H * n, ld=ld)
         ceil_unpadded = mpmi.mpmi_write_rates(ctx, base, N + 1, H * n, ld=N + 1)
+        rceil = mpmi.mpmi_read_rates(ctx, base, N + 1, H * n, ld=ld)
         res[name] = {"candidates": N + 1, "executed_units": units, "traj_row_floats": ld,
                      "traj_bytes_allocated": base.numel() * 4,
                      "ms_decision": times["decision"], "ms_trajectory": times["trajectory"],
                      "bytes_written": wbytes, "write_GB_s": rate, "hbm_frac": rate / 8000.0,
                      "pattern_ceiling_GB_s": ceil["pattern_GB_s"], "stream_ceiling_GB_s": ceil["stream_GB_s"],
                      "pattern_ceiling_unpadded_GB_s": ceil_unpadded["pattern_GB_s"],
-                     "pattern_frac": rate / ceil["pattern_GB_s"]}
+                     "pattern_frac": rate / ceil["pattern_GB_s"],
+                     "read_pattern_ceiling_GB_s": rceil["pattern_GB_s"],
+                     "read_stream_ceiling_GB_s": rceil["stream_GB_s"]}
         if side == 1024:
             # The same tick through the separable calls: candidates, full
             # rollout (no early exit: the mask decides afterwards), safe mask,
@@ -421,6 +424,11 @@ def run_trajectory_store(st: dict, reps: int = 10):
             res["separable_calls_1m"]["ms_total"] = float(sum(np.median(v) for v in ph.values()))
             res["separable_calls_1m"]["ms_fused_tick"] = times["decision"]
             res["separable_calls_1m"]["same_selection"] = bool(sel_s == sel_f)
+            # safe_mask needs the states up to each first violation: the
+            # executed units' bytes, against the read ceiling of its pattern
+            mask_gbs = wbytes / (float(np.median(ph["safe_mask"])) * 1e-3) / 1e9
+            res["separable_calls_1m"]["safe_mask_read_GB_s"] = mask_gbs
+            res["separable_calls_1m"]["safe_mask_read_frac"] = mask_gbs / rceil["pattern_GB_s"]
             del cand
         del traj, base
         torch.cuda.empty_cache()

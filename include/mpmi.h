@@ -299,6 +299,16 @@ mpmi_status mpmi_fp32_fma_rate(mpmi_ctx ctx, double* tflops /* host */);
 mpmi_status mpmi_write_rates(mpmi_ctx ctx, float* buf, int32_t Nc, int64_t ld, int32_t rows,
                              double* pattern_gbs /* host */, double* stream_gbs /* host */);
 
+/* Diagnostic: HBM read ceilings of the safety check over stored
+ * trajectories (GB/s, host), on a caller buffer buf of rows * ld floats
+ * (device, 16-byte aligned; read only): *pattern_gbs for the load pattern of
+ * traj[rows][ld] alone (lane c < Nc reads element c of every row, no
+ * compute), *stream_gbs for contiguous 16-byte loads of rows * Nc floats;
+ * best of three timed launches each.  Synchronous (default stream);
+ * allocates nothing.  MPMI_EINVAL as for mpmi_write_rates. */
+mpmi_status mpmi_read_rates(mpmi_ctx ctx, const float* buf, int32_t Nc, int64_t ld, int32_t rows,
+                            double* pattern_gbs /* host */, double* stream_gbs /* host */);
+
 /* ---------------------------------------------------------------------------
  * Many concurrent control loops in one launch per tick.
  *

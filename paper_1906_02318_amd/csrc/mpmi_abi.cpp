@@ -409,6 +409,17 @@ mpmi_status mpmi_write_rates(mpmi_ctx ctx, float* buf, int32_t Nc, int64_t ld, i
                    "mpmi_write_rates");
 }
 
+mpmi_status mpmi_read_rates(mpmi_ctx ctx, const float* buf, int32_t Nc, int64_t ld, int32_t rows, double* pattern_gbs,
+                            double* stream_gbs) {
+  if (!ctx) return MPMI_EINVAL;
+  if (!buf || !pattern_gbs || !stream_gbs) return fail(ctx, MPMI_EINVAL, "buf, pattern_gbs and stream_gbs must be non-NULL");
+  if (!aligned(buf, 16)) return fail(ctx, MPMI_EINVAL, "buf must be 16-byte aligned");
+  if (Nc < 1 || rows < 1 || ld < Nc || (long long)ld * rows > (1ll << 33))
+    return fail(ctx, MPMI_EINVAL, "Nc=%d ld=%lld rows=%d out of range", Nc, (long long)ld, rows);
+  return check_hip(ctx, mpmi::measure_read_rates(buf, Nc, (long long)ld, rows, pattern_gbs, stream_gbs),
+                   "mpmi_read_rates");
+}
+
 mpmi_status mpmi_generate_candidates(mpmi_ctx ctx, const void* model, const mpmi_tick_desc* desc,
                                      const float* u_user, const float* cand, float* cand_out, void* stream) {
   if (!ctx) return MPMI_EINVAL;

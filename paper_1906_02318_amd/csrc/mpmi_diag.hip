@@ -110,4 +110,62 @@ hipError_t measure_write_rates(void* buf, int Nc, long long ld, int rows, double
   return hipSuccess;
 }
 
+// HBM read ceilings for the safety check over stored trajectories: the load
+// pattern of traj[rows][ld] alone (lane c < Nc reads element c of every row,
+// no compute) and a contiguous stream of 16-byte loads of the same number of
+// bytes.  The sums feed an empty asm statement, so the loads stay and
+// nothing is written.
+__global__ void __launch_bounds__(256) traj_read_kernel(const float* __restrict__ traj, int Nc, long long ld,
+                                                        int rows) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= Nc) return;
+  float acc = 0.0f;
+#pragma unroll 4
+  for (int r = 0; r < rows; ++r) acc += traj[(size_t)r * (size_t)ld + c];
+  asm volatile("" ::"v"(acc));
+}
+
+__global__ void __launch_bounds__(256) read_stream_kernel(const float4* __restrict__ in, size_t n4) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  float acc = 0.0f;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride) {
+    const float4 v = in[i];
+    acc += (v.x + v.y) + (v.z + v.w);
+  }
+  asm volatile("" ::"v"(acc));
+}
+
+hipError_t measure_read_rates(const void* buf, int Nc, long long ld, int rows, double* pattern_gbs,
+                              double* stream_gbs) {
+  const size_t bytes = (size_t)rows * (size_t)Nc * sizeof(float);
+  const size_t n4 = bytes / 16;
+  const int block = 256;
+  const unsigned grid_p = (unsigned)((Nc + block - 1) / block);
+  const unsigned grid_s = (unsigned)(device_cu_count() * 16);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  float best_p = 1e30f, best_s = 1e30f;
+  for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
+    for (int kind = 0; kind < 2 && e == hipSuccess; ++kind) {
+      if ((e = hipEventRecord(e0, 0)) != hipSuccess) break;
+      if (kind == 0) traj_read_kernel<<<grid_p, block, 0, 0>>>((const float*)buf, Nc, ld, rows);
+      else read_stream_kernel<<<grid_s, block, 0, 0>>>((const float4*)buf, n4);
+      if ((e = hipGetLastError()) != hipSuccess) break;
+      if ((e = hipEventRecord(e1, 0)) != hipSuccess) break;
+      if ((e = hipEventSynchronize(e1)) != hipSuccess) break;
+      float ms = 0.0f;
+      if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
+      if (kind == 0) best_p = ms < best_p ? ms : best_p;
+      else best_s = ms < best_s ? ms : best_s;
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return e;
+  *pattern_gbs = (double)bytes / ((double)best_p * 1e-3) / 1e9;
+  *stream_gbs = (double)(n4 * 16) / ((double)best_s * 1e-3) / 1e9;
+  return hipSuccess;
+}
+
 }  // namespace mpmi

@@ -94,6 +94,8 @@ hipError_t measure_fma_rate(float* sink, double* tflops);
 // Write ceilings on buf (rows * Nc floats, overwritten): the trajectory
 // store's pattern and a contiguous stream, GB/s.
 hipError_t measure_write_rates(void* buf, int Nc, long long ld, int rows, double* pattern_gbs, double* stream_gbs);
+hipError_t measure_read_rates(const void* buf, int Nc, long long ld, int rows, double* pattern_gbs,
+                              double* stream_gbs);
 
 // Many-loop tick (mpmi_multi.hip).
 struct WorkItem;

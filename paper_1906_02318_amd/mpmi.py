@@ -107,6 +107,7 @@ def library() -> ctypes.CDLL:
         "mpmi_generate_candidates": (i32, [vp, vp, ctypes.POINTER(TickDesc), vp, vp, vp, vp]),
         "mpmi_fp32_fma_rate": (i32, [vp, ctypes.POINTER(f64)]),
         "mpmi_write_rates": (i32, [vp, vp, i32, i64, i32, ctypes.POINTER(f64), ctypes.POINTER(f64)]),
+        "mpmi_read_rates": (i32, [vp, vp, i32, i64, i32, ctypes.POINTER(f64), ctypes.POINTER(f64)]),
         "mpmi_multi_create": (i32, [vp, ctypes.POINTER(LoopDesc), i32, ctypes.POINTER(MultiConfig), ctypes.POINTER(vp)]),
         "mpmi_multi_destroy": (None, [vp]),
         "mpmi_multi_set_config": (i32, [vp, vp, ctypes.POINTER(MultiConfig)]),
@@ -433,6 +434,17 @@ def mpmi_write_rates(ctx: Context, buf, Nc: int, rows: int, ld: int = None) -> d
     _need(buf, "buf", torch.float32, rows * ld, device=ctx.device)
     p, q = ctypes.c_double(0.0), ctypes.c_double(0.0)
     ctx.check(ctx.lib.mpmi_write_rates(ctx.handle, _ptr(buf), Nc, ld, rows, ctypes.byref(p), ctypes.byref(q)))
+    return dict(pattern_GB_s=p.value, stream_GB_s=q.value)
+
+
+def mpmi_read_rates(ctx: Context, buf, Nc: int, rows: int, ld: int = None) -> dict:
+    """Read ceilings (GB/s) of the safety check's load pattern over stored
+    trajectories (rows ld >= Nc floats apart; default Nc) and of a contiguous
+    stream, on buf (rows * ld float32, read only; synchronous)."""
+    ld = Nc if ld is None else ld
+    _need(buf, "buf", torch.float32, rows * ld, device=ctx.device)
+    p, q = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    ctx.check(ctx.lib.mpmi_read_rates(ctx.handle, _ptr(buf), Nc, ld, rows, ctypes.byref(p), ctypes.byref(q)))
     return dict(pattern_GB_s=p.value, stream_GB_s=q.value)
 
 

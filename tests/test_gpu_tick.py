@@ -725,9 +725,10 @@ def test_tick_lanes_per_candidate_identical_and_autotuned(ctx, bb, rc, case):
 
 
 def test_write_rate_diagnostic(ctx):
-    """The trajectory store's write ceilings: rates finite and below the
-    part's 8 TB/s, for rows Nc floats apart and for rows padded to 256-byte
-    boundaries; misaligned buffers and strides below Nc are rejected."""
+    """The trajectory store's write ceilings and the safety check's read
+    ceilings: rates finite and below the part's 8 TB/s, for rows Nc floats
+    apart and for rows padded to 256-byte boundaries; misaligned buffers and
+    strides below Nc are rejected."""
     Nc, rows = 262145, 60
     ld = mpmi.traj_ld(Nc)
     buf = torch.empty(rows * ld, dtype=torch.float32, device="cuda")
@@ -740,6 +741,13 @@ def test_write_rate_diagnostic(ctx):
         mpmi.mpmi_write_rates(ctx, buf[1:], Nc - 1, rows)  # misaligned
     with pytest.raises(mpmi.MpmiError):
         mpmi.mpmi_write_rates(ctx, buf, Nc, rows, ld=Nc - 1)
+    rr = mpmi.mpmi_read_rates(ctx, buf, Nc, rows, ld=ld)
+    log(f"[diag] read ceilings, rows {ld} floats apart: {rr}")
+    assert 100.0 < rr["pattern_GB_s"] < 8000.0 and 100.0 < rr["stream_GB_s"] < 8000.0
+    with pytest.raises(mpmi.MpmiError):
+        mpmi.mpmi_read_rates(ctx, buf[1:], Nc - 1, rows)  # misaligned
+    with pytest.raises(mpmi.MpmiError):
+        mpmi.mpmi_read_rates(ctx, buf, Nc, rows, ld=Nc - 1)
 
 
 @pytest.mark.parametrize("system", ["rc", "bb", "linear"])
