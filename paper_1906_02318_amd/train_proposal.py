@@ -88,7 +88,7 @@ def main():
     ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--eval-ticks", type=int, default=1000)
-    ap.add_argument("--out", default="gpurun_out/proposal_net.npz")
+    ap.add_argument("--out", default="proposal_net.npz", help="where the trained network is saved (the served one is assets/proposal_net.npz)")
     ap.add_argument("--eval-only", default=None, help="evaluate a saved network instead of training")
     args = ap.parse_args()
     log = lambda m: print(m, flush=True)
