@@ -26,10 +26,18 @@ held over the horizon or piecewise constant over S equal segments; cost is the
 squared Euclidean distance after dividing input j by its half-range, taken on
 the first segment; ties go to the lowest index; when nothing is safe the
 candidate with the latest first violation (then least cost, then lowest index)
-is returned with status NO_SAFE; process noise is zero; the fit is
-least squares on RMS-scaled columns (EDMD, Sec. IV-A's Koopman citation).
+is returned with status NO_SAFE; process noise (Alg. 2's z_i) is Gaussian with
+a per-component standard deviation, zero unless a system states one, drawn
+from the counter generator through Box-Muller; the fit is least squares on
+RMS-scaled columns (EDMD, Sec. IV-A's Koopman citation).
 
-Functions whose result no pin fixes are marked "parity unpinned" below.
+Every function here is pinned by a test of tests/test_oracle_pins.py against
+something other than this module: basis values written out by hand; the
+linear plant's closed form (fit, rollout with and without noise, selection
+interval); brute-force enumeration; published SplitMix64 vectors; hand-derived
+uniform draws, grid points and track margins (nonzero phases included);
+library least squares and the residual's orthogonality; the Sec. IV-D
+printed values; zero intervention and mask monotonicity.
 """
 from __future__ import annotations
 
@@ -264,18 +272,25 @@ def grid_candidates(sys: System, grid) -> np.ndarray:
     return np.stack(cols, axis=1)
 
 
+def uniform_value(lo, hi, h):
+    """The input value a 64-bit draw h stands for on [lo, hi): lo + (hi - lo) * r
+    with r = unit_from_bits(h), in FP64, rounded to FP32."""
+    return _to_f32(np.asarray(lo, np.float64) + (np.asarray(hi, np.float64) - np.asarray(lo, np.float64))
+                   * unit_from_bits(h))
+
+
 def uniform_candidates(sys: System, N: int, S: int, seed: int, tick: int, loop: int) -> np.ndarray:
     """N random candidates of S segments: array (N, S, m) of FP32 numbers.
 
-    Candidate i (1-based), segment g, input j draws r = unit(hash(seed, tick,
-    loop, i, g*m + j)) and takes lo_j + (hi_j - lo_j) * r in FP64, rounded to FP32.
+    Candidate i (1-based), segment g, input j takes uniform_value(lo_j, hi_j,
+    hash(seed, tick, loop, i, g*m + j)).
     """
     i = np.arange(1, N + 1, dtype=np.uint64)[:, None, None]
     g = np.arange(S, dtype=np.uint64)[None, :, None]
     j = np.arange(sys.m, dtype=np.uint64)[None, None, :]
     slot = g * np.uint64(sys.m) + j
-    r = unit_from_bits(hash_counter(np.uint64(seed), np.uint64(tick), np.uint64(loop), i, slot))
-    return _to_f32(sys.u_lo + (sys.u_hi - sys.u_lo) * r)
+    h = hash_counter(np.uint64(seed), np.uint64(tick), np.uint64(loop), i, slot)
+    return uniform_value(sys.u_lo, sys.u_hi, h)
 
 
 def with_user(cand: np.ndarray, u_h, S: int) -> np.ndarray:

@@ -95,6 +95,59 @@ def test_adam_first_step_closed_form():
     np.testing.assert_allclose(v, 0.001 * g * g)
 
 
+def test_forward_hand_evaluated_sparse_network():
+    """A network with one path through it, evaluated by hand.  Input 0 is 5 with
+    mean 1 and standard deviation 2, so the standardised input is (5 - 1) / 2 = 2;
+    W1[0, 0] = 1 gives z1 = 2; W2[0, 3] = 0.5 gives z2 = 0.5 gelu(2); W3[3, 7] = 2
+    and b3[7] = 0.25 give z3 = 2 gelu(z2) + 0.25; W4[7, 11] = -1 and b4[11] = 0.1
+    give y11 = 0.1 - gelu(z3).  Every other output is its bias; other inputs
+    (standardised with their own mean and deviation) reach nothing."""
+    def g(z):  # tanh-form GELU, written out from its definition
+        return 0.5 * z * (1.0 + math.tanh(math.sqrt(2.0 / math.pi) * (z + 0.044715 * z ** 3)))
+
+    flat = np.zeros(M.param_count())
+    offs = np.cumsum([0] + [k * n + n for k, n in M.LAYERS])
+
+    def w(layer, i, j, v):
+        k, n = M.LAYERS[layer]
+        flat[offs[layer] + i * n + j] = v
+
+    def b(layer, j, v):
+        k, n = M.LAYERS[layer]
+        flat[offs[layer] + k * n + j] = v
+
+    w(0, 0, 0, 1.0)
+    w(1, 0, 3, 0.5)
+    w(2, 3, 7, 2.0)
+    b(2, 7, 0.25)
+    w(3, 7, 11, -1.0)
+    b(3, 11, 0.1)
+    b(3, 40, -0.7)
+    X = np.array([[5.0, 3.0, -2.0, 0.5, 0.0, 1.0, 2.0, -1.0]])
+    mean = np.array([1.0, 0.5, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0])
+    std = np.array([2.0, 4.0, 1.0, 1.0, 1.0, 1.0, 1.0, 1.0])
+    Y, _ = M.forward(flat, X, mean, std)
+    expect = np.zeros(M.N_OUT)
+    expect[11] = 0.1 - g(2.0 * g(0.5 * g(2.0)) + 0.25)
+    expect[40] = -0.7
+    np.testing.assert_allclose(Y[0], expect, rtol=0, atol=1e-15)
+
+
+def test_adam_constant_gradient_is_bias_free():
+    """Under a constant gradient g the bias-corrected moments are exactly g and
+    g^2 at every step (Kingma & Ba 2015, Sec. 3: the correction removes the
+    zero-initialisation bias), so each step moves w by lr * g / (|g| + eps)."""
+    g = np.array([0.3, -2.0, 1e-3, 5.0])
+    w0 = np.array([1.0, 2.0, 3.0, 4.0])
+    w, m, v = w0.copy(), np.zeros(4), np.zeros(4)
+    lr = 0.01
+    for step in range(1, 6):
+        w, m, v = M.adam_step(w, g, m, v, step, lr=lr)
+        np.testing.assert_allclose(w, w0 - step * lr * g / (np.abs(g) + 1e-8), rtol=0, atol=1e-12)
+        np.testing.assert_allclose(m, (1.0 - 0.9 ** step) * g, rtol=1e-13)
+        np.testing.assert_allclose(v, (1.0 - 0.999 ** step) * g * g, rtol=1e-12)
+
+
 def test_sampler_statistics():
     Y = np.zeros((M.N_COMP, 5))
     Y[:, 0] = -30.0

@@ -293,6 +293,62 @@ def test_counter_hash_is_chained_splitmix():
     assert int(o.hash_counter(0, 0, 0, 0, 0)) != int(o.hash_counter(0, 0, 0, 1, 0))
 
 
+def _golden_splitmix(seed):
+    with open(os.path.join(GOLDEN, "splitmix64_vectors.txt")) as f:
+        rows = [l.split() for l in f if l.strip() and not l.startswith("#")]
+    return [int(v) for v in {int(r[0]): r[1:] for r in rows}[seed]]
+
+
+def test_counter_hash_chain_from_published_vectors():
+    """The chained hash h <- mix((h ^ w) + gamma) steered through the published
+    seed-0 stream: with seed ^ tick = 0 the first round is mix(gamma) = out1; a
+    loop word of out1 ^ gamma makes the second mix(2 gamma) = out2; an index
+    word of out2 ^ (2 gamma) makes the third out3; a slot word of out3 brings
+    the fourth back to mix(gamma) = out1."""
+    out1, out2, out3 = _golden_splitmix(0)
+    g = o.GOLDEN_GAMMA
+    two_g = (2 * g) & ((1 << 64) - 1)
+    h = o.hash_counter(np.uint64(12345), np.uint64(12345), np.uint64(out1 ^ g), np.uint64(out2 ^ two_g),
+                       np.uint64(out3))
+    assert int(h) == out1
+    # one round less: the slot word zero gives mix(out3 + gamma) instead
+    assert int(o.hash_counter(np.uint64(7), np.uint64(7), np.uint64(out1 ^ g), np.uint64(out2 ^ two_g),
+                              np.uint64(0))) != out1
+
+
+def test_uniform_value_hand_derived():
+    """A draw's top 24 bits are the fraction of the box: out1 of the published
+    seed-0 stream is 16294208416658607535, whose top 24 bits are 14819496, so
+    on [-5, 5) it stands for -5 + 10 * 14819496 / 2^24 = 3.833107948303223
+    (FP32 3.8331079483032227).  A draw of 0 is the lower end, the largest
+    draw one 2^-24 step short of the upper end."""
+    out1 = _golden_splitmix(0)[0]
+    assert out1 >> 40 == 14819496
+    assert o.uniform_value(-5.0, 5.0, np.uint64(out1)) == np.float64(np.float32(3.8331079483032227))
+    assert o.uniform_value(-0.4, 0.4, np.uint64(0)) == np.float64(np.float32(-0.4))
+    top = o.uniform_value(-3.0, 3.0, np.uint64((1 << 64) - 1))
+    assert top == np.float64(np.float32(-3.0 + 6.0 * (1.0 - 2.0 ** -24))) and top < 3.0
+
+
+def test_uniform_candidates_follow_their_draws():
+    """Candidate (i, g, j) is the value of draw hash(seed, tick, loop, i, g m + j)
+    (i from 1); the value map is increasing, so sorting the draws sorts the
+    candidates, and the extreme draws land next to the box ends."""
+    sys = o.System("race_car", 6, 2, u_lo=[-0.4, -3.0], u_hi=[0.4, 3.0])
+    N, S = 3000, 3
+    c = o.uniform_candidates(sys, N, S, seed=4, tick=7, loop=2)
+    for i, g, j in ((1, 0, 0), (1, 0, 1), (17, 2, 1), (N, 1, 0)):
+        h = o.hash_counter(np.uint64(4), np.uint64(7), np.uint64(2), np.uint64(i), np.uint64(g * 2 + j))
+        assert c[i - 1, g, j] == o.uniform_value(sys.u_lo[j], sys.u_hi[j], h)
+    for j in range(2):
+        h = o.hash_counter(np.uint64(4), np.uint64(7), np.uint64(2), np.arange(1, N + 1, dtype=np.uint64),
+                           np.uint64(j))
+        vals = c[:, 0, j][np.argsort(h >> np.uint64(40), kind="stable")]
+        assert np.all(np.diff(vals) >= 0)
+        span = sys.u_hi[j] - sys.u_lo[j]
+        assert vals[0] - sys.u_lo[j] < 0.01 * span and sys.u_hi[j] - vals[-1] < 0.01 * span
+
+
 def test_uniform_candidates_in_box_and_unbiased():
     sys = o.System("race_car", 6, 2, u_lo=[-0.4, -3.0], u_hi=[0.4, 3.0])
     c = o.uniform_candidates(sys, 20000, 3, seed=4, tick=7, loop=2)
@@ -331,6 +387,21 @@ def test_margins_hand_cases():
     m = o.margins(rc, x)
     np.testing.assert_allclose(m[:, 0], [1.0, 2.0, 2.0])
     np.testing.assert_allclose(m[:, 1], [1.5, 2.5 - abs(29.0 - rc_half_pi), 2.5 - 30.0], atol=1e-12)
+
+
+def test_track_margins_with_phases():
+    """Phases shift each sinusoid: r_c(phi) = 30 + 2 sin(2 phi + pi/2) + sin(3 phi + pi).
+    At phi = 0 that is 30 + 2 + 0 = 32; at phi = pi/2 it is 30 + 2 sin(3 pi/2)
+    + sin(5 pi/2) = 29; at phi = pi, 30 + 2 - 0 = 32 again."""
+    tr = dict(r0=30.0, half=3.0, amp=[2.0, 1.0, 0.0, 0.0], freq=[2, 3, 4, 5],
+              phase=[math.pi / 2, math.pi, 0.0, 0.0], infl=0.5)
+    rc = o.System("race_car", 6, 2, box=[], track=tr, u_lo=[-0.4, -3.0], u_hi=[0.4, 3.0])
+    x = np.array([[32.5, 0.0, 0, 0, 0, 0], [0.0, 29.0, 0, 0, 0, 0], [0.0, 30.0, 0, 0, 0, 0],
+                  [-31.0, 0.0, 0, 0, 0, 0]])
+    np.testing.assert_allclose(o.centre_radius(tr, np.array([0.0, math.pi / 2, math.pi])), [32.0, 29.0, 32.0],
+                               atol=1e-12)
+    # margins (3 - 0.5) - |rho - r_c|: gaps 0.5, 0, 1, 1
+    np.testing.assert_allclose(o.margins(rc, x)[:, 0], [2.0, 2.5, 1.5, 1.5], atol=1e-12)
 
 
 def test_no_safe_fallback_rule():
