@@ -202,14 +202,8 @@ def run_multi(n_ticks: int = 2000, warmup: int = 50, seed: int = 5):
                phase=list(track.phase), infl=0.0)
     sr = mpmi.race_car_system(trd)
     mr = mpmi.mpmi_model_pack(ctx, sr, mpmi.koopman_fit(ctx, sr, d(Xr), d(Ur), d(Yr))[0])
-    N, H = synth.loop_sizes(64, seed=seed)
-    kinds = ["bb"] * 32 + ["rc"] * 32
-    xs = np.zeros((64, 8), np.float32)
-    us = np.zeros((64, 4), np.float32)
-    xs[:32, :4] = synth.balance_bot_states(32, seed=1)
-    xs[32:, :6] = synth.race_car_states(32, track, seed=1)
-    users = [synth.AR1User([-5.0], [5.0], seed=100 + i) for i in range(32)] + \
-            [synth.AR1User(synth.RC_U_LO, synth.RC_U_HI, sigma=[0.08, 0.6], seed=200 + i) for i in range(32)]
+    scen = synth.ManyLoops(track, 64, seed=seed)
+    N, H = scen.N, scen.H
     x_dev = torch.zeros((64, 8), dtype=torch.float32, device="cuda")
     u_dev = torch.zeros((64, 4), dtype=torch.float32, device="cuda")
     out_dev = torch.zeros((64, mpmi.SELECTION_BYTES), dtype=torch.uint8, device="cuda")
@@ -217,23 +211,22 @@ def run_multi(n_ticks: int = 2000, warmup: int = 50, seed: int = 5):
     u_pin = torch.zeros((64, 4), dtype=torch.float32).pin_memory()
     o_pin = torch.zeros((64, mpmi.SELECTION_BYTES), dtype=torch.uint8).pin_memory()
     loops = [dict(model=mb if k == "bb" else mr, x_t=x_dev[i], u_user=u_dev[i], out=out_dev[i], n_cand=int(N[i]),
-                  horizon=int(H[i]), gen=mpmi.GEN_UNIFORM, seed=1000 + i, tick=0) for i, k in enumerate(kinds)]
+                  horizon=int(H[i]), gen=mpmi.GEN_UNIFORM, seed=scen.seeds[i], tick=0)
+             for i, k in enumerate(scen.kinds)]
     multi = mpmi.Multi(ctx, loops)
     stream = torch.cuda.current_stream()
-    for i in range(64):
-        us[i, :users[i].lo.size] = users[i].next()
-    x_pin.copy_(torch.from_numpy(xs))
-    u_pin.copy_(torch.from_numpy(us))
+    x_pin.copy_(torch.from_numpy(scen.x))
+    u_pin.copy_(torch.from_numpy(scen.u))
     x_dev.copy_(x_pin)
     u_dev.copy_(u_pin)
     tuned = multi.autotune(reps=10)
     multi.capture_graph()
-    dev_ms, e2e_ms, resets, interventions, nosafe = [], [], 0, 0, 0
+    dev_ms, e2e_ms, interventions, nosafe = [], [], 0, 0
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     for t in range(warmup + n_ticks):
         t0 = time.perf_counter()
-        x_pin.copy_(torch.from_numpy(xs))
-        u_pin.copy_(torch.from_numpy(us))
+        x_pin.copy_(torch.from_numpy(scen.x))
+        u_pin.copy_(torch.from_numpy(scen.u))
         x_dev.copy_(x_pin, non_blocking=True)
         u_dev.copy_(u_pin, non_blocking=True)
         ev0.record(stream)
@@ -251,23 +244,7 @@ def run_multi(n_ticks: int = 2000, warmup: int = 50, seed: int = 5):
             interventions += int(np.sum(raw[:, 0] != 0))
             nosafe += int(np.sum(raw[:, 1] != 0))
         # plants advance with the applied inputs; users move on
-        ub = flt[:32, 4:5].astype(np.float64)
-        xb = synth.cartpole_step(xs[:32, :4].astype(np.float64), ub[:, 0])
-        bad = (np.abs(xb[:, 2]) > 0.5) | (np.abs(xb[:, 0]) > 2.0)
-        resets += int(bad.sum())
-        if bad.any():
-            xb[bad] = synth.balance_bot_states(int(bad.sum()), seed=7 + t)
-        xs[:32, :4] = xb
-        xr = synth.bicycle_step(xs[32:, :6].astype(np.float64), flt[32:, 4:6].astype(np.float64))
-        rho = np.hypot(xr[:, 0], xr[:, 1])
-        off = rho - track.centre_radius(np.arctan2(xr[:, 1], xr[:, 0]))
-        badr = (np.abs(off) > 3.0) | (np.abs(xr[:, 4]) > 2.0)
-        resets += int(badr.sum())
-        if badr.any():
-            xr[badr] = synth.race_car_states(int(badr.sum()), track, seed=9 + t)
-        xs[32:, :6] = xr
-        for i in range(64):
-            us[i, :users[i].lo.size] = users[i].next()
+        scen.advance(flt[:, 4:8], t)
     multi.close()
     dev = np.array(dev_ms)
     e2e = np.array(e2e_ms)
@@ -281,7 +258,7 @@ def run_multi(n_ticks: int = 2000, warmup: int = 50, seed: int = 5):
         "p50_tick_ms": float(np.percentile(dev, 50)), "p99_tick_ms": float(np.percentile(dev, 99)),
         "p50_end_to_end_ms": float(np.percentile(e2e, 50)), "p99_end_to_end_ms": float(np.percentile(e2e, 99)),
         "interventions_per_tick": interventions / n_ticks, "no_safe_per_tick": nosafe / n_ticks,
-        "plant_resets": resets,
+        "plant_resets": scen.resets,
     }
 
 

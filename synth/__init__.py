@@ -255,6 +255,56 @@ def loop_sizes(n_loops: int = 64, seed: int = 5, n_lo: int = 1024, n_hi: int = 6
     return N, H
 
 
+class ManyLoops:
+    """The mixed serving workload: n_loops closed control loops, the first half
+    cart-poles and the second half race cars, with candidate counts and
+    horizons from loop_sizes(n_loops, seed), AR(1) users (cart-pole: sigma
+    1 N, seeds 100 + i; race car: sigma (0.08 rad, 0.6 m/s^2), seeds 200 + i)
+    and plants that advance with the applied inputs and restart from a fresh
+    seeded state when they leave their safe set.  States and user inputs are
+    padded to (n_loops, 8) and (n_loops, 4); loop i draws its candidates with
+    seed 1000 + i."""
+
+    def __init__(self, track: "Track", n_loops: int = 64, seed: int = 5):
+        self.track = track
+        self.n_loops = n_loops
+        self.nb = n_loops // 2
+        self.N, self.H = loop_sizes(n_loops, seed=seed)
+        self.kinds = ["bb"] * self.nb + ["rc"] * (n_loops - self.nb)
+        self.seeds = [1000 + i for i in range(n_loops)]
+        self.x = np.zeros((n_loops, 8), np.float32)
+        self.u = np.zeros((n_loops, 4), np.float32)
+        self.x[: self.nb, :4] = balance_bot_states(self.nb, seed=1)
+        self.x[self.nb:, :6] = race_car_states(n_loops - self.nb, track, seed=1)
+        self.users = [AR1User([BB_U_LO], [BB_U_HI], seed=100 + i) for i in range(self.nb)] + \
+                     [AR1User(RC_U_LO, RC_U_HI, sigma=[0.08, 0.6], seed=200 + i) for i in range(n_loops - self.nb)]
+        self.resets = 0
+        self._next_users()
+
+    def _next_users(self):
+        for i, us in enumerate(self.users):
+            self.u[i, : us.lo.size] = us.next()
+
+    def advance(self, u_applied: np.ndarray, t: int):
+        """Steps every plant with its applied input (n_loops, >= 2), restarts
+        those that left their safe set, and moves the users on."""
+        nb = self.nb
+        xb = cartpole_step(self.x[:nb, :4].astype(np.float64), u_applied[:nb, 0].astype(np.float64))
+        bad = (np.abs(xb[:, 2]) > 0.5) | (np.abs(xb[:, 0]) > 2.0)
+        self.resets += int(bad.sum())
+        if bad.any():
+            xb[bad] = balance_bot_states(int(bad.sum()), seed=7 + t)
+        self.x[:nb, :4] = xb
+        xr = bicycle_step(self.x[nb:, :6].astype(np.float64), u_applied[nb:, :2].astype(np.float64))
+        off = np.hypot(xr[:, 0], xr[:, 1]) - self.track.centre_radius(np.arctan2(xr[:, 1], xr[:, 0]))
+        badr = (np.abs(off) > 3.0) | (np.abs(xr[:, 4]) > 2.0)
+        self.resets += int(badr.sum())
+        if badr.any():
+            xr[badr] = race_car_states(int(badr.sum()), self.track, seed=9 + t)
+        self.x[nb:, :6] = xr
+        self._next_users()
+
+
 # ----------------------------------------------------------------------------
 # Proposal-network initialisation and label states
 # ----------------------------------------------------------------------------

@@ -7,10 +7,26 @@
 * Safety verdicts: first violations must be identical except for candidates
   whose oracle margin comes within eps_j of zero at some step up to the
   earlier of the two first violations (ambiguous by FP32 rounding).
-* Selection: the same candidate, or two candidates that are both oracle-safe
-  or ambiguous and whose FP64 costs agree to 1e-6 relative.
+* Selection, complete: the GPU's choice, status and safe count are those of
+  the selection rule (Alg. 2 selection step; the fallback rule when nothing
+  is safe) applied to the GPU's own first violations -- which the previous
+  rule ties to the oracle's everywhere outside the eps band.  A different
+  candidate of equal first violation and equal FP64 cost (to 1e-6
+  relative; the GPU ranks FP32 costs) is accepted.
+* Agreement with the oracle's decision (counted, not assumed): the same
+  candidate ("identical"), or two candidates both oracle-safe or ambiguous
+  whose FP64 costs agree to 1e-6 relative ("equal_cost").  Any other outcome
+  ("eps_band") can only come from ambiguous verdicts, by the two rules above,
+  and counts as a disagreement.
+
+Long replays run the oracle in a pool of worker processes (spawn context;
+the workers import only NumPy and the oracle, never the GPU library).
 """
 from __future__ import annotations
+
+import multiprocessing
+import os
+from concurrent.futures import ProcessPoolExecutor
 
 import numpy as np
 
@@ -42,38 +58,123 @@ def ambiguous(sys: o.System, traj64: np.ndarray, fv_a: np.ndarray, fv_b: np.ndar
     return np.any(near & (steps <= upto[None, :]), axis=0)
 
 
-def check_tick(sys: o.System, K, x_t, u_h, cand64: np.ndarray, H: int, sel: dict, fv_gpu: np.ndarray, eps,
-               label: str = "", noise_key=None) -> dict:
-    """Checks one GPU tick against the oracle; returns counters for reporting."""
-    traj, fv_o = o.rollout(sys, K, x_t, cand64, H, early_exit=False, noise_key=noise_key)
+def _same_choice(cost, fv, i, j) -> bool:
+    return i == j or (fv[i] == fv[j] and abs(cost[i] - cost[j]) <= 1e-6 * max(abs(cost[j]), 1e-30))
+
+
+def check_selection(sys: o.System, cand64: np.ndarray, H: int, u_h, sel: dict, fv_gpu: np.ndarray,
+                    label: str = "") -> dict:
+    """The GPU's record is the selection rule over its own first violations."""
     fv_gpu = np.asarray(fv_gpu, np.int64)
-    amb = ambiguous(sys, traj, fv_o, fv_gpu, eps)
+    own = o.select(sys, cand64, fv_gpu, H, u_h)
+    cost = o.cost(sys, cand64, u_h)
+    i_g = sel["idx"]
+    assert 0 <= i_g < fv_gpu.size, f"{label}: index {i_g} out of range"
+    assert _same_choice(cost, fv_gpu, i_g, own["idx"]), (
+        f"{label}: GPU chose {i_g} (cost {cost[i_g]:.9g}, fv {fv_gpu[i_g]}) but its own verdicts select "
+        f"{own['idx']} (cost {cost[own['idx']]:.9g}, fv {fv_gpu[own['idx']]})")
+    assert sel["status"] == own["status"], f"{label}: status {sel['status']} vs {own['status']} over its verdicts"
+    assert sel["n_safe"] == own["n_safe"], f"{label}: n_safe {sel['n_safe']} vs {own['n_safe']} over its verdicts"
+    if "first_violation" in sel:
+        assert sel["first_violation"] == fv_gpu[i_g], f"{label}: record's first violation"
+    np.testing.assert_array_equal(np.asarray(sel["u_r"][: sys.m], np.float64), cand64[i_g, 0, :])
+    return own
+
+
+def judge(sys: o.System, cand64: np.ndarray, H: int, u_h, traj64: np.ndarray, fv_o: np.ndarray, sel: dict,
+          fv_gpu: np.ndarray, eps, label: str = "") -> dict:
+    """Checks one GPU tick against an oracle rollout (full horizon, traj64
+    (H, Nc, n), first violations fv_o); returns counters for reporting."""
+    fv_gpu = np.asarray(fv_gpu, np.int64)
+    amb = ambiguous(sys, traj64, fv_o, fv_gpu, eps)
     mism = (fv_o != fv_gpu) & ~amb
     assert not mism.any(), (f"{label}: first-violation mismatch outside the eps band at candidates "
                             f"{np.nonzero(mism)[0][:10]} (oracle {fv_o[mism][:10]}, gpu {fv_gpu[mism][:10]})")
+    check_selection(sys, cand64, H, u_h, sel, fv_gpu, label)
+    return agreement(sys, cand64, H, u_h, fv_o, amb, sel)
+
+
+def agreement(sys: o.System, cand64: np.ndarray, H: int, u_h, fv_o: np.ndarray, amb: np.ndarray, sel: dict) -> dict:
+    """Agreement of the GPU's decision with the oracle's (see the module header)."""
     ref = o.select(sys, cand64, fv_o, H, u_h)
     cost = o.cost(sys, cand64, u_h)
     i_g, i_o = sel["idx"], ref["idx"]
     safe_o = fv_o == H + 1
-    kind = "identical"
-    if i_g != i_o:
-        ok_g = safe_o[i_g] or amb[i_g]
-        ok_o = safe_o[i_o] or amb[i_o]
-        if ok_g and ok_o and abs(cost[i_g] - cost[i_o]) <= 1e-6 * max(abs(cost[i_o]), 1e-30):
-            kind = "equal_cost"
-        elif amb[i_g] and cost[i_g] <= cost[i_o]:
-            kind = "eps_band"   # GPU kept an ambiguous candidate the oracle rejected
-        elif amb[i_o] and ok_g and cost[i_g] >= cost[i_o]:
-            kind = "eps_band"   # GPU rejected the oracle's ambiguous choice
-        elif ref["status"] != o.STATUS_OK and sel["status"] != o.STATUS_OK and amb.any():
-            kind = "eps_band"   # fallback ordering decided by ambiguous first violations
-        else:
-            raise AssertionError(
-                f"{label}: selection {i_g} (cost {cost[i_g]:.9g}, fv {fv_o[i_g]}, amb {amb[i_g]}) vs oracle "
-                f"{i_o} (cost {cost[i_o]:.9g}, fv {fv_o[i_o]}, amb {amb[i_o]}), status {sel['status']}/{ref['status']}")
+    if i_g == i_o:
+        kind = "identical"
+    elif ((safe_o[i_g] or amb[i_g]) and (safe_o[i_o] or amb[i_o])
+          and abs(cost[i_g] - cost[i_o]) <= 1e-6 * max(abs(cost[i_o]), 1e-30)):
+        kind = "equal_cost"
+    else:
+        kind = "eps_band"
+        assert amb.any(), "a disagreement with no ambiguous verdict"
     if not amb.any():
-        assert sel["status"] == ref["status"], f"{label}: status {sel['status']} vs {ref['status']}"
-        assert sel["n_safe"] == ref["n_safe"], f"{label}: n_safe {sel['n_safe']} vs {ref['n_safe']}"
-    np.testing.assert_array_equal(np.asarray(sel["u_r"][: sys.m], np.float64), cand64[i_g, 0, :])
-    return dict(kind=kind, ambiguous=int(amb.sum()), status=ref["status"], idx=i_o,
-                n_safe=ref["n_safe"], zero_intervention=bool(i_o == 0))
+        assert sel["status"] == ref["status"] and sel["n_safe"] == ref["n_safe"]
+    return dict(kind=kind, ambiguous=int(amb.sum()), status=ref["status"], idx=i_o, gpu_idx=i_g,
+                n_safe=ref["n_safe"], zero_intervention=bool(i_o == 0),
+                cost_gap=float(cost[i_g] - cost[i_o]))
+
+
+def check_tick(sys: o.System, K, x_t, u_h, cand64: np.ndarray, H: int, sel: dict, fv_gpu: np.ndarray, eps,
+               label: str = "", noise_key=None) -> dict:
+    """Checks one GPU tick against the oracle; returns counters for reporting."""
+    traj, fv_o = o.rollout(sys, K, x_t, cand64, H, early_exit=False, noise_key=noise_key)
+    return judge(sys, cand64, H, u_h, traj, fv_o, sel, fv_gpu, eps, label)
+
+
+def agreed(kinds: dict) -> int:
+    return kinds.get("identical", 0) + kinds.get("equal_cost", 0)
+
+
+def tally(results) -> dict:
+    kinds = {}
+    for r in results:
+        kinds[r["kind"]] = kinds.get(r["kind"], 0) + 1
+        kinds["zero_intervention"] = kinds.get("zero_intervention", 0) + int(r["zero_intervention"])
+        kinds["no_safe"] = kinds.get("no_safe", 0) + int(r["status"] != o.STATUS_OK)
+    return kinds
+
+
+# ----------------------------------------------------------------------------
+# Replays in worker processes
+# ----------------------------------------------------------------------------
+def _one_blas_thread():
+    from threadpoolctl import threadpool_limits
+
+    threadpool_limits(limits=1)
+
+
+def replay_pool(workers: int = 0) -> ProcessPoolExecutor:
+    """A pool of oracle workers (at most 8, never more than the usable cores)."""
+    n = workers or max(1, min(8, len(os.sched_getaffinity(0))))
+    return ProcessPoolExecutor(max_workers=n, mp_context=multiprocessing.get_context("spawn"),
+                               initializer=_one_blas_thread)
+
+
+def candidates(sys: o.System, spec, u_h) -> np.ndarray:
+    """A tick's candidate set (N+1, S, m) from an array or a generator spec:
+    ("grid", [G_0, ...]) or ("uniform", N, S, seed, tick, loop)."""
+    if isinstance(spec, np.ndarray):
+        return spec
+    if spec[0] == "grid":
+        return o.with_user(o.grid_candidates(sys, spec[1]), u_h, 1)
+    _, N, S, seed, tick, loop = spec
+    return o.with_user(o.uniform_candidates(sys, N, S, seed, tick, loop), u_h, S)
+
+
+def replay_job(job) -> list:
+    """One tick replayed by the oracle and judged against one or more GPU
+    results: job = (sys, K, x_t, u_h, cand_spec, H, eps, noise_key,
+    [(sel, fv_gpu, label), ...])."""
+    sys, K, x_t, u_h, spec, H, eps, noise_key, results = job
+    cand = candidates(sys, spec, u_h)
+    traj, fv_o = o.rollout(sys, K, x_t, cand, H, early_exit=False, noise_key=noise_key)
+    return [judge(sys, cand, H, u_h, traj, fv_o, sel, fv, eps, label) for sel, fv, label in results]
+
+
+def oracle_chunk(job):
+    """First violations and ambiguity of a slice of one tick's candidates:
+    job = (sys, K, x_t, cand_slice, H, fv_gpu_slice, eps)."""
+    sys, K, x_t, cand, H, fv_gpu, eps = job
+    traj, fv_o = o.rollout(sys, K, x_t, cand, H, early_exit=False)
+    return fv_o, ambiguous(sys, traj, fv_o, np.asarray(fv_gpu, np.int64), eps)

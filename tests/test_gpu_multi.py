@@ -10,7 +10,7 @@ import synth
 from oracle import mpmi_oracle as o
 from paper_1906_02318_amd import mpmi
 from tests import workloads as W
-from tests.parity import check_tick
+from tests.parity import agreed, check_tick, replay_job, tally
 
 pytestmark = pytest.mark.gpu
 
@@ -161,3 +161,51 @@ def test_multi_model_snapshot_taken_at_replan(setup):
         mpmi.mpmi_model_pack(ctx, mpmi.race_car_system(W.track_dict(W.rc_track())), dev(Kr, torch.float64), into=mr)
         torch.cuda.synchronize()
         multi.set_config(multi.config()["block"])
+
+
+def test_serving_workload_decisions_against_oracle(oracle_pool):
+    """The bench's serving workload -- 64 closed loops (32 cart-poles, 32 race
+    cars; N_l log-uniform in [1,024, 65,536], H_l in 20..60, AR(1) users), one
+    graph replay per tick -- for 1,001 ticks; at every 500th tick all 64 loops
+    are replayed by the oracle on their visited (x_t, u_h, candidates): every
+    record is the selection rule over its loop's first violations, and at
+    least 99.9% of the decisions agree with the oracle's."""
+    ctx = mpmi.Context(0)
+    track = W.rc_track()
+    Kb, Kr = W.bb_model()[0], W.rc_model()[0]
+    mb = mpmi.mpmi_model_pack(ctx, mpmi.balance_bot_system(), dev(Kb, torch.float64))
+    mr = mpmi.mpmi_model_pack(ctx, mpmi.race_car_system(W.track_dict(track)), dev(Kr, torch.float64))
+    systems = {"bb": (W.bb_oracle_system(), Kb, 4, 1), "rc": (W.rc_oracle_system(track), Kr, 6, 2)}
+    scen = synth.ManyLoops(track, 64, seed=5)
+    n = scen.n_loops
+    x_dev = torch.zeros((n, 8), dtype=torch.float32, device="cuda")
+    u_dev = torch.zeros((n, 4), dtype=torch.float32, device="cuda")
+    out_dev = torch.zeros((n, mpmi.SELECTION_BYTES), dtype=torch.uint8, device="cuda")
+    fvs = [torch.zeros(int(N) + 1, dtype=torch.int16, device="cuda") for N in scen.N]
+    loops = [dict(model=mb if k == "bb" else mr, x_t=x_dev[i], u_user=u_dev[i], out=out_dev[i],
+                  first_violation=fvs[i], n_cand=int(scen.N[i]), horizon=int(scen.H[i]), gen=mpmi.GEN_UNIFORM,
+                  seed=scen.seeds[i], tick=0) for i, k in enumerate(scen.kinds)]
+    multi = mpmi.Multi(ctx, loops)
+    multi.capture_graph()
+    jobs = []
+    for t in range(1001):
+        x_dev.copy_(torch.from_numpy(scen.x))
+        u_dev.copy_(torch.from_numpy(scen.u))
+        multi.launch_graph()
+        torch.cuda.synchronize()
+        rec = out_dev.cpu().numpy()
+        if t % 500 == 0:
+            sels = mpmi.decode_selection(out_dev)
+            for i, k in enumerate(scen.kinds):
+                so, K, nx, nu = systems[k]
+                x, u = W.f32(scen.x[i, :nx]), W.f32(scen.u[i, :nu])
+                jobs.append((so, K, x, u, ("uniform", int(scen.N[i]), 1, scen.seeds[i], t, i), int(scen.H[i]),
+                             EPS[k], None, [(sels[i], fvs[i].cpu().numpy(), f"tick {t} loop {i} ({k})")]))
+            log(f"[serving] tick {t}: records of {n} loops taken")
+        scen.advance(rec.view(np.float32).reshape(n, -1)[:, 4:8], t)
+    assert multi.ticks() == [1001] * n
+    multi.close()
+    res = [r for rs in oracle_pool.map(replay_job, jobs) for r in rs]
+    kinds = tally(res)
+    log(f"[serving] {len(res)} loop-ticks replayed: {kinds}; plant restarts {scen.resets}")
+    assert agreed(kinds) >= 0.999 * len(res)
