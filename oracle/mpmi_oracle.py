@@ -175,6 +175,41 @@ def predict(kind: str, K: np.ndarray, X, U) -> np.ndarray:
     return lift(kind, X, U) @ K
 
 
+def state_columns(kind: str, n: int) -> np.ndarray:
+    """Features of psi that are the state components themselves (psi holds w
+    = [x; u] linearly): linear -> 0..n-1, balance bot and race car -> 1..n
+    (after the constant feature)."""
+    first = 0 if kind == "linear" else 1
+    return np.arange(first, first + n)
+
+
+def fit_lifted(kind: str, X, U, Y, ridge: float = 0.0):
+    """The full lifted operator of Sec. IV-A's linear representation: K (D, D)
+    with psi(x_{t+1}, u_t) ~ psi(x_t, u_t) K, in the least-squares sense on
+    RMS-scaled columns, as fit() does for the state columns.  The input is
+    held over the step, as a candidate's input is held over the horizon, so
+    the lifted state z = psi(x, u) of a constant-input rollout advances by
+    z <- z K (one matrix-vector product per step; a batch of candidates, one
+    matrix-matrix product).  Returns (K, info) like fit()."""
+    X, U, Y = (np.asarray(a, np.float64) for a in (X, U, Y))
+    Psi = lift(kind, X, U)
+    Target = lift(kind, Y, U)
+    scale = np.sqrt(np.mean(Psi * Psi, axis=0))
+    scale[scale == 0.0] = 1.0
+    Ps = Psi / scale
+    A, B = Ps, Target
+    if ridge > 0.0:
+        D = Ps.shape[1]
+        A = np.vstack([Ps, np.sqrt(ridge) * np.eye(D)])
+        B = np.vstack([Target, np.zeros((D, Target.shape[1]))])
+    Ks, _, _, sv = np.linalg.lstsq(A, B, rcond=None)
+    K = Ks / scale[:, None]
+    resid = Target - Psi @ K
+    info = dict(cond=float(sv[0] / sv[-1]) if sv[-1] > 0 else np.inf,
+                resid_rms=np.sqrt(np.mean(resid * resid, axis=0)), scale=scale)
+    return K, info
+
+
 # ----------------------------------------------------------------------------
 # Safety (Sec. IV-B "geometric safety checks", Sec. V-C-1 inflated barrier)
 # ----------------------------------------------------------------------------
@@ -369,6 +404,48 @@ def rollout(sys: System, K: np.ndarray, x0, cand: np.ndarray, H: int, early_exit
         fv[newly] = s
         alive[bad] = False
     return traj, fv
+
+
+def rollout_lifted(sys: System, K: np.ndarray, x0, cand: np.ndarray, H: int, early_exit: bool = True):
+    """Constant-input rollouts in the lifted space (Sec. IV-A: predicting with
+    the Koopman representation is a matrix-vector product per step, and a
+    batch of trajectories a matrix-matrix product).  Z holds one lifted state
+    z = psi(x0, u_i) per candidate (rows); each step Z <- Z K with the full
+    lifted operator K (D, D) of fit_lifted; the predicted state is read off
+    the state columns of Z.  cand: (Nc, 1, m), one segment.  Safety, first
+    violations and early exit as in rollout(): returns (traj (H, Nc, n),
+    fv (Nc,))."""
+    cand = np.asarray(cand, np.float64)
+    Nc, S, _ = cand.shape
+    if S != 1:
+        raise ValueError("lifted rollouts hold each candidate's input over the horizon (one segment)")
+    K = np.asarray(K, np.float64)
+    cols = state_columns(sys.kind, sys.n)
+    Z = lift(sys.kind, np.tile(np.asarray(x0, np.float64).reshape(1, -1), (Nc, 1)), cand[:, 0, :])
+    traj = np.full((H, Nc, sys.n), np.nan)
+    fv = np.full(Nc, H + 1, dtype=np.int64)
+    alive = np.ones(Nc, dtype=bool)
+    for s in range(1, H + 1):
+        idx = np.nonzero(alive)[0] if early_exit else np.arange(Nc)
+        if idx.size == 0:
+            break
+        with np.errstate(over="ignore", invalid="ignore"):
+            Z[idx] = Z[idx] @ K
+        x = Z[idx][:, cols]
+        traj[s - 1, idx] = x
+        bad = idx[~is_safe(sys, x)]
+        newly = bad[fv[bad] == H + 1]
+        fv[newly] = s
+        alive[bad] = False
+    return traj, fv
+
+
+def tick_lifted(sys: System, K, x_t, u_h, cand: np.ndarray, H: int) -> dict:
+    """One MPMI-SC tick whose predictions come from the lifted rollout."""
+    traj, fv = rollout_lifted(sys, K, x_t, cand, H, early_exit=True)
+    out = select(sys, cand, fv, H, u_h)
+    out["fv"] = fv
+    return out
 
 
 # ----------------------------------------------------------------------------

@@ -449,3 +449,86 @@ def test_noisy_linear_rollout_closed_form():
     t0, _ = o.rollout(sys0, K, x0, cand, H, early_exit=False, noise_key=(11, 12, 13))
     t1, _ = o.rollout(o.System("linear", 4, 1, box=[], u_lo=[-1.0], u_hi=[1.0]), K, x0, cand, H, early_exit=False)
     np.testing.assert_array_equal(t0, t1)
+
+
+# ------------------------------------------- lifted (whole-horizon) form ------
+def test_lifted_fit_identity_basis_is_the_plant_with_the_input_held():
+    """With psi = [x; u] and the input held over a step, psi(x', u) = psi(x, u) K
+    has the exact solution K = [[A^T, 0], [B^T, I]] (rows: x then u)."""
+    A, B, X, U, Y = _linear_case()
+    K, info = o.fit_lifted("linear", X, U, Y)
+    expect = np.block([[A.T, np.zeros((4, 1))], [B.T, np.eye(1)]])
+    np.testing.assert_allclose(K, expect, rtol=0, atol=1e-11)
+    assert np.all(info["resid_rms"] < 1e-12)
+
+
+@pytest.mark.parametrize("seed", [11, 13, 17])
+def test_lifted_rollout_is_exact_for_a_linear_plant_in_the_quadratic_basis(seed):
+    """The span of 1, w and all degree-2 monomials of w = [x; u] is closed under
+    x' = A x + B u with u held (each product of two affine forms is again in
+    the span), so the fitted lifted operator is exact and its rollout follows
+    the closed form A^s x0 + sum_{j<s} A^j B u for 30 steps."""
+    A, B, X, U, Y = _linear_case(seed)
+    K, info = o.fit_lifted("balance_bot", X, U, Y)
+    assert np.all(info["resid_rms"] < 1e-12)
+    sysb = o.System("balance_bot", 4, 1, box=[], u_lo=[-1.0], u_hi=[1.0])
+    x0 = np.array([0.3, -0.2, 0.5, 0.1])
+    cand = o.with_user(o.grid_candidates(sysb, [9]), [0.25], 1)
+    H = 30
+    traj, fv = o.rollout_lifted(sysb, K, x0, cand, H, early_exit=False)
+    for s, (a, b) in enumerate(_affine_in_u(A, B, x0, H), start=1):
+        np.testing.assert_allclose(traj[s - 1], a[None, :] + np.outer(cand[:, 0, 0], b), rtol=0, atol=1e-10)
+    assert np.all(fv == H + 1)
+
+
+def test_lifted_state_columns_are_the_relift_fit(bb_model):
+    """The state columns of the lifted operator solve the same least-squares
+    problem as the re-lifting model's K (same rows, same targets x_{t+1}), so
+    they agree, and the first predicted step of both rollouts is the same."""
+    K, _, (X, U, Y) = bb_model
+    KL, _ = o.fit_lifted("balance_bot", X, U, Y)
+    cols = o.state_columns("balance_bot", 4)
+    np.testing.assert_allclose(KL[:, cols], K, rtol=0, atol=1e-9 * np.max(np.abs(K)))
+    assert list(o.state_columns("race_car", 6)) == [1, 2, 3, 4, 5, 6]
+    assert list(o.state_columns("linear", 3)) == [0, 1, 2]
+    sys = _bb()
+    x0 = synth.balance_bot_states(1, seed=4)[0]
+    cand = o.with_user(o.grid_candidates(sys, [50]), [1.0], 1)
+    t1, _ = o.rollout(sys, K, x0, cand, 1, early_exit=False)
+    t2, _ = o.rollout_lifted(sys, KL, x0, cand, 1, early_exit=False)
+    np.testing.assert_allclose(t2, t1, rtol=0, atol=1e-9)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_lifted_tick_brute_force(bb_model, seed):
+    """Tiny lifted ticks against a candidate-by-candidate evaluation: z = psi(x0,
+    u) as a vector, z <- z K per step, state read off the state coordinates,
+    box checks, then the first safe candidate in (cost, index) order."""
+    _, _, (X, U, Y) = bb_model
+    KL, _ = o.fit_lifted("balance_bot", X, U, Y)
+    rng = np.random.default_rng(300 + seed)
+    sys = _bb(theta=0.15, p=0.6)
+    H = int(rng.integers(2, 9))
+    N = int(rng.integers(4, 16))
+    x0 = np.array([rng.uniform(-0.3, 0.3), rng.uniform(-1, 1), rng.uniform(-0.1, 0.1), rng.uniform(-1, 1)])
+    u_h = rng.uniform(-5, 5, size=1)
+    cand = o.with_user(o.uniform_candidates(sys, N, 1, seed, 0, 0), u_h, 1)
+    res = o.tick_lifted(sys, KL, x0, u_h, cand, H)
+    fvs, costs = [], []
+    for i in range(N + 1):
+        u = cand[i, 0, 0]
+        w = [x0[0], x0[1], x0[2], x0[3], u]
+        z = np.array([1.0] + w + [w[k] * w[l] for k in range(5) for l in range(k, 5)])
+        first = H + 1
+        for s in range(1, H + 1):
+            z = z @ KL
+            p, th = z[1], z[3]
+            if first == H + 1 and not (abs(th) < 0.15 and abs(p) < 0.6):
+                first = s
+        fvs.append(first)
+        costs.append(((u - u_h[0]) / 5.0) ** 2)
+    order = sorted(range(N + 1), key=lambda i: (costs[i], i))
+    safe = [i for i in order if fvs[i] == H + 1]
+    expect = safe[0] if safe else sorted(range(N + 1), key=lambda i: (-fvs[i], costs[i], i))[0]
+    np.testing.assert_array_equal(res["fv"], fvs)
+    assert res["idx"] == expect
