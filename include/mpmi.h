@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define MPMI_ABI_VERSION 3
+#define MPMI_ABI_VERSION 4
 
 /* Size limits (checked on the host). */
 #define MPMI_MAX_STATE 8      /* n */
@@ -263,6 +263,71 @@ mpmi_status mpmi_tick(mpmi_ctx ctx, const void* model, const mpmi_tick_desc* des
                       const float* x_t, const float* u_user, const float* cand,
                       mpmi_selection* out, int16_t* first_violation, float* traj,
                       int64_t traj_ld, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Lifted whole-horizon form (Sec. IV-A: in the Koopman representation a
+ * prediction step is one matrix-vector product and a batch of trajectories one
+ * matrix-matrix product).  Instead of re-lifting the predicted state at every
+ * step, a candidate's lifted state z = psi(x_t, u) advances by z <- z K with
+ * the full lifted operator K (D x D, row f = feature f), and the predicted
+ * state is read off z's state coordinates (features state_feat0 ..
+ * state_feat0 + n - 1: 0 for LINEAR, 1 otherwise).  Inputs are held over the
+ * horizon (one segment).  The predictions differ from the re-lifting model's
+ * from the second step on; the safety check, cost and selection are those of
+ * mpmi_tick.
+ * ------------------------------------------------------------------------- */
+
+/* Fits the lifted operator: min || Psi_s K_s - Psi' ||^2 + ridge || K_s ||^2
+ * over transitions (X[t], U[t]) -> Y[t], with Psi' rows psi(Y[t], U[t]) (the
+ * input held over the step) and the scaling and FP64 solver of koopman_fit;
+ * K_out device FP64 [D][D].  Its state columns solve koopman_fit's problem.
+ * Synchronous; errors as koopman_fit.                                       */
+mpmi_status koopman_fit_lifted(mpmi_ctx ctx, const mpmi_system* sys /* host */, const double* X, const double* U,
+                               const double* Y, int64_t T, double ridge, double* K_out, double* cond_out /* host */,
+                               void* stream);
+
+/* Bytes of a packed lifted model for horizons up to h_max (0 if h_max is out
+ * of 1..MPMI_MAX_HORIZON).                                                 */
+size_t mpmi_lifted_bytes(int32_t h_max);
+
+/* The factorisation the lifted tick runs on (host only, no device needed):
+ * every feature is psi_f(x, u) = g[feat_g[f]](u) * phi[feat_phi[f]](x), with
+ *   LINEAR       phi = [1, x_0 .. x_{n-1}]                  g = [1, u_0 .. u_{m-1}]
+ *   BALANCE_BOT  phi = [1, x_0..x_3, x_k x_l (k <= l < 4)]  g = [1, u, u^2]
+ *   RACE_CAR     phi = [1, x_0..x_5, x_k x_l (k <= l < 6), sin psi, cos psi,
+ *                       sin psi (vx, vy, r), cos psi (vx, vy, r)]
+ *                g = [1, delta, a, delta^2, delta a, a^2, sin delta, cos delta,
+ *                     a sin delta]
+ * (products k outer, l inner).  feat_g, feat_phi: host [D]; *n_phi, *n_g
+ * receive the lengths of phi and g.  MPMI_EINVAL for an invalid basis/size. */
+mpmi_status mpmi_lifted_layout(int32_t basis, int32_t n_state, int32_t n_input, int32_t* feat_g /* host */,
+                               int32_t* feat_phi /* host */, int32_t* n_phi /* host */, int32_t* n_g /* host */);
+
+/* Packs a lifted model for horizons up to h_max from a model packed by
+ * mpmi_model_pack (its system, safety set and input box) and the lifted
+ * operator K_full (device FP64 [D][D]) into `lifted` (device,
+ * mpmi_lifted_bytes(h_max) bytes, 256-byte aligned).  With the input held,
+ * x_s[j](u) = sum_k g_k(u) Q_s[k][j], Q_s[k][j] = sum_r P_s[k][j][r] phi_r(x_t),
+ * P_s[k][j][r] = sum over features f with (feat_g, feat_phi) = (k, r) of
+ * (K^s)[f][state_feat0 + j]; the powers and P are formed here in FP64 on the
+ * host and stored in FP32.  Synchronous.  MPMI_EUNSUPPORTED when more than
+ * four state components are constrained.  The lifted blob also holds the
+ * per-tick table Q: lifted ticks on one blob must be ordered on one stream.  */
+mpmi_status mpmi_lifted_pack(mpmi_ctx ctx, const void* model, const double* K_full, int32_t h_max, void* lifted,
+                             void* stream);
+
+/* One tick with lifted predictions (Alg. 2 with Sec. IV-A's matrix-product
+ * prediction): a prologue launch forms Q for x_t, then one launch evaluates
+ * every candidate's horizon as a product [candidates x g] by [g x H * slots]
+ * on the FP32 matrix cores with the safety check on each output tile, the
+ * first violation, and the selection of mpmi_tick.  desc as for mpmi_tick
+ * with n_seg 1, precision FP32, block 0 or 256, lanes_per_cand 0 or 1,
+ * horizon <= the blob's h_max.  Optional first_violation [N+1] and traj
+ * [H][n][traj_ld] (every state up to a candidate's first violation is
+ * written; some later ones may be).                                         */
+mpmi_status mpmi_tick_lifted(mpmi_ctx ctx, void* lifted, const mpmi_tick_desc* desc /* host */, const float* x_t,
+                             const float* u_user, const float* cand, mpmi_selection* out, int16_t* first_violation,
+                             float* traj, int64_t traj_ld, void* stream);
 
 /* Tick autotuner: times `reps` ticks of *desc for every launch shape in the
  * library's search space (block 64..512, lanes_per_cand 1, 2, 4, 8; FP32 only)

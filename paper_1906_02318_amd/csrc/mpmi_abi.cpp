@@ -21,6 +21,11 @@ struct mpmi_ctx_s {
   void* fit_work = nullptr;    // fit partial sums, totals and info
   void* recheck = nullptr;     // BF16X3 recheck list (count + indices)
   std::unordered_map<const void*, mpmi_system> models;  // packed models, by device address
+  struct Lifted {
+    mpmi_system sys;
+    int32_t h_max;
+  };
+  std::unordered_map<const void*, Lifted> lifted;      // packed lifted models, by device address
   std::string err;
 };
 
@@ -200,13 +205,112 @@ mpmi_status koopman_fit(mpmi_ctx ctx, const mpmi_system* sys, const double* X, c
   e = hipStreamSynchronize(st);
   if (e != hipSuccess) return fail(ctx, MPMI_EDEVICE, "koopman_fit: %s", hipGetErrorString(e));
   struct { int32_t status, pad; double cond; } info;
-  const size_t info_off = mpmi::fit_workspace_bytes() - 256;
+  const size_t info_off = mpmi::fit_info_offset();
   e = hipMemcpy(&info, (char*)ctx->fit_work + info_off, sizeof info, hipMemcpyDeviceToHost);
   if (e != hipSuccess) return fail(ctx, MPMI_EDEVICE, "koopman_fit readback: %s", hipGetErrorString(e));
   if (cond_out) *cond_out = info.cond;
   if (info.status != MPMI_OK)
     return fail(ctx, MPMI_ESINGULAR, "scaled Gram matrix is not numerically positive definite");
   return ok(ctx);
+}
+
+static mpmi_status validate_desc(mpmi_ctx ctx, const mpmi_system& sys, const mpmi_tick_desc* d);
+
+mpmi_status koopman_fit_lifted(mpmi_ctx ctx, const mpmi_system* sys, const double* X, const double* U,
+                               const double* Y, int64_t T, double ridge, double* K_out, double* cond_out,
+                               void* stream) {
+  if (!ctx) return MPMI_EINVAL;
+  mpmi_status s = validate_system(ctx, sys);
+  if (s != MPMI_OK) return s;
+  const int D = basis_dim(*sys);
+  if (!X || !U || !Y || !K_out) return fail(ctx, MPMI_EINVAL, "X, U, Y and K_out must be non-NULL");
+  if (T < D) return fail(ctx, MPMI_EINVAL, "T=%lld rows cannot determine D=%d features", (long long)T, D);
+  if (T > (int64_t)1 << 40) return fail(ctx, MPMI_EINVAL, "T=%lld too large", (long long)T);
+  if (!(ridge >= 0.0)) return fail(ctx, MPMI_EINVAL, "ridge must be >= 0");
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = mpmi::launch_fit_lifted(*sys, D, X, U, Y, T, ridge, K_out, ctx->fit_work, st);
+  if (e != hipSuccess) return fail(ctx, MPMI_EDEVICE, "koopman_fit_lifted launch: %s", hipGetErrorString(e));
+  e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return fail(ctx, MPMI_EDEVICE, "koopman_fit_lifted: %s", hipGetErrorString(e));
+  struct { int32_t status, pad; double cond; } info;
+  e = hipMemcpy(&info, (char*)ctx->fit_work + mpmi::fit_info_offset(), sizeof info, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return fail(ctx, MPMI_EDEVICE, "koopman_fit_lifted readback: %s", hipGetErrorString(e));
+  if (cond_out) *cond_out = info.cond;
+  if (info.status != MPMI_OK)
+    return fail(ctx, MPMI_ESINGULAR, "scaled Gram matrix is not numerically positive definite");
+  return ok(ctx);
+}
+
+size_t mpmi_lifted_bytes(int32_t h_max) {
+  if (h_max < 1 || h_max > MPMI_MAX_HORIZON) return 0;
+  return mpmi::lifted_bytes(h_max);
+}
+
+mpmi_status mpmi_lifted_layout(int32_t basis, int32_t n_state, int32_t n_input, int32_t* feat_g, int32_t* feat_phi,
+                               int32_t* n_phi, int32_t* n_g) {
+  mpmi_system s;
+  std::memset(&s, 0, sizeof s);
+  s.basis = basis;
+  s.n_state = n_state;
+  s.n_input = n_input;
+  for (int j = 0; j < n_input && j < MPMI_MAX_INPUT; ++j) s.u_hi[j] = 1.0f;
+  if (validate_system(nullptr, &s) != MPMI_OK) return MPMI_EINVAL;
+  if (!feat_g || !feat_phi || !n_phi || !n_g) return MPMI_EINVAL;
+  int a = 0, b = 0;
+  mpmi::lifted_layout(basis, n_state, n_input, basis_dim(s), feat_g, feat_phi, &a, &b);
+  *n_phi = a;
+  *n_g = b;
+  return MPMI_OK;
+}
+
+mpmi_status mpmi_lifted_pack(mpmi_ctx ctx, const void* model, const double* K_full, int32_t h_max, void* lifted,
+                             void* stream) {
+  if (!ctx) return MPMI_EINVAL;
+  mpmi_system sys;
+  mpmi_status s = model_system(ctx, model, &sys, (hipStream_t)stream);
+  if (s != MPMI_OK) return s;
+  if (!K_full || !lifted) return fail(ctx, MPMI_EINVAL, "K_full and lifted must be non-NULL");
+  if (!aligned(lifted, 256)) return fail(ctx, MPMI_EINVAL, "lifted must be 256-byte aligned");
+  if (!aligned(K_full, 8)) return fail(ctx, MPMI_EINVAL, "K_full must be 8-byte aligned");
+  if (h_max < 1 || h_max > MPMI_MAX_HORIZON)
+    return fail(ctx, MPMI_EINVAL, "h_max=%d out of 1..%d", h_max, MPMI_MAX_HORIZON);
+  hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+  if (e != hipSuccess) return fail(ctx, MPMI_EDEVICE, "mpmi_lifted_pack: %s", hipGetErrorString(e));
+  int n_safe = 0;
+  e = mpmi::lifted_pack(sys, basis_dim(sys), state_feat0(sys), model, K_full, h_max, lifted, &n_safe);
+  if (n_safe < 0)
+    return fail(ctx, MPMI_EUNSUPPORTED, "the lifted form checks at most four constrained state components");
+  if (e != hipSuccess) return fail(ctx, MPMI_EDEVICE, "mpmi_lifted_pack: %s", hipGetErrorString(e));
+  ctx->lifted[lifted] = mpmi_ctx_s::Lifted{sys, h_max};
+  return ok(ctx);
+}
+
+mpmi_status mpmi_tick_lifted(mpmi_ctx ctx, void* lifted, const mpmi_tick_desc* desc, const float* x_t,
+                             const float* u_user, const float* cand, mpmi_selection* out, int16_t* first_violation,
+                             float* traj, int64_t traj_ld, void* stream) {
+  if (!ctx) return MPMI_EINVAL;
+  if (!lifted) return fail(ctx, MPMI_EINVAL, "lifted is NULL");
+  auto it = ctx->lifted.find(lifted);
+  if (it == ctx->lifted.end())
+    return fail(ctx, MPMI_EINVAL, "lifted model %p was not packed by mpmi_lifted_pack on this context", lifted);
+  const mpmi_system& sys = it->second.sys;
+  mpmi_status s = validate_desc(ctx, sys, desc);
+  if (s != MPMI_OK) return s;
+  if (!x_t || !u_user || !out) return fail(ctx, MPMI_EINVAL, "x_t, u_user and out must be non-NULL");
+  if (desc->horizon > it->second.h_max)
+    return fail(ctx, MPMI_EINVAL, "horizon=%d beyond the lifted model's h_max=%d", desc->horizon, it->second.h_max);
+  if (desc->n_seg != 1) return fail(ctx, MPMI_EUNSUPPORTED, "lifted ticks hold each input over the horizon (n_seg 1)");
+  if (desc->precision != MPMI_PREC_FP32) return fail(ctx, MPMI_EUNSUPPORTED, "lifted ticks are FP32");
+  if (desc->block != 0 && desc->block != 256) return fail(ctx, MPMI_EUNSUPPORTED, "lifted ticks use 256-thread workgroups");
+  if (desc->lanes_per_cand > 1) return fail(ctx, MPMI_EUNSUPPORTED, "lifted ticks use one candidate per lane");
+  if (desc->gen == MPMI_GEN_EXPLICIT && desc->n_cand > 0 && !cand)
+    return fail(ctx, MPMI_EINVAL, "EXPLICIT candidates need cand");
+  if (traj && traj_ld < (int64_t)desc->n_cand + 1)
+    return fail(ctx, MPMI_EINVAL, "traj_ld=%lld below N+1=%d", (long long)traj_ld, desc->n_cand + 1);
+  void* slot = (char*)ctx->slots + (size_t)desc->loop * mpmi::slot_bytes();
+  return check_hip(ctx, mpmi::launch_tick_lifted(sys, lifted, it->second.h_max, *desc, x_t, u_user, cand, slot, out,
+                                                 first_violation, traj, traj ? traj_ld : 0, 4, (hipStream_t)stream),
+                   "mpmi_tick_lifted launch");
 }
 
 mpmi_status rollout_batch(mpmi_ctx ctx, const void* model, int32_t precision, const float* x0, const float* cand,

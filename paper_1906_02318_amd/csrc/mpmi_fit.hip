@@ -86,11 +86,14 @@ static_assert(kGaBlocks * kGbBlocks == kFitThreads - 64, "one register block per
 static_assert(MPMI_MAX_DIM % kGa == 0, "feature blocks");
 static_assert(kFitRows == 64, "wave 0 lifts one row per lane");
 
+// Right-hand sides: ny columns, either Y itself (yc0 < 0; ny = n) or, for the
+// lifted operator, features yc0 .. yc0 + ny - 1 of psi(Y_t, U_t) (the input
+// held over the step), lifted on the fly like the rows of Psi.
 __global__ void __launch_bounds__(kFitThreads)
-gram_kernel(int basis, int n, int m, int D, const double* __restrict__ X, const double* __restrict__ U,
-            const double* __restrict__ Y, long long T, double* __restrict__ part) {
+gram_kernel(int basis, int n, int m, int D, int ny, int yc0, const double* __restrict__ X,
+            const double* __restrict__ U, const double* __restrict__ Y, long long T, double* __restrict__ part) {
   __shared__ __attribute__((aligned(16))) double Z[2][kFitRows][kZStride];
-  const int C = D + n;
+  const int C = D + ny;
   const int E = D * C;
   const bool lifter = threadIdx.x < 64;
   const int blk = (int)threadIdx.x - 64;
@@ -109,8 +112,14 @@ gram_kernel(int basis, int n, int m, int D, const double* __restrict__ X, const 
     const long long r = (blockIdx.x + k * gridDim.x) * kFitRows + threadIdx.x;
     double* z = Z[buf][threadIdx.x];
     if (r < T) {
+      if (yc0 >= 0) {
+        // psi(Y_t, U_t) into the row first, its chunk moved past the D features
+        lift_row(basis, n, m, Y + r * n, U + r * m, z);
+        for (int q = 0; q < ny; ++q) z[D + q] = z[yc0 + q];
+      } else {
+        for (int q = 0; q < ny; ++q) z[D + q] = Y[r * n + q];
+      }
       lift_row(basis, n, m, X + r * n, U + r * m, z);
-      for (int q = 0; q < n; ++q) z[D + q] = Y[r * n + q];
     } else {
       for (int q = 0; q < C; ++q) z[q] = 0.0;
     }
@@ -484,28 +493,54 @@ solve_kernel(int n, int D, long long T, double ridge, const double* __restrict__
   }
 }
 
-size_t fit_workspace_bytes() {
-  const size_t E = (size_t)MPMI_MAX_DIM * kFitCols;
-  return (size_t)(kFitBlocks + 1) * E * sizeof(double) + 256;
-}
+// Workspace: partial sums, totals, the info record (256 bytes at
+// fit_info_offset()), then a [D][MPMI_MAX_STATE] chunk of the lifted solution.
+size_t fit_info_offset() { return (size_t)(kFitBlocks + 1) * MPMI_MAX_DIM * kFitCols * sizeof(double); }
+size_t fit_workspace_bytes() { return fit_info_offset() + 256 + (size_t)MPMI_MAX_DIM * MPMI_MAX_STATE * 8; }
 
-hipError_t launch_fit(const mpmi_system& sys, int dim, const double* X, const double* U, const double* Y,
-                      int64_t T, double ridge, double* K_out, void* work, hipStream_t st) {
+// One least-squares solve with ny right-hand sides (see gram_kernel).
+static hipError_t fit_columns(const mpmi_system& sys, int dim, int ny, int yc0, const double* X, const double* U,
+                              const double* Y, int64_t T, double ridge, double* K_out, void* work, hipStream_t st) {
   const int n = sys.n_state, m = sys.n_input;
-  const int E = dim * (dim + n);
+  const int E = dim * (dim + ny);
   long long ntiles = (T + kFitRows - 1) / kFitRows;
   const int nparts = (int)(ntiles < kFitBlocks ? ntiles : kFitBlocks);
   double* part = (double*)work;
   double* tot = part + (size_t)kFitBlocks * MPMI_MAX_DIM * kFitCols;
   FitInfo* info = (FitInfo*)(tot + (size_t)MPMI_MAX_DIM * kFitCols);
-  gram_kernel<<<nparts, kFitThreads, 0, st>>>(sys.basis, n, m, dim, X, U, Y, (long long)T, part);
+  gram_kernel<<<nparts, kFitThreads, 0, st>>>(sys.basis, n, m, dim, ny, yc0, X, U, Y, (long long)T, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   reduce_kernel<<<(E + kReduceElems - 1) / kReduceElems, kReduceElems * kReduceWays, 0, st>>>(nparts, E, part, tot);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  solve_kernel<<<1, kFitThreads, 0, st>>>(n, dim, (long long)T, ridge, tot, K_out, info);
+  solve_kernel<<<1, kFitThreads, 0, st>>>(ny, dim, (long long)T, ridge, tot, K_out, info);
   return hipGetLastError();
+}
+
+hipError_t launch_fit(const mpmi_system& sys, int dim, const double* X, const double* U, const double* Y,
+                      int64_t T, double ridge, double* K_out, void* work, hipStream_t st) {
+  return fit_columns(sys, dim, sys.n_state, -1, X, U, Y, T, ridge, K_out, work, st);
+}
+
+// The lifted operator K (dim x dim, targets psi(Y_t, U_t)): the same scaled
+// least-squares problem solved for MPMI_MAX_STATE target columns at a time;
+// each chunk's [dim][ny] solution goes from the workspace into its columns of
+// K_out.  Every chunk recomputes the Gram matrix (a set-up call: the cost is
+// dim / 8 fits).  The status and condition estimate left in the workspace
+// are those of the last chunk (the Gram matrix, and so both, are the same).
+hipError_t launch_fit_lifted(const mpmi_system& sys, int dim, const double* X, const double* U, const double* Y,
+                             int64_t T, double ridge, double* K_out, void* work, hipStream_t st) {
+  double* Kc = (double*)((char*)work + fit_info_offset() + 256);
+  for (int c0 = 0; c0 < dim; c0 += MPMI_MAX_STATE) {
+    const int ny = dim - c0 < MPMI_MAX_STATE ? dim - c0 : MPMI_MAX_STATE;
+    hipError_t e = fit_columns(sys, dim, ny, c0, X, U, Y, T, ridge, Kc, work, st);
+    if (e != hipSuccess) return e;
+    e = hipMemcpy2DAsync(K_out + c0, (size_t)dim * sizeof(double), Kc, (size_t)ny * sizeof(double),
+                         (size_t)ny * sizeof(double), (size_t)dim, hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace mpmi

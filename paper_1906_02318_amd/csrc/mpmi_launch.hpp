@@ -51,8 +51,24 @@ hipError_t launch_gen(const void* model, const mpmi_tick_desc& d, const float* u
 
 // Koopman fit (FP64): Gram accumulation, reduction, Cholesky solve.
 size_t fit_workspace_bytes();
+size_t fit_info_offset();  // {int32 status, int32 pad, double cond} of the last solve
 hipError_t launch_fit(const mpmi_system& sys, int dim, const double* X, const double* U, const double* Y,
                       int64_t T, double ridge, double* K_out, void* work, hipStream_t st);
+// Lifted operator (dim x dim) with targets psi(Y_t, U_t).
+hipError_t launch_fit_lifted(const mpmi_system& sys, int dim, const double* X, const double* U, const double* Y,
+                             int64_t T, double ridge, double* K_out, void* work, hipStream_t st);
+
+// Lifted whole-horizon tick (mpmi_lifted.hip).
+size_t lifted_bytes(int h_max);
+void lifted_layout(int basis, int n, int m, int D, int* feat_g, int* feat_phi, int* n_phi, int* n_g);
+// Host-side pack (synchronous); *n_safe_slots < 0 when more than four state
+// components are constrained (then nothing is written).
+hipError_t lifted_pack(const mpmi_system& sys, int D, int state_feat0, const void* model, const double* K_dev,
+                       int h_max, void* lifted, int* n_safe_slots);
+hipError_t launch_tick_lifted(const mpmi_system& sys, void* lifted, int h_max, const mpmi_tick_desc& d,
+                              const float* x_t, const float* u_user, const float* cand, void* slot,
+                              mpmi_selection* out, int16_t* fv, float* traj, long long traj_ld, int grid_per_cu,
+                              hipStream_t st);
 
 // Latency form of the tick (mpmi_split.hip).
 hipError_t launch_tick_split(const mpmi_system& sys, int split, const void* model, const mpmi_tick_desc& d,

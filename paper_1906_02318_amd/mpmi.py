@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmpmi.so")
 
 # Constants mirrored from include/mpmi.h
-ABI_VERSION = 3
+ABI_VERSION = 4
 MAX_STATE, MAX_INPUT, MAX_DIM, MAX_BOX = 8, 4, 64, 4
 MAX_HORIZON, MAX_SEGMENTS, MAX_CAND, MAX_LOOPS = 255, 8, 33554431, 4096
 OK, NO_SAFE, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED, ESINGULAR = 0, 1, -1, -2, -3, -4, -5
@@ -128,6 +128,11 @@ def library() -> ctypes.CDLL:
         "mpmi_gemm_bf16": (i32, [vp, vp, vp, i32, i32, i32, i32, i32, vp, vp]),
         "mpmi_tick_autotune": (i32, [vp, vp, ctypes.POINTER(TickDesc), vp, vp, vp, vp, i32,
                                      ctypes.POINTER(ctypes.c_float), vp]),
+        "koopman_fit_lifted": (i32, [vp, ctypes.POINTER(System), vp, vp, vp, i64, f64, vp, ctypes.POINTER(f64), vp]),
+        "mpmi_lifted_bytes": (ctypes.c_size_t, [i32]),
+        "mpmi_lifted_layout": (i32, [i32, i32, i32, vp, vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
+        "mpmi_lifted_pack": (i32, [vp, vp, vp, i32, vp, vp]),
+        "mpmi_tick_lifted": (i32, [vp, vp, ctypes.POINTER(TickDesc), vp, vp, vp, vp, vp, vp, i64, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -329,6 +334,83 @@ def koopman_fit(ctx: Context, system: System, X, U, Y, ridge: float = 0.0, strea
     ctx.check(ctx.lib.koopman_fit(ctx.handle, ctypes.byref(system), _ptr(X), _ptr(U), _ptr(Y), T, float(ridge),
                                   _ptr(K), ctypes.byref(cond), _stream(stream)))
     return K, cond.value
+
+
+def basis_dim(system: System) -> int:
+    return {BASIS_LINEAR: system.n_state + system.n_input, BASIS_BALANCE_BOT: 21, BASIS_RACE_CAR: 64}[system.basis]
+
+
+def koopman_fit_lifted(ctx: Context, system: System, X, U, Y, ridge: float = 0.0, stream=None):
+    """Lifted operator (D, D) float64 device tensor and the condition estimate."""
+    T, n = X.shape
+    for t, name in ((X, "X"), (U, "U"), (Y, "Y")):
+        _need(t, name, torch.float64, device=ctx.device)
+    if U.shape[0] != T or Y.shape != X.shape:
+        raise ValueError("X, U, Y must have T rows; Y shaped like X")
+    if n != system.n_state or U.shape[1] != system.n_input:
+        raise ValueError("X/U widths do not match the system")
+    D = basis_dim(system)
+    K = torch.empty((D, D), dtype=torch.float64, device=ctx.device)
+    cond = ctypes.c_double(0.0)
+    ctx.check(ctx.lib.koopman_fit_lifted(ctx.handle, ctypes.byref(system), _ptr(X), _ptr(U), _ptr(Y), T,
+                                         float(ridge), _ptr(K), ctypes.byref(cond), _stream(stream)))
+    return K, cond.value
+
+
+def mpmi_lifted_layout(basis: int, n: int, m: int):
+    """(feat_g, feat_phi, n_phi, n_g) of a basis (host only)."""
+    lib = library()
+    D = {BASIS_LINEAR: n + m, BASIS_BALANCE_BOT: 21, BASIS_RACE_CAR: 64}[basis]
+    fg, fp = (ctypes.c_int32 * D)(), (ctypes.c_int32 * D)()
+    a, b = ctypes.c_int32(), ctypes.c_int32()
+    st = lib.mpmi_lifted_layout(basis, n, m, fg, fp, ctypes.byref(a), ctypes.byref(b))
+    if st != OK:
+        raise MpmiError(st, "mpmi_lifted_layout failed")
+    return list(fg), list(fp), a.value, b.value
+
+
+@dataclass
+class Lifted:
+    """A packed lifted model (device blob) and the packed model it came from."""
+
+    blob: torch.Tensor
+    ptr: int
+    model: Model
+    h_max: int
+
+
+def mpmi_lifted_pack(ctx: Context, model: Model, K_full, h_max: int, stream=None) -> Lifted:
+    D = basis_dim(model.system)
+    _need(K_full, "K_full", torch.float64, D * D, device=ctx.device)
+    nbytes = int(ctx.lib.mpmi_lifted_bytes(h_max))
+    if nbytes == 0:
+        raise ValueError(f"h_max={h_max} out of range")
+    blob = torch.empty(nbytes + 256, dtype=torch.uint8, device=ctx.device)
+    ptr = (blob.data_ptr() + 255) // 256 * 256
+    ctx.check(ctx.lib.mpmi_lifted_pack(ctx.handle, ctypes.c_void_p(model.ptr), _ptr(K_full), h_max,
+                                       ctypes.c_void_p(ptr), _stream(stream)))
+    return Lifted(blob=blob, ptr=ptr, model=model, h_max=h_max)
+
+
+def mpmi_tick_lifted(ctx: Context, lifted: Lifted, desc: TickDesc, x_t, u_user, cand=None, out=None,
+                     first_violation=None, traj=None, stream=None):
+    """One tick with lifted predictions; returns the selection record (uint8 device tensor, 48 B)."""
+    model = lifted.model
+    _need(x_t, "x_t", torch.float32, model.n, device=ctx.device)
+    _need(u_user, "u_user", torch.float32, model.m, device=ctx.device)
+    Nc = desc.n_cand + 1
+    if cand is not None:
+        _need(cand, "cand", torch.float32, model.m * desc.n_cand, device=ctx.device)
+    if first_violation is not None:
+        _need(first_violation, "first_violation", torch.int16, Nc, device=ctx.device)
+    ld = 0 if traj is None else _traj_stride(traj, "traj", desc.horizon, model.n, Nc, ctx.device)
+    if out is None:
+        out = torch.empty(SELECTION_BYTES, dtype=torch.uint8, device=ctx.device)
+    _need(out, "out", torch.uint8, SELECTION_BYTES, device=ctx.device)
+    ctx.check(ctx.lib.mpmi_tick_lifted(ctx.handle, ctypes.c_void_p(lifted.ptr), ctypes.byref(desc), _ptr(x_t),
+                                       _ptr(u_user), _ptr(cand), _ptr(out), _ptr(first_violation), _ptr(traj), ld,
+                                       _stream(stream)))
+    return out
 
 
 def rollout_batch(ctx: Context, model: Model, x0, cand, H: int, traj=None, precision=PREC_FP32, stream=None):

@@ -122,6 +122,13 @@ def check_tick(sys: o.System, K, x_t, u_h, cand64: np.ndarray, H: int, sel: dict
     return judge(sys, cand64, H, u_h, traj, fv_o, sel, fv_gpu, eps, label)
 
 
+def check_tick_lifted(sys: o.System, K_full, x_t, u_h, cand64: np.ndarray, H: int, sel: dict, fv_gpu: np.ndarray,
+                      eps, label: str = "") -> dict:
+    """check_tick for the lifted whole-horizon form (oracle: rollout_lifted)."""
+    traj, fv_o = o.rollout_lifted(sys, K_full, x_t, cand64, H, early_exit=False)
+    return judge(sys, cand64, H, u_h, traj, fv_o, sel, fv_gpu, eps, label)
+
+
 def agreed(kinds: dict) -> int:
     return kinds.get("identical", 0) + kinds.get("equal_cost", 0)
 

@@ -78,3 +78,33 @@ def test_missing_library_fails_loudly(monkeypatch):
     monkeypatch.setattr(mpmi, "LIB_PATH", "/nonexistent/libmpmi.so")
     with pytest.raises(RuntimeError, match="missing"):
         mpmi.library()
+
+
+@pytest.mark.parametrize("basis,n,m", [(2, 6, 2), (1, 4, 1), (0, 5, 3)])
+def test_lifted_layout_factorises_the_basis(basis, n, m):
+    """The lifted tick's table: psi_f(x, u) = g[feat_g[f]](u) phi[feat_phi[f]](x),
+    with phi and g as the header states them, equals the oracle's basis at
+    random points."""
+    import numpy as np
+
+    from oracle import mpmi_oracle as o
+    from paper_1906_02318_amd import mpmi
+    fg, fp, n_phi, n_g = mpmi.mpmi_lifted_layout(basis, n, m)
+    kind = {0: "linear", 1: "balance_bot", 2: "race_car"}[basis]
+    rng = np.random.default_rng(basis)
+    for _ in range(5):
+        x, u = rng.normal(size=n), rng.normal(size=m)
+        if kind == "linear":
+            phi, g = [1.0, *x], [1.0, *u]
+        elif kind == "balance_bot":
+            phi = [1.0, *x] + [x[k] * x[l] for k in range(4) for l in range(k, 4)]
+            g = [1.0, u[0], u[0] ** 2]
+        else:
+            sp, cp = np.sin(x[2]), np.cos(x[2])
+            phi = [1.0, *x] + [x[k] * x[l] for k in range(6) for l in range(k, 6)] + \
+                [sp, cp, sp * x[3], sp * x[4], sp * x[5], cp * x[3], cp * x[4], cp * x[5]]
+            d, a = u
+            g = [1.0, d, a, d * d, d * a, a * a, np.sin(d), np.cos(d), a * np.sin(d)]
+        assert (n_phi, n_g) == (len(phi), len(g))
+        psi = o.lift(kind, x[None], u[None])[0]
+        np.testing.assert_allclose([g[fg[f]] * phi[fp[f]] for f in range(psi.size)], psi, rtol=1e-14, atol=1e-14)

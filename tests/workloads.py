@@ -72,3 +72,17 @@ def rc_floors():
     X = rc_model()[2][0]
     s = X.std(axis=0)
     return np.array([3.0, 3.0, s[2], s[3], RC_VY, s[5]])
+
+
+@functools.lru_cache(maxsize=None)
+def bb_lifted_model():
+    """Oracle-fitted FP64 lifted operator (21 x 21) of the cart-pole data."""
+    X, U, Y = bb_model()[2]
+    return o.fit_lifted("balance_bot", X, U, Y)
+
+
+@functools.lru_cache(maxsize=None)
+def rc_lifted_model():
+    """Oracle-fitted FP64 lifted operator (64 x 64) of the bicycle data."""
+    X, U, Y = rc_model()[2]
+    return o.fit_lifted("race_car", X, U, Y)
