@@ -87,7 +87,9 @@ enum { MPMI_BASIS_LINEAR = 0, MPMI_BASIS_BALANCE_BOT = 1, MPMI_BASIS_RACE_CAR = 
  *          hi/lo BF16 splits of the features and of (K - E) in residual form
  *          x' = x + psi^T (K - E), FP32 accumulation; every candidate whose
  *          margin comes within the system's eps band of a constraint is then
- *          re-rolled in FP32 and the FP32 verdict is kept.                  */
+ *          re-rolled in FP32 and the FP32 verdict is kept.  Race-car models,
+ *          ticks of at most 2^22 candidates (the recheck list holds them all;
+ *          larger ticks return MPMI_EUNSUPPORTED).                          */
 enum { MPMI_PREC_FP32 = 0, MPMI_PREC_BF16X3 = 1 };
 
 /* How a tick obtains candidates 1..N (candidate 0 is always the user's input,
@@ -221,7 +223,9 @@ mpmi_status koopman_fit(mpmi_ctx ctx, const mpmi_system* sys /* host */,
  * (Alg. 2 prediction loop; Fig. 1's cloud of trajectories): from x0 [n],
  * x_s = psi(x_{s-1}, u_c(seg(s)))^T K for s = 1..H.  cand [S][m][Nc];
  * traj [H][n][traj_ld] receives x_1..x_H (candidate fastest; row stride
- * traj_ld >= Nc floats, columns past Nc untouched).  FP32 only.
+ * traj_ld >= Nc floats, columns past Nc untouched).  precision FP32, or
+ * BF16X3 for race-car models (the BF16X3 tick's step, its states stored
+ * unchecked: the precision's own rollout error can be measured).
  *
  * Trajectory rows and write rate (this call, mpmi_tick, safe_mask): rows
  * that start on 256-byte boundaries (traj 256-byte aligned, traj_ld a

@@ -316,8 +316,8 @@ mpmi_status mpmi_tick_lifted(mpmi_ctx ctx, void* lifted, const mpmi_tick_desc* d
 mpmi_status rollout_batch(mpmi_ctx ctx, const void* model, int32_t precision, const float* x0, const float* cand,
                           int32_t Nc, int32_t S, int32_t H, float* traj, int64_t traj_ld, void* stream) {
   if (!ctx) return MPMI_EINVAL;
-  if (precision != MPMI_PREC_FP32)
-    return fail(ctx, MPMI_EUNSUPPORTED, "rollout_batch stores FP32 trajectories; precision must be MPMI_PREC_FP32");
+  if (precision != MPMI_PREC_FP32 && precision != MPMI_PREC_BF16X3)
+    return fail(ctx, MPMI_EINVAL, "unknown precision %d", precision);
   if (Nc < 1 || Nc > MPMI_MAX_CAND) return fail(ctx, MPMI_EINVAL, "Nc=%d out of 1..%d", Nc, MPMI_MAX_CAND);
   if (S < 1 || S > MPMI_MAX_SEGMENTS) return fail(ctx, MPMI_EINVAL, "S=%d out of 1..%d", S, MPMI_MAX_SEGMENTS);
   if (H < 1 || H > MPMI_MAX_HORIZON) return fail(ctx, MPMI_EINVAL, "H=%d out of 1..%d", H, MPMI_MAX_HORIZON);
@@ -326,6 +326,12 @@ mpmi_status rollout_batch(mpmi_ctx ctx, const void* model, int32_t precision, co
   mpmi_system sys;
   mpmi_status s = model_system(ctx, model, &sys, (hipStream_t)stream);
   if (s != MPMI_OK) return s;
+  if (precision == MPMI_PREC_BF16X3) {
+    if (sys.basis != MPMI_BASIS_RACE_CAR)
+      return fail(ctx, MPMI_EUNSUPPORTED, "BF16X3 is implemented for race-car models");
+    return check_hip(ctx, mpmi::launch_rollout_bf16(model, Nc, S, H, x0, cand, traj, traj_ld, (hipStream_t)stream),
+                     "rollout_batch (BF16X3) launch");
+  }
   return check_hip(ctx, mpmi::launch_rollout(sys.basis, model, Nc, S, H, x0, cand, traj, traj_ld, (hipStream_t)stream),
                    "rollout_batch launch");
 }
@@ -435,6 +441,10 @@ mpmi_status mpmi_tick(mpmi_ctx ctx, const void* model, const mpmi_tick_desc* des
     if (mpmi::system_noisy(sys)) return fail(ctx, MPMI_EUNSUPPORTED, "BF16X3 ticks are noise-free");
     if (desc->block != 0 && desc->block != 256)
       return fail(ctx, MPMI_EUNSUPPORTED, "BF16X3 ticks use 256-thread workgroups");
+    if ((long long)desc->n_cand + 1 > mpmi::kRecheckCapacity)
+      return fail(ctx, MPMI_EUNSUPPORTED,
+                  "BF16X3 ticks take at most %d candidates (the FP32 recheck list holds every one)",
+                  mpmi::kRecheckCapacity);
     return check_hip(ctx, mpmi::launch_tick_bf16(sys, model, *desc, x_t, u_user, cand, slot, out, first_violation,
                                                  ctx->recheck, mpmi::kRecheckCapacity,
                                                  mpmi::device_cu_count() * 4, (hipStream_t)stream),

@@ -116,6 +116,70 @@ __device__ __forceinline__ void rc_shared_features(const float* x, float sp, flo
   for (int r = 27; r < 32; ++r) f[r] = 0.0f;
 }
 
+// B operand of the step: the 27 shared K rows (k) x 6 outputs (n) as BF16
+// hi/lo splits, zero-padded to 32 x 16.
+__device__ __forceinline__ void rc_b_operand(const float4* sK, int lane, bf16x8_t* bhi, bf16x8_t* blo) {
+  const float* Ks = reinterpret_cast<const float*>(sK) + kRcStepOff;
+  const int n = lane & 15, k0 = (lane >> 4) * 8;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int k = k0 + i;
+    const float v = (n < 6 && k < kRcStepRows) ? Ks[k * 6 + n] : 0.0f;
+    const uint16_t h = bf16_hi(v);
+    const float vh = __uint_as_float((uint32_t)h << 16);
+    const uint16_t l = bf16_hi(v - vh);
+    (*bhi)[i] = __builtin_bit_cast(__bf16, h);
+    (*blo)[i] = __builtin_bit_cast(__bf16, l);
+  }
+}
+
+// One BF16X3 prediction step of a wave (every lane takes part: the matrix
+// instructions need the whole wave): y = folded input terms (FP32) + the
+// shared-coefficient contraction on the matrix cores, for this lane's state x.
+__device__ __forceinline__ void rc_bf16x3_step(const Stepper<MPMI_BASIS_RACE_CAR>& stp, const float* x,
+                                               bf16x8_t bhi, bf16x8_t blo, uint16_t (*sAw)[64][kArow],
+                                               float (*sDw)[64], int lane, float* y) {
+  // The FP32 path's hardware sine and cosine (the recheck re-rolls with it).
+  const float sp = __sinf(x[2]), cp = __cosf(x[2]);
+  // Per-step shared-coefficient features, split into BF16 hi/lo, to LDS,
+  // eight at a time.
+  float feat[32];
+  rc_shared_features(x, sp, cp, feat);
+#pragma unroll
+  for (int k8 = 0; k8 < 4; ++k8) {
+    uint32_t h[4], l[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) split_pair(feat[k8 * 8 + 2 * i], feat[k8 * 8 + 2 * i + 1], &h[i], &l[i]);
+    *reinterpret_cast<uint4*>(&sAw[0][lane][k8 * 8]) = make_uint4(h[0], h[1], h[2], h[3]);
+    *reinterpret_cast<uint4*>(&sAw[1][lane][k8 * 8]) = make_uint4(l[0], l[1], l[2], l[3]);
+  }
+  __builtin_amdgcn_wave_barrier();
+  // Four groups of 16 candidates: D = Ahi Bhi + Ahi Blo + Alo Bhi.  Lane
+  // (col, quarter) holds outputs col of four consecutive candidates.
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb) {
+    const int row = rb * 16 + (lane & 15), k0 = (lane >> 4) * 8;
+    const bf16x8_t ah = *reinterpret_cast<const bf16x8_t*>(&sAw[0][row][k0]);
+    const bf16x8_t al = *reinterpret_cast<const bf16x8_t*>(&sAw[1][row][k0]);
+    f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bhi, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, blo, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bhi, acc, 0, 0, 0);
+    const int col = lane & 15;
+    if (col < 6)
+      *reinterpret_cast<float4*>(&sDw[col][rb * 16 + (lane >> 4) * 4]) = make_float4(acc[0], acc[1], acc[2], acc[3]);
+  }
+  __builtin_amdgcn_wave_barrier();
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    float v = fmaf(stp.Tc[j], cp, fmaf(stp.Ts[j], sp, stp.cu[j]));
+#pragma unroll
+    for (int k = 0; k < 6; ++k) v = fmaf(stp.L[k][j], x[k], v);
+    y[j] = v + sDw[j][lane];
+  }
+  __builtin_amdgcn_wave_barrier();
+}
+
 template <int DEG>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 4)))
 tick_bf16_race_car_kernel(const ModelDev* __restrict__ md, GenParams gp, int H, const float* __restrict__ x_t,
@@ -131,22 +195,8 @@ tick_bf16_race_car_kernel(const ModelDev* __restrict__ md, GenParams gp, int H, 
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   const bool valid = c < Nc;
 
-  // B operand: the 27 shared K rows (k) x 6 outputs (n), zero-padded to 32 x 16.
   bf16x8_t bhi, blo;
-  {
-    const float* Ks = reinterpret_cast<const float*>(sK) + kRcStepOff;
-    const int n = lane & 15, k0 = (lane >> 4) * 8;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int k = k0 + i;
-      const float v = (n < 6 && k < kRcStepRows) ? Ks[k * 6 + n] : 0.0f;
-      const uint16_t h = bf16_hi(v);
-      const float vh = __uint_as_float((uint32_t)h << 16);
-      const uint16_t l = bf16_hi(v - vh);
-      bhi[i] = __builtin_bit_cast(__bf16, h);
-      blo[i] = __builtin_bit_cast(__bf16, l);
-    }
-  }
+  rc_b_operand(sK, lane, &bhi, &blo);
 
   float x[6], u[2], u0[2];
 #pragma unroll
@@ -172,46 +222,8 @@ tick_bf16_race_car_kernel(const ModelDev* __restrict__ md, GenParams gp, int H, 
       for (int j = 0; j < 2; ++j) u[j] = valid ? cand_value(gp, md, cand, u_user, c, gcur, j) : 0.0f;
       stp.set_input(md, sK, u);
     }
-    // The FP32 path's hardware sine and cosine (the recheck re-rolls with it).
-    const float sp = __sinf(x[2]), cp = __cosf(x[2]);
-    // Per-step shared-coefficient features, split into BF16 hi/lo, to LDS,
-    // eight at a time.
-    float feat[32];
-    rc_shared_features(x, sp, cp, feat);
-#pragma unroll
-    for (int k8 = 0; k8 < 4; ++k8) {
-      uint32_t h[4], l[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) split_pair(feat[k8 * 8 + 2 * i], feat[k8 * 8 + 2 * i + 1], &h[i], &l[i]);
-      *reinterpret_cast<uint4*>(&sA[wave][0][lane][k8 * 8]) = make_uint4(h[0], h[1], h[2], h[3]);
-      *reinterpret_cast<uint4*>(&sA[wave][1][lane][k8 * 8]) = make_uint4(l[0], l[1], l[2], l[3]);
-    }
-    __builtin_amdgcn_wave_barrier();
-    // Four groups of 16 candidates: D = Ahi Bhi + Ahi Blo + Alo Bhi.  Lane
-    // (col, quarter) holds outputs col of four consecutive candidates.
-#pragma unroll
-    for (int rb = 0; rb < 4; ++rb) {
-      const int row = rb * 16 + (lane & 15), k0 = (lane >> 4) * 8;
-      const bf16x8_t ah = *reinterpret_cast<const bf16x8_t*>(&sA[wave][0][row][k0]);
-      const bf16x8_t al = *reinterpret_cast<const bf16x8_t*>(&sA[wave][1][row][k0]);
-      f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
-      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bhi, acc, 0, 0, 0);
-      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, blo, acc, 0, 0, 0);
-      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bhi, acc, 0, 0, 0);
-      const int col = lane & 15;
-      if (col < 6)
-        *reinterpret_cast<float4*>(&sD[wave][col][rb * 16 + (lane >> 4) * 4]) = make_float4(acc[0], acc[1], acc[2], acc[3]);
-    }
-    __builtin_amdgcn_wave_barrier();
     float y[6];
-#pragma unroll
-    for (int j = 0; j < 6; ++j) {
-      float v = fmaf(stp.Tc[j], cp, fmaf(stp.Ts[j], sp, stp.cu[j]));
-#pragma unroll
-      for (int k = 0; k < 6; ++k) v = fmaf(stp.L[k][j], x[k], v);
-      y[j] = v + sD[wave][j][lane];
-    }
-    __builtin_amdgcn_wave_barrier();
+    rc_bf16x3_step(stp, x, bhi, blo, sA[wave], sD[wave], lane, y);
     if (alive) {
 #pragma unroll
       for (int j = 0; j < 6; ++j) x[j] = y[j];
@@ -304,6 +316,54 @@ recheck_race_car_kernel(const ModelDev* __restrict__ md, GenParams gp, int H, co
     rl->count = 0u;
     __threadfence();
   }
+}
+
+// Full-horizon BF16X3 rollout (rollout_batch with MPMI_PREC_BF16X3): the
+// tick's step without safety checks, every state stored.  Lanes past Nc
+// take part in the wave's matrix instructions and store nothing.
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 4)))
+rollout_bf16_race_car_kernel(const ModelDev* __restrict__ md, int Nc, int S, int H, const float* __restrict__ x0,
+                             const float* __restrict__ cand, float* __restrict__ traj, long long traj_ld) {
+  __shared__ float4 sK[kLdsKFloat4];
+  __shared__ __attribute__((aligned(16))) uint16_t sA[kWaves][2][64][kArow];
+  __shared__ __attribute__((aligned(16))) float sD[kWaves][8][64];
+  stage_K<MPMI_BASIS_RACE_CAR>(md, sK);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = c < Nc;
+  const int cc = valid ? c : Nc - 1;  // lanes past the end read a valid candidate
+  bf16x8_t bhi, blo;
+  rc_b_operand(sK, lane, &bhi, &blo);
+  float x[6], u[2];
+#pragma unroll
+  for (int j = 0; j < 6; ++j) x[j] = x0[j];
+  Stepper<MPMI_BASIS_RACE_CAR> stp;
+  int gcur = -1;
+  for (int s = 1; s <= H; ++s) {
+    const int g = ((s - 1) * S) / H;
+    if (g != gcur) {
+      gcur = g;
+#pragma unroll
+      for (int j = 0; j < 2; ++j) u[j] = cand[((size_t)g * 2 + j) * (size_t)Nc + cc];
+      stp.set_input(md, sK, u);
+    }
+    float y[6];
+    rc_bf16x3_step(stp, x, bhi, blo, sA[wave], sD[wave], lane, y);
+#pragma unroll
+    for (int j = 0; j < 6; ++j) x[j] = y[j];
+    if (valid) {
+#pragma unroll
+      for (int j = 0; j < 6; ++j)
+        __builtin_nontemporal_store(x[j], &traj[((size_t)(s - 1) * 6 + j) * (size_t)traj_ld + c]);
+    }
+  }
+}
+
+hipError_t launch_rollout_bf16(const void* model, int Nc, int S, int H, const float* x0, const float* cand,
+                               float* traj, long long traj_ld, hipStream_t st) {
+  const unsigned grid = (unsigned)(((long long)Nc + 255) / 256);
+  rollout_bf16_race_car_kernel<<<grid, 256, 0, st>>>((const ModelDev*)model, Nc, S, H, x0, cand, traj, traj_ld);
+  return hipGetLastError();
 }
 
 size_t recheck_bytes(int capacity) { return sizeof(RecheckList) + sizeof(int) * (size_t)capacity; }

@@ -78,6 +78,8 @@ hipError_t launch_tick_split(const mpmi_system& sys, int split, const void* mode
 // BF16X3 race-car tick + FP32 recheck (mpmi_bf16.hip).
 constexpr int kRecheckCapacity = 1 << 22;
 size_t recheck_bytes(int capacity);
+hipError_t launch_rollout_bf16(const void* model, int Nc, int S, int H, const float* x0, const float* cand,
+                               float* traj, long long traj_ld, hipStream_t st);
 hipError_t launch_tick_bf16(const mpmi_system& sys, const void* model, const mpmi_tick_desc& d, const float* x_t,
                             const float* u_user, const float* cand, void* slot, mpmi_selection* out, int16_t* fv,
                             void* recheck, int capacity, int recheck_grid, hipStream_t st);

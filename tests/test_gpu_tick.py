@@ -823,3 +823,50 @@ def test_fp32_fma_rate_diagnostic(ctx):
     r = mpmi.mpmi_fp32_fma_rate(ctx)
     log(f"[diag] FP32 FMA rate {r:.1f} TFLOP/s")
     assert 40.0 < r < 80.0
+
+
+def test_bf16x3_rollout_state_error(ctx, rc):
+    """BF16X3 predictions (rollout_batch with MPMI_PREC_BF16X3: the tick's
+    step with every state stored, unchecked) against the FP64 oracle over the
+    full horizon, race car, H = 60: within 2e-2 relative (floors as for FP32).
+    The error of the constraint margins is what the FP32 recheck band covers:
+    it stays below that band (0.02 m on the track, 0.02 m/s on v_y)."""
+    so, model, K = rc
+    H, N = 60, 4095
+    xs = synth.race_car_states(4, W.rc_track(), seed=21)
+    floors = W.rc_floors()
+    worst, worst_fp32, worst_margin = 0.0, 0.0, 0.0
+    for t, x0 in enumerate(xs):
+        x0 = W.f32(x0)
+        cand = W.f32(o.with_user(o.uniform_candidates(so, N, 1, 41, t, 0), [0.0, 0.0], 1))
+        c_dev = dev(to_sm(cand), torch.float32)
+        tb = mpmi.rollout_batch(ctx, model, dev(x0, torch.float32), c_dev, H, precision=mpmi.PREC_BF16X3)
+        tf = mpmi.rollout_batch(ctx, model, dev(x0, torch.float32), c_dev, H)
+        ref, _ = o.rollout(so, K, x0, cand, H, early_exit=False)
+        got = tb.cpu().numpy().transpose(0, 2, 1).astype(np.float64)
+        worst = max(worst, rollout_rel_err(got, ref, floors, comp_axis=2))
+        worst_fp32 = max(worst_fp32, rollout_rel_err(tf.cpu().numpy().transpose(0, 2, 1), ref, floors, comp_axis=2))
+        with np.errstate(invalid="ignore"):
+            mg = o.margins(so, got.reshape(-1, 6))
+            mr = o.margins(so, ref.reshape(-1, 6))
+        keep = np.isfinite(mr).all(axis=1) & (np.abs(mr) < 10.0).all(axis=1)
+        worst_margin = max(worst_margin, float(np.max(np.abs(mg[keep] - mr[keep]))))
+    log(f"[bf16x3 states] race car H=60: max relative error vs FP64 {worst:.3e} (FP32 path {worst_fp32:.3e}); "
+        f"max margin error {worst_margin:.3e} (recheck band 0.02)")
+    assert worst <= 2e-2
+    assert worst_margin < 0.02
+
+
+def test_bf16x3_tick_size_limit(ctx, rc):
+    """A BF16X3 tick takes at most 2^22 candidates, so that every
+    near-boundary candidate fits the FP32 recheck list; larger ones are
+    refused before anything is enqueued."""
+    so, model, K = rc
+    x, u = dev(W.f32(synth.race_car_states(1, W.rc_track(), seed=3)[0]), torch.float32), dev([0.0, 0.0], torch.float32)
+    big = mpmi.tick_desc(1 << 22, 10, gen=mpmi.GEN_UNIFORM, precision=mpmi.PREC_BF16X3)
+    with pytest.raises(mpmi.MpmiError) as e:
+        mpmi.mpmi_tick(ctx, model, big, x, u)
+    assert e.value.status == mpmi.EUNSUPPORTED
+    ok = mpmi.tick_desc((1 << 22) - 1, 2, gen=mpmi.GEN_UNIFORM, precision=mpmi.PREC_BF16X3)
+    sel = mpmi.decode_selection(mpmi.mpmi_tick(ctx, model, ok, x, u))
+    assert sel["n_cand"] == 1 << 22
