@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define MPMI_ABI_VERSION 4
+#define MPMI_ABI_VERSION 5
 
 /* Size limits (checked on the host). */
 #define MPMI_MAX_STATE 8      /* n */
@@ -56,6 +56,7 @@ extern "C" {
 #define MPMI_MAX_SEGMENTS 8   /* S, piecewise-constant input segments */
 #define MPMI_MAX_CAND 33554431 /* Nc = N + 1 <= 2^25 - 1 */
 #define MPMI_MAX_LOOPS 4096   /* selection slots per context */
+#define MPMI_MAX_ATOMS 32     /* atoms of a custom basis */
 
 typedef int32_t mpmi_status;
 enum {
@@ -79,7 +80,10 @@ enum {
  *                sin psi * (vx, vy, r, a), cos psi * (vx, vy, r, a),
  *                sin delta * (vx, vy, r), cos delta * (vx, vy, r),
  *                a sin delta]                               D = 64        */
-enum { MPMI_BASIS_LINEAR = 0, MPMI_BASIS_BALANCE_BOT = 1, MPMI_BASIS_RACE_CAR = 2 };
+enum { MPMI_BASIS_LINEAR = 0, MPMI_BASIS_BALANCE_BOT = 1, MPMI_BASIS_RACE_CAR = 2, MPMI_BASIS_CUSTOM = 3 };
+
+/* Atoms of a custom basis (functions of one component of w = [x; u]). */
+enum { MPMI_ATOM_ONE = 0, MPMI_ATOM_VAR = 1, MPMI_ATOM_SIN = 2, MPMI_ATOM_COS = 3 };
 
 /* Arithmetic of the prediction step.
  *  FP32    states, features and K in FP32, FP32 accumulation.
@@ -143,7 +147,30 @@ typedef struct mpmi_system {
   float u_lo[4];          /* input box; cost divides input j by (u_hi-u_lo)/2 */
   float u_hi[4];
   float noise_sigma[8];   /* per state component, >= 0 */
+  /* MPMI_BASIS_CUSTOM only (a basis given as data, Sec. IV-A's functions of
+   * state chosen by the caller, e.g. by basis selection): feature f is
+   * psi_f(w) = atom[feat_a[f]](w) * atom[feat_b[f]](w), atom q being 1
+   * (ONE), w[atom_var[q]] (VAR), sin w[atom_var[q]] (SIN) or cos w[atom_var[q]]
+   * (COS), with w = [x; u].  Ignored for the fixed families.               */
+  int32_t n_atoms;        /* 1..MPMI_MAX_ATOMS */
+  int32_t dim;            /* D, 1..MPMI_MAX_DIM */
+  int8_t atom_kind[MPMI_MAX_ATOMS];
+  int8_t atom_var[MPMI_MAX_ATOMS];  /* 0 .. n + m - 1 */
+  int8_t feat_a[MPMI_MAX_DIM];      /* 0 .. n_atoms - 1 */
+  int8_t feat_b[MPMI_MAX_DIM];
 } mpmi_system;
+
+/* Fills the custom-basis fields of *sys with the atoms and features of a
+ * fixed family (LINEAR with n_state, n_input; BALANCE_BOT; RACE_CAR), and
+ * sets sys->basis = MPMI_BASIS_CUSTOM, n_state and n_input; other fields are
+ * left as they are.  Host only.  MPMI_EINVAL for an unknown family or sizes. */
+int32_t mpmi_basis_describe(int32_t family, int32_t n_state, int32_t n_input, mpmi_system* sys /* host */);
+
+/* The fixed family whose features, in order, are those of a custom basis
+ * (its fast kernels compute the same functions), or MPMI_BASIS_CUSTOM if
+ * none is; for a fixed family, that family.  Host only.  A caller switches
+ * to the fast path by setting sys->basis to the result.                     */
+int32_t mpmi_basis_match(const mpmi_system* sys /* host */);
 
 /* Result of one tick (device memory, written by the library).
  * Selection (Alg. 2 selection step, Sec. IV-D): among candidates whose H

@@ -89,7 +89,39 @@ class System:
         return 0.5 * (self.u_hi - self.u_lo)
 
 
-def basis_dim(kind: str, n: int, m: int) -> int:
+@dataclass(frozen=True)
+class Basis:
+    """A basis given as data (Sec. IV-A: the functions of state the Koopman
+    operator acts on, here chosen by the caller): atoms are (kind, k) with
+    kind 'one', 'var', 'sin' or 'cos' of component k of w = [x; u]; feature f
+    is the product of atoms feats[f][0] and feats[f][1]."""
+
+    atoms: tuple
+    feats: tuple
+
+    def atom_values(self, W: np.ndarray) -> list:
+        out = []
+        for kind, k in self.atoms:
+            if kind == "one":
+                out.append(np.ones(W.shape[0]))
+            elif kind == "var":
+                out.append(W[:, k])
+            elif kind == "sin":
+                out.append(np.sin(W[:, k]))
+            elif kind == "cos":
+                out.append(np.cos(W[:, k]))
+            else:
+                raise ValueError(kind)
+        return out
+
+    def lift(self, W: np.ndarray) -> np.ndarray:
+        at = self.atom_values(W)
+        return np.stack([at[a] * at[b] for a, b in self.feats], axis=1)
+
+
+def basis_dim(kind, n: int, m: int) -> int:
+    if isinstance(kind, Basis):
+        return len(kind.feats)
     if kind == "linear":
         return n + m
     if kind == "balance_bot":
@@ -113,6 +145,8 @@ def lift(kind: str, X: np.ndarray, U: np.ndarray) -> np.ndarray:
         U = U[None]
     W = np.concatenate([X, U], axis=1)  # w = [x; u]
     T = W.shape[0]
+    if isinstance(kind, Basis):
+        return kind.lift(W)
     if kind == "linear":
         return W.copy()
     if kind == "balance_bot":
@@ -179,6 +213,18 @@ def state_columns(kind: str, n: int) -> np.ndarray:
     """Features of psi that are the state components themselves (psi holds w
     = [x; u] linearly): linear -> 0..n-1, balance bot and race car -> 1..n
     (after the constant feature)."""
+    if isinstance(kind, Basis):
+        # the features that are w_j itself (VAR j times ONE, either order)
+        cols = []
+        for j in range(n):
+            hit = [f for f, (a, b) in enumerate(kind.feats)
+                   if {kind.atoms[a], kind.atoms[b]} in ({("var", j), ("one", 0)},)
+                   or (kind.atoms[a] == ("var", j) and kind.atoms[b][0] == "one")
+                   or (kind.atoms[b] == ("var", j) and kind.atoms[a][0] == "one")]
+            if not hit:
+                raise ValueError(f"the basis has no feature equal to x_{j}")
+            cols.append(hit[0])
+        return np.array(cols)
     first = 0 if kind == "linear" else 1
     return np.arange(first, first + n)
 

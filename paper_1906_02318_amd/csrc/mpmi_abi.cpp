@@ -60,8 +60,58 @@ int basis_dim(const mpmi_system& s) {
     case MPMI_BASIS_LINEAR: return s.n_state + s.n_input;
     case MPMI_BASIS_BALANCE_BOT: return 21;
     case MPMI_BASIS_RACE_CAR: return 64;
+    case MPMI_BASIS_CUSTOM: return s.dim;
     default: return -1;
   }
+}
+
+// Atoms and features of a fixed family, in its feature order (the custom
+// form of the same functions).  Returns false for an unknown family.
+bool family_descriptor(int family, int n, int m, mpmi_system* s) {
+  int na = 0, d = 0;
+  auto atom = [&](int kind, int var) { s->atom_kind[na] = (int8_t)kind; s->atom_var[na] = (int8_t)var; return na++; };
+  auto feat = [&](int a, int b) { s->feat_a[d] = (int8_t)a; s->feat_b[d] = (int8_t)b; ++d; };
+  if (family == MPMI_BASIS_LINEAR) {
+    if (n < 1 || n > MPMI_MAX_STATE || m < 1 || m > MPMI_MAX_INPUT) return false;
+    const int one = atom(MPMI_ATOM_ONE, 0);
+    for (int k = 0; k < n + m; ++k) feat(atom(MPMI_ATOM_VAR, k), one);
+  } else if (family == MPMI_BASIS_BALANCE_BOT || family == MPMI_BASIS_RACE_CAR) {
+    const int nw = family == MPMI_BASIS_BALANCE_BOT ? 5 : 8;
+    n = family == MPMI_BASIS_BALANCE_BOT ? 4 : 6;
+    m = nw - n;
+    const int one = atom(MPMI_ATOM_ONE, 0);
+    int w[8];
+    for (int k = 0; k < nw; ++k) w[k] = atom(MPMI_ATOM_VAR, k);
+    feat(one, one);
+    for (int k = 0; k < nw; ++k) feat(w[k], one);
+    for (int k = 0; k < nw; ++k)
+      for (int l = k; l < nw; ++l) feat(w[k], w[l]);
+    if (family == MPMI_BASIS_RACE_CAR) {
+      const int sp = atom(MPMI_ATOM_SIN, 2), cp = atom(MPMI_ATOM_COS, 2);
+      const int sd = atom(MPMI_ATOM_SIN, 6), cd = atom(MPMI_ATOM_COS, 6);
+      feat(sp, one); feat(cp, one); feat(sd, one); feat(cd, one);
+      for (int k : {3, 4, 5, 7}) feat(sp, w[k]);
+      for (int k : {3, 4, 5, 7}) feat(cp, w[k]);
+      for (int k : {3, 4, 5}) feat(sd, w[k]);
+      for (int k : {3, 4, 5}) feat(cd, w[k]);
+      feat(w[7], sd);
+    }
+  } else {
+    return false;
+  }
+  s->basis = MPMI_BASIS_CUSTOM;
+  s->n_state = n;
+  s->n_input = m;
+  s->n_atoms = na;
+  s->dim = d;
+  for (int q = na; q < MPMI_MAX_ATOMS; ++q) s->atom_kind[q] = s->atom_var[q] = 0;
+  for (int f = d; f < MPMI_MAX_DIM; ++f) s->feat_a[f] = s->feat_b[f] = 0;
+  return true;
+}
+
+// The value of atom q of s as (kind, variable) with the variable ignored for ONE.
+inline int atom_code(const mpmi_system& s, int q) {
+  return s.atom_kind[q] == MPMI_ATOM_ONE ? -1 : s.atom_kind[q] * 64 + s.atom_var[q];
 }
 
 // Index in psi of feature w_0 = x_0 (the state features are contiguous).
@@ -83,6 +133,24 @@ mpmi_status validate_system(mpmi_ctx ctx, const mpmi_system* s) {
       if (s->n_state != 6 || s->n_input != 2)
         return fail(ctx, MPMI_EINVAL, "RACE_CAR basis needs n=6, m=2 (got n=%d m=%d)", s->n_state, s->n_input);
       break;
+    case MPMI_BASIS_CUSTOM: {
+      if (s->n_state < 1 || s->n_state > MPMI_MAX_STATE || s->n_input < 1 || s->n_input > MPMI_MAX_INPUT)
+        return fail(ctx, MPMI_EINVAL, "CUSTOM basis needs 1 <= n <= %d and 1 <= m <= %d (got n=%d m=%d)",
+                    MPMI_MAX_STATE, MPMI_MAX_INPUT, s->n_state, s->n_input);
+      if (s->n_atoms < 1 || s->n_atoms > MPMI_MAX_ATOMS)
+        return fail(ctx, MPMI_EINVAL, "n_atoms=%d out of 1..%d", s->n_atoms, MPMI_MAX_ATOMS);
+      if (s->dim < 1 || s->dim > MPMI_MAX_DIM) return fail(ctx, MPMI_EINVAL, "dim=%d out of 1..%d", s->dim, MPMI_MAX_DIM);
+      for (int q = 0; q < s->n_atoms; ++q) {
+        if (s->atom_kind[q] < MPMI_ATOM_ONE || s->atom_kind[q] > MPMI_ATOM_COS)
+          return fail(ctx, MPMI_EINVAL, "atom_kind[%d]=%d is not an atom kind", q, s->atom_kind[q]);
+        if (s->atom_var[q] < 0 || s->atom_var[q] >= s->n_state + s->n_input)
+          return fail(ctx, MPMI_EINVAL, "atom_var[%d]=%d is not a component of w = [x; u]", q, s->atom_var[q]);
+      }
+      for (int f = 0; f < s->dim; ++f)
+        if (s->feat_a[f] < 0 || s->feat_a[f] >= s->n_atoms || s->feat_b[f] < 0 || s->feat_b[f] >= s->n_atoms)
+          return fail(ctx, MPMI_EINVAL, "feature %d names an atom outside 0..%d", f, s->n_atoms - 1);
+      break;
+    }
     default:
       return fail(ctx, MPMI_EINVAL, "unknown basis %d", s->basis);
   }
@@ -126,6 +194,39 @@ mpmi_status model_system(mpmi_ctx ctx, const void* model, mpmi_system* out, hipS
 extern "C" {
 
 int32_t mpmi_abi_version(void) { return MPMI_ABI_VERSION; }
+
+int32_t mpmi_basis_describe(int32_t family, int32_t n_state, int32_t n_input, mpmi_system* sys) {
+  if (!sys) return MPMI_EINVAL;
+  mpmi_system t = *sys;
+  if (!family_descriptor(family, n_state, n_input, &t)) return MPMI_EINVAL;
+  *sys = t;
+  return MPMI_OK;
+}
+
+int32_t mpmi_basis_match(const mpmi_system* sys) {
+  if (!sys) return MPMI_EINVAL;
+  if (sys->basis != MPMI_BASIS_CUSTOM) return sys->basis;
+  // only the descriptor matters here (not the safety set or the input box)
+  if (sys->n_atoms < 1 || sys->n_atoms > MPMI_MAX_ATOMS || sys->dim < 1 || sys->dim > MPMI_MAX_DIM)
+    return MPMI_BASIS_CUSTOM;
+  for (int f = 0; f < sys->dim; ++f)
+    if (sys->feat_a[f] < 0 || sys->feat_a[f] >= sys->n_atoms || sys->feat_b[f] < 0 || sys->feat_b[f] >= sys->n_atoms)
+      return MPMI_BASIS_CUSTOM;
+  for (int fam : {MPMI_BASIS_LINEAR, MPMI_BASIS_BALANCE_BOT, MPMI_BASIS_RACE_CAR}) {
+    mpmi_system t = *sys;
+    if (!family_descriptor(fam, sys->n_state, sys->n_input, &t)) continue;
+    if (t.n_state != sys->n_state || t.n_input != sys->n_input || t.dim != sys->dim) continue;
+    bool same = true;
+    for (int f = 0; f < t.dim && same; ++f) {
+      // the same product of the same two functions, in either order
+      const int a = atom_code(t, t.feat_a[f]), b = atom_code(t, t.feat_b[f]);
+      const int c = atom_code(*sys, sys->feat_a[f]), d = atom_code(*sys, sys->feat_b[f]);
+      same = (a == c && b == d) || (a == d && b == c);
+    }
+    if (same) return fam;
+  }
+  return MPMI_BASIS_CUSTOM;
+}
 
 size_t mpmi_model_bytes(void) { return mpmi::model_bytes(); }
 
@@ -270,6 +371,8 @@ mpmi_status mpmi_lifted_pack(mpmi_ctx ctx, const void* model, const double* K_fu
   mpmi_status s = model_system(ctx, model, &sys, (hipStream_t)stream);
   if (s != MPMI_OK) return s;
   if (!K_full || !lifted) return fail(ctx, MPMI_EINVAL, "K_full and lifted must be non-NULL");
+  if (sys.basis == MPMI_BASIS_CUSTOM)
+    return fail(ctx, MPMI_EUNSUPPORTED, "the lifted form runs the fixed bases (see mpmi_basis_match)");
   if (!aligned(lifted, 256)) return fail(ctx, MPMI_EINVAL, "lifted must be 256-byte aligned");
   if (!aligned(K_full, 8)) return fail(ctx, MPMI_EINVAL, "K_full must be 8-byte aligned");
   if (h_max < 1 || h_max > MPMI_MAX_HORIZON)
@@ -387,8 +490,11 @@ static mpmi_status validate_desc(mpmi_ctx ctx, const mpmi_system& sys, const mpm
   if (d->lanes_per_cand != 0 && d->lanes_per_cand != 1 && d->lanes_per_cand != 2 && d->lanes_per_cand != 4 &&
       d->lanes_per_cand != 8)
     return fail(ctx, MPMI_EINVAL, "lanes_per_cand=%d must be 0, 1, 2, 4 or 8", d->lanes_per_cand);
-  if (d->lanes_per_cand > 1 && (d->precision != MPMI_PREC_FP32 || sys.basis == MPMI_BASIS_LINEAR))
+  if (d->lanes_per_cand > 1 &&
+      (d->precision != MPMI_PREC_FP32 || sys.basis == MPMI_BASIS_LINEAR || sys.basis == MPMI_BASIS_CUSTOM))
     return fail(ctx, MPMI_EUNSUPPORTED, "several lanes per candidate: FP32 ticks of the fixed bases only");
+  if (sys.basis == MPMI_BASIS_CUSTOM && d->block > mpmi::kCustomBlock)
+    return fail(ctx, MPMI_EUNSUPPORTED, "custom-basis ticks use at most %d threads per workgroup", mpmi::kCustomBlock);
   switch (d->gen) {
     case MPMI_GEN_EXPLICIT:
     case MPMI_GEN_UNIFORM:
@@ -473,8 +579,10 @@ mpmi_status mpmi_tick_autotune(mpmi_ctx ctx, const void* model, mpmi_tick_desc* 
   float bms = 1e30f;
   int bblock = 256, blanes = 1;
   for (int lanes : {1, 2, 4, 8}) {
-    if (lanes > 1 && (sys.basis == MPMI_BASIS_LINEAR || mpmi::system_noisy(sys))) continue;
+    if (lanes > 1 && (sys.basis == MPMI_BASIS_LINEAR || sys.basis == MPMI_BASIS_CUSTOM || mpmi::system_noisy(sys)))
+      continue;
     for (int block : {64, 128, 256, 512}) {
+      if (sys.basis == MPMI_BASIS_CUSTOM && block > mpmi::kCustomBlock) continue;
       if (lanes > 1 && block > 256) continue;
       d.block = block;
       d.lanes_per_cand = lanes;
@@ -576,6 +684,10 @@ mpmi_status mpmi_multi_create(mpmi_ctx ctx, const mpmi_loop_desc* loops, int32_t
     if (s != MPMI_OK) {
       delete m;
       return fail(ctx, s, "loop %d: %s", l, ctx->err.c_str());
+    }
+    if (sys.basis == MPMI_BASIS_CUSTOM) {
+      delete m;
+      return fail(ctx, MPMI_EUNSUPPORTED, "loop %d: many-loop ticks serve the fixed bases (see mpmi_basis_match)", l);
     }
     mpmi_tick_desc d{};
     d.seed = L.seed;

@@ -7,6 +7,7 @@
 #include <stdint.h>
 
 #include "../../include/mpmi.h"
+#include "mpmi_launch.hpp"
 
 namespace mpmi {
 
@@ -205,6 +206,9 @@ template <>
 struct Dims<MPMI_BASIS_BALANCE_BOT> { static constexpr int N = 4, M = 1; };
 template <>
 struct Dims<MPMI_BASIS_RACE_CAR> { static constexpr int N = 6, M = 2; };
+template <>
+struct Dims<MPMI_BASIS_CUSTOM> { static constexpr int N = MPMI_MAX_STATE, M = MPMI_MAX_INPUT; };
+
 
 // Index of the quadratic feature w_k w_l (k <= l) in a basis [1, w_0..w_{nw-1}, w_k w_l ...].
 __host__ __device__ constexpr int quad_index(int k, int l, int nw) {
@@ -239,7 +243,7 @@ template <int BASIS>
 __device__ __forceinline__ void stage_K(const ModelDev* __restrict__ md, float4* sK) {
   float* f = reinterpret_cast<float*>(sK);
   const int t = threadIdx.x, nt = blockDim.x;
-  if constexpr (BASIS == MPMI_BASIS_LINEAR) {
+  if constexpr (BASIS == MPMI_BASIS_LINEAR || BASIS == MPMI_BASIS_CUSTOM) {
     for (int e = t; e < md->dim * 8; e += nt) f[e] = md->K[e >> 3][e & 7];
   } else if constexpr (BASIS == MPMI_BASIS_BALANCE_BOT) {
     for (int e = t; e < 21 * 4; e += nt) f[e] = md->K[e >> 2][e & 3];
@@ -308,6 +312,55 @@ struct Stepper<MPMI_BASIS_LINEAR> {
     }
 #pragma unroll
     for (int j = 0; j < NM; ++j) x[j] = (j < n) ? y[j] : 0.0f;
+  }
+};
+
+// A basis given as data (MPMI_BASIS_CUSTOM): per step, w = [x; u] and the
+// atoms go to this lane's column of two LDS tables (atom-major, so a wave's
+// accesses hit 64 consecutive words), then every feature is the product of
+// two atoms read back at wave-uniform rows, contracted with its K row (LDS
+// broadcast).  The descriptor is read by scalar loads.  Sine and cosine are
+// the hardware ones, as in the race-car step.
+template <>
+struct Stepper<MPMI_BASIS_CUSTOM> {
+  float u[MPMI_MAX_INPUT];
+  __device__ __forceinline__ void set_input(const ModelDev* __restrict__, const float4*, const float* uin) {
+#pragma unroll
+    for (int j = 0; j < MPMI_MAX_INPUT; ++j) u[j] = uin[j];
+  }
+  __device__ __forceinline__ void step(const ModelDev* __restrict__ md, const float4* sK, float* x) {
+    __shared__ float sW[MPMI_MAX_STATE + MPMI_MAX_INPUT][kCustomBlock];
+    __shared__ float sAt[MPMI_MAX_ATOMS][kCustomBlock];
+    const int t = threadIdx.x;
+    const int n = md->n, m = md->m;
+#pragma unroll
+    for (int j = 0; j < MPMI_MAX_STATE; ++j) sW[j][t] = x[j];
+#pragma unroll
+    for (int j = 0; j < MPMI_MAX_INPUT; ++j) sW[MPMI_MAX_STATE + j][t] = u[j];
+    const int na = md->sys.n_atoms;
+    for (int q = 0; q < na; ++q) {
+      const int kd = md->sys.atom_kind[q], v = md->sys.atom_var[q];
+      const float w = sW[v < n ? v : MPMI_MAX_STATE + (v - n)][t];
+      float a = 1.0f;
+      if (kd == MPMI_ATOM_VAR) a = w;
+      else if (kd == MPMI_ATOM_SIN) a = __sinf(w);
+      else if (kd == MPMI_ATOM_COS) a = __cosf(w);
+      sAt[q][t] = a;
+    }
+    (void)m;
+    const float4* k = opaque_lds(sK);
+    float y[MPMI_MAX_STATE];
+#pragma unroll
+    for (int j = 0; j < MPMI_MAX_STATE; ++j) y[j] = 0.0f;
+    const int D = md->dim;
+    for (int f = 0; f < D; ++f) {
+      const float p = sAt[md->sys.feat_a[f]][t] * sAt[md->sys.feat_b[f]][t];
+      const float4 a = k[2 * f], b = k[2 * f + 1];
+      y[0] = fmaf(p, a.x, y[0]); y[1] = fmaf(p, a.y, y[1]); y[2] = fmaf(p, a.z, y[2]); y[3] = fmaf(p, a.w, y[3]);
+      y[4] = fmaf(p, b.x, y[4]); y[5] = fmaf(p, b.y, y[5]); y[6] = fmaf(p, b.z, y[6]); y[7] = fmaf(p, b.w, y[7]);
+    }
+#pragma unroll
+    for (int j = 0; j < MPMI_MAX_STATE; ++j) x[j] = (j < n) ? y[j] : 0.0f;
   }
 };
 

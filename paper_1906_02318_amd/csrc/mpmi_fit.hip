@@ -33,8 +33,25 @@ struct FitInfo {
 // psi(x, u) of one transition in FP64, the FP32 path's feature order,
 // written to z (an LDS row) from the row's state xr[n] and input ur[m].  The
 // fixed bases take their atoms into registers by constant index.
-__device__ __forceinline__ void lift_row(int basis, int n, int m, const double* __restrict__ xr,
+// Atom q of a custom basis at w = [xr; ur], FP64.
+__device__ __forceinline__ double custom_atom(const mpmi_system& sys, int q, const double* __restrict__ xr,
+                                              const double* __restrict__ ur) {
+  const int kd = sys.atom_kind[q], v = sys.atom_var[q];
+  const double w = v < sys.n_state ? xr[v] : ur[v - sys.n_state];
+  if (kd == MPMI_ATOM_VAR) return w;
+  if (kd == MPMI_ATOM_SIN) return sin(w);
+  if (kd == MPMI_ATOM_COS) return cos(w);
+  return 1.0;
+}
+
+__device__ __forceinline__ void lift_row(const mpmi_system& sys, const double* __restrict__ xr,
                                          const double* __restrict__ ur, double* z) {
+  const int basis = sys.basis, n = sys.n_state, m = sys.n_input;
+  if (basis == MPMI_BASIS_CUSTOM) {
+    for (int f = 0; f < sys.dim; ++f)
+      z[f] = custom_atom(sys, sys.feat_a[f], xr, ur) * custom_atom(sys, sys.feat_b[f], xr, ur);
+    return;
+  }
   if (basis == MPMI_BASIS_LINEAR) {
     for (int k = 0; k < n; ++k) z[k] = xr[k];
     for (int k = 0; k < m; ++k) z[n + k] = ur[k];
@@ -90,9 +107,10 @@ static_assert(kFitRows == 64, "wave 0 lifts one row per lane");
 // lifted operator, features yc0 .. yc0 + ny - 1 of psi(Y_t, U_t) (the input
 // held over the step), lifted on the fly like the rows of Psi.
 __global__ void __launch_bounds__(kFitThreads)
-gram_kernel(int basis, int n, int m, int D, int ny, int yc0, const double* __restrict__ X,
-            const double* __restrict__ U, const double* __restrict__ Y, long long T, double* __restrict__ part) {
+gram_kernel(mpmi_system sys, int D, int ny, int yc0, const double* __restrict__ X, const double* __restrict__ U,
+            const double* __restrict__ Y, long long T, double* __restrict__ part) {
   __shared__ __attribute__((aligned(16))) double Z[2][kFitRows][kZStride];
+  const int n = sys.n_state, m = sys.n_input;
   const int C = D + ny;
   const int E = D * C;
   const bool lifter = threadIdx.x < 64;
@@ -114,12 +132,12 @@ gram_kernel(int basis, int n, int m, int D, int ny, int yc0, const double* __res
     if (r < T) {
       if (yc0 >= 0) {
         // psi(Y_t, U_t) into the row first, its chunk moved past the D features
-        lift_row(basis, n, m, Y + r * n, U + r * m, z);
+        lift_row(sys, Y + r * n, U + r * m, z);
         for (int q = 0; q < ny; ++q) z[D + q] = z[yc0 + q];
       } else {
         for (int q = 0; q < ny; ++q) z[D + q] = Y[r * n + q];
       }
-      lift_row(basis, n, m, X + r * n, U + r * m, z);
+      lift_row(sys, X + r * n, U + r * m, z);
     } else {
       for (int q = 0; q < C; ++q) z[q] = 0.0;
     }
@@ -501,14 +519,13 @@ size_t fit_workspace_bytes() { return fit_info_offset() + 256 + (size_t)MPMI_MAX
 // One least-squares solve with ny right-hand sides (see gram_kernel).
 static hipError_t fit_columns(const mpmi_system& sys, int dim, int ny, int yc0, const double* X, const double* U,
                               const double* Y, int64_t T, double ridge, double* K_out, void* work, hipStream_t st) {
-  const int n = sys.n_state, m = sys.n_input;
   const int E = dim * (dim + ny);
   long long ntiles = (T + kFitRows - 1) / kFitRows;
   const int nparts = (int)(ntiles < kFitBlocks ? ntiles : kFitBlocks);
   double* part = (double*)work;
   double* tot = part + (size_t)kFitBlocks * MPMI_MAX_DIM * kFitCols;
   FitInfo* info = (FitInfo*)(tot + (size_t)MPMI_MAX_DIM * kFitCols);
-  gram_kernel<<<nparts, kFitThreads, 0, st>>>(sys.basis, n, m, dim, ny, yc0, X, U, Y, (long long)T, part);
+  gram_kernel<<<nparts, kFitThreads, 0, st>>>(sys, dim, ny, yc0, X, U, Y, (long long)T, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   reduce_kernel<<<(E + kReduceElems - 1) / kReduceElems, kReduceElems * kReduceWays, 0, st>>>(nparts, E, part, tot);

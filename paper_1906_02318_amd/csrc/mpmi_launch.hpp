@@ -12,6 +12,10 @@
 
 namespace mpmi {
 
+// Custom-basis ticks use at most this many threads per workgroup (each lane
+// keeps its w and atoms in LDS).
+constexpr int kCustomBlock = 256;
+
 size_t model_bytes();
 size_t slot_bytes();
 // Host image of n slots in their reset state (keys all-ones, counters zero).

@@ -368,6 +368,10 @@ hipError_t launch_tick(const mpmi_system& sys, const void* model, const mpmi_tic
       tick_dispatch<MPMI_BASIS_BALANCE_BOT, kMaxHarm>(noisy, grid, block, st, md, gp, d.horizon, x_t, u_user, cand,
                                                       sl, out, fv, traj, traj_ld, gate);
       break;
+    case MPMI_BASIS_CUSTOM:
+      tick_dispatch<MPMI_BASIS_CUSTOM, kMaxHarm>(noisy, grid, block, st, md, gp, d.horizon, x_t, u_user, cand, sl,
+                                                 out, fv, traj, traj_ld, gate);
+      break;
     default:
       if (track_degree(sys) <= kSmallTrackDeg)
         tick_dispatch<MPMI_BASIS_RACE_CAR, kSmallTrackDeg>(noisy, grid, block, st, md, gp, d.horizon, x_t, u_user,
@@ -392,6 +396,9 @@ hipError_t launch_rollout(int basis, const void* model, int Nc, int S, int H, co
     case MPMI_BASIS_BALANCE_BOT:
       rollout_fp32_kernel<MPMI_BASIS_BALANCE_BOT><<<grid, block, 0, st>>>(md, Nc, S, H, x0, cand, traj, traj_ld);
       break;
+    case MPMI_BASIS_CUSTOM:
+      rollout_fp32_kernel<MPMI_BASIS_CUSTOM><<<grid, block, 0, st>>>(md, Nc, S, H, x0, cand, traj, traj_ld);
+      break;
     default:
       rollout_fp32_kernel<MPMI_BASIS_RACE_CAR><<<grid, block, 0, st>>>(md, Nc, S, H, x0, cand, traj, traj_ld);
       break;
@@ -406,6 +413,7 @@ hipError_t launch_mask(int basis, const void* model, int Nc, int H, const float*
   const ModelDev* md = (const ModelDev*)model;
   switch (basis) {
     case MPMI_BASIS_LINEAR:
+    case MPMI_BASIS_CUSTOM:
       mask_kernel<MPMI_MAX_STATE><<<grid, block, 0, st>>>(md, Nc, H, traj, traj_ld, fv, mm);
       break;
     case MPMI_BASIS_BALANCE_BOT:

@@ -17,11 +17,13 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmpmi.so")
 
 # Constants mirrored from include/mpmi.h
-ABI_VERSION = 4
+ABI_VERSION = 5
 MAX_STATE, MAX_INPUT, MAX_DIM, MAX_BOX = 8, 4, 64, 4
 MAX_HORIZON, MAX_SEGMENTS, MAX_CAND, MAX_LOOPS = 255, 8, 33554431, 4096
 OK, NO_SAFE, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED, ESINGULAR = 0, 1, -1, -2, -3, -4, -5
-BASIS_LINEAR, BASIS_BALANCE_BOT, BASIS_RACE_CAR = 0, 1, 2
+BASIS_LINEAR, BASIS_BALANCE_BOT, BASIS_RACE_CAR, BASIS_CUSTOM = 0, 1, 2, 3
+ATOM_ONE, ATOM_VAR, ATOM_SIN, ATOM_COS = 0, 1, 2, 3
+MAX_ATOMS = 32
 PREC_FP32, PREC_BF16X3 = 0, 1
 GEN_EXPLICIT, GEN_GRID, GEN_UNIFORM = 0, 1, 2
 
@@ -38,6 +40,9 @@ class System(ctypes.Structure):
         ("track_r0", ctypes.c_float), ("track_half", ctypes.c_float), ("track_infl", ctypes.c_float),
         ("eps_track", ctypes.c_float), ("u_lo", _f32x4), ("u_hi", _f32x4),
         ("noise_sigma", ctypes.c_float * 8),
+        ("n_atoms", ctypes.c_int32), ("dim", ctypes.c_int32),
+        ("atom_kind", ctypes.c_int8 * 32), ("atom_var", ctypes.c_int8 * 32),
+        ("feat_a", ctypes.c_int8 * 64), ("feat_b", ctypes.c_int8 * 64),
     ]
 
 
@@ -128,6 +133,8 @@ def library() -> ctypes.CDLL:
         "mpmi_gemm_bf16": (i32, [vp, vp, vp, i32, i32, i32, i32, i32, vp, vp]),
         "mpmi_tick_autotune": (i32, [vp, vp, ctypes.POINTER(TickDesc), vp, vp, vp, vp, i32,
                                      ctypes.POINTER(ctypes.c_float), vp]),
+        "mpmi_basis_describe": (i32, [i32, i32, i32, ctypes.POINTER(System)]),
+        "mpmi_basis_match": (i32, [ctypes.POINTER(System)]),
         "koopman_fit_lifted": (i32, [vp, ctypes.POINTER(System), vp, vp, vp, i64, f64, vp, ctypes.POINTER(f64), vp]),
         "mpmi_lifted_bytes": (ctypes.c_size_t, [i32]),
         "mpmi_lifted_layout": (i32, [i32, i32, i32, vp, vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
@@ -168,6 +175,33 @@ def _sys(basis, n, m, box, u_lo, u_hi, track=None, eps_box=None, eps_track=0.0, 
         s.track_r0, s.track_half, s.track_infl = track["r0"], track["half"], track.get("infl", 0.0)
         s.eps_track = eps_track
     return s
+
+
+def custom_system(n, m, atoms, feats, box, u_lo, u_hi, track=None, eps_box=None, eps_track=0.0, noise=None):
+    """A basis given as data: atoms [(ATOM_*, w index)], features [(atom a, atom b)]
+    (psi_f = atom_a * atom_b, w = [x; u])."""
+    s = _sys(BASIS_CUSTOM, n, m, box, u_lo, u_hi, track=track, eps_box=eps_box, eps_track=eps_track, noise=noise)
+    if not 1 <= len(atoms) <= MAX_ATOMS or not 1 <= len(feats) <= MAX_DIM:
+        raise ValueError("1..32 atoms and 1..64 features")
+    s.n_atoms, s.dim = len(atoms), len(feats)
+    for q, (kind, var) in enumerate(atoms):
+        s.atom_kind[q], s.atom_var[q] = kind, var
+    for f, (a, b) in enumerate(feats):
+        s.feat_a[f], s.feat_b[f] = a, b
+    return s
+
+
+def basis_describe(family: int, n: int, m: int, system: System) -> System:
+    """system with its custom-basis fields set to the atoms and features of a fixed family."""
+    st = library().mpmi_basis_describe(family, n, m, ctypes.byref(system))
+    if st != OK:
+        raise MpmiError(st, "mpmi_basis_describe failed")
+    return system
+
+
+def basis_match(system: System) -> int:
+    """The fixed family a custom basis equals, or BASIS_CUSTOM."""
+    return int(library().mpmi_basis_match(ctypes.byref(system)))
 
 
 def linear_system(n, m, box, u_lo, u_hi):
@@ -328,7 +362,7 @@ def koopman_fit(ctx: Context, system: System, X, U, Y, ridge: float = 0.0, strea
         raise ValueError("X, U, Y must have T rows; Y shaped like X")
     if n != system.n_state or m != system.n_input:
         raise ValueError("X/U widths do not match the system")
-    D = {BASIS_LINEAR: n + m, BASIS_BALANCE_BOT: 21, BASIS_RACE_CAR: 64}[system.basis]
+    D = basis_dim(system)
     K = torch.empty((D, n), dtype=torch.float64, device=ctx.device)
     cond = ctypes.c_double(0.0)
     ctx.check(ctx.lib.koopman_fit(ctx.handle, ctypes.byref(system), _ptr(X), _ptr(U), _ptr(Y), T, float(ridge),
@@ -337,6 +371,8 @@ def koopman_fit(ctx: Context, system: System, X, U, Y, ridge: float = 0.0, strea
 
 
 def basis_dim(system: System) -> int:
+    if system.basis == BASIS_CUSTOM:
+        return system.dim
     return {BASIS_LINEAR: system.n_state + system.n_input, BASIS_BALANCE_BOT: 21, BASIS_RACE_CAR: 64}[system.basis]
 
 

@@ -226,6 +226,59 @@ def race_car_transitions(T: int = 50000, seed: int = 0, track: Track | None = No
 
 
 # ----------------------------------------------------------------------------
+# The paper's three-input race car (Sec. V-A: a desired heading, gas and brake)
+# ----------------------------------------------------------------------------
+# Inputs w_6.. = [h, gas, brake] on [-1, 1] x [0, 1] x [-1, 0]; the same
+# bicycle with steering delta = 0.4 h rad and acceleration a = 3 (gas + brake) m/s^2.
+RC3_U_LO = np.array([-1.0, 0.0, -1.0])
+RC3_U_HI = np.array([1.0, 1.0, 0.0])
+RC3_STEER, RC3_ACCEL = 0.4, 3.0
+
+
+def race_car3_inputs(u3: np.ndarray) -> np.ndarray:
+    """[h, gas, brake] rows -> the bicycle's [delta, a] rows."""
+    u3 = np.atleast_2d(np.asarray(u3, np.float64))
+    return np.stack([RC3_STEER * u3[:, 0], RC3_ACCEL * (u3[:, 1] + u3[:, 2])], axis=1)
+
+
+def bicycle3_step(x, u3, dt=BICYCLE["dt"]):
+    return bicycle_step(x, race_car3_inputs(u3), dt)
+
+
+def race_car3_transitions(T: int = 50000, seed: int = 0, track: Track | None = None):
+    """T one-step transitions of the three-input car from random on-track states
+    under uniform random inputs in its box.  Returns X (T, 6), U (T, 3), Y (T, 6)."""
+    track = make_track() if track is None else track
+    X = race_car_states(T, track, seed=seed + 1000, offset=3.5, psi_sd=0.4,
+                        vx=(2.0, 18.0), vy=(-1.5, 1.5), r=(-0.8, 0.8))
+    U = uniform_user(T, RC3_U_LO, RC3_U_HI, seed=seed)
+    return X, U, bicycle3_step(X, U)
+
+
+def race_car3_basis():
+    """A 64-feature basis for the three-input car as (atoms, features): atoms
+    ('one' | 'var' | 'sin' | 'cos', component of w = [x, y, psi, vx, vy, r, h,
+    gas, brake]); feature = product of two atoms.  1; w (9); the state
+    quadratics (21); the input quadratics (6); vx, vy, r times h, and vx times
+    gas and brake (5); sin/cos psi and sin/cos h (4); sin/cos psi times (vx, vy,
+    r) (6) and times gas and brake (4); sin/cos h times (vx, vy, r) (6); gas and
+    brake times sin h (2)."""
+    atoms = [("one", 0)] + [("var", k) for k in range(9)] + [("sin", 2), ("cos", 2), ("sin", 6), ("cos", 6)]
+    ONE, W, SP, CP, SH, CH = 0, list(range(1, 10)), 10, 11, 12, 13
+    feats = [(ONE, ONE)] + [(W[k], ONE) for k in range(9)]
+    feats += [(W[k], W[l]) for k in range(6) for l in range(k, 6)]
+    feats += [(W[k], W[l]) for k in range(6, 9) for l in range(k, 9)]
+    feats += [(W[3], W[6]), (W[4], W[6]), (W[5], W[6]), (W[3], W[7]), (W[3], W[8])]
+    feats += [(SP, ONE), (CP, ONE), (SH, ONE), (CH, ONE)]
+    feats += [(SP, W[k]) for k in (3, 4, 5)] + [(CP, W[k]) for k in (3, 4, 5)]
+    feats += [(SP, W[7]), (SP, W[8]), (CP, W[7]), (CP, W[8])]
+    feats += [(SH, W[k]) for k in (3, 4, 5)] + [(CH, W[k]) for k in (3, 4, 5)]
+    feats += [(W[7], SH), (W[8], SH)]
+    assert len(feats) == 64 and len(atoms) == 14
+    return atoms, feats
+
+
+# ----------------------------------------------------------------------------
 # Linear plant (identity-basis checks) and many-loop sizes
 # ----------------------------------------------------------------------------
 def linear_plant(n: int = 4, m: int = 1, seed: int = 11, radius: float = 0.97):

@@ -108,3 +108,42 @@ def test_lifted_layout_factorises_the_basis(basis, n, m):
         assert (n_phi, n_g) == (len(phi), len(g))
         psi = o.lift(kind, x[None], u[None])[0]
         np.testing.assert_allclose([g[fg[f]] * phi[fp[f]] for f in range(psi.size)], psi, rtol=1e-14, atol=1e-14)
+
+
+def _oracle_basis(s):
+    from oracle import mpmi_oracle as o
+    kinds = {0: "one", 1: "var", 2: "sin", 3: "cos"}
+    atoms = tuple((kinds[s.atom_kind[q]], int(s.atom_var[q])) for q in range(s.n_atoms))
+    return o.Basis(atoms=atoms, feats=tuple((int(s.feat_a[f]), int(s.feat_b[f])) for f in range(s.dim)))
+
+
+@pytest.mark.parametrize("family,n,m", [(2, 6, 2), (1, 4, 1), (0, 3, 2)])
+def test_family_descriptors_are_the_families(family, n, m):
+    """The library's atom/feature description of each fixed family computes the
+    family's features in its order (checked with the oracle's lifts), and
+    mpmi_basis_match recognises it."""
+    import numpy as np
+
+    from oracle import mpmi_oracle as o
+    from paper_1906_02318_amd import mpmi
+    s = mpmi.basis_describe(family, n, m, mpmi.System())
+    assert s.basis == mpmi.BASIS_CUSTOM and (s.n_state, s.n_input) == (n, m)
+    kind = {0: "linear", 1: "balance_bot", 2: "race_car"}[family]
+    b = _oracle_basis(s)
+    rng = np.random.default_rng(family)
+    X, U = rng.normal(size=(7, n)), rng.normal(size=(7, m))
+    np.testing.assert_array_equal(o.lift(b, X, U), o.lift(kind, X, U))
+    assert mpmi.basis_match(s) == family
+
+
+def test_basis_match_rejects_other_bases():
+    from paper_1906_02318_amd import mpmi
+    s = mpmi.basis_describe(1, 4, 1, mpmi.System())
+    a, b = s.feat_a[7], s.feat_b[7]
+    s.feat_a[7], s.feat_b[7] = b, a  # the same product in the other order still matches
+    assert mpmi.basis_match(s) == 1
+    s.feat_b[7] = s.feat_a[7]         # a different product
+    assert mpmi.basis_match(s) == mpmi.BASIS_CUSTOM
+    t = mpmi.custom_system(2, 1, [(mpmi.ATOM_ONE, 0), (mpmi.ATOM_SIN, 0)], [(0, 0), (1, 0)], [], [-1.0], [1.0])
+    assert mpmi.basis_match(t) == mpmi.BASIS_CUSTOM
+    assert mpmi.basis_match(mpmi.balance_bot_system()) == mpmi.BASIS_BALANCE_BOT

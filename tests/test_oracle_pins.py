@@ -532,3 +532,19 @@ def test_lifted_tick_brute_force(bb_model, seed):
     expect = safe[0] if safe else sorted(range(N + 1), key=lambda i: (-fvs[i], costs[i], i))[0]
     np.testing.assert_array_equal(res["fv"], fvs)
     assert res["idx"] == expect
+
+
+# ------------------------------------------------------ a basis given as data --
+def test_custom_basis_hand_values():
+    """Atoms [1, w_0, sin w_1, cos w_2] at w = (0.5, pi/6, pi/3): features
+    1*1 = 1, w_0 sin w_1 = 0.25, sin w_1 cos w_2 = 0.25, w_0^2 = 0.25 and
+    cos w_2 * 1 = 0.5."""
+    b = o.Basis(atoms=(("one", 0), ("var", 0), ("sin", 1), ("cos", 2)),
+                feats=((0, 0), (1, 2), (2, 3), (1, 1), (3, 0)))
+    psi = o.lift(b, np.array([[0.5, math.pi / 6]]), np.array([[math.pi / 3]]))[0]
+    np.testing.assert_allclose(psi, [1.0, 0.25, 0.25, 0.25, 0.5], rtol=0, atol=1e-15)
+    assert o.basis_dim(b, 2, 1) == 5
+    with pytest.raises(ValueError):
+        o.state_columns(b, 2)  # no feature is x_1 itself
+    b2 = o.Basis(atoms=(("one", 0), ("var", 1), ("var", 0)), feats=((0, 0), (2, 0), (0, 1)))
+    assert list(o.state_columns(b2, 2)) == [1, 2]

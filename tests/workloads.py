@@ -86,3 +86,30 @@ def rc_lifted_model():
     """Oracle-fitted FP64 lifted operator (64 x 64) of the bicycle data."""
     X, U, Y = rc_model()[2]
     return o.fit_lifted("race_car", X, U, Y)
+
+
+def rc3_basis():
+    atoms, feats = synth.race_car3_basis()
+    return o.Basis(atoms=tuple(atoms), feats=tuple(feats))
+
+
+def rc3_oracle_system(track: synth.Track, infl=0.0):
+    return o.System(rc3_basis(), 6, 3, box=[(4, float(f32(RC_VY)), float(f32(infl)))],
+                    track=track_dict(track, infl), u_lo=synth.RC3_U_LO, u_hi=synth.RC3_U_HI)
+
+
+def rc3_gpu_system(mpmi, track: synth.Track, infl=0.0):
+    """The library's descriptor of the three-input car (custom basis)."""
+    kinds = {"one": mpmi.ATOM_ONE, "var": mpmi.ATOM_VAR, "sin": mpmi.ATOM_SIN, "cos": mpmi.ATOM_COS}
+    atoms, feats = synth.race_car3_basis()
+    return mpmi.custom_system(6, 3, [(kinds[k], v) for k, v in atoms], feats, [(4, RC_VY, infl)],
+                              synth.RC3_U_LO, synth.RC3_U_HI, track=track_dict(track, infl),
+                              eps_box=[0.02], eps_track=0.02)
+
+
+@functools.lru_cache(maxsize=None)
+def rc3_model():
+    """Oracle-fitted FP64 K of the three-input car (50,000 transitions, seed 0)."""
+    X, U, Y = synth.race_car3_transitions(50000, seed=0, track=rc_track())
+    K, info = o.fit(rc3_basis(), X, U, Y)
+    return K, info, (X, U, Y)
