@@ -28,7 +28,8 @@
  *    before the kernels run.
  *  - One context may be used by one host thread at a time.  Calls on one
  *    context that share a `loop` slot must be ordered on one stream, and so
- *    must all BF16X3 ticks of a context (they share its recheck list).
+ *    must all BF16X3 and FP32_RECHECK64 ticks of a context (they share its
+ *    recheck list).
  *  - Set-up calls (mpmi_create, mpmi_model_pack, koopman_fit,
  *    mpmi_multi_create / _set_config / _autotune / _graph) may allocate or
  *    synchronise and are not meant for stream capture; tick calls allocate
@@ -45,7 +46,7 @@
 extern "C" {
 #endif
 
-#define MPMI_ABI_VERSION 5
+#define MPMI_ABI_VERSION 6
 
 /* Size limits (checked on the host). */
 #define MPMI_MAX_STATE 8      /* n */
@@ -87,6 +88,17 @@ enum { MPMI_ATOM_ONE = 0, MPMI_ATOM_VAR = 1, MPMI_ATOM_SIN = 2, MPMI_ATOM_COS = 
 
 /* Arithmetic of the prediction step.
  *  FP32    states, features and K in FP32, FP32 accumulation.
+ *  FP32_RECHECK64  the FP32 tick, and every candidate that has a checked
+ *          state (steps 1 .. its first violation) whose margin to some
+ *          constraint lies within that constraint's FP32 band (eps32_box,
+ *          eps32_track) of zero is then re-rolled from x_t in FP64 (K, the
+ *          features, noise and margins in FP64, as in the sketch of Sec.
+ *          IV-A and IV-B written in double precision); the FP64 first
+ *          violation replaces the FP32 one before the selection.  With bands
+ *          at least the FP32 rollout's margin error, every verdict, and so
+ *          the selection, is that of an FP64 rollout.  One lane per
+ *          candidate, ticks of at most 2^22 candidates (MPMI_EUNSUPPORTED
+ *          otherwise); trajectories, when stored, are the FP32 states.
  *  BF16X3  the contraction runs on BF16 matrix cores as three products of
  *          hi/lo BF16 splits of the features and of (K - E) in residual form
  *          x' = x + psi^T (K - E), FP32 accumulation; every candidate whose
@@ -94,7 +106,7 @@ enum { MPMI_ATOM_ONE = 0, MPMI_ATOM_VAR = 1, MPMI_ATOM_SIN = 2, MPMI_ATOM_COS = 
  *          re-rolled in FP32 and the FP32 verdict is kept.  Race-car models,
  *          ticks of at most 2^22 candidates (the recheck list holds them all;
  *          larger ticks return MPMI_EUNSUPPORTED).                          */
-enum { MPMI_PREC_FP32 = 0, MPMI_PREC_BF16X3 = 1 };
+enum { MPMI_PREC_FP32 = 0, MPMI_PREC_BF16X3 = 1, MPMI_PREC_FP32_RECHECK64 = 2 };
 
 /* How a tick obtains candidates 1..N (candidate 0 is always the user's input,
  * held over all segments; Sec. III-D: a safe user input passes unchanged).
@@ -118,7 +130,10 @@ enum { MPMI_GEN_EXPLICIT = 0, MPMI_GEN_GRID = 1, MPMI_GEN_UNIFORM = 2 };
  *             polar coordinates of (x[0], x[1]) and
  *             r_c(phi) = track_r0 + sum_k track_amp[k] sin(track_freq[k] phi + track_phase[k])
  * eps_box / eps_track: in BF16X3 mode, a candidate whose margin at some step
- * falls below eps is re-rolled in FP32.
+ * falls below eps is re-rolled in FP32.  eps32_box / eps32_track: the FP32
+ * bands of MPMI_PREC_FP32_RECHECK64 (a margin within them sends the candidate
+ * to the FP64 re-roll); several boxes on one component use the band of the
+ * one with the least limit.
  * noise_sigma: process noise of the fused tick (Alg. 2 adds a Gaussian z_i to
  * every predicted state): after step s, component j of candidate i's state
  * gains noise_sigma[j] * z_j.  z comes in pairs (components 2q, 2q+1) from
@@ -158,6 +173,9 @@ typedef struct mpmi_system {
   int8_t atom_var[MPMI_MAX_ATOMS];  /* 0 .. n + m - 1 */
   int8_t feat_a[MPMI_MAX_DIM];      /* 0 .. n_atoms - 1 */
   int8_t feat_b[MPMI_MAX_DIM];
+  float eps32_box[4];     /* FP32_RECHECK64 bands, >= 0 */
+  float eps32_track;
+  int32_t pad_eps;
 } mpmi_system;
 
 /* Fills the custom-basis fields of *sys with the atoms and features of a
@@ -218,7 +236,9 @@ int32_t mpmi_abi_version(void);
  * thread) and allocates its slots and workspace.  *out is NULL on failure.  */
 mpmi_status mpmi_create(mpmi_ctx* out, int32_t device);
 void mpmi_destroy(mpmi_ctx ctx);
-/* Message of the last failed call on ctx (never NULL; "" after success).    */
+/* Message of the last failed call on ctx (never NULL; "" after success);
+ * with ctx NULL, of the last failed call made without a context on the
+ * calling thread.                                                         */
 const char* mpmi_last_error(mpmi_ctx ctx);
 
 /* Size in bytes of a packed model (device blob read by every rollout).      */
@@ -361,7 +381,8 @@ mpmi_status mpmi_tick_lifted(mpmi_ctx ctx, void* lifted, const mpmi_tick_desc* d
                              float* traj, int64_t traj_ld, void* stream);
 
 /* Tick autotuner: times `reps` ticks of *desc for every launch shape in the
- * library's search space (block 64..512, lanes_per_cand 1, 2, 4, 8; FP32 only)
+ * library's search space (block 64..512; lanes_per_cand 1, 2, 4, 8 for FP32, 1
+ * for FP32_RECHECK64; other precisions MPMI_EUNSUPPORTED)
  * and writes the fastest into desc->block and desc->lanes_per_cand (host);
  * *best_ms (host, may be NULL) receives its mean tick time.  The timed ticks
  * are real ticks writing *out. */
@@ -447,6 +468,9 @@ typedef struct mpmi_loop_desc {
 typedef struct mpmi_multi_config {
   int32_t block;
   int32_t grid;
+  int32_t precision;  /* MPMI_PREC_FP32, or MPMI_PREC_FP32_RECHECK64: one more
+                         launch per tick re-rolls every loop's near-band
+                         candidates in FP64 and then finalises all loops */
 } mpmi_multi_config;
 
 typedef struct mpmi_multi_s* mpmi_multi;
@@ -458,7 +482,8 @@ mpmi_status mpmi_multi_create(mpmi_ctx ctx, const mpmi_loop_desc* loops /* host 
                               const mpmi_multi_config* cfg /* host, may be NULL */, mpmi_multi* out);
 void mpmi_multi_destroy(mpmi_multi multi);
 
-/* Re-plans the work list for a new launch shape (synchronous, no allocation). */
+/* Re-plans the work list for a new launch shape and precision (synchronous,
+ * no allocation). */
 mpmi_status mpmi_multi_set_config(mpmi_ctx ctx, mpmi_multi multi, const mpmi_multi_config* cfg /* host */);
 
 /* Current launch shape and work-list size (host outputs, may be NULL). */

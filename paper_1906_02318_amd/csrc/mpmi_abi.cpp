@@ -31,15 +31,17 @@ struct mpmi_ctx_s {
 
 namespace {
 
+// Message of the last failed call made without a context on this thread.
+thread_local std::string g_noctx_err;
+
 mpmi_status fail(mpmi_ctx ctx, mpmi_status code, const char* fmt, ...) {
-  if (ctx) {
-    char buf[512];
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
-    va_end(ap);
-    ctx->err = buf;
-  }
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (ctx) ctx->err = buf;
+  else g_noctx_err = buf;
   return code;
 }
 
@@ -172,6 +174,11 @@ mpmi_status validate_system(mpmi_ctx ctx, const mpmi_system* s) {
   for (int j = 0; j < 8; ++j)
     if (!(s->noise_sigma[j] >= 0.0f) || s->noise_sigma[j] > 1e30f)
       return fail(ctx, MPMI_EINVAL, "noise_sigma[%d] must be finite and >= 0", j);
+  for (int b = 0; b < MPMI_MAX_BOX; ++b)
+    if (!(s->eps32_box[b] >= 0.0f) || s->eps32_box[b] > 1e30f)
+      return fail(ctx, MPMI_EINVAL, "eps32_box[%d] must be finite and >= 0", b);
+  if (!(s->eps32_track >= 0.0f) || s->eps32_track > 1e30f)
+    return fail(ctx, MPMI_EINVAL, "eps32_track must be finite and >= 0");
   for (int j = 0; j < s->n_input; ++j)
     if (!(s->u_hi[j] > s->u_lo[j]))
       return fail(ctx, MPMI_EINVAL, "input box %d is empty (lo=%g hi=%g)", j, (double)s->u_lo[j], (double)s->u_hi[j]);
@@ -274,7 +281,7 @@ void mpmi_destroy(mpmi_ctx ctx) {
   delete ctx;
 }
 
-const char* mpmi_last_error(mpmi_ctx ctx) { return ctx ? ctx->err.c_str() : "NULL context"; }
+const char* mpmi_last_error(mpmi_ctx ctx) { return ctx ? ctx->err.c_str() : g_noctx_err.c_str(); }
 
 mpmi_status mpmi_model_pack(mpmi_ctx ctx, const mpmi_system* sys, const double* K, void* model, void* stream) {
   if (!ctx) return MPMI_EINVAL;
@@ -284,7 +291,14 @@ mpmi_status mpmi_model_pack(mpmi_ctx ctx, const mpmi_system* sys, const double* 
   if (!model) return fail(ctx, MPMI_EINVAL, "model is NULL");
   if (!aligned(model, 256)) return fail(ctx, MPMI_EINVAL, "model must be 256-byte aligned");
   if (!aligned(K, 8)) return fail(ctx, MPMI_EINVAL, "K must be 8-byte aligned");
-  s = check_hip(ctx, mpmi::launch_pack(*sys, basis_dim(*sys), state_feat0(*sys), K, model, (hipStream_t)stream),
+  // The FP64 re-roll evaluates every basis from its atom/feature description.
+  mpmi_system packed = *sys;
+  if (packed.basis != MPMI_BASIS_CUSTOM) {
+    if (mpmi_basis_describe(sys->basis, sys->n_state, sys->n_input, &packed) != MPMI_OK)
+      return fail(ctx, MPMI_EINVAL, "no description of basis %d", sys->basis);
+    packed.basis = sys->basis;
+  }
+  s = check_hip(ctx, mpmi::launch_pack(packed, basis_dim(*sys), state_feat0(*sys), K, model, (hipStream_t)stream),
                 "mpmi_model_pack launch");
   if (s == MPMI_OK) ctx->models[model] = *sys;
   return s;
@@ -485,7 +499,7 @@ static mpmi_status validate_desc(mpmi_ctx ctx, const mpmi_system& sys, const mpm
     return fail(ctx, MPMI_EINVAL, "loop=%d out of 0..%d", d->loop, MPMI_MAX_LOOPS - 1);
   if (d->block != 0 && (d->block < 64 || d->block > 1024 || d->block % 64 != 0))
     return fail(ctx, MPMI_EINVAL, "block=%d must be 0 or a multiple of 64 in 64..1024", d->block);
-  if (d->precision != MPMI_PREC_FP32 && d->precision != MPMI_PREC_BF16X3)
+  if (d->precision != MPMI_PREC_FP32 && d->precision != MPMI_PREC_BF16X3 && d->precision != MPMI_PREC_FP32_RECHECK64)
     return fail(ctx, MPMI_EINVAL, "unknown precision %d", d->precision);
   if (d->lanes_per_cand != 0 && d->lanes_per_cand != 1 && d->lanes_per_cand != 2 && d->lanes_per_cand != 4 &&
       d->lanes_per_cand != 8)
@@ -556,6 +570,16 @@ mpmi_status mpmi_tick(mpmi_ctx ctx, const void* model, const mpmi_tick_desc* des
                                                  mpmi::device_cu_count() * 4, (hipStream_t)stream),
                      "mpmi_tick (BF16X3) launch");
   }
+  if (desc->precision == MPMI_PREC_FP32_RECHECK64) {
+    if ((long long)desc->n_cand + 1 > mpmi::kRecheckCapacity)
+      return fail(ctx, MPMI_EUNSUPPORTED,
+                  "FP32_RECHECK64 ticks take at most %d candidates (the FP64 recheck list holds every one)",
+                  mpmi::kRecheckCapacity);
+    return check_hip(ctx, mpmi::launch_tick(sys, model, *desc, x_t, u_user, cand, slot, out, first_violation, traj,
+                                            traj ? traj_ld : 0, (hipStream_t)stream, nullptr, ctx->recheck,
+                                            mpmi::kRecheckCapacity, mpmi::device_cu_count() * 4),
+                     "mpmi_tick (FP32_RECHECK64) launch");
+  }
   return check_hip(ctx, mpmi::launch_tick(sys, model, *desc, x_t, u_user, cand, slot, out, first_violation,
                                           traj, traj ? traj_ld : 0, (hipStream_t)stream),
                    "mpmi_tick launch");
@@ -567,7 +591,8 @@ mpmi_status mpmi_tick_autotune(mpmi_ctx ctx, const void* model, mpmi_tick_desc* 
   if (!ctx) return MPMI_EINVAL;
   if (!desc) return fail(ctx, MPMI_EINVAL, "desc is NULL");
   if (reps < 1 || reps > 100000) return fail(ctx, MPMI_EINVAL, "reps=%d out of 1..100000", reps);
-  if (desc->precision != MPMI_PREC_FP32) return fail(ctx, MPMI_EUNSUPPORTED, "the tick autotuner times FP32 ticks");
+  if (desc->precision != MPMI_PREC_FP32 && desc->precision != MPMI_PREC_FP32_RECHECK64)
+    return fail(ctx, MPMI_EUNSUPPORTED, "the tick autotuner times FP32 and FP32_RECHECK64 ticks");
   mpmi_system sys;
   mpmi_status s = model_system(ctx, model, &sys, nullptr);
   if (s != MPMI_OK) return s;
@@ -579,7 +604,8 @@ mpmi_status mpmi_tick_autotune(mpmi_ctx ctx, const void* model, mpmi_tick_desc* 
   float bms = 1e30f;
   int bblock = 256, blanes = 1;
   for (int lanes : {1, 2, 4, 8}) {
-    if (lanes > 1 && (sys.basis == MPMI_BASIS_LINEAR || sys.basis == MPMI_BASIS_CUSTOM || mpmi::system_noisy(sys)))
+    if (lanes > 1 && (sys.basis == MPMI_BASIS_LINEAR || sys.basis == MPMI_BASIS_CUSTOM || mpmi::system_noisy(sys) ||
+                      desc->precision != MPMI_PREC_FP32))
       continue;
     for (int block : {64, 128, 256, 512}) {
       if (sys.basis == MPMI_BASIS_CUSTOM && block > mpmi::kCustomBlock) continue;
@@ -671,12 +697,16 @@ mpmi_status mpmi_multi_create(mpmi_ctx ctx, const mpmi_loop_desc* loops, int32_t
     return fail(ctx, MPMI_EINVAL, "n_loops=%d out of 1..%d", n_loops, MPMI_MAX_LOOPS);
   const int block = cfg ? cfg->block : 256;
   const int grid = cfg ? cfg->grid : 0;
+  const int prec = cfg ? cfg->precision : MPMI_PREC_FP32;
   if (block < 64 || block > 1024 || block % 64 != 0)
     return fail(ctx, MPMI_EINVAL, "block=%d must be a multiple of 64 in 64..1024", block);
   if (grid != 0) return fail(ctx, MPMI_EINVAL, "grid=%d must be 0 (one workgroup per work item)", grid);
+  if (prec != MPMI_PREC_FP32 && prec != MPMI_PREC_FP32_RECHECK64)
+    return fail(ctx, MPMI_EUNSUPPORTED, "many-loop ticks run FP32 or FP32_RECHECK64 (precision=%d)", prec);
   mpmi_multi m = new (std::nothrow) mpmi_multi_s();
   if (!m) return fail(ctx, MPMI_ENOMEM, "out of host memory");
   m->plan.n_loops = n_loops;
+  m->plan.precision = prec;
   for (int l = 0; l < n_loops; ++l) {
     const mpmi_loop_desc& L = loops[l];
     mpmi_system sys;
@@ -736,7 +766,11 @@ mpmi_status mpmi_multi_set_config(mpmi_ctx ctx, mpmi_multi m, const mpmi_multi_c
   if (cfg->block < 64 || cfg->block > 1024 || cfg->block % 64 != 0)
     return fail(ctx, MPMI_EINVAL, "block=%d must be a multiple of 64 in 64..1024", cfg->block);
   if (cfg->grid != 0) return fail(ctx, MPMI_EINVAL, "grid=%d must be 0 (one workgroup per work item)", cfg->grid);
-  return check_hip(ctx, mpmi::multi_plan(m->plan, cfg->block), "mpmi_multi_set_config");
+  if (cfg->precision != MPMI_PREC_FP32 && cfg->precision != MPMI_PREC_FP32_RECHECK64)
+    return fail(ctx, MPMI_EUNSUPPORTED, "many-loop ticks run FP32 or FP32_RECHECK64 (precision=%d)", cfg->precision);
+  mpmi_status s = check_hip(ctx, mpmi::multi_plan(m->plan, cfg->block), "mpmi_multi_set_config");
+  if (s == MPMI_OK) m->plan.precision = cfg->precision;
+  return s;
 }
 
 mpmi_status mpmi_multi_get_config(mpmi_multi m, mpmi_multi_config* cfg, int32_t* n_work_items) {
@@ -744,6 +778,7 @@ mpmi_status mpmi_multi_get_config(mpmi_multi m, mpmi_multi_config* cfg, int32_t*
   if (cfg) {
     cfg->block = m->plan.block;
     cfg->grid = m->plan.n_work;
+    cfg->precision = m->plan.precision;
   }
   if (n_work_items) *n_work_items = m->plan.n_work;
   return MPMI_OK;
@@ -800,6 +835,7 @@ mpmi_status mpmi_multi_autotune(mpmi_ctx ctx, mpmi_multi m, int32_t reps, mpmi_m
   if (best) {
     best->block = m->plan.block;
     best->grid = m->plan.n_work;
+    best->precision = m->plan.precision;
   }
   if (best_ms) *best_ms = bms;
   return ok(ctx);
@@ -951,3 +987,4 @@ mpmi_status mpmi_gemm_bf16(mpmi_ctx ctx, const uint16_t* A, const uint16_t* B, i
 }
 
 }  // extern "C"
+

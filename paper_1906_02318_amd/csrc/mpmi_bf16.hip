@@ -30,12 +30,6 @@ typedef float f32x4_t __attribute__((ext_vector_type(4)));
 constexpr int kWaves = 4;            // waves per workgroup (256 threads)
 constexpr int kArow = 40;            // bf16 per LDS feature row (32 + 8 pad = 80 B)
 
-struct RecheckList {
-  unsigned int count;
-  unsigned int pad[63];
-  int idx[1];  // capacity entries follow
-};
-
 // Safety verdict of x (min_margin's rule: every checked margin positive, a
 // NaN margin unsafe) and whether some constraint margin is within its eps of
 // zero (either side), with the track's centreline evaluated once.

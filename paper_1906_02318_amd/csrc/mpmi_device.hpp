@@ -50,6 +50,30 @@ struct SafetyConsts {
   float trk_lim;                     // track_half - track_infl
   float trk_p[kMaxHarm + 1];         // r_c = P(cos phi) + sin phi * Q(cos phi): P coefficients
   float trk_q[kMaxHarm];             // Q coefficients (monomial, ascending powers)
+  // FP32 rounding bands (MPMI_PREC_FP32_RECHECK64): a state whose margin to a
+  // constraint is within its band of zero sends the candidate to the FP64
+  // re-roll.  Per component: the band of the binding (least-limit) box.
+  float comp_eps[MPMI_MAX_STATE];
+  float trk_eps;
+};
+
+// What the FP64 re-roll reads (MPMI_PREC_FP32_RECHECK64): K and the safety
+// set in FP64, and the basis as atoms and features (filled for the fixed
+// families too, from their descriptions).  Limits are (double)bound -
+// (double)inflation; the track is r0 + sum_k amp_k sin(f_k phi + p_k),
+// expanded by the angle-addition rule with sin p_k, cos p_k formed once.
+struct Model64 {
+  double K[MPMI_MAX_DIM][8];        // row = feature, col = state component
+  double comp_lim[MPMI_MAX_STATE];  // least limit over the boxes on a component; +inf if none
+  double trk_lim, trk_r0;
+  double trk_amp[4], trk_sinp[4], trk_cosp[4];
+  double sigma[MPMI_MAX_STATE];     // process-noise deviations
+  int32_t trk_freq[4];
+  int32_t trk_n, has_track, comp_mask, n_atoms;
+  int8_t atom_kind[MPMI_MAX_ATOMS];
+  int8_t atom_var[MPMI_MAX_ATOMS];
+  int8_t feat_a[MPMI_MAX_DIM];
+  int8_t feat_b[MPMI_MAX_DIM];
 };
 
 // Packed model: everything a rollout reads, in one device blob.
@@ -69,6 +93,7 @@ struct alignas(256) ModelDev {
   float Kstep[kStepWords];        // race car: the rows of K the step reads, in its order
   uint32_t Rhi[kRTileWords];      // BF16 hi split of R, MFMA B-operand order
   uint32_t Rlo[kRTileWords];      // BF16 lo split of R
+  alignas(256) Model64 m64;       // the FP64 re-roll's copy
 };
 
 // Per-loop selection slot (context-owned device memory).  The memory-side
@@ -554,6 +579,36 @@ __device__ __forceinline__ float min_margin(const ModelDev* __restrict__ md, con
     nan |= (mg != mg);
     mm = fminf(mm, mg);
   }
+  return nan ? NAN : mm;
+}
+
+// min_margin, also OR-ing into *near whether some constraint's margin lies
+// within that constraint's FP32 band of zero (either side; a NaN margin is
+// unsafe and not near).
+template <int NS, int DEG = kMaxHarm>
+__device__ __forceinline__ float min_margin_near(const ModelDev* __restrict__ md, const float* x, bool* near) {
+  const ConstSafety* sc = safety_of(md);
+  float mm = INFINITY;
+  bool nan = false, nr = false;
+  const int mask = sc->comp_mask;
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    if (mask & (1 << k)) {
+      const float mg = sc->comp_lim[k] - fabsf(x[k]);
+      nan |= (mg != mg);
+      mm = fminf(mm, mg);
+      nr |= fabsf(mg) < sc->comp_eps[k];
+    }
+  }
+  if (sc->has_track) {
+    float rho;
+    const float rc = track_centre<DEG>(sc, x, &rho);
+    const float mg = sc->trk_lim - fabsf(rho - rc);
+    nan |= (mg != mg);
+    mm = fminf(mm, mg);
+    nr |= fabsf(mg) < sc->trk_eps;
+  }
+  *near |= nr;
   return nan ? NAN : mm;
 }
 

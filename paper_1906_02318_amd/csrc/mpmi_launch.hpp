@@ -40,10 +40,21 @@ inline int track_degree(const mpmi_system& s) {
   return h;
 }
 
+// With `recheck` non-NULL (FP32_RECHECK64): the FP32 tick lists near-band
+// candidates there, then the FP64 re-roll launch (recheck_grid workgroups)
+// completes the selection.
 hipError_t launch_tick(const mpmi_system& sys, const void* model, const mpmi_tick_desc& d, const float* x_t,
                        const float* u_user, const float* cand, void* slot, mpmi_selection* out,
                        int16_t* fv, float* traj, long long traj_ld, hipStream_t st,
-                       const mpmi_selection* gate = nullptr);
+                       const mpmi_selection* gate = nullptr, void* recheck = nullptr, int recheck_capacity = 0,
+                       int recheck_grid = 0);
+// FP64 re-roll of a tick's listed candidates and the selection (mpmi_recheck64.hip).
+hipError_t launch_recheck64(const mpmi_system& sys, const void* model, const mpmi_tick_desc& d, const float* x_t,
+                            const float* u_user, const float* cand, void* slot, mpmi_selection* out, int16_t* fv,
+                            void* recheck, int capacity, int grid, hipStream_t st);
+size_t multi_recheck_bytes(size_t capacity);
+hipError_t launch_multi_recheck64(const mpmi_loop_desc* loops, const void* models, const int* model_of_loop,
+                                  void* slots, uint64_t* ticks, void* recheck, int n_loops, int grid, hipStream_t st);
 hipError_t launch_rollout(int basis, const void* model, int Nc, int S, int H, const float* x0,
                           const float* cand, float* traj, long long traj_ld, hipStream_t st);
 hipError_t launch_mask(int basis, const void* model, int Nc, int H, const float* traj, long long traj_ld,
@@ -136,6 +147,9 @@ struct MultiPlan {
   size_t work_capacity = 0;
   int n_work = 0;
   int block = 256;
+  int precision = MPMI_PREC_FP32;     // or MPMI_PREC_FP32_RECHECK64
+  void* d_recheck = nullptr;          // MultiRecheck list, one entry per candidate of all loops
+  int* d_model_idx = nullptr;         // loop -> index into d_models
   std::vector<mpmi_loop_desc> host;
   std::vector<int> basis;
   bool noisy = false;  // some loop's model draws process noise

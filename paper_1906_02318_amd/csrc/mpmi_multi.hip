@@ -32,11 +32,14 @@ struct WorkItem {
   uint32_t pad;
 };
 
-template <bool NOISE>
+// RECHECK (precision FP32_RECHECK64): near-band candidates go to the plan's
+// FP64 re-roll list and each tile publishes without a ticket; the re-roll
+// launch that follows finalises every loop and advances the tick counters.
+template <bool NOISE, bool RECHECK>
 __global__ void __launch_bounds__(1024)
 multi_kernel(const mpmi_loop_desc* __restrict__ loops, const ModelDev* __restrict__ models,
              const int* __restrict__ n_tiles, const WorkItem* __restrict__ work, Slot* __restrict__ slots,
-             uint64_t* __restrict__ ticks) {
+             uint64_t* __restrict__ ticks, MultiRecheck* __restrict__ rl) {
   __shared__ float4 sK[kLdsKFloat4];
   const WorkItem w = work[blockIdx.x];
   const mpmi_loop_desc* L = &loops[w.loop];
@@ -63,15 +66,21 @@ multi_kernel(const mpmi_loop_desc* __restrict__ loops, const ModelDev* __restric
   const int c = (int)w.tile * (int)blockDim.x + (int)threadIdx.x;
   CandResult r;
   if (basis == MPMI_BASIS_RACE_CAR)
-    r = evaluate_candidate<MPMI_BASIS_RACE_CAR, NOISE>(md, sK, gp, H, L->x_t, L->u_user, L->cand, c,
-                                                       L->first_violation, nullptr, 0);
+    r = evaluate_candidate<MPMI_BASIS_RACE_CAR, NOISE, kMaxHarm, RECHECK>(md, sK, gp, H, L->x_t, L->u_user, L->cand,
+                                                                         c, L->first_violation, nullptr, 0);
   else if (basis == MPMI_BASIS_BALANCE_BOT)
-    r = evaluate_candidate<MPMI_BASIS_BALANCE_BOT, NOISE>(md, sK, gp, H, L->x_t, L->u_user, L->cand, c,
-                                                          L->first_violation, nullptr, 0);
+    r = evaluate_candidate<MPMI_BASIS_BALANCE_BOT, NOISE, kMaxHarm, RECHECK>(md, sK, gp, H, L->x_t, L->u_user,
+                                                                            L->cand, c, L->first_violation, nullptr, 0);
   else
-    r = evaluate_candidate<MPMI_BASIS_LINEAR, NOISE>(md, sK, gp, H, L->x_t, L->u_user, L->cand, c,
-                                                     L->first_violation, nullptr, 0);
+    r = evaluate_candidate<MPMI_BASIS_LINEAR, NOISE, kMaxHarm, RECHECK>(md, sK, gp, H, L->x_t, L->u_user, L->cand, c,
+                                                                       L->first_violation, nullptr, 0);
   Slot* slot = &slots[w.loop];
+  if constexpr (RECHECK) {
+    wave_append(&rl->count, rl->e, r.near, make_uint4(w.loop, (unsigned int)c, w.model, 0u));
+    publish_partial(r.ks, r.kf, (unsigned int)__popcll(__ballot(r.safe_counted)),
+                    (unsigned int)__popcll(__ballot(r.near)), slot, w.tile);
+    return;
+  }
   if (reduce_and_publish(r.ks, r.kf, r.safe_counted, slot, (unsigned int)n_tiles[w.loop], w.tile) &&
       threadIdx.x == 0) {
     finalize<MPMI_MAX_INPUT>(md, gp, L->cand, L->u_user, H, slot, L->out);
@@ -108,6 +117,16 @@ hipError_t multi_alloc(MultiPlan& p) {
     p.model_of_loop[l] = k;
   }
   if ((e = hipMalloc(&p.d_models, sizeof(ModelDev) * p.model_src.size())) != hipSuccess) return e;
+  // FP64 re-roll list: room for every candidate of every loop; count and
+  // ticket start at zero (the re-roll launch leaves them at zero).
+  size_t total = 0;
+  for (const auto& l : p.host) total += (size_t)l.n_cand + 1;
+  if ((e = hipMalloc(&p.d_recheck, multi_recheck_bytes(total))) != hipSuccess) return e;
+  if ((e = hipMemset(p.d_recheck, 0, 256)) != hipSuccess) return e;
+  if ((e = hipMalloc(&p.d_model_idx, sizeof(int) * p.n_loops)) != hipSuccess) return e;
+  if ((e = hipMemcpy(p.d_model_idx, p.model_of_loop.data(), sizeof(int) * p.n_loops, hipMemcpyHostToDevice)) !=
+      hipSuccess)
+    return e;
   std::vector<uint64_t> tk(p.n_loops);
   for (int l = 0; l < p.n_loops; ++l) tk[l] = p.host[l].tick;
   if ((e = hipMemcpy(p.d_ticks, tk.data(), sizeof(uint64_t) * p.n_loops, hipMemcpyHostToDevice)) != hipSuccess)
@@ -127,6 +146,10 @@ void multi_free(MultiPlan& p) {
   if (p.d_slots) (void)hipFree(p.d_slots);
   if (p.d_ticks) (void)hipFree(p.d_ticks);
   if (p.d_models) (void)hipFree(p.d_models);
+  if (p.d_recheck) (void)hipFree(p.d_recheck);
+  if (p.d_model_idx) (void)hipFree(p.d_model_idx);
+  p.d_recheck = nullptr;
+  p.d_model_idx = nullptr;
   p.d_loops = nullptr;
   p.d_ntiles = nullptr;
   p.d_work = nullptr;
@@ -178,13 +201,24 @@ hipError_t multi_plan(MultiPlan& p, int block) {
 }
 
 hipError_t multi_launch(const MultiPlan& p, hipStream_t st) {
-  if (p.noisy)
-    multi_kernel<true><<<p.n_work, p.block, 0, st>>>(p.d_loops, p.d_models, p.d_ntiles, p.d_work, p.d_slots,
-                                                     p.d_ticks);
+  MultiRecheck* rl = (MultiRecheck*)p.d_recheck;
+  const bool re = p.precision == MPMI_PREC_FP32_RECHECK64;
+  if (p.noisy && re)
+    multi_kernel<true, true><<<p.n_work, p.block, 0, st>>>(p.d_loops, p.d_models, p.d_ntiles, p.d_work, p.d_slots,
+                                                           p.d_ticks, rl);
+  else if (p.noisy)
+    multi_kernel<true, false><<<p.n_work, p.block, 0, st>>>(p.d_loops, p.d_models, p.d_ntiles, p.d_work, p.d_slots,
+                                                            p.d_ticks, rl);
+  else if (re)
+    multi_kernel<false, true><<<p.n_work, p.block, 0, st>>>(p.d_loops, p.d_models, p.d_ntiles, p.d_work, p.d_slots,
+                                                            p.d_ticks, rl);
   else
-    multi_kernel<false><<<p.n_work, p.block, 0, st>>>(p.d_loops, p.d_models, p.d_ntiles, p.d_work, p.d_slots,
-                                                      p.d_ticks);
-  return hipGetLastError();
+    multi_kernel<false, false><<<p.n_work, p.block, 0, st>>>(p.d_loops, p.d_models, p.d_ntiles, p.d_work, p.d_slots,
+                                                             p.d_ticks, rl);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !re) return e;
+  return launch_multi_recheck64(p.d_loops, p.d_models, p.d_model_idx, p.d_slots, p.d_ticks, p.d_recheck, p.n_loops,
+                                device_cu_count() * 4, st);
 }
 
 }  // namespace mpmi

@@ -1,0 +1,393 @@
+// FP64 re-roll of the candidates an FP32 tick left in its rounding band
+// (precision MPMI_PREC_FP32_RECHECK64).
+//
+// A minimal-intervention choice lies on the boundary of the safe input set
+// whenever the user's own input is unsafe, so the candidate the selection
+// picks is often one whose predicted margin is within FP32 rounding of zero.
+// The FP32 tick therefore lists every candidate with such a margin at some
+// checked step instead of publishing it; this launch predicts each listed
+// candidate again from x_t with K, the basis, the process noise and the
+// margins in FP64 (Sec. IV-A's prediction and Sec. IV-B's checks), writes its
+// first violation, publishes its keys, and the last workgroup finalises the
+// selection.  Every verdict of the tick is then that of an FP64 rollout
+// whenever the bands cover the FP32 margin error.
+//
+// One candidate per lane, 64-lane workgroups: a tick lists at most a few
+// percent of its candidates, so the launch is latency-bound and small
+// workgroups spread the listed candidates over more compute units.  The
+// race-car basis runs a folded step (input terms folded once per segment, as
+// in the FP32 tick); the other bases are evaluated from their atom/feature
+// description, the atoms going through a per-lane column of LDS.
+#include <hip/hip_runtime.h>
+
+#include "mpmi_device.hpp"
+#include "mpmi_launch.hpp"
+#include "mpmi_tick_common.hpp"
+
+namespace mpmi {
+
+constexpr int kR64Block = 64;
+
+// The coefficient pointer behind an opaque zero offset, taken at every step:
+// without it the compiler hoists the loop-invariant coefficient loads out of
+// the horizon loop, and the 162 doubles of the race-car step overflow the
+// register file.
+__device__ __forceinline__ const double* opaque_coeffs(const double* p) {
+  int off = 0;
+  asm volatile("" : "+s"(off));
+  return p + off;
+}
+
+// Least margin of x in FP64 (NaN if any margin is NaN): boxes per component,
+// then the track, r_c(phi) = r0 + sum_q amp_q (sin(f_q phi) cos p_q +
+// cos(f_q phi) sin p_q) with sin(k phi), cos(k phi) from (cos phi, sin phi) =
+// (x0, x1) / rho by the multiple-angle recurrences.
+__device__ __forceinline__ double margin64(const Model64* __restrict__ m, const double* x) {
+  double mm = INFINITY;
+  bool nan = false;
+  const int mask = m->comp_mask;
+#pragma unroll
+  for (int k = 0; k < MPMI_MAX_STATE; ++k) {
+    if (mask & (1 << k)) {
+      const double mg = m->comp_lim[k] - fabs(x[k]);
+      nan |= (mg != mg);
+      mm = fmin(mm, mg);
+    }
+  }
+  if (m->has_track) {
+    const double rho = sqrt(x[0] * x[0] + x[1] * x[1]);
+    const double c1 = x[0] / rho, s1 = x[1] / rho;
+    double cs[kMaxHarm + 1], sn[kMaxHarm + 1];
+    cs[0] = 1.0;
+    sn[0] = 0.0;
+    cs[1] = c1;
+    sn[1] = s1;
+#pragma unroll
+    for (int k = 1; k < kMaxHarm; ++k) {
+      cs[k + 1] = 2.0 * c1 * cs[k] - cs[k - 1];
+      sn[k + 1] = 2.0 * c1 * sn[k] - sn[k - 1];
+    }
+    double rc = m->trk_r0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (q < m->trk_n) {
+        const int f = m->trk_freq[q];
+        double cf = 1.0, sf = 0.0;
+#pragma unroll
+        for (int k = 1; k <= kMaxHarm; ++k) {
+          cf = (f == k) ? cs[k] : cf;
+          sf = (f == k) ? sn[k] : sf;
+        }
+        rc += m->trk_amp[q] * (sf * m->trk_cosp[q] + cf * m->trk_sinp[q]);
+      }
+    }
+    const double mg = m->trk_lim - fabs(rho - rc);
+    nan |= (mg != mg);
+    mm = fmin(mm, mg);
+  }
+  return nan ? NAN : mm;
+}
+
+// A basis given by its description: atoms of w = [x; u] into this lane's LDS
+// column (stride kR64Block), then x' = sum_f atom[a_f] atom[b_f] K[f].
+__device__ __forceinline__ void step64_described(const Model64* __restrict__ m, const double* __restrict__ K, int n,
+                                                 int D, const double* u, double* x, double* at) {
+  const int na = m->n_atoms;
+  for (int q = 0; q < na; ++q) {
+    const int kd = m->atom_kind[q], v = m->atom_var[q];
+    double w = 0.0;
+#pragma unroll
+    for (int k = 0; k < MPMI_MAX_STATE; ++k) w = (v == k) ? x[k] : w;
+#pragma unroll
+    for (int j = 0; j < MPMI_MAX_INPUT; ++j) w = (v == n + j) ? u[j] : w;
+    double a = 1.0;
+    if (kd == MPMI_ATOM_VAR) a = w;
+    else if (kd == MPMI_ATOM_SIN) a = sin(w);
+    else if (kd == MPMI_ATOM_COS) a = cos(w);
+    at[q * kR64Block] = a;
+  }
+  double y[MPMI_MAX_STATE];
+#pragma unroll
+  for (int j = 0; j < MPMI_MAX_STATE; ++j) y[j] = 0.0;
+  K = opaque_coeffs(K);
+  for (int f = 0; f < D; ++f) {
+    const double p = at[m->feat_a[f] * kR64Block] * at[m->feat_b[f] * kR64Block];
+#pragma unroll
+    for (int j = 0; j < MPMI_MAX_STATE; ++j) y[j] = fma(p, K[f * 8 + j], y[j]);
+  }
+#pragma unroll
+  for (int j = 0; j < MPMI_MAX_STATE; ++j) x[j] = (j < n) ? y[j] : 0.0;
+}
+
+// Race car, w = [x, y, psi, vx, vy, r, delta, a]: the FP32 tick's folded
+// step in FP64 (K row stride 8).
+struct Stepper64RaceCar {
+  double cu[6], L[6][6], Ts[6], Tc[6];
+  __device__ __forceinline__ void set_input(const double* __restrict__ Kin, const double* u) {
+    const double* K = opaque_coeffs(Kin);
+    const double d = u[0], a = u[1];
+    const double sd = sin(d), cd = cos(d);
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      double c = K[0 * 8 + j];
+      c = fma(d, K[7 * 8 + j], c);
+      c = fma(a, K[8 * 8 + j], c);
+      c = fma(d * d, K[quad_index(6, 6, 8) * 8 + j], c);
+      c = fma(d * a, K[quad_index(6, 7, 8) * 8 + j], c);
+      c = fma(a * a, K[quad_index(7, 7, 8) * 8 + j], c);
+      c = fma(sd, K[47 * 8 + j], c);
+      c = fma(cd, K[48 * 8 + j], c);
+      c = fma(a * sd, K[63 * 8 + j], c);
+      cu[j] = c;
+#pragma unroll
+      for (int k = 0; k < 6; ++k)
+        L[k][j] = fma(a, K[quad_index(k, 7, 8) * 8 + j], fma(d, K[quad_index(k, 6, 8) * 8 + j], K[(1 + k) * 8 + j]));
+      L[3][j] = fma(cd, K[60 * 8 + j], fma(sd, K[57 * 8 + j], L[3][j]));
+      L[4][j] = fma(cd, K[61 * 8 + j], fma(sd, K[58 * 8 + j], L[4][j]));
+      L[5][j] = fma(cd, K[62 * 8 + j], fma(sd, K[59 * 8 + j], L[5][j]));
+      Ts[j] = fma(a, K[52 * 8 + j], K[45 * 8 + j]);
+      Tc[j] = fma(a, K[56 * 8 + j], K[46 * 8 + j]);
+    }
+  }
+  __device__ __forceinline__ void step(const double* __restrict__ Kin, double* x) {
+    const double* K = opaque_coeffs(Kin);
+    double sp, cp;
+    sincos(x[2], &sp, &cp);
+    double p[kRcStepRows];
+    int q = 0;
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+#pragma unroll
+      for (int l = k; l < 6; ++l) p[q++] = x[k] * x[l];
+    p[21] = sp * x[3]; p[22] = sp * x[4]; p[23] = sp * x[5];
+    p[24] = cp * x[3]; p[25] = cp * x[4]; p[26] = cp * x[5];
+    double y[6];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      double v = fma(Tc[j], cp, fma(Ts[j], sp, cu[j]));
+#pragma unroll
+      for (int k = 0; k < 6; ++k) v = fma(L[k][j], x[k], v);
+      y[j] = v;
+    }
+#pragma unroll
+    for (int r = 0; r < kRcStepRows; ++r) {
+      const double* row = K + rc_step_row(r) * 8;
+#pragma unroll
+      for (int j = 0; j < 6; ++j) y[j] = fma(p[r], row[j], y[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < 6; ++j) x[j] = y[j];
+  }
+};
+
+// First violation (1..H, or H + 1) of candidate c (c < Nc) predicted in FP64
+// from x_t.  K: the model's FP64 K (LDS copy or the blob's); at: this lane's
+// LDS column for the described bases.
+template <bool RC>
+__device__ int evaluate64(const ModelDev* __restrict__ md, const double* __restrict__ K, const GenParams& gp, int H,
+                          const float* __restrict__ x_t, const float* __restrict__ u_user,
+                          const float* __restrict__ cand, int c, double* at) {
+  const Model64* m = &md->m64;
+  const int n = md->n, mi = md->m, S = gp.n_seg, D = md->dim;
+  double x[MPMI_MAX_STATE], u[MPMI_MAX_INPUT];
+#pragma unroll
+  for (int j = 0; j < MPMI_MAX_STATE; ++j) x[j] = (j < n) ? (double)x_t[j] : 0.0;
+#pragma unroll
+  for (int j = 0; j < MPMI_MAX_INPUT; ++j) u[j] = (j < mi) ? (double)cand_value(gp, md, cand, u_user, c, 0, j) : 0.0;
+  Stepper64RaceCar stp;
+  if constexpr (RC) stp.set_input(K, u);
+  const bool noisy = md->has_noise != 0;
+  const uint64_t pre = noisy ? hash_prefix(gp.seed, gp.tick, (uint64_t)(uint32_t)gp.loop, (uint64_t)c) : 0ull;
+  int gcur = 0;
+  for (int s = 1; s <= H; ++s) {
+    const int g = ((s - 1) * S) / H;
+    if (g != gcur) {
+      gcur = g;
+#pragma unroll
+      for (int j = 0; j < MPMI_MAX_INPUT; ++j)
+        u[j] = (j < mi) ? (double)cand_value(gp, md, cand, u_user, c, g, j) : 0.0;
+      if constexpr (RC) stp.set_input(K, u);
+    }
+    if constexpr (RC) stp.step(K, x);
+    else step64_described(m, K, n, D, u, x, at);
+    if (noisy) {
+      // Alg. 2's z_i: the draws of the FP32 tick, Box-Muller in FP64.
+#pragma unroll
+      for (int q = 0; q < MPMI_MAX_STATE / 2; ++q) {
+        if (2 * q < n) {
+          const uint64_t h = hash_finish(pre, kNoiseSlot + 4ull * (uint64_t)(s - 1) + (uint64_t)q);
+          const double u1 = ((double)(h >> 40) + 1.0) * 0x1p-24;
+          const double u2 = (double)((h >> 16) & 0xFFFFFFull) * 0x1p-24;
+          const double r = sqrt(-2.0 * log(u1));
+          const double ang = 6.283185307179586 * u2;
+          x[2 * q] = x[2 * q] + m->sigma[2 * q] * (r * cos(ang));
+          if (2 * q + 1 < n) x[2 * q + 1] = x[2 * q + 1] + m->sigma[2 * q + 1] * (r * sin(ang));
+        }
+      }
+    }
+    if (!(margin64(m, x) > 0.0)) return s;
+  }
+  return H + 1;
+}
+
+// Keys of a re-rolled candidate (cost in FP32 from its first-segment input,
+// as in the FP32 tick).
+__device__ __forceinline__ void keys_of(const ModelDev* __restrict__ md, const GenParams& gp,
+                                        const float* __restrict__ cand, const float* __restrict__ u_user, int c,
+                                        int fv, int H, unsigned long long* ks, unsigned long long* kf, bool* safe) {
+  float u0[MPMI_MAX_INPUT];
+#pragma unroll
+  for (int j = 0; j < MPMI_MAX_INPUT; ++j) u0[j] = (j < md->m) ? cand_value(gp, md, cand, u_user, c, 0, j) : 0.0f;
+  const float cst = cost_of<MPMI_MAX_INPUT>(md, u0, u_user);
+  *safe = fv == H + 1;
+  *ks = *safe ? safe_key(cst, c) : kKeyNone;
+  *kf = *safe ? kKeyNone : fallback_key(fv, cst, c);
+}
+
+// ---------------------------------------------------------------------------
+// Single loop: re-roll the context's list, publish, finalise.
+// ---------------------------------------------------------------------------
+template <bool RC>
+__global__ void __launch_bounds__(kR64Block)
+recheck64_kernel(const ModelDev* __restrict__ md, GenParams gp, int H, const float* __restrict__ x_t,
+                 const float* __restrict__ u_user, const float* __restrict__ cand, Slot* __restrict__ slot,
+                 mpmi_selection* __restrict__ out, int16_t* __restrict__ fv_out, RecheckList* __restrict__ rl,
+                 int capacity) {
+  __shared__ double sK[MPMI_MAX_DIM * 8];
+  __shared__ double sAt[RC ? 1 : MPMI_MAX_ATOMS * kR64Block];
+  const unsigned int cnt_raw = rl->count;
+  const int count = (int)(cnt_raw < (unsigned int)capacity ? cnt_raw : (unsigned int)capacity);
+  const int lane = threadIdx.x;
+  unsigned long long ks = kKeyNone, kf = kKeyNone;
+  unsigned int n_safe = 0;
+  if ((int)blockIdx.x * kR64Block < count) {  // uniform across the workgroup
+    const double* Kg = &md->m64.K[0][0];
+    for (int e = lane; e < MPMI_MAX_DIM * 8; e += kR64Block) sK[e] = Kg[e];
+    __syncthreads();
+    for (int e0 = blockIdx.x * kR64Block; e0 < count; e0 += gridDim.x * kR64Block) {
+      const int e = e0 + lane;
+      if (e < count) {
+        const int c = rl->idx[e];
+        const int fv = evaluate64<RC>(md, sK, gp, H, x_t, u_user, cand, c, sAt + lane);
+        if (fv_out) fv_out[c] = (int16_t)fv;
+        unsigned long long a, b;
+        bool safe;
+        keys_of(md, gp, cand, u_user, c, fv, H, &a, &b, &safe);
+        ks = a < ks ? a : ks;
+        kf = b < kf ? b : kf;
+        n_safe += (safe && c > 0) ? 1u : 0u;
+      }
+    }
+  }
+  unsigned int wsum = n_safe;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) wsum += __shfl_xor(wsum, off, 64);
+  if (publish_wave_counted(ks, kf, wsum, slot, gridDim.x, blockIdx.x) && threadIdx.x == 0) {
+    finalize<MPMI_MAX_INPUT>(md, gp, cand, u_user, H, slot, out);
+    rl->count = 0u;
+    __threadfence();
+  }
+}
+
+hipError_t launch_recheck64(const mpmi_system& sys, const void* model, const mpmi_tick_desc& d, const float* x_t,
+                            const float* u_user, const float* cand, void* slot, mpmi_selection* out, int16_t* fv,
+                            void* recheck, int capacity, int grid, hipStream_t st) {
+  GenParams gp;
+  gp.seed = d.seed;
+  gp.tick = d.tick;
+  gp.loop = d.loop;
+  gp.gen = d.gen;
+  gp.n_cand = d.n_cand;
+  gp.n_seg = d.n_seg;
+  for (int j = 0; j < MPMI_MAX_INPUT; ++j) gp.grid[j] = d.grid[j] > 0 ? d.grid[j] : 1;
+  const ModelDev* md = (const ModelDev*)model;
+  if (sys.basis == MPMI_BASIS_RACE_CAR)
+    recheck64_kernel<true><<<grid, kR64Block, 0, st>>>(md, gp, d.horizon, x_t, u_user, cand, (Slot*)slot, out, fv,
+                                                       (RecheckList*)recheck, capacity);
+  else
+    recheck64_kernel<false><<<grid, kR64Block, 0, st>>>(md, gp, d.horizon, x_t, u_user, cand, (Slot*)slot, out, fv,
+                                                        (RecheckList*)recheck, capacity);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Many loops: re-roll every loop's listed candidates (each entry names its
+// loop and model), publish per lane into the loop's slot, then the last
+// workgroup finalises every loop and advances the tick counters.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ GenParams loop_gen(const mpmi_loop_desc* __restrict__ L, uint64_t tick, int loop) {
+  GenParams gp;
+  gp.seed = L->seed;
+  gp.tick = tick;
+  gp.loop = loop;
+  gp.gen = L->gen;
+  gp.n_cand = L->n_cand;
+  gp.n_seg = L->n_seg;
+#pragma unroll
+  for (int j = 0; j < MPMI_MAX_INPUT; ++j) gp.grid[j] = L->grid[j] > 0 ? L->grid[j] : 1;
+  return gp;
+}
+
+__global__ void __launch_bounds__(kR64Block)
+multi_recheck64_kernel(const mpmi_loop_desc* __restrict__ loops, const ModelDev* __restrict__ models,
+                       const int* __restrict__ model_of_loop, Slot* __restrict__ slots, uint64_t* __restrict__ ticks,
+                       MultiRecheck* __restrict__ rl, int n_loops) {
+  __shared__ double sAt[MPMI_MAX_ATOMS * kR64Block];
+  __shared__ int s_last;
+  const int lane = threadIdx.x;
+  const int count = (int)rl->count;
+  for (int e0 = blockIdx.x * kR64Block; e0 < count; e0 += gridDim.x * kR64Block) {
+    const int e = e0 + lane;
+    if (e < count) {
+      const uint4 en = rl->e[e];
+      const int loop = (int)en.x, c = (int)en.y;
+      const mpmi_loop_desc* L = &loops[loop];
+      const ModelDev* md = models + en.z;
+      const GenParams gp = loop_gen(L, ticks[loop], loop);
+      const int H = L->horizon;
+      const int fv = md->sys.basis == MPMI_BASIS_RACE_CAR
+                         ? evaluate64<true>(md, &md->m64.K[0][0], gp, H, L->x_t, L->u_user, L->cand, c, sAt + lane)
+                         : evaluate64<false>(md, &md->m64.K[0][0], gp, H, L->x_t, L->u_user, L->cand, c, sAt + lane);
+      if (L->first_violation) L->first_violation[c] = (int16_t)fv;
+      unsigned long long a, b;
+      bool safe;
+      keys_of(md, gp, L->cand, L->u_user, c, fv, H, &a, &b, &safe);
+      SubSlot* ss = &slots[loop].sub[c % kSubSlots];
+      if (a != kKeyNone) atomicMin(&ss->key_safe, a);
+      if (b != kKeyNone) atomicMin(&ss->key_fb, b);
+      if (safe && c > 0) atomicAdd(&ss->count, 1ull);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    s_last = atomicAdd(&rl->done, 1u) == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  for (int l = lane; l < n_loops; l += kR64Block) {
+    const mpmi_loop_desc* L = &loops[l];
+    const ModelDev* md = models + model_of_loop[l];
+    const GenParams gp = loop_gen(L, ticks[l], l);
+    finalize<MPMI_MAX_INPUT>(md, gp, L->cand, L->u_user, L->horizon, &slots[l], L->out);
+    ticks[l] = gp.tick + 1;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    rl->count = 0u;
+    rl->done = 0u;
+    __threadfence();
+  }
+}
+
+size_t multi_recheck_bytes(size_t capacity) { return sizeof(MultiRecheck) + sizeof(uint4) * capacity; }
+
+hipError_t launch_multi_recheck64(const mpmi_loop_desc* loops, const void* models, const int* model_of_loop,
+                                  void* slots, uint64_t* ticks, void* recheck, int n_loops, int grid, hipStream_t st) {
+  multi_recheck64_kernel<<<grid, kR64Block, 0, st>>>(loops, (const ModelDev*)models, model_of_loop, (Slot*)slots,
+                                                     ticks, (MultiRecheck*)recheck, n_loops);
+  return hipGetLastError();
+}
+
+}  // namespace mpmi

@@ -23,13 +23,17 @@ namespace mpmi {
 // ---------------------------------------------------------------------------
 // Fused tick, FP32
 // ---------------------------------------------------------------------------
-template <int BASIS, bool NOISE, int DEG>
+// RECHECK (precision FP32_RECHECK64): candidates with a checked margin within
+// the FP32 band are appended to the recheck list instead of publishing, and
+// the workgroup publishes without a ticket; the FP64 re-roll launch that
+// follows completes the slot.
+template <int BASIS, bool NOISE, int DEG, bool RECHECK>
 __global__ void __launch_bounds__(1024)
 tick_fp32_kernel(const ModelDev* __restrict__ md, GenParams gp, int H, const float* __restrict__ x_t,
                  const float* __restrict__ u_user, const float* __restrict__ cand,
                  Slot* __restrict__ slot, mpmi_selection* __restrict__ out,
                  int16_t* __restrict__ fv_out, float* __restrict__ traj, long long traj_ld,
-                 const mpmi_selection* __restrict__ gate) {
+                 const mpmi_selection* __restrict__ gate, RecheckList* __restrict__ rl) {
   constexpr int MS = Dims<BASIS>::M;
   // Gated form (fallback after a proposal tick): nothing to do if the gate
   // selection already found a safe candidate.  Uniform across the grid.
@@ -37,10 +41,16 @@ tick_fp32_kernel(const ModelDev* __restrict__ md, GenParams gp, int H, const flo
   __shared__ float4 sK[kLdsKFloat4];
   stage_K<BASIS>(md, sK);
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  const CandResult r =
-      evaluate_candidate<BASIS, NOISE, DEG>(md, sK, gp, H, x_t, u_user, cand, c, fv_out, traj, (size_t)traj_ld);
-  if (reduce_and_publish(r.ks, r.kf, r.safe_counted, slot, gridDim.x, blockIdx.x) && threadIdx.x == 0)
-    finalize<MS>(md, gp, cand, u_user, H, slot, out);
+  const CandResult r = evaluate_candidate<BASIS, NOISE, DEG, RECHECK>(md, sK, gp, H, x_t, u_user, cand, c, fv_out,
+                                                                      traj, (size_t)traj_ld);
+  if constexpr (RECHECK) {
+    wave_append(&rl->count, rl->idx, r.near, c);
+    publish_partial(r.ks, r.kf, (unsigned int)__popcll(__ballot(r.safe_counted)),
+                    (unsigned int)__popcll(__ballot(r.near)), slot, blockIdx.x);
+  } else {
+    if (reduce_and_publish(r.ks, r.kf, r.safe_counted, slot, gridDim.x, blockIdx.x) && threadIdx.x == 0)
+      finalize<MS>(md, gp, cand, u_user, H, slot, out);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -223,6 +233,11 @@ __global__ void pack_kernel(mpmi_system sys, int dim, int state_feat0, const dou
     const int f = e >> 3, j = e & 7;
     md->K[f][j] = (f < dim && j < n) ? (float)K[(size_t)f * n + j] : 0.0f;
   }
+  // FP64 K for the re-roll.
+  for (int e = t; e < MPMI_MAX_DIM * 8; e += blockDim.x) {
+    const int f = e >> 3, j = e & 7;
+    md->m64.K[f][j] = (f < dim && j < n) ? K[(size_t)f * n + j] : 0.0;
+  }
   // Race-car step table (the rows the per-step contraction reads, in order).
   for (int e = t; e < kStepWords; e += blockDim.x) {
     const int q = e / 6, j = e % 6;
@@ -267,6 +282,13 @@ __global__ void pack_kernel(mpmi_system sys, int dim, int state_feat0, const dou
       md->safe.comp_lim[k] = fminf(md->safe.comp_lim[k], md->safe.bb_lim[b]);
     }
     md->safe.comp_mask = cmask;
+    // FP32 bands: per component the band of its binding (least-limit) box.
+    for (int k = 0; k < MPMI_MAX_STATE; ++k) md->safe.comp_eps[k] = 0.0f;
+    for (int b = 0; b < sys.n_box; ++b) {
+      const int k = sys.box_index[b];
+      if (md->safe.bb_lim[b] == md->safe.comp_lim[k]) md->safe.comp_eps[k] = fmaxf(md->safe.comp_eps[k], sys.eps32_box[b]);
+    }
+    md->safe.trk_eps = sys.has_track ? sys.eps32_track : 0.0f;
     md->safe.n_box = sys.n_box;
     md->safe.has_track = sys.has_track;
     md->safe.trk_lim = (float)((double)sys.track_half - (double)sys.track_infl);
@@ -304,6 +326,36 @@ __global__ void pack_kernel(mpmi_system sys, int dim, int state_feat0, const dou
     for (int k = 0; k <= kMaxHarm; ++k) md->safe.trk_p[k] = (float)P[k];
     for (int k = 0; k < kMaxHarm; ++k) md->safe.trk_q[k] = (float)Q[k];
     md->safe.hmax = hmax;
+    // The FP64 re-roll's safety set, noise and basis description.
+    Model64* m = &md->m64;
+    m->comp_mask = cmask;
+    for (int k = 0; k < MPMI_MAX_STATE; ++k) m->comp_lim[k] = INFINITY;
+    for (int b = 0; b < sys.n_box; ++b) {
+      const int k = sys.box_index[b];
+      const double lim = (double)sys.box_bound[b] - (double)sys.box_infl[b];
+      m->comp_lim[k] = lim < m->comp_lim[k] ? lim : m->comp_lim[k];
+    }
+    m->has_track = sys.has_track;
+    m->trk_n = sys.has_track ? sys.track_n : 0;
+    m->trk_lim = (double)sys.track_half - (double)sys.track_infl;
+    m->trk_r0 = sys.track_r0;
+    for (int q = 0; q < 4; ++q) {
+      const bool on = sys.has_track && q < sys.track_n;
+      m->trk_freq[q] = on ? sys.track_freq[q] : 0;
+      m->trk_amp[q] = on ? (double)sys.track_amp[q] : 0.0;
+      m->trk_sinp[q] = on ? sin((double)sys.track_phase[q]) : 0.0;
+      m->trk_cosp[q] = on ? cos((double)sys.track_phase[q]) : 1.0;
+    }
+    for (int j = 0; j < MPMI_MAX_STATE; ++j) m->sigma[j] = j < n ? (double)sys.noise_sigma[j] : 0.0;
+    m->n_atoms = sys.n_atoms;
+    for (int q = 0; q < MPMI_MAX_ATOMS; ++q) {
+      m->atom_kind[q] = sys.atom_kind[q];
+      m->atom_var[q] = sys.atom_var[q];
+    }
+    for (int f = 0; f < MPMI_MAX_DIM; ++f) {
+      m->feat_a[f] = sys.feat_a[f];
+      m->feat_b[f] = sys.feat_b[f];
+    }
     int noisy = 0;
     for (int j = 0; j < 8; ++j) noisy |= (j < n && sys.noise_sigma[j] > 0.0f) ? 1 : 0;
     md->has_noise = noisy;
@@ -341,47 +393,61 @@ template <int BASIS, int DEG>
 static void tick_dispatch(bool noisy, unsigned grid, int block, hipStream_t st, const ModelDev* md,
                           const GenParams& gp, int H, const float* x_t, const float* u_user, const float* cand,
                           Slot* sl, mpmi_selection* out, int16_t* fv, float* traj, long long ld,
-                          const mpmi_selection* gate) {
-  if (noisy)
-    tick_fp32_kernel<BASIS, true, DEG>
-        <<<grid, block, 0, st>>>(md, gp, H, x_t, u_user, cand, sl, out, fv, traj, ld, gate);
-  else
-    tick_fp32_kernel<BASIS, false, DEG>
-        <<<grid, block, 0, st>>>(md, gp, H, x_t, u_user, cand, sl, out, fv, traj, ld, gate);
+                          const mpmi_selection* gate, RecheckList* rl) {
+  if (rl) {
+    if (noisy)
+      tick_fp32_kernel<BASIS, true, DEG, true>
+          <<<grid, block, 0, st>>>(md, gp, H, x_t, u_user, cand, sl, out, fv, traj, ld, gate, rl);
+    else
+      tick_fp32_kernel<BASIS, false, DEG, true>
+          <<<grid, block, 0, st>>>(md, gp, H, x_t, u_user, cand, sl, out, fv, traj, ld, gate, rl);
+  } else {
+    if (noisy)
+      tick_fp32_kernel<BASIS, true, DEG, false>
+          <<<grid, block, 0, st>>>(md, gp, H, x_t, u_user, cand, sl, out, fv, traj, ld, gate, rl);
+    else
+      tick_fp32_kernel<BASIS, false, DEG, false>
+          <<<grid, block, 0, st>>>(md, gp, H, x_t, u_user, cand, sl, out, fv, traj, ld, gate, rl);
+  }
 }
 
 hipError_t launch_tick(const mpmi_system& sys, const void* model, const mpmi_tick_desc& d, const float* x_t,
                        const float* u_user, const float* cand, void* slot, mpmi_selection* out,
-                       int16_t* fv, float* traj, long long traj_ld, hipStream_t st, const mpmi_selection* gate) {
+                       int16_t* fv, float* traj, long long traj_ld, hipStream_t st, const mpmi_selection* gate,
+                       void* recheck, int recheck_capacity, int recheck_grid) {
   const GenParams gp = make_gen(d);
   const int block = d.block > 0 ? d.block : 256;
   const unsigned grid = blocks_for((long long)d.n_cand + 1, block);
   const ModelDev* md = (const ModelDev*)model;
   Slot* sl = (Slot*)slot;
   const bool noisy = system_noisy(sys);
+  RecheckList* rl = (RecheckList*)recheck;
   switch (sys.basis) {
     case MPMI_BASIS_LINEAR:
       tick_dispatch<MPMI_BASIS_LINEAR, kMaxHarm>(noisy, grid, block, st, md, gp, d.horizon, x_t, u_user, cand, sl,
-                                                 out, fv, traj, traj_ld, gate);
+                                                 out, fv, traj, traj_ld, gate, rl);
       break;
     case MPMI_BASIS_BALANCE_BOT:
       tick_dispatch<MPMI_BASIS_BALANCE_BOT, kMaxHarm>(noisy, grid, block, st, md, gp, d.horizon, x_t, u_user, cand,
-                                                      sl, out, fv, traj, traj_ld, gate);
+                                                      sl, out, fv, traj, traj_ld, gate, rl);
       break;
     case MPMI_BASIS_CUSTOM:
       tick_dispatch<MPMI_BASIS_CUSTOM, kMaxHarm>(noisy, grid, block, st, md, gp, d.horizon, x_t, u_user, cand, sl,
-                                                 out, fv, traj, traj_ld, gate);
+                                                 out, fv, traj, traj_ld, gate, rl);
       break;
     default:
       if (track_degree(sys) <= kSmallTrackDeg)
         tick_dispatch<MPMI_BASIS_RACE_CAR, kSmallTrackDeg>(noisy, grid, block, st, md, gp, d.horizon, x_t, u_user,
-                                                           cand, sl, out, fv, traj, traj_ld, gate);
+                                                           cand, sl, out, fv, traj, traj_ld, gate, rl);
       else
         tick_dispatch<MPMI_BASIS_RACE_CAR, kMaxHarm>(noisy, grid, block, st, md, gp, d.horizon, x_t, u_user, cand,
-                                                     sl, out, fv, traj, traj_ld, gate);
+                                                     sl, out, fv, traj, traj_ld, gate, rl);
       break;
   }
-  return hipGetLastError();
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !rl) return e;
+  return launch_recheck64(sys, model, d, x_t, u_user, cand, slot, out, fv, recheck, recheck_capacity, recheck_grid,
+                          st);
 }
 
 hipError_t launch_rollout(int basis, const void* model, int Nc, int S, int H, const float* x0,

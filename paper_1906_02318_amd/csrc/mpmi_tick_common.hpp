@@ -7,6 +7,24 @@
 
 namespace mpmi {
 
+// Candidates of one tick left to a re-roll launch (BF16X3: FP32 re-roll;
+// FP32_RECHECK64: FP64 re-roll), in context-owned device memory.
+struct RecheckList {
+  unsigned int count;
+  unsigned int pad[63];
+  int idx[1];  // capacity entries follow
+};
+
+// Candidates of a many-loop tick left to the FP64 re-roll: {loop, candidate,
+// model index, 0}; the last workgroup of the re-roll launch (ticket `done`)
+// finalises every loop.
+struct MultiRecheck {
+  unsigned int count;
+  unsigned int done;
+  unsigned int pad[62];
+  uint4 e[1];  // capacity entries follow
+};
+
 // Candidate source modes: the three public generators plus FULL (an explicit
 // array that already holds candidate 0 in column 0).
 constexpr int kGenFull = 3;
@@ -164,7 +182,59 @@ __device__ void finalize(const ModelDev* __restrict__ md, const GenParams& gp,
 struct CandResult {
   unsigned long long ks, kf;
   bool safe_counted;
+  bool near;  // NEAR instances: some checked state lies within the FP32 band of a constraint
 };
+
+// Publishes a workgroup's keys and counts (cnt: the wave's safe count, n_re:
+// the wave's re-rolled count, both uniform across the wave) into sub-slot
+// part % kSubSlots without taking a ticket: a later launch completes the
+// slot.  Every thread of the workgroup calls it.
+__device__ __forceinline__ void publish_partial(unsigned long long ks, unsigned long long kf, unsigned int cnt,
+                                                unsigned int n_re, Slot* __restrict__ slot, unsigned int part) {
+  __shared__ unsigned long long s_ks[16], s_kf[16];
+  __shared__ unsigned int s_cnt[16], s_re[16];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  ks = wave_min_u64(ks);
+  kf = wave_min_u64(kf);
+  if (lane == 0) {
+    s_ks[wave] = ks;
+    s_kf[wave] = kf;
+    s_cnt[wave] = cnt;
+    s_re[wave] = n_re;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int nw = (blockDim.x + 63) >> 6;
+    unsigned long long bks = kKeyNone, bkf = kKeyNone;
+    unsigned int bcnt = 0, bre = 0;
+    for (int w = 0; w < nw; ++w) {
+      bks = s_ks[w] < bks ? s_ks[w] : bks;
+      bkf = s_kf[w] < bkf ? s_kf[w] : bkf;
+      bcnt += s_cnt[w];
+      bre += s_re[w];
+    }
+    SubSlot* ss = &slot->sub[part % kSubSlots];
+    if (bks != kKeyNone) atomicMin(&ss->key_safe, bks);
+    if (bkf != kKeyNone) atomicMin(&ss->key_fb, bkf);
+    if (bcnt) atomicAdd(&ss->count, (unsigned long long)bcnt);
+    if (bre) atomicAdd(&ss->n_recheck, bre);
+  }
+}
+
+// Appends value v of every lane with `flag` set to list[] (one atomic on
+// *count per wave; the lanes' order within the wave is kept).  Called by
+// every lane of the wave.
+template <typename T>
+__device__ __forceinline__ void wave_append(unsigned int* __restrict__ count, T* __restrict__ list, bool flag, T v) {
+  const unsigned long long b = __ballot(flag);
+  if (b == 0ull) return;  // uniform
+  const int lane = threadIdx.x & 63;
+  const int leader = __ffsll((long long)b) - 1;
+  unsigned int base = 0;
+  if (lane == leader) base = atomicAdd(count, (unsigned int)__popcll(b));
+  base = (unsigned int)__shfl((int)base, leader, 64);
+  if (flag) list[base + (unsigned int)__popcll(b & ((1ull << lane) - 1ull))] = v;
+}
 
 // Prediction of candidate c with early exit at the first unsafe state
 // (Alg. 2 inner loop), then its selection keys.  Lanes with c >= Nc return
@@ -172,7 +242,12 @@ struct CandResult {
 // draw in (models with a positive sigma); noise-free instances carry none of
 // its registers (a noisy instance still skips the draw for a noise-free model).
 // DEG is the track polynomial's degree (>= the model's highest harmonic).
-template <int BASIS, bool NOISE, int DEG = kMaxHarm>
+//
+// NEAR instances also track whether some checked state (steps 1 .. first
+// violation) has a margin within its constraint's FP32 band: such a
+// candidate is left to the FP64 re-roll, so it gets no keys here and its
+// first violation is not stored.
+template <int BASIS, bool NOISE, int DEG = kMaxHarm, bool NEAR = false>
 __device__ __forceinline__ CandResult evaluate_candidate(const ModelDev* __restrict__ md, const float4* sK,
                                                          const GenParams& gp, int H,
                                                          const float* __restrict__ x_t,
@@ -195,6 +270,7 @@ __device__ __forceinline__ CandResult evaluate_candidate(const ModelDev* __restr
   Stepper<BASIS> stp;
   stp.set_input(md, sK, u);
   int fv = H + 1;
+  bool near = false;
   if (valid) {
     const bool noisy = NOISE && md->has_noise != 0;
     const uint64_t nprefix = noisy ? hash_prefix(gp.seed, gp.tick, (uint64_t)(uint32_t)gp.loop, (uint64_t)c) : 0ull;
@@ -216,18 +292,21 @@ __device__ __forceinline__ CandResult evaluate_candidate(const ModelDev* __restr
         for (int j = 0; j < NS; ++j)
           if (j < n) __builtin_nontemporal_store(x[j], &traj[((size_t)(s - 1) * n + j) * traj_ld + c]);
       }
-      if (!(min_margin<NS, DEG>(md, x) > 0.0f)) {
+      const float mg = NEAR ? min_margin_near<NS, DEG>(md, x, &near) : min_margin<NS, DEG>(md, x);
+      if (!(mg > 0.0f)) {
         fv = s;
         break;
       }
     }
-    if (fv_out) fv_out[c] = (int16_t)fv;
+    if (fv_out && !(NEAR && near)) fv_out[c] = (int16_t)fv;
   }
-  const bool safe = valid && fv == H + 1;
+  const bool pub = valid && !(NEAR && near);
+  const bool safe = pub && fv == H + 1;
   CandResult r;
   r.ks = safe ? safe_key(cst, c) : kKeyNone;
-  r.kf = (valid && !safe) ? fallback_key(fv, cst, c) : kKeyNone;
+  r.kf = (pub && !safe) ? fallback_key(fv, cst, c) : kKeyNone;
   r.safe_counted = safe && c > 0;
+  r.near = NEAR && valid && near;
   return r;
 }
 

@@ -17,14 +17,14 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmpmi.so")
 
 # Constants mirrored from include/mpmi.h
-ABI_VERSION = 5
+ABI_VERSION = 6
 MAX_STATE, MAX_INPUT, MAX_DIM, MAX_BOX = 8, 4, 64, 4
 MAX_HORIZON, MAX_SEGMENTS, MAX_CAND, MAX_LOOPS = 255, 8, 33554431, 4096
 OK, NO_SAFE, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED, ESINGULAR = 0, 1, -1, -2, -3, -4, -5
 BASIS_LINEAR, BASIS_BALANCE_BOT, BASIS_RACE_CAR, BASIS_CUSTOM = 0, 1, 2, 3
 ATOM_ONE, ATOM_VAR, ATOM_SIN, ATOM_COS = 0, 1, 2, 3
 MAX_ATOMS = 32
-PREC_FP32, PREC_BF16X3 = 0, 1
+PREC_FP32, PREC_BF16X3, PREC_FP32_RECHECK64 = 0, 1, 2
 GEN_EXPLICIT, GEN_GRID, GEN_UNIFORM = 0, 1, 2
 
 _i32x4 = ctypes.c_int32 * 4
@@ -43,6 +43,7 @@ class System(ctypes.Structure):
         ("n_atoms", ctypes.c_int32), ("dim", ctypes.c_int32),
         ("atom_kind", ctypes.c_int8 * 32), ("atom_var", ctypes.c_int8 * 32),
         ("feat_a", ctypes.c_int8 * 64), ("feat_b", ctypes.c_int8 * 64),
+        ("eps32_box", _f32x4), ("eps32_track", ctypes.c_float), ("pad_eps", ctypes.c_int32),
     ]
 
 
@@ -76,7 +77,7 @@ class LoopDesc(ctypes.Structure):
 
 
 class MultiConfig(ctypes.Structure):
-    _fields_ = [("block", ctypes.c_int32), ("grid", ctypes.c_int32)]
+    _fields_ = [("block", ctypes.c_int32), ("grid", ctypes.c_int32), ("precision", ctypes.c_int32)]
 
 
 class MpmiError(RuntimeError):
@@ -154,7 +155,8 @@ def library() -> ctypes.CDLL:
 # ---------------------------------------------------------------------------
 # System descriptors (plain data)
 # ---------------------------------------------------------------------------
-def _sys(basis, n, m, box, u_lo, u_hi, track=None, eps_box=None, eps_track=0.0, noise=None):
+def _sys(basis, n, m, box, u_lo, u_hi, track=None, eps_box=None, eps_track=0.0, noise=None, eps32_box=None,
+         eps32_track=0.0):
     s = System()
     for j, v in enumerate(noise or []):
         s.noise_sigma[j] = float(v)
@@ -163,6 +165,7 @@ def _sys(basis, n, m, box, u_lo, u_hi, track=None, eps_box=None, eps_track=0.0, 
     for b, (idx, bound, infl) in enumerate(box):
         s.box_index[b], s.box_bound[b], s.box_infl[b] = idx, bound, infl
         s.eps_box[b] = 0.0 if eps_box is None else eps_box[b]
+        s.eps32_box[b] = 0.0 if eps32_box is None else eps32_box[b]
     for j in range(m):
         s.u_lo[j], s.u_hi[j] = float(u_lo[j]), float(u_hi[j])
     if track is not None:
@@ -174,13 +177,16 @@ def _sys(basis, n, m, box, u_lo, u_hi, track=None, eps_box=None, eps_track=0.0, 
             s.track_phase[k] = float(track["phase"][k])
         s.track_r0, s.track_half, s.track_infl = track["r0"], track["half"], track.get("infl", 0.0)
         s.eps_track = eps_track
+        s.eps32_track = eps32_track
     return s
 
 
-def custom_system(n, m, atoms, feats, box, u_lo, u_hi, track=None, eps_box=None, eps_track=0.0, noise=None):
+def custom_system(n, m, atoms, feats, box, u_lo, u_hi, track=None, eps_box=None, eps_track=0.0, noise=None,
+                  eps32_box=None, eps32_track=0.0):
     """A basis given as data: atoms [(ATOM_*, w index)], features [(atom a, atom b)]
     (psi_f = atom_a * atom_b, w = [x; u])."""
-    s = _sys(BASIS_CUSTOM, n, m, box, u_lo, u_hi, track=track, eps_box=eps_box, eps_track=eps_track, noise=noise)
+    s = _sys(BASIS_CUSTOM, n, m, box, u_lo, u_hi, track=track, eps_box=eps_box, eps_track=eps_track, noise=noise,
+             eps32_box=eps32_box, eps32_track=eps32_track)
     if not 1 <= len(atoms) <= MAX_ATOMS or not 1 <= len(feats) <= MAX_DIM:
         raise ValueError("1..32 atoms and 1..64 features")
     s.n_atoms, s.dim = len(atoms), len(feats)
@@ -210,17 +216,19 @@ def linear_system(n, m, box, u_lo, u_hi):
 
 
 def balance_bot_system(theta_bound=0.5, p_bound=2.0, infl=0.0, u_lo=-5.0, u_hi=5.0, eps=(5e-5, 2e-4),
-                       noise=None):
-    """Cart-pole: |theta| < theta_bound - infl, |p| < p_bound - infl, u in [u_lo, u_hi]."""
+                       noise=None, eps32=(1e-4, 4e-4)):
+    """Cart-pole: |theta| < theta_bound - infl, |p| < p_bound - infl, u in [u_lo, u_hi].
+    eps: BF16X3 bands; eps32: FP32_RECHECK64 bands (theta, p)."""
     return _sys(BASIS_BALANCE_BOT, 4, 1, [(2, theta_bound, infl), (0, p_bound, infl)], [u_lo], [u_hi],
-                eps_box=list(eps), noise=noise)
+                eps_box=list(eps), noise=noise, eps32_box=list(eps32))
 
 
 def race_car_system(track: dict, vy_bound=2.0, infl=0.0, u_lo=(-0.4, -3.0), u_hi=(0.4, 3.0),
-                    eps_track=0.02, eps_vy=0.02, noise=None):
-    """Dynamic bicycle on a track (dict r0, half, amp, freq, phase, infl) with |v_y| < vy_bound - infl."""
+                    eps_track=0.02, eps_vy=0.02, noise=None, eps32_track=2e-3, eps32_vy=3e-4):
+    """Dynamic bicycle on a track (dict r0, half, amp, freq, phase, infl) with |v_y| < vy_bound - infl.
+    eps_*: BF16X3 bands; eps32_*: FP32_RECHECK64 bands."""
     return _sys(BASIS_RACE_CAR, 6, 2, [(4, vy_bound, infl)], u_lo, u_hi, track=track,
-                eps_box=[eps_vy], eps_track=eps_track, noise=noise)
+                eps_box=[eps_vy], eps_track=eps_track, noise=noise, eps32_box=[eps32_vy], eps32_track=eps32_track)
 
 
 # ---------------------------------------------------------------------------
@@ -597,7 +605,7 @@ class Multi:
     first_violation.  The tensors are kept alive by this object.
     """
 
-    def __init__(self, ctx: Context, loops, block: int = 256):
+    def __init__(self, ctx: Context, loops, block: int = 256, precision: int = PREC_FP32):
         self.ctx = ctx
         self._keep = []
         arr = (LoopDesc * len(loops))()
@@ -622,7 +630,7 @@ class Multi:
                 d.grid[j] = g
             d.n_seg, d.horizon = l.get("n_seg", 1), l["horizon"]
             self._keep.append(l)
-        cfg = MultiConfig(block, 0)
+        cfg = MultiConfig(block, 0, precision)
         h = ctypes.c_void_p()
         ctx.check(ctx.lib.mpmi_multi_create(ctx.handle, arr, len(loops), ctypes.byref(cfg), ctypes.byref(h)))
         self.handle = h
@@ -631,7 +639,7 @@ class Multi:
     def config(self):
         cfg, n = MultiConfig(), ctypes.c_int32()
         self.ctx.lib.mpmi_multi_get_config(self.handle, ctypes.byref(cfg), ctypes.byref(n))
-        return dict(block=cfg.block, grid=cfg.grid, n_work=n.value)
+        return dict(block=cfg.block, grid=cfg.grid, n_work=n.value, precision=cfg.precision)
 
     def _drop_graph(self):
         # A captured graph holds the launch shape of the plan it was taken from.
@@ -639,10 +647,12 @@ class Multi:
             self.ctx.lib.mpmi_graph_destroy(self.graph)
             self.graph = None
 
-    def set_config(self, block: int):
+    def set_config(self, block: int, precision=None):
         self._drop_graph()
+        if precision is None:
+            precision = self.config()["precision"]
         self.ctx.check(self.ctx.lib.mpmi_multi_set_config(self.ctx.handle, self.handle,
-                                                         ctypes.byref(MultiConfig(block, 0))))
+                                                         ctypes.byref(MultiConfig(block, 0, precision))))
 
     def tick(self, stream=None):
         self.ctx.check(self.ctx.lib.mpmi_multi_tick(self.ctx.handle, self.handle, _stream(stream)))

@@ -19,6 +19,10 @@
   ("eps_band") can only come from ambiguous verdicts, by the two rules above,
   and counts as a disagreement.
 
+FP32_RECHECK64 ticks (FP32 tick, FP64 re-roll of the candidates in the FP32
+band) are judged with an FP64 band (EPS64, 1e-9): their first violations must
+equal the oracle's wherever its margins are not within FP64 rounding of zero.
+
 Long replays run the oracle in a pool of worker processes (spawn context;
 the workers import only NumPy and the oracle, never the GPU library).
 """
@@ -31,6 +35,16 @@ from concurrent.futures import ProcessPoolExecutor
 import numpy as np
 
 from oracle import mpmi_oracle as o
+
+
+# Band for verdicts computed in FP64 on the GPU (margins of order one,
+# rollouts of at most a few hundred steps).
+EPS64 = 1e-9
+
+
+def eps64(sys: o.System) -> list:
+    """The FP64 band for every constraint of sys."""
+    return [EPS64] * (len(sys.box) + (1 if sys.track is not None else 0))
 
 
 def rollout_rel_err(x_gpu: np.ndarray, x_64: np.ndarray, floors: np.ndarray, comp_axis: int) -> float:
@@ -172,16 +186,24 @@ def candidates(sys: o.System, spec, u_h) -> np.ndarray:
 def replay_job(job) -> list:
     """One tick replayed by the oracle and judged against one or more GPU
     results: job = (sys, K, x_t, u_h, cand_spec, H, eps, noise_key,
-    [(sel, fv_gpu, label), ...])."""
+    [(sel, fv_gpu, label[, eps of this result]), ...])."""
     sys, K, x_t, u_h, spec, H, eps, noise_key, results = job
     cand = candidates(sys, spec, u_h)
     traj, fv_o = o.rollout(sys, K, x_t, cand, H, early_exit=False, noise_key=noise_key)
-    return [judge(sys, cand, H, u_h, traj, fv_o, sel, fv, eps, label) for sel, fv, label in results]
+    return [judge(sys, cand, H, u_h, traj, fv_o, r[0], r[1], r[3] if len(r) > 3 else eps, r[2]) for r in results]
 
 
 def oracle_chunk(job):
     """First violations and ambiguity of a slice of one tick's candidates:
-    job = (sys, K, x_t, cand_slice, H, fv_gpu_slice, eps)."""
-    sys, K, x_t, cand, H, fv_gpu, eps = job
+    job = (sys, K, x_t, cand_slice, H, fv_gpu_slice, eps), or with a list of
+    (fv_gpu_slice, eps) pairs in place of the last two (one ambiguity mask per
+    pair: (fv_o, [amb, ...]))."""
+    if len(job) == 6:
+        sys, K, x_t, cand, H, pairs = job
+    else:
+        sys, K, x_t, cand, H, fv_gpu, eps = job
+        pairs = None
     traj, fv_o = o.rollout(sys, K, x_t, cand, H, early_exit=False)
-    return fv_o, ambiguous(sys, traj, fv_o, np.asarray(fv_gpu, np.int64), eps)
+    if pairs is None:
+        return fv_o, ambiguous(sys, traj, fv_o, np.asarray(fv_gpu, np.int64), eps)
+    return fv_o, [ambiguous(sys, traj, fv_o, np.asarray(f, np.int64), e) for f, e in pairs]

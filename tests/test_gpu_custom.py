@@ -12,7 +12,7 @@ import synth
 from oracle import mpmi_oracle as o
 from paper_1906_02318_amd import mpmi
 from tests import workloads as W
-from tests.parity import ambiguous, check_tick, tally
+from tests.parity import agreed, ambiguous, check_tick, replay_job, tally
 
 pytestmark = pytest.mark.gpu
 
@@ -62,24 +62,25 @@ def test_custom_fit_parity(ctx, system):
     assert abs(cond - info["cond"]) <= 1e-3 * info["cond"]
 
 
-def test_generic_path_against_the_family_kernels(ctx):
+def test_generic_path_against_the_family_kernels(ctx, oracle_pool):
     """A custom basis that describes the balance-bot family runs the generic
     step (atoms and features from the descriptor); the same functions on the
-    family's fast kernels.  Over 200 ticks (N = 1,024 grid, H = 20), both are
-    complete and agree with the oracle (check_tick), and their first violations
-    are identical outside the FP32 band (the two evaluate the polynomial in a
-    different order)."""
+    family's fast kernels.  Over 1,000 ticks (N = 1,024 grid, H = 20), every
+    generic tick is complete against the oracle (replay_job), its decisions
+    agree with the oracle's on at least 99.9% of the ticks, and its first
+    violations equal the family kernels' outside the FP32 band (the two
+    evaluate the polynomial in a different order)."""
     K = W.bb_model()[0]
     so = W.bb_oracle_system()
     sg = bb_custom()
     assert sg.basis == mpmi.BASIS_CUSTOM and mpmi.basis_match(sg) == mpmi.BASIS_BALANCE_BOT
     m_gen = mpmi.mpmi_model_pack(ctx, sg, dev(K, torch.float64))
     m_fam = mpmi.mpmi_model_pack(ctx, mpmi.balance_bot_system(), dev(K, torch.float64))
-    T = 200
+    T = 1000
     xs = synth.balance_bot_states(T, seed=1)
     uhs = synth.uniform_user(T, [-5.0], [5.0], seed=2)
     grid = o.grid_candidates(so, [1024])
-    res, same_rec, band_only = [], 0, 0
+    jobs, same_rec, band_only = [], 0, 0
     for t in range(T):
         x, u = W.f32(xs[t]), W.f32(uhs[t])
         desc = mpmi.tick_desc(1024, 20, gen=mpmi.GEN_GRID, grid=[1024])
@@ -88,19 +89,20 @@ def test_generic_path_against_the_family_kernels(ctx):
         ra = mpmi.mpmi_tick(ctx, m_gen, desc, dev(x, torch.float32), dev(u, torch.float32), first_violation=fa)
         rb = mpmi.mpmi_tick(ctx, m_fam, desc, dev(x, torch.float32), dev(u, torch.float32), first_violation=fb)
         same_rec += int(ra.cpu().numpy().tobytes() == rb.cpu().numpy().tobytes())
-        cand = o.with_user(grid, u, 1)
-        res.append(check_tick(so, K, x, u, cand, 20, mpmi.decode_selection(ra), fa.cpu().numpy(), EPS_BB,
-                              label=f"generic tick {t}"))
         fa_, fb_ = fa.cpu().numpy(), fb.cpu().numpy()
+        jobs.append((so, K, x, u, ("grid", [1024]), 20, EPS_BB, None,
+                     [(mpmi.decode_selection(ra), fa_, f"generic tick {t}")]))
         if not np.array_equal(fa_, fb_):
+            cand = o.with_user(grid, u, 1)
             traj, fvo = o.rollout(so, K, x, cand, 20, early_exit=False)
             amb = ambiguous(so, traj, fa_.astype(np.int64), fb_.astype(np.int64), EPS_BB)
             assert np.all((fa_ == fb_) | amb), f"tick {t}: generic and family verdicts differ outside the band"
             band_only += 1
+    res = [r for rs in oracle_pool.map(replay_job, jobs, chunksize=16) for r in rs]
     kinds = tally(res)
-    log(f"[generic] {kinds}; records identical to the family kernels on {same_rec}/{T} ticks; "
-        f"verdicts differing only inside the band on {band_only}")
-    assert kinds.get("identical", 0) + kinds.get("equal_cost", 0) >= 0.999 * T
+    log(f"[generic] {kinds}; agreement {agreed(kinds) / T:.4f}; records identical to the family kernels on "
+        f"{same_rec}/{T} ticks; verdicts differing only inside the band on {band_only}")
+    assert agreed(kinds) >= 0.999 * T
 
 
 def test_custom_rollout_parity(ctx):

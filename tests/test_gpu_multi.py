@@ -10,7 +10,7 @@ import synth
 from oracle import mpmi_oracle as o
 from paper_1906_02318_amd import mpmi
 from tests import workloads as W
-from tests.parity import agreed, check_tick, replay_job, tally
+from tests.parity import agreed, check_tick, eps64, replay_job, tally
 
 pytestmark = pytest.mark.gpu
 
@@ -166,10 +166,12 @@ def test_multi_model_snapshot_taken_at_replan(setup):
 def test_serving_workload_decisions_against_oracle(oracle_pool):
     """The bench's serving workload -- 64 closed loops (32 cart-poles, 32 race
     cars; N_l log-uniform in [1,024, 65,536], H_l in 20..60, AR(1) users), one
-    graph replay per tick -- for 1,001 ticks; at every 500th tick all 64 loops
-    are replayed by the oracle on their visited (x_t, u_h, candidates): every
-    record is the selection rule over its loop's first violations, and at
-    least 99.9% of the decisions agree with the oracle's."""
+    graph replay per tick, FP32 ticks with the FP64 re-roll of each loop's
+    FP32 band (FP32_RECHECK64) -- for 1,001 ticks; at every 500th tick all 64
+    loops are replayed by the oracle on their visited (x_t, u_h, candidates):
+    every record is the selection rule over its loop's first violations, those
+    equal the oracle's outside the FP64 band, and at least 99.9% of the
+    decisions agree with the oracle's."""
     ctx = mpmi.Context(0)
     track = W.rc_track()
     Kb, Kr = W.bb_model()[0], W.rc_model()[0]
@@ -185,7 +187,7 @@ def test_serving_workload_decisions_against_oracle(oracle_pool):
     loops = [dict(model=mb if k == "bb" else mr, x_t=x_dev[i], u_user=u_dev[i], out=out_dev[i],
                   first_violation=fvs[i], n_cand=int(scen.N[i]), horizon=int(scen.H[i]), gen=mpmi.GEN_UNIFORM,
                   seed=scen.seeds[i], tick=0) for i, k in enumerate(scen.kinds)]
-    multi = mpmi.Multi(ctx, loops)
+    multi = mpmi.Multi(ctx, loops, precision=mpmi.PREC_FP32_RECHECK64)
     multi.capture_graph()
     jobs = []
     for t in range(1001):
@@ -200,7 +202,7 @@ def test_serving_workload_decisions_against_oracle(oracle_pool):
                 so, K, nx, nu = systems[k]
                 x, u = W.f32(scen.x[i, :nx]), W.f32(scen.u[i, :nu])
                 jobs.append((so, K, x, u, ("uniform", int(scen.N[i]), 1, scen.seeds[i], t, i), int(scen.H[i]),
-                             EPS[k], None, [(sels[i], fvs[i].cpu().numpy(), f"tick {t} loop {i} ({k})")]))
+                             eps64(so), None, [(sels[i], fvs[i].cpu().numpy(), f"tick {t} loop {i} ({k})")]))
             log(f"[serving] tick {t}: records of {n} loops taken")
         scen.advance(rec.view(np.float32).reshape(n, -1)[:, 4:8], t)
     assert multi.ticks() == [1001] * n

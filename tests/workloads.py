@@ -104,7 +104,7 @@ def rc3_gpu_system(mpmi, track: synth.Track, infl=0.0):
     atoms, feats = synth.race_car3_basis()
     return mpmi.custom_system(6, 3, [(kinds[k], v) for k, v in atoms], feats, [(4, RC_VY, infl)],
                               synth.RC3_U_LO, synth.RC3_U_HI, track=track_dict(track, infl),
-                              eps_box=[0.02], eps_track=0.02)
+                              eps_box=[0.02], eps_track=0.02, eps32_box=[3e-4], eps32_track=2e-3)
 
 
 @functools.lru_cache(maxsize=None)
