@@ -37,7 +37,12 @@ linear plant's closed form (fit, rollout with and without noise, selection
 interval); brute-force enumeration; published SplitMix64 vectors; hand-derived
 uniform draws, grid points and track margins (nonzero phases included);
 library least squares and the residual's orthogonality; the Sec. IV-D
-printed values; zero intervention and mask monotonicity.
+printed values; zero intervention and mask monotonicity.  The basis
+selection (selection_problem, group_shrink, sparse_admm, select_basis) is
+pinned in tests/test_selection_pins.py: hand-computed shrinkage, the
+closed-form solution of an orthonormal design, the optimality conditions of
+the convex problem, the least-squares limit, the zero solution above the
+critical penalty, and a planted support with its polished coefficients.
 """
 from __future__ import annotations
 
@@ -544,3 +549,85 @@ def tick(sys: System, K, x_t, u_h, cand: np.ndarray, H: int, noise_key=None) -> 
 def deviation_bound(lebesgue_measure: float, N: int) -> float:
     """lambda*(U) / (2 N): half the spacing of N equally spaced 1-D samples."""
     return lebesgue_measure / (2.0 * N)
+
+
+# ----------------------------------------------------------------------------
+# Basis selection (Sec. IV-A and Sec. V-C-3: a library of random basis
+# functions is reduced to the ones most relevant to the dynamics by the
+# sparsity-promoting method of Jovanovic, Schmid and Nichols (2014))
+# ----------------------------------------------------------------------------
+def selection_problem(library, X, U, Y):
+    """The quadratic data term of the selection on scaled columns.
+
+    Psi_s = Psi / s (s the RMS of each library function over the T rows) and
+    Y_s = Y / s_y (s_y the RMS of each state component); with K the (L, n)
+    coefficients of the scaled problem,
+        J(K) = ||Psi_s K - Y_s||^2 / T = tr(K^T G K) - 2 tr(K^T A) + c,
+    G = Psi_s^T Psi_s / T, A = Psi_s^T Y_s / T.  Returns (G, A, s, s_y)."""
+    X, U, Y = (np.asarray(a, np.float64) for a in (X, U, Y))
+    Psi = lift(library, X, U)
+    T = Psi.shape[0]
+    s = np.sqrt(np.sum(Psi * Psi, axis=0) / T)
+    s[s == 0.0] = 1.0
+    sy = np.sqrt(np.sum(Y * Y, axis=0) / T)
+    sy[sy == 0.0] = 1.0
+    Ps, Ys = Psi / s, Y / sy
+    return Ps.T @ Ps / T, Ps.T @ Ys / T, s, sy
+
+
+def group_shrink(V: np.ndarray, kappa: float) -> np.ndarray:
+    """Row-wise block soft threshold: row v -> max(0, 1 - kappa / ||v||) v
+    (a row of norm <= kappa becomes exactly zero; for one column this is the
+    scalar soft threshold sign(v) max(|v| - kappa, 0))."""
+    norms = np.sqrt(np.sum(V * V, axis=1))
+    with np.errstate(divide="ignore", invalid="ignore"):
+        f = np.where(norms > kappa, 1.0 - kappa / norms, 0.0)
+    return V * f[:, None]
+
+
+def sparse_admm(G, A, gamma: float, rho: float, iters: int):
+    """ADMM of the sparsity-promoting problem, in the three steps of
+    Jovanovic et al. (2014), Sec. III, with a basis function's row of
+    coefficients as the unit that is kept or dropped:
+        minimise  J(K) + gamma * sum_f ||B_f||   subject to  K = B,
+    augmented Lagrangian with multiplier Lam and penalty rho; from
+    B = Lam = 0, each iteration
+        K   <- (G + rho/2 I)^-1 (A + rho/2 (B - Lam / rho))   (J's minimiser plus the penalty)
+        B'  <- group_shrink(K + Lam / rho, gamma / rho)        (the sparsity step)
+        Lam <- Lam + rho (K - B')
+    and reports the primal residual ||K - B'||_F and the dual residual
+    rho ||B' - B||_F of the last iteration.  A fixed number of iterations
+    (no data-dependent stop).  Returns (B, K, Lam, (primal, dual))."""
+    G = np.asarray(G, np.float64)
+    A = np.asarray(A, np.float64)
+    L, n = A.shape
+    Mreg = G + 0.5 * rho * np.eye(L)
+    B = np.zeros((L, n))
+    Lam = np.zeros((L, n))
+    K = np.zeros((L, n))
+    prim = dual = 0.0
+    for _ in range(iters):
+        K = np.linalg.solve(Mreg, A + 0.5 * rho * (B - Lam / rho))
+        Bn = group_shrink(K + Lam / rho, gamma / rho)
+        Lam = Lam + rho * (K - Bn)
+        prim = float(np.sqrt(np.sum((K - Bn) ** 2)))
+        dual = float(rho * np.sqrt(np.sum((Bn - B) ** 2)))
+        B = Bn
+    return B, K, Lam, (prim, dual)
+
+
+def select_basis(library, X, U, Y, gamma: float, rho: float = 1.0, iters: int = 500):
+    """Basis selection followed by the polishing step of Jovanovic et al.:
+    the support S = {f : B_f != 0} of the sparse solution, then the plain
+    least-squares fit (fit()) on the selected functions alone.  Returns
+    dict(support, B (unscaled: B_s * s_y / s), K_polished (|S|, n) or None,
+    basis (the selected Basis) or None, residuals)."""
+    G, A, s, sy = selection_problem(library, X, U, Y)
+    B, _, _, res = sparse_admm(G, A, gamma, rho, iters)
+    support = np.nonzero(np.any(B != 0.0, axis=1))[0]
+    out = dict(support=support, B=B * sy[None, :] / s[:, None], residuals=res, K_polished=None, basis=None)
+    if support.size:
+        sel = Basis(atoms=library.atoms, feats=tuple(library.feats[f] for f in support))
+        out["basis"] = sel
+        out["K_polished"] = fit(sel, X, U, Y)[0]
+    return out

@@ -278,6 +278,26 @@ def race_car3_basis():
     return atoms, feats
 
 
+def random_library(n: int, m: int, L: int, seed: int = 0):
+    """A library of L candidate basis functions as (atoms, features): the
+    atoms 1, w_k, sin w_k, cos w_k of w = [x; u] (k < n + m), the features the
+    constant, every w_k, and L - 1 - (n + m) further products of two atoms
+    drawn uniformly without replacement from the remaining unordered atom
+    pairs (seeded)."""
+    nw = n + m
+    atoms = [("one", 0)] + [("var", k) for k in range(nw)] + [("sin", k) for k in range(nw)] + \
+        [("cos", k) for k in range(nw)]
+    base = [(0, 0)] + [(1 + k, 0) for k in range(nw)]
+    pairs = [(a, b) for a in range(len(atoms)) for b in range(a, len(atoms))]
+    rest = [p for p in pairs if p not in base and (p[1], p[0]) not in base]
+    k = L - len(base)
+    if k < 0 or k > len(rest):
+        raise ValueError(f"a library of {L} functions does not fit {len(atoms)} atoms")
+    rng = np.random.default_rng(seed)
+    pick = sorted(rng.choice(len(rest), size=k, replace=False))
+    return atoms, base + [rest[i] for i in pick]
+
+
 # ----------------------------------------------------------------------------
 # Linear plant (identity-basis checks) and many-loop sizes
 # ----------------------------------------------------------------------------
