@@ -237,8 +237,8 @@ int32_t mpmi_abi_version(void);
 mpmi_status mpmi_create(mpmi_ctx* out, int32_t device);
 void mpmi_destroy(mpmi_ctx ctx);
 /* Message of the last failed call on ctx (never NULL; "" after success);
- * with ctx NULL, of the last failed call made without a context on the
- * calling thread.                                                         */
+ * with ctx NULL, of the last failed call made without a context
+ * (mpmi_tick_noalloc) on the calling thread.                              */
 const char* mpmi_last_error(mpmi_ctx ctx);
 
 /* Size in bytes of a packed model (device blob read by every rollout).      */
@@ -314,6 +314,25 @@ mpmi_status mpmi_tick(mpmi_ctx ctx, const void* model, const mpmi_tick_desc* des
                       const float* x_t, const float* u_user, const float* cand,
                       mpmi_selection* out, int16_t* first_violation, float* traj,
                       int64_t traj_ld, void* stream);
+
+/* The tick of mpmi_tick for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): no context, nothing allocated or freed, no synchronisation.
+ * The tick's scratch -- the selection slots of loops 0..63 and an FP64
+ * re-roll list of 65,536 entries (about 292 KiB in all) -- is a file-scope
+ * device array of the library, one copy per GPU, held until the process
+ * ends; its load-time image is the reset state and every tick leaves it so.
+ * sys (host) must be the system `model` was packed from (mpmi_model_pack);
+ * the tick runs on the current device.  desc as for mpmi_tick with loop
+ * 0..63, precision FP32 (any launch shape) or FP32_RECHECK64 (at most 65,536
+ * candidates); MPMI_EINVAL / MPMI_EUNSUPPORTED beyond these limits, with the
+ * message in mpmi_last_error(NULL) (thread-local).  Calls on one GPU share
+ * the array: calls that overlap in time on that GPU (other streams, other
+ * threads) race; order them on one stream.  The record and first violations
+ * equal mpmi_tick's for the same inputs.                                  */
+mpmi_status mpmi_tick_noalloc(const mpmi_system* sys /* host */, const void* model,
+                              const mpmi_tick_desc* desc /* host */, const float* x_t, const float* u_user,
+                              const float* cand, mpmi_selection* out, int16_t* first_violation, void* stream);
 
 /* ---------------------------------------------------------------------------
  * Lifted whole-horizon form (Sec. IV-A: in the Koopman representation a

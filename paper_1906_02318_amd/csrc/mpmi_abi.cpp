@@ -7,6 +7,7 @@
 #include <cstddef>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <unordered_map>
@@ -14,6 +15,7 @@
 
 #include "../../include/mpmi.h"
 #include "mpmi_launch.hpp"
+#include "mpmi_tick_common.hpp"
 
 struct mpmi_ctx_s {
   int device = 0;
@@ -31,7 +33,8 @@ struct mpmi_ctx_s {
 
 namespace {
 
-// Message of the last failed call made without a context on this thread.
+// Message of the last failed call made without a context on this thread
+// (mpmi_tick_noalloc and the validation it shares).
 thread_local std::string g_noctx_err;
 
 mpmi_status fail(mpmi_ctx ctx, mpmi_status code, const char* fmt, ...) {
@@ -988,3 +991,113 @@ mpmi_status mpmi_gemm_bf16(mpmi_ctx ctx, const uint16_t* A, const uint16_t* B, i
 
 }  // extern "C"
 
+// ---------------------------------------------------------------------------
+// Allocation-free tick (mpmi_tick_noalloc).  The tick's scratch -- the
+// selection slots of kScratchLoops loops and one FP64 re-roll list of
+// kScratchRecheck entries -- is one file-scope device object, `scratch`,
+// whose load-time image is already the reset state (keys all-ones, counts
+// zero): the tick's last workgroup, and the re-roll launch, leave it in that
+// state again, so no call ever has to clear it.  Every device the library
+// runs on holds its own copy until the process ends; its address on a device
+// is taken once, with that device current, by hipGetSymbolAddress, and only
+// that address is passed to kernels.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int kScratchLoops = 64;
+constexpr int kScratchRecheck = 1 << 16;
+constexpr int kScratchDevices = 64;
+
+struct alignas(64) ScratchSubSlot {
+  unsigned long long key_safe = ~0ull, key_fb = ~0ull, count = 0ull;
+  unsigned int n_recheck = 0u;
+  unsigned int pad[9] = {};
+};
+struct alignas(64) ScratchSlot {
+  ScratchSubSlot sub[mpmi::kSubSlots];
+  unsigned int done = 0u;
+  unsigned int pad[15] = {};
+};
+struct alignas(256) ScratchImage {
+  ScratchSlot slots[kScratchLoops];
+  unsigned int count = 0u;  // the re-roll list: a RecheckList of kScratchRecheck entries
+  unsigned int pad[63] = {};
+  int idx[kScratchRecheck] = {};
+};
+static_assert(sizeof(ScratchSlot) == sizeof(mpmi::Slot) && sizeof(ScratchSubSlot) == sizeof(mpmi::SubSlot),
+              "scratch slots have the library's slot layout");
+static_assert(offsetof(ScratchImage, count) == (size_t)kScratchLoops * sizeof(mpmi::Slot) &&
+                  offsetof(ScratchImage, idx) - offsetof(ScratchImage, count) == offsetof(mpmi::RecheckList, idx),
+              "scratch list has the recheck list's layout");
+
+static __device__ __align__(256) ScratchImage scratch[1];
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kScratchDevices] = {};
+
+// This device's address of `scratch` (taken on the first call on the device).
+mpmi_status scratch_address(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(nullptr, MPMI_EDEVICE, "mpmi_tick_noalloc: hipGetDevice: %s", hipGetErrorString(e));
+  if (dev < 0 || dev >= kScratchDevices)
+    return fail(nullptr, MPMI_EUNSUPPORTED, "mpmi_tick_noalloc: device %d beyond the %d the library serves", dev,
+                kScratchDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(nullptr, MPMI_EDEVICE, "mpmi_tick_noalloc: hipGetSymbolAddress: %s", hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return MPMI_OK;
+}
+
+}  // namespace
+
+extern "C" mpmi_status mpmi_tick_noalloc(const mpmi_system* sys, const void* model, const mpmi_tick_desc* desc,
+                                         const float* x_t, const float* u_user, const float* cand,
+                                         mpmi_selection* out, int16_t* first_violation, void* stream) {
+  mpmi_status s = validate_system(nullptr, sys);
+  if (s != MPMI_OK) return s;
+  s = validate_desc(nullptr, *sys, desc);
+  if (s != MPMI_OK) return s;
+  if (!model || !aligned(model, 256)) return fail(nullptr, MPMI_EINVAL, "model must be non-NULL and 256-byte aligned");
+  if (!x_t || !u_user || !out) return fail(nullptr, MPMI_EINVAL, "x_t, u_user and out must be non-NULL");
+  if (desc->gen == MPMI_GEN_EXPLICIT && desc->n_cand > 0 && !cand)
+    return fail(nullptr, MPMI_EINVAL, "EXPLICIT candidates need cand");
+  if (desc->loop >= kScratchLoops)
+    return fail(nullptr, MPMI_EINVAL, "loop=%d: the allocation-free tick has %d selection slots", desc->loop,
+                kScratchLoops);
+  if (desc->precision == MPMI_PREC_BF16X3)
+    return fail(nullptr, MPMI_EUNSUPPORTED, "the allocation-free tick runs FP32 and FP32_RECHECK64 ticks");
+  if (desc->precision == MPMI_PREC_FP32_RECHECK64 && (long long)desc->n_cand + 1 > kScratchRecheck)
+    return fail(nullptr, MPMI_EUNSUPPORTED,
+                "FP32_RECHECK64 ticks without allocation take at most %d candidates (N+1=%lld)", kScratchRecheck,
+                (long long)desc->n_cand + 1);
+  if (desc->lanes_per_cand > 1) {
+    if (desc->block > 256) return fail(nullptr, MPMI_EUNSUPPORTED, "several lanes per candidate: block <= 256");
+    if (mpmi::system_noisy(*sys))
+      return fail(nullptr, MPMI_EUNSUPPORTED, "several lanes per candidate: noise-free models only");
+  }
+  void* base = nullptr;
+  s = scratch_address(&base);
+  if (s != MPMI_OK) return s;
+  void* slot = (char*)base + (size_t)desc->loop * sizeof(mpmi::Slot);
+  void* list = (char*)base + offsetof(ScratchImage, count);
+  const hipStream_t st = (hipStream_t)stream;
+  hipError_t e;
+  if (desc->lanes_per_cand > 1)
+    e = mpmi::launch_tick_split(*sys, desc->lanes_per_cand, model, *desc, x_t, u_user, cand, slot, out,
+                                first_violation, st);
+  else if (desc->precision == MPMI_PREC_FP32_RECHECK64)
+    e = mpmi::launch_tick(*sys, model, *desc, x_t, u_user, cand, slot, out, first_violation, nullptr, 0, st, nullptr,
+                          list, kScratchRecheck, mpmi::device_cu_count() * 4);
+  else
+    e = mpmi::launch_tick(*sys, model, *desc, x_t, u_user, cand, slot, out, first_violation, nullptr, 0, st);
+  if (e != hipSuccess) return fail(nullptr, MPMI_EDEVICE, "mpmi_tick_noalloc launch: %s", hipGetErrorString(e));
+  g_noctx_err.clear();
+  return MPMI_OK;
+}

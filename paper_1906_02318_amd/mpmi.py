@@ -135,6 +135,7 @@ def library() -> ctypes.CDLL:
         "mpmi_tick_autotune": (i32, [vp, vp, ctypes.POINTER(TickDesc), vp, vp, vp, vp, i32,
                                      ctypes.POINTER(ctypes.c_float), vp]),
         "mpmi_basis_describe": (i32, [i32, i32, i32, ctypes.POINTER(System)]),
+        "mpmi_tick_noalloc": (i32, [ctypes.POINTER(System), vp, ctypes.POINTER(TickDesc), vp, vp, vp, vp, vp, vp]),
         "mpmi_basis_match": (i32, [ctypes.POINTER(System)]),
         "koopman_fit_lifted": (i32, [vp, ctypes.POINTER(System), vp, vp, vp, i64, f64, vp, ctypes.POINTER(f64), vp]),
         "mpmi_lifted_bytes": (ctypes.c_size_t, [i32]),
@@ -183,15 +184,15 @@ def _sys(basis, n, m, box, u_lo, u_hi, track=None, eps_box=None, eps_track=0.0, 
 
 def custom_system(n, m, atoms, feats, box, u_lo, u_hi, track=None, eps_box=None, eps_track=0.0, noise=None,
                   eps32_box=None, eps32_track=0.0):
-    """A basis given as data: atoms [(ATOM_*, w index)], features [(atom a, atom b)]
-    (psi_f = atom_a * atom_b, w = [x; u])."""
+    """A basis given as data: atoms [(ATOM_* or 'one'/'var'/'sin'/'cos', w index)],
+    features [(atom a, atom b)] (psi_f = atom_a * atom_b, w = [x; u])."""
     s = _sys(BASIS_CUSTOM, n, m, box, u_lo, u_hi, track=track, eps_box=eps_box, eps_track=eps_track, noise=noise,
              eps32_box=eps32_box, eps32_track=eps32_track)
     if not 1 <= len(atoms) <= MAX_ATOMS or not 1 <= len(feats) <= MAX_DIM:
         raise ValueError("1..32 atoms and 1..64 features")
     s.n_atoms, s.dim = len(atoms), len(feats)
     for q, (kind, var) in enumerate(atoms):
-        s.atom_kind[q], s.atom_var[q] = kind, var
+        s.atom_kind[q], s.atom_var[q] = _ATOM_CODES.get(kind, kind), var
     for f, (a, b) in enumerate(feats):
         s.feat_a[f], s.feat_b[f] = a, b
     return s
@@ -208,6 +209,9 @@ def basis_describe(family: int, n: int, m: int, system: System) -> System:
 def basis_match(system: System) -> int:
     """The fixed family a custom basis equals, or BASIS_CUSTOM."""
     return int(library().mpmi_basis_match(ctypes.byref(system)))
+
+
+_ATOM_CODES = {"one": ATOM_ONE, "var": ATOM_VAR, "sin": ATOM_SIN, "cos": ATOM_COS}
 
 
 def linear_system(n, m, box, u_lo, u_hi):
@@ -527,6 +531,28 @@ def mpmi_tick(ctx: Context, model: Model, desc: TickDesc, x_t, u_user, cand=None
     ctx.check(ctx.lib.mpmi_tick(ctx.handle, ctypes.c_void_p(model.ptr), ctypes.byref(desc), _ptr(x_t),
                                 _ptr(u_user), _ptr(cand), _ptr(out), _ptr(first_violation), _ptr(traj), ld,
                                 _stream(stream)))
+    return out
+
+
+def mpmi_tick_noalloc(model: Model, desc: TickDesc, x_t, u_user, out, cand=None, first_violation=None,
+                      stream=None):
+    """The allocation-free tick (no context; the library's static scratch on
+    the current device): writes the record into `out` (uint8 device tensor,
+    48 B) and returns it.  Argument checks only -- the binding allocates
+    nothing either."""
+    lib = library()
+    dev = torch.device("cuda", torch.cuda.current_device())
+    _need(x_t, "x_t", torch.float32, model.n, device=dev)
+    _need(u_user, "u_user", torch.float32, model.m, device=dev)
+    _need(out, "out", torch.uint8, SELECTION_BYTES, device=dev)
+    if cand is not None:
+        _need(cand, "cand", torch.float32, desc.n_seg * model.m * desc.n_cand, device=dev)
+    if first_violation is not None:
+        _need(first_violation, "first_violation", torch.int16, desc.n_cand + 1, device=dev)
+    st = lib.mpmi_tick_noalloc(ctypes.byref(model.system), ctypes.c_void_p(model.ptr), ctypes.byref(desc), _ptr(x_t),
+                               _ptr(u_user), _ptr(cand), _ptr(out), _ptr(first_violation), _stream(stream))
+    if st != OK:
+        raise MpmiError(st, lib.mpmi_last_error(None).decode())
     return out
 
 
