@@ -58,6 +58,7 @@ extern "C" {
 #define MPMI_MAX_CAND 33554431 /* Nc = N + 1 <= 2^25 - 1 */
 #define MPMI_MAX_LOOPS 4096   /* selection slots per context */
 #define MPMI_MAX_ATOMS 32     /* atoms of a custom basis */
+#define MPMI_MAX_LIBRARY 160  /* candidate functions of a basis-selection library */
 
 typedef int32_t mpmi_status;
 enum {
@@ -333,6 +334,51 @@ mpmi_status mpmi_tick(mpmi_ctx ctx, const void* model, const mpmi_tick_desc* des
 mpmi_status mpmi_tick_noalloc(const mpmi_system* sys /* host */, const void* model,
                               const mpmi_tick_desc* desc /* host */, const float* x_t, const float* u_user,
                               const float* cand, mpmi_selection* out, int16_t* first_violation, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Basis selection (Sec. IV-A: the basis is chosen from data by the
+ * sparsity-promoting method of Jovanovic, Schmid and Nichols 2014; Sec.
+ * V-C-3: a library of random basis functions is reduced to the relevant few).
+ * ------------------------------------------------------------------------- */
+
+/* A library of candidate functions (host struct): function f is
+ * atom[feat_a[f]](w) * atom[feat_b[f]](w), w = [x; u], atoms as in
+ * mpmi_system's custom basis. */
+typedef struct mpmi_library {
+  int32_t n_state;   /* n, 1..MPMI_MAX_STATE */
+  int32_t n_input;   /* m, 1..MPMI_MAX_INPUT */
+  int32_t n_atoms;   /* 1..MPMI_MAX_ATOMS */
+  int32_t n_feat;    /* L, 1..MPMI_MAX_LIBRARY */
+  int8_t atom_kind[MPMI_MAX_ATOMS];
+  int8_t atom_var[MPMI_MAX_ATOMS];
+  uint8_t feat_a[MPMI_MAX_LIBRARY];
+  uint8_t feat_b[MPMI_MAX_LIBRARY];
+} mpmi_library;
+
+/* Selects basis functions from transitions X [T][n], U [T][m] -> Y [T][n]
+ * (device FP64), for each penalty gamma[g] (host, g < n_gamma, >= 0) at
+ * once.  With Psi_s the library's values divided by each function's RMS over
+ * the T rows and Y_s the targets divided by each component's RMS, and
+ * G = Psi_s' Psi_s / T, A = Psi_s' Y_s / T, it minimises
+ *   tr(B' G B) - 2 tr(B' A) + gamma sum_f ||B_f||
+ * over L x n coefficients B (one row per library function) by `iters`
+ * iterations of ADMM from B = Lam = 0 with penalty rho > 0:
+ *   K <- (G + rho/2 I)^-1 (A + rho/2 (B - Lam/rho)),
+ *   B <- rows of K + Lam/rho shrunk by max(0, 1 - (gamma/rho)/||row||),
+ *   Lam <- Lam + rho (K - B)
+ * (FP64 throughout).  Writes B_out [n_gamma][L][n] (device FP64, unscaled:
+ * B_s[f][j] * rms(Y_j) / rms(psi_f)), support [n_gamma][L] (device, 1 where
+ * row f of B is nonzero: the selected functions) and, if resid is not NULL,
+ * resid [n_gamma][2] (host) = the last iteration's primal ||K - B||_F and
+ * dual rho ||B - B_prev||_F residuals.  The selected functions' model is then
+ * fitted (the method's polishing step) by koopman_fit on a custom basis of
+ * them.  Synchronous; a set-up call (allocates and frees its workspace).
+ * MPMI_EINVAL for a bad library, T < L, n_gamma out of 1..1024, rho <= 0, a
+ * negative gamma or iters out of 1..1000000. */
+mpmi_status koopman_select_basis(mpmi_ctx ctx, const mpmi_library* lib /* host */, const double* X,
+                                 const double* U, const double* Y, int64_t T, const double* gamma /* host */,
+                                 int32_t n_gamma, double rho, int32_t iters, double* B_out, uint8_t* support,
+                                 double* resid /* host, may be NULL */, void* stream);
 
 /* ---------------------------------------------------------------------------
  * Lifted whole-horizon form (Sec. IV-A: in the Koopman representation a

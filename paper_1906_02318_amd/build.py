@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmpmi.so")
-SOURCES = ["mpmi_abi.cpp", "mpmi_tick.hip", "mpmi_fit.hip", "mpmi_multi.hip", "mpmi_mlp.hip", "mpmi_bf16.hip", "mpmi_split.hip", "mpmi_diag.hip", "mpmi_lifted.hip", "mpmi_recheck64.hip"]
+SOURCES = ["mpmi_abi.cpp", "mpmi_tick.hip", "mpmi_fit.hip", "mpmi_multi.hip", "mpmi_mlp.hip", "mpmi_bf16.hip", "mpmi_split.hip", "mpmi_diag.hip", "mpmi_lifted.hip", "mpmi_recheck64.hip", "mpmi_select.hip"]
 HEADERS = ["mpmi_device.hpp", "mpmi_launch.hpp", "mpmi_tick_common.hpp"]
 
 ARCH = os.environ.get("MPMI_OFFLOAD_ARCH", "gfx950")

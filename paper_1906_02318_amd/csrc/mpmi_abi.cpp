@@ -359,6 +359,45 @@ mpmi_status koopman_fit_lifted(mpmi_ctx ctx, const mpmi_system* sys, const doubl
   return ok(ctx);
 }
 
+mpmi_status koopman_select_basis(mpmi_ctx ctx, const mpmi_library* lib, const double* X, const double* U,
+                                 const double* Y, int64_t T, const double* gamma, int32_t n_gamma, double rho,
+                                 int32_t iters, double* B_out, uint8_t* support, double* resid, void* stream) {
+  if (!ctx) return MPMI_EINVAL;
+  if (!lib) return fail(ctx, MPMI_EINVAL, "library is NULL");
+  const int n = lib->n_state, m = lib->n_input, na = lib->n_atoms, L = lib->n_feat;
+  if (n < 1 || n > MPMI_MAX_STATE || m < 1 || m > MPMI_MAX_INPUT)
+    return fail(ctx, MPMI_EINVAL, "library needs 1 <= n <= %d and 1 <= m <= %d", MPMI_MAX_STATE, MPMI_MAX_INPUT);
+  if (na < 1 || na > MPMI_MAX_ATOMS) return fail(ctx, MPMI_EINVAL, "n_atoms=%d out of 1..%d", na, MPMI_MAX_ATOMS);
+  if (L < 1 || L > MPMI_MAX_LIBRARY) return fail(ctx, MPMI_EINVAL, "n_feat=%d out of 1..%d", L, MPMI_MAX_LIBRARY);
+  for (int q = 0; q < na; ++q) {
+    if (lib->atom_kind[q] < MPMI_ATOM_ONE || lib->atom_kind[q] > MPMI_ATOM_COS)
+      return fail(ctx, MPMI_EINVAL, "atom_kind[%d]=%d is not an atom kind", q, lib->atom_kind[q]);
+    if (lib->atom_var[q] < 0 || lib->atom_var[q] >= n + m)
+      return fail(ctx, MPMI_EINVAL, "atom_var[%d]=%d is not a component of w = [x; u]", q, lib->atom_var[q]);
+  }
+  for (int f = 0; f < L; ++f)
+    if (lib->feat_a[f] >= na || lib->feat_b[f] >= na)
+      return fail(ctx, MPMI_EINVAL, "library function %d names an atom outside 0..%d", f, na - 1);
+  if (!X || !U || !Y || !gamma || !B_out || !support)
+    return fail(ctx, MPMI_EINVAL, "X, U, Y, gamma, B_out and support must be non-NULL");
+  if (T < L) return fail(ctx, MPMI_EINVAL, "T=%lld rows cannot determine L=%d functions", (long long)T, L);
+  if (T > (int64_t)1 << 40) return fail(ctx, MPMI_EINVAL, "T=%lld too large", (long long)T);
+  if (n_gamma < 1 || n_gamma > 1024) return fail(ctx, MPMI_EINVAL, "n_gamma=%d out of 1..1024", n_gamma);
+  for (int g = 0; g < n_gamma; ++g)
+    if (!(gamma[g] >= 0.0) || gamma[g] > 1e300) return fail(ctx, MPMI_EINVAL, "gamma[%d] must be finite and >= 0", g);
+  if (!(rho > 0.0) || rho > 1e300) return fail(ctx, MPMI_EINVAL, "rho must be finite and > 0");
+  if (iters < 1 || iters > 1000000) return fail(ctx, MPMI_EINVAL, "iters=%d out of 1..1000000", iters);
+  void* work = nullptr;
+  hipError_t e = hipMalloc(&work, mpmi::select_workspace_bytes(n_gamma));
+  if (e != hipSuccess) return fail(ctx, MPMI_ENOMEM, "koopman_select_basis workspace: %s", hipGetErrorString(e));
+  e = mpmi::launch_select_basis(*lib, X, U, Y, T, gamma, n_gamma, rho, iters, B_out, support, resid, work,
+                                (hipStream_t)stream);
+  const hipError_t ef = hipFree(work);
+  if (e != hipSuccess) return fail(ctx, MPMI_EDEVICE, "koopman_select_basis: %s", hipGetErrorString(e));
+  if (ef != hipSuccess) return fail(ctx, MPMI_EDEVICE, "koopman_select_basis free: %s", hipGetErrorString(ef));
+  return ok(ctx);
+}
+
 size_t mpmi_lifted_bytes(int32_t h_max) {
   if (h_max < 1 || h_max > MPMI_MAX_HORIZON) return 0;
   return mpmi::lifted_bytes(h_max);

@@ -73,6 +73,13 @@ hipError_t launch_fit(const mpmi_system& sys, int dim, const double* X, const do
 hipError_t launch_fit_lifted(const mpmi_system& sys, int dim, const double* X, const double* U, const double* Y,
                              int64_t T, double ridge, double* K_out, void* work, hipStream_t st);
 
+// Basis selection (mpmi_select.hip): workspace bytes for n_gamma penalties,
+// and the synchronous selection.
+size_t select_workspace_bytes(int n_gamma);
+hipError_t launch_select_basis(const mpmi_library& lib, const double* X, const double* U, const double* Y, int64_t T,
+                               const double* gammas_host, int n_gamma, double rho, int iters, double* B_out,
+                               uint8_t* support, double* resid_host, void* work, hipStream_t st);
+
 // Lifted whole-horizon tick (mpmi_lifted.hip).
 size_t lifted_bytes(int h_max);
 void lifted_layout(int basis, int n, int m, int D, int* feat_g, int* feat_phi, int* n_phi, int* n_g);

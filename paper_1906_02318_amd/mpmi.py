@@ -80,6 +80,17 @@ class MultiConfig(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("grid", ctypes.c_int32), ("precision", ctypes.c_int32)]
 
 
+MAX_LIBRARY = 160
+
+
+class Library(ctypes.Structure):
+    _fields_ = [
+        ("n_state", ctypes.c_int32), ("n_input", ctypes.c_int32), ("n_atoms", ctypes.c_int32),
+        ("n_feat", ctypes.c_int32), ("atom_kind", ctypes.c_int8 * 32), ("atom_var", ctypes.c_int8 * 32),
+        ("feat_a", ctypes.c_uint8 * MAX_LIBRARY), ("feat_b", ctypes.c_uint8 * MAX_LIBRARY),
+    ]
+
+
 class MpmiError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"mpmi status {status}: {msg}")
@@ -135,6 +146,8 @@ def library() -> ctypes.CDLL:
         "mpmi_tick_autotune": (i32, [vp, vp, ctypes.POINTER(TickDesc), vp, vp, vp, vp, i32,
                                      ctypes.POINTER(ctypes.c_float), vp]),
         "mpmi_basis_describe": (i32, [i32, i32, i32, ctypes.POINTER(System)]),
+        "koopman_select_basis": (i32, [vp, ctypes.POINTER(Library), vp, vp, vp, i64, ctypes.POINTER(f64), i32, f64,
+                                       i32, vp, vp, ctypes.POINTER(f64), vp]),
         "mpmi_tick_noalloc": (i32, [ctypes.POINTER(System), vp, ctypes.POINTER(TickDesc), vp, vp, vp, vp, vp, vp]),
         "mpmi_basis_match": (i32, [ctypes.POINTER(System)]),
         "koopman_fit_lifted": (i32, [vp, ctypes.POINTER(System), vp, vp, vp, i64, f64, vp, ctypes.POINTER(f64), vp]),
@@ -212,6 +225,20 @@ def basis_match(system: System) -> int:
 
 
 _ATOM_CODES = {"one": ATOM_ONE, "var": ATOM_VAR, "sin": ATOM_SIN, "cos": ATOM_COS}
+
+
+def library_desc(n: int, m: int, atoms, feats) -> Library:
+    """A basis-selection library: atoms [(ATOM_* or 'one'/'var'/'sin'/'cos', w index)],
+    functions [(atom a, atom b)]."""
+    lib = Library()
+    if not 1 <= len(atoms) <= MAX_ATOMS or not 1 <= len(feats) <= MAX_LIBRARY:
+        raise ValueError("1..32 atoms and 1..160 functions")
+    lib.n_state, lib.n_input, lib.n_atoms, lib.n_feat = n, m, len(atoms), len(feats)
+    for q, (kind, var) in enumerate(atoms):
+        lib.atom_kind[q], lib.atom_var[q] = _ATOM_CODES.get(kind, kind), var
+    for f, (a, b) in enumerate(feats):
+        lib.feat_a[f], lib.feat_b[f] = a, b
+    return lib
 
 
 def linear_system(n, m, box, u_lo, u_hi):
@@ -386,6 +413,27 @@ def basis_dim(system: System) -> int:
     if system.basis == BASIS_CUSTOM:
         return system.dim
     return {BASIS_LINEAR: system.n_state + system.n_input, BASIS_BALANCE_BOT: 21, BASIS_RACE_CAR: 64}[system.basis]
+
+
+def koopman_select_basis(ctx: Context, lib: Library, X, U, Y, gammas, rho: float = 1.0, iters: int = 500,
+                         stream=None):
+    """Sparsity-promoting selection over the library for every penalty in
+    gammas: returns (B (n_gamma, L, n) float64 device tensor, support
+    (n_gamma, L) uint8 device tensor, residuals (n_gamma, 2) numpy)."""
+    T, n = X.shape
+    for t, name in ((X, "X"), (U, "U"), (Y, "Y")):
+        _need(t, name, torch.float64, device=ctx.device)
+    if U.shape[0] != T or Y.shape != X.shape or n != lib.n_state or U.shape[1] != lib.n_input:
+        raise ValueError("X, U, Y must have T rows, n and m columns as the library states")
+    g = (ctypes.c_double * len(gammas))(*[float(v) for v in gammas])
+    B = torch.empty((len(gammas), lib.n_feat, n), dtype=torch.float64, device=ctx.device)
+    sup = torch.empty((len(gammas), lib.n_feat), dtype=torch.uint8, device=ctx.device)
+    res = (ctypes.c_double * (2 * len(gammas)))()
+    ctx.check(ctx.lib.koopman_select_basis(ctx.handle, ctypes.byref(lib), _ptr(X.contiguous()),
+                                           _ptr(U.contiguous()), _ptr(Y.contiguous()), T, g, len(gammas),
+                                           float(rho), int(iters), _ptr(B), _ptr(sup), res, _stream(stream)))
+    import numpy as _np
+    return B, sup, _np.array(res[:]).reshape(len(gammas), 2)
 
 
 def koopman_fit_lifted(ctx: Context, system: System, X, U, Y, ridge: float = 0.0, stream=None):
