@@ -29,9 +29,11 @@ PEAK_HBM_GBS = 8000.0
 
 # Algorithmic FP32 work of one unit (one candidate advanced one step and
 # checked), flops with an FMA counted as 2.
-#   race car: 51 feature products + 64x6 contraction (768) + track/v_y check (62)
+#   race car: 51 feature products + 64x6 contraction (768) + ~41 for the
+#     track and v_y checks (rho^2, the centreline's harmonics, two margins
+#     and compares) = 860
 #   balance bot: 15 feature products + 21x4 contraction (168) + two box checks (4)
-FLOPS_PER_UNIT = {"race_car": 881, "balance_bot": 187}
+FLOPS_PER_UNIT = {"race_car": 860, "balance_bot": 187}
 # What the folded step executes per unit (input terms folded once per segment):
 #   race car: 511, from the FP32 FMA/MUL/ADD instruction counters of the
 #     1M-candidate tick per executed unit (27 feature products, 210 step FMAs,
@@ -133,14 +135,34 @@ def setup(wl: dict, n_ticks: int):
                 fit=(X, U, Y), cond=cond, fit_ms=fit_ms)
 
 
-def cpu_baseline(wl: dict, st: dict, budget_s: float = 15.0):
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(wl: dict, st: dict, budget_s: float = 15.0, budget_1t_s: float = 5.0):
     """FP64 oracle timed on this host's cores on a bounded sample of the same
-    workload: every k-th candidate of each tick's candidate set."""
+    workload: every k-th candidate of each tick's candidate set; then the same
+    sample with one BLAS thread."""
+    cores = len(os.sched_getaffinity(0))
+    multi = _cpu_oracle_rate(wl, st, cores, budget_s)
+    one = _cpu_oracle_rate(wl, st, 1, budget_1t_s)
+    multi.update(cores=cores, kind="oracle", cpu_model=cpu_model(),
+                 one_thread={"value": one["value"], "unit": one["unit"], "sample": one["sample"]})
+    return multi
+
+
+def _cpu_oracle_rate(wl: dict, st: dict, cores: int, budget_s: float):
     from threadpoolctl import threadpool_limits
 
     from oracle import mpmi_oracle as o
 
-    cores = len(os.sched_getaffinity(0))
     X, U, Y = st["fit"]
     kind = wl["system"]
     K, _ = o.fit(kind, X, U, Y)
@@ -176,9 +198,9 @@ def cpu_baseline(wl: dict, st: dict, budget_s: float = 15.0):
             ticks += 1
             if t_used > budget_s:
                 break
-    return dict(value=n_eval / t_used, unit="trajectories/s", cores=cores, kind="oracle",
+    return dict(value=n_eval / t_used, unit="trajectories/s",
                 sample=f"{ticks} ticks x {n_eval // ticks} candidates (every {stride}th of the {N}-candidate set "
-                       f"plus u_h), H={H}, FP64 NumPy, {t_used:.1f} s")
+                       f"plus u_h), H={H}, FP64 NumPy, {cores} BLAS thread(s), {t_used:.1f} s")
 
 
 def run_multi(n_ticks: int = 2000, warmup: int = 50, seed: int = 5):
@@ -412,6 +434,143 @@ def run_trajectory_store(st: dict, reps: int = 10):
     return res
 
 
+def timed_ticks(step, n_ticks: int, warmup: int, stream):
+    """Per-tick device times (HIP events on `stream`) and the wall time of n_ticks calls of step(t)."""
+    import torch
+
+    for t in range(warmup):
+        step(t)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n_ticks)]
+    t0 = time.perf_counter()
+    for t in range(n_ticks):
+        ev[t][0].record(stream)
+        step(t)
+        ev[t][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return np.array([a.elapsed_time(b) for a, b in ev]), wall
+
+
+def run_recheck64(st: dict, n_ticks: int = 100, warmup: int = 5):
+    """The headline ticks with the FP64 re-roll of the FP32 rounding band
+    (every candidate whose FP32 margin comes within 2e-3 m of the track edge or
+    3e-4 m/s of the v_y bound is predicted again in FP64 before the
+    selection)."""
+    import torch
+
+    from paper_1906_02318_amd import mpmi
+
+    ctx, model, N = st["ctx"], st["model"], st["N"]
+    stream = torch.cuda.current_stream()
+    outs = torch.empty((64, mpmi.SELECTION_BYTES), dtype=torch.uint8, device="cuda")
+    descs = [st["mk"](t) for t in range(64)]
+    for d in descs:
+        d.precision = mpmi.PREC_FP32_RECHECK64
+
+    def step(t):
+        i = t % 64
+        mpmi.mpmi_tick(ctx, model, descs[i], st["x"][i], st["u"][i], out=outs[i], stream=stream)
+
+    ms, wall = timed_ticks(step, n_ticks, warmup, stream)
+    sels = mpmi.decode_selection(outs)
+    re = [s_["n_recheck"] for s_ in sels[:min(n_ticks, 64)]]
+    return {"trajectories_per_s": (N + 1) * n_ticks / wall, "ms_per_tick": wall * 1e3 / n_ticks,
+            "p50_tick_ms": float(np.percentile(ms, 50)), "p99_tick_ms": float(np.percentile(ms, 99)),
+            "rechecked_per_tick_mean": float(np.mean(re)), "rechecked_per_tick_max": int(np.max(re)),
+            "note": "FP32 tick (near-band candidates listed) + FP64 re-roll launch; decisions those of FP64 "
+                    "rollouts (tests: 1M tick identical to the full oracle)"}
+
+
+def run_lifted(st: dict, wl: dict, n_ticks: int = 100, warmup: int = 5):
+    """The same ticks in the lifted whole-horizon form (Sec. IV-A's batch
+    prediction as one matrix product): the full lifted operator fitted on the
+    GPU, powers folded on the host, every candidate's horizon as
+    [candidates x 12] x [12 x 4 H] products on v_mfma_f32_16x16x4f32 with the
+    safety check on each output tile."""
+    import torch
+
+    from paper_1906_02318_amd import mpmi
+
+    ctx, model, N, H = st["ctx"], st["model"], st["N"], wl["H"]
+    stream = torch.cuda.current_stream()
+    X, U, Y = st["fit"]
+    d = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+    t0 = time.perf_counter()
+    KL, cond = mpmi.koopman_fit_lifted(ctx, model.system, d(X), d(U), d(Y))
+    fit_ms = (time.perf_counter() - t0) * 1e3
+    t0 = time.perf_counter()
+    lifted = mpmi.mpmi_lifted_pack(ctx, model, KL, H)
+    pack_ms = (time.perf_counter() - t0) * 1e3
+    outs = torch.empty((64, mpmi.SELECTION_BYTES), dtype=torch.uint8, device="cuda")
+    descs = [st["mk"](t) for t in range(64)]
+    fv = torch.empty(N + 1, dtype=torch.int16, device="cuda")
+    units = []
+    for i in range(64):
+        mpmi.mpmi_tick_lifted(ctx, lifted, descs[i], st["x"][i], st["u"][i], out=outs[i], first_violation=fv,
+                              stream=stream)
+        units.append(int(torch.clamp(fv.to(torch.int64), max=H).sum().item()))
+
+    def step(t):
+        i = t % 64
+        mpmi.mpmi_tick_lifted(ctx, lifted, descs[i], st["x"][i], st["u"][i], out=outs[i], stream=stream)
+
+    ms, wall = timed_ticks(step, n_ticks, warmup, stream)
+    units_tick = float(np.mean([units[t % 64] for t in range(n_ticks)]))
+    # Matrix-core work: per 16 candidates x 4 steps, three 16x16x4 FP32 MFMAs
+    # (2 * 16 * 16 * 12 flops), i.e. 96 flops per candidate-step, of which the
+    # 9 input functions x 4 output slots are algorithmic (72).
+    mfma_tflops = 96.0 * units_tick / (float(ms.mean()) * 1e-3) / 1e12
+    return {"trajectories_per_s": (N + 1) * n_ticks / wall, "ms_per_tick": wall * 1e3 / n_ticks,
+            "p50_tick_ms": float(np.percentile(ms, 50)), "p99_tick_ms": float(np.percentile(ms, 99)),
+            "units_per_tick": units_tick, "lifted_fit_ms": fit_ms, "lifted_pack_ms": pack_ms, "cond": cond,
+            "mfma_tflops_executed_lower_bound": mfma_tflops, "mfma_peak_fp32_tflops": PEAK_FP32_VECTOR_TFLOPS,
+            "note": "lifted predictions differ from the re-lifting model's (tests: median position error vs the "
+                    "plant 0.68 m lifted / 0.31 m re-lift at step 60); MFMA busy from rocprofv3 counters in "
+                    "profiles/"}
+
+
+MLP_FLOPS_PER_SAMPLE = 917504  # forward 2(8*256 + 2*256*256 + 256*80) + the same for dW + dX of layers 1..3
+PEAK_BF16_MFMA_TFLOPS = 2500.0
+
+
+def run_mlp_training(batch: int = 4096, steps: int = 50, warmup: int = 5):
+    """One training step of the proposal network (forward, mixture loss,
+    backward, Adam) on the library's kernels, batch 4,096, synthetic rows:
+    step time, and the BF16 matrix-core rate of its dense products."""
+    import torch
+
+    import synth
+    from paper_1906_02318_amd import mpmi
+    from paper_1906_02318_amd.proposal import ProposalNet
+
+    ctx = mpmi.Context(0)
+    rng = np.random.default_rng(21)
+    X = rng.normal(size=(batch, 8)).astype(np.float32)
+    T = rng.uniform(-0.9, 0.9, size=(batch, 2)).astype(np.float32)
+    net = ProposalNet(ctx, synth.mlp_init(6), X.mean(axis=0), X.std(axis=0))
+    Xd, Td = torch.tensor(X, device="cuda"), torch.tensor(T, device="cuda")
+    work = mpmi.mlp_workspace(ctx, batch)
+    grad = torch.empty(mpmi.MLP_PARAMS, dtype=torch.float32, device="cuda")
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def step(t):
+        mpmi.mlp_grad(ctx, net.w16, net.w32, net.mean, net.std, Xd, Td, work=work, grad=grad, loss=loss,
+                      stream=stream)
+        net.step += 1
+        mpmi.mlp_adam(ctx, net.w32, net.w16, net.m, net.v, grad, net.step, 1e-3, stream=stream)
+
+    ms, wall = timed_ticks(step, steps, warmup, stream)
+    step_ms = float(np.median(ms))
+    tflops = MLP_FLOPS_PER_SAMPLE * batch / (step_ms * 1e-3) / 1e12
+    return {"batch": batch, "step_ms_p50": step_ms, "step_ms_wall": wall * 1e3 / steps,
+            "tflops": tflops, "bf16_mfma_peak_tflops": PEAK_BF16_MFMA_TFLOPS,
+            "mfma_frac": tflops / PEAK_BF16_MFMA_TFLOPS,
+            "note": "11 dense products of at most 4096 x 256 x 256 (0.5 GFLOP each) plus loss, split-K "
+                    "reductions and Adam: launch- and latency-bound; kernel times in profiles/"}
+
+
 def run_plain_vs_learned(n_ticks: int = 500, warmup: int = 20):
     """Race car at its stated size: exhaustive 128 x 128 grid tick vs the learned
     2,048-proposal tick (exhaustive fallback), on the same tick inputs."""
@@ -479,6 +638,9 @@ def run_plain_vs_learned(n_ticks: int = 500, warmup: int = 20):
     return out
 
 
+LEGS = ("bf16x3", "recheck64", "lifted", "trajectory", "learned", "mlp", "multi", "closed_loop")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -488,11 +650,16 @@ def main():
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
-    ap.add_argument("--no-extras", action="store_true", help="skip the many-loop and plain-vs-learned legs")
+    ap.add_argument("--no-extras", action="store_true", help="skip every leg after the headline ticks")
+    ap.add_argument("--legs", default=",".join(LEGS),
+                    help="comma-separated legs to run after the headline ticks (of: " + ", ".join(LEGS) + ")")
     ap.add_argument("--multi-ticks", type=int, default=10000)
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="after timing, run one device-to-device copy of this many bytes (counter calibration)")
     args = ap.parse_args()
+    legs = set() if args.no_extras or args.workload != "race_car_1m" else {x for x in args.legs.split(",") if x}
+    if legs - set(LEGS):
+        ap.error(f"unknown legs {sorted(legs - set(LEGS))}")
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the tick's candidates would shard "
               f"across GPUs with one 8-byte arg-min exchange per loop; multi-GPU runs are not implemented.",
@@ -596,7 +763,7 @@ def main():
                     "ceiling measured live (fp32_fma_ceiling_tflops; 78.6 theoretical)",
         },
     }
-    if not args.no_extras and args.workload == "race_car_1m":
+    if "bf16x3" in legs:
         # Same ticks with the shared-coefficient contraction on BF16 matrix cores
         # (hi/lo split) and the FP32 recheck of near-boundary candidates.
         bdescs = [st["mk"](t) for t in range(n_inputs)]
@@ -631,10 +798,19 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         out["calibration_copy_bytes"] = args.copy_bytes
-    if not args.no_extras and args.workload == "race_car_1m":
+    if "recheck64" in legs:
+        out["race_car_1m_fp32_recheck64"] = run_recheck64(st)
+    if "lifted" in legs:
+        out["race_car_1m_lifted"] = run_lifted(st, wl)
+    if "trajectory" in legs:
         out["trajectory_store"] = run_trajectory_store(st)
+    if "learned" in legs:
         out["race_car_16k"] = run_plain_vs_learned()
+    if "mlp" in legs:
+        out["mlp_training"] = run_mlp_training()
+    if "multi" in legs:
         out["many_loops"] = run_multi(n_ticks=args.multi_ticks)
+    if "closed_loop" in legs:
         out["balance_bot_closed_loop"] = run_closed_loop_balance_bot()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, st, args.cpu_budget)

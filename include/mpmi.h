@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define MPMI_ABI_VERSION 6
+#define MPMI_ABI_VERSION 7
 
 /* Size limits (checked on the host). */
 #define MPMI_MAX_STATE 8      /* n */
@@ -89,17 +89,22 @@ enum { MPMI_ATOM_ONE = 0, MPMI_ATOM_VAR = 1, MPMI_ATOM_SIN = 2, MPMI_ATOM_COS = 
 
 /* Arithmetic of the prediction step.
  *  FP32    states, features and K in FP32, FP32 accumulation.
- *  FP32_RECHECK64  the FP32 tick, and every candidate that has a checked
- *          state (steps 1 .. its first violation) whose margin to some
- *          constraint lies within that constraint's FP32 band (eps32_box,
- *          eps32_track) of zero is then re-rolled from x_t in FP64 (K, the
- *          features, noise and margins in FP64, as in the sketch of Sec.
- *          IV-A and IV-B written in double precision); the FP64 first
- *          violation replaces the FP32 one before the selection.  With bands
- *          at least the FP32 rollout's margin error, every verdict, and so
- *          the selection, is that of an FP64 rollout.  One lane per
- *          candidate, ticks of at most 2^22 candidates (MPMI_EUNSUPPORTED
- *          otherwise); trajectories, when stored, are the FP32 states.
+ *  FP32_RECHECK64  the FP32 tick; every candidate that has a checked state
+ *          (steps 1 .. its first violation) whose margin to some constraint
+ *          lies within that constraint's FP32 band (eps32_box, eps32_track)
+ *          of zero is listed instead of ranked (n_recheck counts them).  A
+ *          second launch predicts again from x_t, with K, the features, noise
+ *          and margins in FP64 (Sec. IV-A and IV-B in double precision), every
+ *          listed candidate whose selection key precedes the least key
+ *          ranked outside the band -- every listed one when no candidate
+ *          outside the band is safe -- and its FP64 first violation replaces
+ *          the FP32 one; the other listed candidates cannot change the
+ *          selection and keep their FP32 verdicts.  With bands at least the
+ *          FP32 rollout's margin error, the selection is that of an FP64
+ *          rollout, and so is every first violation outside the band (and
+ *          every one, when nothing is safe).  One lane per candidate, ticks of
+ *          at most 2^22 candidates (MPMI_EUNSUPPORTED otherwise);
+ *          trajectories, when stored, are the FP32 states.
  *  BF16X3  the contraction runs on BF16 matrix cores as three products of
  *          hi/lo BF16 splits of the features and of (K - E) in residual form
  *          x' = x + psi^T (K - E), FP32 accumulation; every candidate whose
@@ -288,12 +293,16 @@ mpmi_status rollout_batch(mpmi_ctx ctx, const void* model, int32_t precision,
 
 /* Safety verdicts of stored trajectories (Sec. IV-B; Alg. 2 safety check):
  * traj [H][n][traj_ld] (traj_ld >= Nc); first_violation[c] = first step s in
- * 1..H whose state traj[s-1][.][c] is unsafe, or H+1.  min_margin
- * (optional, may be NULL) [Nc] = the least margin over all constraints and
- * over steps 1..min(first_violation, H).                                     */
+ * 1..H whose state traj[s-1][.][c] is unsafe, or H+1.  near_bits (optional,
+ * may be NULL) [ceil(Nc/32)]: bit c % 32 of word c / 32 is set when some state
+ * of steps 1..min(first_violation, H) has a margin within its constraint's
+ * FP32 band (eps32_box / eps32_track of the packed system) of zero -- the
+ * candidates whose verdict FP32 rounding could decide.  min_margin (optional,
+ * may be NULL) [Nc] = the least margin over all constraints and over steps
+ * 1..min(first_violation, H).                                                */
 mpmi_status safe_mask(mpmi_ctx ctx, const void* model, const float* traj, int64_t traj_ld,
-                      int32_t Nc, int32_t H, int16_t* first_violation, float* min_margin,
-                      void* stream);
+                      int32_t Nc, int32_t H, int16_t* first_violation, uint32_t* near_bits,
+                      float* min_margin, void* stream);
 
 /* Minimal-intervention choice (Alg. 2 selection step; Sec. III-D; Sec. IV-D)
  * over candidates cand [S][m][Nc] with verdicts first_violation [Nc]
@@ -574,6 +583,17 @@ mpmi_status mpmi_multi_autotune(mpmi_ctx ctx, mpmi_multi multi, int32_t reps, mp
  * holds the launch shape of the plan at capture: after mpmi_multi_set_config
  * or mpmi_multi_autotune, destroy it and capture again. */
 mpmi_status mpmi_multi_graph(mpmi_ctx ctx, mpmi_multi multi, void** graph_exec);
+/* Captures one mpmi_tick (all of its launches: the FP32 tick, or the tick
+ * and its re-roll for BF16X3 / FP32_RECHECK64) with these arguments into an
+ * instantiated HIP graph (*graph_exec).  Replays read x_t, u_user (and cand)
+ * at the same addresses and write out and first_violation, so the caller
+ * updates the inputs between replays; the descriptor is fixed at capture (a
+ * UNIFORM tick replays the same draws: capture again, or use GRID /
+ * EXPLICIT candidates, for fresh ones).  No trajectory store.  Destroy with
+ * mpmi_graph_destroy. */
+mpmi_status mpmi_tick_graph(mpmi_ctx ctx, const void* model, const mpmi_tick_desc* desc /* host */,
+                            const float* x_t, const float* u_user, const float* cand, mpmi_selection* out,
+                            int16_t* first_violation, void** graph_exec);
 mpmi_status mpmi_graph_launch(mpmi_ctx ctx, void* graph_exec, void* stream);
 void mpmi_graph_destroy(void* graph_exec);
 

@@ -496,7 +496,7 @@ mpmi_status rollout_batch(mpmi_ctx ctx, const void* model, int32_t precision, co
 }
 
 mpmi_status safe_mask(mpmi_ctx ctx, const void* model, const float* traj, int64_t traj_ld, int32_t Nc, int32_t H,
-                      int16_t* first_violation, float* min_margin, void* stream) {
+                      int16_t* first_violation, uint32_t* near_bits, float* min_margin, void* stream) {
   if (!ctx) return MPMI_EINVAL;
   if (Nc < 1 || Nc > MPMI_MAX_CAND) return fail(ctx, MPMI_EINVAL, "Nc=%d out of 1..%d", Nc, MPMI_MAX_CAND);
   if (H < 1 || H > MPMI_MAX_HORIZON) return fail(ctx, MPMI_EINVAL, "H=%d out of 1..%d", H, MPMI_MAX_HORIZON);
@@ -506,7 +506,7 @@ mpmi_status safe_mask(mpmi_ctx ctx, const void* model, const float* traj, int64_
   mpmi_status s = model_system(ctx, model, &sys, (hipStream_t)stream);
   if (s != MPMI_OK) return s;
   return check_hip(ctx, mpmi::launch_mask(sys.basis, model, Nc, H, traj, traj_ld, first_violation, min_margin,
-                                          (hipStream_t)stream),
+                                          near_bits, (hipStream_t)stream),
                    "safe_mask launch");
 }
 
@@ -905,6 +905,31 @@ mpmi_status mpmi_multi_graph(mpmi_ctx ctx, mpmi_multi m, void** graph_exec) {
   return ok(ctx);
 }
 
+mpmi_status mpmi_tick_graph(mpmi_ctx ctx, const void* model, const mpmi_tick_desc* desc, const float* x_t,
+                            const float* u_user, const float* cand, mpmi_selection* out, int16_t* first_violation,
+                            void** graph_exec) {
+  if (!ctx) return MPMI_EINVAL;
+  if (!graph_exec) return fail(ctx, MPMI_EINVAL, "graph_exec is NULL");
+  *graph_exec = nullptr;
+  hipStream_t s = nullptr;
+  hipGraph_t g = nullptr;
+  hipGraphExec_t ge = nullptr;
+  mpmi_status st = MPMI_OK;
+  hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    st = mpmi_tick(ctx, model, desc, x_t, u_user, cand, out, first_violation, nullptr, 0, (void*)s);
+    e = hipStreamEndCapture(s, &g);
+  }
+  if (st == MPMI_OK && e == hipSuccess) e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+  if (g) (void)hipGraphDestroy(g);
+  if (s) (void)hipStreamDestroy(s);
+  if (st != MPMI_OK) return st;  // mpmi_tick's own message stays in ctx
+  if (e != hipSuccess) return fail(ctx, MPMI_EDEVICE, "mpmi_tick_graph: %s", hipGetErrorString(e));
+  *graph_exec = (void*)ge;
+  return ok(ctx);
+}
+
 mpmi_status mpmi_graph_launch(mpmi_ctx ctx, void* graph_exec, void* stream) {
   if (!ctx) return MPMI_EINVAL;
   if (!graph_exec) return fail(ctx, MPMI_EINVAL, "graph_exec is NULL");
@@ -1049,8 +1074,9 @@ constexpr int kScratchDevices = 64;
 
 struct alignas(64) ScratchSubSlot {
   unsigned long long key_safe = ~0ull, key_fb = ~0ull, count = 0ull;
-  unsigned int n_recheck = 0u;
-  unsigned int pad[9] = {};
+  unsigned int n_recheck = 0u, pad0 = 0u;
+  unsigned long long key_safe64 = ~0ull;
+  unsigned int pad[6] = {};
 };
 struct alignas(64) ScratchSlot {
   ScratchSubSlot sub[mpmi::kSubSlots];
@@ -1063,7 +1089,12 @@ struct alignas(256) ScratchImage {
   unsigned int pad[63] = {};
   int idx[kScratchRecheck] = {};
 };
-static_assert(sizeof(ScratchSlot) == sizeof(mpmi::Slot) && sizeof(ScratchSubSlot) == sizeof(mpmi::SubSlot),
+static_assert(sizeof(ScratchSlot) == sizeof(mpmi::Slot) && sizeof(ScratchSubSlot) == sizeof(mpmi::SubSlot) &&
+                  offsetof(ScratchSubSlot, key_fb) == offsetof(mpmi::SubSlot, key_fb) &&
+                  offsetof(ScratchSubSlot, count) == offsetof(mpmi::SubSlot, count) &&
+                  offsetof(ScratchSubSlot, n_recheck) == offsetof(mpmi::SubSlot, n_recheck) &&
+                  offsetof(ScratchSubSlot, key_safe64) == offsetof(mpmi::SubSlot, key_safe64) &&
+                  offsetof(ScratchSlot, done) == offsetof(mpmi::Slot, done),
               "scratch slots have the library's slot layout");
 static_assert(offsetof(ScratchImage, count) == (size_t)kScratchLoops * sizeof(mpmi::Slot) &&
                   offsetof(ScratchImage, idx) - offsetof(ScratchImage, count) == offsetof(mpmi::RecheckList, idx),

@@ -106,11 +106,14 @@ struct alignas(256) ModelDev {
 // and restores the reset state (keys all-ones, counters zero).
 constexpr int kSubSlots = 8;
 struct alignas(64) SubSlot {
-  unsigned long long key_safe;  // (cost bits << 32) | idx  over safe candidates
-  unsigned long long key_fb;    // ((255 - fv) << 56) | (cost bits << 25) | idx
-  unsigned long long count;     // low 32 bits: safe count; high 32: parts published
+  unsigned long long key_safe;    // (cost bits << 32) | idx  over safe candidates
+  unsigned long long key_fb;      // ((255 - fv) << 56) | (cost bits << 25) | idx
+  unsigned long long count;       // low 32 bits: safe count; high 32: parts published
   unsigned int n_recheck;
-  unsigned int pad[9];
+  unsigned int pad0;
+  unsigned long long key_safe64;  // safe keys of the FP64 re-roll (kept apart from key_safe,
+                                  // whose least value the re-roll compares against)
+  unsigned int pad[6];
 };
 struct alignas(64) Slot {
   SubSlot sub[kSubSlots];

@@ -58,7 +58,7 @@ hipError_t launch_multi_recheck64(const mpmi_loop_desc* loops, const void* model
 hipError_t launch_rollout(int basis, const void* model, int Nc, int S, int H, const float* x0,
                           const float* cand, float* traj, long long traj_ld, hipStream_t st);
 hipError_t launch_mask(int basis, const void* model, int Nc, int H, const float* traj, long long traj_ld,
-                       int16_t* fv, float* mm, hipStream_t st);
+                       int16_t* fv, float* mm, uint32_t* near_bits, hipStream_t st);
 hipError_t launch_select(const void* model, int Nc, int S, int H, const float* cand, const int16_t* fv,
                          const float* u_user, int loop, void* slot, mpmi_selection* out, hipStream_t st);
 hipError_t launch_gen(const void* model, const mpmi_tick_desc& d, const float* u_user, const float* cand,

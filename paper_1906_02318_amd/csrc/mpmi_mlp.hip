@@ -48,48 +48,159 @@ struct GemmArgs {
   const float* zin;    // kGeluBack: pre-activation [M][N] FP32
   float* out_f32;      // [M][N] or NULL
   uint16_t* out_bf16;  // [M][N] or NULL
+  // Split-K (kPlain only): gridDim.z parts of ksplit rows of K each write
+  // FP32 partial products to part[z][M][N]; colsum (or NULL), an FP32
+  // [K][N] matrix whose column sums over each part's K range go to
+  // part_cs[z][N] (the bias gradient of a dW product).
+  int ksplit;
+  float* part;
+  const float* colsum;
+  float* part_cs;
+  bool vec_a, vec_b;   // 16-byte loads allowed (leading dimension a multiple of 8, 16-byte aligned base)
 };
+
+// C = op(A) op(B) on v_mfma_f32_16x16x32_bf16.  A 256-thread workgroup owns a
+// 64 x 64 tile of C, each wave a 32 x 32 quarter as 2 x 2 MFMA blocks.  Per
+// 32-wide k step every thread moves one 16-byte chunk (8 BF16) of A and one
+// of B from global memory into LDS, in the operand order the MFMA reads (row
+// or column, then k): a chunk along k (row-major A, transposed B) is stored
+// as one 16-byte LDS write, a chunk along m or n as eight 2-byte writes.  The
+// next step's chunks are loaded into registers while the current step's
+// MFMAs run, and the two LDS buffers alternate (one barrier per step).
+// Chunks that are contiguous, aligned and wholly inside the matrix take one
+// 16-byte load; others (ragged edges, odd leading dimensions) load element by
+// element.
+constexpr int kGemmKP = 40;  // padded k extent of an LDS row (80 B, keeps 16-B alignment)
+
+struct GemmChunk {
+  uint4 a, b;
+};
+
+// Eight BF16 values p[0], p[s], ..., p[7 s], those with index >= lim zero,
+// packed as a 16-byte chunk; one 16-byte load when all eight are in range
+// and contiguous and aligned (vec).
+__device__ __forceinline__ uint4 load_chunk(const uint16_t* __restrict__ p, size_t s, int idx, int lim, bool vec) {
+  if (vec && idx + 8 <= lim) return *reinterpret_cast<const uint4*>(p);
+  uint32_t w[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+    if (idx + i < lim) w[i >> 1] |= (uint32_t)p[(size_t)i * s] << ((i & 1) * 16);
+  return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+// This thread's chunks of the k step at k0: A row-major -- row t / 4, k
+// (t % 4) * 8 .. +8; A transposed -- k t / 8, rows (t % 8) * 8 .. +8; B
+// transposed -- column t / 4, k (t % 4) * 8 .. +8; B row-major -- k t / 8,
+// columns (t % 8) * 8 .. +8.  Values outside the matrix (or past kend) are 0.
+__device__ __forceinline__ void gemm_load(const GemmArgs& g, int m0, int n0, int k0, int kend, GemmChunk* c) {
+  const int t = threadIdx.x;
+  c->a = make_uint4(0u, 0u, 0u, 0u);
+  c->b = make_uint4(0u, 0u, 0u, 0u);
+  if (!g.ta) {
+    const int m = m0 + (t >> 2), k = k0 + (t & 3) * 8;
+    if (m < g.M && k < kend) c->a = load_chunk(g.A + (size_t)m * g.lda + k, 1, k, kend, g.vec_a);
+  } else {
+    const int k = k0 + (t >> 3), m = m0 + (t & 7) * 8;
+    if (m < g.M && k < kend) c->a = load_chunk(g.A + (size_t)k * g.lda + m, 1, m, g.M, g.vec_a);
+  }
+  if (g.tb) {
+    const int n = n0 + (t >> 2), k = k0 + (t & 3) * 8;
+    if (n < g.N && k < kend) c->b = load_chunk(g.B + (size_t)n * g.ldb + k, 1, k, kend, g.vec_b);
+  } else {
+    const int k = k0 + (t >> 3), n = n0 + (t & 7) * 8;
+    if (n < g.N && k < kend) c->b = load_chunk(g.B + (size_t)k * g.ldb + n, 1, n, g.N, g.vec_b);
+  }
+}
+
+__device__ __forceinline__ void gemm_store(const GemmArgs& g, const GemmChunk& c, uint16_t (*As)[kGemmKP],
+                                           uint16_t (*Bs)[kGemmKP]) {
+  const int t = threadIdx.x;
+  const uint32_t wa[4] = {c.a.x, c.a.y, c.a.z, c.a.w};
+  const uint32_t wb[4] = {c.b.x, c.b.y, c.b.z, c.b.w};
+  if (!g.ta) {
+    *reinterpret_cast<uint4*>(&As[t >> 2][(t & 3) * 8]) = c.a;
+  } else {
+    const int k = t >> 3, m = (t & 7) * 8;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      As[m + 2 * i][k] = (uint16_t)(wa[i] & 0xffffu);
+      As[m + 2 * i + 1][k] = (uint16_t)(wa[i] >> 16);
+    }
+  }
+  if (g.tb) {
+    *reinterpret_cast<uint4*>(&Bs[t >> 2][(t & 3) * 8]) = c.b;
+  } else {
+    const int k = t >> 3, n = (t & 7) * 8;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      Bs[n + 2 * i][k] = (uint16_t)(wb[i] & 0xffffu);
+      Bs[n + 2 * i + 1][k] = (uint16_t)(wb[i] >> 16);
+    }
+  }
+}
 
 template <int EPI>
 __global__ void __launch_bounds__(256) gemm_bf16_kernel(GemmArgs g) {
-  constexpr int KP = 40;  // padded k extent of an LDS row (80 B, keeps 16-B alignment)
-  __shared__ __attribute__((aligned(16))) uint16_t As[64][KP];
-  __shared__ __attribute__((aligned(16))) uint16_t Bs[64][KP];
+  __shared__ __attribute__((aligned(16))) uint16_t As[2][64][kGemmKP];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[2][64][kGemmKP];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+  const int kbeg = blockIdx.z * g.ksplit;
+  const int kend = min(g.K, kbeg + g.ksplit);
   f32x4_t acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-  const int lr = t >> 2, lk = (t & 3) * 8;  // staging: row/col lr, k chunk lk..lk+7
-  for (int k0 = 0; k0 < g.K; k0 += 32) {
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int k = k0 + lk + q;
-      const int m = m0 + lr, n = n0 + lr;
-      uint16_t a = 0, b = 0;
-      if (m < g.M && k < g.K) a = g.ta ? g.A[(size_t)k * g.lda + m] : g.A[(size_t)m * g.lda + k];
-      if (n < g.N && k < g.K) b = g.tb ? g.B[(size_t)n * g.ldb + k] : g.B[(size_t)k * g.ldb + n];
-      As[lr][lk + q] = a;
-      Bs[lr][lk + q] = b;
-    }
-    __syncthreads();
+  GemmChunk c;
+  gemm_load(g, m0, n0, kbeg, kend, &c);
+  gemm_store(g, c, As[0], Bs[0]);
+  __syncthreads();
+  int buf = 0;
+  for (int k0 = kbeg; k0 < kend; k0 += 32) {
+    const bool more = k0 + 32 < kend;
+    if (more) gemm_load(g, m0, n0, k0 + 32, kend, &c);
     const int kq = (lane >> 4) * 8;
     bf16x8_t af[2], bfr[2];
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
-      af[i] = *reinterpret_cast<const bf16x8_t*>(&As[wm * 32 + i * 16 + (lane & 15)][kq]);
-      bfr[i] = *reinterpret_cast<const bf16x8_t*>(&Bs[wn * 32 + i * 16 + (lane & 15)][kq]);
+      af[i] = *reinterpret_cast<const bf16x8_t*>(&As[buf][wm * 32 + i * 16 + (lane & 15)][kq]);
+      bfr[i] = *reinterpret_cast<const bf16x8_t*>(&Bs[buf][wn * 32 + i * 16 + (lane & 15)][kq]);
     }
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
       for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+    if (more) gemm_store(g, c, As[buf ^ 1], Bs[buf ^ 1]);
     __syncthreads();
+    buf ^= 1;
+  }
+  // Bias-gradient partial column sums over this part's K range (dW products:
+  // the workgroups of the first tile row).  Thread t sums rows
+  // kbeg + (t >> 6) + 4 i of column n0 + (t & 63) into four interleaved
+  // accumulators (independent loads in flight); the four row groups are then
+  // added in a fixed order.
+  if (EPI == kPlain && g.colsum && blockIdx.y == 0) {  // uniform across the workgroup
+    __shared__ float cs[4][64];
+    const int col = t & 63, rg = t >> 6;
+    const int n = n0 + col;
+    float a[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (n < g.N) {
+      int k = kbeg + rg;
+      for (; k + 12 < kend; k += 16) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) a[q] += g.colsum[(size_t)(k + 4 * q) * g.N + n];
+      }
+      for (int q = 0; k < kend; k += 4, ++q) a[q & 3] += g.colsum[(size_t)k * g.N + n];
+    }
+    cs[rg][col] = (a[0] + a[1]) + (a[2] + a[3]);
+    __syncthreads();
+    if (t < 64 && n0 + t < g.N)
+      g.part_cs[(size_t)blockIdx.z * g.N + n0 + t] = (cs[0][t] + cs[1][t]) + (cs[2][t] + cs[3][t]);
   }
   // D fragment: lane holds column (lane & 15), rows (lane >> 4) * 4 + r.
+  float* dst = (EPI == kPlain && g.part) ? g.part + (size_t)blockIdx.z * g.M * g.N : nullptr;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -101,7 +212,9 @@ __global__ void __launch_bounds__(256) gemm_bf16_kernel(GemmArgs g) {
         if (m >= g.M || n >= g.N) continue;
         float v = acc[i][j][r];
         const size_t o = (size_t)m * g.N + n;
-        if (EPI == kGelu) {
+        if (dst) {
+          dst[o] = v;
+        } else if (EPI == kGelu) {
           v += g.bias[n];
           if (g.out_f32) g.out_f32[o] = v;
           g.out_bf16[o] = f2bf(gelu_f(v));
@@ -120,9 +233,34 @@ __global__ void __launch_bounds__(256) gemm_bf16_kernel(GemmArgs g) {
       }
 }
 
+// Split-K reduction: out[e] = sum over parts z (in order) of part[z][e],
+// e < M N; then cs_out[n] = sum over z of part_cs[z][n] when cs_out is set.
+__global__ void splitk_reduce_kernel(const float* __restrict__ part, int parts, int MN, float* __restrict__ out,
+                                     const float* __restrict__ part_cs, int N, float* __restrict__ cs_out) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < MN) {
+    float s = 0.0f;
+    for (int z = 0; z < parts; ++z) s += part[(size_t)z * MN + e];
+    out[e] = s;
+  } else if (cs_out && e < MN + N) {
+    const int n = e - MN;
+    float s = 0.0f;
+    for (int z = 0; z < parts; ++z) s += part_cs[(size_t)z * N + n];
+    cs_out[n] = s;
+  }
+}
+
+// Launches op(A) op(B) in `splits` parts of the K range (rounded to 32-row
+// steps; *parts_out receives the number of parts launched).
 template <int EPI>
-static hipError_t gemm(const GemmArgs& g, hipStream_t st) {
-  dim3 grid((g.N + 63) / 64, (g.M + 63) / 64);
+static hipError_t gemm(GemmArgs g, hipStream_t st, int splits = 1, int* parts_out = nullptr) {
+  g.vec_a = g.lda % 8 == 0 && ((uintptr_t)g.A & 15) == 0;
+  g.vec_b = g.ldb % 8 == 0 && ((uintptr_t)g.B & 15) == 0;
+  if (splits < 1) splits = 1;
+  g.ksplit = (((g.K + splits - 1) / splits) + 31) / 32 * 32;
+  splits = (g.K + g.ksplit - 1) / g.ksplit;
+  if (parts_out) *parts_out = splits;
+  dim3 grid((g.N + 63) / 64, (g.M + 63) / 64, splits);
   gemm_bf16_kernel<EPI><<<grid, 256, 0, st>>>(g);
   return hipGetLastError();
 }
@@ -199,15 +337,6 @@ __global__ void mdn_loss_kernel(const float* __restrict__ Y, const float* __rest
     __syncthreads();
   }
   if (threadIdx.x == 0 && loss_sum) atomicAdd(loss_sum, red[0] / (float)B);
-}
-
-// Column sums of dZ [M][N] (FP32), deterministic: one thread per column.
-__global__ void colsum_kernel(const float* __restrict__ dZ, int M, int N, float* __restrict__ db) {
-  const int n = blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= N) return;
-  float s = 0.0f;
-  for (int m = 0; m < M; ++m) s += dZ[(size_t)m * N + n];
-  db[n] = s;
 }
 
 // Adam (Kingma & Ba 2015) with bias correction on the FP32 master weights,
@@ -444,9 +573,13 @@ mlp_row_forward_kernel(const float* __restrict__ x_t, const float* __restrict__ 
 // ---------------------------------------------------------------------------
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Split-K parts of the weight-gradient products (batch rows split into at
+// most kMlpSplits ranges of at least kMlpSplitRows rows).
+constexpr int kMlpSplits = 16, kMlpSplitRows = 256;
+
 struct MlpWork {
   uint16_t *h0, *h1, *h2, *h3, *dY16, *dz16;
-  float *z1, *z2, *z3, *Y, *dY32, *dz32, *nll, *loss, *row;
+  float *z1, *z2, *z3, *Y, *dY32, *dz32, *nll, *loss, *row, *part, *part_cs;
 };
 
 static MlpWork carve(void* base, int B) {
@@ -468,13 +601,15 @@ static MlpWork carve(void* base, int B) {
   w.nll = (float*)take((size_t)B * 4);
   w.loss = (float*)take(4);
   w.row = (float*)take(kMlpIn * 4);
+  w.part = (float*)take((size_t)kMlpSplits * kMlpHid * kMlpHid * 4);
+  w.part_cs = (float*)take((size_t)kMlpSplits * kMlpHid * 4);
   return w;
 }
 
 size_t mlp_workspace_bytes(int B) {
   char* base = nullptr;
   MlpWork w = carve((void*)base, B);
-  return (size_t)((char*)w.row - base) + align256(kMlpIn * 4);
+  return (size_t)((char*)w.part_cs - base) + align256((size_t)kMlpSplits * kMlpHid * 4);
 }
 
 // Offsets of (W_l, b_l) in the flat parameter vector.
@@ -539,13 +674,20 @@ hipError_t launch_mlp_grad(const uint16_t* w16, const float* w32, const float* m
   const uint16_t* dz16 = w.dY16;
   for (int l = 3; l >= 0; --l) {
     const int kin = dims[l], nout = dims[l + 1];
-    // dW_l = h_{l-1}^T dz  ([kin][nout])
+    // dW_l = h_{l-1}^T dz  ([kin][nout]), split over the batch rows, with
+    // the bias gradient db_l = column sums of dz (FP32) in the same parts;
+    // both reduced over the parts in order.
     GemmArgs gw{};
     gw.A = hin[l]; gw.ta = 1; gw.lda = kin;
     gw.B = dz16; gw.ldb = nout;
-    gw.M = kin; gw.N = nout; gw.K = B; gw.out_f32 = grad + ow[l];
-    if ((e = gemm<kPlain>(gw, st)) != hipSuccess) return e;
-    colsum_kernel<<<(nout + 255) / 256, 256, 0, st>>>(dz32, B, nout, grad + ob[l]);
+    gw.M = kin; gw.N = nout; gw.K = B;
+    gw.part = w.part; gw.colsum = dz32; gw.part_cs = w.part_cs;
+    int splits = B / kMlpSplitRows;
+    splits = splits < 1 ? 1 : (splits > kMlpSplits ? kMlpSplits : splits);
+    int parts = 1;
+    if ((e = gemm<kPlain>(gw, st, splits, &parts)) != hipSuccess) return e;
+    splitk_reduce_kernel<<<(kin * nout + nout + 255) / 256, 256, 0, st>>>(w.part, parts, kin * nout, grad + ow[l],
+                                                                          w.part_cs, nout, grad + ob[l]);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (l == 0) break;
     // dz_{l-1} = (dz W_l^T) * gelu'(z_{l-1})  ([B][kin])

@@ -76,7 +76,7 @@ multi_kernel(const mpmi_loop_desc* __restrict__ loops, const ModelDev* __restric
                                                                        L->first_violation, nullptr, 0);
   Slot* slot = &slots[w.loop];
   if constexpr (RECHECK) {
-    wave_append(&rl->count, rl->e, r.near, make_uint4(w.loop, (unsigned int)c, w.model, 0u));
+    wave_append(&rl->count, rl->e, r.near, make_uint4(w.loop, (unsigned int)c, w.model, r.safe32 ? 1u : 0u));
     publish_partial(r.ks, r.kf, (unsigned int)__popcll(__ballot(r.safe_counted)),
                     (unsigned int)__popcll(__ballot(r.near)), slot, w.tile);
     return;

@@ -5,12 +5,17 @@
 // whenever the user's own input is unsafe, so the candidate the selection
 // picks is often one whose predicted margin is within FP32 rounding of zero.
 // The FP32 tick therefore lists every candidate with such a margin at some
-// checked step instead of publishing it; this launch predicts each listed
-// candidate again from x_t with K, the basis, the process noise and the
-// margins in FP64 (Sec. IV-A's prediction and Sec. IV-B's checks), writes its
-// first violation, publishes its keys, and the last workgroup finalises the
-// selection.  Every verdict of the tick is then that of an FP64 rollout
-// whenever the bands cover the FP32 margin error.
+// checked step (with its FP32 verdict) instead of publishing it.  Outside the
+// band the FP32 verdicts are exact, so the least key K* the tick published is
+// the FP64 selection's unless a listed candidate of smaller key is safe in
+// FP64.  This launch predicts again, from x_t with K, the basis, the process
+// noise and the margins in FP64 (Sec. IV-A's prediction and Sec. IV-B's
+// checks), every listed candidate whose key precedes K* -- every listed one
+// when nothing outside the band is safe, so that the fallback order is exact
+// too -- writes its first violation and publishes its keys; a listed candidate
+// behind K* cannot change the selection and keeps its FP32 verdict (counted in
+// the safe count).  The last workgroup finalises the selection, which is then
+// that of an FP64 rollout whenever the bands cover the FP32 margin error.
 //
 // One candidate per lane, 64-lane workgroups: a tick lists at most a few
 // percent of its candidates, so the launch is latency-bound and small
@@ -230,18 +235,26 @@ __device__ int evaluate64(const ModelDev* __restrict__ md, const double* __restr
   return H + 1;
 }
 
-// Keys of a re-rolled candidate (cost in FP32 from its first-segment input,
-// as in the FP32 tick).
-__device__ __forceinline__ void keys_of(const ModelDev* __restrict__ md, const GenParams& gp,
-                                        const float* __restrict__ cand, const float* __restrict__ u_user, int c,
-                                        int fv, int H, unsigned long long* ks, unsigned long long* kf, bool* safe) {
+// Cost of candidate c (FP32, from its first-segment input, as in the FP32 tick).
+__device__ __forceinline__ float cost_at(const ModelDev* __restrict__ md, const GenParams& gp,
+                                         const float* __restrict__ cand, const float* __restrict__ u_user, int c) {
   float u0[MPMI_MAX_INPUT];
 #pragma unroll
   for (int j = 0; j < MPMI_MAX_INPUT; ++j) u0[j] = (j < md->m) ? cand_value(gp, md, cand, u_user, c, 0, j) : 0.0f;
-  const float cst = cost_of<MPMI_MAX_INPUT>(md, u0, u_user);
-  *safe = fv == H + 1;
-  *ks = *safe ? safe_key(cst, c) : kKeyNone;
-  *kf = *safe ? kKeyNone : fallback_key(fv, cst, c);
+  return cost_of<MPMI_MAX_INPUT>(md, u0, u_user);
+}
+
+// K*: the least safe key the FP32 tick published into a slot (key_safe; the
+// re-roll's own keys go to key_safe64, so K* stays fixed while it runs), or
+// kKeyNone.
+__device__ __forceinline__ unsigned long long published_best(const Slot* __restrict__ slot) {
+  unsigned long long k = kKeyNone;
+#pragma unroll
+  for (int i = 0; i < kSubSlots; ++i) {
+    const unsigned long long v = __atomic_load_n(&slot->sub[i].key_safe, __ATOMIC_RELAXED);
+    k = v < k ? v : k;
+  }
+  return k;
 }
 
 // ---------------------------------------------------------------------------
@@ -261,28 +274,36 @@ recheck64_kernel(const ModelDev* __restrict__ md, GenParams gp, int H, const flo
   unsigned long long ks = kKeyNone, kf = kKeyNone;
   unsigned int n_safe = 0;
   if ((int)blockIdx.x * kR64Block < count) {  // uniform across the workgroup
+    const unsigned long long kstar = published_best(slot);
     const double* Kg = &md->m64.K[0][0];
     for (int e = lane; e < MPMI_MAX_DIM * 8; e += kR64Block) sK[e] = Kg[e];
     __syncthreads();
     for (int e0 = blockIdx.x * kR64Block; e0 < count; e0 += gridDim.x * kR64Block) {
       const int e = e0 + lane;
       if (e < count) {
-        const int c = rl->idx[e];
-        const int fv = evaluate64<RC>(md, sK, gp, H, x_t, u_user, cand, c, sAt + lane);
-        if (fv_out) fv_out[c] = (int16_t)fv;
-        unsigned long long a, b;
-        bool safe;
-        keys_of(md, gp, cand, u_user, c, fv, H, &a, &b, &safe);
-        ks = a < ks ? a : ks;
-        kf = b < kf ? b : kf;
-        n_safe += (safe && c > 0) ? 1u : 0u;
+        const int entry = rl->idx[e];
+        const int c = entry >> 1;
+        const float cst = cost_at(md, gp, cand, u_user, c);
+        if (kstar != kKeyNone && safe_key(cst, c) > kstar) {
+          // behind K*: cannot change the selection; the FP32 verdict stands
+          n_safe += ((entry & 1) && c > 0) ? 1u : 0u;
+        } else {
+          const int fv = evaluate64<RC>(md, sK, gp, H, x_t, u_user, cand, c, sAt + lane);
+          if (fv_out) fv_out[c] = (int16_t)fv;
+          const bool safe = fv == H + 1;
+          const unsigned long long a = safe ? safe_key(cst, c) : kKeyNone;
+          const unsigned long long b = safe ? kKeyNone : fallback_key(fv, cst, c);
+          ks = a < ks ? a : ks;
+          kf = b < kf ? b : kf;
+          n_safe += (safe && c > 0) ? 1u : 0u;
+        }
       }
     }
   }
   unsigned int wsum = n_safe;
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) wsum += __shfl_xor(wsum, off, 64);
-  if (publish_wave_counted(ks, kf, wsum, slot, gridDim.x, blockIdx.x) && threadIdx.x == 0) {
+  if (publish_wave_counted<true>(ks, kf, wsum, slot, gridDim.x, blockIdx.x) && threadIdx.x == 0) {
     finalize<MPMI_MAX_INPUT>(md, gp, cand, u_user, H, slot, out);
     rl->count = 0u;
     __threadfence();
@@ -345,17 +366,24 @@ multi_recheck64_kernel(const mpmi_loop_desc* __restrict__ loops, const ModelDev*
       const ModelDev* md = models + en.z;
       const GenParams gp = loop_gen(L, ticks[loop], loop);
       const int H = L->horizon;
-      const int fv = md->sys.basis == MPMI_BASIS_RACE_CAR
-                         ? evaluate64<true>(md, &md->m64.K[0][0], gp, H, L->x_t, L->u_user, L->cand, c, sAt + lane)
-                         : evaluate64<false>(md, &md->m64.K[0][0], gp, H, L->x_t, L->u_user, L->cand, c, sAt + lane);
-      if (L->first_violation) L->first_violation[c] = (int16_t)fv;
-      unsigned long long a, b;
-      bool safe;
-      keys_of(md, gp, L->cand, L->u_user, c, fv, H, &a, &b, &safe);
+      // The loop's K* is complete: the many-loop launch before this one
+      // published every tile of every loop.
+      const unsigned long long kstar = published_best(&slots[loop]);
+      const float cst = cost_at(md, gp, L->cand, L->u_user, c);
       SubSlot* ss = &slots[loop].sub[c % kSubSlots];
-      if (a != kKeyNone) atomicMin(&ss->key_safe, a);
-      if (b != kKeyNone) atomicMin(&ss->key_fb, b);
-      if (safe && c > 0) atomicAdd(&ss->count, 1ull);
+      if (kstar != kKeyNone && safe_key(cst, c) > kstar) {
+        if (en.w && c > 0) atomicAdd(&ss->count, 1ull);  // FP32 verdict stands
+      } else {
+        const int fv = md->sys.basis == MPMI_BASIS_RACE_CAR
+                           ? evaluate64<true>(md, &md->m64.K[0][0], gp, H, L->x_t, L->u_user, L->cand, c, sAt + lane)
+                           : evaluate64<false>(md, &md->m64.K[0][0], gp, H, L->x_t, L->u_user, L->cand, c,
+                                               sAt + lane);
+        if (L->first_violation) L->first_violation[c] = (int16_t)fv;
+        const bool safe = fv == H + 1;
+        if (safe) atomicMin(&ss->key_safe64, safe_key(cst, c));
+        else atomicMin(&ss->key_fb, fallback_key(fv, cst, c));
+        if (safe && c > 0) atomicAdd(&ss->count, 1ull);
+      }
     }
   }
   __syncthreads();

@@ -24,9 +24,9 @@ namespace mpmi {
 // Fused tick, FP32
 // ---------------------------------------------------------------------------
 // RECHECK (precision FP32_RECHECK64): candidates with a checked margin within
-// the FP32 band are appended to the recheck list instead of publishing, and
-// the workgroup publishes without a ticket; the FP64 re-roll launch that
-// follows completes the slot.
+// the FP32 band are appended to the recheck list (with their FP32 verdict)
+// instead of publishing, and the workgroup publishes without a ticket; the
+// FP64 re-roll launch that follows completes the slot.
 template <int BASIS, bool NOISE, int DEG, bool RECHECK>
 __global__ void __launch_bounds__(1024)
 tick_fp32_kernel(const ModelDev* __restrict__ md, GenParams gp, int H, const float* __restrict__ x_t,
@@ -44,7 +44,7 @@ tick_fp32_kernel(const ModelDev* __restrict__ md, GenParams gp, int H, const flo
   const CandResult r = evaluate_candidate<BASIS, NOISE, DEG, RECHECK>(md, sK, gp, H, x_t, u_user, cand, c, fv_out,
                                                                       traj, (size_t)traj_ld);
   if constexpr (RECHECK) {
-    wave_append(&rl->count, rl->idx, r.near, c);
+    wave_append(&rl->count, rl->idx, r.near, (c << 1) | (r.safe32 ? 1 : 0));
     publish_partial(r.ks, r.kf, (unsigned int)__popcll(__ballot(r.safe_counted)),
                     (unsigned int)__popcll(__ballot(r.near)), slot, blockIdx.x);
   } else {
@@ -96,15 +96,21 @@ rollout_fp32_kernel(const ModelDev* __restrict__ md, int Nc, int S, int H, const
 // are read and ignored.
 constexpr int kMaskChunk = 4;
 
-template <int NS>
+// NEAR: also the near-boundary bitmask (bit c % 32 of word c / 32 set when
+// some checked state of candidate c has a margin within its FP32 band), one
+// ballot per wave.  Blocks are whole waves; lanes past Nc take part in the
+// ballot only.
+template <int NS, bool NEAR>
 __global__ void __launch_bounds__(1024)
 mask_kernel(const ModelDev* __restrict__ md, int Nc, int H, const float* __restrict__ traj, long long traj_ld,
-            int16_t* __restrict__ fv_out, float* __restrict__ mm_out) {
+            int16_t* __restrict__ fv_out, float* __restrict__ mm_out, uint32_t* __restrict__ near_bits) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= Nc) return;
+  const bool valid = c < Nc;
+  const int cc = valid ? c : Nc - 1;  // lanes past the end scan a valid candidate and store nothing
   const int n = md->n;
   int fv = H + 1;
   float least = INFINITY;
+  bool near = false;
   for (int s0 = 1; s0 <= H && fv > H; s0 += kMaskChunk) {
     float x[kMaskChunk][NS];
     // Every load is issued: a step past the horizon rereads the last one
@@ -116,14 +122,14 @@ mask_kernel(const ModelDev* __restrict__ md, int Nc, int H, const float* __restr
 #pragma unroll
       for (int j = 0; j < NS; ++j) {
         const int jj = j < n ? j : n - 1;
-        const float v = traj[((size_t)(s - 1) * n + jj) * (size_t)traj_ld + c];
+        const float v = traj[((size_t)(s - 1) * n + jj) * (size_t)traj_ld + cc];
         x[k][j] = j < n ? v : 0.0f;
       }
     }
 #pragma unroll
     for (int k = 0; k < kMaskChunk; ++k) {
       if (s0 + k > H) break;
-      const float mg = min_margin<NS>(md, x[k]);
+      const float mg = NEAR ? min_margin_near<NS>(md, x[k], &near) : min_margin<NS>(md, x[k]);
       least = (mg != mg) ? mg : fminf(least, mg);
       if (!(mg > 0.0f)) {
         fv = s0 + k;
@@ -131,8 +137,17 @@ mask_kernel(const ModelDev* __restrict__ md, int Nc, int H, const float* __restr
       }
     }
   }
-  fv_out[c] = (int16_t)fv;
-  if (mm_out) mm_out[c] = least;
+  if (valid) {
+    fv_out[c] = (int16_t)fv;
+    if (mm_out) mm_out[c] = least;
+  }
+  if (NEAR) {
+    const unsigned long long b = __ballot(valid && near);
+    const int lane = threadIdx.x & 63;
+    const int c0 = c - lane;
+    if (lane == 0 && c0 < Nc) near_bits[c0 >> 5] = (uint32_t)b;
+    if (lane == 32 && c0 + 32 < Nc) near_bits[(c0 >> 5) + 1] = (uint32_t)(b >> 32);
+  }
 }
 
 // Selection over given first violations (Alg. 2's arg-min).  A pass of a
@@ -472,21 +487,28 @@ hipError_t launch_rollout(int basis, const void* model, int Nc, int S, int H, co
   return hipGetLastError();
 }
 
+template <int NS>
+static void mask_dispatch(unsigned grid, int block, hipStream_t st, const ModelDev* md, int Nc, int H,
+                          const float* traj, long long traj_ld, int16_t* fv, float* mm, uint32_t* nb) {
+  if (nb) mask_kernel<NS, true><<<grid, block, 0, st>>>(md, Nc, H, traj, traj_ld, fv, mm, nb);
+  else mask_kernel<NS, false><<<grid, block, 0, st>>>(md, Nc, H, traj, traj_ld, fv, mm, nb);
+}
+
 hipError_t launch_mask(int basis, const void* model, int Nc, int H, const float* traj, long long traj_ld,
-                       int16_t* fv, float* mm, hipStream_t st) {
+                       int16_t* fv, float* mm, uint32_t* near_bits, hipStream_t st) {
   const int block = 256;
   const unsigned grid = blocks_for(Nc, block);
   const ModelDev* md = (const ModelDev*)model;
   switch (basis) {
     case MPMI_BASIS_LINEAR:
     case MPMI_BASIS_CUSTOM:
-      mask_kernel<MPMI_MAX_STATE><<<grid, block, 0, st>>>(md, Nc, H, traj, traj_ld, fv, mm);
+      mask_dispatch<MPMI_MAX_STATE>(grid, block, st, md, Nc, H, traj, traj_ld, fv, mm, near_bits);
       break;
     case MPMI_BASIS_BALANCE_BOT:
-      mask_kernel<4><<<grid, block, 0, st>>>(md, Nc, H, traj, traj_ld, fv, mm);
+      mask_dispatch<4>(grid, block, st, md, Nc, H, traj, traj_ld, fv, mm, near_bits);
       break;
     default:
-      mask_kernel<6><<<grid, block, 0, st>>>(md, Nc, H, traj, traj_ld, fv, mm);
+      mask_dispatch<6>(grid, block, st, md, Nc, H, traj, traj_ld, fv, mm, near_bits);
       break;
   }
   return hipGetLastError();
@@ -521,7 +543,7 @@ size_t slot_bytes() { return sizeof(Slot); }
 void slot_reset_image(unsigned char* dst, int n) {
   Slot r;
   std::memset(&r, 0, sizeof(r));
-  for (int i = 0; i < kSubSlots; ++i) r.sub[i].key_safe = r.sub[i].key_fb = kKeyNone;
+  for (int i = 0; i < kSubSlots; ++i) r.sub[i].key_safe = r.sub[i].key_fb = r.sub[i].key_safe64 = kKeyNone;
   for (int l = 0; l < n; ++l) std::memcpy(dst + (size_t)l * sizeof(Slot), &r, sizeof(Slot));
 }
 

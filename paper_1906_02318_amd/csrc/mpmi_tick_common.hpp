@@ -7,8 +7,9 @@
 
 namespace mpmi {
 
-// Candidates of one tick left to a re-roll launch (BF16X3: FP32 re-roll;
-// FP32_RECHECK64: FP64 re-roll), in context-owned device memory.
+// Candidates of one tick left to a re-roll launch, in context-owned device
+// memory: BF16X3 lists candidate indices (FP32 re-roll); FP32_RECHECK64
+// lists (candidate << 1) | FP32 verdict (1 = safe) (FP64 re-roll).
 struct RecheckList {
   unsigned int count;
   unsigned int pad[63];
@@ -16,8 +17,8 @@ struct RecheckList {
 };
 
 // Candidates of a many-loop tick left to the FP64 re-roll: {loop, candidate,
-// model index, 0}; the last workgroup of the re-roll launch (ticket `done`)
-// finalises every loop.
+// model index, FP32 verdict (1 = safe)}; the last workgroup of the re-roll
+// launch (ticket `done`) finalises every loop.
 struct MultiRecheck {
   unsigned int count;
   unsigned int done;
@@ -59,6 +60,7 @@ __device__ __forceinline__ float cost_of(const ModelDev* __restrict__ md, const 
 // small); more parts take one on their sub-slot first, and the last of each
 // sub-slot one on the slot.
 constexpr unsigned int kOneLevelParts = 128;
+template <bool SAFE64 = false>  // the FP64 re-roll's safe keys go to key_safe64
 __device__ __forceinline__ bool publish_wave_counted(unsigned long long ks, unsigned long long kf,
                                                      unsigned int cnt, Slot* __restrict__ slot,
                                                      unsigned int n_parts, unsigned int part) {
@@ -85,7 +87,7 @@ __device__ __forceinline__ bool publish_wave_counted(unsigned long long ks, unsi
     }
     const unsigned int sidx = part % kSubSlots;
     SubSlot* ss = &slot->sub[sidx];
-    if (bks != kKeyNone) atomicMin(&ss->key_safe, bks);
+    if (bks != kKeyNone) atomicMin(SAFE64 ? &ss->key_safe64 : &ss->key_safe, bks);
     if (bkf != kKeyNone) atomicMin(&ss->key_fb, bkf);
     bool last = false;
     if (n_parts <= kOneLevelParts) {
@@ -133,7 +135,9 @@ __device__ void finalize(const ModelDev* __restrict__ md, const GenParams& gp,
 #pragma unroll
   for (int i = 0; i < kSubSlots; ++i) {
     SubSlot* ss = &slot->sub[i];
-    const unsigned long long a = atomicExch(&ss->key_safe, kKeyNone);
+    const unsigned long long a0 = atomicExch(&ss->key_safe, kKeyNone);
+    const unsigned long long a1 = atomicExch(&ss->key_safe64, kKeyNone);
+    const unsigned long long a = a0 < a1 ? a0 : a1;
     const unsigned long long b = atomicExch(&ss->key_fb, kKeyNone);
     const unsigned long long n = atomicExch(&ss->count, 0ull);
     const unsigned int r = atomicExch(&ss->n_recheck, 0u);
@@ -182,7 +186,8 @@ __device__ void finalize(const ModelDev* __restrict__ md, const GenParams& gp,
 struct CandResult {
   unsigned long long ks, kf;
   bool safe_counted;
-  bool near;  // NEAR instances: some checked state lies within the FP32 band of a constraint
+  bool near;    // NEAR instances: some checked state lies within the FP32 band of a constraint
+  bool safe32;  // the FP32 verdict: every state safe (valid candidates)
 };
 
 // Publishes a workgroup's keys and counts (cnt: the wave's safe count, n_re:
@@ -245,8 +250,9 @@ __device__ __forceinline__ void wave_append(unsigned int* __restrict__ count, T*
 //
 // NEAR instances also track whether some checked state (steps 1 .. first
 // violation) has a margin within its constraint's FP32 band: such a
-// candidate is left to the FP64 re-roll, so it gets no keys here and its
-// first violation is not stored.
+// candidate is left to the FP64 re-roll, so it gets no keys here (its FP32
+// first violation is stored; the re-roll overwrites it when it predicts the
+// candidate again).
 template <int BASIS, bool NOISE, int DEG = kMaxHarm, bool NEAR = false>
 __device__ __forceinline__ CandResult evaluate_candidate(const ModelDev* __restrict__ md, const float4* sK,
                                                          const GenParams& gp, int H,
@@ -298,7 +304,7 @@ __device__ __forceinline__ CandResult evaluate_candidate(const ModelDev* __restr
         break;
       }
     }
-    if (fv_out && !(NEAR && near)) fv_out[c] = (int16_t)fv;
+    if (fv_out) fv_out[c] = (int16_t)fv;
   }
   const bool pub = valid && !(NEAR && near);
   const bool safe = pub && fv == H + 1;
@@ -307,6 +313,7 @@ __device__ __forceinline__ CandResult evaluate_candidate(const ModelDev* __restr
   r.kf = (pub && !safe) ? fallback_key(fv, cst, c) : kKeyNone;
   r.safe_counted = safe && c > 0;
   r.near = NEAR && valid && near;
+  r.safe32 = valid && fv == H + 1;
   return r;
 }
 

@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmpmi.so")
 
 # Constants mirrored from include/mpmi.h
-ABI_VERSION = 6
+ABI_VERSION = 7
 MAX_STATE, MAX_INPUT, MAX_DIM, MAX_BOX = 8, 4, 64, 4
 MAX_HORIZON, MAX_SEGMENTS, MAX_CAND, MAX_LOOPS = 255, 8, 33554431, 4096
 OK, NO_SAFE, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED, ESINGULAR = 0, 1, -1, -2, -3, -4, -5
@@ -118,7 +118,8 @@ def library() -> ctypes.CDLL:
         "mpmi_model_pack": (i32, [vp, ctypes.POINTER(System), vp, vp, vp]),
         "koopman_fit": (i32, [vp, ctypes.POINTER(System), vp, vp, vp, i64, f64, vp, ctypes.POINTER(f64), vp]),
         "rollout_batch": (i32, [vp, vp, i32, vp, vp, i32, i32, i32, vp, i64, vp]),
-        "safe_mask": (i32, [vp, vp, vp, i64, i32, i32, vp, vp, vp]),
+        "safe_mask": (i32, [vp, vp, vp, i64, i32, i32, vp, vp, vp, vp]),
+        "mpmi_tick_graph": (i32, [vp, vp, ctypes.POINTER(TickDesc), vp, vp, vp, vp, vp, ctypes.POINTER(vp)]),
         "select_min_intervention": (i32, [vp, vp, vp, i32, i32, vp, i32, vp, i32, vp, vp]),
         "mpmi_tick": (i32, [vp, vp, ctypes.POINTER(TickDesc), vp, vp, vp, vp, vp, vp, i64, vp]),
         "mpmi_generate_candidates": (i32, [vp, vp, ctypes.POINTER(TickDesc), vp, vp, vp, vp]),
@@ -523,16 +524,18 @@ def rollout_batch(ctx: Context, model: Model, x0, cand, H: int, traj=None, preci
     return traj
 
 
-def safe_mask(ctx: Context, model: Model, traj, with_margin: bool = True, stream=None):
+def safe_mask(ctx: Context, model: Model, traj, with_margin: bool = True, stream=None, with_near: bool = False):
     """traj (H, n, Nc), rows possibly padded -> (first_violation int16 (Nc,),
-    min_margin float32 (Nc,) or None)."""
+    min_margin float32 (Nc,) or None), and with_near: also the near-boundary
+    bitmask int32 (ceil(Nc / 32),)."""
     H, n, Nc = traj.shape
     ld = _traj_stride(traj, "traj", H, n, Nc, ctx.device)
     fv = torch.empty(Nc, dtype=torch.int16, device=ctx.device)
     mm = torch.empty(Nc, dtype=torch.float32, device=ctx.device) if with_margin else None
-    ctx.check(ctx.lib.safe_mask(ctx.handle, ctypes.c_void_p(model.ptr), _ptr(traj), ld, Nc, H, _ptr(fv), _ptr(mm),
-                                _stream(stream)))
-    return fv, mm
+    nb = torch.empty((Nc + 31) // 32, dtype=torch.int32, device=ctx.device) if with_near else None
+    ctx.check(ctx.lib.safe_mask(ctx.handle, ctypes.c_void_p(model.ptr), _ptr(traj), ld, Nc, H, _ptr(fv), _ptr(nb),
+                                _ptr(mm), _stream(stream)))
+    return (fv, mm, nb) if with_near else (fv, mm)
 
 
 def select_min_intervention(ctx: Context, model: Model, cand, first_violation, H: int, u_user, loop: int = 0,
@@ -602,6 +605,43 @@ def mpmi_tick_noalloc(model: Model, desc: TickDesc, x_t, u_user, out, cand=None,
     if st != OK:
         raise MpmiError(st, lib.mpmi_last_error(None).decode())
     return out
+
+
+class TickGraph:
+    """One mpmi_tick captured as a HIP graph (mpmi_tick_graph); replays read
+    the captured x_t / u_user / cand tensors and write out / first_violation."""
+
+    def __init__(self, ctx: Context, model: Model, desc: TickDesc, x_t, u_user, cand=None, out=None,
+                 first_violation=None):
+        _need(x_t, "x_t", torch.float32, model.n, device=ctx.device)
+        _need(u_user, "u_user", torch.float32, model.m, device=ctx.device)
+        if cand is not None:
+            _need(cand, "cand", torch.float32, desc.n_seg * model.m * desc.n_cand, device=ctx.device)
+        if first_violation is not None:
+            _need(first_violation, "first_violation", torch.int16, desc.n_cand + 1, device=ctx.device)
+        self.out = torch.zeros(SELECTION_BYTES, dtype=torch.uint8, device=ctx.device) if out is None else out
+        _need(self.out, "out", torch.uint8, SELECTION_BYTES, device=ctx.device)
+        self.ctx, self._keep = ctx, (model, x_t, u_user, cand, first_violation)
+        g = ctypes.c_void_p()
+        ctx.check(ctx.lib.mpmi_tick_graph(ctx.handle, ctypes.c_void_p(model.ptr), ctypes.byref(desc), _ptr(x_t),
+                                          _ptr(u_user), _ptr(cand), _ptr(self.out), _ptr(first_violation),
+                                          ctypes.byref(g)))
+        self.graph = g
+
+    def launch(self, stream=None):
+        self.ctx.check(self.ctx.lib.mpmi_graph_launch(self.ctx.handle, self.graph, _stream(stream)))
+        return self.out
+
+    def close(self):
+        if getattr(self, "graph", None) is not None:
+            self.ctx.lib.mpmi_graph_destroy(self.graph)
+            self.graph = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def mpmi_tick_autotune(ctx: Context, model: Model, desc: TickDesc, x_t, u_user, cand=None, reps: int = 20,

@@ -19,9 +19,13 @@
   ("eps_band") can only come from ambiguous verdicts, by the two rules above,
   and counts as a disagreement.
 
-FP32_RECHECK64 ticks (FP32 tick, FP64 re-roll of the candidates in the FP32
-band) are judged with an FP64 band (EPS64, 1e-9): their first violations must
-equal the oracle's wherever its margins are not within FP64 rounding of zero.
+FP32_RECHECK64 ticks (FP32 tick, FP64 re-roll of the band's candidates that
+could precede the best key outside the band -- all of them when nothing
+outside the band is safe): a tick that found nothing safe re-rolled every
+band candidate, so its first violations must equal the oracle's wherever its
+margins are not within FP64 rounding of zero (EPS64, 1e-9); any other tick is
+held to the FP32 band, and its decision must agree (the re-roll makes the
+selection the FP64 one).
 
 Long replays run the oracle in a pool of worker processes (spawn context;
 the workers import only NumPy and the oracle, never the GPU library).
@@ -45,6 +49,11 @@ EPS64 = 1e-9
 def eps64(sys: o.System) -> list:
     """The FP64 band for every constraint of sys."""
     return [EPS64] * (len(sys.box) + (1 if sys.track is not None else 0))
+
+
+def recheck64_eps(sys: o.System, sel: dict, eps32) -> list:
+    """The band an FP32_RECHECK64 record is judged with (see the header)."""
+    return eps64(sys) if sel["status"] != o.STATUS_OK else list(eps32)
 
 
 def rollout_rel_err(x_gpu: np.ndarray, x_64: np.ndarray, floors: np.ndarray, comp_axis: int) -> float:

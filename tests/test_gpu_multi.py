@@ -10,7 +10,7 @@ import synth
 from oracle import mpmi_oracle as o
 from paper_1906_02318_amd import mpmi
 from tests import workloads as W
-from tests.parity import agreed, check_tick, eps64, replay_job, tally
+from tests.parity import agreed, check_tick, recheck64_eps, replay_job, tally
 
 pytestmark = pytest.mark.gpu
 
@@ -170,8 +170,8 @@ def test_serving_workload_decisions_against_oracle(oracle_pool):
     FP32 band (FP32_RECHECK64) -- for 1,001 ticks; at every 500th tick all 64
     loops are replayed by the oracle on their visited (x_t, u_h, candidates):
     every record is the selection rule over its loop's first violations, those
-    equal the oracle's outside the FP64 band, and at least 99.9% of the
-    decisions agree with the oracle's."""
+    equal the oracle's outside the band of recheck64_eps, and at least 99.9%
+    of the decisions agree with the oracle's."""
     ctx = mpmi.Context(0)
     track = W.rc_track()
     Kb, Kr = W.bb_model()[0], W.rc_model()[0]
@@ -202,7 +202,8 @@ def test_serving_workload_decisions_against_oracle(oracle_pool):
                 so, K, nx, nu = systems[k]
                 x, u = W.f32(scen.x[i, :nx]), W.f32(scen.u[i, :nu])
                 jobs.append((so, K, x, u, ("uniform", int(scen.N[i]), 1, scen.seeds[i], t, i), int(scen.H[i]),
-                             eps64(so), None, [(sels[i], fvs[i].cpu().numpy(), f"tick {t} loop {i} ({k})")]))
+                             recheck64_eps(so, sels[i], EPS[k]), None,
+                             [(sels[i], fvs[i].cpu().numpy(), f"tick {t} loop {i} ({k})")]))
             log(f"[serving] tick {t}: records of {n} loops taken")
         scen.advance(rec.view(np.float32).reshape(n, -1)[:, 4:8], t)
     assert multi.ticks() == [1001] * n

@@ -15,8 +15,8 @@ import synth
 from oracle import mpmi_oracle as o
 from paper_1906_02318_amd import mpmi
 from tests import workloads as W
-from tests.parity import agreed, agreement, ambiguous, check_selection, check_tick, eps64, oracle_chunk, replay_job, \
-    rollout_rel_err, tally
+from tests.parity import agreed, agreement, ambiguous, check_selection, check_tick, eps64, oracle_chunk, \
+    recheck64_eps, replay_job, rollout_rel_err, tally
 
 pytestmark = pytest.mark.gpu
 
@@ -479,11 +479,12 @@ def test_closed_loop_balance_bot_decisions_replayed(ctx, bb, oracle_pool):
         u = W.f32(user.next())
         xt = W.f32(x)
         results = []
-        for prec, name, eps in ((mpmi.PREC_FP32_RECHECK64, "fp32+fp64", eps64(so)), (mpmi.PREC_FP32, "fp32", EPS_BB)):
+        for prec, name in ((mpmi.PREC_FP32_RECHECK64, "fp32+fp64"), (mpmi.PREC_FP32, "fp32")):
             desc = mpmi.tick_desc(10240, 50, gen=mpmi.GEN_UNIFORM, n_seg=5, seed=4, tick=t, precision=prec)
             fv = torch.empty(10241, dtype=torch.int16, device="cuda")
             sel = mpmi.decode_selection(mpmi.mpmi_tick(ctx, model, desc, dev(xt, torch.float32),
                                                        dev(u, torch.float32), first_violation=fv))
+            eps = recheck64_eps(so, sel, EPS_BB) if prec == mpmi.PREC_FP32_RECHECK64 else EPS_BB
             results.append((sel, fv.cpu().numpy(), f"closed loop tick {t} ({name})", eps))
         rechecked.append(results[0][0]["n_recheck"])
         jobs.append((so, K, xt, u, ("uniform", 10240, 5, 4, t, 0), 50, EPS_BB, None, results))
@@ -584,7 +585,8 @@ def test_full_size_race_car_sampled_parity_and_properties(ctx, rc, oracle_pool):
             check_selection(so, full, H, u, sel64, fvg64, label="1M tick 0 (FP32+FP64)")
             log("[full size] tick 0: oracle rollout of every candidate")
             step = 65536
-            jobs = [(so, K, x, full[a:a + step], H, [(fvg[a:a + step], EPS_RC), (fvg64[a:a + step], eps64(so))])
+            e64 = recheck64_eps(so, sel64, EPS_RC)
+            jobs = [(so, K, x, full[a:a + step], H, [(fvg[a:a + step], EPS_RC), (fvg64[a:a + step], e64)])
                     for a in range(0, N + 1, step)]
             parts = list(oracle_pool.map(oracle_chunk, jobs))
             fv_o = np.concatenate([p[0] for p in parts])
@@ -598,7 +600,7 @@ def test_full_size_race_car_sampled_parity_and_properties(ctx, rc, oracle_pool):
             ag64 = agreement(so, full, H, u, fv_o, amb64, sel64)
             log(f"[full size] tick 0 against the full oracle: FP32 {ag['kind']} (FP32 band holds "
                 f"{int(amb32.sum())} candidates, oracle idx {ag['idx']}, gpu idx {ag['gpu_idx']}); FP32+FP64 "
-                f"{ag64['kind']} (re-rolled {sel64['n_recheck']}, FP64 band {int(amb64.sum())}, idx {sel64['idx']})")
+                f"{ag64['kind']} (band candidates listed {sel64['n_recheck']}, idx {sel64['idx']})")
             assert ag64["kind"] in ("identical", "equal_cost")
             assert sel64["n_recheck"] > 0
         # monotone under inflation (same candidates, tighter set)
@@ -895,3 +897,81 @@ def test_bf16x3_tick_size_limit(ctx, rc):
     ok = mpmi.tick_desc((1 << 22) - 1, 2, gen=mpmi.GEN_UNIFORM, precision=mpmi.PREC_BF16X3)
     sel = mpmi.decode_selection(mpmi.mpmi_tick(ctx, model, ok, x, u))
     assert sel["n_cand"] == 1 << 22
+
+
+@pytest.mark.parametrize("system", ["bb", "rc"])
+def test_safe_mask_near_bits(ctx, bb, rc, system):
+    """safe_mask's near-boundary bitmask over full-horizon rollouts: against
+    the oracle (set wherever some oracle margin up to the first violation is
+    inside half the FP32 band, clear wherever every one is outside one and a
+    half bands: the margin error is below half a band, C18-C19), and exactly
+    as many candidates as the FP32_RECHECK64 tick re-rolls on the same
+    candidates (the same FP32 states and margin code)."""
+    so, model, K = bb if system == "bb" else rc
+    sysg = model.system
+    eps = np.array([sysg.eps32_box[b] for b in range(sysg.n_box)] + ([sysg.eps32_track] if sysg.has_track else []))
+    if system == "bb":
+        grid, H = [4096], 50  # 44 candidates inside half a band in FP64 over the 6 ticks
+        xs, us = synth.balance_bot_states(6, seed=7), synth.uniform_user(6, [-5.0], [5.0], seed=8)
+    else:
+        grid, H = [128, 128], 60
+        xs = synth.race_car_states(4, W.rc_track(), seed=7)
+        us = synth.uniform_user(4, synth.RC_U_LO, synth.RC_U_HI, seed=8)
+    N = int(np.prod(grid))
+    total = 0
+    for t in range(len(xs)):
+        x, u = W.f32(xs[t]), W.f32(us[t])
+        desc = mpmi.tick_desc(N, H, gen=mpmi.GEN_GRID, grid=grid, precision=mpmi.PREC_FP32_RECHECK64)
+        cand = mpmi.mpmi_generate_candidates(ctx, model, desc, dev(u, torch.float32))
+        traj = mpmi.rollout_batch(ctx, model, dev(x, torch.float32), cand, H)
+        fv, _, nb = mpmi.safe_mask(ctx, model, traj, with_margin=False, with_near=True)
+        words = nb.cpu().numpy().view(np.uint32)
+        bits = ((words[:, None] >> np.arange(32, dtype=np.uint32)[None, :]) & 1).reshape(-1)[: N + 1].astype(bool)
+        assert not np.any(((words[-1] >> np.uint32((N + 1) % 32)) if (N + 1) % 32 else 0))  # nothing past Nc
+        sel = mpmi.decode_selection(mpmi.mpmi_tick(ctx, model, desc, dev(x, torch.float32), dev(u, torch.float32)))
+        assert int(bits.sum()) == sel["n_recheck"], (t, int(bits.sum()), sel["n_recheck"])
+        c64 = np.transpose(cand.cpu().numpy().astype(np.float64), (2, 0, 1))
+        t64, fv_o = o.rollout(so, K, x, c64, H, early_exit=False)
+        M = o.margins(so, t64.reshape(-1, so.n)).reshape(H, N + 1, -1)
+        upto = np.minimum(np.minimum(fv_o, fv.cpu().numpy().astype(np.int64)), H)
+        keep = (np.arange(1, H + 1)[:, None] <= upto[None, :])[:, :, None]
+        inside = np.any(keep & (np.abs(M) < 0.5 * eps), axis=(0, 2))
+        outside = ~np.any(keep & (np.abs(M) < 1.5 * eps), axis=(0, 2))
+        assert np.all(bits[inside]), f"tick {t}: near candidates not flagged"
+        assert not np.any(bits[outside]), f"tick {t}: far candidates flagged"
+        total += int(bits.sum())
+    log(f"[near bits] {system}: {total} flagged over {len(xs)} ticks, equal to the re-rolled counts")
+    assert total > 0
+
+
+@pytest.mark.parametrize("prec", [mpmi.PREC_FP32, mpmi.PREC_FP32_RECHECK64])
+def test_tick_graph_replays(ctx, rc, prec):
+    """A single-loop tick captured as a HIP graph (mpmi_tick_graph): three
+    replays, each after writing new inputs into the captured tensors and some
+    eager work, give the records and first violations of eager ticks on the
+    same inputs."""
+    so, model, K = rc
+    N, H = 128 * 128, 60
+    desc = mpmi.tick_desc(N, H, gen=mpmi.GEN_GRID, grid=[128, 128], precision=prec)
+    xs = synth.race_car_states(4, W.rc_track(), seed=17)
+    us = synth.uniform_user(4, synth.RC_U_LO, synth.RC_U_HI, seed=18)
+    x_dev, u_dev = dev(W.f32(xs[0]), torch.float32), dev(W.f32(us[0]), torch.float32)
+    fv = torch.zeros(N + 1, dtype=torch.int16, device="cuda")
+    g = mpmi.TickGraph(ctx, model, desc, x_dev, u_dev, first_violation=fv)
+    try:
+        for r in range(1, 4):
+            x_dev.copy_(dev(W.f32(xs[r]), torch.float32))
+            u_dev.copy_(dev(W.f32(us[r]), torch.float32))
+            junk = torch.randn(1 << 20, device="cuda").sum()
+            rec = g.launch().clone()
+            fv_g = fv.clone()
+            torch.cuda.synchronize()
+            del junk
+            fv_e = torch.zeros(N + 1, dtype=torch.int16, device="cuda")
+            ref = mpmi.mpmi_tick(ctx, model, desc, x_dev, u_dev, first_violation=fv_e)
+            torch.cuda.synchronize()
+            assert rec.cpu().numpy().tobytes() == ref.cpu().numpy().tobytes(), f"replay {r}"
+            assert torch.equal(fv_g, fv_e), f"replay {r}"
+        log(f"[tick graph] precision {prec}: 3 replays equal eager ticks")
+    finally:
+        g.close()
