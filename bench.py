@@ -808,6 +808,8 @@ def main():
         out["race_car_16k"] = run_plain_vs_learned()
     if "mlp" in legs:
         out["mlp_training"] = run_mlp_training()
+        # the same step at a batch large enough that the products are not latency-bound
+        out["mlp_training"]["batch_65536"] = run_mlp_training(batch=65536, steps=20)
     if "multi" in legs:
         out["many_loops"] = run_multi(n_ticks=args.multi_ticks)
     if "closed_loop" in legs:

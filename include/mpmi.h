@@ -92,18 +92,20 @@ enum { MPMI_ATOM_ONE = 0, MPMI_ATOM_VAR = 1, MPMI_ATOM_SIN = 2, MPMI_ATOM_COS = 
  *  FP32_RECHECK64  the FP32 tick; every candidate that has a checked state
  *          (steps 1 .. its first violation) whose margin to some constraint
  *          lies within that constraint's FP32 band (eps32_box, eps32_track)
- *          of zero is listed instead of ranked (n_recheck counts them).  A
- *          second launch predicts again from x_t, with K, the features, noise
- *          and margins in FP64 (Sec. IV-A and IV-B in double precision), every
- *          listed candidate whose selection key precedes the least key
- *          ranked outside the band -- every listed one when no candidate
- *          outside the band is safe -- and its FP64 first violation replaces
- *          the FP32 one; the other listed candidates cannot change the
- *          selection and keep their FP32 verdicts.  With bands at least the
+ *          of zero is listed instead of ranked (n_recheck counts them).
+ *          Two more launches on the same stream keep the listed candidates
+ *          whose selection key precedes the least key ranked outside the
+ *          band -- every listed one when no candidate outside the band is
+ *          safe -- and predict each again from x_t, with K, the features,
+ *          noise and margins in FP64 (Sec. IV-A and IV-B in double
+ *          precision); its FP64 first violation replaces the FP32 one.  The
+ *          other listed candidates cannot change the selection and keep
+ *          their FP32 verdicts.  With bands at least the
  *          FP32 rollout's margin error, the selection is that of an FP64
  *          rollout, and so is every first violation outside the band (and
- *          every one, when nothing is safe).  One lane per candidate, ticks of
- *          at most 2^22 candidates (MPMI_EUNSUPPORTED otherwise);
+ *          every one, when nothing is safe).  One lane per candidate in the
+ *          FP32 tick; ticks of at most 2^22 candidates (MPMI_EUNSUPPORTED
+ *          otherwise);
  *          trajectories, when stored, are the FP32 states.
  *  BF16X3  the contraction runs on BF16 matrix cores as three products of
  *          hi/lo BF16 splits of the features and of (K - E) in residual form
@@ -329,7 +331,8 @@ mpmi_status mpmi_tick(mpmi_ctx ctx, const void* model, const mpmi_tick_desc* des
  * under HIP graph capture, tight serving loops, harnesses that forbid
  * hipMalloc): no context, nothing allocated or freed, no synchronisation.
  * The tick's scratch -- the selection slots of loops 0..63 and an FP64
- * re-roll list of 65,536 entries (about 292 KiB in all) -- is a file-scope
+ * re-roll list of 65,536 entries and as many kept entries (about 548 KiB in
+ * all) -- is a file-scope
  * device array of the library, one copy per GPU, held until the process
  * ends; its load-time image is the reset state and every tick leaves it so.
  * sys (host) must be the system `model` was packed from (mpmi_model_pack);

@@ -1058,10 +1058,11 @@ mpmi_status mpmi_gemm_bf16(mpmi_ctx ctx, const uint16_t* A, const uint16_t* B, i
 // ---------------------------------------------------------------------------
 // Allocation-free tick (mpmi_tick_noalloc).  The tick's scratch -- the
 // selection slots of kScratchLoops loops and one FP64 re-roll list of
-// kScratchRecheck entries -- is one file-scope device object, `scratch`,
-// whose load-time image is already the reset state (keys all-ones, counts
-// zero): the tick's last workgroup, and the re-roll launch, leave it in that
-// state again, so no call ever has to clear it.  Every device the library
+// kScratchRecheck entries (and as many kept entries) -- is one file-scope
+// device object, `scratch`, whose load-time image is already the reset state
+// (keys all-ones, counts zero): the workgroup that finalises a tick (of the
+// tick launch, or of the re-roll launch) leaves it in that state again, so no
+// call ever has to clear it.  Every device the library
 // runs on holds its own copy until the process ends; its address on a device
 // is taken once, with that device current, by hipGetSymbolAddress, and only
 // that address is passed to kernels.
@@ -1086,8 +1087,10 @@ struct alignas(64) ScratchSlot {
 struct alignas(256) ScratchImage {
   ScratchSlot slots[kScratchLoops];
   unsigned int count = 0u;  // the re-roll list: a RecheckList of kScratchRecheck entries
-  unsigned int pad[63] = {};
+  unsigned int n_keep = 0u;
+  unsigned int pad[62] = {};
   int idx[kScratchRecheck] = {};
+  int keep[kScratchRecheck] = {};
 };
 static_assert(sizeof(ScratchSlot) == sizeof(mpmi::Slot) && sizeof(ScratchSubSlot) == sizeof(mpmi::SubSlot) &&
                   offsetof(ScratchSubSlot, key_fb) == offsetof(mpmi::SubSlot, key_fb) &&
@@ -1097,7 +1100,10 @@ static_assert(sizeof(ScratchSlot) == sizeof(mpmi::Slot) && sizeof(ScratchSubSlot
                   offsetof(ScratchSlot, done) == offsetof(mpmi::Slot, done),
               "scratch slots have the library's slot layout");
 static_assert(offsetof(ScratchImage, count) == (size_t)kScratchLoops * sizeof(mpmi::Slot) &&
-                  offsetof(ScratchImage, idx) - offsetof(ScratchImage, count) == offsetof(mpmi::RecheckList, idx),
+                  offsetof(ScratchImage, n_keep) - offsetof(ScratchImage, count) ==
+                      offsetof(mpmi::RecheckList, n_keep) &&
+                  offsetof(ScratchImage, idx) - offsetof(ScratchImage, count) == offsetof(mpmi::RecheckList, idx) &&
+                  offsetof(ScratchImage, keep) == offsetof(ScratchImage, idx) + sizeof(int) * kScratchRecheck,
               "scratch list has the recheck list's layout");
 
 static __device__ __align__(256) ScratchImage scratch[1];

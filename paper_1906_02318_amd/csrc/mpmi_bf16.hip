@@ -360,7 +360,8 @@ hipError_t launch_rollout_bf16(const void* model, int Nc, int S, int H, const fl
   return hipGetLastError();
 }
 
-size_t recheck_bytes(int capacity) { return sizeof(RecheckList) + sizeof(int) * (size_t)capacity; }
+// Room for both arrays of the list (the FP64 re-roll's kept entries follow the listed ones).
+size_t recheck_bytes(int capacity) { return sizeof(RecheckList) + 2 * sizeof(int) * (size_t)capacity; }
 
 template <int DEG>
 static hipError_t bf16_dispatch(const ModelDev* md, const GenParams& gp, int H, const float* x_t, const float* u_user,

@@ -65,11 +65,11 @@ struct SafetyConsts {
 struct Model64 {
   double K[MPMI_MAX_DIM][8];        // row = feature, col = state component
   double comp_lim[MPMI_MAX_STATE];  // least limit over the boxes on a component; +inf if none
-  double trk_lim, trk_r0;
-  double trk_amp[4], trk_sinp[4], trk_cosp[4];
+  double trk_lim;
+  double trk_p[kMaxHarm + 1];       // r_c = P(cos phi) + sin phi * Q(cos phi), FP64 monomial coefficients
+  double trk_q[kMaxHarm];
   double sigma[MPMI_MAX_STATE];     // process-noise deviations
-  int32_t trk_freq[4];
-  int32_t trk_n, has_track, comp_mask, n_atoms;
+  int32_t has_track, comp_mask, n_atoms, pad;
   int8_t atom_kind[MPMI_MAX_ATOMS];
   int8_t atom_var[MPMI_MAX_ATOMS];
   int8_t feat_a[MPMI_MAX_DIM];

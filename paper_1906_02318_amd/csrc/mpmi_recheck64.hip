@@ -8,21 +8,22 @@
 // checked step (with its FP32 verdict) instead of publishing it.  Outside the
 // band the FP32 verdicts are exact, so the least key K* the tick published is
 // the FP64 selection's unless a listed candidate of smaller key is safe in
-// FP64.  This launch predicts again, from x_t with K, the basis, the process
-// noise and the margins in FP64 (Sec. IV-A's prediction and Sec. IV-B's
-// checks), every listed candidate whose key precedes K* -- every listed one
-// when nothing outside the band is safe, so that the fallback order is exact
-// too -- writes its first violation and publishes its keys; a listed candidate
-// behind K* cannot change the selection and keeps its FP32 verdict (counted in
-// the safe count).  The last workgroup finalises the selection, which is then
-// that of an FP64 rollout whenever the bands cover the FP32 margin error.
+// FP64.  The tick's last workgroup keeps in the list only the listed
+// candidates whose key precedes K* (every listed one when nothing outside the
+// band is safe, so that the fallback order is exact too); the others keep
+// their FP32 verdicts.  This launch predicts each kept candidate again, from
+// x_t with K, the basis, the process noise and the margins in FP64 (Sec.
+// IV-A's prediction and Sec. IV-B's checks), writes its first violation and
+// publishes its keys.  The last workgroup finalises the selection, which is
+// then that of an FP64 rollout whenever the bands cover the FP32 margin error.
 //
-// One candidate per lane, 64-lane workgroups: a tick lists at most a few
-// percent of its candidates, so the launch is latency-bound and small
-// workgroups spread the listed candidates over more compute units.  The
-// race-car basis runs a folded step (input terms folded once per segment, as
-// in the FP32 tick); the other bases are evaluated from their atom/feature
-// description, the atoms going through a per-lane column of LDS.
+// The launch is latency-bound: a tick keeps from none to a few thousand
+// candidates, each a serial H-step FP64 prediction.  The race car spreads one
+// candidate over eight lanes (one output component each, the step's
+// coefficients read from LDS) and holds eight per 64-lane workgroup; the
+// described bases run one candidate per lane, the atoms going through a
+// per-lane column of LDS.  The many-loop form lists (loop, candidate, model)
+// entries and prunes by each loop's K* itself.
 #include <hip/hip_runtime.h>
 
 #include "mpmi_device.hpp"
@@ -44,9 +45,12 @@ __device__ __forceinline__ const double* opaque_coeffs(const double* p) {
 }
 
 // Least margin of x in FP64 (NaN if any margin is NaN): boxes per component,
-// then the track, r_c(phi) = r0 + sum_q amp_q (sin(f_q phi) cos p_q +
-// cos(f_q phi) sin p_q) with sin(k phi), cos(k phi) from (cos phi, sin phi) =
-// (x0, x1) / rho by the multiple-angle recurrences.
+// then the track.  The centreline radius r_c(phi) is the FP32 tick's
+// Chebyshev form in FP64, P(cos phi) + sin phi * Q(cos phi) with the model's
+// FP64 monomial coefficients, (cos phi, sin phi) = (x0, x1) / rho; Horner runs
+// over a fixed DEG >= the model's highest harmonic (zero coefficients above it
+// leave each partial sum unchanged).
+template <int DEG>
 __device__ __forceinline__ double margin64(const Model64* __restrict__ m, const double* x) {
   double mm = INFINITY;
   bool nan = false;
@@ -60,37 +64,37 @@ __device__ __forceinline__ double margin64(const Model64* __restrict__ m, const 
     }
   }
   if (m->has_track) {
-    const double rho = sqrt(x[0] * x[0] + x[1] * x[1]);
-    const double c1 = x[0] / rho, s1 = x[1] / rho;
-    double cs[kMaxHarm + 1], sn[kMaxHarm + 1];
-    cs[0] = 1.0;
-    sn[0] = 0.0;
-    cs[1] = c1;
-    sn[1] = s1;
+    const double rho = sqrt(fma(x[0], x[0], x[1] * x[1]));
+    const double inv = 1.0 / rho;
+    const double c1 = x[0] * inv, s1 = x[1] * inv;
+    double P = m->trk_p[DEG];
 #pragma unroll
-    for (int k = 1; k < kMaxHarm; ++k) {
-      cs[k + 1] = 2.0 * c1 * cs[k] - cs[k - 1];
-      sn[k + 1] = 2.0 * c1 * sn[k] - sn[k - 1];
-    }
-    double rc = m->trk_r0;
+    for (int k = DEG - 1; k >= 0; --k) P = fma(P, c1, m->trk_p[k]);
+    double Q = m->trk_q[DEG - 1];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      if (q < m->trk_n) {
-        const int f = m->trk_freq[q];
-        double cf = 1.0, sf = 0.0;
-#pragma unroll
-        for (int k = 1; k <= kMaxHarm; ++k) {
-          cf = (f == k) ? cs[k] : cf;
-          sf = (f == k) ? sn[k] : sf;
-        }
-        rc += m->trk_amp[q] * (sf * m->trk_cosp[q] + cf * m->trk_sinp[q]);
-      }
-    }
-    const double mg = m->trk_lim - fabs(rho - rc);
+    for (int k = DEG - 2; k >= 0; --k) Q = fma(Q, c1, m->trk_q[k]);
+    const double mg = m->trk_lim - fabs(rho - fma(s1, Q, P));
     nan |= (mg != mg);
     mm = fmin(mm, mg);
   }
   return nan ? NAN : mm;
+}
+
+// Alg. 2's z_i for step s: the FP32 tick's draws (same counter hash), the
+// Box-Muller transform in FP64.
+__device__ __forceinline__ void add_noise64(const Model64* __restrict__ m, uint64_t pre, int s, int n, double* x) {
+#pragma unroll
+  for (int q = 0; q < MPMI_MAX_STATE / 2; ++q) {
+    if (2 * q < n) {
+      const uint64_t h = hash_finish(pre, kNoiseSlot + 4ull * (uint64_t)(s - 1) + (uint64_t)q);
+      const double u1 = ((double)(h >> 40) + 1.0) * 0x1p-24;
+      const double u2 = (double)((h >> 16) & 0xFFFFFFull) * 0x1p-24;
+      const double r = sqrt(-2.0 * log(u1));
+      const double ang = 6.283185307179586 * u2;
+      x[2 * q] = x[2 * q] + m->sigma[2 * q] * (r * cos(ang));
+      if (2 * q + 1 < n) x[2 * q + 1] = x[2 * q + 1] + m->sigma[2 * q + 1] * (r * sin(ang));
+    }
+  }
 }
 
 // A basis given by its description: atoms of w = [x; u] into this lane's LDS
@@ -124,34 +128,43 @@ __device__ __forceinline__ void step64_described(const Model64* __restrict__ m, 
   for (int j = 0; j < MPMI_MAX_STATE; ++j) x[j] = (j < n) ? y[j] : 0.0;
 }
 
-// Race car, w = [x, y, psi, vx, vy, r, delta, a]: the FP32 tick's folded
-// step in FP64 (K row stride 8).
+// Race car, w = [x, y, psi, vx, vy, r, delta, a]: the input terms of output
+// column j folded once per segment (K row stride 8): the constant cu, the
+// coefficients L[k] of x_k, and Ts, Tc of sin psi, cos psi.
+__device__ __forceinline__ void fold_column64(const double* __restrict__ K, int j, double d, double a, double sd,
+                                              double cd, double* cu, double* L, double* Ts, double* Tc) {
+  double c = K[0 * 8 + j];
+  c = fma(d, K[7 * 8 + j], c);
+  c = fma(a, K[8 * 8 + j], c);
+  c = fma(d * d, K[quad_index(6, 6, 8) * 8 + j], c);
+  c = fma(d * a, K[quad_index(6, 7, 8) * 8 + j], c);
+  c = fma(a * a, K[quad_index(7, 7, 8) * 8 + j], c);
+  c = fma(sd, K[47 * 8 + j], c);
+  c = fma(cd, K[48 * 8 + j], c);
+  c = fma(a * sd, K[63 * 8 + j], c);
+  *cu = c;
+#pragma unroll
+  for (int k = 0; k < 6; ++k)
+    L[k] = fma(a, K[quad_index(k, 7, 8) * 8 + j], fma(d, K[quad_index(k, 6, 8) * 8 + j], K[(1 + k) * 8 + j]));
+  L[3] = fma(cd, K[60 * 8 + j], fma(sd, K[57 * 8 + j], L[3]));
+  L[4] = fma(cd, K[61 * 8 + j], fma(sd, K[58 * 8 + j], L[4]));
+  L[5] = fma(cd, K[62 * 8 + j], fma(sd, K[59 * 8 + j], L[5]));
+  *Ts = fma(a, K[52 * 8 + j], K[45 * 8 + j]);
+  *Tc = fma(a, K[56 * 8 + j], K[46 * 8 + j]);
+}
+
+// Race car, one candidate per lane: the FP32 tick's folded step in FP64.
 struct Stepper64RaceCar {
   double cu[6], L[6][6], Ts[6], Tc[6];
   __device__ __forceinline__ void set_input(const double* __restrict__ Kin, const double* u) {
     const double* K = opaque_coeffs(Kin);
-    const double d = u[0], a = u[1];
-    const double sd = sin(d), cd = cos(d);
+    const double sd = sin(u[0]), cd = cos(u[0]);
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
-      double c = K[0 * 8 + j];
-      c = fma(d, K[7 * 8 + j], c);
-      c = fma(a, K[8 * 8 + j], c);
-      c = fma(d * d, K[quad_index(6, 6, 8) * 8 + j], c);
-      c = fma(d * a, K[quad_index(6, 7, 8) * 8 + j], c);
-      c = fma(a * a, K[quad_index(7, 7, 8) * 8 + j], c);
-      c = fma(sd, K[47 * 8 + j], c);
-      c = fma(cd, K[48 * 8 + j], c);
-      c = fma(a * sd, K[63 * 8 + j], c);
-      cu[j] = c;
+      double Lj[6];
+      fold_column64(K, j, u[0], u[1], sd, cd, &cu[j], Lj, &Ts[j], &Tc[j]);
 #pragma unroll
-      for (int k = 0; k < 6; ++k)
-        L[k][j] = fma(a, K[quad_index(k, 7, 8) * 8 + j], fma(d, K[quad_index(k, 6, 8) * 8 + j], K[(1 + k) * 8 + j]));
-      L[3][j] = fma(cd, K[60 * 8 + j], fma(sd, K[57 * 8 + j], L[3][j]));
-      L[4][j] = fma(cd, K[61 * 8 + j], fma(sd, K[58 * 8 + j], L[4][j]));
-      L[5][j] = fma(cd, K[62 * 8 + j], fma(sd, K[59 * 8 + j], L[5][j]));
-      Ts[j] = fma(a, K[52 * 8 + j], K[45 * 8 + j]);
-      Tc[j] = fma(a, K[56 * 8 + j], K[46 * 8 + j]);
+      for (int k = 0; k < 6; ++k) L[k][j] = Lj[k];
     }
   }
   __device__ __forceinline__ void step(const double* __restrict__ Kin, double* x) {
@@ -186,9 +199,9 @@ struct Stepper64RaceCar {
 };
 
 // First violation (1..H, or H + 1) of candidate c (c < Nc) predicted in FP64
-// from x_t.  K: the model's FP64 K (LDS copy or the blob's); at: this lane's
-// LDS column for the described bases.
-template <bool RC>
+// from x_t, one lane.  K: the model's FP64 K (LDS copy or the blob's); at:
+// this lane's LDS column for the described bases.
+template <bool RC, int DEG>
 __device__ int evaluate64(const ModelDev* __restrict__ md, const double* __restrict__ K, const GenParams& gp, int H,
                           const float* __restrict__ x_t, const float* __restrict__ u_user,
                           const float* __restrict__ cand, int c, double* at) {
@@ -215,99 +228,242 @@ __device__ int evaluate64(const ModelDev* __restrict__ md, const double* __restr
     }
     if constexpr (RC) stp.step(K, x);
     else step64_described(m, K, n, D, u, x, at);
-    if (noisy) {
-      // Alg. 2's z_i: the draws of the FP32 tick, Box-Muller in FP64.
-#pragma unroll
-      for (int q = 0; q < MPMI_MAX_STATE / 2; ++q) {
-        if (2 * q < n) {
-          const uint64_t h = hash_finish(pre, kNoiseSlot + 4ull * (uint64_t)(s - 1) + (uint64_t)q);
-          const double u1 = ((double)(h >> 40) + 1.0) * 0x1p-24;
-          const double u2 = (double)((h >> 16) & 0xFFFFFFull) * 0x1p-24;
-          const double r = sqrt(-2.0 * log(u1));
-          const double ang = 6.283185307179586 * u2;
-          x[2 * q] = x[2 * q] + m->sigma[2 * q] * (r * cos(ang));
-          if (2 * q + 1 < n) x[2 * q + 1] = x[2 * q + 1] + m->sigma[2 * q + 1] * (r * sin(ang));
-        }
-      }
-    }
-    if (!(margin64(m, x) > 0.0)) return s;
+    if (noisy) add_noise64(m, pre, s, n, x);
+    if (!(margin64<DEG>(m, x) > 0.0)) return s;
   }
   return H + 1;
 }
 
-// Cost of candidate c (FP32, from its first-segment input, as in the FP32 tick).
-__device__ __forceinline__ float cost_at(const ModelDev* __restrict__ md, const GenParams& gp,
-                                         const float* __restrict__ cand, const float* __restrict__ u_user, int c) {
-  float u0[MPMI_MAX_INPUT];
-#pragma unroll
-  for (int j = 0; j < MPMI_MAX_INPUT; ++j) u0[j] = (j < md->m) ? cand_value(gp, md, cand, u_user, c, 0, j) : 0.0f;
-  return cost_of<MPMI_MAX_INPUT>(md, u0, u_user);
-}
+// Race car, one candidate over the 8 lanes of an aligned lane group: lane j
+// (< 6) holds output column j's coefficients in registers and forms x'_j, the
+// group exchanges the six new components, and every lane then holds the same
+// state (the same bits, so the same verdict and the same exit step).  Lanes 6
+// and 7 repeat column 5.  The features, the noise draws and the margin are
+// formed by every lane.  Returns the first violation (1..H, or H + 1).
+static_assert(kRcStepRows % 3 == 0, "three partial sums over the step rows");
 
-// K*: the least safe key the FP32 tick published into a slot (key_safe; the
-// re-roll's own keys go to key_safe64, so K* stays fixed while it runs), or
-// kKeyNone.
-__device__ __forceinline__ unsigned long long published_best(const Slot* __restrict__ slot) {
-  unsigned long long k = kKeyNone;
+template <int DEG>
+__device__ int evaluate64_rc8(const ModelDev* __restrict__ md, const double* __restrict__ K, const GenParams& gp,
+                              int H, const float* __restrict__ x_t, const float* __restrict__ u_user,
+                              const float* __restrict__ cand, int c) {
+  const Model64* m = &md->m64;
+  const int lane = threadIdx.x & 63;
+  const int j = (lane & 7) < 6 ? (lane & 7) : 5;
+  const int base = lane & ~7;
+  const int S = gp.n_seg;
+  double x[6];
 #pragma unroll
-  for (int i = 0; i < kSubSlots; ++i) {
-    const unsigned long long v = __atomic_load_n(&slot->sub[i].key_safe, __ATOMIC_RELAXED);
-    k = v < k ? v : k;
+  for (int k = 0; k < 6; ++k) x[k] = (double)x_t[k];
+  double cu, L[6], Ts, Tc;
+  {
+    const double d = (double)cand_value(gp, md, cand, u_user, c, 0, 0);
+    const double a = (double)cand_value(gp, md, cand, u_user, c, 0, 1);
+    fold_column64(K, j, d, a, sin(d), cos(d), &cu, L, &Ts, &Tc);
   }
-  return k;
+  const bool noisy = md->has_noise != 0;
+  const uint64_t pre = noisy ? hash_prefix(gp.seed, gp.tick, (uint64_t)(uint32_t)gp.loop, (uint64_t)c) : 0ull;
+  int gcur = 0;
+  for (int s = 1; s <= H; ++s) {
+    const int g = ((s - 1) * S) / H;
+    if (g != gcur) {
+      gcur = g;
+      const double d = (double)cand_value(gp, md, cand, u_user, c, g, 0);
+      const double a = (double)cand_value(gp, md, cand, u_user, c, g, 1);
+      fold_column64(K, j, d, a, sin(d), cos(d), &cu, L, &Ts, &Tc);
+    }
+    double sp, cp;
+    sincos(x[2], &sp, &cp);
+    double p[kRcStepRows];
+    int q = 0;
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+#pragma unroll
+      for (int l = k; l < 6; ++l) p[q++] = x[k] * x[l];
+    p[21] = sp * x[3]; p[22] = sp * x[4]; p[23] = sp * x[5];
+    p[24] = cp * x[3]; p[25] = cp * x[4]; p[26] = cp * x[5];
+    // four independent partial sums (the chain of one column is short of
+    // independent work otherwise)
+    double y0 = fma(Tc, cp, fma(Ts, sp, cu));
+#pragma unroll
+    for (int k = 0; k < 6; ++k) y0 = fma(L[k], x[k], y0);
+    // the step rows of column j, read from LDS at every step (held in
+    // registers they would cost a second wave per SIMD)
+    const double* Kc = opaque_coeffs(K) + j;
+    double y1 = p[0] * Kc[rc_step_row(0) * 8], y2 = p[1] * Kc[rc_step_row(1) * 8], y3 = p[2] * Kc[rc_step_row(2) * 8];
+#pragma unroll
+    for (int r = 3; r < kRcStepRows; r += 3) {
+      y1 = fma(p[r], Kc[rc_step_row(r) * 8], y1);
+      y2 = fma(p[r + 1], Kc[rc_step_row(r + 1) * 8], y2);
+      y3 = fma(p[r + 2], Kc[rc_step_row(r + 2) * 8], y3);
+    }
+    const double y = (y0 + y1) + (y2 + y3);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) x[k] = __shfl(y, base + k, 64);
+    if (noisy) add_noise64(m, pre, s, 6, x);
+    if (!(margin64<DEG>(m, x) > 0.0)) return s;
+  }
+  return H + 1;
 }
 
 // ---------------------------------------------------------------------------
 // Single loop: re-roll the context's list, publish, finalise.
 // ---------------------------------------------------------------------------
-template <bool RC>
+
+// The end of a re-roll workgroup: the wave's keys and safe count published,
+// and the last workgroup finalises the selection and empties the list.
+__device__ __forceinline__ void recheck_publish(const ModelDev* __restrict__ md, const GenParams& gp, int H,
+                                                const float* __restrict__ u_user, const float* __restrict__ cand,
+                                                Slot* __restrict__ slot, mpmi_selection* __restrict__ out,
+                                                RecheckList* __restrict__ rl, unsigned long long ks,
+                                                unsigned long long kf, unsigned int n_safe, unsigned int n_parts) {
+  unsigned int wsum = n_safe;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) wsum += __shfl_xor(wsum, off, 64);
+  if (publish_wave_counted<true>(ks, kf, wsum, slot, n_parts, blockIdx.x) && threadIdx.x == 0) {
+    finalize<MPMI_MAX_INPUT>(md, gp, cand, u_user, H, slot, out);
+    rl->count = 0u;
+    rl->n_keep = 0u;
+    __threadfence();
+  }
+}
+
+// Filter: K* is final once the FP32 tick has completed (every candidate
+// outside the band published), so a listed candidate can change the selection
+// only if its key precedes K* (every listed one when nothing outside the band
+// is safe).  Those are copied to the kept array; the others keep their FP32
+// verdicts and their safe ones are added to the safe count.  One entry per
+// lane; workgroups past the list's end return at once.
+constexpr int kFilterBlock = 256;
+__global__ void __launch_bounds__(kFilterBlock)
+recheck64_filter_kernel(const ModelDev* __restrict__ md, GenParams gp, const float* __restrict__ u_user,
+                        const float* __restrict__ cand, Slot* __restrict__ slot, RecheckList* __restrict__ rl,
+                        int capacity) {
+  __shared__ unsigned int s_w[kFilterBlock / 64];
+  const unsigned int cnt_raw = rl->count;
+  const int count = (int)(cnt_raw < (unsigned int)capacity ? cnt_raw : (unsigned int)capacity);
+  if ((int)blockIdx.x * kFilterBlock >= count) return;  // uniform
+  const unsigned long long kstar = published_best(slot);
+  int* keep = rl->idx + capacity;
+  const int t = threadIdx.x;
+  unsigned int kept_safe = 0;
+  for (int e0 = blockIdx.x * kFilterBlock; e0 < count; e0 += gridDim.x * kFilterBlock) {  // uniform
+    const int e = e0 + t;
+    bool want = false;
+    int entry = 0;
+    if (e < count) {
+      entry = rl->idx[e];
+      const int c = entry >> 1;
+      if (kstar != kKeyNone && safe_key(cost_at(md, gp, cand, u_user, c), c) > kstar)
+        kept_safe += ((entry & 1) && c > 0) ? 1u : 0u;
+      else
+        want = true;
+    }
+    wave_append(&rl->n_keep, keep, want, entry);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) kept_safe += __shfl_xor(kept_safe, o, 64);
+  if ((t & 63) == 0) s_w[t >> 6] = kept_safe;
+  __syncthreads();
+  if (t == 0) {
+    unsigned int tot = 0;
+#pragma unroll
+    for (int w = 0; w < kFilterBlock / 64; ++w) tot += s_w[w];
+    if (tot) atomicAdd(&slot->sub[blockIdx.x % kSubSlots].count, (unsigned long long)tot);
+  }
+}
+
+// Re-roll of the kept entries.  With none kept, the first workgroup
+// finalises and the others return at once; otherwise only the workgroups
+// that own kept entries take part (and count the tickets).
+__device__ __forceinline__ bool recheck_nothing_kept(const ModelDev* __restrict__ md, const GenParams& gp, int H,
+                                                     const float* __restrict__ u_user,
+                                                     const float* __restrict__ cand, Slot* __restrict__ slot,
+                                                     mpmi_selection* __restrict__ out, RecheckList* __restrict__ rl,
+                                                     int n_keep) {
+  if (n_keep > 0) return false;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    finalize<MPMI_MAX_INPUT>(md, gp, cand, u_user, H, slot, out);
+    rl->count = 0u;
+    rl->n_keep = 0u;
+    __threadfence();
+  }
+  return true;
+}
+
+// Described bases: one kept candidate per lane.
+template <int DEG>
 __global__ void __launch_bounds__(kR64Block)
 recheck64_kernel(const ModelDev* __restrict__ md, GenParams gp, int H, const float* __restrict__ x_t,
                  const float* __restrict__ u_user, const float* __restrict__ cand, Slot* __restrict__ slot,
                  mpmi_selection* __restrict__ out, int16_t* __restrict__ fv_out, RecheckList* __restrict__ rl,
                  int capacity) {
   __shared__ double sK[MPMI_MAX_DIM * 8];
-  __shared__ double sAt[RC ? 1 : MPMI_MAX_ATOMS * kR64Block];
-  const unsigned int cnt_raw = rl->count;
-  const int count = (int)(cnt_raw < (unsigned int)capacity ? cnt_raw : (unsigned int)capacity);
+  __shared__ double sAt[MPMI_MAX_ATOMS * kR64Block];
+  const unsigned int kn = rl->n_keep;
+  const int n_keep = (int)(kn < (unsigned int)capacity ? kn : (unsigned int)capacity);
+  if (recheck_nothing_kept(md, gp, H, u_user, cand, slot, out, rl, n_keep)) return;
+  const int parts = min((int)gridDim.x, (n_keep + kR64Block - 1) / kR64Block);
+  if ((int)blockIdx.x >= parts) return;  // uniform
+  const int* keep = rl->idx + capacity;
   const int lane = threadIdx.x;
   unsigned long long ks = kKeyNone, kf = kKeyNone;
   unsigned int n_safe = 0;
-  if ((int)blockIdx.x * kR64Block < count) {  // uniform across the workgroup
-    const unsigned long long kstar = published_best(slot);
-    const double* Kg = &md->m64.K[0][0];
-    for (int e = lane; e < MPMI_MAX_DIM * 8; e += kR64Block) sK[e] = Kg[e];
-    __syncthreads();
-    for (int e0 = blockIdx.x * kR64Block; e0 < count; e0 += gridDim.x * kR64Block) {
-      const int e = e0 + lane;
-      if (e < count) {
-        const int entry = rl->idx[e];
-        const int c = entry >> 1;
-        const float cst = cost_at(md, gp, cand, u_user, c);
-        if (kstar != kKeyNone && safe_key(cst, c) > kstar) {
-          // behind K*: cannot change the selection; the FP32 verdict stands
-          n_safe += ((entry & 1) && c > 0) ? 1u : 0u;
-        } else {
-          const int fv = evaluate64<RC>(md, sK, gp, H, x_t, u_user, cand, c, sAt + lane);
-          if (fv_out) fv_out[c] = (int16_t)fv;
-          const bool safe = fv == H + 1;
-          const unsigned long long a = safe ? safe_key(cst, c) : kKeyNone;
-          const unsigned long long b = safe ? kKeyNone : fallback_key(fv, cst, c);
-          ks = a < ks ? a : ks;
-          kf = b < kf ? b : kf;
-          n_safe += (safe && c > 0) ? 1u : 0u;
-        }
-      }
+  const double* Kg = &md->m64.K[0][0];
+  for (int e = lane; e < MPMI_MAX_DIM * 8; e += kR64Block) sK[e] = Kg[e];
+  __syncthreads();
+  for (int e = blockIdx.x * kR64Block + lane; e < n_keep; e += parts * kR64Block) {
+    const int c = keep[e] >> 1;
+    const int fv = evaluate64<false, DEG>(md, sK, gp, H, x_t, u_user, cand, c, sAt + lane);
+    if (fv_out) fv_out[c] = (int16_t)fv;
+    const float cst = cost_at(md, gp, cand, u_user, c);
+    const bool safe = fv == H + 1;
+    const unsigned long long a = safe ? safe_key(cst, c) : kKeyNone;
+    const unsigned long long b = safe ? kKeyNone : fallback_key(fv, cst, c);
+    ks = a < ks ? a : ks;
+    kf = b < kf ? b : kf;
+    n_safe += (safe && c > 0) ? 1u : 0u;
+  }
+  recheck_publish(md, gp, H, u_user, cand, slot, out, rl, ks, kf, n_safe, (unsigned int)parts);
+}
+
+// Race car: one kept candidate per 8-lane group (evaluate64_rc8), eight per
+// workgroup.
+template <int DEG>
+__global__ void __launch_bounds__(kR64Block, 2)
+recheck64_rc_kernel(const ModelDev* __restrict__ md, GenParams gp, int H, const float* __restrict__ x_t,
+                    const float* __restrict__ u_user, const float* __restrict__ cand, Slot* __restrict__ slot,
+                    mpmi_selection* __restrict__ out, int16_t* __restrict__ fv_out, RecheckList* __restrict__ rl,
+                    int capacity) {
+  static_assert(kR64Block == 64, "one wave per workgroup");
+  constexpr int kPer = kR64Block / 8;  // candidates per workgroup pass
+  __shared__ double sK[MPMI_MAX_DIM * 8];
+  const unsigned int kn = rl->n_keep;
+  const int n_keep = (int)(kn < (unsigned int)capacity ? kn : (unsigned int)capacity);
+  if (recheck_nothing_kept(md, gp, H, u_user, cand, slot, out, rl, n_keep)) return;
+  const int parts = min((int)gridDim.x, (n_keep + kPer - 1) / kPer);
+  if ((int)blockIdx.x >= parts) return;  // uniform
+  const int* keep = rl->idx + capacity;
+  const int lane = threadIdx.x;
+  unsigned long long ks = kKeyNone, kf = kKeyNone;
+  unsigned int n_safe = 0;
+  const double* Kg = &md->m64.K[0][0];
+  for (int e = lane; e < MPMI_MAX_DIM * 8; e += kR64Block) sK[e] = Kg[e];
+  __syncthreads();
+  for (int q = blockIdx.x * kPer + (lane >> 3); q < n_keep; q += parts * kPer) {  // uniform per 8-lane group
+    const int c = keep[q] >> 1;
+    const int fv = evaluate64_rc8<DEG>(md, sK, gp, H, x_t, u_user, cand, c);
+    if ((lane & 7) == 0) {
+      if (fv_out) fv_out[c] = (int16_t)fv;
+      const float cst = cost_at(md, gp, cand, u_user, c);
+      const bool safe = fv == H + 1;
+      const unsigned long long a = safe ? safe_key(cst, c) : kKeyNone;
+      const unsigned long long b = safe ? kKeyNone : fallback_key(fv, cst, c);
+      ks = a < ks ? a : ks;
+      kf = b < kf ? b : kf;
+      n_safe += (safe && c > 0) ? 1u : 0u;
     }
   }
-  unsigned int wsum = n_safe;
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) wsum += __shfl_xor(wsum, off, 64);
-  if (publish_wave_counted<true>(ks, kf, wsum, slot, gridDim.x, blockIdx.x) && threadIdx.x == 0) {
-    finalize<MPMI_MAX_INPUT>(md, gp, cand, u_user, H, slot, out);
-    rl->count = 0u;
-    __threadfence();
-  }
+  recheck_publish(md, gp, H, u_user, cand, slot, out, rl, ks, kf, n_safe, (unsigned int)parts);
 }
 
 hipError_t launch_recheck64(const mpmi_system& sys, const void* model, const mpmi_tick_desc& d, const float* x_t,
@@ -322,12 +478,26 @@ hipError_t launch_recheck64(const mpmi_system& sys, const void* model, const mpm
   gp.n_seg = d.n_seg;
   for (int j = 0; j < MPMI_MAX_INPUT; ++j) gp.grid[j] = d.grid[j] > 0 ? d.grid[j] : 1;
   const ModelDev* md = (const ModelDev*)model;
-  if (sys.basis == MPMI_BASIS_RACE_CAR)
-    recheck64_kernel<true><<<grid, kR64Block, 0, st>>>(md, gp, d.horizon, x_t, u_user, cand, (Slot*)slot, out, fv,
-                                                       (RecheckList*)recheck, capacity);
-  else
-    recheck64_kernel<false><<<grid, kR64Block, 0, st>>>(md, gp, d.horizon, x_t, u_user, cand, (Slot*)slot, out, fv,
-                                                        (RecheckList*)recheck, capacity);
+  Slot* sl = (Slot*)slot;
+  RecheckList* rl = (RecheckList*)recheck;
+  const bool small = track_degree(sys) <= kSmallTrackDeg;
+  recheck64_filter_kernel<<<grid, kFilterBlock, 0, st>>>(md, gp, u_user, cand, sl, rl, capacity);
+  if (sys.basis == MPMI_BASIS_RACE_CAR) {
+    // Windows of 8 entries, one wave per workgroup, up to three waves per
+    // SIMD: 16 workgroups per compute unit cover 32,768 entries per pass.
+    if (small)
+      recheck64_rc_kernel<kSmallTrackDeg><<<grid * 4, kR64Block, 0, st>>>(md, gp, d.horizon, x_t, u_user, cand, sl,
+                                                                          out, fv, rl, capacity);
+    else
+      recheck64_rc_kernel<kMaxHarm><<<grid * 4, kR64Block, 0, st>>>(md, gp, d.horizon, x_t, u_user, cand, sl, out,
+                                                                    fv, rl, capacity);
+  } else if (small) {
+    recheck64_kernel<kSmallTrackDeg><<<grid, kR64Block, 0, st>>>(md, gp, d.horizon, x_t, u_user, cand, sl, out, fv,
+                                                                 rl, capacity);
+  } else {
+    recheck64_kernel<kMaxHarm><<<grid, kR64Block, 0, st>>>(md, gp, d.horizon, x_t, u_user, cand, sl, out, fv, rl,
+                                                           capacity);
+  }
   return hipGetLastError();
 }
 
@@ -375,8 +545,9 @@ multi_recheck64_kernel(const mpmi_loop_desc* __restrict__ loops, const ModelDev*
         if (en.w && c > 0) atomicAdd(&ss->count, 1ull);  // FP32 verdict stands
       } else {
         const int fv = md->sys.basis == MPMI_BASIS_RACE_CAR
-                           ? evaluate64<true>(md, &md->m64.K[0][0], gp, H, L->x_t, L->u_user, L->cand, c, sAt + lane)
-                           : evaluate64<false>(md, &md->m64.K[0][0], gp, H, L->x_t, L->u_user, L->cand, c,
+                           ? evaluate64<true, kMaxHarm>(md, &md->m64.K[0][0], gp, H, L->x_t, L->u_user, L->cand,
+                                                        c, sAt + lane)
+                           : evaluate64<false, kMaxHarm>(md, &md->m64.K[0][0], gp, H, L->x_t, L->u_user, L->cand, c,
                                                sAt + lane);
         if (L->first_violation) L->first_violation[c] = (int16_t)fv;
         const bool safe = fv == H + 1;

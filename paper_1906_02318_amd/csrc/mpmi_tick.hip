@@ -26,7 +26,7 @@ namespace mpmi {
 // RECHECK (precision FP32_RECHECK64): candidates with a checked margin within
 // the FP32 band are appended to the recheck list (with their FP32 verdict)
 // instead of publishing, and the workgroup publishes without a ticket; the
-// FP64 re-roll launch that follows completes the slot.
+// filter and FP64 re-roll launches that follow complete the slot.
 template <int BASIS, bool NOISE, int DEG, bool RECHECK>
 __global__ void __launch_bounds__(1024)
 tick_fp32_kernel(const ModelDev* __restrict__ md, GenParams gp, int H, const float* __restrict__ x_t,
@@ -351,16 +351,9 @@ __global__ void pack_kernel(mpmi_system sys, int dim, int state_feat0, const dou
       m->comp_lim[k] = lim < m->comp_lim[k] ? lim : m->comp_lim[k];
     }
     m->has_track = sys.has_track;
-    m->trk_n = sys.has_track ? sys.track_n : 0;
     m->trk_lim = (double)sys.track_half - (double)sys.track_infl;
-    m->trk_r0 = sys.track_r0;
-    for (int q = 0; q < 4; ++q) {
-      const bool on = sys.has_track && q < sys.track_n;
-      m->trk_freq[q] = on ? sys.track_freq[q] : 0;
-      m->trk_amp[q] = on ? (double)sys.track_amp[q] : 0.0;
-      m->trk_sinp[q] = on ? sin((double)sys.track_phase[q]) : 0.0;
-      m->trk_cosp[q] = on ? cos((double)sys.track_phase[q]) : 1.0;
-    }
+    for (int k = 0; k <= kMaxHarm; ++k) m->trk_p[k] = P[k];
+    for (int k = 0; k < kMaxHarm; ++k) m->trk_q[k] = Q[k];
     for (int j = 0; j < MPMI_MAX_STATE; ++j) m->sigma[j] = j < n ? (double)sys.noise_sigma[j] : 0.0;
     m->n_atoms = sys.n_atoms;
     for (int q = 0; q < MPMI_MAX_ATOMS; ++q) {

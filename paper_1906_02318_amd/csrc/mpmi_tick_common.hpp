@@ -9,11 +9,14 @@ namespace mpmi {
 
 // Candidates of one tick left to a re-roll launch, in context-owned device
 // memory: BF16X3 lists candidate indices (FP32 re-roll); FP32_RECHECK64
-// lists (candidate << 1) | FP32 verdict (1 = safe) (FP64 re-roll).
+// lists (candidate << 1) | FP32 verdict (1 = safe) (FP64 re-roll), and its
+// filter launch copies the entries that can still change the selection to a
+// second array of capacity entries after the first (n_keep of them).
 struct RecheckList {
   unsigned int count;
-  unsigned int pad[63];
-  int idx[1];  // capacity entries follow
+  unsigned int n_keep;
+  unsigned int pad[62];
+  int idx[1];  // capacity entries follow, then (FP32_RECHECK64) capacity kept entries
 };
 
 // Candidates of a many-loop tick left to the FP64 re-roll: {loop, candidate,
@@ -315,6 +318,27 @@ __device__ __forceinline__ CandResult evaluate_candidate(const ModelDev* __restr
   r.near = NEAR && valid && near;
   r.safe32 = valid && fv == H + 1;
   return r;
+}
+
+// Cost of candidate c (FP32, from its first-segment input, as in the tick).
+__device__ __forceinline__ float cost_at(const ModelDev* __restrict__ md, const GenParams& gp,
+                                         const float* __restrict__ cand, const float* __restrict__ u_user, int c) {
+  float u0[MPMI_MAX_INPUT];
+#pragma unroll
+  for (int j = 0; j < MPMI_MAX_INPUT; ++j) u0[j] = (j < md->m) ? cand_value(gp, md, cand, u_user, c, 0, j) : 0.0f;
+  return cost_of<MPMI_MAX_INPUT>(md, u0, u_user);
+}
+
+// K*: the least safe key the FP32 tick published into a slot (key_safe; the
+// FP64 re-roll's own keys go to key_safe64), or kKeyNone.
+__device__ __forceinline__ unsigned long long published_best(const Slot* __restrict__ slot) {
+  unsigned long long k = kKeyNone;
+#pragma unroll
+  for (int i = 0; i < kSubSlots; ++i) {
+    const unsigned long long v = __atomic_load_n(&slot->sub[i].key_safe, __ATOMIC_RELAXED);
+    k = v < k ? v : k;
+  }
+  return k;
 }
 
 }  // namespace mpmi
