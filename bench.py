@@ -45,9 +45,13 @@ EXECUTED_FLOPS_PER_UNIT = {"race_car": 511, "balance_bot": 128}
 # HBM traffic of the tick kernel, from rocprofv3 FETCH_SIZE / WRITE_SIZE runs
 # scaled by a copy-kernel calibration; the record names a digest of the
 # kernel's sources and is used only while the sources still match it.
-TRAFFIC_PROFILES = {"race_car_1m": os.path.join(ROOT, "profiles", "tick_fp32_race_car_N1048576_H60.md")}
+TRAFFIC_PROFILES = {
+    ("race_car_1m", "fp32"): os.path.join(ROOT, "profiles", "tick_fp32_race_car_N1048576_H60.md"),
+    ("race_car_1m", "fp32_recheck64"): os.path.join(ROOT, "profiles", "tick_fp32_recheck64_race_car_N1048576_H60.md"),
+}
 TICK_SOURCES = ["paper_1906_02318_amd/csrc/mpmi_tick.hip", "paper_1906_02318_amd/csrc/mpmi_device.hpp",
-                "paper_1906_02318_amd/csrc/mpmi_tick_common.hpp", "include/mpmi.h"]
+                "paper_1906_02318_amd/csrc/mpmi_tick_common.hpp", "paper_1906_02318_amd/csrc/mpmi_recheck64.hip",
+                "include/mpmi.h"]
 
 
 def tick_source_digest() -> str:
@@ -60,9 +64,9 @@ def tick_source_digest() -> str:
     return h.hexdigest()
 
 
-def traffic_record(workload: str):
-    """(bytes per launch, detail) from the workload's profile summary, or (None, reason)."""
-    path = TRAFFIC_PROFILES.get(workload)
+def traffic_record(workload: str, precision: str):
+    """(bytes per tick, detail) from the workload's profile summary, or (None, reason)."""
+    path = TRAFFIC_PROFILES.get((workload, precision))
     if not path or not os.path.exists(path):
         return None, "no counter profile for this workload"
     rec = None
@@ -452,11 +456,12 @@ def timed_ticks(step, n_ticks: int, warmup: int, stream):
     return np.array([a.elapsed_time(b) for a, b in ev]), wall
 
 
-def run_recheck64(st: dict, n_ticks: int = 100, warmup: int = 5):
-    """The headline ticks with the FP64 re-roll of the FP32 rounding band
-    (every candidate whose FP32 margin comes within 2e-3 m of the track edge or
-    3e-4 m/s of the v_y bound is predicted again in FP64 before the
-    selection)."""
+def run_precision(st: dict, precision: int, n_ticks: int = 100, warmup: int = 5):
+    """The headline ticks in another arithmetic: plain FP32 (verdicts inside
+    the FP32 rounding band decided in FP32), or FP32 with the FP64 re-roll of
+    that band (every candidate whose FP32 margin comes within 2e-3 m of the
+    track edge or 3e-4 m/s of the v_y bound is listed, and those that can
+    still change the selection are predicted again in FP64)."""
     import torch
 
     from paper_1906_02318_amd import mpmi
@@ -466,20 +471,26 @@ def run_recheck64(st: dict, n_ticks: int = 100, warmup: int = 5):
     outs = torch.empty((64, mpmi.SELECTION_BYTES), dtype=torch.uint8, device="cuda")
     descs = [st["mk"](t) for t in range(64)]
     for d in descs:
-        d.precision = mpmi.PREC_FP32_RECHECK64
+        d.precision = precision
 
     def step(t):
         i = t % 64
         mpmi.mpmi_tick(ctx, model, descs[i], st["x"][i], st["u"][i], out=outs[i], stream=stream)
 
     ms, wall = timed_ticks(step, n_ticks, warmup, stream)
-    sels = mpmi.decode_selection(outs)
-    re = [s_["n_recheck"] for s_ in sels[:min(n_ticks, 64)]]
-    return {"trajectories_per_s": (N + 1) * n_ticks / wall, "ms_per_tick": wall * 1e3 / n_ticks,
-            "p50_tick_ms": float(np.percentile(ms, 50)), "p99_tick_ms": float(np.percentile(ms, 99)),
-            "rechecked_per_tick_mean": float(np.mean(re)), "rechecked_per_tick_max": int(np.max(re)),
-            "note": "FP32 tick (near-band candidates listed) + FP64 re-roll launch; decisions those of FP64 "
-                    "rollouts (tests: 1M tick identical to the full oracle)"}
+    out = {"trajectories_per_s": (N + 1) * n_ticks / wall, "ms_per_tick": wall * 1e3 / n_ticks,
+           "p50_tick_ms": float(np.percentile(ms, 50)), "p99_tick_ms": float(np.percentile(ms, 99)),
+           "mean_tick_ms": float(ms.mean())}
+    if precision == mpmi.PREC_FP32_RECHECK64:
+        re = [s_["n_recheck"] for s_ in mpmi.decode_selection(outs)[:min(n_ticks, 64)]]
+        out.update({"listed_per_tick_mean": float(np.mean(re)), "listed_per_tick_max": int(np.max(re)),
+                    "note": "FP32 tick listing its rounding band + filter + FP64 re-roll of the kept "
+                            "candidates; decisions those of FP64 rollouts (tests: 1M tick identical to the "
+                            "full oracle)"})
+    else:
+        out["note"] = ("plain FP32: the decision inside the FP32 rounding band is FP32's (tests: the 1M tick "
+                       "picks a different candidate than the FP64 oracle; closed-loop agreement 99.5%)")
+    return out
 
 
 def run_lifted(st: dict, wl: dict, n_ticks: int = 100, warmup: int = 5):
@@ -638,7 +649,7 @@ def run_plain_vs_learned(n_ticks: int = 500, warmup: int = 20):
     return out
 
 
-LEGS = ("bf16x3", "recheck64", "lifted", "trajectory", "learned", "mlp", "multi", "closed_loop")
+LEGS = ("bf16x3", "other_precision", "lifted", "trajectory", "learned", "mlp", "multi", "closed_loop")
 
 
 def main():
@@ -648,6 +659,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="race_car_1m", choices=sorted(WORKLOADS))
     ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--precision", default="fp32_recheck64", choices=["fp32", "fp32_recheck64"],
+                    help="arithmetic of the headline ticks (fp32_recheck64: FP32 with the FP64 re-roll of the "
+                         "FP32 rounding band, the decisions of FP64 rollouts)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-extras", action="store_true", help="skip every leg after the headline ticks")
@@ -677,9 +691,11 @@ def main():
     Nc = N + 1
     stream = torch.cuda.current_stream()
     outs = torch.empty((n_inputs, mpmi.SELECTION_BYTES), dtype=torch.uint8, device="cuda")
+    prec = mpmi.PREC_FP32_RECHECK64 if args.precision == "fp32_recheck64" else mpmi.PREC_FP32
     descs = [st["mk"](t) for t in range(n_inputs)]
     for d in descs:
         d.block = args.block
+        d.precision = prec
 
     def step(i):
         t = i % n_inputs
@@ -715,7 +731,7 @@ def main():
     avg_kernel_s = float(dev_ms.mean()) * 1e-3
     flops = FLOPS_PER_UNIT[wl["system"]] * units_per_tick
     achieved = flops / avg_kernel_s / 1e12
-    traffic = traffic_record(args.workload)
+    traffic = traffic_record(args.workload, args.precision)
     fma_ceiling = mpmi.mpmi_fp32_fma_rate(ctx)
     out = {
         "metric": METRIC,
@@ -728,12 +744,12 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "fp32",
+        "dtype": "fp32+fp64" if prec == mpmi.PREC_FP32_RECHECK64 else "fp32",
         "data": "synthetic",
         "config": {
             "workload": f"{args.workload}: {wl['system']} tick, N={N} candidates + u_h, H={H}, "
                         f"{'grid ' + 'x'.join(map(str, wl['grid'])) if wl['gen'] == 'grid' else 'uniform S=' + str(wl['S'])}",
-            "N": N, "H": H, "system": wl["system"], "precision": "fp32", "plain_or_learned": "plain",
+            "N": N, "H": H, "system": wl["system"], "precision": args.precision, "plain_or_learned": "plain",
         },
         "p50_tick_ms": float(np.percentile(dev_ms, 50)),
         "p99_tick_ms": float(np.percentile(dev_ms, 99)),
@@ -752,15 +768,19 @@ def main():
             "frac": achieved / PEAK_FP32_VECTOR_TFLOPS,
             "traffic": traffic[0],
             "traffic_detail": traffic[1],
-            "kernel": f"tick_fp32_kernel<{wl['system']}>",
+            "kernel": (f"tick_fp32_kernel<{wl['system']}, listing> + filter + FP64 re-roll (one tick, "
+                       f"three launches)" if prec == mpmi.PREC_FP32_RECHECK64
+                       else f"tick_fp32_kernel<{wl['system']}>"),
             "avg_kernel_ms": avg_kernel_s * 1e3,
             "flops_per_unit": FLOPS_PER_UNIT[wl["system"]],
             "executed_flops_per_unit": EXECUTED_FLOPS_PER_UNIT[wl["system"]],
             "executed_tflops": EXECUTED_FLOPS_PER_UNIT[wl["system"]] * units_per_tick / avg_kernel_s / 1e12,
             "fp32_fma_ceiling_tflops": fma_ceiling,
-            "note": "algorithmic = plain psi^T K step; the kernel folds input terms once per segment and executes "
-                    "fewer flops; packed FP32 is disabled, so the reachable vector rate is the non-packed FMA "
-                    "ceiling measured live (fp32_fma_ceiling_tflops; 78.6 theoretical)",
+            "note": "algorithmic = plain psi^T K step of the FP32 pass over the whole tick's device time (with "
+                    "fp32_recheck64 the filter and FP64 re-roll launches count as time, not flops); the kernel "
+                    "folds input terms once per segment and executes fewer flops; packed FP32 is disabled, so "
+                    "the reachable vector rate is the non-packed FMA ceiling measured live "
+                    "(fp32_fma_ceiling_tflops; 78.6 theoretical)",
         },
     }
     if "bf16x3" in legs:
@@ -798,8 +818,11 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         out["calibration_copy_bytes"] = args.copy_bytes
-    if "recheck64" in legs:
-        out["race_car_1m_fp32_recheck64"] = run_recheck64(st)
+    if "other_precision" in legs:
+        if prec == mpmi.PREC_FP32_RECHECK64:
+            out["race_car_1m_fp32"] = run_precision(st, mpmi.PREC_FP32)
+        else:
+            out["race_car_1m_fp32_recheck64"] = run_precision(st, mpmi.PREC_FP32_RECHECK64)
     if "lifted" in legs:
         out["race_car_1m_lifted"] = run_lifted(st, wl)
     if "trajectory" in legs:
