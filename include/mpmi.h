@@ -661,9 +661,12 @@ mpmi_status mdn_sample(mpmi_ctx ctx, const void* model, const float* head, int32
  * lanes_per_cand as in mpmi_tick) into *out, then the exhaustive fallback
  * tick described by *fallback (GRID or UNIFORM), which runs only if *out
  * holds MPMI_NO_SAFE and then overwrites it (out->n_cand tells which
- * candidate set decided).  cand_work [1][2][P] device; head_out [80] device
- * or NULL; w_bf16 16-byte aligned (MPMI_EINVAL otherwise).  Race-car models
- * only. */
+ * candidate set decided).  Each of the two ticks is FP32 or FP32_RECHECK64
+ * (its descriptor's precision; the latter with one lane per candidate and at
+ * most 2^22 candidates, and sharing the context's recheck list, so ordered
+ * on one stream with the context's other such ticks).  cand_work [1][2][P]
+ * device; head_out [80] device or NULL; w_bf16 16-byte aligned (MPMI_EINVAL
+ * otherwise).  Race-car models only. */
 mpmi_status mpmi_proposal_tick(mpmi_ctx ctx, const void* model, const uint16_t* w_bf16, const float* w_f32,
                                const float* in_mean, const float* in_std, const float* x_t,
                                const float* u_user, const mpmi_tick_desc* prop /* host */,

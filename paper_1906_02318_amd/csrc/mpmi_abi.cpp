@@ -1020,8 +1020,14 @@ mpmi_status mpmi_proposal_tick(mpmi_ctx ctx, const void* model, const uint16_t* 
   if ((s = validate_desc(ctx, sys, fallback)) != MPMI_OK) return s;
   if (pd.n_cand < 1 || pd.n_seg != 1) return fail(ctx, MPMI_EINVAL, "proposals need n_cand >= 1 and n_seg == 1");
   if (fallback->gen == MPMI_GEN_EXPLICIT) return fail(ctx, MPMI_EINVAL, "the fallback must be GRID or UNIFORM");
-  if (pd.precision != MPMI_PREC_FP32 || fallback->precision != MPMI_PREC_FP32)
-    return fail(ctx, MPMI_EUNSUPPORTED, "only FP32 ticks are available");
+  const bool r64 = pd.precision == MPMI_PREC_FP32_RECHECK64, fb64 = fallback->precision == MPMI_PREC_FP32_RECHECK64;
+  if ((pd.precision != MPMI_PREC_FP32 && !r64) || (fallback->precision != MPMI_PREC_FP32 && !fb64))
+    return fail(ctx, MPMI_EUNSUPPORTED, "proposal ticks are FP32 or FP32_RECHECK64");
+  if (r64 && pd.lanes_per_cand > 1)
+    return fail(ctx, MPMI_EUNSUPPORTED, "FP32_RECHECK64 proposal ticks run one lane per candidate");
+  if ((r64 && (long long)pd.n_cand + 1 > mpmi::kRecheckCapacity) ||
+      (fb64 && (long long)fallback->n_cand + 1 > mpmi::kRecheckCapacity))
+    return fail(ctx, MPMI_EUNSUPPORTED, "FP32_RECHECK64 ticks take at most %d candidates", mpmi::kRecheckCapacity);
   if (!x_t || !u_user || !cand_work || !out) return fail(ctx, MPMI_EINVAL, "x_t, u_user, cand_work, out must be non-NULL");
   if (!aligned(w_bf16, 16)) return fail(ctx, MPMI_EINVAL, "w_bf16 must be 16-byte aligned");
   if (pd.lanes_per_cand > 1 && mpmi::system_noisy(sys))
@@ -1035,12 +1041,20 @@ mpmi_status mpmi_proposal_tick(mpmi_ctx ctx, const void* model, const uint16_t* 
     if (pd.lanes_per_cand > 1)
       e = mpmi::launch_tick_split(sys, pd.lanes_per_cand, model, pd, x_t, u_user, cand_work, slot, out, nullptr,
                                   st);
+    else if (r64)
+      e = mpmi::launch_tick(sys, model, pd, x_t, u_user, cand_work, slot, out, nullptr, nullptr, 0, st, nullptr,
+                            ctx->recheck, mpmi::kRecheckCapacity, mpmi::device_cu_count() * 4);
     else
       e = mpmi::launch_tick(sys, model, pd, x_t, u_user, cand_work, slot, out, nullptr, nullptr, 0, st);
   }
   void* slot2 = (char*)ctx->slots + (size_t)fallback->loop * mpmi::slot_bytes();
-  if (e == hipSuccess)
-    e = mpmi::launch_tick(sys, model, *fallback, x_t, u_user, nullptr, slot2, out, nullptr, nullptr, 0, st, out);
+  if (e == hipSuccess) {
+    if (fb64)
+      e = mpmi::launch_tick(sys, model, *fallback, x_t, u_user, nullptr, slot2, out, nullptr, nullptr, 0, st, out,
+                            ctx->recheck, mpmi::kRecheckCapacity, mpmi::device_cu_count() * 4);
+    else
+      e = mpmi::launch_tick(sys, model, *fallback, x_t, u_user, nullptr, slot2, out, nullptr, nullptr, 0, st, out);
+  }
   return check_hip(ctx, e, "mpmi_proposal_tick launch");
 }
 

@@ -48,10 +48,13 @@ hipError_t launch_tick(const mpmi_system& sys, const void* model, const mpmi_tic
                        int16_t* fv, float* traj, long long traj_ld, hipStream_t st,
                        const mpmi_selection* gate = nullptr, void* recheck = nullptr, int recheck_capacity = 0,
                        int recheck_grid = 0);
-// FP64 re-roll of a tick's listed candidates and the selection (mpmi_recheck64.hip).
+// Filter and FP64 re-roll of a tick's listed candidates, and the selection
+// (mpmi_recheck64.hip); with `gate` set, nothing is finalised when the gate
+// record already holds a safe choice.
 hipError_t launch_recheck64(const mpmi_system& sys, const void* model, const mpmi_tick_desc& d, const float* x_t,
                             const float* u_user, const float* cand, void* slot, mpmi_selection* out, int16_t* fv,
-                            void* recheck, int capacity, int grid, hipStream_t st);
+                            void* recheck, int capacity, int grid, hipStream_t st,
+                            const mpmi_selection* gate = nullptr);
 size_t multi_recheck_bytes(size_t capacity);
 hipError_t launch_multi_recheck64(const mpmi_loop_desc* loops, const void* models, const int* model_of_loop,
                                   void* slots, uint64_t* ticks, void* recheck, int n_loops, int grid, hipStream_t st);

@@ -48,6 +48,8 @@ struct GemmArgs {
   const float* zin;    // kGeluBack: pre-activation [M][N] FP32
   float* out_f32;      // [M][N] or NULL
   uint16_t* out_bf16;  // [M][N] or NULL
+  uint16_t* out_bf16_t;  // the BF16 output transposed, [N][ldt], or NULL
+  int ldt;
   // Split-K (kPlain only): gridDim.z parts of ksplit rows of K each write
   // FP32 partial products to part[z][M][N]; colsum (or NULL), an FP32
   // [K][N] matrix whose column sums over each part's K range go to
@@ -57,6 +59,7 @@ struct GemmArgs {
   const float* colsum;
   float* part_cs;
   bool vec_a, vec_b;   // 16-byte loads allowed (leading dimension a multiple of 8, 16-byte aligned base)
+  bool vec_t;          // 8-byte transposed stores allowed (ldt a multiple of 4, 8-byte aligned base)
 };
 
 // C = op(A) op(B) on v_mfma_f32_16x16x32_bf16.  A 256-thread workgroup owns a
@@ -65,9 +68,8 @@ struct GemmArgs {
 // of B from global memory into LDS, in the operand order the MFMA reads (row
 // or column, then k): a chunk along k (row-major A, transposed B) is stored
 // as one 16-byte LDS write, a chunk along m or n as eight 2-byte writes.  The
-// next step's chunks are loaded into registers while the current step's
-// MFMAs run, and the two LDS buffers alternate (one barrier per step).
-// Chunks that are contiguous, aligned and wholly inside the matrix take one
+// next stage's chunks (several k steps) are loaded into registers while the
+// current stage's MFMAs run (see gemm_bf16_kernel).  Chunks that are contiguous, aligned and wholly inside the matrix take one
 // 16-byte load; others (ragged edges, odd leading dimensions) load element by
 // element.
 constexpr int kGemmKP = 40;  // padded k extent of an LDS row (80 B, keeps 16-B alignment)
@@ -139,42 +141,63 @@ __device__ __forceinline__ void gemm_store(const GemmArgs& g, const GemmChunk& c
   }
 }
 
+// A stage is kGemmSub k-steps of 32 (128 values of k): every thread issues
+// the loads of the whole next stage (kGemmSub 16-byte chunks of A and of B)
+// into registers before the MFMAs of the current one, so a product with
+// K = 256 takes two memory round trips instead of eight.  One LDS buffer
+// (40 KB, several workgroups per CU): the registers are stored into it
+// after a barrier that ends the current stage's reads.
+constexpr int kGemmSub = 4;
+
 template <int EPI>
 __global__ void __launch_bounds__(256) gemm_bf16_kernel(GemmArgs g) {
-  __shared__ __attribute__((aligned(16))) uint16_t As[2][64][kGemmKP];
-  __shared__ __attribute__((aligned(16))) uint16_t Bs[2][64][kGemmKP];
+  __shared__ __attribute__((aligned(16))) uint16_t As[kGemmSub][64][kGemmKP];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[kGemmSub][64][kGemmKP];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
   const int kbeg = blockIdx.z * g.ksplit;
   const int kend = min(g.K, kbeg + g.ksplit);
+  constexpr int kStage = 32 * kGemmSub;
   f32x4_t acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-  GemmChunk c;
-  gemm_load(g, m0, n0, kbeg, kend, &c);
-  gemm_store(g, c, As[0], Bs[0]);
+  GemmChunk c[kGemmSub];
+#pragma unroll
+  for (int q = 0; q < kGemmSub; ++q) gemm_load(g, m0, n0, kbeg + 32 * q, kend, &c[q]);
+#pragma unroll
+  for (int q = 0; q < kGemmSub; ++q) gemm_store(g, c[q], As[q], Bs[q]);
   __syncthreads();
-  int buf = 0;
-  for (int k0 = kbeg; k0 < kend; k0 += 32) {
-    const bool more = k0 + 32 < kend;
-    if (more) gemm_load(g, m0, n0, k0 + 32, kend, &c);
-    const int kq = (lane >> 4) * 8;
-    bf16x8_t af[2], bfr[2];
+  for (int k0 = kbeg; k0 < kend; k0 += kStage) {
+    const bool more = k0 + kStage < kend;
+    if (more) {
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      af[i] = *reinterpret_cast<const bf16x8_t*>(&As[buf][wm * 32 + i * 16 + (lane & 15)][kq]);
-      bfr[i] = *reinterpret_cast<const bf16x8_t*>(&Bs[buf][wn * 32 + i * 16 + (lane & 15)][kq]);
+      for (int q = 0; q < kGemmSub; ++q) gemm_load(g, m0, n0, k0 + kStage + 32 * q, kend, &c[q]);
     }
+    const int kq = (lane >> 4) * 8;
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int q = 0; q < kGemmSub; ++q) {
+      if (k0 + 32 * q >= kend) break;  // uniform: a ragged last stage
+      bf16x8_t af[2], bfr[2];
 #pragma unroll
-      for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
-    if (more) gemm_store(g, c, As[buf ^ 1], Bs[buf ^ 1]);
-    __syncthreads();
-    buf ^= 1;
+      for (int i = 0; i < 2; ++i) {
+        af[i] = *reinterpret_cast<const bf16x8_t*>(&As[q][wm * 32 + i * 16 + (lane & 15)][kq]);
+        bfr[i] = *reinterpret_cast<const bf16x8_t*>(&Bs[q][wn * 32 + i * 16 + (lane & 15)][kq]);
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+    }
+    if (more) {  // uniform
+      __syncthreads();  // the stage's reads are done
+#pragma unroll
+      for (int q = 0; q < kGemmSub; ++q) gemm_store(g, c[q], As[q], Bs[q]);
+      __syncthreads();
+    }
   }
   // Bias-gradient partial column sums over this part's K range (dW products:
   // the workgroups of the first tile row).  Thread t sums rows
@@ -199,16 +222,20 @@ __global__ void __launch_bounds__(256) gemm_bf16_kernel(GemmArgs g) {
     if (t < 64 && n0 + t < g.N)
       g.part_cs[(size_t)blockIdx.z * g.N + n0 + t] = (cs[0][t] + cs[1][t]) + (cs[2][t] + cs[3][t]);
   }
-  // D fragment: lane holds column (lane & 15), rows (lane >> 4) * 4 + r.
+  // D fragment: lane holds column (lane & 15), rows (lane >> 4) * 4 + r.  The
+  // transposed BF16 copy (when asked for) takes the lane's four rows of one
+  // column as one 8-byte store.
   float* dst = (EPI == kPlain && g.part) ? g.part + (size_t)blockIdx.z * g.M * g.N : nullptr;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < 2; ++j) {
+      const int mb = m0 + wm * 32 + i * 16 + (lane >> 4) * 4;
+      const int n = n0 + wn * 32 + j * 16 + (lane & 15);
+      uint16_t hb[4] = {0, 0, 0, 0};
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int m = m0 + wm * 32 + i * 16 + (lane >> 4) * 4 + r;
-        const int n = n0 + wn * 32 + j * 16 + (lane & 15);
+        const int m = mb + r;
         if (m >= g.M || n >= g.N) continue;
         float v = acc[i][j][r];
         const size_t o = (size_t)m * g.N + n;
@@ -217,20 +244,36 @@ __global__ void __launch_bounds__(256) gemm_bf16_kernel(GemmArgs g) {
         } else if (EPI == kGelu) {
           v += g.bias[n];
           if (g.out_f32) g.out_f32[o] = v;
-          g.out_bf16[o] = f2bf(gelu_f(v));
+          hb[r] = f2bf(gelu_f(v));
+          g.out_bf16[o] = hb[r];
         } else if (EPI == kLinear) {
           v += g.bias[n];
           if (g.out_f32) g.out_f32[o] = v;
-          if (g.out_bf16) g.out_bf16[o] = f2bf(v);
+          hb[r] = f2bf(v);
+          if (g.out_bf16) g.out_bf16[o] = hb[r];
         } else if (EPI == kGeluBack) {
           v *= gelu_grad_f(g.zin[o]);
           if (g.out_f32) g.out_f32[o] = v;
-          g.out_bf16[o] = f2bf(v);
+          hb[r] = f2bf(v);
+          g.out_bf16[o] = hb[r];
         } else {
           if (g.out_f32) g.out_f32[o] = v;
-          if (g.out_bf16) g.out_bf16[o] = f2bf(v);
+          hb[r] = f2bf(v);
+          if (g.out_bf16) g.out_bf16[o] = hb[r];
         }
       }
+      if (!dst && g.out_bf16_t && n < g.N) {
+        uint16_t* tp = g.out_bf16_t + (size_t)n * g.ldt + mb;
+        if (g.vec_t && mb + 3 < g.M) {
+          *reinterpret_cast<uint2*>(tp) =
+              make_uint2((uint32_t)hb[0] | ((uint32_t)hb[1] << 16), (uint32_t)hb[2] | ((uint32_t)hb[3] << 16));
+        } else {
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            if (mb + r < g.M) tp[r] = hb[r];
+        }
+      }
+    }
 }
 
 // Split-K reduction: out[e] = sum over parts z (in order) of part[z][e],
@@ -256,6 +299,7 @@ template <int EPI>
 static hipError_t gemm(GemmArgs g, hipStream_t st, int splits = 1, int* parts_out = nullptr) {
   g.vec_a = g.lda % 8 == 0 && ((uintptr_t)g.A & 15) == 0;
   g.vec_b = g.ldb % 8 == 0 && ((uintptr_t)g.B & 15) == 0;
+  g.vec_t = g.ldt % 4 == 0 && ((uintptr_t)g.out_bf16_t & 7) == 0;
   if (splits < 1) splits = 1;
   g.ksplit = (((g.K + splits - 1) / splits) + 31) / 32 * 32;
   splits = (g.K + g.ksplit - 1) / g.ksplit;
@@ -265,20 +309,42 @@ static hipError_t gemm(GemmArgs g, hipStream_t st, int splits = 1, int* parts_ou
   return hipGetLastError();
 }
 
-// Standardised inputs, BF16: X [B][8] -> H0 [B][8].
+// Standardised inputs, BF16: X [B][8] -> H0 [B][8], and H0T [8][B] when set.
 __global__ void mlp_input_kernel(const float* __restrict__ X, const float* __restrict__ mean,
-                                 const float* __restrict__ stdv, int B, uint16_t* __restrict__ H0) {
+                                 const float* __restrict__ stdv, int B, uint16_t* __restrict__ H0,
+                                 uint16_t* __restrict__ H0T) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= B * kMlpIn) return;
   const int j = e % kMlpIn;
-  H0[e] = f2bf((X[e] - mean[j]) / stdv[j]);
+  const uint16_t h = f2bf((X[e] - mean[j]) / stdv[j]);
+  H0[e] = h;
+  if (H0T) H0T[(size_t)j * B + e / kMlpIn] = h;
+}
+
+// The weights of every layer transposed: W_l [din][dout] -> Wt_l [dout][din],
+// at the same offsets of the flat vector (the forward product's B operand
+// then runs along k).  One thread per parameter; biases are skipped.
+__global__ void mlp_weights_t_kernel(const uint16_t* __restrict__ w16, uint16_t* __restrict__ w16t) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const int dims[5] = {kMlpIn, kMlpHid, kMlpHid, kMlpHid, kMlpOut};
+  int o = 0;
+#pragma unroll
+  for (int l = 0; l < 4; ++l) {
+    const int din = dims[l], dout = dims[l + 1], nw = din * dout;
+    if (e >= o && e < o + nw) {
+      const int k = (e - o) / dout, n = (e - o) % dout;
+      w16t[o + n * din + k] = w16[e];
+    }
+    o += nw + dout;
+  }
 }
 
 // Mixture negative log-likelihood of targets T [B][2] under heads Y [B][80]:
-// per-sample NLL (FP32) and dNLL/dY / B as FP32 and BF16.  One thread per sample.
+// per-sample NLL (FP32) and dNLL/dY / B as FP32 and BF16 ([B][80], and the
+// BF16 values again as [80][B]).  One thread per sample.
 __global__ void mdn_loss_kernel(const float* __restrict__ Y, const float* __restrict__ T, int B,
                                 float* __restrict__ nll, float* __restrict__ dY32, uint16_t* __restrict__ dY16,
-                                float* __restrict__ loss_sum) {
+                                uint16_t* __restrict__ dY16T, float* __restrict__ loss_sum) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   float contrib = 0.0f;
   if (b < B) {
@@ -325,6 +391,7 @@ __global__ void mdn_loss_kernel(const float* __restrict__ Y, const float* __rest
         const float v = gk[q] * inv_b;
         dY32[(size_t)b * kMlpOut + 5 * k + q] = v;
         dY16[(size_t)b * kMlpOut + 5 * k + q] = f2bf(v);
+        dY16T[(size_t)(5 * k + q) * B + b] = f2bf(v);  // [80][B]: the dW product's B operand
       }
     }
   }
@@ -574,11 +641,19 @@ mlp_row_forward_kernel(const float* __restrict__ x_t, const float* __restrict__ 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Split-K parts of the weight-gradient products (batch rows split into at
-// most kMlpSplits ranges of at least kMlpSplitRows rows).
-constexpr int kMlpSplits = 16, kMlpSplitRows = 256;
+// most kMlpSplits ranges of at least kMlpSplitRows rows): batch 4,096 runs 16
+// parts, 256 workgroups for a 256 x 256 product; batch 16,384 and more run 64
+// parts (1,024 workgroups), each part a chain of at most B / 2,048 k-steps.
+constexpr int kMlpSplits = 64, kMlpSplitRows = 256;
 
+// Activations and their gradients are kept batch-major ([B][width]) for the
+// forward products and the dX products, and batch-minor ([width][B], the "T"
+// copies, written by the same epilogues) for the weight-gradient products,
+// whose contraction runs over the batch: every product then stages operands
+// whose k index is contiguous in memory.
 struct MlpWork {
   uint16_t *h0, *h1, *h2, *h3, *dY16, *dz16;
+  uint16_t *w16t, *h0T, *h1T, *h2T, *h3T, *dY16T, *dz16T;
   float *z1, *z2, *z3, *Y, *dY32, *dz32, *nll, *loss, *row, *part, *part_cs;
 };
 
@@ -592,6 +667,13 @@ static MlpWork carve(void* base, int B) {
   w.h3 = (uint16_t*)take((size_t)B * kMlpHid * 2);
   w.dY16 = (uint16_t*)take((size_t)B * kMlpOut * 2);
   w.dz16 = (uint16_t*)take((size_t)B * kMlpHid * 2 * 2);  // two ping-pong halves
+  w.w16t = (uint16_t*)take((size_t)kMlpParams * 2);
+  w.h0T = (uint16_t*)take((size_t)B * kMlpIn * 2);
+  w.h1T = (uint16_t*)take((size_t)B * kMlpHid * 2);
+  w.h2T = (uint16_t*)take((size_t)B * kMlpHid * 2);
+  w.h3T = (uint16_t*)take((size_t)B * kMlpHid * 2);
+  w.dY16T = (uint16_t*)take((size_t)B * kMlpOut * 2);
+  w.dz16T = (uint16_t*)take((size_t)B * kMlpHid * 2 * 2);
   w.z1 = (float*)take((size_t)B * kMlpHid * 4);
   w.z2 = (float*)take((size_t)B * kMlpHid * 4);
   w.z3 = (float*)take((size_t)B * kMlpHid * 4);
@@ -624,26 +706,35 @@ static void layer_offsets(size_t* ow, size_t* ob) {
   }
 }
 
+// The forward products read the transposed weights (w.w16t, formed first);
+// with `with_t` the hidden activations are also written batch-minor.
 static hipError_t forward_into(const uint16_t* w16, const float* bias32, const float* mean, const float* stdv,
-                               const float* X, int B, const MlpWork& w, float* Y, hipStream_t st) {
+                               const float* X, int B, const MlpWork& w, float* Y, bool with_t, hipStream_t st) {
   size_t ow[4], ob[4];
   layer_offsets(ow, ob);
-  mlp_input_kernel<<<(B * kMlpIn + 255) / 256, 256, 0, st>>>(X, mean, stdv, B, w.h0);
+  mlp_weights_t_kernel<<<(kMlpParams + 255) / 256, 256, 0, st>>>(w16, w.w16t);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  mlp_input_kernel<<<(B * kMlpIn + 255) / 256, 256, 0, st>>>(X, mean, stdv, B, w.h0, with_t ? w.h0T : nullptr);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
   const uint16_t* hin[4] = {w.h0, w.h1, w.h2, w.h3};
   uint16_t* hout[3] = {w.h1, w.h2, w.h3};
+  uint16_t* hout_t[3] = {w.h1T, w.h2T, w.h3T};
   float* zout[3] = {w.z1, w.z2, w.z3};
   const int din[4] = {kMlpIn, kMlpHid, kMlpHid, kMlpHid};
   for (int l = 0; l < 3; ++l) {
     GemmArgs g{};
-    g.A = hin[l]; g.B = w16 + ow[l]; g.M = B; g.N = kMlpHid; g.K = din[l];
-    g.lda = din[l]; g.ldb = kMlpHid; g.bias = bias32 + ob[l]; g.out_f32 = zout[l]; g.out_bf16 = hout[l];
+    g.A = hin[l]; g.B = w.w16t + ow[l]; g.tb = 1; g.M = B; g.N = kMlpHid; g.K = din[l];
+    g.lda = din[l]; g.ldb = din[l]; g.bias = bias32 + ob[l]; g.out_f32 = zout[l]; g.out_bf16 = hout[l];
+    if (with_t) {
+      g.out_bf16_t = hout_t[l];
+      g.ldt = B;
+    }
     if ((e = gemm<kGelu>(g, st)) != hipSuccess) return e;
   }
   GemmArgs g{};
-  g.A = w.h3; g.B = w16 + ow[3]; g.M = B; g.N = kMlpOut; g.K = kMlpHid;
-  g.lda = kMlpHid; g.ldb = kMlpOut; g.bias = bias32 + ob[3]; g.out_f32 = Y;
+  g.A = w.h3; g.B = w.w16t + ow[3]; g.tb = 1; g.M = B; g.N = kMlpOut; g.K = kMlpHid;
+  g.lda = kMlpHid; g.ldb = kMlpHid; g.bias = bias32 + ob[3]; g.out_f32 = Y;
   return gemm<kLinear>(g, st);
 }
 
@@ -652,7 +743,7 @@ static hipError_t forward_into(const uint16_t* w16, const float* bias32, const f
 hipError_t launch_mlp_forward(const uint16_t* w16, const float* w32, const float* mean, const float* stdv,
                               const float* X, int B, float* Y, void* work, hipStream_t st) {
   const MlpWork w = carve(work, B);
-  return forward_into(w16, w32, mean, stdv, X, B, w, Y, st);
+  return forward_into(w16, w32, mean, stdv, X, B, w, Y, false, st);
 }
 
 hipError_t launch_mlp_grad(const uint16_t* w16, const float* w32, const float* mean, const float* stdv,
@@ -661,25 +752,28 @@ hipError_t launch_mlp_grad(const uint16_t* w16, const float* w32, const float* m
   const MlpWork w = carve(work, B);
   hipError_t e = hipMemsetAsync(w.loss, 0, sizeof(float), st);
   if (e != hipSuccess) return e;
-  if ((e = forward_into(w16, w32, mean, stdv, X, B, w, w.Y, st)) != hipSuccess) return e;
-  mdn_loss_kernel<<<(B + 255) / 256, 256, 0, st>>>(w.Y, T, B, w.nll, w.dY32, w.dY16, w.loss);
+  if ((e = forward_into(w16, w32, mean, stdv, X, B, w, w.Y, true, st)) != hipSuccess) return e;
+  mdn_loss_kernel<<<(B + 255) / 256, 256, 0, st>>>(w.Y, T, B, w.nll, w.dY32, w.dY16, w.dY16T, w.loss);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   size_t ow[4], ob[4];
   layer_offsets(ow, ob);
   const int dims[5] = {kMlpIn, kMlpHid, kMlpHid, kMlpHid, kMlpOut};
-  const uint16_t* hin[4] = {w.h0, w.h1, w.h2, w.h3};
+  const uint16_t* hin_t[4] = {w.h0T, w.h1T, w.h2T, w.h3T};
   const float* zin[4] = {nullptr, w.z1, w.z2, w.z3};
-  // dz of the current layer (output width dims[l+1]): FP32 for bias sums, BF16 as operand.
+  // dz of the current layer (output width dims[l+1]): FP32 for bias sums,
+  // BF16 as operand, batch-major and batch-minor.
   const float* dz32 = w.dY32;
   const uint16_t* dz16 = w.dY16;
+  const uint16_t* dz16t = w.dY16T;
   for (int l = 3; l >= 0; --l) {
     const int kin = dims[l], nout = dims[l + 1];
-    // dW_l = h_{l-1}^T dz  ([kin][nout]), split over the batch rows, with
-    // the bias gradient db_l = column sums of dz (FP32) in the same parts;
-    // both reduced over the parts in order.
+    // dW_l = h_{l-1}^T dz  ([kin][nout]) from the batch-minor copies
+    // (h^T [kin][B] as A, dz^T [nout][B] as the transposed B), split over the
+    // batch, with the bias gradient db_l = column sums of dz (FP32) in the
+    // same parts; both reduced over the parts in order.
     GemmArgs gw{};
-    gw.A = hin[l]; gw.ta = 1; gw.lda = kin;
-    gw.B = dz16; gw.ldb = nout;
+    gw.A = hin_t[l]; gw.lda = B;
+    gw.B = dz16t; gw.tb = 1; gw.ldb = B;
     gw.M = kin; gw.N = nout; gw.K = B;
     gw.part = w.part; gw.colsum = dz32; gw.part_cs = w.part_cs;
     int splits = B / kMlpSplitRows;
@@ -697,9 +791,11 @@ hipError_t launch_mlp_grad(const uint16_t* w16, const float* w32, const float* m
     gd.B = w16 + ow[l]; gd.tb = 1; gd.ldb = nout;
     gd.M = B; gd.N = kin; gd.K = nout;
     gd.zin = zin[l]; gd.out_f32 = w.dz32 + half; gd.out_bf16 = w.dz16 + half;
+    gd.out_bf16_t = w.dz16T + half; gd.ldt = B;
     if ((e = gemm<kGeluBack>(gd, st)) != hipSuccess) return e;
     dz32 = w.dz32 + half;
     dz16 = w.dz16 + half;
+    dz16t = w.dz16T + half;
   }
   if (loss) {
     e = hipMemcpyAsync(loss, w.loss, sizeof(float), hipMemcpyDeviceToDevice, st);

@@ -396,9 +396,11 @@ __global__ void __launch_bounds__(kR64Block)
 recheck64_kernel(const ModelDev* __restrict__ md, GenParams gp, int H, const float* __restrict__ x_t,
                  const float* __restrict__ u_user, const float* __restrict__ cand, Slot* __restrict__ slot,
                  mpmi_selection* __restrict__ out, int16_t* __restrict__ fv_out, RecheckList* __restrict__ rl,
-                 int capacity) {
+                 int capacity, const mpmi_selection* __restrict__ gate) {
   __shared__ double sK[MPMI_MAX_DIM * 8];
   __shared__ double sAt[MPMI_MAX_ATOMS * kR64Block];
+  // Gated tick (a fallback after a proposal tick): nothing ran, nothing to finalise.
+  if (gate && gate->status == MPMI_OK) return;
   const unsigned int kn = rl->n_keep;
   const int n_keep = (int)(kn < (unsigned int)capacity ? kn : (unsigned int)capacity);
   if (recheck_nothing_kept(md, gp, H, u_user, cand, slot, out, rl, n_keep)) return;
@@ -433,10 +435,12 @@ __global__ void __launch_bounds__(kR64Block, 2)
 recheck64_rc_kernel(const ModelDev* __restrict__ md, GenParams gp, int H, const float* __restrict__ x_t,
                     const float* __restrict__ u_user, const float* __restrict__ cand, Slot* __restrict__ slot,
                     mpmi_selection* __restrict__ out, int16_t* __restrict__ fv_out, RecheckList* __restrict__ rl,
-                    int capacity) {
+                    int capacity, const mpmi_selection* __restrict__ gate) {
   static_assert(kR64Block == 64, "one wave per workgroup");
   constexpr int kPer = kR64Block / 8;  // candidates per workgroup pass
   __shared__ double sK[MPMI_MAX_DIM * 8];
+  // Gated tick (a fallback after a proposal tick): nothing ran, nothing to finalise.
+  if (gate && gate->status == MPMI_OK) return;
   const unsigned int kn = rl->n_keep;
   const int n_keep = (int)(kn < (unsigned int)capacity ? kn : (unsigned int)capacity);
   if (recheck_nothing_kept(md, gp, H, u_user, cand, slot, out, rl, n_keep)) return;
@@ -468,7 +472,7 @@ recheck64_rc_kernel(const ModelDev* __restrict__ md, GenParams gp, int H, const 
 
 hipError_t launch_recheck64(const mpmi_system& sys, const void* model, const mpmi_tick_desc& d, const float* x_t,
                             const float* u_user, const float* cand, void* slot, mpmi_selection* out, int16_t* fv,
-                            void* recheck, int capacity, int grid, hipStream_t st) {
+                            void* recheck, int capacity, int grid, hipStream_t st, const mpmi_selection* gate) {
   GenParams gp;
   gp.seed = d.seed;
   gp.tick = d.tick;
@@ -487,16 +491,16 @@ hipError_t launch_recheck64(const mpmi_system& sys, const void* model, const mpm
     // SIMD: 16 workgroups per compute unit cover 32,768 entries per pass.
     if (small)
       recheck64_rc_kernel<kSmallTrackDeg><<<grid * 4, kR64Block, 0, st>>>(md, gp, d.horizon, x_t, u_user, cand, sl,
-                                                                          out, fv, rl, capacity);
+                                                                          out, fv, rl, capacity, gate);
     else
       recheck64_rc_kernel<kMaxHarm><<<grid * 4, kR64Block, 0, st>>>(md, gp, d.horizon, x_t, u_user, cand, sl, out,
-                                                                    fv, rl, capacity);
+                                                                    fv, rl, capacity, gate);
   } else if (small) {
     recheck64_kernel<kSmallTrackDeg><<<grid, kR64Block, 0, st>>>(md, gp, d.horizon, x_t, u_user, cand, sl, out, fv,
-                                                                 rl, capacity);
+                                                                 rl, capacity, gate);
   } else {
     recheck64_kernel<kMaxHarm><<<grid, kR64Block, 0, st>>>(md, gp, d.horizon, x_t, u_user, cand, sl, out, fv, rl,
-                                                           capacity);
+                                                           capacity, gate);
   }
   return hipGetLastError();
 }

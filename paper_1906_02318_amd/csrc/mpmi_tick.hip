@@ -455,7 +455,7 @@ hipError_t launch_tick(const mpmi_system& sys, const void* model, const mpmi_tic
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !rl) return e;
   return launch_recheck64(sys, model, d, x_t, u_user, cand, slot, out, fv, recheck, recheck_capacity, recheck_grid,
-                          st);
+                          st, gate);
 }
 
 hipError_t launch_rollout(int basis, const void* model, int Nc, int S, int H, const float* x0,

@@ -135,19 +135,21 @@ class LearnedTicker:
 
     def __init__(self, ctx: mpmi.Context, model: mpmi.Model, net: ProposalNet, proposals: int = 2048,
                  horizon: int = 60, fallback_grid=(128, 128), seed: int = 8, loop: int = 1, fallback_loop: int = 2,
-                 lanes_per_cand: int = 1, block: int = 0):
+                 lanes_per_cand: int = 1, block: int = 0, precision: int = mpmi.PREC_FP32):
         self.ctx, self.model, self.net = ctx, model, net
         self.P, self.H = proposals, horizon
         self.lanes, self.block = lanes_per_cand, block
+        self.precision = precision
         self.fallback = mpmi.tick_desc(int(fallback_grid[0] * fallback_grid[1]), horizon, gen=mpmi.GEN_GRID,
-                                       grid=list(fallback_grid), loop=fallback_loop)
+                                       grid=list(fallback_grid), loop=fallback_loop, precision=precision)
         self.seed, self.loop = seed, loop
         self.cand = torch.empty((1, 2, proposals), dtype=torch.float32, device=ctx.device)
         self.head = torch.empty(mpmi.MLP_OUT, dtype=torch.float32, device=ctx.device)
         self.work = mpmi.mlp_workspace(ctx, 1)
 
     def tick(self, x_t, u_user, tick: int, out=None, stream=None):
-        prop = mpmi.tick_desc(self.P, self.H, gen=mpmi.GEN_EXPLICIT, seed=self.seed, tick=tick, loop=self.loop)
+        prop = mpmi.tick_desc(self.P, self.H, gen=mpmi.GEN_EXPLICIT, seed=self.seed, tick=tick, loop=self.loop,
+                              precision=self.precision)
         prop.lanes_per_cand, prop.block = self.lanes, self.block
         return mpmi.mpmi_proposal_tick(self.ctx, self.model, self.net.tensors(), x_t, u_user, prop, self.fallback,
                                        self.cand, self.work, out=out, head_out=self.head, stream=stream)

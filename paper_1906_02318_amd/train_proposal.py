@@ -38,11 +38,13 @@ def race_car_model(ctx):
     return track, mpmi.mpmi_model_pack(ctx, system, K)
 
 
-def evaluate(ctx, model, net, track, n_ticks=1000, seed=8, proposals=2048, log=print):
-    """Learned ticks vs exhaustive 128 x 128 ticks vs 2,048 uniform samples on the same states."""
+def evaluate(ctx, model, net, track, n_ticks=1000, seed=8, proposals=2048, log=print, precision=mpmi.PREC_FP32):
+    """Learned ticks vs exhaustive 128 x 128 ticks vs 2,048 uniform samples on
+    the same states.  Rates are over the ticks the exhaustive grid decides
+    (some grid candidate safe); the fallback rate is over all ticks."""
     xs = synth.race_car_states(n_ticks, track, seed=seed)
     uh = synth.uniform_user(n_ticks, synth.RC_U_LO, synth.RC_U_HI, seed=seed + 100)
-    ticker = LearnedTicker(ctx, model, net, proposals=proposals)
+    ticker = LearnedTicker(ctx, model, net, proposals=proposals, precision=precision)
     exh = mpmi.tick_desc(128 * 128, 60, gen=mpmi.GEN_GRID, grid=[128, 128], loop=3)
     lo, hi = synth.RC_U_LO, synth.RC_U_HI
     res = dict(agree_learned=0, agree_uniform=0, fallback=0, ticks=n_ticks, gap_learned=[], gap_uniform=[],
@@ -70,8 +72,9 @@ def evaluate(ctx, model, net, track, n_ticks=1000, seed=8, proposals=2048, log=p
                 # as good as the exhaustive grid: a safe choice no costlier than the
                 # grid's, up to the cost of half a grid cell's diagonal
                 res[f"asgood_{name}"] += int(s["cost"] <= se["cost"] + HALF_CELL_DIAG_128 ** 2)
-    n_ok = n_ticks
-    out = dict(ticks=n_ticks, interventions=res["interventions"], fallback_rate=res["fallback"] / n_ticks,
+    n_ok = max(1, res["decided"])
+    out = dict(ticks=n_ticks, decided=res["decided"], interventions=res["interventions"],
+               fallback_rate=res["fallback"] / n_ticks,
                agreement_learned=res["agree_learned"] / n_ok, agreement_uniform=res["agree_uniform"] / n_ok,
                as_good_learned=res["asgood_learned"] / max(1, res["decided"]),
                as_good_uniform=res["asgood_uniform"] / max(1, res["decided"]),

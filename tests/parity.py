@@ -202,6 +202,23 @@ def replay_job(job) -> list:
     return [judge(sys, cand, H, u_h, traj, fv_o, r[0], r[1], r[3] if len(r) > 3 else eps, r[2]) for r in results]
 
 
+def decision_job(job) -> list:
+    """One tick's decisions (no first violations from the GPU) against the
+    oracle over the same candidate set: job = (sys, K, x_t, u_h, cand_spec, H,
+    [(sel, eps, label), ...]); each result's ambiguity mask is taken from the
+    oracle's own verdicts."""
+    sys, K, x_t, u_h, spec, H, results = job
+    cand = candidates(sys, spec, u_h)
+    traj, fv_o = o.rollout(sys, K, x_t, cand, H, early_exit=False)
+    out = []
+    for sel, eps, label in results:
+        amb = ambiguous(sys, traj, fv_o, fv_o, eps)
+        r = agreement(sys, cand, H, u_h, fv_o, amb, sel)
+        r["label"] = label
+        out.append(r)
+    return out
+
+
 def oracle_chunk(job):
     """First violations and ambiguity of a slice of one tick's candidates:
     job = (sys, K, x_t, cand_slice, H, fv_gpu_slice, eps), or with a list of

@@ -1,0 +1,81 @@
+"""Learned-proposal ticks against the FP64 oracle, decision by decision, side
+by side with the plain exhaustive form: on 1,000 held-out race-car states,
+with the committed network, the GPU's choice among {u_h} and its own 2,048
+proposals (or, when neither is safe, among the 128 x 128 fallback grid) is
+compared with the oracle's choice over the same candidate set.  Ticks with the
+FP64 re-roll (FP32_RECHECK64, proposals and fallback) are held to the >= 99.9%
+agreement target; plain FP32 ticks are reported beside them (their choices
+inside the FP32 rounding band are FP32's)."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import mpmi_oracle as o
+from paper_1906_02318_amd import mpmi
+from paper_1906_02318_amd.proposal import ASSET, LearnedTicker, ProposalNet
+from tests import workloads as W
+from tests.parity import agreed, decision_job, eps64
+
+pytestmark = pytest.mark.gpu
+
+N_TICKS = 1000
+P = 2048
+GRID = [128, 128]
+EPS32_FP32 = [1e-3, 1e-3]     # plain FP32 ticks: v_y, track (C18-C19)
+EPS32_R64 = [3e-4, 2e-3]      # the race car's re-roll bands (v_y, track)
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def test_learned_ticks_against_the_oracle(oracle_pool):
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    ctx = mpmi.Context(0)
+    K = W.rc_model()[0]
+    so = W.rc_oracle_system(W.rc_track())
+    model = mpmi.mpmi_model_pack(ctx, mpmi.race_car_system(W.track_dict(W.rc_track())),
+                                 torch.tensor(K, dtype=torch.float64, device="cuda"))
+    net = ProposalNet.load(ctx, ASSET)
+    tickers = {name: LearnedTicker(ctx, model, net, proposals=P, fallback_grid=GRID, precision=prec)
+               for name, prec in (("fp32", mpmi.PREC_FP32), ("fp32_recheck64", mpmi.PREC_FP32_RECHECK64))}
+    xs = synth.race_car_states(N_TICKS, W.rc_track(), seed=41)
+    uh = synth.uniform_user(N_TICKS, synth.RC_U_LO, synth.RC_U_HI, seed=42)
+    jobs, fallbacks = [], {n: 0 for n in tickers}
+    for t in range(N_TICKS):
+        x, u = W.f32(xs[t]), W.f32(uh[t])
+        xt = torch.tensor(x, dtype=torch.float32, device="cuda")
+        ut = torch.tensor(u, dtype=torch.float32, device="cuda")
+        per_spec = {}
+        for name, tk in tickers.items():
+            sel = mpmi.decode_selection(tk.tick(xt, ut, tick=t))
+            if sel["n_cand"] == P + 1:
+                props = tk.cand[0].cpu().numpy().astype(np.float64).T  # the GPU's FP32 proposals (P, m)
+                key, spec = ("proposals", props.tobytes()), o.with_user(props, u, 1)
+            else:
+                assert sel["n_cand"] == GRID[0] * GRID[1] + 1, sel
+                fallbacks[name] += 1
+                key, spec = ("grid",), ("grid", GRID)
+            eps = EPS32_FP32 if name == "fp32" else (eps64(so) if sel["status"] != mpmi.OK else EPS32_R64)
+            per_spec.setdefault(key, [spec, []])[1].append((sel, eps, f"{name} tick {t}"))
+        for spec, results in per_spec.values():
+            jobs.append((so, K, x, u, spec, 60, results))
+    out = [r for rs in oracle_pool.map(decision_job, jobs, chunksize=4) for r in rs]
+    summary = {}
+    for name in tickers:
+        rs = [r for r in out if r["label"].startswith(name + " ")]
+        assert len(rs) == N_TICKS
+        kinds = {}
+        for r in rs:
+            kinds[r["kind"]] = kinds.get(r["kind"], 0) + 1
+        kinds["no_safe"] = sum(int(r["status"] != 0) for r in rs)
+        kinds["zero_intervention"] = sum(int(r["zero_intervention"]) for r in rs)
+        summary[name] = (kinds, agreed(kinds) / N_TICKS)
+        log(f"[learned] {name}: {N_TICKS:,} ticks against the oracle over the same candidates: {kinds}, "
+            f"agreement {agreed(kinds) / N_TICKS:.4f}, fallback taken on {fallbacks[name]} ticks")
+    assert summary["fp32_recheck64"][1] >= 0.999
+

@@ -61,10 +61,12 @@ def test_gemm_bf16_matches_fp32_reference(ctx, M_, N_, K_, ta, tb):
     assert err <= 1e-5 * np.sqrt(K_) * 4, (err, M_, N_, K_, ta, tb)
 
 
-@pytest.fixture(scope="module")
-def batch():
+@pytest.fixture(scope="module", params=[512, 300], ids=["b512", "b300_ragged"])
+def batch(request):
+    """A batch of 512 rows, and a ragged one of 300 (not a multiple of the
+    64-row tiles nor of the 8-element chunks of the batch-minor copies)."""
     rng = np.random.default_rng(11)
-    B = 512
+    B = request.param
     X = np.concatenate([synth.race_car_states(B, W.rc_track(), seed=12),
                         synth.uniform_user(B, synth.RC_U_LO, synth.RC_U_HI, seed=13)], axis=1)
     mean, std = X.mean(axis=0), X.std(axis=0)
