@@ -69,6 +69,7 @@ struct Model64 {
   double trk_p[kMaxHarm + 1];       // r_c = P(cos phi) + sin phi * Q(cos phi), FP64 monomial coefficients
   double trk_q[kMaxHarm];
   double sigma[MPMI_MAX_STATE];     // process-noise deviations
+  double Kstep[27][8];              // race car: the rows of K the step reads, in its order (rc_step_row)
   int32_t has_track, comp_mask, n_atoms, pad;
   int8_t atom_kind[MPMI_MAX_ATOMS];
   int8_t atom_var[MPMI_MAX_ATOMS];
@@ -253,6 +254,7 @@ __host__ __device__ constexpr int quad_index(int k, int l, int nw) {
 constexpr int kBbStepOff = 84;
 constexpr int kRcStepOff = 384;
 constexpr int kRcStepRows = 27;
+static_assert(sizeof(Model64::Kstep) == sizeof(double) * 8 * kRcStepRows, "FP64 step table");
 constexpr int kLdsKFloat4 = 137;  // 546 floats rounded up to float4
 
 // Row of K feeding row q of the race-car step table: the 21 state-state

@@ -8,10 +8,10 @@
 // checked step (with its FP32 verdict) instead of publishing it.  Outside the
 // band the FP32 verdicts are exact, so the least key K* the tick published is
 // the FP64 selection's unless a listed candidate of smaller key is safe in
-// FP64.  The tick's last workgroup keeps in the list only the listed
-// candidates whose key precedes K* (every listed one when nothing outside the
-// band is safe, so that the fallback order is exact too); the others keep
-// their FP32 verdicts.  This launch predicts each kept candidate again, from
+// FP64.  A filter launch keeps the listed candidates whose key precedes K*
+// (every listed one when nothing outside the band is safe, so that the
+// fallback order is exact too); the others keep their FP32 verdicts.  The
+// re-roll launch predicts each kept candidate again, from
 // x_t with K, the basis, the process noise and the margins in FP64 (Sec.
 // IV-A's prediction and Sec. IV-B's checks), writes its first violation and
 // publishes its keys.  The last workgroup finalises the selection, which is
@@ -167,8 +167,9 @@ struct Stepper64RaceCar {
       for (int k = 0; k < 6; ++k) L[k][j] = Lj[k];
     }
   }
-  __device__ __forceinline__ void step(const double* __restrict__ Kin, double* x) {
-    const double* K = opaque_coeffs(Kin);
+  // Ks: the step rows in step order (Model64::Kstep).
+  __device__ __forceinline__ void step(const double* __restrict__ Ksin, double* x) {
+    const double* Ks = opaque_coeffs(Ksin);
     double sp, cp;
     sincos(x[2], &sp, &cp);
     double p[kRcStepRows];
@@ -189,7 +190,7 @@ struct Stepper64RaceCar {
     }
 #pragma unroll
     for (int r = 0; r < kRcStepRows; ++r) {
-      const double* row = K + rc_step_row(r) * 8;
+      const double* row = Ks + r * 8;
 #pragma unroll
       for (int j = 0; j < 6; ++j) y[j] = fma(p[r], row[j], y[j]);
     }
@@ -199,10 +200,12 @@ struct Stepper64RaceCar {
 };
 
 // First violation (1..H, or H + 1) of candidate c (c < Nc) predicted in FP64
-// from x_t, one lane.  K: the model's FP64 K (LDS copy or the blob's); at:
-// this lane's LDS column for the described bases.
+// from x_t, one lane.  K: the model's FP64 K (LDS copy or the blob's); Ks:
+// the race car's step rows in step order; at: this lane's LDS column for the
+// described bases.
 template <bool RC, int DEG>
-__device__ int evaluate64(const ModelDev* __restrict__ md, const double* __restrict__ K, const GenParams& gp, int H,
+__device__ int evaluate64(const ModelDev* __restrict__ md, const double* __restrict__ K,
+                          const double* __restrict__ Ks, const GenParams& gp, int H,
                           const float* __restrict__ x_t, const float* __restrict__ u_user,
                           const float* __restrict__ cand, int c, double* at) {
   const Model64* m = &md->m64;
@@ -226,7 +229,7 @@ __device__ int evaluate64(const ModelDev* __restrict__ md, const double* __restr
         u[j] = (j < mi) ? (double)cand_value(gp, md, cand, u_user, c, g, j) : 0.0;
       if constexpr (RC) stp.set_input(K, u);
     }
-    if constexpr (RC) stp.step(K, x);
+    if constexpr (RC) stp.step(Ks, x);
     else step64_described(m, K, n, D, u, x, at);
     if (noisy) add_noise64(m, pre, s, n, x);
     if (!(margin64<DEG>(m, x) > 0.0)) return s;
@@ -243,8 +246,9 @@ __device__ int evaluate64(const ModelDev* __restrict__ md, const double* __restr
 static_assert(kRcStepRows % 3 == 0, "three partial sums over the step rows");
 
 template <int DEG>
-__device__ int evaluate64_rc8(const ModelDev* __restrict__ md, const double* __restrict__ K, const GenParams& gp,
-                              int H, const float* __restrict__ x_t, const float* __restrict__ u_user,
+__device__ int evaluate64_rc8(const ModelDev* __restrict__ md, const double* __restrict__ K,
+                              const double* __restrict__ Ks, const GenParams& gp, int H,
+                              const float* __restrict__ x_t, const float* __restrict__ u_user,
                               const float* __restrict__ cand, int c) {
   const Model64* m = &md->m64;
   const int lane = threadIdx.x & 63;
@@ -286,15 +290,15 @@ __device__ int evaluate64_rc8(const ModelDev* __restrict__ md, const double* __r
     double y0 = fma(Tc, cp, fma(Ts, sp, cu));
 #pragma unroll
     for (int k = 0; k < 6; ++k) y0 = fma(L[k], x[k], y0);
-    // the step rows of column j, read from LDS at every step (held in
-    // registers they would cost a second wave per SIMD)
-    const double* Kc = opaque_coeffs(K) + j;
-    double y1 = p[0] * Kc[rc_step_row(0) * 8], y2 = p[1] * Kc[rc_step_row(1) * 8], y3 = p[2] * Kc[rc_step_row(2) * 8];
+    // the step rows of column j (the step-ordered table), read from LDS at
+    // every step (held in registers they would cost a second wave per SIMD)
+    const double* Kc = opaque_coeffs(Ks) + j;
+    double y1 = p[0] * Kc[0], y2 = p[1] * Kc[8], y3 = p[2] * Kc[16];
 #pragma unroll
     for (int r = 3; r < kRcStepRows; r += 3) {
-      y1 = fma(p[r], Kc[rc_step_row(r) * 8], y1);
-      y2 = fma(p[r + 1], Kc[rc_step_row(r + 1) * 8], y2);
-      y3 = fma(p[r + 2], Kc[rc_step_row(r + 2) * 8], y3);
+      y1 = fma(p[r], Kc[r * 8], y1);
+      y2 = fma(p[r + 1], Kc[(r + 1) * 8], y2);
+      y3 = fma(p[r + 2], Kc[(r + 2) * 8], y3);
     }
     const double y = (y0 + y1) + (y2 + y3);
 #pragma unroll
@@ -415,7 +419,7 @@ recheck64_kernel(const ModelDev* __restrict__ md, GenParams gp, int H, const flo
   __syncthreads();
   for (int e = blockIdx.x * kR64Block + lane; e < n_keep; e += parts * kR64Block) {
     const int c = keep[e] >> 1;
-    const int fv = evaluate64<false, DEG>(md, sK, gp, H, x_t, u_user, cand, c, sAt + lane);
+    const int fv = evaluate64<false, DEG>(md, sK, nullptr, gp, H, x_t, u_user, cand, c, sAt + lane);
     if (fv_out) fv_out[c] = (int16_t)fv;
     const float cst = cost_at(md, gp, cand, u_user, c);
     const bool safe = fv == H + 1;
@@ -439,6 +443,7 @@ recheck64_rc_kernel(const ModelDev* __restrict__ md, GenParams gp, int H, const 
   static_assert(kR64Block == 64, "one wave per workgroup");
   constexpr int kPer = kR64Block / 8;  // candidates per workgroup pass
   __shared__ double sK[MPMI_MAX_DIM * 8];
+  __shared__ double sKs[kRcStepRows * 8];
   // Gated tick (a fallback after a proposal tick): nothing ran, nothing to finalise.
   if (gate && gate->status == MPMI_OK) return;
   const unsigned int kn = rl->n_keep;
@@ -452,10 +457,11 @@ recheck64_rc_kernel(const ModelDev* __restrict__ md, GenParams gp, int H, const 
   unsigned int n_safe = 0;
   const double* Kg = &md->m64.K[0][0];
   for (int e = lane; e < MPMI_MAX_DIM * 8; e += kR64Block) sK[e] = Kg[e];
+  for (int e = lane; e < kRcStepRows * 8; e += kR64Block) sKs[e] = (&md->m64.Kstep[0][0])[e];
   __syncthreads();
   for (int q = blockIdx.x * kPer + (lane >> 3); q < n_keep; q += parts * kPer) {  // uniform per 8-lane group
     const int c = keep[q] >> 1;
-    const int fv = evaluate64_rc8<DEG>(md, sK, gp, H, x_t, u_user, cand, c);
+    const int fv = evaluate64_rc8<DEG>(md, sK, sKs, gp, H, x_t, u_user, cand, c);
     if ((lane & 7) == 0) {
       if (fv_out) fv_out[c] = (int16_t)fv;
       const float cst = cost_at(md, gp, cand, u_user, c);
@@ -549,10 +555,10 @@ multi_recheck64_kernel(const mpmi_loop_desc* __restrict__ loops, const ModelDev*
         if (en.w && c > 0) atomicAdd(&ss->count, 1ull);  // FP32 verdict stands
       } else {
         const int fv = md->sys.basis == MPMI_BASIS_RACE_CAR
-                           ? evaluate64<true, kMaxHarm>(md, &md->m64.K[0][0], gp, H, L->x_t, L->u_user, L->cand,
-                                                        c, sAt + lane)
-                           : evaluate64<false, kMaxHarm>(md, &md->m64.K[0][0], gp, H, L->x_t, L->u_user, L->cand, c,
-                                               sAt + lane);
+                           ? evaluate64<true, kMaxHarm>(md, &md->m64.K[0][0], &md->m64.Kstep[0][0], gp, H,
+                                                        L->x_t, L->u_user, L->cand, c, sAt + lane)
+                           : evaluate64<false, kMaxHarm>(md, &md->m64.K[0][0], nullptr, gp, H, L->x_t, L->u_user,
+                                                         L->cand, c, sAt + lane);
         if (L->first_violation) L->first_violation[c] = (int16_t)fv;
         const bool safe = fv == H + 1;
         if (safe) atomicMin(&ss->key_safe64, safe_key(cst, c));

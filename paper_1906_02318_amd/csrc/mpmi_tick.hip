@@ -248,10 +248,14 @@ __global__ void pack_kernel(mpmi_system sys, int dim, int state_feat0, const dou
     const int f = e >> 3, j = e & 7;
     md->K[f][j] = (f < dim && j < n) ? (float)K[(size_t)f * n + j] : 0.0f;
   }
-  // FP64 K for the re-roll.
+  // FP64 K for the re-roll, and (race car) its step rows in step order.
   for (int e = t; e < MPMI_MAX_DIM * 8; e += blockDim.x) {
     const int f = e >> 3, j = e & 7;
     md->m64.K[f][j] = (f < dim && j < n) ? K[(size_t)f * n + j] : 0.0;
+  }
+  for (int e = t; e < kRcStepRows * 8; e += blockDim.x) {
+    const int q = e >> 3, j = e & 7;
+    md->m64.Kstep[q][j] = (sys.basis == MPMI_BASIS_RACE_CAR && j < n) ? K[(size_t)rc_step_row(q) * n + j] : 0.0;
   }
   // Race-car step table (the rows the per-step contraction reads, in order).
   for (int e = t; e < kStepWords; e += blockDim.x) {

@@ -62,9 +62,11 @@ def normalise(u: np.ndarray, lo, hi) -> np.ndarray:
 
 
 def generate_labels(ctx: mpmi.Context, model: mpmi.Model, states: np.ndarray, users: np.ndarray,
-                    grid=(256, 256), horizon: int = 60, chunk: int = 4096, log=None):
+                    grid=(256, 256), horizon: int = 60, chunk: int = 4096, log=None, precision: int = mpmi.PREC_FP32,
+                    with_index: bool = False):
     """u* (n, 2), status (n,) and n_safe (n,) for every (state, user input) pair,
-    from exhaustive ticks served as the loops of one many-loop launch."""
+    from exhaustive ticks served as the loops of one many-loop launch (and the
+    chosen candidate's index (n,) with with_index)."""
     n = states.shape[0]
     chunk = min(chunk, n, mpmi.MAX_LOOPS)
     dev = ctx.device
@@ -74,10 +76,11 @@ def generate_labels(ctx: mpmi.Context, model: mpmi.Model, states: np.ndarray, us
     N = int(grid[0] * grid[1])
     loops = [dict(model=model, x_t=xb[i], u_user=ub[i], out=ob[i], n_cand=N, horizon=horizon,
                   gen=mpmi.GEN_GRID, grid=list(grid)) for i in range(chunk)]
-    multi = mpmi.Multi(ctx, loops, block=256)
+    multi = mpmi.Multi(ctx, loops, block=256, precision=precision)
     u_star = np.zeros((n, 2))
     status = np.zeros(n, np.int32)
     n_safe = np.zeros(n, np.int64)
+    idx = np.zeros(n, np.int64)
     t0 = time.perf_counter()
     for s in range(0, n, chunk):
         e = min(n, s + chunk)
@@ -91,13 +94,14 @@ def generate_labels(ctx: mpmi.Context, model: mpmi.Model, states: np.ndarray, us
         rec = ob.cpu().numpy()
         raw = rec.view(np.int32).reshape(chunk, -1)
         flt = rec.view(np.float32).reshape(chunk, -1)
+        idx[s:e] = raw[:k, 0]
         status[s:e] = raw[:k, 1]
         n_safe[s:e] = raw[:k, 2]
         u_star[s:e] = flt[:k, 4:6]
         if log and (s // chunk) % 32 == 0:
             log(f"labels {e}/{n} ({time.perf_counter() - t0:.1f} s)")
     multi.close()
-    return u_star, status, n_safe
+    return (u_star, status, n_safe, idx) if with_index else (u_star, status, n_safe)
 
 
 def train(ctx: mpmi.Context, net: ProposalNet, X: np.ndarray, T: np.ndarray, epochs: int, batch: int = 4096,

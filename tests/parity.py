@@ -219,6 +219,28 @@ def decision_job(job) -> list:
     return out
 
 
+def label_job(job) -> dict:
+    """An exhaustive tick's decision checked by the oracle without rolling
+    every candidate: job = (sys, K, x_t, u_h, cand_spec, H, idx, status).  A
+    safe choice is right when the oracle finds it safe and finds unsafe every
+    candidate of lower FP64 cost (candidates of equal cost to 1e-6 relative
+    are accepted, as in the agreement rule); a NO_SAFE record needs the
+    oracle's full selection."""
+    sys, K, x_t, u_h, spec, H, idx, status = job
+    cand = candidates(sys, spec, u_h)
+    cost = o.cost(sys, cand, u_h)
+    if status == o.STATUS_OK:
+        cheaper = np.nonzero(cost < cost[idx] - 1e-6 * max(cost[idx], 1e-30))[0]
+        sub = np.concatenate([[idx], cheaper]).astype(np.int64)
+        _, fv = o.rollout(sys, K, x_t, cand[sub], H, early_exit=True)
+        ok = bool(fv[0] == H + 1) and not np.any(fv[1:] == H + 1)
+        return dict(ok=ok, rolled=int(sub.size), status=status, idx=int(idx), zero=bool(idx == 0))
+    _, fv = o.rollout(sys, K, x_t, cand, H, early_exit=True)
+    ref = o.select(sys, cand, fv, H, u_h)
+    return dict(ok=bool(ref["status"] == o.STATUS_NO_SAFE and ref["idx"] == idx), rolled=int(cand.shape[0]),
+                status=status, idx=int(idx), zero=False)
+
+
 def oracle_chunk(job):
     """First violations and ambiguity of a slice of one tick's candidates:
     job = (sys, K, x_t, cand_slice, H, fv_gpu_slice, eps), or with a list of

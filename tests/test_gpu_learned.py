@@ -15,9 +15,9 @@ import torch
 import synth
 from oracle import mpmi_oracle as o
 from paper_1906_02318_amd import mpmi
-from paper_1906_02318_amd.proposal import ASSET, LearnedTicker, ProposalNet
+from paper_1906_02318_amd.proposal import ASSET, LearnedTicker, ProposalNet, generate_labels
 from tests import workloads as W
-from tests.parity import agreed, decision_job, eps64
+from tests.parity import agreed, decision_job, eps64, label_job
 
 pytestmark = pytest.mark.gpu
 
@@ -79,3 +79,30 @@ def test_learned_ticks_against_the_oracle(oracle_pool):
             f"agreement {agreed(kinds) / N_TICKS:.4f}, fallback taken on {fallbacks[name]} ticks")
     assert summary["fp32_recheck64"][1] >= 0.999
 
+
+
+def test_proposal_labels_against_the_oracle(oracle_pool):
+    """1,000 training labels (state distribution and user seed of the label
+    set; exhaustive 256 x 256 grid, H = 60, served as the loops of many-loop
+    launches in FP32_RECHECK64) verified by the oracle: each label's choice is
+    safe and every cheaper grid candidate unsafe (NO_SAFE labels: the oracle's
+    full selection)."""
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    ctx = mpmi.Context(0)
+    K = W.rc_model()[0]
+    so = W.rc_oracle_system(W.rc_track())
+    model = mpmi.mpmi_model_pack(ctx, mpmi.race_car_system(W.track_dict(W.rc_track())),
+                                 torch.tensor(K, dtype=torch.float64, device="cuda"))
+    n = 1000
+    states = W.f32(synth.race_car_states(n, W.rc_track(), seed=7))
+    users = W.f32(synth.uniform_user(n, synth.RC_U_LO, synth.RC_U_HI, seed=17))
+    grid = [256, 256]
+    u_star, status, n_safe, idx = generate_labels(ctx, model, states, users, grid=grid, chunk=500,
+                                                  precision=mpmi.PREC_FP32_RECHECK64, with_index=True)
+    jobs = [(so, K, states[i], users[i], ("grid", grid), 60, int(idx[i]), int(status[i])) for i in range(n)]
+    res = list(oracle_pool.map(label_job, jobs, chunksize=8))
+    bad = [i for i, r in enumerate(res) if not r["ok"]]
+    log(f"[labels] {n:,} labels (256 x 256 grid, H = 60) verified by the oracle: {n - len(bad)} right, "
+        f"{sum(r['zero'] for r in res)} zero-intervention, {int(np.sum(status != 0))} NO_SAFE, "
+        f"mean candidates rolled by the oracle per label {np.mean([r['rolled'] for r in res]):.0f}")
+    assert not bad, f"labels {bad[:10]} disagree with the oracle"
