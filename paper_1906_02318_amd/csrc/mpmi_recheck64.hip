@@ -64,8 +64,15 @@ __device__ __forceinline__ double margin64(const Model64* __restrict__ m, const 
     }
   }
   if (m->has_track) {
-    const double rho = sqrt(fma(x[0], x[0], x[1] * x[1]));
-    const double inv = 1.0 / rho;
+    // 1 / rho by the hardware reciprocal square root and two Newton steps
+    // (each at least doubles the correct bits), rho = r2 / rho: a shorter
+    // dependent chain than a square root followed by a division.  r2 = 0 or
+    // an infinite coordinate gives NaN (unsafe), as in the FP32 tick.
+    const double r2 = fma(x[0], x[0], x[1] * x[1]);
+    double inv = __builtin_amdgcn_rsq(r2);
+    inv = inv * fma(-0.5 * r2, inv * inv, 1.5);
+    inv = inv * fma(-0.5 * r2, inv * inv, 1.5);
+    const double rho = r2 * inv;
     const double c1 = x[0] * inv, s1 = x[1] * inv;
     double P = m->trk_p[DEG];
 #pragma unroll
@@ -285,11 +292,15 @@ __device__ int evaluate64_rc8(const ModelDev* __restrict__ md, const double* __r
       for (int l = k; l < 6; ++l) p[q++] = x[k] * x[l];
     p[21] = sp * x[3]; p[22] = sp * x[4]; p[23] = sp * x[5];
     p[24] = cp * x[3]; p[25] = cp * x[4]; p[26] = cp * x[5];
-    // four independent partial sums (the chain of one column is short of
+    // independent partial sums (the chain of one column is short of
     // independent work otherwise)
     double y0 = fma(Tc, cp, fma(Ts, sp, cu));
+    double ya = L[0] * x[0], yb = L[1] * x[1];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) y0 = fma(L[k], x[k], y0);
+    for (int k = 2; k < 6; k += 2) {
+      ya = fma(L[k], x[k], ya);
+      yb = fma(L[k + 1], x[k + 1], yb);
+    }
     // the step rows of column j (the step-ordered table), read from LDS at
     // every step (held in registers they would cost a second wave per SIMD)
     const double* Kc = opaque_coeffs(Ks) + j;
@@ -300,7 +311,7 @@ __device__ int evaluate64_rc8(const ModelDev* __restrict__ md, const double* __r
       y2 = fma(p[r + 1], Kc[(r + 1) * 8], y2);
       y3 = fma(p[r + 2], Kc[(r + 2) * 8], y3);
     }
-    const double y = (y0 + y1) + (y2 + y3);
+    const double y = ((y0 + ya) + (yb + y1)) + (y2 + y3);
 #pragma unroll
     for (int k = 0; k < 6; ++k) x[k] = __shfl(y, base + k, 64);
     if (noisy) add_noise64(m, pre, s, 6, x);
