@@ -144,7 +144,9 @@ __device__ __forceinline__ void gemm_store(const GemmArgs& g, const GemmChunk& c
 // A stage is kGemmSub k-steps of 32 (128 values of k): every thread issues
 // the loads of the whole next stage (kGemmSub 16-byte chunks of A and of B)
 // into registers before the MFMAs of the current one, so a product with
-// K = 256 takes two memory round trips instead of eight.  One LDS buffer
+// K = 256 takes two memory round trips instead of eight (a single stage of
+// 256, one round trip, measured the same at batch 4,096: launch and epilogue
+// latency, not the round trips, bound those products).  One LDS buffer
 // (40 KB, several workgroups per CU): the registers are stored into it
 // after a barrier that ends the current stage's reads.
 constexpr int kGemmSub = 4;
@@ -341,66 +343,74 @@ __global__ void mlp_weights_t_kernel(const uint16_t* __restrict__ w16, uint16_t*
 
 // Mixture negative log-likelihood of targets T [B][2] under heads Y [B][80]:
 // per-sample NLL (FP32) and dNLL/dY / B as FP32 and BF16 ([B][80], and the
-// BF16 values again as [80][B]).  One thread per sample.
-__global__ void mdn_loss_kernel(const float* __restrict__ Y, const float* __restrict__ T, int B,
-                                float* __restrict__ nll, float* __restrict__ dY32, uint16_t* __restrict__ dY16,
-                                uint16_t* __restrict__ dY16T, float* __restrict__ loss_sum) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  float contrib = 0.0f;
-  if (b < B) {
-    const float* y = Y + (size_t)b * kMlpOut;
-    const float t0 = T[2 * b], t1 = T[2 * b + 1];
-    float a[kMlpComp], lp[kMlpComp];
-    float lmax = -INFINITY;
-    for (int k = 0; k < kMlpComp; ++k) lmax = fmaxf(lmax, y[5 * k]);
-    float se = 0.0f;
-    for (int k = 0; k < kMlpComp; ++k) se += expf(y[5 * k] - lmax);
-    const float lse_logit = lmax + logf(se);
-    float amax = -INFINITY;
-    for (int k = 0; k < kMlpComp; ++k) {
-      const float l0 = fminf(fmaxf(y[5 * k + 3], kLogSigMin), kLogSigMax);
-      const float l1 = fminf(fmaxf(y[5 * k + 4], kLogSigMin), kLogSigMax);
-      const float d0 = (t0 - y[5 * k + 1]) * expf(-l0);
-      const float d1 = (t1 - y[5 * k + 2]) * expf(-l1);
-      lp[k] = y[5 * k] - lse_logit;
-      a[k] = lp[k] - (0.5f * (d0 * d0 + d1 * d1) + l0 + l1 + kLog2Pi);
-      amax = fmaxf(amax, a[k]);
-    }
-    float sa = 0.0f;
-    for (int k = 0; k < kMlpComp; ++k) sa += expf(a[k] - amax);
-    const float lse = amax + logf(sa);
-    nll[b] = -lse;
-    contrib = -lse;
+// BF16 values again as [80][B]).  One lane per (sample, component): the 16
+// lanes of a sample form the two log-sum-exps by shuffles within their group
+// (a wave holds four samples), so a sample's work is 16 lanes wide instead of
+// a loop over its components.
+__device__ __forceinline__ float group16_max(float v) {
+#pragma unroll
+  for (int o = 8; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 16));
+  return v;
+}
+__device__ __forceinline__ float group16_sum(float v) {
+#pragma unroll
+  for (int o = 8; o > 0; o >>= 1) v += __shfl_xor(v, o, 16);
+  return v;
+}
+
+__global__ void __launch_bounds__(256)
+mdn_loss_kernel(const float* __restrict__ Y, const float* __restrict__ T, int B, float* __restrict__ nll,
+                float* __restrict__ dY32, uint16_t* __restrict__ dY16, uint16_t* __restrict__ dY16T,
+                float* __restrict__ loss_sum) {
+  static_assert(kMlpComp == 16, "one 16-lane group per sample");
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int b = gid >> 4, k = gid & 15;
+  const bool valid = b < B;  // uniform across each 16-lane group
+  const int bb = valid ? b : 0;
+  const float* y = Y + (size_t)bb * kMlpOut + 5 * k;
+  const float logit = y[0];
+  const float lse_logit = [&] {
+    const float lmax = group16_max(logit);
+    return lmax + logf(group16_sum(expf(logit - lmax)));
+  }();
+  const float t0 = T[2 * bb], t1 = T[2 * bb + 1];
+  const float r0 = y[3], r1 = y[4];
+  const float l0 = fminf(fmaxf(r0, kLogSigMin), kLogSigMax);
+  const float l1 = fminf(fmaxf(r1, kLogSigMin), kLogSigMax);
+  const float is0 = expf(-l0), is1 = expf(-l1);
+  const float d0 = (t0 - y[1]) * is0;
+  const float d1 = (t1 - y[2]) * is1;
+  const float lp = logit - lse_logit;
+  const float a = lp - (0.5f * (d0 * d0 + d1 * d1) + l0 + l1 + kLog2Pi);
+  const float amax = group16_max(a);
+  const float lse = amax + logf(group16_sum(expf(a - amax)));
+  const float contrib = (valid && k == 0) ? -lse : 0.0f;
+  if (valid) {
+    if (k == 0) nll[b] = -lse;
     const float inv_b = 1.0f / (float)B;
-    for (int k = 0; k < kMlpComp; ++k) {
-      const float gam = expf(a[k] - lse);
-      const float pi = expf(lp[k]);
-      const float r0 = y[5 * k + 3], r1 = y[5 * k + 4];
-      const float l0 = fminf(fmaxf(r0, kLogSigMin), kLogSigMax);
-      const float l1 = fminf(fmaxf(r1, kLogSigMin), kLogSigMax);
-      const float is0 = expf(-l0), is1 = expf(-l1);
-      const float d0 = (t0 - y[5 * k + 1]) * is0;
-      const float d1 = (t1 - y[5 * k + 2]) * is1;
-      float gk[5];
-      gk[0] = pi - gam;
-      gk[1] = -gam * d0 * is0;
-      gk[2] = -gam * d1 * is1;
-      gk[3] = (r0 > kLogSigMin && r0 < kLogSigMax) ? gam * (1.0f - d0 * d0) : 0.0f;
-      gk[4] = (r1 > kLogSigMin && r1 < kLogSigMax) ? gam * (1.0f - d1 * d1) : 0.0f;
-      for (int q = 0; q < 5; ++q) {
-        const float v = gk[q] * inv_b;
-        dY32[(size_t)b * kMlpOut + 5 * k + q] = v;
-        dY16[(size_t)b * kMlpOut + 5 * k + q] = f2bf(v);
-        dY16T[(size_t)(5 * k + q) * B + b] = f2bf(v);  // [80][B]: the dW product's B operand
-      }
+    const float gam = expf(a - lse);
+    const float pi = expf(lp);
+    float gk[5];
+    gk[0] = pi - gam;
+    gk[1] = -gam * d0 * is0;
+    gk[2] = -gam * d1 * is1;
+    gk[3] = (r0 > kLogSigMin && r0 < kLogSigMax) ? gam * (1.0f - d0 * d0) : 0.0f;
+    gk[4] = (r1 > kLogSigMin && r1 < kLogSigMax) ? gam * (1.0f - d1 * d1) : 0.0f;
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+      const float v = gk[q] * inv_b;
+      const uint16_t h = f2bf(v);
+      dY32[(size_t)b * kMlpOut + 5 * k + q] = v;
+      dY16[(size_t)b * kMlpOut + 5 * k + q] = h;
+      dY16T[(size_t)(5 * k + q) * B + b] = h;  // [80][B]: the dW product's B operand
     }
   }
   // Workgroup sum of the NLL, one atomic per workgroup (reported loss only).
   __shared__ float red[256];
   red[threadIdx.x] = contrib;
   __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+  for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
     __syncthreads();
   }
   if (threadIdx.x == 0 && loss_sum) atomicAdd(loss_sum, red[0] / (float)B);
@@ -753,7 +763,7 @@ hipError_t launch_mlp_grad(const uint16_t* w16, const float* w32, const float* m
   hipError_t e = hipMemsetAsync(w.loss, 0, sizeof(float), st);
   if (e != hipSuccess) return e;
   if ((e = forward_into(w16, w32, mean, stdv, X, B, w, w.Y, true, st)) != hipSuccess) return e;
-  mdn_loss_kernel<<<(B + 255) / 256, 256, 0, st>>>(w.Y, T, B, w.nll, w.dY32, w.dY16, w.dY16T, w.loss);
+  mdn_loss_kernel<<<(B * kMlpComp + 255) / 256, 256, 0, st>>>(w.Y, T, B, w.nll, w.dY32, w.dY16, w.dY16T, w.loss);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   size_t ow[4], ob[4];
   layer_offsets(ow, ob);

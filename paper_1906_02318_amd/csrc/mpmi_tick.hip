@@ -8,7 +8,9 @@
 // contraction is VALU FMAs fed from LDS with no HBM traffic.  The
 // arg-min is a 64-bit key reduced across the wave with shuffles, across the
 // workgroup in LDS, and across workgroups with one atomicMin per workgroup;
-// the last workgroup to finish decodes the key (no second launch).
+// the last workgroup to finish decodes the key (no second launch; an
+// FP32_RECHECK64 tick adds the filter and FP64 re-roll launches of
+// mpmi_recheck64.hip, whose last workgroup decodes it instead).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
