@@ -57,11 +57,12 @@ struct SafetyConsts {
   float trk_eps;
 };
 
-// What the FP64 re-roll reads (MPMI_PREC_FP32_RECHECK64): K and the safety
-// set in FP64, and the basis as atoms and features (filled for the fixed
-// families too, from their descriptions).  Limits are (double)bound -
-// (double)inflation; the track is r0 + sum_k amp_k sin(f_k phi + p_k),
-// expanded by the angle-addition rule with sin p_k, cos p_k formed once.
+// What the FP64 re-roll reads (MPMI_PREC_FP32_RECHECK64): K (and the race
+// car's step rows in step order) and the safety set in FP64, and the basis as
+// atoms and features (filled for the fixed families too, from their
+// descriptions).  Limits are (double)bound - (double)inflation; the track's
+// centreline radius is the FP32 tick's Chebyshev form P(cos phi) +
+// sin phi Q(cos phi) with the FP64 coefficients.
 struct Model64 {
   double K[MPMI_MAX_DIM][8];        // row = feature, col = state component
   double comp_lim[MPMI_MAX_STATE];  // least limit over the boxes on a component; +inf if none
@@ -534,8 +535,8 @@ __device__ __forceinline__ float pick(const float* x, int idx) {
 // partial sum exactly as it is, and the fixed trip count lets all the
 // coefficients arrive in one scalar-load batch.
 constexpr int kSmallTrackDeg = 5;  // the paper's track: harmonics 2..5
-template <int DEG = kMaxHarm>
-__device__ __forceinline__ float track_centre(const ConstSafety* sc, const float* x, float* rho) {
+template <int DEG = kMaxHarm, class SC>
+__device__ __forceinline__ float track_centre(const SC* sc, const float* x, float* rho) {
   static_assert(DEG >= 1 && DEG <= kMaxHarm, "track degree");
   const float r2 = fmaf(x[0], x[0], x[1] * x[1]);
   const float inv = __builtin_amdgcn_rsqf(r2);
@@ -564,8 +565,12 @@ __device__ __forceinline__ const ConstSafety* safety_of(const ModelDev* __restri
 // compile-time register indices): several boxes on one component reduce to
 // the least limit, which gives the same least margin.
 template <int NS, int DEG = kMaxHarm>
-__device__ __forceinline__ float min_margin(const ModelDev* __restrict__ md, const float* x) {
-  const ConstSafety* sc = safety_of(md);
+__device__ __forceinline__ float min_margin(const ModelDev* __restrict__ md, const float* x);
+
+// The same over constants the caller holds (SC: SafetyConsts in registers, or
+// the model's constant-space copy).
+template <int NS, int DEG = kMaxHarm, class SC>
+__device__ __forceinline__ float min_margin_of(const SC* sc, const float* x) {
   float mm = INFINITY;
   bool nan = false;
   const int mask = sc->comp_mask;
@@ -585,6 +590,11 @@ __device__ __forceinline__ float min_margin(const ModelDev* __restrict__ md, con
     mm = fminf(mm, mg);
   }
   return nan ? NAN : mm;
+}
+
+template <int NS, int DEG>
+__device__ __forceinline__ float min_margin(const ModelDev* __restrict__ md, const float* x) {
+  return min_margin_of<NS, DEG>(safety_of(md), x);
 }
 
 // min_margin, also OR-ing into *near whether some constraint's margin lies

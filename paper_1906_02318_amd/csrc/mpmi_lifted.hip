@@ -230,6 +230,9 @@ lifted_tick_kernel(const LiftedDev* __restrict__ ld, GenParams gp, int H, int hp
   constexpr int KP = LiftShape<BASIS>::KP, KC = KP / 4, MS = Dims<BASIS>::M, G = TRAJ ? 2 : 1;
   extern __shared__ float sQ[];  // [G][hpad][KP][4]
   const ModelDev* __restrict__ md = &ld->md;
+  // The constraint constants held in registers for the whole launch (a call
+  // per output tile re-fetching them by scalar loads stalled on each fetch).
+  const SafetyConsts sc = md->safe;
   {
     const float4* src = reinterpret_cast<const float4*>(Qt);
     float4* dst = reinterpret_cast<float4*>(sQ);
@@ -312,7 +315,7 @@ lifted_tick_kernel(const LiftedDev* __restrict__ ld, GenParams gp, int H, int hp
             }
           }
         }
-        const float mg = min_margin<4, DEG>(md, x4);
+        const float mg = min_margin_of<4, DEG>(&sc, x4);
         if (s <= H && !(mg > 0.0f)) fvm[ct] = min(fvm[ct], s);
       }
 #pragma unroll
