@@ -315,8 +315,7 @@ lifted_tick_kernel(const LiftedDev* __restrict__ ld, GenParams gp, int H, int hp
             }
           }
         }
-        const float mg = min_margin_of<4, DEG>(&sc, x4);
-        if (s <= H && !(mg > 0.0f)) fvm[ct] = min(fvm[ct], s);
+        if (s <= H && !all_safe_of<4, DEG>(&sc, x4)) fvm[ct] = min(fvm[ct], s);
       }
 #pragma unroll
       for (int ct = 0; ct < 4; ++ct) {
