@@ -547,8 +547,8 @@ PEAK_BF16_MFMA_TFLOPS = 2500.0
 
 def run_mlp_training(batch: int = 4096, steps: int = 50, warmup: int = 5):
     """One training step of the proposal network (forward, mixture loss,
-    backward, Adam) on the library's kernels, batch 4,096, synthetic rows:
-    step time, and the BF16 matrix-core rate of its dense products."""
+    backward, Adam) on the library's kernels, synthetic rows: step time, and
+    the BF16 matrix-core rate of its dense products."""
     import torch
 
     import synth
@@ -578,8 +578,9 @@ def run_mlp_training(batch: int = 4096, steps: int = 50, warmup: int = 5):
     return {"batch": batch, "step_ms_p50": step_ms, "step_ms_wall": wall * 1e3 / steps,
             "tflops": tflops, "bf16_mfma_peak_tflops": PEAK_BF16_MFMA_TFLOPS,
             "mfma_frac": tflops / PEAK_BF16_MFMA_TFLOPS,
-            "note": "11 dense products of at most 4096 x 256 x 256 (0.5 GFLOP each) plus loss, split-K "
-                    "reductions and Adam: launch- and latency-bound; kernel times in profiles/"}
+            "note": (f"11 dense products of at most {batch} x 256 x 256 plus loss, split-K reductions and "
+                     "Adam; " + ("launch- and latency-bound" if batch <= 8192 else
+                                 "HBM-bound (37-51 flops per byte moved)") + "; kernel times in profiles/")}
 
 
 def run_plain_vs_learned(n_ticks: int = 500, warmup: int = 20):
