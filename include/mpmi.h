@@ -482,6 +482,16 @@ mpmi_status mpmi_generate_candidates(mpmi_ctx ctx, const void* model,
  * Synchronous (default stream, about 15 ms); allocates nothing. */
 mpmi_status mpmi_fp32_fma_rate(mpmi_ctx ctx, double* tflops /* host */);
 
+/* Diagnostic: the sine and cosine the FP64 re-roll of MPMI_PREC_FP32_RECHECK64
+ * applies to the race car's heading (the prediction of Sec. IV-A in FP64),
+ * of n doubles: sn[i], cs[i] = sin, cos of x[i] (all device, n entries,
+ * caller-owned).  Cody and Waite's reduction by pi/2 and the Taylor series
+ * on [-pi/4, pi/4], about an ulp from the correctly rounded values for
+ * |x| < 2^20; larger, infinite and NaN arguments take the HIP library's
+ * sincos.  Asynchronous on `stream`; allocates nothing.  MPMI_EINVAL for
+ * NULL pointers with n > 0 or n < 0. */
+mpmi_status mpmi_sincos64(mpmi_ctx ctx, const double* x, double* sn, double* cs, int32_t n, void* stream);
+
 /* Diagnostic: HBM write ceilings of the trajectory store (GB/s, host), on a
  * caller buffer buf of rows * ld floats (device, 16-byte aligned; contents
  * overwritten): *pattern_gbs for the store pattern of traj[rows][ld] alone

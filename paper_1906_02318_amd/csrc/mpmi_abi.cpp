@@ -688,6 +688,13 @@ mpmi_status mpmi_fp32_fma_rate(mpmi_ctx ctx, double* tflops) {
   return check_hip(ctx, mpmi::measure_fma_rate((float*)ctx->fit_work, tflops), "mpmi_fp32_fma_rate");
 }
 
+mpmi_status mpmi_sincos64(mpmi_ctx ctx, const double* x, double* sn, double* cs, int32_t n, void* stream) {
+  if (!ctx) return MPMI_EINVAL;
+  if (n < 0) return fail(ctx, MPMI_EINVAL, "n=%d must be >= 0", n);
+  if (n > 0 && (!x || !sn || !cs)) return fail(ctx, MPMI_EINVAL, "x, sn and cs must be non-NULL");
+  return check_hip(ctx, mpmi::launch_sincos64(x, sn, cs, n, (hipStream_t)stream), "mpmi_sincos64");
+}
+
 mpmi_status mpmi_write_rates(mpmi_ctx ctx, float* buf, int32_t Nc, int64_t ld, int32_t rows, double* pattern_gbs,
                              double* stream_gbs) {
   if (!ctx) return MPMI_EINVAL;

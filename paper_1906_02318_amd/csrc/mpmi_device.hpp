@@ -514,6 +514,55 @@ struct Stepper<MPMI_BASIS_RACE_CAR> {
 };
 
 // ---------------------------------------------------------------------------
+// sin and cos of a double, for the FP64 re-roll's heading.
+//
+// Cody and Waite's reduction by pi/2 in two FMA steps: k = rint(x 2/pi) and
+// r = (x - k P1) - k P2, with P1 the double nearest pi/2 and P2 the double
+// nearest pi/2 - P1 (each step one rounding; the part of pi/2 below P2 adds
+// at most |k| 2^-107).  On |r| <= pi/4 (+ rounding) the Taylor series of
+// sin through r^17 and of cos through r^16, in z = r^2 (the first omitted
+// terms, r^19/19! and r^18/18!, are below 2^-62 and 2^-57 of the result),
+// then the quadrant k mod 4 swaps and negates.  About an ulp from the
+// correctly rounded values; |x| >= 2^20 (and NaN, +-inf) take the library's
+// sincos, whose reduction holds for any argument.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void sincos_rr64(double x, double* sn, double* cs) {
+  if (!(fabs(x) < 0x1p20)) {
+    sincos(x, sn, cs);
+    return;
+  }
+  constexpr double kTwoOverPi = 0x1.45f306dc9c883p-1;
+  constexpr double kP1 = 0x1.921fb54442d18p+0;
+  constexpr double kP2 = 0x1.1a62633145c07p-54;
+  const double k = rint(x * kTwoOverPi);
+  const double r = fma(-k, kP2, fma(-k, kP1, x));
+  const double z = r * r;
+  // (-1)^n / (2n + 1)!, n = 8 .. 1, and (-1)^n / (2n)!, n = 8 .. 2
+  double ps = 1.0 / 355687428096000.0;
+  ps = fma(ps, z, -1.0 / 1307674368000.0);
+  ps = fma(ps, z, 1.0 / 6227020800.0);
+  ps = fma(ps, z, -1.0 / 39916800.0);
+  ps = fma(ps, z, 1.0 / 362880.0);
+  ps = fma(ps, z, -1.0 / 5040.0);
+  ps = fma(ps, z, 1.0 / 120.0);
+  ps = fma(ps, z, -1.0 / 6.0);
+  double pc = 1.0 / 20922789888000.0;
+  pc = fma(pc, z, -1.0 / 87178291200.0);
+  pc = fma(pc, z, 1.0 / 479001600.0);
+  pc = fma(pc, z, -1.0 / 3628800.0);
+  pc = fma(pc, z, 1.0 / 40320.0);
+  pc = fma(pc, z, -1.0 / 720.0);
+  pc = fma(pc, z, 1.0 / 24.0);
+  const double s = fma(r * z, ps, r);                   // r + r z (-1/6 + ...)
+  const double c = fma(z * z, pc, fma(-0.5, z, 1.0));   // 1 - z/2 + z^2 (1/24 + ...)
+  const int q = (int)k;  // |k| < 2^20
+  const bool swap = (q & 1) != 0;
+  const double sv = swap ? c : s, cv = swap ? s : c;
+  *sn = (q & 2) ? -sv : sv;
+  *cs = ((q + 1) & 2) ? -cv : cv;
+}
+
+// ---------------------------------------------------------------------------
 // Safety margins (Sec. IV-B geometric checks, Sec. V-C-1 inflation)
 // ---------------------------------------------------------------------------
 template <int NS>

@@ -5,8 +5,10 @@
 // disabled in every kernel of the library).  fma_rate_kernel measures the
 // rate such instructions reach on the part: registers only, 16 independent
 // FMA chains per lane, 8 workgroups of 256 lanes per compute unit.
+// sincos64_kernel exposes the FP64 re-roll's sin/cos for accuracy checks.
 #include <hip/hip_runtime.h>
 
+#include "mpmi_device.hpp"
 #include "mpmi_launch.hpp"
 
 namespace mpmi {
@@ -166,6 +168,19 @@ hipError_t measure_read_rates(const void* buf, int Nc, long long ld, int rows, d
   *pattern_gbs = (double)bytes / ((double)best_p * 1e-3) / 1e9;
   *stream_gbs = (double)(n4 * 16) / ((double)best_s * 1e-3) / 1e9;
   return hipSuccess;
+}
+
+// The FP64 re-roll's sin and cos (sincos_rr64) of n doubles.
+__global__ void __launch_bounds__(256) sincos64_kernel(const double* __restrict__ x, double* __restrict__ sn,
+                                                       double* __restrict__ cs, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) sincos_rr64(x[i], &sn[i], &cs[i]);
+}
+
+hipError_t launch_sincos64(const double* x, double* sn, double* cs, int n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  sincos64_kernel<<<(n + 255) / 256, 256, 0, st>>>(x, sn, cs, n);
+  return hipGetLastError();
 }
 
 }  // namespace mpmi

@@ -139,6 +139,8 @@ hipError_t measure_fma_rate(float* sink, double* tflops);
 hipError_t measure_write_rates(void* buf, int Nc, long long ld, int rows, double* pattern_gbs, double* stream_gbs);
 hipError_t measure_read_rates(const void* buf, int Nc, long long ld, int rows, double* pattern_gbs,
                               double* stream_gbs);
+// The FP64 re-roll's sin and cos of n doubles (device arrays).
+hipError_t launch_sincos64(const double* x, double* sn, double* cs, int n, hipStream_t st);
 
 // Many-loop tick (mpmi_multi.hip).
 struct WorkItem;

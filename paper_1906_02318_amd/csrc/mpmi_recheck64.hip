@@ -44,26 +44,56 @@ __device__ __forceinline__ const double* opaque_coeffs(const double* p) {
   return p + off;
 }
 
+// First step s (1-based) of input segment g >= 1: the least s with
+// ((s - 1) S) / H >= g, i.e. ceil(g H / S) + 1 (H + 1 when g >= S).  The
+// horizon loop compares the step with it instead of dividing at every step.
+__device__ __forceinline__ int segment_start(int g, int S, int H) { return (g * H + S - 1) / S + 1; }
+
+// The safety set's FP64 constants, read in one batch (every component's
+// limit, masked afterwards, rather than one load behind each component's
+// test) so that the step can issue the reads early and wait once.
+template <int NS, int DEG>
+struct Safety64 {
+  double lim[NS];
+  double trk_lim, P[DEG + 1], Q[DEG];
+  int mask, has_track;
+};
+template <int NS, int DEG>
+__device__ __forceinline__ Safety64<NS, DEG> safety64(const Model64* __restrict__ m) {
+  Safety64<NS, DEG> sc;
+#pragma unroll
+  for (int k = 0; k < NS; ++k) sc.lim[k] = m->comp_lim[k];
+  sc.trk_lim = m->trk_lim;
+#pragma unroll
+  for (int k = 0; k <= DEG; ++k) sc.P[k] = m->trk_p[k];
+#pragma unroll
+  for (int k = 0; k < DEG; ++k) sc.Q[k] = m->trk_q[k];
+  sc.mask = m->comp_mask;
+  sc.has_track = m->has_track;
+  return sc;
+}
+
 // Least margin of x in FP64 (NaN if any margin is NaN): boxes per component,
 // then the track.  The centreline radius r_c(phi) is the FP32 tick's
 // Chebyshev form in FP64, P(cos phi) + sin phi * Q(cos phi) with the model's
 // FP64 monomial coefficients, (cos phi, sin phi) = (x0, x1) / rho; Horner runs
 // over a fixed DEG >= the model's highest harmonic (zero coefficients above it
-// leave each partial sum unchanged).
-template <int DEG>
-__device__ __forceinline__ double margin64(const Model64* __restrict__ m, const double* x) {
+// leave each partial sum unchanged).  NS: the components that can carry a
+// box (6 for the race car, MPMI_MAX_STATE for the described bases).
+template <int NS, int DEG>
+__device__ __forceinline__ double margin64(const Safety64<NS, DEG>& sc, const double* x) {
+  // A component without a box has limit +inf: its margin is +inf, or NaN
+  // for an infinite or NaN coordinate, which fmin ignores; so the minimum
+  // runs over every component and only the boxed ones can flag a NaN.
   double mm = INFINITY;
   bool nan = false;
-  const int mask = m->comp_mask;
 #pragma unroll
-  for (int k = 0; k < MPMI_MAX_STATE; ++k) {
-    if (mask & (1 << k)) {
-      const double mg = m->comp_lim[k] - fabs(x[k]);
-      nan |= (mg != mg);
-      mm = fmin(mm, mg);
-    }
+  for (int k = 0; k < NS; ++k) {
+    const double mg = sc.lim[k] - fabs(x[k]);
+    nan |= ((sc.mask >> k) & 1) && (mg != mg);
+    mm = fmin(mm, mg);
   }
-  if (m->has_track) {
+  if (sc.has_track) {
     // 1 / rho by the hardware reciprocal square root and two Newton steps
     // (each at least doubles the correct bits), rho = r2 / rho: a shorter
     // dependent chain than a square root followed by a division.  r2 = 0 or
@@ -74,13 +104,13 @@ __device__ __forceinline__ double margin64(const Model64* __restrict__ m, const 
     inv = inv * fma(-0.5 * r2, inv * inv, 1.5);
     const double rho = r2 * inv;
     const double c1 = x[0] * inv, s1 = x[1] * inv;
-    double P = m->trk_p[DEG];
+    double P = sc.P[DEG];
 #pragma unroll
-    for (int k = DEG - 1; k >= 0; --k) P = fma(P, c1, m->trk_p[k]);
-    double Q = m->trk_q[DEG - 1];
+    for (int k = DEG - 1; k >= 0; --k) P = fma(P, c1, sc.P[k]);
+    double Q = sc.Q[DEG - 1];
 #pragma unroll
-    for (int k = DEG - 2; k >= 0; --k) Q = fma(Q, c1, m->trk_q[k]);
-    const double mg = m->trk_lim - fabs(rho - fma(s1, Q, P));
+    for (int k = DEG - 2; k >= 0; --k) Q = fma(Q, c1, sc.Q[k]);
+    const double mg = sc.trk_lim - fabs(rho - fma(s1, Q, P));
     nan |= (mg != mg);
     mm = fmin(mm, mg);
   }
@@ -178,7 +208,7 @@ struct Stepper64RaceCar {
   __device__ __forceinline__ void step(const double* __restrict__ Ksin, double* x) {
     const double* Ks = opaque_coeffs(Ksin);
     double sp, cp;
-    sincos(x[2], &sp, &cp);
+    sincos_rr64(x[2], &sp, &cp);
     double p[kRcStepRows];
     int q = 0;
 #pragma unroll
@@ -226,20 +256,21 @@ __device__ int evaluate64(const ModelDev* __restrict__ md, const double* __restr
   if constexpr (RC) stp.set_input(K, u);
   const bool noisy = md->has_noise != 0;
   const uint64_t pre = noisy ? hash_prefix(gp.seed, gp.tick, (uint64_t)(uint32_t)gp.loop, (uint64_t)c) : 0ull;
-  int gcur = 0;
+  int snext = segment_start(1, S, H);
   for (int s = 1; s <= H; ++s) {
-    const int g = ((s - 1) * S) / H;
-    if (g != gcur) {
-      gcur = g;
+    if (s == snext) {
+      const int g = ((s - 1) * S) / H;
+      snext = segment_start(g + 1, S, H);
 #pragma unroll
       for (int j = 0; j < MPMI_MAX_INPUT; ++j)
         u[j] = (j < mi) ? (double)cand_value(gp, md, cand, u_user, c, g, j) : 0.0;
       if constexpr (RC) stp.set_input(K, u);
     }
+    const Safety64<MPMI_MAX_STATE, DEG> sc = safety64<MPMI_MAX_STATE, DEG>(m);
     if constexpr (RC) stp.step(Ks, x);
     else step64_described(m, K, n, D, u, x, at);
     if (noisy) add_noise64(m, pre, s, n, x);
-    if (!(margin64<DEG>(m, x) > 0.0)) return s;
+    if (!(margin64(sc, x) > 0.0)) return s;
   }
   return H + 1;
 }
@@ -273,17 +304,28 @@ __device__ int evaluate64_rc8(const ModelDev* __restrict__ md, const double* __r
   }
   const bool noisy = md->has_noise != 0;
   const uint64_t pre = noisy ? hash_prefix(gp.seed, gp.tick, (uint64_t)(uint32_t)gp.loop, (uint64_t)c) : 0ull;
-  int gcur = 0;
+  int snext = segment_start(1, S, H);
   for (int s = 1; s <= H; ++s) {
-    const int g = ((s - 1) * S) / H;
-    if (g != gcur) {
-      gcur = g;
+    if (s == snext) {
+      const int g = ((s - 1) * S) / H;
+      snext = segment_start(g + 1, S, H);
       const double d = (double)cand_value(gp, md, cand, u_user, c, g, 0);
       const double a = (double)cand_value(gp, md, cand, u_user, c, g, 1);
       fold_column64(K, j, d, a, sin(d), cos(d), &cu, L, &Ts, &Tc);
     }
+    // The step rows of column j (the step-ordered table), read from LDS at
+    // every step (held in registers across the horizon they spill), all
+    // issued here and awaited together before the contraction: left to the
+    // scheduler, the reads go one round trip per pair of FMAs.
+    double kc[kRcStepRows];
+    {
+      const double* Kc = opaque_coeffs(Ks) + j;
+#pragma unroll
+      for (int r = 0; r < kRcStepRows; ++r) kc[r] = Kc[r * 8];
+    }
+    const Safety64<6, DEG> sc = safety64<6, DEG>(m);
     double sp, cp;
-    sincos(x[2], &sp, &cp);
+    sincos_rr64(x[2], &sp, &cp);
     double p[kRcStepRows];
     int q = 0;
 #pragma unroll
@@ -292,6 +334,8 @@ __device__ int evaluate64_rc8(const ModelDev* __restrict__ md, const double* __r
       for (int l = k; l < 6; ++l) p[q++] = x[k] * x[l];
     p[21] = sp * x[3]; p[22] = sp * x[4]; p[23] = sp * x[5];
     p[24] = cp * x[3]; p[25] = cp * x[4]; p[26] = cp * x[5];
+#pragma unroll
+    for (int r = 0; r < kRcStepRows; ++r) asm volatile("" : "+v"(kc[r]));
     // independent partial sums (the chain of one column is short of
     // independent work otherwise)
     double y0 = fma(Tc, cp, fma(Ts, sp, cu));
@@ -301,21 +345,18 @@ __device__ int evaluate64_rc8(const ModelDev* __restrict__ md, const double* __r
       ya = fma(L[k], x[k], ya);
       yb = fma(L[k + 1], x[k + 1], yb);
     }
-    // the step rows of column j (the step-ordered table), read from LDS at
-    // every step (held in registers they would cost a second wave per SIMD)
-    const double* Kc = opaque_coeffs(Ks) + j;
-    double y1 = p[0] * Kc[0], y2 = p[1] * Kc[8], y3 = p[2] * Kc[16];
+    double y1 = p[0] * kc[0], y2 = p[1] * kc[1], y3 = p[2] * kc[2];
 #pragma unroll
     for (int r = 3; r < kRcStepRows; r += 3) {
-      y1 = fma(p[r], Kc[r * 8], y1);
-      y2 = fma(p[r + 1], Kc[(r + 1) * 8], y2);
-      y3 = fma(p[r + 2], Kc[(r + 2) * 8], y3);
+      y1 = fma(p[r], kc[r], y1);
+      y2 = fma(p[r + 1], kc[r + 1], y2);
+      y3 = fma(p[r + 2], kc[r + 2], y3);
     }
     const double y = ((y0 + ya) + (yb + y1)) + (y2 + y3);
 #pragma unroll
     for (int k = 0; k < 6; ++k) x[k] = __shfl(y, base + k, 64);
     if (noisy) add_noise64(m, pre, s, 6, x);
-    if (!(margin64<DEG>(m, x) > 0.0)) return s;
+    if (!(margin64(sc, x) > 0.0)) return s;
   }
   return H + 1;
 }

@@ -124,6 +124,7 @@ def library() -> ctypes.CDLL:
         "mpmi_tick": (i32, [vp, vp, ctypes.POINTER(TickDesc), vp, vp, vp, vp, vp, vp, i64, vp]),
         "mpmi_generate_candidates": (i32, [vp, vp, ctypes.POINTER(TickDesc), vp, vp, vp, vp]),
         "mpmi_fp32_fma_rate": (i32, [vp, ctypes.POINTER(f64)]),
+        "mpmi_sincos64": (i32, [vp, vp, vp, vp, i32, vp]),
         "mpmi_write_rates": (i32, [vp, vp, i32, i64, i32, ctypes.POINTER(f64), ctypes.POINTER(f64)]),
         "mpmi_read_rates": (i32, [vp, vp, i32, i64, i32, ctypes.POINTER(f64), ctypes.POINTER(f64)]),
         "mpmi_multi_create": (i32, [vp, ctypes.POINTER(LoopDesc), i32, ctypes.POINTER(MultiConfig), ctypes.POINTER(vp)]),
@@ -693,6 +694,14 @@ def mpmi_fp32_fma_rate(ctx: Context) -> float:
     r = ctypes.c_double(0.0)
     ctx.check(ctx.lib.mpmi_fp32_fma_rate(ctx.handle, ctypes.byref(r)))
     return r.value
+
+
+def mpmi_sincos64(ctx: Context, x, sn, cs, stream=None) -> None:
+    """sn, cs = sin, cos of x (float64 device tensors of equal size) by the FP64 re-roll's function."""
+    n = x.numel()
+    for t, name in ((x, "x"), (sn, "sn"), (cs, "cs")):
+        _need(t, name, torch.float64, n, device=ctx.device)
+    ctx.check(ctx.lib.mpmi_sincos64(ctx.handle, _ptr(x), _ptr(sn), _ptr(cs), n, _stream(stream)))
 
 
 def decode_selection(rec) -> dict:

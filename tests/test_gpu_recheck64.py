@@ -224,3 +224,38 @@ def test_fp32_margin_error_within_the_recheck_bands(ctx, name):
         f"(bands {eps}); kernel least-margin error {worst_least:.3e}")
     assert np.all(worst_state <= 0.5 * eps)
     assert worst_least <= 0.5 * eps.max()
+
+
+def test_reroll_sincos_accuracy(ctx):
+    """The FP64 re-roll's sin/cos of the heading (mpmi_sincos64): within 2
+    ulp of NumPy's over ordinary headings, arguments next to multiples of
+    pi/2 (where the reduction cancels), tiny and signed-zero arguments, and
+    the library path (|x| >= 2^20, infinities, NaN)."""
+    rng = np.random.default_rng(31)
+    k = rng.integers(-60, 61, size=20000).astype(np.float64)
+    delta = rng.choice([-1.0, 1.0], size=k.size) * 10.0 ** rng.uniform(-14, -2, size=k.size)
+    finite = np.concatenate([
+        rng.uniform(-30.0, 30.0, size=200000),
+        k * (np.pi / 2) + delta,
+        np.array([0.0, -0.0, 1e-300, -1e-300, 1e-20, -1e-8, np.pi / 4, -np.pi / 4, 3 * np.pi / 4,
+                  2.0 ** 20 - 1.0, 2.0 ** 20, -(2.0 ** 20), 1e6, -1e10, 1e300]),
+    ])
+    special = np.array([np.nan, np.inf, -np.inf])
+    x = np.concatenate([finite, special])
+    xd = dev(x, torch.float64)
+    sn = torch.empty_like(xd)
+    cs = torch.empty_like(xd)
+    mpmi.mpmi_sincos64(ctx, xd, sn, cs)
+    torch.cuda.synchronize()
+    s, c = sn.cpu().numpy(), cs.cpu().numpy()
+    nf = finite.size
+    rs, rc = np.sin(finite), np.cos(finite)
+    es = np.abs(s[:nf] - rs) / np.spacing(np.abs(rs))
+    ec = np.abs(c[:nf] - rc) / np.spacing(np.abs(rc))
+    log(f"[sincos64] {nf} arguments: max error sin {es.max():.2f} ulp, cos {ec.max():.2f} ulp; "
+        f"mean {es.mean():.3f} / {ec.mean():.3f} ulp")
+    assert es.max() <= 2.0 and ec.max() <= 2.0
+    assert s[nf - 15] == 0.0 and c[nf - 15] == 1.0  # x = 0 exactly
+    assert np.all(np.isnan(s[nf:])) and np.all(np.isnan(c[nf:]))
+    with pytest.raises(mpmi.MpmiError):
+        ctx.check(ctx.lib.mpmi_sincos64(ctx.handle, None, None, None, 4, None))
