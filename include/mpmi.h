@@ -624,8 +624,9 @@ void mpmi_graph_destroy(void* graph_exec);
  * clamped to [-7, 2].  Parameters: one flat vector of MPMI_MLP_PARAMS values,
  * per layer W [in][out] row-major then b [out], layers in order.  Products
  * use the BF16 copy of the weights with FP32 accumulation; biases and the
- * Adam state are FP32.  Workspace: caller-allocated device memory of
- * mlp_workspace_bytes(B) bytes (256-byte aligned).
+ * Adam state are FP32; w_bf16 16-byte aligned (the products read it in
+ * 16-byte chunks; MPMI_EINVAL otherwise).  Workspace: caller-allocated
+ * device memory of mlp_workspace_bytes(B) bytes (256-byte aligned).
  * ------------------------------------------------------------------------- */
 #define MPMI_MLP_IN 8
 #define MPMI_MLP_HIDDEN 256

@@ -955,6 +955,7 @@ size_t mlp_workspace_bytes(int32_t batch) {
 static mpmi_status check_mlp_common(mpmi_ctx ctx, const void* w16, const void* w32, const void* mean,
                                     const void* stdv, int32_t B, void* work, size_t work_bytes) {
   if (!w16 || !w32 || !mean || !stdv) return fail(ctx, MPMI_EINVAL, "weights, in_mean and in_std must be non-NULL");
+  if (!aligned(w16, 16)) return fail(ctx, MPMI_EINVAL, "w_bf16 must be 16-byte aligned");
   if (B < 1 || B > MPMI_MLP_MAX_BATCH) return fail(ctx, MPMI_EINVAL, "batch %d out of 1..%d", B, MPMI_MLP_MAX_BATCH);
   if (!work || !aligned(work, 256)) return fail(ctx, MPMI_EINVAL, "workspace must be non-NULL and 256-byte aligned");
   if (work_bytes < mpmi::mlp_workspace_bytes(B))

@@ -7,13 +7,17 @@
 // normalised to [-1, 1]^2.  Weights are BF16 (FP32 master copy for Adam);
 // every product accumulates in FP32.
 //
-// The dense products run on BF16 matrix cores (v_mfma_f32_16x16x32_bf16):
-// a 256-thread workgroup computes a 64 x 64 tile of C = op(A) op(B), each wave
-// a 32 x 32 quarter as 2 x 2 MFMA blocks, with 64 x 32 slices of A and B
-// staged through LDS per k-step (transposed operands are transposed while
-// staging, so one kernel serves the forward product and both backward ones).
+// The dense products run on BF16 matrix cores (v_mfma_f32_16x16x32_bf16).
+// The forward and the backward dX products run layer after layer inside two
+// fused row-block kernels (activations in LDS).  The weight-gradient
+// products, contractions over the batch, run as split-K tiles: a 256-thread
+// workgroup computes a 64 x 64 tile of C = op(A) op(B), each wave a 32 x 32
+// quarter as 2 x 2 MFMA blocks, with 64 x 32 slices of A and B staged through
+// LDS per k-step (transposed operands are transposed while staging).
 #include <hip/hip_runtime.h>
 #include <hip/hip_bf16.h>
+
+#include <algorithm>
 
 #include "mpmi_device.hpp"
 #include "mpmi_launch.hpp"
@@ -23,7 +27,6 @@ namespace mpmi {
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
-constexpr int kGelu = 1, kLinear = 2, kGeluBack = 3, kPlain = 4;
 constexpr float kGeluC = 0.7978845608028654f;  // sqrt(2/pi)
 constexpr float kGeluA = 0.044715f;
 
@@ -44,22 +47,12 @@ struct GemmArgs {
   int M, N, K;
   int lda, ldb;
   int ta, tb;          // A(m,k) = ta ? A[k*lda+m] : A[m*lda+k]; B(k,n) = tb ? B[n*ldb+k] : B[k*ldb+n]
-  const float* bias;   // [N] or NULL
-  const float* zin;    // kGeluBack: pre-activation [M][N] FP32
-  float* out_f32;      // [M][N] or NULL
-  uint16_t* out_bf16;  // [M][N] or NULL
-  uint16_t* out_bf16_t;  // the BF16 output transposed, [N][ldt], or NULL
-  int ldt;
-  // Split-K (kPlain only): gridDim.z parts of ksplit rows of K each write
-  // FP32 partial products to part[z][M][N]; colsum (or NULL), an FP32
-  // [K][N] matrix whose column sums over each part's K range go to
-  // part_cs[z][N] (the bias gradient of a dW product).
+  float* out_f32;      // [M][N] (single part)
+  // Split-K: gridDim.z parts of ksplit rows of K each write FP32 partial
+  // products to part[z][M][N].
   int ksplit;
   float* part;
-  const float* colsum;
-  float* part_cs;
   bool vec_a, vec_b;   // 16-byte loads allowed (leading dimension a multiple of 8, 16-byte aligned base)
-  bool vec_t;          // 8-byte transposed stores allowed (ldt a multiple of 4, 8-byte aligned base)
 };
 
 // C = op(A) op(B) on v_mfma_f32_16x16x32_bf16.  A 256-thread workgroup owns a
@@ -151,14 +144,15 @@ __device__ __forceinline__ void gemm_store(const GemmArgs& g, const GemmChunk& c
 // after a barrier that ends the current stage's reads.
 constexpr int kGemmSub = 4;
 
-template <int EPI>
-__global__ void __launch_bounds__(256) gemm_bf16_kernel(GemmArgs g) {
+// One 64 x 64 output tile (bx, by) of K part bz; every thread of the
+// workgroup calls it.
+__device__ __forceinline__ void gemm_tile(const GemmArgs& g, int bx, int by, int bz) {
   __shared__ __attribute__((aligned(16))) uint16_t As[kGemmSub][64][kGemmKP];
   __shared__ __attribute__((aligned(16))) uint16_t Bs[kGemmSub][64][kGemmKP];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
-  const int kbeg = blockIdx.z * g.ksplit;
+  const int m0 = by * 64, n0 = bx * 64;
+  const int kbeg = bz * g.ksplit;
   const int kend = min(g.K, kbeg + g.ksplit);
   constexpr int kStage = 32 * kGemmSub;
   f32x4_t acc[2][2];
@@ -201,126 +195,100 @@ __global__ void __launch_bounds__(256) gemm_bf16_kernel(GemmArgs g) {
       __syncthreads();
     }
   }
-  // Bias-gradient partial column sums over this part's K range (dW products:
-  // the workgroups of the first tile row).  Thread t sums rows
-  // kbeg + (t >> 6) + 4 i of column n0 + (t & 63) into four interleaved
-  // accumulators (independent loads in flight); the four row groups are then
-  // added in a fixed order.
-  if (EPI == kPlain && g.colsum && blockIdx.y == 0) {  // uniform across the workgroup
-    __shared__ float cs[4][64];
-    const int col = t & 63, rg = t >> 6;
-    const int n = n0 + col;
-    float a[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-    if (n < g.N) {
-      int k = kbeg + rg;
-      for (; k + 12 < kend; k += 16) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) a[q] += g.colsum[(size_t)(k + 4 * q) * g.N + n];
-      }
-      for (int q = 0; k < kend; k += 4, ++q) a[q & 3] += g.colsum[(size_t)k * g.N + n];
-    }
-    cs[rg][col] = (a[0] + a[1]) + (a[2] + a[3]);
-    __syncthreads();
-    if (t < 64 && n0 + t < g.N)
-      g.part_cs[(size_t)blockIdx.z * g.N + n0 + t] = (cs[0][t] + cs[1][t]) + (cs[2][t] + cs[3][t]);
-  }
-  // D fragment: lane holds column (lane & 15), rows (lane >> 4) * 4 + r.  The
-  // transposed BF16 copy (when asked for) takes the lane's four rows of one
-  // column as one 8-byte store.
-  float* dst = (EPI == kPlain && g.part) ? g.part + (size_t)blockIdx.z * g.M * g.N : nullptr;
+  // D fragment: lane holds column (lane & 15), rows (lane >> 4) * 4 + r.
+  float* dst = g.part ? g.part + (size_t)bz * g.M * g.N : g.out_f32;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       const int mb = m0 + wm * 32 + i * 16 + (lane >> 4) * 4;
       const int n = n0 + wn * 32 + j * 16 + (lane & 15);
-      uint16_t hb[4] = {0, 0, 0, 0};
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int m = mb + r;
-        if (m >= g.M || n >= g.N) continue;
-        float v = acc[i][j][r];
-        const size_t o = (size_t)m * g.N + n;
-        if (dst) {
-          dst[o] = v;
-        } else if (EPI == kGelu) {
-          v += g.bias[n];
-          if (g.out_f32) g.out_f32[o] = v;
-          hb[r] = f2bf(gelu_f(v));
-          g.out_bf16[o] = hb[r];
-        } else if (EPI == kLinear) {
-          v += g.bias[n];
-          if (g.out_f32) g.out_f32[o] = v;
-          hb[r] = f2bf(v);
-          if (g.out_bf16) g.out_bf16[o] = hb[r];
-        } else if (EPI == kGeluBack) {
-          v *= gelu_grad_f(g.zin[o]);
-          if (g.out_f32) g.out_f32[o] = v;
-          hb[r] = f2bf(v);
-          g.out_bf16[o] = hb[r];
-        } else {
-          if (g.out_f32) g.out_f32[o] = v;
-          hb[r] = f2bf(v);
-          if (g.out_bf16) g.out_bf16[o] = hb[r];
-        }
-      }
-      if (!dst && g.out_bf16_t && n < g.N) {
-        uint16_t* tp = g.out_bf16_t + (size_t)n * g.ldt + mb;
-        if (g.vec_t && mb + 3 < g.M) {
-          *reinterpret_cast<uint2*>(tp) =
-              make_uint2((uint32_t)hb[0] | ((uint32_t)hb[1] << 16), (uint32_t)hb[2] | ((uint32_t)hb[3] << 16));
-        } else {
-#pragma unroll
-          for (int r = 0; r < 4; ++r)
-            if (mb + r < g.M) tp[r] = hb[r];
-        }
-      }
+      for (int r = 0; r < 4; ++r)
+        if (mb + r < g.M && n < g.N) dst[(size_t)(mb + r) * g.N + n] = acc[i][j][r];
     }
 }
 
-// Split-K reduction: out[e] = sum over parts z (in order) of part[z][e],
-// e < M N; then cs_out[n] = sum over z of part_cs[z][n] when cs_out is set.
-__global__ void splitk_reduce_kernel(const float* __restrict__ part, int parts, int MN, float* __restrict__ out,
-                                     const float* __restrict__ part_cs, int N, float* __restrict__ cs_out) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < MN) {
+__global__ void __launch_bounds__(256) gemm_bf16_kernel(GemmArgs g) { gemm_tile(g, blockIdx.x, blockIdx.y, blockIdx.z); }
+
+// Several independent products in one launch (the weight gradients of every
+// layer): member i owns the grid's z range [zbase[i], zbase[i + 1]) as its
+// K parts; the grid's x and y cover the largest member, and a workgroup past
+// its member's tiles returns at once.
+constexpr int kGemmGroupMax = 4;
+struct GemmGroup {
+  GemmArgs g[kGemmGroupMax];
+  int zbase[kGemmGroupMax + 1];
+  int n;
+};
+
+__global__ void __launch_bounds__(256) gemm_group_kernel(GemmGroup gg) {
+  int i = 0;
+  while (i + 1 < gg.n && (int)blockIdx.z >= gg.zbase[i + 1]) ++i;  // uniform
+  const GemmArgs& g = gg.g[i];
+  if ((int)blockIdx.x * 64 >= g.N || (int)blockIdx.y * 64 >= g.M) return;  // uniform
+  gemm_tile(g, blockIdx.x, blockIdx.y, blockIdx.z - gg.zbase[i]);
+}
+
+// The split-K reductions of a GemmGroup in one launch.  The grid's first
+// wblocks workgroups take the weight elements, one thread each: member i
+// owns elements [wbase[i], wbase[i + 1]), out[e] = sum over parts z, in
+// order, of part[z][e].  The rest take the bias columns, one wave each:
+// member i owns columns [cbase[i], cbase[i + 1]), cs_out[n] = sum over row
+// blocks r of cs_part[r cs_ld + n], lane l summing blocks l, l + 64, ... in
+// order and the lanes then combined by a fixed butterfly.
+struct ReduceGroup {
+  const float* part[kGemmGroupMax];
+  const float* cs_part[kGemmGroupMax];
+  float* out[kGemmGroupMax];
+  float* cs_out[kGemmGroupMax];
+  int parts[kGemmGroupMax], cs_parts[kGemmGroupMax], cs_ld[kGemmGroupMax];
+  int wbase[kGemmGroupMax + 1], cbase[kGemmGroupMax + 1];
+  int wblocks, n;
+};
+
+__global__ void __launch_bounds__(256) splitk_reduce_group_kernel(ReduceGroup rg) {
+  if ((int)blockIdx.x < rg.wblocks) {
+    const int e0 = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e0 >= rg.wbase[rg.n]) return;
+    int i = 0;
+    while (i + 1 < rg.n && e0 >= rg.wbase[i + 1]) ++i;
+    const int e = e0 - rg.wbase[i], MN = rg.wbase[i + 1] - rg.wbase[i], parts = rg.parts[i];
     float s = 0.0f;
-    for (int z = 0; z < parts; ++z) s += part[(size_t)z * MN + e];
-    out[e] = s;
-  } else if (cs_out && e < MN + N) {
-    const int n = e - MN;
-    float s = 0.0f;
-    for (int z = 0; z < parts; ++z) s += part_cs[(size_t)z * N + n];
-    cs_out[n] = s;
+    for (int z = 0; z < parts; ++z) s += rg.part[i][(size_t)z * MN + e];
+    rg.out[i][e] = s;
+    return;
   }
+  const int c0 = ((int)blockIdx.x - rg.wblocks) * 4 + (int)(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (c0 >= rg.cbase[rg.n]) return;  // uniform per wave
+  int i = 0;
+  while (i + 1 < rg.n && c0 >= rg.cbase[i + 1]) ++i;
+  const int n = c0 - rg.cbase[i], ld = rg.cs_ld[i], cp = rg.cs_parts[i];
+  float s = 0.0f;
+  for (int r = lane; r < cp; r += 64) s += rg.cs_part[i][(size_t)r * ld + n];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if (lane == 0) rg.cs_out[i][n] = s;
+}
+
+// Sets a product's derived fields (16-byte load flags, K part size for
+// `splits` parts rounded to 32-row steps) and returns the number of parts.
+static int gemm_prepare(GemmArgs& g, int splits) {
+  g.vec_a = g.lda % 8 == 0 && ((uintptr_t)g.A & 15) == 0;
+  g.vec_b = g.ldb % 8 == 0 && ((uintptr_t)g.B & 15) == 0;
+  if (splits < 1) splits = 1;
+  g.ksplit = (((g.K + splits - 1) / splits) + 31) / 32 * 32;
+  return (g.K + g.ksplit - 1) / g.ksplit;
 }
 
 // Launches op(A) op(B) in `splits` parts of the K range (rounded to 32-row
 // steps; *parts_out receives the number of parts launched).
-template <int EPI>
 static hipError_t gemm(GemmArgs g, hipStream_t st, int splits = 1, int* parts_out = nullptr) {
-  g.vec_a = g.lda % 8 == 0 && ((uintptr_t)g.A & 15) == 0;
-  g.vec_b = g.ldb % 8 == 0 && ((uintptr_t)g.B & 15) == 0;
-  g.vec_t = g.ldt % 4 == 0 && ((uintptr_t)g.out_bf16_t & 7) == 0;
-  if (splits < 1) splits = 1;
-  g.ksplit = (((g.K + splits - 1) / splits) + 31) / 32 * 32;
-  splits = (g.K + g.ksplit - 1) / g.ksplit;
+  splits = gemm_prepare(g, splits);
   if (parts_out) *parts_out = splits;
   dim3 grid((g.N + 63) / 64, (g.M + 63) / 64, splits);
-  gemm_bf16_kernel<EPI><<<grid, 256, 0, st>>>(g);
+  gemm_bf16_kernel<<<grid, 256, 0, st>>>(g);
   return hipGetLastError();
-}
-
-// Standardised inputs, BF16: X [B][8] -> H0 [B][8], and H0T [8][B] when set.
-__global__ void mlp_input_kernel(const float* __restrict__ X, const float* __restrict__ mean,
-                                 const float* __restrict__ stdv, int B, uint16_t* __restrict__ H0,
-                                 uint16_t* __restrict__ H0T) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= B * kMlpIn) return;
-  const int j = e % kMlpIn;
-  const uint16_t h = f2bf((X[e] - mean[j]) / stdv[j]);
-  H0[e] = h;
-  if (H0T) H0T[(size_t)j * B + e / kMlpIn] = h;
 }
 
 // The weights of every layer transposed: W_l [din][dout] -> Wt_l [dout][din],
@@ -341,12 +309,7 @@ __global__ void mlp_weights_t_kernel(const uint16_t* __restrict__ w16, uint16_t*
   }
 }
 
-// Mixture negative log-likelihood of targets T [B][2] under heads Y [B][80]:
-// per-sample NLL (FP32) and dNLL/dY / B as FP32 and BF16 ([B][80], and the
-// BF16 values again as [80][B]).  One lane per (sample, component): the 16
-// lanes of a sample form the two log-sum-exps by shuffles within their group
-// (a wave holds four samples), so a sample's work is 16 lanes wide instead of
-// a loop over its components.
+// Max and sum over a 16-lane group (one sample's mixture components).
 __device__ __forceinline__ float group16_max(float v) {
 #pragma unroll
   for (int o = 8; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 16));
@@ -356,64 +319,6 @@ __device__ __forceinline__ float group16_sum(float v) {
 #pragma unroll
   for (int o = 8; o > 0; o >>= 1) v += __shfl_xor(v, o, 16);
   return v;
-}
-
-__global__ void __launch_bounds__(256)
-mdn_loss_kernel(const float* __restrict__ Y, const float* __restrict__ T, int B, float* __restrict__ nll,
-                float* __restrict__ dY32, uint16_t* __restrict__ dY16, uint16_t* __restrict__ dY16T,
-                float* __restrict__ loss_sum) {
-  static_assert(kMlpComp == 16, "one 16-lane group per sample");
-  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
-  const int b = gid >> 4, k = gid & 15;
-  const bool valid = b < B;  // uniform across each 16-lane group
-  const int bb = valid ? b : 0;
-  const float* y = Y + (size_t)bb * kMlpOut + 5 * k;
-  const float logit = y[0];
-  const float lse_logit = [&] {
-    const float lmax = group16_max(logit);
-    return lmax + logf(group16_sum(expf(logit - lmax)));
-  }();
-  const float t0 = T[2 * bb], t1 = T[2 * bb + 1];
-  const float r0 = y[3], r1 = y[4];
-  const float l0 = fminf(fmaxf(r0, kLogSigMin), kLogSigMax);
-  const float l1 = fminf(fmaxf(r1, kLogSigMin), kLogSigMax);
-  const float is0 = expf(-l0), is1 = expf(-l1);
-  const float d0 = (t0 - y[1]) * is0;
-  const float d1 = (t1 - y[2]) * is1;
-  const float lp = logit - lse_logit;
-  const float a = lp - (0.5f * (d0 * d0 + d1 * d1) + l0 + l1 + kLog2Pi);
-  const float amax = group16_max(a);
-  const float lse = amax + logf(group16_sum(expf(a - amax)));
-  const float contrib = (valid && k == 0) ? -lse : 0.0f;
-  if (valid) {
-    if (k == 0) nll[b] = -lse;
-    const float inv_b = 1.0f / (float)B;
-    const float gam = expf(a - lse);
-    const float pi = expf(lp);
-    float gk[5];
-    gk[0] = pi - gam;
-    gk[1] = -gam * d0 * is0;
-    gk[2] = -gam * d1 * is1;
-    gk[3] = (r0 > kLogSigMin && r0 < kLogSigMax) ? gam * (1.0f - d0 * d0) : 0.0f;
-    gk[4] = (r1 > kLogSigMin && r1 < kLogSigMax) ? gam * (1.0f - d1 * d1) : 0.0f;
-#pragma unroll
-    for (int q = 0; q < 5; ++q) {
-      const float v = gk[q] * inv_b;
-      const uint16_t h = f2bf(v);
-      dY32[(size_t)b * kMlpOut + 5 * k + q] = v;
-      dY16[(size_t)b * kMlpOut + 5 * k + q] = h;
-      dY16T[(size_t)(5 * k + q) * B + b] = h;  // [80][B]: the dW product's B operand
-    }
-  }
-  // Workgroup sum of the NLL, one atomic per workgroup (reported loss only).
-  __shared__ float red[256];
-  red[threadIdx.x] = contrib;
-  __syncthreads();
-  for (int st = blockDim.x / 2; st > 0; st >>= 1) {
-    if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0 && loss_sum) atomicAdd(loss_sum, red[0] / (float)B);
 }
 
 // Adam (Kingma & Ba 2015) with bias correction on the FP32 master weights,
@@ -516,6 +421,284 @@ constexpr size_t kMlpB2 = kMlpW2 + (size_t)kMlpHid * kMlpHid;
 constexpr size_t kMlpW3 = kMlpB2 + kMlpHid;
 constexpr size_t kMlpB3 = kMlpW3 + (size_t)kMlpHid * kMlpOut;
 static_assert(kMlpB3 + kMlpOut == MPMI_MLP_PARAMS, "parameter layout");
+
+// ---------------------------------------------------------------------------
+// Fused row-block passes of the training step.  A workgroup owns 32 batch
+// rows and takes them through every layer with the activations in LDS, so a
+// pass is one launch instead of a launch per layer: the forward (inputs
+// standardised, three GELU layers, the linear head) and the backward (the
+// mixture loss, then the three dX products with GELU').  Each product is the
+// block's activations [32 x K] (BF16, LDS) times B (K x N) on
+// v_mfma_f32_16x16x32_bf16, B read from global memory (L2) as 8-value
+// k-chunks straight into the operand registers, wave w taking the output
+// column tiles w, w + 4, ...; per output tile the k-steps run in the order
+// the one-product kernel uses, so results equal the layer-by-layer products.
+// The weight-gradient products (a contraction over the batch) stay separate.
+// ---------------------------------------------------------------------------
+constexpr int kFuseRows = 32;
+constexpr int kFuseLd = 264;  // LDS row stride in BF16: 256 + 8, rows 16 B apart in bank order
+constexpr int kFuseWaves = 16;  // one 16-column output tile per wave for the 256-wide layers
+constexpr int kFuseThreads = 64 * kFuseWaves;
+
+// acc[i][jt] = A[16 i .. 16 i + 15][0 .. K) B[0 .. K)[tile j = wave + 16 jt],
+// Bk(n, k) at W[n * ldw + k] (k-chunks of 8 with k + 8 <= K or k >= K, zero
+// past K); tiles j >= NT are skipped.  A's columns [K, K rounded up to 32)
+// must hold zeros.  Every B chunk of the product is loaded before the first
+// MFMA (one memory round trip per layer; the registers are there, a pass
+// runs few waves per SIMD), then the k-steps run in order.
+template <int K, int NTW>
+__device__ __forceinline__ void rowblock_product(const uint16_t (*A)[kFuseLd], const uint16_t* __restrict__ W,
+                                                 int ldw, int NT, f32x4_t (&acc)[2][NTW]) {
+  constexpr int KS = (K + 31) / 32;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int kq = (lane >> 4) * 8;
+  uint4 bv[KS][NTW];
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+    for (int jt = 0; jt < NTW; ++jt) {
+      const int j = wave + kFuseWaves * jt, k = ks * 32 + kq;
+      const int n = j * 16 + (lane & 15);
+      bv[ks][jt] = (j < NT && k < K) ? *reinterpret_cast<const uint4*>(W + (size_t)n * ldw + k)
+                                     : make_uint4(0u, 0u, 0u, 0u);
+    }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int jt = 0; jt < NTW; ++jt) acc[i][jt] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) {
+    bf16x8_t af[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+      af[i] = *reinterpret_cast<const bf16x8_t*>(&A[i * 16 + (lane & 15)][ks * 32 + kq]);
+#pragma unroll
+    for (int jt = 0; jt < NTW; ++jt) {
+      if (wave + kFuseWaves * jt >= NT) break;  // uniform across the wave
+      const bf16x8_t bf = __builtin_bit_cast(bf16x8_t, bv[ks][jt]);
+#pragma unroll
+      for (int i = 0; i < 2; ++i) acc[i][jt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bf, acc[i][jt], 0, 0, 0);
+    }
+  }
+}
+
+// Four BF16 values of consecutive batch rows b0 .. b0 + 3 (those < B) into
+// a batch-minor row: one 8-byte store when all four are in range and aligned.
+__device__ __forceinline__ void store_rows4(uint16_t* __restrict__ p, int b0, int B, const uint16_t* h) {
+  if (b0 + 3 < B && ((uintptr_t)p & 7) == 0) {
+    *reinterpret_cast<uint2*>(p) =
+        make_uint2((uint32_t)h[0] | ((uint32_t)h[1] << 16), (uint32_t)h[2] | ((uint32_t)h[3] << 16));
+  } else {
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      if (b0 + r < B) p[r] = h[r];
+  }
+}
+
+// One hidden layer of the forward pass (KIN inputs, the transposed weights
+// Wt [256][KIN]): z = h W + b to zout (FP32, [B][256]), GELU(z) in BF16 to
+// the next LDS buffer and, with hT set, batch-minor [256][B].
+template <int KIN>
+__device__ __forceinline__ void fwd_hidden_layer(const uint16_t (*hin)[kFuseLd], uint16_t (*hout)[kFuseLd],
+                                                 const uint16_t* __restrict__ Wt, const float* __restrict__ bias,
+                                                 int r0, int B, float* __restrict__ zout, uint16_t* __restrict__ hT) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  constexpr int NTW = kMlpHid / 16 / kFuseWaves;
+  f32x4_t acc[2][NTW];
+  rowblock_product<KIN, NTW>(hin, Wt, KIN, kMlpHid / 16, acc);
+#pragma unroll
+  for (int jt = 0; jt < NTW; ++jt) {
+    const int n = (wave + kFuseWaves * jt) * 16 + (lane & 15);
+    const float bn = bias[n];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int rb = i * 16 + (lane >> 4) * 4;
+      uint16_t hb[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int b = r0 + rb + r;
+        const float v = acc[i][jt][r] + bn;
+        if (b < B) zout[(size_t)b * kMlpHid + n] = v;
+        hb[r] = f2bf(gelu_f(v));
+        hout[rb + r][n] = hb[r];
+      }
+      if (hT) store_rows4(hT + (size_t)n * B + r0 + rb, r0 + rb, B, hb);
+    }
+  }
+  __syncthreads();
+}
+
+// Forward pass of 32 rows: z1..z3 (FP32 pre-activations, [B][256]) and Y
+// ([B][80]); with hT set, the BF16 activations h0..h3 batch-minor too (the
+// weight-gradient products' operands).  loss_zero (optional): zeroed by the
+// first workgroup, for the backward pass to accumulate into.
+__global__ void __launch_bounds__(kFuseThreads)
+mlp_forward_fused_kernel(const uint16_t* __restrict__ w16t, const float* __restrict__ bias32,
+                         const float* __restrict__ mean, const float* __restrict__ stdv, const float* __restrict__ X,
+                         int B, float* __restrict__ z1, float* __restrict__ z2, float* __restrict__ z3,
+                         float* __restrict__ Y, uint16_t* __restrict__ h0T, uint16_t* __restrict__ h1T,
+                         uint16_t* __restrict__ h2T, uint16_t* __restrict__ h3T, float* __restrict__ loss_zero) {
+  __shared__ __attribute__((aligned(16))) uint16_t hs[2][kFuseRows][kFuseLd];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int r0 = blockIdx.x * kFuseRows;
+  if (loss_zero && blockIdx.x == 0 && t == 0) *loss_zero = 0.0f;
+  // standardised inputs, k 8 .. 31 zero (the first product's K step)
+  for (int e = t; e < kFuseRows * 32; e += kFuseThreads) {
+    const int r = e >> 5, k = e & 31, b = r0 + r;
+    uint16_t v = 0;
+    if (k < kMlpIn && b < B) {
+      v = f2bf((X[(size_t)b * kMlpIn + k] - mean[k]) / stdv[k]);
+      if (h0T) h0T[(size_t)k * B + b] = v;
+    }
+    hs[0][r][k] = v;
+  }
+  __syncthreads();
+  fwd_hidden_layer<kMlpIn>(hs[0], hs[1], w16t + kMlpW0, bias32 + kMlpB0, r0, B, z1, h1T);
+  fwd_hidden_layer<kMlpHid>(hs[1], hs[0], w16t + kMlpW1, bias32 + kMlpB1, r0, B, z2, h2T);
+  fwd_hidden_layer<kMlpHid>(hs[0], hs[1], w16t + kMlpW2, bias32 + kMlpB2, r0, B, z3, h3T);
+  // the head: 80 outputs, five column tiles (waves 0-4), linear
+  f32x4_t acc[2][1];
+  rowblock_product<kMlpHid, 1>(hs[1], w16t + kMlpW3, kMlpHid, kMlpOut / 16, acc);
+#pragma unroll
+  for (int jt = 0; jt < 1; ++jt) {
+    const int j = wave + kFuseWaves * jt;
+    if (j >= kMlpOut / 16) break;
+    const int n = j * 16 + (lane & 15);
+    const float bias = bias32[kMlpB3 + n];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int b = r0 + i * 16 + (lane >> 4) * 4 + r;
+        if (b < B) Y[(size_t)b * kMlpOut + n] = acc[i][jt][r] + bias;
+      }
+  }
+}
+
+// One dX product of the backward pass: layer l with NOUT outputs (W_l
+// [256][NOUT], row-major), dz_{l-1} = (dz_l W_l^T) * gelu'(z_l) from the BF16
+// dz_l in LDS, written BF16 batch-minor [256][B] (o16t) and to the next LDS
+// buffer, and the block's FP32 column sums of dz_{l-1} (its part of the bias
+// gradient of layer l - 1) to csum[256]: per column, the lane's rows in
+// order, then the four lane groups by two butterfly steps.
+template <int NOUT>
+__device__ __forceinline__ void bwd_layer(const uint16_t (*din)[kFuseLd], uint16_t (*dout)[kFuseLd],
+                                          const uint16_t* __restrict__ Wl, const float* __restrict__ zl, int r0,
+                                          int B, uint16_t* __restrict__ o16t, float* __restrict__ csum) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  constexpr int NTW = kMlpHid / 16 / kFuseWaves;
+  f32x4_t acc[2][NTW];
+  rowblock_product<NOUT, NTW>(din, Wl, NOUT, kMlpHid / 16, acc);
+#pragma unroll
+  for (int jt = 0; jt < NTW; ++jt) {
+    const int n = (wave + kFuseWaves * jt) * 16 + (lane & 15);
+    float cs = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int rb = i * 16 + (lane >> 4) * 4;
+      uint16_t hb[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int b = r0 + rb + r;
+        float v = 0.0f;
+        if (b < B) v = acc[i][jt][r] * gelu_grad_f(zl[(size_t)b * kMlpHid + n]);
+        cs += v;
+        hb[r] = f2bf(v);
+        dout[rb + r][n] = hb[r];
+      }
+      store_rows4(o16t + (size_t)n * B + r0 + rb, r0 + rb, B, hb);
+    }
+    cs += __shfl_xor(cs, 16);
+    cs += __shfl_xor(cs, 32);
+    if (lane < 16) csum[n] = cs;
+  }
+  __syncthreads();
+}
+
+// Backward pass of 32 rows: the mixture negative log-likelihood of T [B][2]
+// under Y (per-sample NLL, and its sum / B added into *loss_sum), dNLL/dY / B
+// (BF16 batch-minor [80][B]), then for layers 3, 2, 1 dz_{l-1} = (dz_l W_l^T)
+// * gelu'(z_l), BF16 batch-minor [256][B] at slot l - 1 of dz16T (dz_3 =
+// dNLL/dY).  The block's FP32 column sums of each gradient, its parts of
+// the bias gradients, go to bsum: layer l's ([256], or [80] for l = 3) at
+// bsum + (l nblk + block) 256.  The loss takes one lane per (sample,
+// component): the 16 lanes of a sample form the two log-sum-exps by shuffles
+// within their group.
+__global__ void __launch_bounds__(kFuseThreads)
+mlp_backward_fused_kernel(const uint16_t* __restrict__ w16, const float* __restrict__ Y, const float* __restrict__ T,
+                          int B, const float* __restrict__ z1, const float* __restrict__ z2,
+                          const float* __restrict__ z3, float* __restrict__ nll, uint16_t* __restrict__ dY16T,
+                          uint16_t* __restrict__ dz16T, float* __restrict__ bsum, float* __restrict__ loss_sum) {
+  static_assert(kMlpComp == 16, "one 16-lane group per sample");
+  __shared__ __attribute__((aligned(16))) uint16_t ds[2][kFuseRows][kFuseLd];
+  __shared__ float red[kFuseThreads];
+  __shared__ float dys[kFuseRows][kMlpOut];  // FP32 dNLL/dY of the block, for its column sums
+  const int t = threadIdx.x;
+  const int r0 = blockIdx.x * kFuseRows;
+  const float inv_b = 1.0f / (float)B;
+  float contrib = 0.0f;
+  static_assert(kFuseRows * kMlpComp <= kFuseThreads, "one lane per (sample, component)");
+  if (t < kFuseRows * kMlpComp) {  // uniform per wave
+    const int sl = t >> 4, k = t & 15;
+    const int b = r0 + sl;
+    const bool valid = b < B;  // uniform across each 16-lane group
+    const int bb = valid ? b : 0;
+    const float* y = Y + (size_t)bb * kMlpOut + 5 * k;
+    const float logit = y[0];
+    const float lmax0 = group16_max(logit);
+    const float lse_logit = lmax0 + logf(group16_sum(expf(logit - lmax0)));
+    const float t0 = T[2 * bb], t1 = T[2 * bb + 1];
+    const float q0 = y[3], q1 = y[4];
+    const float l0 = fminf(fmaxf(q0, kLogSigMin), kLogSigMax);
+    const float l1 = fminf(fmaxf(q1, kLogSigMin), kLogSigMax);
+    const float is0 = expf(-l0), is1 = expf(-l1);
+    const float d0 = (t0 - y[1]) * is0;
+    const float d1 = (t1 - y[2]) * is1;
+    const float lp = logit - lse_logit;
+    const float a = lp - (0.5f * (d0 * d0 + d1 * d1) + l0 + l1 + kLog2Pi);
+    const float amax = group16_max(a);
+    const float lse = amax + logf(group16_sum(expf(a - amax)));
+    contrib += (valid && k == 0) ? -lse : 0.0f;
+    float gk[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+    if (valid) {
+      if (k == 0) nll[b] = -lse;
+      const float gam = expf(a - lse);
+      const float pi = expf(lp);
+      gk[0] = pi - gam;
+      gk[1] = -gam * d0 * is0;
+      gk[2] = -gam * d1 * is1;
+      gk[3] = (q0 > kLogSigMin && q0 < kLogSigMax) ? gam * (1.0f - d0 * d0) : 0.0f;
+      gk[4] = (q1 > kLogSigMin && q1 < kLogSigMax) ? gam * (1.0f - d1 * d1) : 0.0f;
+    }
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+      const float v = gk[q] * inv_b;
+      const uint16_t h = f2bf(v);
+      if (valid) dY16T[(size_t)(5 * k + q) * B + b] = h;  // [80][B]: the dW product's B operand
+      ds[0][sl][5 * k + q] = valid ? h : (uint16_t)0;
+      dys[sl][5 * k + q] = valid ? v : 0.0f;
+    }
+  }
+  // the head's K runs to 96 (three k-steps): its last 16 columns are zero
+  for (int e = t; e < kFuseRows * 16; e += kFuseThreads) ds[0][e >> 4][kMlpOut + (e & 15)] = 0;
+  red[t] = contrib;
+  __syncthreads();
+  for (int st = kFuseThreads / 2; st > 0; st >>= 1) {
+    if (t < st) red[t] += red[t + st];
+    __syncthreads();
+  }
+  if (t == 0 && loss_sum) atomicAdd(loss_sum, red[0] / (float)B);
+  const size_t nblk = gridDim.x;
+  if (t < kMlpOut) {  // the head's bias gradient part: rows in order
+    float cs = 0.0f;
+    for (int r = 0; r < kFuseRows; ++r) cs += dys[r][t];
+    bsum[(3 * nblk + blockIdx.x) * kMlpHid + t] = cs;
+  }
+  const size_t slot = (size_t)B * kMlpHid;
+  bwd_layer<kMlpOut>(ds[0], ds[1], w16 + kMlpW3, z3, r0, B, dz16T + 2 * slot, bsum + (2 * nblk + blockIdx.x) * kMlpHid);
+  bwd_layer<kMlpHid>(ds[1], ds[0], w16 + kMlpW2, z2, r0, B, dz16T + slot, bsum + (nblk + blockIdx.x) * kMlpHid);
+  bwd_layer<kMlpHid>(ds[0], ds[1], w16 + kMlpW1, z1, r0, B, dz16T, bsum + blockIdx.x * kMlpHid);
+}
 
 // Forward pass of the one row [x_t; u_user] in a workgroup of 1,024
 // threads, then draws from its head: each of the launch's workgroups runs the
@@ -656,52 +839,51 @@ static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 // parts (1,024 workgroups), each part a chain of at most B / 2,048 k-steps.
 constexpr int kMlpSplits = 64, kMlpSplitRows = 256;
 
-// Activations and their gradients are kept batch-major ([B][width]) for the
-// forward products and the dX products, and batch-minor ([width][B], the "T"
-// copies, written by the same epilogues) for the weight-gradient products,
-// whose contraction runs over the batch: every product then stages operands
-// whose k index is contiguous in memory.
+// The fused passes keep a row block's activations in LDS; what leaves them
+// is what later launches read: the FP32 pre-activations z (GELU' of the
+// backward pass), and the BF16 activations and gradients batch-minor
+// ([width][B], the "T" copies) for the weight-gradient products, whose
+// contraction runs over the batch, so their operands' k index is contiguous
+// in memory.  The gradients dz_0, dz_1, dz_2 of the hidden layers (index l:
+// the input side of layer l + 1) all stay alive until those products, which
+// run together after the backward pass; each layer has its own split-K
+// partial buffers.
 struct MlpWork {
-  uint16_t *h0, *h1, *h2, *h3, *dY16, *dz16;
   uint16_t *w16t, *h0T, *h1T, *h2T, *h3T, *dY16T, *dz16T;
-  float *z1, *z2, *z3, *Y, *dY32, *dz32, *nll, *loss, *row, *part, *part_cs;
+  float *z1, *z2, *z3, *Y, *nll, *loss, *row, *bsum;
+  float* part[4];
 };
+
+constexpr int kMlpDims[5] = {kMlpIn, kMlpHid, kMlpHid, kMlpHid, kMlpOut};
 
 static MlpWork carve(void* base, int B) {
   char* p = (char*)base;
   MlpWork w;
   auto take = [&](size_t bytes) { char* r = p; p += align256(bytes); return (void*)r; };
-  w.h0 = (uint16_t*)take((size_t)B * kMlpIn * 2);
-  w.h1 = (uint16_t*)take((size_t)B * kMlpHid * 2);
-  w.h2 = (uint16_t*)take((size_t)B * kMlpHid * 2);
-  w.h3 = (uint16_t*)take((size_t)B * kMlpHid * 2);
-  w.dY16 = (uint16_t*)take((size_t)B * kMlpOut * 2);
-  w.dz16 = (uint16_t*)take((size_t)B * kMlpHid * 2 * 2);  // two ping-pong halves
   w.w16t = (uint16_t*)take((size_t)kMlpParams * 2);
   w.h0T = (uint16_t*)take((size_t)B * kMlpIn * 2);
   w.h1T = (uint16_t*)take((size_t)B * kMlpHid * 2);
   w.h2T = (uint16_t*)take((size_t)B * kMlpHid * 2);
   w.h3T = (uint16_t*)take((size_t)B * kMlpHid * 2);
   w.dY16T = (uint16_t*)take((size_t)B * kMlpOut * 2);
-  w.dz16T = (uint16_t*)take((size_t)B * kMlpHid * 2 * 2);
+  w.dz16T = (uint16_t*)take((size_t)B * kMlpHid * 2 * 3);  // dz_0, dz_1, dz_2
   w.z1 = (float*)take((size_t)B * kMlpHid * 4);
   w.z2 = (float*)take((size_t)B * kMlpHid * 4);
   w.z3 = (float*)take((size_t)B * kMlpHid * 4);
   w.Y = (float*)take((size_t)B * kMlpOut * 4);
-  w.dY32 = (float*)take((size_t)B * kMlpOut * 4);
-  w.dz32 = (float*)take((size_t)B * kMlpHid * 4 * 2);
   w.nll = (float*)take((size_t)B * 4);
   w.loss = (float*)take(4);
   w.row = (float*)take(kMlpIn * 4);
-  w.part = (float*)take((size_t)kMlpSplits * kMlpHid * kMlpHid * 4);
-  w.part_cs = (float*)take((size_t)kMlpSplits * kMlpHid * 4);
+  // bias-gradient parts: four layers x row blocks x 256 (the head uses 80)
+  w.bsum = (float*)take((size_t)4 * ((B + kFuseRows - 1) / kFuseRows) * kMlpHid * 4);
+  for (int l = 0; l < 4; ++l) w.part[l] = (float*)take((size_t)kMlpSplits * kMlpDims[l] * kMlpDims[l + 1] * 4);
   return w;
 }
 
 size_t mlp_workspace_bytes(int B) {
   char* base = nullptr;
   MlpWork w = carve((void*)base, B);
-  return (size_t)((char*)w.part_cs - base) + align256((size_t)kMlpSplits * kMlpHid * 4);
+  return (size_t)((char*)w.part[3] - base) + align256((size_t)kMlpSplits * kMlpHid * kMlpOut * 4);
 }
 
 // Offsets of (W_l, b_l) in the flat parameter vector.
@@ -716,36 +898,19 @@ static void layer_offsets(size_t* ow, size_t* ob) {
   }
 }
 
-// The forward products read the transposed weights (w.w16t, formed first);
-// with `with_t` the hidden activations are also written batch-minor.
+// The forward pass reads the transposed weights (w.w16t, formed first);
+// with `with_t` the activations are also written batch-minor, and loss_zero
+// (optional) is zeroed for the backward pass.
 static hipError_t forward_into(const uint16_t* w16, const float* bias32, const float* mean, const float* stdv,
-                               const float* X, int B, const MlpWork& w, float* Y, bool with_t, hipStream_t st) {
-  size_t ow[4], ob[4];
-  layer_offsets(ow, ob);
+                               const float* X, int B, const MlpWork& w, float* Y, bool with_t, float* loss_zero,
+                               hipStream_t st) {
   mlp_weights_t_kernel<<<(kMlpParams + 255) / 256, 256, 0, st>>>(w16, w.w16t);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  mlp_input_kernel<<<(B * kMlpIn + 255) / 256, 256, 0, st>>>(X, mean, stdv, B, w.h0, with_t ? w.h0T : nullptr);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  const uint16_t* hin[4] = {w.h0, w.h1, w.h2, w.h3};
-  uint16_t* hout[3] = {w.h1, w.h2, w.h3};
-  uint16_t* hout_t[3] = {w.h1T, w.h2T, w.h3T};
-  float* zout[3] = {w.z1, w.z2, w.z3};
-  const int din[4] = {kMlpIn, kMlpHid, kMlpHid, kMlpHid};
-  for (int l = 0; l < 3; ++l) {
-    GemmArgs g{};
-    g.A = hin[l]; g.B = w.w16t + ow[l]; g.tb = 1; g.M = B; g.N = kMlpHid; g.K = din[l];
-    g.lda = din[l]; g.ldb = din[l]; g.bias = bias32 + ob[l]; g.out_f32 = zout[l]; g.out_bf16 = hout[l];
-    if (with_t) {
-      g.out_bf16_t = hout_t[l];
-      g.ldt = B;
-    }
-    if ((e = gemm<kGelu>(g, st)) != hipSuccess) return e;
-  }
-  GemmArgs g{};
-  g.A = w.h3; g.B = w.w16t + ow[3]; g.tb = 1; g.M = B; g.N = kMlpOut; g.K = kMlpHid;
-  g.lda = kMlpHid; g.ldb = kMlpHid; g.bias = bias32 + ob[3]; g.out_f32 = Y;
-  return gemm<kLinear>(g, st);
+  mlp_forward_fused_kernel<<<(B + kFuseRows - 1) / kFuseRows, kFuseThreads, 0, st>>>(
+      w.w16t, bias32, mean, stdv, X, B, w.z1, w.z2, w.z3, Y, with_t ? w.h0T : nullptr, with_t ? w.h1T : nullptr,
+      with_t ? w.h2T : nullptr, with_t ? w.h3T : nullptr, loss_zero);
+  return hipGetLastError();
 }
 
 // Biases are kept in FP32 (they add to FP32 accumulators): the FP32 master
@@ -753,65 +918,64 @@ static hipError_t forward_into(const uint16_t* w16, const float* bias32, const f
 hipError_t launch_mlp_forward(const uint16_t* w16, const float* w32, const float* mean, const float* stdv,
                               const float* X, int B, float* Y, void* work, hipStream_t st) {
   const MlpWork w = carve(work, B);
-  return forward_into(w16, w32, mean, stdv, X, B, w, Y, false, st);
+  return forward_into(w16, w32, mean, stdv, X, B, w, Y, false, nullptr, st);
 }
 
+// One gradient: weights transposed, the fused forward and backward passes,
+// every layer's weight gradient in one launch and their split-K reductions
+// in another.  The loss accumulates straight into *loss (or the workspace).
 hipError_t launch_mlp_grad(const uint16_t* w16, const float* w32, const float* mean, const float* stdv,
                            const float* X, const float* T, int B, float* grad, float* loss, void* work,
                            hipStream_t st) {
   const MlpWork w = carve(work, B);
-  hipError_t e = hipMemsetAsync(w.loss, 0, sizeof(float), st);
+  float* const lossp = loss ? loss : w.loss;
+  hipError_t e = forward_into(w16, w32, mean, stdv, X, B, w, w.Y, true, lossp, st);
   if (e != hipSuccess) return e;
-  if ((e = forward_into(w16, w32, mean, stdv, X, B, w, w.Y, true, st)) != hipSuccess) return e;
-  mdn_loss_kernel<<<(B * kMlpComp + 255) / 256, 256, 0, st>>>(w.Y, T, B, w.nll, w.dY32, w.dY16, w.dY16T, w.loss);
+  mlp_backward_fused_kernel<<<(B + kFuseRows - 1) / kFuseRows, kFuseThreads, 0, st>>>(
+      w16, w.Y, T, B, w.z1, w.z2, w.z3, w.nll, w.dY16T, w.dz16T, w.bsum, lossp);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   size_t ow[4], ob[4];
   layer_offsets(ow, ob);
-  const int dims[5] = {kMlpIn, kMlpHid, kMlpHid, kMlpHid, kMlpOut};
   const uint16_t* hin_t[4] = {w.h0T, w.h1T, w.h2T, w.h3T};
-  const float* zin[4] = {nullptr, w.z1, w.z2, w.z3};
-  // dz of the current layer (output width dims[l+1]): FP32 for bias sums,
-  // BF16 as operand, batch-major and batch-minor.
-  const float* dz32 = w.dY32;
-  const uint16_t* dz16 = w.dY16;
-  const uint16_t* dz16t = w.dY16T;
-  for (int l = 3; l >= 0; --l) {
-    const int kin = dims[l], nout = dims[l + 1];
-    // dW_l = h_{l-1}^T dz  ([kin][nout]) from the batch-minor copies
-    // (h^T [kin][B] as A, dz^T [nout][B] as the transposed B), split over the
-    // batch, with the bias gradient db_l = column sums of dz (FP32) in the
-    // same parts; both reduced over the parts in order.
-    GemmArgs gw{};
+  // dz of each layer's output, BF16 batch-minor (the operand); layer 3's is
+  // dNLL/dY.
+  const uint16_t* dz16t[4];
+  for (int l = 0; l < 3; ++l) dz16t[l] = w.dz16T + (size_t)l * B * kMlpHid;
+  dz16t[3] = w.dY16T;
+  const int nblk = (B + kFuseRows - 1) / kFuseRows;
+  // Every layer's weight gradient in one launch: dW_l = h_l^T dz_l
+  // ([kin][nout]) from the batch-minor copies (h^T [kin][B] as A, dz^T
+  // [nout][B] as the transposed B), split over the batch; then one launch
+  // reduces every layer's parts in order, and its bias gradient (db_l =
+  // column sums of dz_l) from the backward pass's per-block FP32 sums.
+  int splits = B / kMlpSplitRows;
+  splits = splits < 1 ? 1 : (splits > kMlpSplits ? kMlpSplits : splits);
+  GemmGroup gg{};
+  ReduceGroup rg{};
+  gg.n = rg.n = 4;
+  int mt = 1, nt = 1;
+  for (int l = 0; l < 4; ++l) {
+    const int kin = kMlpDims[l], nout = kMlpDims[l + 1];
+    GemmArgs& gw = gg.g[l];
     gw.A = hin_t[l]; gw.lda = B;
-    gw.B = dz16t; gw.tb = 1; gw.ldb = B;
+    gw.B = dz16t[l]; gw.tb = 1; gw.ldb = B;
     gw.M = kin; gw.N = nout; gw.K = B;
-    gw.part = w.part; gw.colsum = dz32; gw.part_cs = w.part_cs;
-    int splits = B / kMlpSplitRows;
-    splits = splits < 1 ? 1 : (splits > kMlpSplits ? kMlpSplits : splits);
-    int parts = 1;
-    if ((e = gemm<kPlain>(gw, st, splits, &parts)) != hipSuccess) return e;
-    splitk_reduce_kernel<<<(kin * nout + nout + 255) / 256, 256, 0, st>>>(w.part, parts, kin * nout, grad + ow[l],
-                                                                          w.part_cs, nout, grad + ob[l]);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (l == 0) break;
-    // dz_{l-1} = (dz W_l^T) * gelu'(z_{l-1})  ([B][kin])
-    const int half = (l % 2) * B * kMlpHid;
-    GemmArgs gd{};
-    gd.A = dz16; gd.lda = nout;
-    gd.B = w16 + ow[l]; gd.tb = 1; gd.ldb = nout;
-    gd.M = B; gd.N = kin; gd.K = nout;
-    gd.zin = zin[l]; gd.out_f32 = w.dz32 + half; gd.out_bf16 = w.dz16 + half;
-    gd.out_bf16_t = w.dz16T + half; gd.ldt = B;
-    if ((e = gemm<kGeluBack>(gd, st)) != hipSuccess) return e;
-    dz32 = w.dz32 + half;
-    dz16 = w.dz16 + half;
-    dz16t = w.dz16T + half;
+    gw.part = w.part[l];
+    const int parts = gemm_prepare(gw, splits);
+    gg.zbase[l + 1] = gg.zbase[l] + parts;
+    mt = std::max(mt, (kin + 63) / 64);
+    nt = std::max(nt, (nout + 63) / 64);
+    rg.part[l] = w.part[l]; rg.cs_part[l] = w.bsum + (size_t)l * nblk * kMlpHid;
+    rg.out[l] = grad + ow[l]; rg.cs_out[l] = grad + ob[l];
+    rg.parts[l] = parts; rg.cs_parts[l] = nblk; rg.cs_ld[l] = kMlpHid;
+    rg.wbase[l + 1] = rg.wbase[l] + kin * nout;
+    rg.cbase[l + 1] = rg.cbase[l] + nout;
   }
-  if (loss) {
-    e = hipMemcpyAsync(loss, w.loss, sizeof(float), hipMemcpyDeviceToDevice, st);
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
+  rg.wblocks = (rg.wbase[4] + 255) / 256;
+  gemm_group_kernel<<<dim3(nt, mt, gg.zbase[4]), 256, 0, st>>>(gg);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  splitk_reduce_group_kernel<<<rg.wblocks + (rg.cbase[4] + 3) / 4, 256, 0, st>>>(rg);
+  return hipGetLastError();
 }
 
 hipError_t launch_mlp_adam(float* w32, uint16_t* w16, float* m, float* v, const float* grad, int step, float lr,
@@ -851,7 +1015,7 @@ hipError_t launch_gemm_test(const uint16_t* A, const uint16_t* B, int M, int N, 
   g.lda = ta ? M : K;
   g.ldb = tb ? K : N;
   g.out_f32 = C;
-  return gemm<kPlain>(g, st);
+  return gemm(g, st);
 }
 
 }  // namespace mpmi
