@@ -423,19 +423,23 @@ constexpr size_t kMlpB3 = kMlpW3 + (size_t)kMlpHid * kMlpOut;
 static_assert(kMlpB3 + kMlpOut == MPMI_MLP_PARAMS, "parameter layout");
 
 // ---------------------------------------------------------------------------
-// Fused row-block passes of the training step.  A workgroup owns 32 batch
-// rows and takes them through every layer with the activations in LDS, so a
-// pass is one launch instead of a launch per layer: the forward (inputs
-// standardised, three GELU layers, the linear head) and the backward (the
-// mixture loss, then the three dX products with GELU').  Each product is the
-// block's activations [32 x K] (BF16, LDS) times B (K x N) on
-// v_mfma_f32_16x16x32_bf16, B read from global memory (L2) as 8-value
-// k-chunks straight into the operand registers, wave w taking the output
-// column tiles w, w + 4, ...; per output tile the k-steps run in the order
-// the one-product kernel uses, so results equal the layer-by-layer products.
-// The weight-gradient products (a contraction over the batch) stay separate.
+// Fused row-block passes of the training step.  A workgroup owns a block of
+// 16 or 32 batch rows and takes them through every layer with the
+// activations in LDS, so a pass is one launch instead of a launch per layer:
+// the forward (inputs standardised, three GELU layers, the linear head) and
+// the backward (the mixture loss, then the three dX products with GELU').
+// Each product is the block's activations [rows x K] (BF16, LDS) times B
+// (K x N) on v_mfma_f32_16x16x32_bf16, B read from global memory (L2) as
+// 8-value k-chunks straight into the operand registers, wave w of the 16
+// taking the output column tile w (16 columns); per output tile the k-steps
+// run in the order the one-product kernel uses, so results equal the
+// layer-by-layer products.  The weight-gradient products (a contraction over
+// the batch) stay separate.
 // ---------------------------------------------------------------------------
-constexpr int kFuseRows = 32;
+// Block height: 16 rows while the batch has too few 32-row blocks to fill
+// the chip (twice the workgroups, each half the serial work), 32 above (half
+// the weight reads from L2).
+__host__ __device__ constexpr int fuse_rows(int B) { return B < 16384 ? 16 : 32; }
 constexpr int kFuseLd = 264;  // LDS row stride in BF16: 256 + 8, rows 16 B apart in bank order
 constexpr int kFuseWaves = 16;  // one 16-column output tile per wave for the 256-wide layers
 constexpr int kFuseThreads = 64 * kFuseWaves;
@@ -446,9 +450,9 @@ constexpr int kFuseThreads = 64 * kFuseWaves;
 // must hold zeros.  Every B chunk of the product is loaded before the first
 // MFMA (one memory round trip per layer; the registers are there, a pass
 // runs few waves per SIMD), then the k-steps run in order.
-template <int K, int NTW>
+template <int RT, int K, int NTW>
 __device__ __forceinline__ void rowblock_product(const uint16_t (*A)[kFuseLd], const uint16_t* __restrict__ W,
-                                                 int ldw, int NT, f32x4_t (&acc)[2][NTW]) {
+                                                 int ldw, int NT, f32x4_t (&acc)[RT][NTW]) {
   constexpr int KS = (K + 31) / 32;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int kq = (lane >> 4) * 8;
@@ -463,21 +467,21 @@ __device__ __forceinline__ void rowblock_product(const uint16_t (*A)[kFuseLd], c
                                      : make_uint4(0u, 0u, 0u, 0u);
     }
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < RT; ++i)
 #pragma unroll
     for (int jt = 0; jt < NTW; ++jt) acc[i][jt] = f32x4_t{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
   for (int ks = 0; ks < KS; ++ks) {
-    bf16x8_t af[2];
+    bf16x8_t af[RT];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < RT; ++i)
       af[i] = *reinterpret_cast<const bf16x8_t*>(&A[i * 16 + (lane & 15)][ks * 32 + kq]);
 #pragma unroll
     for (int jt = 0; jt < NTW; ++jt) {
       if (wave + kFuseWaves * jt >= NT) break;  // uniform across the wave
       const bf16x8_t bf = __builtin_bit_cast(bf16x8_t, bv[ks][jt]);
 #pragma unroll
-      for (int i = 0; i < 2; ++i) acc[i][jt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bf, acc[i][jt], 0, 0, 0);
+      for (int i = 0; i < RT; ++i) acc[i][jt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bf, acc[i][jt], 0, 0, 0);
     }
   }
 }
@@ -498,20 +502,20 @@ __device__ __forceinline__ void store_rows4(uint16_t* __restrict__ p, int b0, in
 // One hidden layer of the forward pass (KIN inputs, the transposed weights
 // Wt [256][KIN]): z = h W + b to zout (FP32, [B][256]), GELU(z) in BF16 to
 // the next LDS buffer and, with hT set, batch-minor [256][B].
-template <int KIN>
+template <int RT, int KIN>
 __device__ __forceinline__ void fwd_hidden_layer(const uint16_t (*hin)[kFuseLd], uint16_t (*hout)[kFuseLd],
                                                  const uint16_t* __restrict__ Wt, const float* __restrict__ bias,
                                                  int r0, int B, float* __restrict__ zout, uint16_t* __restrict__ hT) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   constexpr int NTW = kMlpHid / 16 / kFuseWaves;
-  f32x4_t acc[2][NTW];
-  rowblock_product<KIN, NTW>(hin, Wt, KIN, kMlpHid / 16, acc);
+  f32x4_t acc[RT][NTW];
+  rowblock_product<RT, KIN, NTW>(hin, Wt, KIN, kMlpHid / 16, acc);
 #pragma unroll
   for (int jt = 0; jt < NTW; ++jt) {
     const int n = (wave + kFuseWaves * jt) * 16 + (lane & 15);
     const float bn = bias[n];
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < RT; ++i) {
       const int rb = i * 16 + (lane >> 4) * 4;
       uint16_t hb[4];
 #pragma unroll
@@ -528,22 +532,24 @@ __device__ __forceinline__ void fwd_hidden_layer(const uint16_t (*hin)[kFuseLd],
   __syncthreads();
 }
 
-// Forward pass of 32 rows: z1..z3 (FP32 pre-activations, [B][256]) and Y
+// Forward pass of a block of ROWS rows: z1..z3 (FP32 pre-activations, [B][256]) and Y
 // ([B][80]); with hT set, the BF16 activations h0..h3 batch-minor too (the
 // weight-gradient products' operands).  loss_zero (optional): zeroed by the
 // first workgroup, for the backward pass to accumulate into.
+template <int ROWS>
 __global__ void __launch_bounds__(kFuseThreads)
 mlp_forward_fused_kernel(const uint16_t* __restrict__ w16t, const float* __restrict__ bias32,
                          const float* __restrict__ mean, const float* __restrict__ stdv, const float* __restrict__ X,
                          int B, float* __restrict__ z1, float* __restrict__ z2, float* __restrict__ z3,
                          float* __restrict__ Y, uint16_t* __restrict__ h0T, uint16_t* __restrict__ h1T,
                          uint16_t* __restrict__ h2T, uint16_t* __restrict__ h3T, float* __restrict__ loss_zero) {
-  __shared__ __attribute__((aligned(16))) uint16_t hs[2][kFuseRows][kFuseLd];
+  constexpr int RT = ROWS / 16;
+  __shared__ __attribute__((aligned(16))) uint16_t hs[2][ROWS][kFuseLd];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int r0 = blockIdx.x * kFuseRows;
+  const int r0 = blockIdx.x * ROWS;
   if (loss_zero && blockIdx.x == 0 && t == 0) *loss_zero = 0.0f;
   // standardised inputs, k 8 .. 31 zero (the first product's K step)
-  for (int e = t; e < kFuseRows * 32; e += kFuseThreads) {
+  for (int e = t; e < ROWS * 32; e += kFuseThreads) {
     const int r = e >> 5, k = e & 31, b = r0 + r;
     uint16_t v = 0;
     if (k < kMlpIn && b < B) {
@@ -553,12 +559,12 @@ mlp_forward_fused_kernel(const uint16_t* __restrict__ w16t, const float* __restr
     hs[0][r][k] = v;
   }
   __syncthreads();
-  fwd_hidden_layer<kMlpIn>(hs[0], hs[1], w16t + kMlpW0, bias32 + kMlpB0, r0, B, z1, h1T);
-  fwd_hidden_layer<kMlpHid>(hs[1], hs[0], w16t + kMlpW1, bias32 + kMlpB1, r0, B, z2, h2T);
-  fwd_hidden_layer<kMlpHid>(hs[0], hs[1], w16t + kMlpW2, bias32 + kMlpB2, r0, B, z3, h3T);
+  fwd_hidden_layer<RT, kMlpIn>(hs[0], hs[1], w16t + kMlpW0, bias32 + kMlpB0, r0, B, z1, h1T);
+  fwd_hidden_layer<RT, kMlpHid>(hs[1], hs[0], w16t + kMlpW1, bias32 + kMlpB1, r0, B, z2, h2T);
+  fwd_hidden_layer<RT, kMlpHid>(hs[0], hs[1], w16t + kMlpW2, bias32 + kMlpB2, r0, B, z3, h3T);
   // the head: 80 outputs, five column tiles (waves 0-4), linear
-  f32x4_t acc[2][1];
-  rowblock_product<kMlpHid, 1>(hs[1], w16t + kMlpW3, kMlpHid, kMlpOut / 16, acc);
+  f32x4_t acc[RT][1];
+  rowblock_product<RT, kMlpHid, 1>(hs[1], w16t + kMlpW3, kMlpHid, kMlpOut / 16, acc);
 #pragma unroll
   for (int jt = 0; jt < 1; ++jt) {
     const int j = wave + kFuseWaves * jt;
@@ -566,7 +572,7 @@ mlp_forward_fused_kernel(const uint16_t* __restrict__ w16t, const float* __restr
     const int n = j * 16 + (lane & 15);
     const float bias = bias32[kMlpB3 + n];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < RT; ++i)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int b = r0 + i * 16 + (lane >> 4) * 4 + r;
@@ -581,20 +587,20 @@ mlp_forward_fused_kernel(const uint16_t* __restrict__ w16t, const float* __restr
 // buffer, and the block's FP32 column sums of dz_{l-1} (its part of the bias
 // gradient of layer l - 1) to csum[256]: per column, the lane's rows in
 // order, then the four lane groups by two butterfly steps.
-template <int NOUT>
+template <int RT, int NOUT>
 __device__ __forceinline__ void bwd_layer(const uint16_t (*din)[kFuseLd], uint16_t (*dout)[kFuseLd],
                                           const uint16_t* __restrict__ Wl, const float* __restrict__ zl, int r0,
                                           int B, uint16_t* __restrict__ o16t, float* __restrict__ csum) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   constexpr int NTW = kMlpHid / 16 / kFuseWaves;
-  f32x4_t acc[2][NTW];
-  rowblock_product<NOUT, NTW>(din, Wl, NOUT, kMlpHid / 16, acc);
+  f32x4_t acc[RT][NTW];
+  rowblock_product<RT, NOUT, NTW>(din, Wl, NOUT, kMlpHid / 16, acc);
 #pragma unroll
   for (int jt = 0; jt < NTW; ++jt) {
     const int n = (wave + kFuseWaves * jt) * 16 + (lane & 15);
     float cs = 0.0f;
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < RT; ++i) {
       const int rb = i * 16 + (lane >> 4) * 4;
       uint16_t hb[4];
 #pragma unroll
@@ -615,7 +621,7 @@ __device__ __forceinline__ void bwd_layer(const uint16_t (*din)[kFuseLd], uint16
   __syncthreads();
 }
 
-// Backward pass of 32 rows: the mixture negative log-likelihood of T [B][2]
+// Backward pass of a block of ROWS rows: the mixture negative log-likelihood of T [B][2]
 // under Y (per-sample NLL, and its sum / B added into *loss_sum), dNLL/dY / B
 // (BF16 batch-minor [80][B]), then for layers 3, 2, 1 dz_{l-1} = (dz_l W_l^T)
 // * gelu'(z_l), BF16 batch-minor [256][B] at slot l - 1 of dz16T (dz_3 =
@@ -624,21 +630,23 @@ __device__ __forceinline__ void bwd_layer(const uint16_t (*din)[kFuseLd], uint16
 // bsum + (l nblk + block) 256.  The loss takes one lane per (sample,
 // component): the 16 lanes of a sample form the two log-sum-exps by shuffles
 // within their group.
+template <int ROWS>
 __global__ void __launch_bounds__(kFuseThreads)
 mlp_backward_fused_kernel(const uint16_t* __restrict__ w16, const float* __restrict__ Y, const float* __restrict__ T,
                           int B, const float* __restrict__ z1, const float* __restrict__ z2,
                           const float* __restrict__ z3, float* __restrict__ nll, uint16_t* __restrict__ dY16T,
                           uint16_t* __restrict__ dz16T, float* __restrict__ bsum, float* __restrict__ loss_sum) {
   static_assert(kMlpComp == 16, "one 16-lane group per sample");
-  __shared__ __attribute__((aligned(16))) uint16_t ds[2][kFuseRows][kFuseLd];
+  constexpr int RT = ROWS / 16;
+  __shared__ __attribute__((aligned(16))) uint16_t ds[2][ROWS][kFuseLd];
   __shared__ float red[kFuseThreads];
-  __shared__ float dys[kFuseRows][kMlpOut];  // FP32 dNLL/dY of the block, for its column sums
+  __shared__ float dys[ROWS][kMlpOut];  // FP32 dNLL/dY of the block, for its column sums
   const int t = threadIdx.x;
-  const int r0 = blockIdx.x * kFuseRows;
+  const int r0 = blockIdx.x * ROWS;
   const float inv_b = 1.0f / (float)B;
   float contrib = 0.0f;
-  static_assert(kFuseRows * kMlpComp <= kFuseThreads, "one lane per (sample, component)");
-  if (t < kFuseRows * kMlpComp) {  // uniform per wave
+  static_assert(ROWS * kMlpComp <= kFuseThreads, "one lane per (sample, component)");
+  if (t < ROWS * kMlpComp) {  // uniform per wave
     const int sl = t >> 4, k = t & 15;
     const int b = r0 + sl;
     const bool valid = b < B;  // uniform across each 16-lane group
@@ -680,7 +688,7 @@ mlp_backward_fused_kernel(const uint16_t* __restrict__ w16, const float* __restr
     }
   }
   // the head's K runs to 96 (three k-steps): its last 16 columns are zero
-  for (int e = t; e < kFuseRows * 16; e += kFuseThreads) ds[0][e >> 4][kMlpOut + (e & 15)] = 0;
+  for (int e = t; e < ROWS * 16; e += kFuseThreads) ds[0][e >> 4][kMlpOut + (e & 15)] = 0;
   red[t] = contrib;
   __syncthreads();
   for (int st = kFuseThreads / 2; st > 0; st >>= 1) {
@@ -691,13 +699,13 @@ mlp_backward_fused_kernel(const uint16_t* __restrict__ w16, const float* __restr
   const size_t nblk = gridDim.x;
   if (t < kMlpOut) {  // the head's bias gradient part: rows in order
     float cs = 0.0f;
-    for (int r = 0; r < kFuseRows; ++r) cs += dys[r][t];
+    for (int r = 0; r < ROWS; ++r) cs += dys[r][t];
     bsum[(3 * nblk + blockIdx.x) * kMlpHid + t] = cs;
   }
   const size_t slot = (size_t)B * kMlpHid;
-  bwd_layer<kMlpOut>(ds[0], ds[1], w16 + kMlpW3, z3, r0, B, dz16T + 2 * slot, bsum + (2 * nblk + blockIdx.x) * kMlpHid);
-  bwd_layer<kMlpHid>(ds[1], ds[0], w16 + kMlpW2, z2, r0, B, dz16T + slot, bsum + (nblk + blockIdx.x) * kMlpHid);
-  bwd_layer<kMlpHid>(ds[0], ds[1], w16 + kMlpW1, z1, r0, B, dz16T, bsum + blockIdx.x * kMlpHid);
+  bwd_layer<RT, kMlpOut>(ds[0], ds[1], w16 + kMlpW3, z3, r0, B, dz16T + 2 * slot, bsum + (2 * nblk + blockIdx.x) * kMlpHid);
+  bwd_layer<RT, kMlpHid>(ds[1], ds[0], w16 + kMlpW2, z2, r0, B, dz16T + slot, bsum + (nblk + blockIdx.x) * kMlpHid);
+  bwd_layer<RT, kMlpHid>(ds[0], ds[1], w16 + kMlpW1, z1, r0, B, dz16T, bsum + blockIdx.x * kMlpHid);
 }
 
 // Forward pass of the one row [x_t; u_user] in a workgroup of 1,024
@@ -875,7 +883,7 @@ static MlpWork carve(void* base, int B) {
   w.loss = (float*)take(4);
   w.row = (float*)take(kMlpIn * 4);
   // bias-gradient parts: four layers x row blocks x 256 (the head uses 80)
-  w.bsum = (float*)take((size_t)4 * ((B + kFuseRows - 1) / kFuseRows) * kMlpHid * 4);
+  w.bsum = (float*)take((size_t)4 * ((B + 15) / 16) * kMlpHid * 4);  // blocks of at least 16 rows
   for (int l = 0; l < 4; ++l) w.part[l] = (float*)take((size_t)kMlpSplits * kMlpDims[l] * kMlpDims[l + 1] * 4);
   return w;
 }
@@ -907,9 +915,11 @@ static hipError_t forward_into(const uint16_t* w16, const float* bias32, const f
   mlp_weights_t_kernel<<<(kMlpParams + 255) / 256, 256, 0, st>>>(w16, w.w16t);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  mlp_forward_fused_kernel<<<(B + kFuseRows - 1) / kFuseRows, kFuseThreads, 0, st>>>(
-      w.w16t, bias32, mean, stdv, X, B, w.z1, w.z2, w.z3, Y, with_t ? w.h0T : nullptr, with_t ? w.h1T : nullptr,
-      with_t ? w.h2T : nullptr, with_t ? w.h3T : nullptr, loss_zero);
+  const int rows = fuse_rows(B);
+  auto kern = rows == 16 ? mlp_forward_fused_kernel<16> : mlp_forward_fused_kernel<32>;
+  kern<<<(B + rows - 1) / rows, kFuseThreads, 0, st>>>(w.w16t, bias32, mean, stdv, X, B, w.z1, w.z2, w.z3, Y,
+                                                       with_t ? w.h0T : nullptr, with_t ? w.h1T : nullptr,
+                                                       with_t ? w.h2T : nullptr, with_t ? w.h3T : nullptr, loss_zero);
   return hipGetLastError();
 }
 
@@ -931,8 +941,10 @@ hipError_t launch_mlp_grad(const uint16_t* w16, const float* w32, const float* m
   float* const lossp = loss ? loss : w.loss;
   hipError_t e = forward_into(w16, w32, mean, stdv, X, B, w, w.Y, true, lossp, st);
   if (e != hipSuccess) return e;
-  mlp_backward_fused_kernel<<<(B + kFuseRows - 1) / kFuseRows, kFuseThreads, 0, st>>>(
-      w16, w.Y, T, B, w.z1, w.z2, w.z3, w.nll, w.dY16T, w.dz16T, w.bsum, lossp);
+  const int rows = fuse_rows(B);
+  auto bkern = rows == 16 ? mlp_backward_fused_kernel<16> : mlp_backward_fused_kernel<32>;
+  bkern<<<(B + rows - 1) / rows, kFuseThreads, 0, st>>>(w16, w.Y, T, B, w.z1, w.z2, w.z3, w.nll, w.dY16T, w.dz16T,
+                                                        w.bsum, lossp);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   size_t ow[4], ob[4];
   layer_offsets(ow, ob);
@@ -942,7 +954,7 @@ hipError_t launch_mlp_grad(const uint16_t* w16, const float* w32, const float* m
   const uint16_t* dz16t[4];
   for (int l = 0; l < 3; ++l) dz16t[l] = w.dz16T + (size_t)l * B * kMlpHid;
   dz16t[3] = w.dY16T;
-  const int nblk = (B + kFuseRows - 1) / kFuseRows;
+  const int nblk = (B + rows - 1) / rows;
   // Every layer's weight gradient in one launch: dW_l = h_l^T dz_l
   // ([kin][nout]) from the batch-minor copies (h^T [kin][B] as A, dz^T
   // [nout][B] as the transposed B), split over the batch; then one launch

@@ -61,10 +61,12 @@ def test_gemm_bf16_matches_fp32_reference(ctx, M_, N_, K_, ta, tb):
     assert err <= 1e-5 * np.sqrt(K_) * 4, (err, M_, N_, K_, ta, tb)
 
 
-@pytest.fixture(scope="module", params=[512, 300], ids=["b512", "b300_ragged"])
+@pytest.fixture(scope="module", params=[512, 300, 16400], ids=["b512", "b300_ragged", "b16400_32row_blocks"])
 def batch(request):
-    """A batch of 512 rows, and a ragged one of 300 (not a multiple of the
-    64-row tiles nor of the 8-element chunks of the batch-minor copies)."""
+    """A batch of 512 rows, a ragged one of 300 (not a multiple of the 64-row
+    tiles nor of the 8-element chunks of the batch-minor copies), and one of
+    16,400, where the fused passes take 32-row blocks (16 below 16,384), the
+    last one ragged."""
     rng = np.random.default_rng(11)
     B = request.param
     X = np.concatenate([synth.race_car_states(B, W.rc_track(), seed=12),
