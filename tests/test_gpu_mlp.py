@@ -183,6 +183,29 @@ def test_mlp_gradient_parity(ctx, batch):
         assert rel < 6e-2 and cos > 0.998
 
 
+def test_mlp_rejects_misaligned_weights(ctx):
+    """The fused passes read the BF16 weights in 16-byte chunks: a weight
+    vector that does not start on a 16-byte boundary is rejected (EINVAL)
+    before any launch, and the aligned one is accepted."""
+    flat = synth.mlp_init(6)
+    w32 = torch.tensor(flat, dtype=torch.float32, device="cuda")
+    buf = torch.empty(len(flat) + 8, dtype=torch.bfloat16, device="cuda")
+    buf[1:1 + len(flat)] = w32.to(torch.bfloat16)
+    w16_bad = buf[1:1 + len(flat)]  # 2 bytes past a 256-byte boundary
+    assert w16_bad.data_ptr() % 16 != 0
+    mean = torch.zeros(8, device="cuda")
+    std = torch.ones(8, device="cuda")
+    X = torch.zeros((4, 8), device="cuda")
+    T = torch.zeros((4, 2), device="cuda")
+    with pytest.raises(mpmi.MpmiError, match="16-byte aligned"):
+        mpmi.mlp_grad(ctx, w16_bad, w32, mean, std, X, T)
+    with pytest.raises(mpmi.MpmiError, match="16-byte aligned"):
+        mpmi.mlp_forward(ctx, w16_bad, w32, mean, std, X)
+    grad, loss = mpmi.mlp_grad(ctx, w32.to(torch.bfloat16), w32, mean, std, X, T)
+    torch.cuda.synchronize()
+    assert np.isfinite(loss.item())
+
+
 def test_mlp_adam_parity(ctx):
     rng = np.random.default_rng(3)
     n = M.param_count()
