@@ -292,21 +292,33 @@ lifted_tick_kernel(const LiftedDev* __restrict__ ld, GenParams gp, int H, int hp
 #pragma unroll
         for (int i = 0; i < KC; ++i) A[gi][i] = sQ[(size_t)(gi * hpad + 4 * rt) * KP * 4 + a_off + 16 * i];
       const int s = 4 * rt + quarter + 1;  // this lane's step
+      // Every live tile's products first (independent accumulators, issued
+      // back to back), then the checks: one tile's MFMA latency overlaps the
+      // next tile's issue and the checks of the tiles before it.
+      f32x4_t acc[4], acc1[4];
 #pragma unroll
       for (int ct = 0; ct < 4; ++ct) {
-        if (dead & (1u << ct)) continue;
-        f32x4_t acc = {0.0f, 0.0f, 0.0f, 0.0f};
+        acc[ct] = f32x4_t{0.0f, 0.0f, 0.0f, 0.0f};
+        acc1[ct] = f32x4_t{0.0f, 0.0f, 0.0f, 0.0f};
+        if (dead & (1u << ct)) continue;  // uniform
 #pragma unroll
-        for (int i = 0; i < KC; ++i) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(A[0][i], B[ct][i], acc, 0, 0, 0);
-        float x4[4] = {acc[0], acc[1], acc[2], acc[3]};
+        for (int i = 0; i < KC; ++i)
+          acc[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[0][i], B[ct][i], acc[ct], 0, 0, 0);
         if constexpr (TRAJ) {
-          f32x4_t acc1 = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
           for (int i = 0; i < KC; ++i)
-            acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(A[G - 1][i], B[ct][i], acc1, 0, 0, 0);
+            acc1[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[G - 1][i], B[ct][i], acc1[ct], 0, 0, 0);
+        }
+      }
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct) {
+        if (dead & (1u << ct)) continue;  // uniform
+        const float x4[4] = {acc[ct][0], acc[ct][1], acc[ct][2], acc[ct][3]};
+        if constexpr (TRAJ) {
           const int c = wbase + 16 * ct + col;
           if (s <= H && c < Nc) {
-            const float v8[8] = {acc[0], acc[1], acc[2], acc[3], acc1[0], acc1[1], acc1[2], acc1[3]};
+            const float v8[8] = {acc[ct][0], acc[ct][1], acc[ct][2], acc[ct][3],
+                                 acc1[ct][0], acc1[ct][1], acc1[ct][2], acc1[ct][3]};
 #pragma unroll
             for (int i = 0; i < kLiftSlots; ++i) {
               const int comp = ld->slot_comp[i];
@@ -315,7 +327,8 @@ lifted_tick_kernel(const LiftedDev* __restrict__ ld, GenParams gp, int H, int hp
             }
           }
         }
-        if (s <= H && !all_safe_of<4, DEG>(&sc, x4)) fvm[ct] = min(fvm[ct], s);
+        const bool unsafe = !all_safe_of<4, DEG>(&sc, x4);
+        fvm[ct] = (s <= H && unsafe) ? min(fvm[ct], s) : fvm[ct];
       }
 #pragma unroll
       for (int ct = 0; ct < 4; ++ct) {
