@@ -190,9 +190,38 @@ __device__ __forceinline__ void fold_column64(const double* __restrict__ K, int 
   *Tc = fma(a, K[56 * 8 + j], K[46 * 8 + j]);
 }
 
-// Race car, one candidate per lane: the FP32 tick's folded step in FP64.
+// Output column j of the race car's FP64 step, x'_j, from the column's 27
+// step rows kc[r * STRIDE] (the step-ordered table: the 21 quadratic rows
+// (k, l >= k) in order, then sin psi (vx, vy, r) and cos psi (vx, vy, r)) and
+// its folded input terms, in nested form:
+//   x'_j = cu + sin psi (Ts + sum_i kc[21 + i] x_{3+i}) + cos psi (Tc + sum_i kc[24 + i] x_{3+i})
+//        + sum_k x_k (L_k + sum_{l >= k} kc[q(k, l)] x_l).
+// The same polynomial as the sum over the step's features, with no feature
+// products: 37 operations in place of 67.  The inner sums are independent
+// chains; the outer one is split in two, starting from the shortest.
+template <int STRIDE>
+__device__ __forceinline__ double rc_column64(const double* kc, double cu, const double* L, double Ts, double Tc,
+                                              double sp, double cp, const double* x) {
+  const double ts = fma(kc[23 * STRIDE], x[5], fma(kc[22 * STRIDE], x[4], fma(kc[21 * STRIDE], x[3], Ts)));
+  const double tc = fma(kc[26 * STRIDE], x[5], fma(kc[25 * STRIDE], x[4], fma(kc[24 * STRIDE], x[3], Tc)));
+  const double y0 = fma(cp, tc, fma(sp, ts, cu));
+  double t[6];
+  int q = 0;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    t[k] = L[k];
+#pragma unroll
+    for (int l = k; l < 6; ++l, ++q) t[k] = fma(kc[q * STRIDE], x[l], t[k]);
+  }
+  const double ya = fma(x[1], t[1], fma(x[3], t[3], x[5] * t[5]));
+  const double yb = fma(x[0], t[0], fma(x[2], t[2], x[4] * t[4]));
+  return (y0 + ya) + yb;
+}
+
+// Race car, one candidate per lane: the FP32 tick's folded input terms, and
+// the step's six columns in the nested form, in FP64.
 struct Stepper64RaceCar {
-  double cu[6], L[6][6], Ts[6], Tc[6];
+  double cu[6], L[6][6], Ts[6], Tc[6];  // L[j][k]: column j's coefficient of x_k
   __device__ __forceinline__ void set_input(const double* __restrict__ Kin, const double* u) {
     const double* K = opaque_coeffs(Kin);
     const double sd = sin(u[0]), cd = cos(u[0]);
@@ -201,7 +230,7 @@ struct Stepper64RaceCar {
       double Lj[6];
       fold_column64(K, j, u[0], u[1], sd, cd, &cu[j], Lj, &Ts[j], &Tc[j]);
 #pragma unroll
-      for (int k = 0; k < 6; ++k) L[k][j] = Lj[k];
+      for (int k = 0; k < 6; ++k) L[j][k] = Lj[k];
     }
   }
   // Ks: the step rows in step order (Model64::Kstep).
@@ -209,28 +238,9 @@ struct Stepper64RaceCar {
     const double* Ks = opaque_coeffs(Ksin);
     double sp, cp;
     sincos_rr64(x[2], &sp, &cp);
-    double p[kRcStepRows];
-    int q = 0;
-#pragma unroll
-    for (int k = 0; k < 6; ++k)
-#pragma unroll
-      for (int l = k; l < 6; ++l) p[q++] = x[k] * x[l];
-    p[21] = sp * x[3]; p[22] = sp * x[4]; p[23] = sp * x[5];
-    p[24] = cp * x[3]; p[25] = cp * x[4]; p[26] = cp * x[5];
     double y[6];
 #pragma unroll
-    for (int j = 0; j < 6; ++j) {
-      double v = fma(Tc[j], cp, fma(Ts[j], sp, cu[j]));
-#pragma unroll
-      for (int k = 0; k < 6; ++k) v = fma(L[k][j], x[k], v);
-      y[j] = v;
-    }
-#pragma unroll
-    for (int r = 0; r < kRcStepRows; ++r) {
-      const double* row = Ks + r * 8;
-#pragma unroll
-      for (int j = 0; j < 6; ++j) y[j] = fma(p[r], row[j], y[j]);
-    }
+    for (int j = 0; j < 6; ++j) y[j] = rc_column64<8>(Ks + j, cu[j], L[j], Ts[j], Tc[j], sp, cp, x);
 #pragma unroll
     for (int j = 0; j < 6; ++j) x[j] = y[j];
   }
@@ -279,9 +289,9 @@ __device__ int evaluate64(const ModelDev* __restrict__ md, const double* __restr
 // (< 6) holds output column j's coefficients in registers and forms x'_j, the
 // group exchanges the six new components, and every lane then holds the same
 // state (the same bits, so the same verdict and the same exit step).  Lanes 6
-// and 7 repeat column 5.  The features, the noise draws and the margin are
-// formed by every lane.  Returns the first violation (1..H, or H + 1).
-static_assert(kRcStepRows % 3 == 0, "three partial sums over the step rows");
+// and 7 repeat column 5.  The heading's sine and cosine, the noise draws and
+// the margin are formed by every lane.  Returns the first violation (1..H, or
+// H + 1).
 
 template <int DEG>
 __device__ int evaluate64_rc8(const ModelDev* __restrict__ md, const double* __restrict__ K,
@@ -326,33 +336,9 @@ __device__ int evaluate64_rc8(const ModelDev* __restrict__ md, const double* __r
     const Safety64<6, DEG> sc = safety64<6, DEG>(m);
     double sp, cp;
     sincos_rr64(x[2], &sp, &cp);
-    double p[kRcStepRows];
-    int q = 0;
-#pragma unroll
-    for (int k = 0; k < 6; ++k)
-#pragma unroll
-      for (int l = k; l < 6; ++l) p[q++] = x[k] * x[l];
-    p[21] = sp * x[3]; p[22] = sp * x[4]; p[23] = sp * x[5];
-    p[24] = cp * x[3]; p[25] = cp * x[4]; p[26] = cp * x[5];
 #pragma unroll
     for (int r = 0; r < kRcStepRows; ++r) asm volatile("" : "+v"(kc[r]));
-    // independent partial sums (the chain of one column is short of
-    // independent work otherwise)
-    double y0 = fma(Tc, cp, fma(Ts, sp, cu));
-    double ya = L[0] * x[0], yb = L[1] * x[1];
-#pragma unroll
-    for (int k = 2; k < 6; k += 2) {
-      ya = fma(L[k], x[k], ya);
-      yb = fma(L[k + 1], x[k + 1], yb);
-    }
-    double y1 = p[0] * kc[0], y2 = p[1] * kc[1], y3 = p[2] * kc[2];
-#pragma unroll
-    for (int r = 3; r < kRcStepRows; r += 3) {
-      y1 = fma(p[r], kc[r], y1);
-      y2 = fma(p[r + 1], kc[r + 1], y2);
-      y3 = fma(p[r + 2], kc[r + 2], y3);
-    }
-    const double y = ((y0 + ya) + (yb + y1)) + (y2 + y3);
+    const double y = rc_column64<1>(kc, cu, L, Ts, Tc, sp, cp, x);
 #pragma unroll
     for (int k = 0; k < 6; ++k) x[k] = __shfl(y, base + k, 64);
     if (noisy) add_noise64(m, pre, s, 6, x);
