@@ -513,6 +513,22 @@ struct Stepper<MPMI_BASIS_RACE_CAR> {
   }
 };
 
+// a * b + c, one rounding, as the three-address v_fma_f64.  For an addend
+// that stays live (a polynomial coefficient held across a loop) the compiler
+// picks the two-address form, whose destination is the addend, and copies
+// the coefficient into a fresh register before every use; this form needs
+// no copy.  CS: the addend is wave-uniform and lives in scalar registers.
+__device__ __forceinline__ double fma3(double a, double b, double c) {
+  double d;
+  asm("v_fma_f64 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "v"(c));
+  return d;
+}
+__device__ __forceinline__ double fma3s(double a, double b, double c) {
+  double d;
+  asm("v_fma_f64 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "s"(c));
+  return d;
+}
+
 // ---------------------------------------------------------------------------
 // sin and cos of a double, for the FP64 re-roll's heading.
 //
@@ -538,21 +554,19 @@ __device__ __forceinline__ void sincos_rr64(double x, double* sn, double* cs) {
   const double r = fma(-k, kP2, fma(-k, kP1, x));
   const double z = r * r;
   // (-1)^n / (2n + 1)!, n = 8 .. 1, and (-1)^n / (2n)!, n = 8 .. 2
-  double ps = 1.0 / 355687428096000.0;
-  ps = fma(ps, z, -1.0 / 1307674368000.0);
-  ps = fma(ps, z, 1.0 / 6227020800.0);
-  ps = fma(ps, z, -1.0 / 39916800.0);
-  ps = fma(ps, z, 1.0 / 362880.0);
-  ps = fma(ps, z, -1.0 / 5040.0);
-  ps = fma(ps, z, 1.0 / 120.0);
-  ps = fma(ps, z, -1.0 / 6.0);
-  double pc = 1.0 / 20922789888000.0;
-  pc = fma(pc, z, -1.0 / 87178291200.0);
-  pc = fma(pc, z, 1.0 / 479001600.0);
-  pc = fma(pc, z, -1.0 / 3628800.0);
-  pc = fma(pc, z, 1.0 / 40320.0);
-  pc = fma(pc, z, -1.0 / 720.0);
-  pc = fma(pc, z, 1.0 / 24.0);
+  double ps = fma3(1.0 / 355687428096000.0, z, -1.0 / 1307674368000.0);
+  ps = fma3(ps, z, 1.0 / 6227020800.0);
+  ps = fma3(ps, z, -1.0 / 39916800.0);
+  ps = fma3(ps, z, 1.0 / 362880.0);
+  ps = fma3(ps, z, -1.0 / 5040.0);
+  ps = fma3(ps, z, 1.0 / 120.0);
+  ps = fma3(ps, z, -1.0 / 6.0);
+  double pc = fma3(1.0 / 20922789888000.0, z, -1.0 / 87178291200.0);
+  pc = fma3(pc, z, 1.0 / 479001600.0);
+  pc = fma3(pc, z, -1.0 / 3628800.0);
+  pc = fma3(pc, z, 1.0 / 40320.0);
+  pc = fma3(pc, z, -1.0 / 720.0);
+  pc = fma3(pc, z, 1.0 / 24.0);
   const double s = fma(r * z, ps, r);                   // r + r z (-1/6 + ...)
   const double c = fma(z * z, pc, fma(-0.5, z, 1.0));   // 1 - z/2 + z^2 (1/24 + ...)
   const int q = (int)k;  // |k| < 2^20

@@ -73,26 +73,23 @@ __device__ __forceinline__ Safety64<NS, DEG> safety64(const Model64* __restrict_
   return sc;
 }
 
-// Least margin of x in FP64 (NaN if any margin is NaN): boxes per component,
-// then the track.  The centreline radius r_c(phi) is the FP32 tick's
-// Chebyshev form in FP64, P(cos phi) + sin phi * Q(cos phi) with the model's
-// FP64 monomial coefficients, (cos phi, sin phi) = (x0, x1) / rho; Horner runs
-// over a fixed DEG >= the model's highest harmonic (zero coefficients above it
-// leave each partial sum unchanged).  NS: the components that can carry a
-// box (6 for the race car, MPMI_MAX_STATE for the described bases).
+// Safety verdict of x in FP64: every boxed component strictly inside its
+// limit and the track margin positive.  This is "least margin > 0" with
+// the least margin NaN when a boxed component's or the track's margin is
+// NaN: lim - |v| > 0 exactly when |v| < lim (the difference of two distinct
+// doubles is never rounded to zero), and a NaN fails either comparison.  The
+// tests are combined bitwise (a compare each, no branch).  The centreline
+// radius r_c(phi) is the FP32 tick's Chebyshev form in FP64,
+// P(cos phi) + sin phi * Q(cos phi) with the model's FP64 monomial
+// coefficients, (cos phi, sin phi) = (x0, x1) / rho; Horner runs over a fixed
+// DEG >= the model's highest harmonic (zero coefficients above it leave each
+// partial sum unchanged).  NS: the components that can carry a box (6 for
+// the race car, MPMI_MAX_STATE for the described bases).
 template <int NS, int DEG>
-__device__ __forceinline__ double margin64(const Safety64<NS, DEG>& sc, const double* x) {
-  // A component without a box has limit +inf: its margin is +inf, or NaN
-  // for an infinite or NaN coordinate, which fmin ignores; so the minimum
-  // runs over every component and only the boxed ones can flag a NaN.
-  double mm = INFINITY;
-  bool nan = false;
+__device__ __forceinline__ bool safe64(const Safety64<NS, DEG>& sc, const double* x) {
+  bool ok = true;
 #pragma unroll
-  for (int k = 0; k < NS; ++k) {
-    const double mg = sc.lim[k] - fabs(x[k]);
-    nan |= ((sc.mask >> k) & 1) && (mg != mg);
-    mm = fmin(mm, mg);
-  }
+  for (int k = 0; k < NS; ++k) ok &= (fabs(x[k]) < sc.lim[k]) | !((sc.mask >> k) & 1);
   if (sc.has_track) {
     // 1 / rho by the hardware reciprocal square root and two Newton steps
     // (each at least doubles the correct bits), rho = r2 / rho: a shorter
@@ -106,15 +103,13 @@ __device__ __forceinline__ double margin64(const Safety64<NS, DEG>& sc, const do
     const double c1 = x[0] * inv, s1 = x[1] * inv;
     double P = sc.P[DEG];
 #pragma unroll
-    for (int k = DEG - 1; k >= 0; --k) P = fma(P, c1, sc.P[k]);
+    for (int k = DEG - 1; k >= 0; --k) P = fma3s(P, c1, sc.P[k]);
     double Q = sc.Q[DEG - 1];
 #pragma unroll
-    for (int k = DEG - 2; k >= 0; --k) Q = fma(Q, c1, sc.Q[k]);
-    const double mg = sc.trk_lim - fabs(rho - fma(s1, Q, P));
-    nan |= (mg != mg);
-    mm = fmin(mm, mg);
+    for (int k = DEG - 2; k >= 0; --k) Q = fma3s(Q, c1, sc.Q[k]);
+    ok &= fabs(rho - fma(s1, Q, P)) < sc.trk_lim;
   }
-  return nan ? NAN : mm;
+  return ok;
 }
 
 // Alg. 2's z_i for step s: the FP32 tick's draws (same counter hash), the
@@ -280,7 +275,7 @@ __device__ int evaluate64(const ModelDev* __restrict__ md, const double* __restr
     if constexpr (RC) stp.step(Ks, x);
     else step64_described(m, K, n, D, u, x, at);
     if (noisy) add_noise64(m, pre, s, n, x);
-    if (!(margin64(sc, x) > 0.0)) return s;
+    if (!safe64(sc, x)) return s;
   }
   return H + 1;
 }
@@ -342,7 +337,7 @@ __device__ int evaluate64_rc8(const ModelDev* __restrict__ md, const double* __r
 #pragma unroll
     for (int k = 0; k < 6; ++k) x[k] = __shfl(y, base + k, 64);
     if (noisy) add_noise64(m, pre, s, 6, x);
-    if (!(margin64(sc, x) > 0.0)) return s;
+    if (!safe64(sc, x)) return s;
   }
   return H + 1;
 }
