@@ -86,30 +86,33 @@ __device__ __forceinline__ Safety64<NS, DEG> safety64(const Model64* __restrict_
 // partial sum unchanged).  NS: the components that can carry a box (6 for
 // the race car, MPMI_MAX_STATE for the described bases).
 template <int NS, int DEG>
+__device__ __forceinline__ bool track_ok64(const Safety64<NS, DEG>& sc, const double* x) {
+  if (!sc.has_track) return true;
+  // 1 / rho by the hardware reciprocal square root and two Newton steps
+  // (each at least doubles the correct bits), rho = r2 / rho: a shorter
+  // dependent chain than a square root followed by a division.  r2 = 0 or
+  // an infinite coordinate gives NaN (unsafe), as in the FP32 tick.
+  const double r2 = fma(x[0], x[0], x[1] * x[1]);
+  double inv = __builtin_amdgcn_rsq(r2);
+  inv = inv * fma(-0.5 * r2, inv * inv, 1.5);
+  inv = inv * fma(-0.5 * r2, inv * inv, 1.5);
+  const double rho = r2 * inv;
+  const double c1 = x[0] * inv, s1 = x[1] * inv;
+  double P = sc.P[DEG];
+#pragma unroll
+  for (int k = DEG - 1; k >= 0; --k) P = fma3s(P, c1, sc.P[k]);
+  double Q = sc.Q[DEG - 1];
+#pragma unroll
+  for (int k = DEG - 2; k >= 0; --k) Q = fma3s(Q, c1, sc.Q[k]);
+  return fabs(rho - fma(s1, Q, P)) < sc.trk_lim;
+}
+
+template <int NS, int DEG>
 __device__ __forceinline__ bool safe64(const Safety64<NS, DEG>& sc, const double* x) {
   bool ok = true;
 #pragma unroll
   for (int k = 0; k < NS; ++k) ok &= (fabs(x[k]) < sc.lim[k]) | !((sc.mask >> k) & 1);
-  if (sc.has_track) {
-    // 1 / rho by the hardware reciprocal square root and two Newton steps
-    // (each at least doubles the correct bits), rho = r2 / rho: a shorter
-    // dependent chain than a square root followed by a division.  r2 = 0 or
-    // an infinite coordinate gives NaN (unsafe), as in the FP32 tick.
-    const double r2 = fma(x[0], x[0], x[1] * x[1]);
-    double inv = __builtin_amdgcn_rsq(r2);
-    inv = inv * fma(-0.5 * r2, inv * inv, 1.5);
-    inv = inv * fma(-0.5 * r2, inv * inv, 1.5);
-    const double rho = r2 * inv;
-    const double c1 = x[0] * inv, s1 = x[1] * inv;
-    double P = sc.P[DEG];
-#pragma unroll
-    for (int k = DEG - 1; k >= 0; --k) P = fma3s(P, c1, sc.P[k]);
-    double Q = sc.Q[DEG - 1];
-#pragma unroll
-    for (int k = DEG - 2; k >= 0; --k) Q = fma3s(Q, c1, sc.Q[k]);
-    ok &= fabs(rho - fma(s1, Q, P)) < sc.trk_lim;
-  }
-  return ok;
+  return ok & track_ok64(sc, x);
 }
 
 // Alg. 2's z_i for step s: the FP32 tick's draws (same counter hash), the
@@ -285,7 +288,7 @@ __device__ int evaluate64(const ModelDev* __restrict__ md, const double* __restr
 // group exchanges the six new components, and every lane then holds the same
 // state (the same bits, so the same verdict and the same exit step).  Lanes 6
 // and 7 repeat column 5.  The heading's sine and cosine, the noise draws and
-// the margin are formed by every lane.  Returns the first violation (1..H, or
+// the track margin are formed by every lane; lane j tests component j's box.  Returns the first violation (1..H, or
 // H + 1).
 
 template <int DEG>
@@ -307,6 +310,9 @@ __device__ int evaluate64_rc8(const ModelDev* __restrict__ md, const double* __r
     const double a = (double)cand_value(gp, md, cand, u_user, c, 0, 1);
     fold_column64(K, j, d, a, sin(d), cos(d), &cu, L, &Ts, &Tc);
   }
+  // Lane j's box: the limit of component j and whether it is boxed.
+  const double lim_j = m->comp_lim[j];
+  const bool box_j = (m->comp_mask >> j) & 1;
   const bool noisy = md->has_noise != 0;
   const uint64_t pre = noisy ? hash_prefix(gp.seed, gp.tick, (uint64_t)(uint32_t)gp.loop, (uint64_t)c) : 0ull;
   int snext = segment_start(1, S, H);
@@ -336,8 +342,20 @@ __device__ int evaluate64_rc8(const ModelDev* __restrict__ md, const double* __r
     const double y = rc_column64<1>(kc, cu, L, Ts, Tc, sp, cp, x);
 #pragma unroll
     for (int k = 0; k < 6; ++k) x[k] = __shfl(y, base + k, 64);
-    if (noisy) add_noise64(m, pre, s, 6, x);
-    if (!safe64(sc, x)) return s;
+    double own = y;  // component j of the new state
+    if (noisy) {
+      add_noise64(m, pre, s, 6, x);
+      own = x[0];
+#pragma unroll
+      for (int k = 1; k < 6; ++k) own = (j == k) ? x[k] : own;
+    }
+    // The boxes: lane j tests component j, and the group's eight tests are
+    // combined from one ballot (the group's lanes are all active: they hold
+    // the same state and exit together).  safe64's verdict, split over the
+    // group.
+    const unsigned long long okm = __ballot((fabs(own) < lim_j) | !box_j);
+    const bool box_ok = ((okm >> base) & 0xFFull) == 0xFFull;
+    if (!(box_ok & track_ok64(sc, x))) return s;
   }
   return H + 1;
 }
