@@ -107,6 +107,25 @@ __device__ __forceinline__ bool track_ok64(const Safety64<NS, DEG>& sc, const do
   return fabs(rho - fma(s1, Q, P)) < sc.trk_lim;
 }
 
+// track_ok64 with no branch on has_track: the test is formed either way
+// and a model without a track takes true.
+template <int NS, int DEG>
+__device__ __forceinline__ bool track_ok64_nb(const Safety64<NS, DEG>& sc, const double* x) {
+  const double r2 = fma(x[0], x[0], x[1] * x[1]);
+  double inv = __builtin_amdgcn_rsq(r2);
+  inv = inv * fma(-0.5 * r2, inv * inv, 1.5);
+  inv = inv * fma(-0.5 * r2, inv * inv, 1.5);
+  const double rho = r2 * inv;
+  const double c1 = x[0] * inv, s1 = x[1] * inv;
+  double P = sc.P[DEG];
+#pragma unroll
+  for (int k = DEG - 1; k >= 0; --k) P = fma3s(P, c1, sc.P[k]);
+  double Q = sc.Q[DEG - 1];
+#pragma unroll
+  for (int k = DEG - 2; k >= 0; --k) Q = fma3s(Q, c1, sc.Q[k]);
+  return !sc.has_track | (fabs(rho - fma(s1, Q, P)) < sc.trk_lim);
+}
+
 template <int NS, int DEG>
 __device__ __forceinline__ bool safe64(const Safety64<NS, DEG>& sc, const double* x) {
   bool ok = true;
@@ -315,6 +334,10 @@ __device__ int evaluate64_rc8(const ModelDev* __restrict__ md, const double* __r
   const bool box_j = (m->comp_mask >> j) & 1;
   const bool noisy = md->has_noise != 0;
   const uint64_t pre = noisy ? hash_prefix(gp.seed, gp.tick, (uint64_t)(uint32_t)gp.loop, (uint64_t)c) : 0ull;
+  // Iteration s forms x_s from x_{s-1} and, beside it, the verdict of
+  // x_{s-1} (the two are independent, so their chains overlap); an unsafe
+  // x_{s-1} ends the rollout at s - 1 and the step formed with it is dropped.
+  double own = 0.0;  // component j of the state being checked
   int snext = segment_start(1, S, H);
   for (int s = 1; s <= H; ++s) {
     if (s == snext) {
@@ -340,22 +363,30 @@ __device__ int evaluate64_rc8(const ModelDev* __restrict__ md, const double* __r
 #pragma unroll
     for (int r = 0; r < kRcStepRows; ++r) asm volatile("" : "+v"(kc[r]));
     const double y = rc_column64<1>(kc, cu, L, Ts, Tc, sp, cp, x);
+    // The boxes: lane j tests component j, and the group's eight tests are
+    // combined from one ballot (the group's lanes are all active: they hold
+    // the same state and exit together).  safe64's verdict, split over the
+    // group.  x_0, the current state, is not checked.
+    const unsigned long long okm = __ballot((fabs(own) < lim_j) | !box_j);
+    const bool ok = (((okm >> base) & 0xFFull) == 0xFFull) & track_ok64_nb(sc, x);
+    double xn[6];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) x[k] = __shfl(y, base + k, 64);
-    double own = y;  // component j of the new state
+    for (int k = 0; k < 6; ++k) xn[k] = __shfl(y, base + k, 64);
+    if (s > 1 && !ok) return s - 1;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) x[k] = xn[k];
+    own = y;
     if (noisy) {
       add_noise64(m, pre, s, 6, x);
       own = x[0];
 #pragma unroll
       for (int k = 1; k < 6; ++k) own = (j == k) ? x[k] : own;
     }
-    // The boxes: lane j tests component j, and the group's eight tests are
-    // combined from one ballot (the group's lanes are all active: they hold
-    // the same state and exit together).  safe64's verdict, split over the
-    // group.
+  }
+  {
+    const Safety64<6, DEG> sc = safety64<6, DEG>(m);
     const unsigned long long okm = __ballot((fabs(own) < lim_j) | !box_j);
-    const bool box_ok = ((okm >> base) & 0xFFull) == 0xFFull;
-    if (!(box_ok & track_ok64(sc, x))) return s;
+    if (!((((okm >> base) & 0xFFull) == 0xFFull) & track_ok64_nb(sc, x))) return H;
   }
   return H + 1;
 }
